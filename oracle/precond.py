@@ -1,0 +1,360 @@
+"""Block preconditioner for K with the multiplicative auxiliary-space preconditioner
+for the double Schur complement A^d -- oracle (FP64, sequential).
+
+* K-hat^{-1} (eq. mhatinvfactor, with its top-right block read as -A-hat^{-1} B^T
+  and the pressure block +S-hat^{-1}, S-hat = M_p the nu^{-1}-scaled pressure
+  mass matrix, Sec. 5.1), applied with two A-hat^{-1} applications.
+* A-hat_ext (Sec. 6.1 "Preconditioning via the condense system"): A through its
+  bubble factorisation (eq. factorSsigma) with A^d replaced by A-hat^d_m.
+* A-hat^d_m (Theorem aux_pc_schur with Corollary aux_pc_mult and the
+  multiplicative ASP of Sec. 5.2): block Gauss-Seidel over facet blocks (one
+  block per free facet holding its normal and tangential dofs), s sweeps in
+  colour order, then the coarse correction E^d C^{-1} E^d^T on the residual,
+  then s sweeps in reverse colour order (the adjoint smoother).
+* E^d: rows of the embedding E u = (u, u_t) of continuous P1 (eq. defE) for the
+  facet dofs (eq. defED).
+* C: one symmetric V(1,1) multigrid cycle for A-bar, the P1 form
+  a(u, v) = nu int eps(u) : eps(v) (eq. defAhat, read with nu, not nu^{-1}),
+  on the vertex lattice: coarse points every second index per axis plus the
+  last one, linear interpolation in index space, Galerkin coarse operators,
+  l1-Jacobi smoothing with d x d vertex blocks, a dense Cholesky solve on the
+  coarsest level (free dofs <= coarse_max or <= 2 intervals on some axis).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from .poly import elevate_to, multi_indices
+
+
+# ---------------------------------------------------------------------------
+# P1 space and multigrid
+# ---------------------------------------------------------------------------
+
+def p1_element_matrix(ed, nu):
+    """A-bar_T[(v,c),(w,e)] = nu int_T eps(lambda_v e_c) : eps(lambda_w e_e)."""
+    d = ed.d
+    gl = ed.grad_lambda
+    n = (d + 1) * d
+    A = np.zeros((n, n))
+    for v in range(d + 1):
+        for c in range(d):
+            Ev = 0.5 * (np.outer(np.eye(d)[c], gl[v]) + np.outer(gl[v], np.eye(d)[c]))
+            for w in range(d + 1):
+                for e in range(d):
+                    Ew = 0.5 * (np.outer(np.eye(d)[e], gl[w]) + np.outer(gl[w], np.eye(d)[e]))
+                    A[v * d + c, w * d + e] = nu * ed.vol * np.sum(Ev * Ew)
+    return A
+
+
+def coarse_points(n):
+    """Coarse lattice positions (fine indices) for n intervals: 0, 2, 4, ... plus n."""
+    pts = list(range(0, n + 1, 2))
+    if pts[-1] != n:
+        pts.append(n)
+    return pts
+
+
+def interp_1d(n):
+    """(n+1) x (n_c+1) linear interpolation in index space."""
+    cp = coarse_points(n)
+    P = np.zeros((n + 1, len(cp)))
+    cset = {c: j for j, c in enumerate(cp)}
+    for i in range(n + 1):
+        if i in cset:
+            P[i, cset[i]] = 1.0
+        else:
+            P[i, cset[i - 1]] = 0.5
+            P[i, cset[i + 1]] = 0.5
+    return P
+
+
+class P1Multigrid:
+    def __init__(self, Abar, lattice, d, coarse_max=1500):
+        """Abar over free lattice vertices (interior), dof = d*free_vertex + c."""
+        self.d = d
+        self.levels = []
+        dims = [n - 1 for n in lattice]          # intervals per axis
+        A = Abar.tocsr()
+        while True:
+            lvl = {"A": A, "dims": dims}
+            self.levels.append(lvl)
+            nfree = A.shape[0]
+            if nfree <= coarse_max or min(dims) <= 2:
+                lvl["chol"] = sla.cho_factor(A.toarray())
+                break
+            lvl["Dinv"] = self._l1_block_inverse(A)
+            # prolongation restricted to interior points, tensor product (x fastest)
+            Ps = [interp_1d(n)[1:-1, 1:-1] for n in dims]
+            P = sp.csr_matrix(Ps[0])
+            for Pa in Ps[1:]:
+                P = sp.kron(sp.csr_matrix(Pa), P, format="csr")
+            P = sp.kron(P, sp.identity(d), format="csr")
+            lvl["P"] = P
+            A = (P.T @ A @ P).tocsr()
+            dims = [len(coarse_points(n)) - 1 for n in dims]
+
+    def _l1_block_inverse(self, A):
+        d = self.d
+        A = A.tocsr()
+        nv = A.shape[0] // d
+        Dinv = np.zeros((nv, d, d))
+        absA = abs(A)
+        for v in range(nv):
+            rows = slice(v * d, (v + 1) * d)
+            blk = A[rows, rows].toarray()
+            rowsum = np.asarray(absA[rows, :].sum(axis=1)).ravel()
+            inblock = np.abs(blk).sum(axis=1)
+            Dv = blk + np.diag(rowsum - inblock)
+            Dinv[v] = np.linalg.inv(Dv)
+        return Dinv
+
+    def _jacobi(self, lvl, r):
+        d = self.d
+        return np.einsum("vab,vb->va", lvl["Dinv"], r.reshape(-1, d)).ravel()
+
+    def vcycle(self, b, level=0):
+        lvl = self.levels[level]
+        if "chol" in lvl:
+            return sla.cho_solve(lvl["chol"], b)
+        A = lvl["A"]
+        x = self._jacobi(lvl, b)
+        r = b - A @ x
+        x = x + lvl["P"] @ self.vcycle(lvl["P"].T @ r, level + 1)
+        x = x + self._jacobi(lvl, b - A @ x)
+        return x
+
+
+# ---------------------------------------------------------------------------
+# embedding E, E^d
+# ---------------------------------------------------------------------------
+
+def p1_in_element_basis(es, v_local, c):
+    """Coefficients of lambda_v e_c (a P1 field on the element) in the element's
+    BDM basis (original order) and, per facet, in the tangential basis of its
+    tangential trace (eq. defE: E u = (u, u_t))."""
+    ed = es["ed"]
+    d, k = ed.d, ed.k
+    nv = d + 1
+    lin = np.zeros((nv, d))
+    lin[v_local, c] = 1.0                       # coefficients over I_1 = {e_v}
+    # I_1 in lex-descending order is e_0, e_1, ..., e_d
+    target = elevate_to(lin, nv, 1, k)          # (|I_k|, d)
+    Phi = ed.Phi                                # (n_u, |I_k|, d)
+    M = Phi.reshape(Phi.shape[0], -1).T
+    cu, *_ = np.linalg.lstsq(M, target.ravel(), rcond=None)
+    assert np.allclose(M @ cu, target.ravel(), atol=1e-10 * max(1.0, np.abs(target).max()))
+    ch = []
+    tgt_t = elevate_to(lin, nv, 1, k - 1)       # (|I_{k-1}|, d)
+    Ikm1 = multi_indices(nv, k - 1)
+    for i in range(nv):
+        n = ed.normals_out[i]
+        Pt = np.eye(d) - np.outer(n, n)
+        msk = np.array([a[i] == 0 for a in Ikm1])
+        tgt = (tgt_t @ Pt.T)[msk]               # tangential part on facet i
+        V = ed.Vhat[i][:, msk, :]               # (n_hat, n_fac, d)
+        Mv = V.reshape(V.shape[0], -1).T
+        chi, *_ = np.linalg.lstsq(Mv, tgt.ravel(), rcond=None)
+        assert np.allclose(Mv @ chi, tgt.ravel(), atol=1e-10 * max(1.0, np.abs(tgt).max()))
+        ch.append(chi)
+    return cu, ch
+
+
+def embedding(gs, full=False):
+    """Sparse E (n_dof_velocity x n_P1) for the free P1 dofs.  With full=False
+    only the facet rows (E^d) are nonzero; with full=True also the bubble rows.
+    Facet rows are computed from the first neighbour of each facet; the test
+    suite checks that the other neighbour gives the same rows."""
+    topo = gs.topo
+    d = gs.d
+    rows, cols, vals = [], [], []
+    done_facet = np.zeros(topo.n_free_facets, dtype=bool)
+    nb, nF, nh = gs.nb, gs.nF, gs.nh
+    for e in range(gs.n_e):
+        es = gs.elems[e]
+        verts = topo.elements[e]
+        for vl in range(d + 1):
+            fvi = topo.free_vertex_of[verts[vl]]
+            if fvi < 0:
+                continue
+            for c in range(d):
+                col = d * fvi + c
+                cu, ch = p1_in_element_basis(es, vl, c)
+                if full:
+                    for j in range(nb):
+                        rows.append(e * nb + j); cols.append(col); vals.append(cu[j])
+                for i in range(d + 1):
+                    g = topo.free_facet_of[topo.elem_facets[e, i]]
+                    if g < 0 or done_facet[g]:
+                        continue
+                    base = gs.off_f + g * gs.nfb
+                    for q in range(nF):
+                        rows.append(base + q); cols.append(col); vals.append(cu[nb + i * nF + q])
+                    for q in range(nh):
+                        rows.append(base + nF + q); cols.append(col); vals.append(ch[i][q])
+        for i in range(d + 1):
+            g = topo.free_facet_of[topo.elem_facets[e, i]]
+            if g >= 0:
+                done_facet[g] = True
+    n_p1 = d * len(topo.free_vertices)
+    E = sp.coo_matrix((vals, (rows, cols)), shape=(gs.n_dof, n_p1)).tocsr()
+    E.sum_duplicates()
+    return E
+
+
+def assemble_p1(gs):
+    topo = gs.topo
+    d = gs.d
+    rows, cols, vals = [], [], []
+    for e in range(gs.n_e):
+        Ae = p1_element_matrix(gs.elems[e]["ed"], gs.nu[e])
+        idx = []
+        for v in topo.elements[e]:
+            fv = topo.free_vertex_of[v]
+            for c in range(d):
+                idx.append(d * fv + c if fv >= 0 else -1)
+        idx = np.asarray(idx)
+        m = idx >= 0
+        R, C = np.meshgrid(idx[m], idx[m], indexing="ij")
+        rows.append(R.ravel()); cols.append(C.ravel()); vals.append(Ae[np.ix_(m, m)].ravel())
+    n = d * len(topo.free_vertices)
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n, n))
+
+
+# ---------------------------------------------------------------------------
+# the preconditioner
+# ---------------------------------------------------------------------------
+
+class Preconditioner:
+    def __init__(self, gs, lattice, smoothing_steps=2, coarse_max=1500):
+        self.gs = gs
+        topo = gs.topo
+        d = gs.d
+        self.steps = smoothing_steps
+        nfb = gs.nfb
+        # assembled double Schur complement A^d on the facet dofs
+        blocks_r, blocks_c, blocks_v = [], [], []
+        for e, es in enumerate(gs.elems):
+            ld = gs.local_dofs(e)[gs.nb:]
+            m = ld >= 0
+            R, C = np.meshgrid(ld[m], ld[m], indexing="ij")
+            blocks_r.append(R.ravel()); blocks_c.append(C.ravel())
+            blocks_v.append(es["Ad"][np.ix_(m, m)].ravel())
+        self.Ad = sp.csr_matrix((np.concatenate(blocks_v), (np.concatenate(blocks_r),
+                                 np.concatenate(blocks_c))), shape=(gs.n_dof, gs.n_dof))
+        # facet block inverses D_F^{-1}
+        self.Dinv = []
+        for g in range(topo.n_free_facets):
+            fd = gs.facet_dofs(g)
+            D = self.Ad[fd][:, fd].toarray()
+            self.Dinv.append(np.linalg.inv(D))
+        self.colour_lists = [np.nonzero(topo.colour == c)[0] for c in range(topo.n_colours)]
+        # auxiliary space
+        self.E = embedding(gs, full=False)
+        self.Abar = assemble_p1(gs)
+        self.mg = P1Multigrid(self.Abar, lattice, d, coarse_max=coarse_max)
+        # element-local pressure mass inverses
+        self.Mp_inv = [np.linalg.inv(es["Mp"]) for es in gs.elems]
+
+    # ---- pieces ---------------------------------------------------------
+    def smooth(self, x, s, order):
+        gs = self.gs
+        for c in order:
+            for g in self.colour_lists[c]:
+                fd = gs.facet_dofs(g)
+                r = s[fd] - self.Ad[fd] @ x
+                x[fd] += self.Dinv[g] @ r
+        return x
+
+    def forward_sweep(self, x, s):
+        return self.smooth(x, s, range(len(self.colour_lists)))
+
+    def backward_sweep(self, x, s):
+        return self.smooth(x, s, range(len(self.colour_lists) - 1, -1, -1))
+
+    def aux_correction(self, r):
+        return self.E @ self.mg.vcycle(self.E.T @ r)
+
+    def Ad_mult_inv(self, s):
+        """A-hat^d_m^{-1} s (x^0 = 0; s forward sweeps; coarse correction;
+        s backward sweeps).  s and the result live on the facet dofs."""
+        x = np.zeros_like(s)
+        for _ in range(self.steps):
+            x = self.forward_sweep(x, s)
+        r = s - self.Ad @ x
+        x = x + self.aux_correction(r)
+        for _ in range(self.steps):
+            x = self.backward_sweep(x, s)
+        return x
+
+    def A_ext_inv(self, r):
+        """A-hat_ext^{-1} r for a velocity vector r (pressure part ignored/zero):
+        s = r_d - sum_T H_T^T r_o,T;  t = A-hat^d_m^{-1} s;
+        y_o,T = A_oo,T^{-1} r_o,T - H_T t_T;  y_d = t."""
+        gs = self.gs
+        nb = gs.nb
+        s = np.zeros(gs.n_dof)
+        s[gs.off_f:gs.off_p] = r[gs.off_f:gs.off_p]
+        for e, es in enumerate(gs.elems):
+            ro = r[e * nb:(e + 1) * nb]
+            ld = gs.local_dofs(e)[nb:]
+            m = ld >= 0
+            contrib = es["H"].T @ ro
+            np.add.at(s, ld[m], -contrib[m])
+        t = self.Ad_mult_inv(s)
+        y = np.zeros(gs.n_dof)
+        y[gs.off_f:gs.off_p] = t[gs.off_f:gs.off_p]
+        for e, es in enumerate(gs.elems):
+            ro = r[e * nb:(e + 1) * nb]
+            ld = gs.local_dofs(e)[nb:]
+            td = np.where(ld >= 0, t[np.maximum(ld, 0)], 0.0)
+            y[e * nb:(e + 1) * nb] = np.linalg.solve(es["Aoo"], ro) - es["H"] @ td
+        return y
+
+    def B_apply(self, u):
+        gs = self.gs
+        out = np.zeros(gs.n_dof)
+        for e, es in enumerate(gs.elems):
+            ld = gs.local_dofs(e)
+            ul = np.where(ld >= 0, u[np.maximum(ld, 0)], 0.0)
+            uo = np.zeros(gs.dims["n_u"])
+            uo[:] = ul[gs.u_to_reordered(e)]
+            out[gs.pressure_dofs(e)] = es["B"] @ uo
+        return out
+
+    def BT_apply(self, p):
+        gs = self.gs
+        out = np.zeros(gs.n_dof)
+        for e, es in enumerate(gs.elems):
+            ld = gs.local_dofs(e)
+            loc = np.zeros(len(ld))
+            loc[gs.u_to_reordered(e)] = es["B"].T @ p[gs.pressure_dofs(e)]
+            m = ld >= 0
+            np.add.at(out, ld[m], loc[m])
+        return out
+
+    def Mp_inv_apply(self, r):
+        gs = self.gs
+        out = np.zeros(gs.n_dof)
+        for e in range(gs.n_e):
+            pd = gs.pressure_dofs(e)
+            out[pd] = self.Mp_inv[e] @ r[pd]
+        return out
+
+    def apply(self, r):
+        """K-hat^{-1} r:  a = A^{-1} r_u;  y_p = M_p^{-1}(r_p - B a);
+        y_u = a - A^{-1} B^T y_p."""
+        gs = self.gs
+        ru = r.copy()
+        ru[gs.off_p:] = 0.0
+        a = self.A_ext_inv(ru)
+        rp = np.zeros(gs.n_dof)
+        rp[gs.off_p:] = r[gs.off_p:]
+        yp = self.Mp_inv_apply(rp - self.B_apply(a))
+        yu = a - self.A_ext_inv(self.BT_apply(yp))
+        y = yu
+        y[gs.off_p:] = yp[gs.off_p:]
+        return y

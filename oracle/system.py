@@ -1,0 +1,184 @@
+"""Global condensed saddle system K (eq. femSPmat) and its direct solution -- oracle.
+
+Global vector layout (free degrees of freedom only, all of dOmega is Dirichlet):
+
+    [ u_o : element-major, n_bub per element                        ]
+    [ facet blocks : free facets in canonical order, each block is   ]
+    [                (n_F normal-moment dofs, n_hat tangential dofs) ]
+    [ p   : element-major, n_p per element                           ]
+
+K = [[A, B^T], [B, 0]] with A the sigma/omega-condensed velocity block
+(Sec. 4.2) and B the pressure coupling -(div u, q) (weak-form sign of eq.
+discrmixedstressstokesweak).  The pressure is unique up to a constant when all
+of the boundary is Dirichlet (Sec. 1); the direct solve fixes int p = 0 with a
+Lagrange multiplier.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .element import element_geometry, element_system, expected_dims
+from .poly import multi_indices, simplex_moment
+from .topology import Topology
+
+
+def _lattice_indices(d, m):
+    return np.asarray(multi_indices(d + 1, m), dtype=np.int64)
+
+
+class GlobalSystem:
+    def __init__(self, vertices, elements, nu, k, f_lattice=None, m=None):
+        self.topo = topo = Topology(vertices, elements)
+        d = self.d = topo.dim
+        self.k = k
+        n_e = topo.elements.shape[0]
+        self.n_e = n_e
+        nu = np.broadcast_to(np.asarray(nu, dtype=np.float64), (n_e,))
+        self.nu = np.array(nu)
+        dims = self.dims = expected_dims(d, k)
+        self.nb, self.nF, self.nh, self.nfb = dims["n_bub"], dims["n_F"], dims["n_hat"], dims["n_fb"]
+        self.np_ = dims["n_p"]
+        self.off_f = n_e * self.nb
+        self.off_p = self.off_f + topo.n_free_facets * self.nfb
+        self.n_dof = self.off_p + n_e * self.np_
+        self.m = m if m is not None else k + 1
+        lat = _lattice_indices(d, self.m)
+
+        self.elems = []
+        for e in range(n_e):
+            X = topo.element_coords(e)
+            ed = element_geometry(X, k)
+            fl = ls = None
+            if f_lattice is not None:
+                fl = np.asarray(f_lattice[e], dtype=np.float64)
+                ls = lat[:, topo.perm[e]]
+            es = element_system(ed, self.nu[e], k, fl, ls, self.m)
+            self.elems.append(es)
+
+    # ------------------------------------------------------------------ maps
+    def local_dofs(self, e):
+        """Global indices of the reordered local velocity dofs of element e
+        ([bubbles | facet blocks]); -1 marks Dirichlet dofs."""
+        nb, nfb = self.nb, self.nfb
+        out = list(range(e * nb, (e + 1) * nb))
+        for i in range(self.d + 1):
+            g = self.topo.free_facet_of[self.topo.elem_facets[e, i]]
+            if g < 0:
+                out += [-1] * nfb
+            else:
+                out += list(range(self.off_f + g * nfb, self.off_f + (g + 1) * nfb))
+        return np.asarray(out, dtype=np.int64)
+
+    def facet_dofs(self, g):
+        return np.arange(self.off_f + g * self.nfb, self.off_f + (g + 1) * self.nfb)
+
+    def pressure_dofs(self, e):
+        return np.arange(self.off_p + e * self.np_, self.off_p + (e + 1) * self.np_)
+
+    def u_to_reordered(self, e):
+        """Map original local u index (bubbles, facet fns) -> reordered position."""
+        perm = self.elems[e]["perm"]
+        inv = np.empty(len(perm), dtype=np.int64)
+        inv[perm] = np.arange(len(perm))
+        return inv[: self.dims["n_u"]]
+
+    # --------------------------------------------------------------- assembly
+    def _scatter(self, blocks):
+        rows, cols, vals = [], [], []
+        for (gr, gc, M) in blocks:
+            mr = gr >= 0
+            mc = gc >= 0
+            sub = M[np.ix_(mr, mc)]
+            R, C = np.meshgrid(gr[mr], gc[mc], indexing="ij")
+            rows.append(R.ravel())
+            cols.append(C.ravel())
+            vals.append(sub.ravel())
+        r = np.concatenate(rows)
+        c = np.concatenate(cols)
+        v = np.concatenate(vals)
+        return sp.csr_matrix((v, (r, c)), shape=(self.n_dof, self.n_dof))
+
+    def assemble_K(self):
+        blocks = []
+        for e, es in enumerate(self.elems):
+            ld = self.local_dofs(e)
+            perm = es["perm"]
+            blocks.append((ld, ld, es["A"][np.ix_(perm, perm)]))
+            pd = self.pressure_dofs(e)
+            Bl = np.zeros((self.np_, len(ld)))
+            Bl[:, self.u_to_reordered(e)] = es["B"]
+            blocks.append((pd, ld, Bl))
+            blocks.append((ld, pd, Bl.T))
+        return self._scatter(blocks)
+
+    def assemble_rhs(self):
+        b = np.zeros(self.n_dof)
+        for e, es in enumerate(self.elems):
+            ld = self.local_dofs(e)
+            loc = np.zeros(len(ld))
+            loc[self.u_to_reordered(e)] = es["F"]
+            msk = ld >= 0
+            np.add.at(b, ld[msk], loc[msk])
+        return b
+
+    def pressure_mean_functional(self):
+        """c with c.x = int_Omega p_h (p basis lambda^gamma, |gamma| = k-1)."""
+        d = self.d
+        Ig = multi_indices(d + 1, self.k - 1)
+        mom = np.array([simplex_moment(g) for g in Ig])
+        c = np.zeros(self.n_dof)
+        for e, es in enumerate(self.elems):
+            c[self.pressure_dofs(e)] = es["ed"].vol * mom
+        return c
+
+    def constant_pressure(self):
+        """Coefficient vector of p = 1 (sum of multinomial coefficients)."""
+        Ig = multi_indices(self.d + 1, self.k - 1)
+        coef = np.array([math.factorial(self.k - 1) / np.prod([math.factorial(a) for a in g])
+                         for g in Ig])
+        c = np.zeros(self.n_dof)
+        for e in range(self.n_e):
+            c[self.pressure_dofs(e)] = coef
+        return c
+
+    def normalize_pressure(self, x):
+        """Subtract the mean of p_h (Sec. 1: p unique up to a constant)."""
+        c = self.pressure_mean_functional()
+        area = sum(es["ed"].vol for es in self.elems)
+        mean = (c @ x) / area
+        return x - mean * self.constant_pressure()
+
+    def direct_solve(self, b=None):
+        K = self.assemble_K()
+        if b is None:
+            b = self.assemble_rhs()
+        c = self.pressure_mean_functional()
+        Kc = sp.bmat([[K, sp.csr_matrix(c[:, None])], [sp.csr_matrix(c[None, :]), None]],
+                     format="csc")
+        rhs = np.concatenate([b, [0.0]])
+        x = spla.splu(Kc).solve(rhs)
+        return x[:-1]
+
+    # ------------------------------------------------------------- evaluation
+    def eval_element(self, x, e, lam):
+        """Values (u, p) of the discrete solution in element e at barycentric
+        points lam (n, d+1) w.r.t. the sorted vertices."""
+        from .poly import evaluate
+        es = self.elems[e]
+        ed = es["ed"]
+        ld = self.local_dofs(e)
+        coef = np.where(ld >= 0, x[np.maximum(ld, 0)], 0.0)
+        perm = es["perm"]
+        u_coef_reordered = coef
+        orig = np.zeros(len(perm))
+        orig[perm] = u_coef_reordered
+        cu = orig[: self.dims["n_u"]]
+        field = np.tensordot(cu, ed.Phi, axes=(0, 0))           # (|I_k|, d)
+        u = evaluate(field, self.d + 1, self.k, lam)
+        cp = x[self.pressure_dofs(e)]
+        p = evaluate(cp, self.d + 1, self.k - 1, lam)
+        return u, p

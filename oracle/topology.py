@@ -1,0 +1,90 @@
+"""Mesh topology for the oracle: facets, orientation, Dirichlet data, colouring.
+
+Conventions (Sec. 3 of the paper defines the mesh, facets and traces; the
+numbering below is the solver's documented convention):
+
+* every element's vertices are sorted by ascending global index; local facet i
+  is the facet opposite sorted local vertex i;
+* a facet is the sorted tuple of its global vertices; facets are ordered
+  lexicographically by that tuple ("canonical order");
+* all of the boundary is Dirichlet (Gamma_D = boundary): boundary facets and
+  boundary vertices carry no free degrees of freedom;
+* free facets are the interior facets in canonical order;
+* facet colouring: greedy in canonical order, smallest colour not used by any
+  already coloured free facet that shares an element (so facets of one colour
+  never share an element and their smoother blocks are independent).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+class Topology:
+    def __init__(self, vertices: np.ndarray, elements: np.ndarray):
+        self.vertices = np.asarray(vertices, dtype=np.float64)
+        self.elements_in = np.asarray(elements, dtype=np.int64)
+        self.dim = self.vertices.shape[1]
+        d = self.dim
+        self.perm = np.argsort(self.elements_in, axis=1, kind="stable")
+        self.elements = np.take_along_axis(self.elements_in, self.perm, axis=1)
+        n_e = self.elements.shape[0]
+
+        facets = {}
+        for t in range(n_e):
+            ev = self.elements[t]
+            for i in range(d + 1):
+                key = tuple(int(v) for j, v in enumerate(ev) if j != i)
+                facets.setdefault(key, []).append((t, i))
+        keys = sorted(facets)
+        self.facet_vertices = np.asarray(keys, dtype=np.int64)
+        self.facet_neighbors = [sorted(facets[k]) for k in keys]
+        nf = len(keys)
+        self.n_facets = nf
+        self.facet_boundary = np.array([len(nb) == 1 for nb in self.facet_neighbors])
+        fid = {k: n for n, k in enumerate(keys)}
+        self.elem_facets = np.zeros((n_e, d + 1), dtype=np.int64)
+        for t in range(n_e):
+            ev = self.elements[t]
+            for i in range(d + 1):
+                key = tuple(int(v) for j, v in enumerate(ev) if j != i)
+                self.elem_facets[t, i] = fid[key]
+
+        # free (interior) facets in canonical order
+        self.free_facet_of = -np.ones(nf, dtype=np.int64)
+        free = np.nonzero(~self.facet_boundary)[0]
+        self.free_facet_of[free] = np.arange(len(free))
+        self.free_facets = free
+        self.n_free_facets = len(free)
+
+        # boundary / free vertices
+        bverts = set(int(v) for k in np.asarray(keys)[self.facet_boundary] for v in k)
+        nv = self.vertices.shape[0]
+        self.vertex_boundary = np.zeros(nv, dtype=bool)
+        self.vertex_boundary[list(bverts)] = True
+        self.free_vertex_of = -np.ones(nv, dtype=np.int64)
+        fv = np.nonzero(~self.vertex_boundary)[0]
+        self.free_vertex_of[fv] = np.arange(len(fv))
+        self.free_vertices = fv
+
+        self._colour()
+
+    def _colour(self):
+        n = self.n_free_facets
+        colour = -np.ones(n, dtype=np.int64)
+        for g, f in enumerate(self.free_facets):
+            used = set()
+            for (t, _i) in self.facet_neighbors[f]:
+                for f2 in self.elem_facets[t]:
+                    g2 = self.free_facet_of[f2]
+                    if g2 >= 0 and g2 != g and colour[g2] >= 0:
+                        used.add(int(colour[g2]))
+            c = 0
+            while c in used:
+                c += 1
+            colour[g] = c
+        self.colour = colour
+        self.n_colours = int(colour.max()) + 1 if n else 0
+
+    def element_coords(self, t: int) -> np.ndarray:
+        """(d+1, d) coordinates of the sorted vertices of element t."""
+        return self.vertices[self.elements[t]]
