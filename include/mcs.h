@@ -1,0 +1,211 @@
+/*
+ * mcs.h -- C ABI of the MI355X solver for the hybridised mass conserving mixed
+ * stress (MCS) discretisation of the Stokes problem with its conforming
+ * auxiliary-space preconditioner.
+ *
+ * Method: Kogler, Lederer, Schoeberl, "A conforming auxiliary space
+ * preconditioner for the mass conserving mixed stress method"
+ * (arXiv 2207.08481).  Problem statement: Sec. 1, eq. (stokes):
+ *     -div(nu eps(u)) + grad p = f,  div u = 0  in Omega,   u = 0 on dOmega,
+ * discretised by eq. (discrmixedstressstokesweak) with the spaces of Sec. 3
+ * (order k >= 2), sigma and omega statically condensed (Sec. 4.2), and solved
+ * by MINRES preconditioned with the block factorisation eq. (mhatinvfactor)
+ * whose velocity block is the multiplicative auxiliary-space preconditioner
+ * of the double Schur complement (Sec. 6.1, Theorem aux_pc_schur, Corollary
+ * aux_pc_mult) applied through the bubble factorisation eq. (factorSsigma).
+ *
+ * Conventions
+ * -----------
+ * Ownership: every pointer argument is owned by the caller.  Pointers named
+ * *_host are host memory; all other data pointers are device memory of the
+ * device the problem is bound to.  The library never allocates device memory:
+ * all of its device state lives in the caller's workspace (mcs_bind).
+ *
+ * Mesh: dim in {2, 3}; vertices[n_vertices * dim] (double, row-major);
+ * elements[n_elements * (dim+1)] (int32, any vertex order).  All of the
+ * boundary is Dirichlet (homogeneous).  The auxiliary multigrid needs the
+ * vertices to form a structured lattice: lattice[a] = vertices per axis,
+ * vertex (i, j[, l]) has index i + lattice[0] * (j + lattice[1] * l), and
+ * every element lies inside one lattice cell.
+ *
+ * Discrete spaces and the coefficient layout (the documented basis; sorted
+ * vertex order per element, barycentric coordinates lambda_i):
+ *   velocity bubbles (zero normal trace), per element n_bub functions
+ *       lambda^alpha (x_a - x_s0), |alpha| = k, s0 = min supp(alpha),
+ *       a in supp(alpha) \ {s0}   (alpha lexicographically descending);
+ *   per free facet one block of n_fb = n_F + n_hat dofs:
+ *       n_F normal dofs: BDM facet functions lambda^beta (x_j0 - x_i) * c with
+ *       normal trace lambda^beta / |F| w.r.t. the facet normal n_F (the
+ *       normal of the sorted facet vertex tuple), beta over the facet
+ *       vertices, |beta| = k;
+ *       n_hat tangential dofs: lambda_F^gamma (x_{f_b} - x_{f_0}),
+ *       b = 1..dim-1 (outer), |gamma| = k-1 (inner);
+ *   pressure, per element n_p functions lambda^gamma, |gamma| = k-1.
+ *   Global vector: [u_bubble: element-major][facet blocks: free facets in
+ *   canonical order (sorted by their sorted vertex tuple)][p: element-major].
+ *   Auxiliary P1 vectors: dim values per free (interior) vertex, vertices in
+ *   increasing index order.
+ *
+ * Force: f_lattice[n_elements][n_lat][dim], the values of f at the degree-m
+ * principal lattice of each element, m = k + 1, points
+ * x = sum_i (beta_i/m) v_i over the element's vertices in the order given in
+ * `elements`, beta in N^{dim+1}, |beta| = m, lexicographically descending.
+ * f is replaced by its Lagrange interpolant on that lattice.
+ *
+ * Errors: functions return MCS_OK (0) or a negative mcs_status; no exception
+ * crosses the ABI; mcs_last_error() gives a thread-local message.  Calls on one
+ * problem are not thread safe.  Kernels run on the stream given to mcs_bind;
+ * functions marked [sync] synchronise that stream before returning.
+ */
+#ifndef MCS_H
+#define MCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MCS_OK = 0,
+  MCS_ERR_ARG = -1,           /* invalid argument (sizes, k, nu <= 0, NaN ...)   */
+  MCS_ERR_MESH = -2,          /* mesh not usable (degenerate element, lattice)   */
+  MCS_ERR_WORKSPACE = -3,     /* workspace missing or too small                  */
+  MCS_ERR_NOT_SPD = -4,       /* Cholesky breakdown in an element / facet block  */
+  MCS_ERR_NOT_CONVERGED = -5, /* max_it reached                                  */
+  MCS_ERR_BREAKDOWN = -6,     /* MINRES breakdown (preconditioner not SPD)       */
+  MCS_ERR_NONFINITE = -7,     /* NaN / Inf encountered                           */
+  MCS_ERR_STATE = -8,         /* call out of order (e.g. solve before condense)  */
+  MCS_ERR_HIP = -9,           /* HIP runtime error                               */
+  MCS_ERR_UNSUPPORTED = -10   /* order / dimension not compiled in               */
+} mcs_status;
+
+typedef enum { MCS_F64 = 0, MCS_F32 = 1 } mcs_dtype;
+
+/* Operators of mcs_apply; x and y are full global vectors (n_dof). */
+typedef enum {
+  MCS_OP_K = 0,       /* y = K x, K = [[A, B^T], [B, 0]]  (eq. femSPmat)           */
+  MCS_OP_A = 1,       /* y_u = A x_u through eq. factorSsigma; y_p = 0              */
+  MCS_OP_ADELTA = 2,  /* y_d = A^d x_d on the facet dofs; other parts 0             */
+  MCS_OP_B = 3,       /* y_p = B x_u; y_u = 0                                       */
+  MCS_OP_BT = 4       /* y_u = B^T x_p; y_p = 0                                     */
+} mcs_op;
+
+/* Operators of mcs_precond_apply. */
+typedef enum {
+  MCS_PC_KHAT = 0,        /* z = K-hat^{-1} r (eq. mhatinvfactor)                   */
+  MCS_PC_AEXT = 1,        /* z_u = A-hat_ext^{-1} r_u (Sec. 6.1)                    */
+  MCS_PC_ADELTA_MULT = 2, /* z_d = A-hat^d_m^{-1} r_d (Corollary aux_pc_mult)       */
+  MCS_PC_SMOOTH_FWD = 3,  /* z_d = `smoothing_steps` forward block-GS sweeps, x0=0  */
+  MCS_PC_SMOOTH_BWD = 4,  /* same with the colours in reverse order                  */
+  MCS_PC_AUX = 5,         /* z_d = E^d C^{-1} E^d^T r_d                              */
+  MCS_PC_EDELTA = 6,      /* z (global) = E^d r, r a P1 vector                       */
+  MCS_PC_EDELTA_T = 7,    /* z (P1) = E^d^T r, r global                              */
+  MCS_PC_MG = 8,          /* z (P1) = C^{-1} r (one V(1,1) cycle)                    */
+  MCS_PC_MP_INV = 9       /* z_p = M_p^{-1} r_p                                      */
+} mcs_pc;
+
+typedef struct {
+  int32_t dim;
+  int32_t n_vertices;
+  const double* vertices_host;   /* [n_vertices * dim] */
+  int32_t n_elements;
+  const int32_t* elements_host;  /* [n_elements * (dim+1)] */
+  int32_t lattice[3];            /* vertices per axis (unused axes: 1) */
+} mcs_mesh;
+
+typedef struct {
+  int32_t order;            /* k >= 2 */
+  int32_t precision;        /* 0: FP64 MINRES; 1: FP32 inner MINRES + FP64 refinement */
+  int32_t smoothing_steps;  /* block-GS sweeps before / after the coarse correction (2) */
+  int32_t max_it;           /* MINRES iteration limit (per inner solve) */
+  double tol;               /* relative tolerance (preconditioned residual / error target) */
+  double inner_tol;         /* precision 1: inner MINRES relative tolerance (1e-5) */
+  int32_t max_outer;        /* precision 1: refinement step limit (10) */
+  int32_t coarse_max;       /* multigrid: coarsest level when free dofs <= coarse_max (1500) */
+} mcs_options;
+
+typedef struct {
+  int64_t n_dof;            /* full global vector length */
+  int64_t n_bubble_dofs, n_facet_dofs, n_pressure_dofs, n_p1_dofs;
+  int64_t off_facet, off_pressure;
+  int32_t n_bub, n_F, n_hat, n_fb, n_p, n_lat;  /* per element / facet */
+  int32_t n_free_facets, n_colours, n_mg_levels;
+  size_t workspace_bytes;   /* bytes the caller must provide to mcs_bind */
+} mcs_info;
+
+typedef struct {
+  int32_t status;
+  int32_t iterations;       /* MINRES iterations (summed over refinement steps) */
+  int32_t outer_steps;      /* refinement steps (precision 1), else 1 */
+  double rel_precond_residual; /* last inner ||r||_{K-hat^{-1}} / ||b||_{K-hat^{-1}} */
+  double rel_residual;      /* ||b - K x||_2 / ||b||_2 (FP64) */
+  double t_solve_ms;        /* wall time of the iteration (excl. load assembly) */
+} mcs_solve_info;
+
+typedef struct mcs_problem mcs_problem;
+
+/* Host only.  Copies the mesh, builds topology, dof numbering, facet colouring
+ * and the multigrid plan; fills *info (sizes, workspace bytes).  Reference:
+ * Sec. 3 (mesh, facets, spaces).  Errors: MCS_ERR_ARG, MCS_ERR_MESH,
+ * MCS_ERR_UNSUPPORTED. */
+int mcs_plan(const mcs_mesh* mesh, const mcs_options* options, mcs_problem** out,
+             mcs_info* info);
+
+/* Binds the problem to the current HIP device, a caller-owned device
+ * workspace of at least info.workspace_bytes bytes (256-byte aligned) and a
+ * stream (hipStream_t, may be NULL).  Uploads the host tables.  [sync]
+ * Errors: MCS_ERR_WORKSPACE, MCS_ERR_HIP. */
+int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream);
+
+/* Element matrices, sigma/omega condensation, bubble condensation, facet
+ * smoother blocks, embedding blocks and the P1 multigrid hierarchy
+ * (Sec. 4.2, eq. bigfemSPmat, eq. factorSsigma, Theorem aux_pc_schur,
+ * eq. defAhat, eq. defED).  nu: device, [n_elements] viscosities (> 0).
+ * [sync]  Errors: MCS_ERR_ARG (nu <= 0 or not finite), MCS_ERR_NOT_SPD
+ * (Cholesky breakdown of an element or facet block). */
+int mcs_condense(mcs_problem* pb, const double* nu);
+
+/* b = load vector (f, phi_u) in the global layout (zero on uhat and p), from
+ * f_lattice (device).  b: device double[n_dof]. */
+int mcs_load(mcs_problem* pb, const double* f_lattice, double* b);
+
+/* y = op x (see mcs_op); x, y: device vectors of length n_dof in dtype dt
+ * (MCS_F32 uses the FP32 operator copies).  Asynchronous. */
+int mcs_apply(mcs_problem* pb, int op, int dt, const void* x, void* y);
+
+/* z = op r (see mcs_pc).  Asynchronous.  P1 vectors have n_p1_dofs entries. */
+int mcs_precond_apply(mcs_problem* pb, int op, int dt, const void* r, void* z);
+
+/* Solves K x = b(f) with preconditioned MINRES from x = 0 (precision 0), or
+ * FP32 inner MINRES with FP64 iterative refinement on the true residual
+ * (precision 1), then subtracts the mean of p.  f_lattice: device force
+ * values; x: device double[n_dof] (output).  info may be NULL.  [sync]
+ * Errors: MCS_ERR_NOT_CONVERGED, MCS_ERR_BREAKDOWN, MCS_ERR_NONFINITE. */
+int mcs_solve(mcs_problem* pb, const double* f_lattice, double* x, mcs_solve_info* info);
+
+/* Same as mcs_solve with a given right-hand side b (device double[n_dof]). */
+int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* info);
+
+/* Subtracts the mean of the pressure from x (device double[n_dof]). */
+int mcs_normalize_pressure(mcs_problem* pb, double* x);
+
+/* Device pointer and element count of an internal array, for inspection:
+ * name in {"Ad", "H", "Aoo", "Aooinv", "Dinv", "EF", "colour", "elem_ff",
+ * "Ad32", "H32"}.  The memory belongs to the caller's workspace. */
+int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count);
+
+/* Host copy of the facet colour of each free facet, and of each element's
+ * free facet ids (-1: Dirichlet facet), for tests.  Arrays sized n_free_facets
+ * and n_elements*(dim+1). */
+int mcs_get_topology(const mcs_problem* pb, int32_t* colour_host, int32_t* elem_ff_host);
+
+void mcs_destroy(mcs_problem* pb);
+const char* mcs_status_string(int status);
+const char* mcs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCS_H */

@@ -1,0 +1,876 @@
+// C ABI of the MCS solver: plan / bind / condense / load / apply /
+// precond_apply / solve.  Host orchestration of the kernels:
+//   K-hat^{-1} (eq. mhatinvfactor) with two A-hat_ext^{-1} applications
+//   (Sec. 6.1), A-hat^d_m^{-1} (Corollary aux_pc_mult: forward coloured block
+//   Gauss-Seidel sweeps, coarse correction E^d C^{-1} E^d^T, backward sweeps),
+//   C = one V(1,1) cycle on the P1 lattice hierarchy, and preconditioned MINRES
+//   (Paige-Saunders) on K (eq. femSPmat), optionally in FP32 inside FP64
+//   iterative refinement.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "kernels_common.h"
+#include "launch.h"
+
+namespace mcs {
+int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb);
+int layout_workspace(mcs_problem* pb);
+int64_t offset_of(const mcs_problem* pb, const char* name);
+const char* last_error();
+}  // namespace mcs
+
+using namespace mcs;
+
+#define HIPCHK(x)                                                                         \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess) {                                                               \
+      set_error("HIP error '%s' at %s:%d", hipGetErrorString(e_), __FILE__, __LINE__);   \
+      return MCS_ERR_HIP;                                                                 \
+    }                                                                                     \
+  } while (0)
+
+namespace {
+
+// work-vector slots
+enum { VX = 0, VR1, VR2, VY, VV, VW1, VW2, VKV, PA1, PG, PS, PT, PT1, PTMP, PB1, VB64, VR64, VX64, VT64, NVEC };
+
+template <typename T>
+T* ws_ptr(mcs_problem* pb, const char* name) {
+  int64_t off = offset_of(pb, name);
+  return off < 0 ? nullptr : reinterpret_cast<T*>(static_cast<char*>(pb->ws) + off);
+}
+
+SolveParams solve_params(mcs_problem* pb) {
+  SolveParams P{};
+  P.s = pb->sz;
+  P.ne = pb->ne;
+  P.nff = pb->nff;
+  P.off_f = pb->off_f;
+  P.off_p = pb->off_p;
+  P.ndof = pb->ndof;
+  P.elem_ff = pb->p.elem_ff;
+  P.facet_el = pb->p.facet_el;
+  P.facet_slot = pb->p.facet_slot;
+  P.colour_facets = pb->p.colour_facets;
+  P.detJ = pb->p.detJ;
+  P.nu = pb->p.nu;
+  P.rBp = pb->p.rBp;
+  P.rMpinv = pb->p.rMpinv;
+  return P;
+}
+
+template <typename R>
+OpPtrs<R> op_ptrs(mcs_problem* pb);
+template <>
+OpPtrs<double> op_ptrs<double>(mcs_problem* pb) {
+  return {pb->p.Ad, pb->p.H, pb->p.Ht, pb->p.Aoo, pb->p.Aooinv, pb->p.Dinv, pb->p.EF};
+}
+template <>
+OpPtrs<float> op_ptrs<float>(mcs_problem* pb) {
+  return {pb->p.Ad32, pb->p.H32, pb->p.Ht32, pb->p.Aoo32, pb->p.Aooinv32, pb->p.Dinv32, pb->p.EF32};
+}
+
+template <typename R>
+std::vector<MGLevelDev> mg_levels(mcs_problem* pb) {
+  std::vector<MGLevelDev> out;
+  const int d = pb->d, st = d == 3 ? 27 : 9;
+  char* base = static_cast<char*>(pb->ws);
+  for (auto& M : pb->mg) {
+    MGLevelDev L{};
+    for (int a = 0; a < 3; ++a) L.n[a] = M.n[a];
+    L.nvert = M.nvert;
+    size_t nA = (size_t)M.nvert * st * d * d, nD = (size_t)M.nvert * d * d;
+    if (sizeof(R) == 8) {
+      L.A = base + M.off_A;
+      L.Dinv = base + M.off_Dinv;
+    } else {
+      L.A = base + M.off_A + nA * 8;
+      L.Dinv = base + M.off_Dinv + nD * 8;
+    }
+    L.x = base + M.off_x;
+    L.b = base + M.off_b;
+    L.r = base + M.off_r;
+    out.push_back(L);
+  }
+  return out;
+}
+
+template <typename R>
+struct Ctx {
+  mcs_problem* pb;
+  hipStream_t st;
+  SolveParams P;
+  OpPtrs<R> O;
+  std::vector<MGLevelDev> L;
+  R* base;
+  R* escr;
+  R* fscr;
+  int64_t n;
+  explicit Ctx(mcs_problem* p) : pb(p), st(p->stream), P(solve_params(p)), O(op_ptrs<R>(p)), L(mg_levels<R>(p)) {
+    n = p->ndof;
+    base = sizeof(R) == 8 ? reinterpret_cast<R*>(p->p.vec) : reinterpret_cast<R*>(p->p.vec32);
+    escr = reinterpret_cast<R*>(p->p.escr);
+    fscr = reinterpret_cast<R*>(p->p.fscr);
+  }
+  R* v(int i) { return base + (int64_t)i * n; }
+
+  // y = op x on full vectors; flags of k_elem_apply.
+  void apply(const R* x, R* y, int flags) {
+    if (flags & 8) launch_fill<R>(st, n, R(0), y);
+    launch_elem_apply<R>(st, P, O, x, y, escr, flags);
+    launch_facet_sum<R>(st, P, escr, nullptr, R(1), y);
+  }
+
+  void vcycle(size_t l) {
+    const int d = pb->d;
+    if (l + 1 == L.size()) {
+      launch_mg_coarse<R>(st, pb->nc, pb->p.Cinv, pb->p.cmap, L[l]);
+      return;
+    }
+    launch_mg_point<R>(st, d, L[l], 0);
+    launch_mg_point<R>(st, d, L[l], 1);
+    launch_mg_restrict<R>(st, d, L[l], L[l + 1]);
+    vcycle(l + 1);
+    launch_mg_prolong<R>(st, d, L[l], L[l + 1]);
+    launch_mg_point<R>(st, d, L[l], 2);
+  }
+
+  void sweeps(R* x, const R* s, bool forward) {
+    for (int it = 0; it < pb->opt.smoothing_steps; ++it)
+      for (int cc = 0; cc < pb->ncol; ++cc) {
+        int c = forward ? cc : pb->ncol - 1 - cc;
+        launch_smooth_phase<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s);
+      }
+  }
+
+  // z_d = E^d C^{-1} E^d^T r_d  (added to z if add)
+  void aux(const R* r, R* z, int add) {
+    launch_edt<R>(st, P, O, r, fscr, pb->nfv, pb->p.vinc_off, pb->p.vinc, pb->p.free_to_lat, (R*)L[0].b, 0);
+    vcycle(0);
+    launch_ed<R>(st, P, O, pb->p.facet_vfree, pb->p.free_to_lat, (const R*)L[0].x, z, add, 0);
+  }
+
+  // x = A-hat^d_m^{-1} s (facet parts; x fully overwritten)
+  void ad_mult_inv(const R* s, R* x) {
+    R* tmp = v(PTMP);
+    launch_fill<R>(st, n, R(0), x);
+    sweeps(x, s, true);
+    launch_elem_apply<R>(st, P, O, x, x, escr, 1 | 8);
+    launch_facet_sum<R>(st, P, escr, s, R(-1), tmp);
+    aux(tmp, x, 1);
+    sweeps(x, s, false);
+  }
+
+  // y = A-hat_ext^{-1} r (velocity parts; pressure part of y set to 0)
+  void ext_inv(const R* r, R* y) {
+    R *S = v(PS), *T = v(PT), *T1 = v(PT1);
+    launch_ext_pre<R>(st, P, O, r, T1, escr);
+    launch_facet_sum<R>(st, P, escr, r, R(-1), S);
+    ad_mult_inv(S, T);
+    launch_ext_post<R>(st, P, O, T, T1, y);
+    launch_axpby<R>(st, pb->nff * pb->sz.nfb, 1.0, T + pb->off_f, 0.0, y + pb->off_f);
+    launch_fill<R>(st, pb->ndof - pb->off_p, R(0), y + pb->off_p);
+  }
+
+  // z = K-hat^{-1} r:  a = A^{-1} r_u;  z_p = M_p^{-1}(r_p - B a);  z_u = a - A^{-1} B^T z_p
+  void khat(const R* r, R* z) {
+    R *A1 = v(PA1), *G = v(PG), *B1 = v(PB1);
+    ext_inv(r, A1);
+    launch_elem_press<R>(st, P, A1, r, z, 1);
+    launch_elem_apply<R>(st, P, O, z, G, escr, 2 | 16);
+    launch_facet_sum<R>(st, P, escr, nullptr, R(1), G);
+    ext_inv(G, B1);
+    launch_axpby<R>(st, pb->off_p, 1.0, A1, 0.0, z);
+    launch_axpby<R>(st, pb->off_p, -1.0, B1, 1.0, z);
+  }
+
+  double dot(const R* a, const R* b, double* host) {
+    launch_dot<R>(st, n, a, b, pb->p.red, pb->p.scal);
+    hipMemcpyAsync(host, pb->p.scal, sizeof(double), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    return *host;
+  }
+
+  // Preconditioned MINRES from x = 0 for K x = b.  Returns status.
+  int minres(const R* b, R* x, double tol, int maxit, double stop_beta1, int* its, double* rel, double* beta1_out,
+             double* host) {
+    R *r1 = v(VR1), *r2 = v(VR2), *y = v(VY), *vv = v(VV), *w1 = v(VW1), *w2 = v(VW2), *kv = v(VKV);
+    launch_fill<R>(st, n, R(0), x);
+    launch_fill<R>(st, n, R(0), r1);
+    launch_fill<R>(st, n, R(0), w1);
+    launch_fill<R>(st, n, R(0), w2);
+    launch_axpby<R>(st, n, 1.0, b, 0.0, r2);
+    khat(r2, y);
+    double b2 = dot(r2, y, host);
+    *its = 0;
+    if (!std::isfinite(b2)) return MCS_ERR_NONFINITE;
+    if (b2 < 0) return MCS_ERR_BREAKDOWN;
+    double beta1 = std::sqrt(b2);
+    *beta1_out = beta1;
+    *rel = 0.0;
+    if (beta1 == 0.0 || beta1 <= stop_beta1) return MCS_OK;
+    double beta = beta1, oldb = 0.0, dbar = 0.0, eps = 0.0, phibar = beta1, cs = -1.0, sn = 0.0;
+    for (int it = 1; it <= maxit; ++it) {
+      launch_axpby<R>(st, n, 1.0 / beta, y, 0.0, vv);
+      apply(vv, kv, 1 | 2 | 4);
+      if (it > 1) launch_axpby<R>(st, n, -beta / oldb, r1, 1.0, kv);
+      double alpha = dot(vv, kv, host);
+      launch_axpby<R>(st, n, -alpha / beta, r2, 1.0, kv);
+      std::swap(r1, r2);   // r1 <- r2
+      std::swap(r2, kv);   // r2 <- new residual, kv <- old r1 buffer (free)
+      khat(r2, y);
+      oldb = beta;
+      double bb = dot(r2, y, host);
+      if (!std::isfinite(bb) || !std::isfinite(alpha)) return MCS_ERR_NONFINITE;
+      if (bb < 0) return MCS_ERR_BREAKDOWN;
+      beta = std::sqrt(bb);
+      double oldeps = eps;
+      double delta = cs * dbar + sn * alpha;
+      double gbar = sn * dbar - cs * alpha;
+      eps = sn * beta;
+      dbar = -cs * beta;
+      double gamma = std::hypot(gbar, beta);
+      if (gamma == 0.0) gamma = 1e-300;
+      cs = gbar / gamma;
+      sn = beta / gamma;
+      double phi = cs * phibar;
+      phibar = sn * phibar;
+      launch_minres_w<R>(st, n, vv, w1, w2, x, 1.0 / gamma, -oldeps / gamma, -delta / gamma, phi);
+      std::swap(w1, w2);
+      *its = it;
+      *rel = phibar / beta1;
+      if (phibar <= tol * beta1) return MCS_OK;
+    }
+    return MCS_ERR_NOT_CONVERGED;
+  }
+};
+
+int check_bound(mcs_problem* pb) {
+  if (!pb) {
+    set_error("null problem");
+    return MCS_ERR_ARG;
+  }
+  if (!pb->ws) {
+    set_error("problem is not bound to a workspace");
+    return MCS_ERR_STATE;
+  }
+  return MCS_OK;
+}
+
+int sync_status(mcs_problem* pb, const char* what) {
+  HIPCHK(hipStreamSynchronize(pb->stream));
+  HIPCHK(hipGetLastError());
+  int st = 0;
+  HIPCHK(hipMemcpy(&st, pb->p.scal + 200, sizeof(int), hipMemcpyDeviceToHost));
+  if (st & 8) {
+    set_error("%s: viscosity must be positive and finite", what);
+    return MCS_ERR_ARG;
+  }
+  if (st & 7) {
+    set_error("%s: Cholesky breakdown (code %d: 1 element, 2 facet block, 4 coarse grid)", what, st);
+    return MCS_ERR_NOT_SPD;
+  }
+  return MCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mcs_status_string(int status) {
+  switch (status) {
+    case MCS_OK: return "ok";
+    case MCS_ERR_ARG: return "invalid argument";
+    case MCS_ERR_MESH: return "invalid mesh";
+    case MCS_ERR_WORKSPACE: return "workspace missing or too small";
+    case MCS_ERR_NOT_SPD: return "Cholesky breakdown (matrix not SPD)";
+    case MCS_ERR_NOT_CONVERGED: return "not converged";
+    case MCS_ERR_BREAKDOWN: return "MINRES breakdown";
+    case MCS_ERR_NONFINITE: return "non-finite value";
+    case MCS_ERR_STATE: return "call out of order";
+    case MCS_ERR_HIP: return "HIP runtime error";
+    case MCS_ERR_UNSUPPORTED: return "unsupported order or dimension";
+    default: return "unknown status";
+  }
+}
+
+const char* mcs_last_error(void) { return last_error(); }
+
+int mcs_plan(const mcs_mesh* mesh, const mcs_options* options, mcs_problem** out, mcs_info* info) {
+  if (!mesh || !options || !out) {
+    set_error("null argument");
+    return MCS_ERR_ARG;
+  }
+  *out = nullptr;
+  mcs_problem* pb = new (std::nothrow) mcs_problem();
+  if (!pb) {
+    set_error("out of host memory");
+    return MCS_ERR_ARG;
+  }
+  int rc;
+  try {
+    rc = plan_problem(mesh, options, pb);
+    if (rc == MCS_OK) {
+      pb->ref = build_ref_tables(pb->d, pb->sz.k);
+      rc = layout_workspace(pb);
+    }
+  } catch (const std::exception& ex) {
+    set_error("plan failed: %s", ex.what());
+    rc = MCS_ERR_ARG;
+  }
+  if (rc != MCS_OK) {
+    delete pb;
+    return rc;
+  }
+  if (info) {
+    const Sizes& s = pb->sz;
+    info->n_dof = pb->ndof;
+    info->n_bubble_dofs = pb->off_f;
+    info->n_facet_dofs = pb->off_p - pb->off_f;
+    info->n_pressure_dofs = pb->ndof - pb->off_p;
+    info->n_p1_dofs = pb->np1;
+    info->off_facet = pb->off_f;
+    info->off_pressure = pb->off_p;
+    info->n_bub = s.nb;
+    info->n_F = s.nF;
+    info->n_hat = s.nh;
+    info->n_fb = s.nfb;
+    info->n_p = s.np;
+    info->n_lat = s.nlat;
+    info->n_free_facets = (int32_t)pb->nff;
+    info->n_colours = pb->ncol;
+    info->n_mg_levels = (int32_t)pb->mg.size();
+    info->workspace_bytes = pb->ws_bytes;
+  }
+  *out = pb;
+  return MCS_OK;
+}
+
+int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
+  if (!pb) {
+    set_error("null problem");
+    return MCS_ERR_ARG;
+  }
+  if (!workspace || bytes < pb->ws_bytes || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
+    set_error("workspace must be >= %zu bytes and 256-byte aligned", pb->ws_bytes);
+    return MCS_ERR_WORKSPACE;
+  }
+  HIPCHK(hipGetDevice(&pb->device));
+  pb->ws = workspace;
+  pb->stream = static_cast<hipStream_t>(stream);
+  pb->condensed = false;
+  DevPtrs& p = pb->p;
+  p.elem_ff = ws_ptr<int32_t>(pb, "elem_ff");
+  p.elem_verts = ws_ptr<int32_t>(pb, "elem_verts");
+  p.elem_perm = ws_ptr<int32_t>(pb, "elem_perm");
+  p.facet_el = ws_ptr<int32_t>(pb, "facet_el");
+  p.facet_slot = ws_ptr<int32_t>(pb, "facet_slot");
+  p.colour_facets = ws_ptr<int32_t>(pb, "colour_facets");
+  p.facet_vfree = ws_ptr<int32_t>(pb, "facet_vfree");
+  p.vinc_off = ws_ptr<int32_t>(pb, "vinc_off");
+  p.vinc = ws_ptr<int32_t>(pb, "vinc");
+  p.vert_elem_off = ws_ptr<int32_t>(pb, "vert_elem_off");
+  p.vert_elem = ws_ptr<int32_t>(pb, "vert_elem");
+  p.coords = ws_ptr<double>(pb, "coords");
+  p.vfree_of_lat = ws_ptr<int32_t>(pb, "vfree_of_lat");
+  p.free_to_lat = ws_ptr<int32_t>(pb, "free_to_lat");
+  p.rV = ws_ptr<double>(pb, "rV");
+  p.rBf = ws_ptr<double>(pb, "rBf");
+  p.rU = ws_ptr<double>(pb, "rU");
+  p.rL = ws_ptr<double>(pb, "rL");
+  p.rD = ws_ptr<double>(pb, "rD");
+  p.rBp = ws_ptr<double>(pb, "rBp");
+  p.rMp = ws_ptr<double>(pb, "rMp");
+  p.rMpinv = ws_ptr<double>(pb, "rMpinv");
+  p.rRf = ws_ptr<double>(pb, "rRf");
+  p.rcn = ws_ptr<double>(pb, "rcn");
+  p.rct = ws_ptr<double>(pb, "rct");
+  p.rpconst = ws_ptr<double>(pb, "rpconst");
+  p.rpmom = ws_ptr<double>(pb, "rpmom");
+  p.rlatmap = ws_ptr<int32_t>(pb, "rlatmap");
+  p.nu = ws_ptr<double>(pb, "nu");
+  p.detJ = ws_ptr<double>(pb, "detJ");
+  p.Ad = ws_ptr<double>(pb, "Ad");
+  p.H = ws_ptr<double>(pb, "H");
+  p.Ht = ws_ptr<double>(pb, "Ht");
+  p.Aoo = ws_ptr<double>(pb, "Aoo");
+  p.Aooinv = ws_ptr<double>(pb, "Aooinv");
+  p.Ad32 = ws_ptr<float>(pb, "Ad32");
+  p.H32 = ws_ptr<float>(pb, "H32");
+  p.Ht32 = ws_ptr<float>(pb, "Ht32");
+  p.Aoo32 = ws_ptr<float>(pb, "Aoo32");
+  p.Aooinv32 = ws_ptr<float>(pb, "Aooinv32");
+  p.Dinv = ws_ptr<double>(pb, "Dinv");
+  p.EF = ws_ptr<double>(pb, "EF");
+  p.Dinv32 = ws_ptr<float>(pb, "Dinv32");
+  p.EF32 = ws_ptr<float>(pb, "EF32");
+  p.Cinv = ws_ptr<double>(pb, "Cinv");
+  p.cmap = ws_ptr<int32_t>(pb, "cmap");
+  p.cscratch = ws_ptr<double>(pb, "cscratch");
+  p.escr = ws_ptr<double>(pb, "escr");
+  p.escr2 = ws_ptr<double>(pb, "escr2");
+  p.fscr = ws_ptr<double>(pb, "fscr");
+  p.red = ws_ptr<double>(pb, "red");
+  p.scal = ws_ptr<double>(pb, "scal");
+  p.vec = ws_ptr<double>(pb, "vec");
+  p.vec32 = ws_ptr<float>(pb, "vec32");
+  p.p1 = ws_ptr<double>(pb, "p1");
+  p.p132 = ws_ptr<float>(pb, "p132");
+
+  hipStream_t st = pb->stream;
+  auto up = [&](void* dst, const void* src, size_t n) -> hipError_t {
+    if (n == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
+  };
+  const RefTables& r = pb->ref;
+  HIPCHK(up(p.elem_ff, pb->h_elem_ff.data(), pb->h_elem_ff.size() * 4));
+  HIPCHK(up(p.elem_verts, pb->h_elem_verts.data(), pb->h_elem_verts.size() * 4));
+  HIPCHK(up(p.elem_perm, pb->h_elem_perm.data(), pb->h_elem_perm.size() * 4));
+  HIPCHK(up(p.facet_el, pb->h_facet_el.data(), pb->h_facet_el.size() * 4));
+  HIPCHK(up(p.facet_slot, pb->h_facet_slot.data(), pb->h_facet_slot.size() * 4));
+  HIPCHK(up(p.colour_facets, pb->h_colour_facets.data(), pb->h_colour_facets.size() * 4));
+  HIPCHK(up(p.facet_vfree, pb->h_facet_vfree.data(), pb->h_facet_vfree.size() * 4));
+  HIPCHK(up(p.vinc_off, pb->h_vinc_off.data(), pb->h_vinc_off.size() * 4));
+  HIPCHK(up(p.vinc, pb->h_vinc.data(), pb->h_vinc.size() * 4));
+  HIPCHK(up(p.vert_elem_off, pb->h_vert_elem_off.data(), pb->h_vert_elem_off.size() * 4));
+  HIPCHK(up(p.vert_elem, pb->h_vert_elem.data(), pb->h_vert_elem.size() * 4));
+  HIPCHK(up(p.coords, pb->h_coords.data(), pb->h_coords.size() * 8));
+  HIPCHK(up(p.vfree_of_lat, pb->h_vfree_of_lat.data(), pb->h_vfree_of_lat.size() * 4));
+  HIPCHK(up(p.free_to_lat, pb->h_free_to_lat.data(), pb->h_free_to_lat.size() * 4));
+  HIPCHK(up(p.rV, r.V.data(), r.V.size() * 8));
+  HIPCHK(up(p.rBf, r.Bf.data(), r.Bf.size() * 8));
+  HIPCHK(up(p.rU, r.U.data(), r.U.size() * 8));
+  HIPCHK(up(p.rL, r.L.data(), r.L.size() * 8));
+  HIPCHK(up(p.rD, r.D.data(), r.D.size() * 8));
+  HIPCHK(up(p.rBp, r.Bp.data(), r.Bp.size() * 8));
+  HIPCHK(up(p.rMp, r.Mp.data(), r.Mp.size() * 8));
+  HIPCHK(up(p.rMpinv, r.Mpinv.data(), r.Mpinv.size() * 8));
+  HIPCHK(up(p.rRf, r.Rf.data(), r.Rf.size() * 8));
+  HIPCHK(up(p.rcn, r.cn.data(), r.cn.size() * 8));
+  HIPCHK(up(p.rct, r.ct.data(), r.ct.size() * 8));
+  HIPCHK(up(p.rpconst, r.pconst.data(), r.pconst.size() * 8));
+  HIPCHK(up(p.rpmom, r.pmom.data(), r.pmom.size() * 8));
+  HIPCHK(up(p.rlatmap, r.latmap.data(), r.latmap.size() * 4));
+  HIPCHK(up(p.cmap, pb->h_cmap.data(), pb->h_cmap.size() * 4));
+  // multigrid lattice vectors start (and stay) zero on the boundary
+  const int d = pb->d;
+  for (auto& M : pb->mg) {
+    char* base = static_cast<char*>(pb->ws);
+    HIPCHK(hipMemsetAsync(base + M.off_x, 0, (size_t)M.nvert * d * 8, st));
+    HIPCHK(hipMemsetAsync(base + M.off_b, 0, (size_t)M.nvert * d * 8, st));
+    HIPCHK(hipMemsetAsync(base + M.off_r, 0, (size_t)M.nvert * d * 8, st));
+  }
+  HIPCHK(hipMemsetAsync(p.scal, 0, 256 * 8, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return MCS_OK;
+}
+
+int mcs_condense(mcs_problem* pb, const double* nu) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  if (!nu) {
+    set_error("null viscosity");
+    return MCS_ERR_ARG;
+  }
+  hipStream_t st = pb->stream;
+  DevPtrs& p = pb->p;
+  int* status = reinterpret_cast<int*>(p.scal + 200);
+  HIPCHK(hipMemsetAsync(status, 0, sizeof(int), st));
+  HIPCHK(hipMemcpyAsync(p.nu, nu, pb->ne * sizeof(double), hipMemcpyDeviceToDevice, st));
+  launch_check_nu(st, p.nu, pb->ne, status);
+  rc = sync_status(pb, "condense");
+  if (rc) return rc;
+
+  CondParams C{};
+  C.s = pb->sz;
+  C.ne = pb->ne;
+  C.slot_doubles = pb->slot_doubles;
+  C.elem_verts = p.elem_verts;
+  C.coords = p.coords;
+  C.nu = p.nu;
+  C.rV = p.rV;
+  C.rBf = p.rBf;
+  C.rU = p.rU;
+  C.rL = p.rL;
+  C.rD = p.rD;
+  for (int f = 0; f < 4; ++f) C.facet_measure[f] = pb->ref.facet_measure[f];
+  C.scratch = p.cscratch;
+  C.detJ = p.detJ;
+  C.Ad = p.Ad;
+  C.H = p.H;
+  C.Ht = p.Ht;
+  C.Aoo = p.Aoo;
+  C.Aooinv = p.Aooinv;
+  C.Ad32 = p.Ad32;
+  C.H32 = p.H32;
+  C.Ht32 = p.Ht32;
+  C.Aoo32 = p.Aoo32;
+  C.Aooinv32 = p.Aooinv32;
+  C.status = status;
+  launch_condense(st, C, (int)pb->n_slots);
+
+  FacetSetupParams F{};
+  F.s = pb->sz;
+  F.nff = pb->nff;
+  F.facet_el = p.facet_el;
+  F.facet_slot = p.facet_slot;
+  F.elem_verts = p.elem_verts;
+  F.coords = p.coords;
+  F.Ad = p.Ad;
+  F.rcn = p.rcn;
+  F.rct = p.rct;
+  F.Dinv = p.Dinv;
+  F.Dinv32 = p.Dinv32;
+  F.EF = p.EF;
+  F.EF32 = p.EF32;
+  F.status = status;
+  if (pb->nff > 0) launch_facet_setup(st, F);
+
+  // P1 multigrid hierarchy
+  const int d = pb->d, stn = d == 3 ? 27 : 9;
+  char* base = static_cast<char*>(pb->ws);
+  P1Params A{};
+  A.d = d;
+  for (int a = 0; a < 3; ++a) A.n[a] = pb->mg[0].n[a];
+  A.nvert = pb->mg[0].nvert;
+  A.vert_elem_off = p.vert_elem_off;
+  A.vert_elem = p.vert_elem;
+  A.elem_verts = p.elem_verts;
+  A.coords = p.coords;
+  A.nu = p.nu;
+  A.A = reinterpret_cast<double*>(base + pb->mg[0].off_A);
+  launch_p1_assemble(st, A);
+  for (size_t l = 0; l < pb->mg.size(); ++l) {
+    MGLevel& M = pb->mg[l];
+    MGSetupParams S{};
+    S.d = d;
+    for (int a = 0; a < 3; ++a) S.n[a] = M.n[a];
+    S.nvert = M.nvert;
+    S.A = reinterpret_cast<double*>(base + M.off_A);
+    S.Dinv = reinterpret_cast<double*>(base + M.off_Dinv);
+    S.Dinv32 = reinterpret_cast<float*>(base + M.off_Dinv + (size_t)M.nvert * d * d * 8);
+    size_t nA = (size_t)M.nvert * stn * d * d;
+    if (l + 1 < pb->mg.size()) {
+      MGLevel& Mc = pb->mg[l + 1];
+      for (int a = 0; a < 3; ++a) S.nc[a] = Mc.n[a];
+      S.nvert_c = Mc.nvert;
+      S.Ac = reinterpret_cast<double*>(base + Mc.off_A);
+      launch_mg_l1(st, S);
+      launch_mg_rap(st, S);
+    } else {
+      S.ncd = pb->nc;
+      S.cmap = p.cmap;
+      // dense coarse matrix and its Cholesky workspace borrow the condensation scratch
+      double* Cd = p.cscratch;
+      double* W = p.cscratch + (size_t)pb->nc * pb->nc;
+      if ((int64_t)(2 * pb->nc * pb->nc) > pb->n_slots * pb->slot_doubles) {
+        set_error("coarsest level too large for the scratch area");
+        return MCS_ERR_WORKSPACE;
+      }
+      if (pb->nc > 0) launch_coarse(st, S, Cd, W, p.Cinv, status);
+    }
+    launch_to_f32(st, reinterpret_cast<double*>(base + M.off_A),
+                  reinterpret_cast<float*>(base + M.off_A + nA * 8), (int64_t)nA);
+  }
+  rc = sync_status(pb, "condense");
+  if (rc) return rc;
+  pb->condensed = true;
+  return MCS_OK;
+}
+
+int mcs_load(mcs_problem* pb, const double* f_lattice, double* b) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  if (!pb->condensed) {
+    set_error("mcs_load needs mcs_condense first");
+    return MCS_ERR_STATE;
+  }
+  if (!f_lattice || !b) {
+    set_error("null argument");
+    return MCS_ERR_ARG;
+  }
+  hipStream_t st = pb->stream;
+  DevPtrs& p = pb->p;
+  CondParams C{};
+  C.s = pb->sz;
+  C.ne = pb->ne;
+  C.elem_verts = p.elem_verts;
+  C.coords = p.coords;
+  SolveParams P = solve_params(pb);
+  launch_fill<double>(st, pb->ndof, 0.0, b);
+  launch_load(st, C, P, p.elem_perm, p.rlatmap, p.rRf, f_lattice, b, p.escr);
+  launch_facet_sum<double>(st, P, p.escr, nullptr, 1.0, b);
+  HIPCHK(hipGetLastError());
+  return MCS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename R>
+int apply_op(mcs_problem* pb, int op, const void* xv, void* yv) {
+  Ctx<R> c(pb);
+  const R* x = static_cast<const R*>(xv);
+  R* y = static_cast<R*>(yv);
+  switch (op) {
+    case MCS_OP_K: c.apply(x, y, 1 | 2 | 4); break;
+    case MCS_OP_A: c.apply(x, y, 1 | 16); break;
+    case MCS_OP_ADELTA: c.apply(x, y, 1 | 8); break;
+    case MCS_OP_B: c.apply(x, y, 4 | 16); break;
+    case MCS_OP_BT: c.apply(x, y, 2 | 16); break;
+    default:
+      set_error("unknown operator %d", op);
+      return MCS_ERR_ARG;
+  }
+  HIPCHK(hipGetLastError());
+  return MCS_OK;
+}
+
+template <typename R>
+int precond_op(mcs_problem* pb, int op, const void* rv, void* zv) {
+  Ctx<R> c(pb);
+  const R* r = static_cast<const R*>(rv);
+  R* z = static_cast<R*>(zv);
+  const int d = pb->d;
+  switch (op) {
+    case MCS_PC_KHAT: c.khat(r, z); break;
+    case MCS_PC_AEXT: c.ext_inv(r, z); break;
+    case MCS_PC_ADELTA_MULT: c.ad_mult_inv(r, z); break;
+    case MCS_PC_SMOOTH_FWD:
+    case MCS_PC_SMOOTH_BWD:
+      launch_fill<R>(c.st, c.n, R(0), z);
+      c.sweeps(z, r, op == MCS_PC_SMOOTH_FWD);
+      break;
+    case MCS_PC_AUX:
+      launch_fill<R>(c.st, c.n, R(0), z);
+      c.aux(r, z, 1);
+      break;
+    case MCS_PC_EDELTA:
+      launch_fill<R>(c.st, c.n, R(0), z);
+      launch_ed<R>(c.st, c.P, c.O, pb->p.facet_vfree, pb->p.free_to_lat, r, z, 0, 1);
+      break;
+    case MCS_PC_EDELTA_T:
+      launch_edt<R>(c.st, c.P, c.O, r, c.fscr, pb->nfv, pb->p.vinc_off, pb->p.vinc, pb->p.free_to_lat, z, 1);
+      break;
+    case MCS_PC_MG: {
+      R* b0 = (R*)c.L[0].b;
+      R* x0 = (R*)c.L[0].x;
+      launch_scatter_compact<R>(c.st, pb->nfv, d, pb->p.free_to_lat, r, b0);
+      c.vcycle(0);
+      launch_gather_compact<R>(c.st, pb->nfv, d, pb->p.free_to_lat, x0, z);
+      break;
+    }
+    case MCS_PC_MP_INV:
+      launch_fill<R>(c.st, c.n, R(0), z);
+      launch_elem_press<R>(c.st, c.P, r, r, z, 0);
+      break;
+    default:
+      set_error("unknown preconditioner operator %d", op);
+      return MCS_ERR_ARG;
+  }
+  HIPCHK(hipGetLastError());
+  return MCS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mcs_apply(mcs_problem* pb, int op, int dt, const void* x, void* y) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  if (!pb->condensed) {
+    set_error("mcs_apply needs mcs_condense first");
+    return MCS_ERR_STATE;
+  }
+  if (!x || !y) {
+    set_error("null vector");
+    return MCS_ERR_ARG;
+  }
+  if (dt == MCS_F64) return apply_op<double>(pb, op, x, y);
+  if (dt == MCS_F32) return apply_op<float>(pb, op, x, y);
+  set_error("unknown dtype %d", dt);
+  return MCS_ERR_ARG;
+}
+
+int mcs_precond_apply(mcs_problem* pb, int op, int dt, const void* r, void* z) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  if (!pb->condensed) {
+    set_error("mcs_precond_apply needs mcs_condense first");
+    return MCS_ERR_STATE;
+  }
+  if (!r || !z) {
+    set_error("null vector");
+    return MCS_ERR_ARG;
+  }
+  if (dt == MCS_F64) return precond_op<double>(pb, op, r, z);
+  if (dt == MCS_F32) return precond_op<float>(pb, op, r, z);
+  set_error("unknown dtype %d", dt);
+  return MCS_ERR_ARG;
+}
+
+int mcs_normalize_pressure(mcs_problem* pb, double* x) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  if (!pb->condensed) {
+    set_error("mcs_normalize_pressure needs mcs_condense first");
+    return MCS_ERR_STATE;
+  }
+  SolveParams P = solve_params(pb);
+  launch_pressure_mean(pb->stream, P, pb->p.rpmom, pb->p.rpconst, x, pb->p.red);
+  HIPCHK(hipGetLastError());
+  return MCS_OK;
+}
+
+int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* info) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  if (!pb->condensed) {
+    set_error("mcs_solve needs mcs_condense first");
+    return MCS_ERR_STATE;
+  }
+  if (!b || !x) {
+    set_error("null vector");
+    return MCS_ERR_ARG;
+  }
+  double* host = nullptr;
+  HIPCHK(hipHostMalloc((void**)&host, 64));
+  hipStream_t st = pb->stream;
+  const int64_t n = pb->ndof;
+  mcs_solve_info inf{};
+  auto t0 = std::chrono::steady_clock::now();
+  Ctx<double> c64(pb);
+  if (pb->opt.precision == 0) {
+    int its = 0;
+    double rel = 0, b1 = 0;
+    rc = c64.minres(b, x, pb->opt.tol, pb->opt.max_it, -1.0, &its, &rel, &b1, host);
+    inf.iterations = its;
+    inf.outer_steps = 1;
+    inf.rel_precond_residual = rel;
+  } else {
+    Ctx<float> c32(pb);
+    double* r64 = c64.v(VR64);
+    float* r32 = c32.v(VB64);   // slot beyond the FP32 MINRES vectors
+    float* d32 = c32.v(VX64);
+    launch_fill<double>(st, n, 0.0, x);
+    launch_axpby<double>(st, n, 1.0, b, 0.0, r64);
+    double beta0 = -1.0, rel = 1.0;
+    int total = 0, outer = 0;
+    rc = MCS_OK;
+    for (outer = 0; outer < pb->opt.max_outer; ++outer) {
+      double rn = std::sqrt(c64.dot(r64, r64, host));
+      if (!std::isfinite(rn)) {
+        rc = MCS_ERR_NONFINITE;
+        break;
+      }
+      if (rn == 0.0) {
+        rel = 0.0;
+        break;
+      }
+      launch_scale_convert<double, float>(st, n, 1.0 / rn, r64, r32, 0);
+      int its = 0;
+      double irel = 0, b1 = 0;
+      double stop = (beta0 > 0) ? pb->opt.tol * beta0 / rn : -1.0;
+      int irc = c32.minres(r32, d32, pb->opt.inner_tol, pb->opt.max_it, stop, &its, &irel, &b1, host);
+      if (beta0 < 0) beta0 = b1 * rn;
+      rel = b1 * rn / beta0;
+      total += its;
+      if (irc == MCS_ERR_NONFINITE || irc == MCS_ERR_BREAKDOWN) {
+        rc = irc;
+        break;
+      }
+      if (rel <= pb->opt.tol) break;   // current outer residual already small enough
+      launch_scale_convert<float, double>(st, n, rn, d32, x, 1);
+      // r = b - K x in FP64
+      double* kx = c64.v(VT64);
+      c64.apply(x, kx, 1 | 2 | 4);
+      launch_axpby<double>(st, n, 1.0, b, 0.0, r64);
+      launch_axpby<double>(st, n, -1.0, kx, 1.0, r64);
+    }
+    if (rc == MCS_OK && rel > pb->opt.tol) rc = MCS_ERR_NOT_CONVERGED;
+    inf.iterations = total;
+    inf.outer_steps = outer + 1;
+    inf.rel_precond_residual = rel;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  inf.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  // true residual ||b - K x|| / ||b|| in FP64 (before pressure normalisation;
+  // the constant pressure mode is in the kernel of K)
+  {
+    double* kx = c64.v(VT64);
+    double* rr = c64.v(VR64);
+    c64.apply(x, kx, 1 | 2 | 4);
+    launch_axpby<double>(st, n, 1.0, b, 0.0, rr);
+    launch_axpby<double>(st, n, -1.0, kx, 1.0, rr);
+    double rn = c64.dot(rr, rr, host);
+    double bn = c64.dot(b, b, host);
+    inf.rel_residual = bn > 0 ? std::sqrt(rn / bn) : std::sqrt(rn);
+  }
+  SolveParams P = solve_params(pb);
+  launch_pressure_mean(st, P, pb->p.rpmom, pb->p.rpconst, x, pb->p.red);
+  hipError_t he = hipStreamSynchronize(st);
+  hipHostFree(host);
+  if (he != hipSuccess) {
+    set_error("HIP error '%s' in solve", hipGetErrorString(he));
+    return MCS_ERR_HIP;
+  }
+  inf.status = rc;
+  if (info) *info = inf;
+  if (rc) set_error("solve: %s after %d iterations (rel %.3e)", mcs_status_string(rc), inf.iterations,
+                    inf.rel_precond_residual);
+  return rc;
+}
+
+int mcs_solve(mcs_problem* pb, const double* f_lattice, double* x, mcs_solve_info* info) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  double* b = pb->p.vec + (int64_t)VB64 * pb->ndof;
+  rc = mcs_load(pb, f_lattice, b);
+  if (rc) return rc;
+  return mcs_solve_rhs(pb, b, x, info);
+}
+
+int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  if (!name || !ptr || !count) {
+    set_error("null argument");
+    return MCS_ERR_ARG;
+  }
+  const Sizes& s = pb->sz;
+  struct E {
+    const char* n;
+    int64_t cnt;
+  } table[] = {{"Ad", pb->ne * s.nd * s.nd},   {"H", pb->ne * s.nb * s.nd},       {"Ht", pb->ne * s.nb * s.nd},
+               {"Aoo", pb->ne * s.nb * s.nb},  {"Aooinv", pb->ne * s.nb * s.nb},  {"Dinv", pb->nff * s.nfb * s.nfb},
+               {"EF", pb->nff * s.nfb * pb->d * pb->d}, {"Ad32", pb->ne * s.nd * s.nd}, {"H32", pb->ne * s.nb * s.nd},
+               {"detJ", pb->ne},               {"colour_facets", pb->nff},        {"elem_ff", pb->ne * (pb->d + 1)}};
+  for (auto& e : table)
+    if (!strcmp(e.n, name)) {
+      *ptr = ws_ptr<char>(pb, name);
+      *count = e.cnt;
+      return MCS_OK;
+    }
+  set_error("unknown array '%s'", name);
+  return MCS_ERR_ARG;
+}
+
+int mcs_get_topology(const mcs_problem* pb, int32_t* colour_host, int32_t* elem_ff_host) {
+  if (!pb) {
+    set_error("null problem");
+    return MCS_ERR_ARG;
+  }
+  if (colour_host) std::copy(pb->h_colour.begin(), pb->h_colour.end(), colour_host);
+  if (elem_ff_host) std::copy(pb->h_elem_ff.begin(), pb->h_elem_ff.end(), elem_ff_host);
+  return MCS_OK;
+}
+
+void mcs_destroy(mcs_problem* pb) { delete pb; }
+
+}  // extern "C"

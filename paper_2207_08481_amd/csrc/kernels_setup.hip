@@ -1,0 +1,902 @@
+// Setup kernels: element matrices and static condensation (Sec. 4.2,
+// eq. bigfemSPmat, eq. factorSsigma), facet smoother blocks (Theorem
+// aux_pc_schur), embedding blocks E^d (eq. defE, eq. defED) and the P1
+// multigrid hierarchy for A-bar (eq. defAhat).
+//
+// Condensation I is computed in a reduced form that is algebraically equal to
+// A = A^div - B_sigma M^{-1} B_sigma^T: the stress space is described by an
+// L2-orthonormal scalar basis psi_a times an orthonormal basis D_m of
+// trace-free matrices, the symmetry multiplier omega is eliminated by keeping
+// only the top-degree part of the skew components (sigma is orthogonal to
+// P^{k-1}(T, K) exactly when its skew part lies in P^k minus P^{k-1}), and the
+// nt-trace degree condition of Sigma_h is imposed through its constraint
+// matrix Lambda.  With the mass matrix (|T|/nu) I this gives
+//     A = A^div + (nu/|T|) G (I - Q^T Q) G^T,
+// G[i, (a,m)] = b(psi_a D_m, phi_i), Q an orthonormal basis of the rows of
+// Lambda (obtained by two Cholesky-QR passes).
+#include "kernels_common.h"
+#include "launch.h"
+
+namespace mcs {
+
+// --------------------------------------------------------------------------
+// 64x64 output tile of C = A B^T (A: M x K, B: N x K, row-major), 256 threads,
+// 4x4 micro tiles, K panels of 16 staged in LDS.  acc is per thread.
+// --------------------------------------------------------------------------
+__device__ void tile_nt(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
+                        int m0, int n0, int M, int N, int K, double acc[4][4], double* lds) {
+  double* la = lds;            // [16][64]
+  double* lb = lds + 16 * 64;  // [16][64]
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int idx = tid; idx < 1024; idx += 256) {
+      int r = idx >> 4, kk = idx & 15;
+      int gm = m0 + r, gn = n0 + r, gk = k0 + kk;
+      la[kk * 64 + r] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : 0.0;
+      lb[kk * 64 + r] = (gn < N && gk < K) ? B[(size_t)gn * ldb + gk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = la[kk * 64 + ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = lb[kk * 64 + tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+}
+
+// In-place Cholesky (lower) of an n x n row-major SPD matrix in memory
+// visible to the block; returns false on breakdown.  Upper part zeroed.
+__device__ bool block_cholesky(double* S, int n, int ld) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double v = S[j * ld + j];
+      if (!(v > 0.0)) {
+        bad = 1;
+        v = 1.0;
+      }
+      S[j * ld + j] = sqrt(v);
+    }
+    __syncthreads();
+    double piv = S[j * ld + j];
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) S[i * ld + j] /= piv;
+    __syncthreads();
+    int m = n - j - 1;
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      int i = j + 1 + idx / m, c = j + 1 + idx % m;
+      if (c <= i) S[i * ld + c] -= S[i * ld + j] * S[c * ld + j];
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    int i = idx / n, c = idx % n;
+    if (c > i) S[i * ld + c] = 0.0;
+  }
+  __syncthreads();
+  return bad == 0;
+}
+
+// X <- L^{-1} X for lower-triangular L (n x n) and X (n x ncol), column parallel.
+__device__ void block_trsm_lower(const double* L, int ldl, double* X, int ldx, int n, int ncol) {
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    for (int i = 0; i < n; ++i) {
+      double t = X[i * ldx + c];
+      for (int p = 0; p < i; ++p) t -= L[i * ldl + p] * X[p * ldx + c];
+      X[i * ldx + c] = t / L[i * ldl + i];
+    }
+  }
+  __syncthreads();
+}
+
+// Inverse of an SPD matrix given its Cholesky factor L (in S, lower):
+// out = L^{-T} L^{-1}.  W is n x n scratch.
+__device__ void block_spd_inverse(const double* L, int n, double* W, double* out) {
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) W[idx] = ((idx / n) == (idx % n)) ? 1.0 : 0.0;
+  __syncthreads();
+  block_trsm_lower(L, n, W, n, n, n);   // W = L^{-1}
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    int i = idx / n, j = idx % n;
+    int p0 = i > j ? i : j;
+    double t = 0.0;
+    for (int p = p0; p < n; ++p) t += W[p * n + i] * W[p * n + j];
+    out[idx] = t;
+  }
+  __syncthreads();
+}
+
+// Orthonormal trace-free basis (Frobenius): symmetric part, then skew part.
+__device__ void dm_basis(int d, int m, double D[3][3]) {
+  const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) D[i][j] = 0.0;
+  if (d == 2) {
+    if (m == 0) { D[0][1] = r2; D[1][0] = r2; }
+    else if (m == 1) { D[0][0] = r2; D[1][1] = -r2; }
+    else { D[0][1] = r2; D[1][0] = -r2; }
+  } else {
+    switch (m) {
+      case 0: D[0][1] = r2; D[1][0] = r2; break;
+      case 1: D[0][2] = r2; D[2][0] = r2; break;
+      case 2: D[1][2] = r2; D[2][1] = r2; break;
+      case 3: D[0][0] = r2; D[1][1] = -r2; break;
+      case 4: D[0][0] = r6; D[1][1] = r6; D[2][2] = -2.0 * r6; break;
+      case 5: D[0][1] = r2; D[1][0] = -r2; break;
+      case 6: D[0][2] = r2; D[2][0] = -r2; break;
+      default: D[1][2] = r2; D[2][1] = -r2; break;
+    }
+  }
+}
+
+struct ElemGeo {
+  double J[3][3], Ji[3][3], det, vol;
+  double X[4][3];
+  double n[4][3], area[4], t[4][2][3], gl[4][3];
+};
+
+__device__ void element_geometry(const CondParams& P, int64_t e, ElemGeo& g) {
+  const int d = P.s.d, nv = d + 1;
+  for (int j = 0; j < nv; ++j) {
+    int v = P.elem_verts[e * nv + j];
+    for (int r = 0; r < 3; ++r) g.X[j][r] = r < d ? P.coords[(size_t)v * d + r] : 0.0;
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) g.J[r][c] = (r < d && c < d) ? g.X[c + 1][r] - g.X[0][r] : (r == c ? 1.0 : 0.0);
+  double (&J)[3][3] = g.J;
+  double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+               J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  g.det = det;
+  g.Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+  g.Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+  g.Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+  g.Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+  g.Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+  g.Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+  g.Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+  g.Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+  g.Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  g.vol = fabs(det) / (d == 2 ? 2.0 : 6.0);
+  for (int r = 0; r < 3; ++r) {
+    g.gl[0][r] = 0.0;
+    for (int j = 1; j < nv; ++j) {
+      g.gl[j][r] = r < d ? g.Ji[j - 1][r] : 0.0;
+      g.gl[0][r] -= g.gl[j][r];
+    }
+  }
+  for (int f = 0; f < nv; ++f) {
+    double nn = 0.0;
+    for (int r = 0; r < d; ++r) nn += g.gl[f][r] * g.gl[f][r];
+    nn = sqrt(nn);
+    for (int r = 0; r < 3; ++r) g.n[f][r] = r < d ? -g.gl[f][r] / nn : 0.0;
+    g.area[f] = d * g.vol * nn;
+    int fv[3], c = 0;
+    for (int j = 0; j < nv; ++j)
+      if (j != f) fv[c++] = j;
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 3; ++r) g.t[f][b][r] = (b < d - 1) ? g.X[fv[b + 1]][r] - g.X[fv[0]][r] : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_condense(CondParams P) {
+  const Sizes s = P.s;
+  const int d = s.d, nv = d + 1, nD = s.nsym + s.nskew;
+  const int tid = threadIdx.x;
+  __shared__ ElemGeo g;
+  __shared__ double sEm[8][3][3];
+  __shared__ double sW[4][8][3];
+  __shared__ double sTd[4][2][8];
+  __shared__ double sS[48 * 48];
+  __shared__ double lds[2 * 16 * 64];
+  const int nq = s.nFk - s.nFkm1;
+  const int ntop = s.ns - s.nsm1;
+  double* scr = P.scratch + (size_t)blockIdx.x * P.slot_doubles;
+  double* G = scr;                                   // nA x nsig
+  double* Lm = G + (size_t)s.nA * s.nsig;            // nlam x nsig
+  double* Y = Lm + (size_t)s.nlam * s.nsig;          // nA x nlam
+  double* A = Y + (size_t)s.nA * s.nlam;             // nA x nA
+  double* Ai = A + (size_t)s.nA * s.nA;              // nb x nb
+  double* Wk = Ai + (size_t)s.nb * s.nb;             // nb x nb
+
+  for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
+    if (tid == 0) element_geometry(P, e, g);
+    __syncthreads();
+    // coefficient tables
+    for (int idx = tid; idx < nD * nv; idx += blockDim.x) {
+      int m = idx % nD, f = idx / nD;
+      double D[3][3];
+      dm_basis(d, m, D);
+      if (f == 0) {  // Em = J^T D_m J^{-T}
+        for (int r = 0; r < d; ++r)
+          for (int c = 0; c < d; ++c) {
+            double t = 0.0;
+            for (int a = 0; a < d; ++a)
+              for (int b = 0; b < d; ++b) t += g.J[a][r] * D[a][b] * g.Ji[c][b];
+            sEm[m][r][c] = t;
+          }
+      }
+      double Dn[3] = {0, 0, 0}, nDn = 0.0;
+      for (int a = 0; a < d; ++a) {
+        for (int b = 0; b < d; ++b) Dn[a] += D[a][b] * g.n[f][b];
+        nDn += g.n[f][a] * Dn[a];
+      }
+      double Pt[3];
+      for (int a = 0; a < d; ++a) Pt[a] = Dn[a] - g.n[f][a] * nDn;
+      double sc = g.area[f] / P.facet_measure[f];
+      for (int r = 0; r < d; ++r) {
+        double t = 0.0;
+        for (int a = 0; a < d; ++a) t += g.J[a][r] * Pt[a];
+        sW[f][m][r] = sc * t;
+      }
+      for (int b = 0; b < d - 1; ++b) {
+        double t = 0.0;
+        for (int a = 0; a < d; ++a) t += g.t[f][b][a] * Dn[a];
+        sTd[f][b][m] = t;
+      }
+    }
+    __syncthreads();
+    const double adet = fabs(g.det), idet = 1.0 / g.det;
+    // G (reordered local rows) and Lambda
+    for (int64_t idx = tid; idx < (int64_t)s.nA * s.nsig; idx += blockDim.x) {
+      int i = (int)(idx / s.nsig), c = (int)(idx % s.nsig);
+      int m, a;
+      if (c < s.nsym * s.ns) { m = c / s.ns; a = c % s.ns; }
+      else { int cc = c - s.nsym * s.ns; m = s.nsym + cc / ntop; a = s.nsm1 + cc % ntop; }
+      double val;
+      int iu = -1, f = 0, q = 0;
+      double sc = 1.0;
+      if (i < s.nb) iu = i;
+      else {
+        f = (i - s.nb) / s.nfb;
+        q = (i - s.nb) % s.nfb;
+        if (q < s.nF) { iu = s.nb + f * s.nF + q; sc = idet; }
+      }
+      if (iu >= 0) {
+        double t = 0.0;
+        const double* Vp = P.rV + ((size_t)iu * s.ns + a) * d * d;
+        for (int r = 0; r < d; ++r)
+          for (int c2 = 0; c2 < d; ++c2) t += sEm[m][r][c2] * Vp[r * d + c2];
+        t *= -adet;
+        for (int ff = 0; ff < nv; ++ff) {
+          const double* Bp = P.rBf + (((size_t)ff * s.nu + iu) * s.ns + a) * d;
+          for (int r = 0; r < d; ++r) t += sW[ff][m][r] * Bp[r];
+        }
+        val = sc * t;
+      } else {
+        int j = q - s.nF, b = j / s.nFkm1, gm = j % s.nFkm1;
+        val = -(g.area[f] / P.facet_measure[f]) * sTd[f][b][m] * P.rU[((size_t)f * s.nFkm1 + gm) * s.ns + a];
+      }
+      G[idx] = val;
+    }
+    for (int idx = tid; idx < s.nlam * s.nsig; idx += blockDim.x) {
+      int l = idx / s.nsig, c = idx % s.nsig;
+      int m, a;
+      if (c < s.nsym * s.ns) { m = c / s.ns; a = c % s.ns; }
+      else { int cc = c - s.nsym * s.ns; m = s.nsym + cc / ntop; a = s.nsm1 + cc % ntop; }
+      int qq = l % nq, fb = l / nq, f = fb / (d - 1), b = fb % (d - 1);
+      Lm[idx] = sTd[f][b][m] * P.rL[((size_t)f * nq + qq) * s.ns + a];
+    }
+    __syncthreads();
+    // two Cholesky-QR passes: rows of Lm become orthonormal
+    bool ok = true;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int idx = tid; idx < s.nlam * s.nlam; idx += blockDim.x) {
+        int i = idx / s.nlam, j = idx % s.nlam;
+        double t = 0.0;
+        for (int c = 0; c < s.nsig; ++c) t += Lm[i * s.nsig + c] * Lm[j * s.nsig + c];
+        sS[i * 48 + j] = t;
+      }
+      __syncthreads();
+      ok = block_cholesky(sS, s.nlam, 48) && ok;
+      block_trsm_lower(sS, 48, Lm, s.nsig, s.nlam, s.nsig);
+    }
+    // Y = G Q^T
+    for (int n0 = 0; n0 < s.nlam; n0 += 64)
+      for (int m0 = 0; m0 < s.nA; m0 += 64) {
+        double acc[4][4];
+        tile_nt(G, s.nsig, Lm, s.nsig, m0, n0, s.nA, s.nlam, s.nsig, acc, lds);
+        const int tx = tid & 15, ty = tid >> 4;
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) {
+            int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
+            if (r < s.nA && c < s.nlam) Y[r * s.nlam + c] = acc[i][j];
+          }
+      }
+    __syncthreads();
+    // A = A^div + (nu/|T|) (G G^T - Y Y^T)
+    const double nuT = P.nu[e];
+    const double cf = nuT / g.vol;
+    for (int m0 = 0; m0 < s.nA; m0 += 64)
+      for (int n0 = m0; n0 < s.nA; n0 += 64) {
+        double acc[4][4], acc2[4][4];
+        tile_nt(G, s.nsig, G, s.nsig, m0, n0, s.nA, s.nA, s.nsig, acc, lds);
+        tile_nt(Y, s.nlam, Y, s.nlam, m0, n0, s.nA, s.nA, s.nlam, acc2, lds);
+        const int tx = tid & 15, ty = tid >> 4;
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) {
+            int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
+            if (r < s.nA && c < s.nA) {
+              double v = cf * (acc[i][j] - acc2[i][j]);
+              // A^div on velocity rows
+              int ir = -1, ic = -1;
+              double sr = 1.0, sc2 = 1.0;
+              if (r < s.nb) ir = r;
+              else { int f = (r - s.nb) / s.nfb, q = (r - s.nb) % s.nfb; if (q < s.nF) { ir = s.nb + f * s.nF + q; sr = idet; } }
+              if (c < s.nb) ic = c;
+              else { int f = (c - s.nb) / s.nfb, q = (c - s.nb) % s.nfb; if (q < s.nF) { ic = s.nb + f * s.nF + q; sc2 = idet; } }
+              if (ir >= 0 && ic >= 0) v += (nuT / d) * sr * sc2 * adet * P.rD[(size_t)ir * s.nu + ic];
+              A[(size_t)r * s.nA + c] = v;
+              A[(size_t)c * s.nA + r] = v;
+            }
+          }
+      }
+    __syncthreads();
+    // condensation II: Aoo = A[0:nb,0:nb]
+    const int nb = s.nb, nd = s.nd;
+    for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
+      int i = idx / nb, j = idx % nb;
+      double v = A[(size_t)i * s.nA + j];
+      Wk[idx] = v;
+      P.Aoo[(size_t)e * nb * nb + idx] = v;
+      P.Aoo32[(size_t)e * nb * nb + idx] = (float)v;
+    }
+    __syncthreads();
+    ok = block_cholesky(Wk, nb, nb) && ok;
+    for (int idx = tid; idx < nb * nb; idx += blockDim.x) Ai[idx] = ((idx / nb) == (idx % nb)) ? 1.0 : 0.0;
+    __syncthreads();
+    block_trsm_lower(Wk, nb, Ai, nb, nb, nb);  // Ai = L^{-1}
+    for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
+      int i = idx / nb, j = idx % nb;
+      int p0 = i > j ? i : j;
+      double t = 0.0;
+      for (int p = p0; p < nb; ++p) t += Ai[p * nb + i] * Ai[p * nb + j];
+      Wk[idx] = t;  // Wk = Aoo^{-1}
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
+      P.Aooinv[(size_t)e * nb * nb + idx] = Wk[idx];
+      P.Aooinv32[(size_t)e * nb * nb + idx] = (float)Wk[idx];
+    }
+    // Ht[n][m] = sum_k A[nb+n][k] Aooinv[m][k]   (nd x nb)
+    double* Ht = P.Ht + (size_t)e * nb * nd;
+    for (int m0 = 0; m0 < nd; m0 += 64)
+      for (int n0 = 0; n0 < nb; n0 += 64) {
+        double acc[4][4];
+        tile_nt(A + (size_t)nb * s.nA, s.nA, Wk, nb, m0, n0, nd, nb, nb, acc, lds);
+        const int tx = tid & 15, ty = tid >> 4;
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) {
+            int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
+            if (r < nd && c < nb) {
+              double v = acc[i][j];
+              Ht[(size_t)r * nb + c] = v;
+              P.Ht32[(size_t)e * nb * nd + (size_t)r * nb + c] = (float)v;
+              P.H[(size_t)e * nb * nd + (size_t)c * nd + r] = v;
+              P.H32[(size_t)e * nb * nd + (size_t)c * nd + r] = (float)v;
+            }
+          }
+      }
+    __syncthreads();
+    // Ad = A_dd - A_do Ht^T
+    for (int m0 = 0; m0 < nd; m0 += 64)
+      for (int n0 = 0; n0 < nd; n0 += 64) {
+        double acc[4][4];
+        tile_nt(A + (size_t)nb * s.nA, s.nA, Ht, nb, m0, n0, nd, nd, nb, acc, lds);
+        const int tx = tid & 15, ty = tid >> 4;
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) {
+            int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
+            if (r < nd && c < nd) {
+              double v = A[(size_t)(nb + r) * s.nA + nb + c] - acc[i][j];
+              P.Ad[(size_t)e * nd * nd + (size_t)r * nd + c] = v;
+            }
+          }
+      }
+    __syncthreads();
+    // symmetrise Ad exactly and write the FP32 copy
+    double* Ade = P.Ad + (size_t)e * nd * nd;
+    for (int idx = tid; idx < nd * nd; idx += blockDim.x) {
+      int r = idx / nd, c = idx % nd;
+      if (c < r) continue;
+      double v = 0.5 * (Ade[(size_t)r * nd + c] + Ade[(size_t)c * nd + r]);
+      Ade[(size_t)r * nd + c] = v;
+      Ade[(size_t)c * nd + r] = v;
+      P.Ad32[(size_t)e * nd * nd + (size_t)r * nd + c] = (float)v;
+      P.Ad32[(size_t)e * nd * nd + (size_t)c * nd + r] = (float)v;
+    }
+    if (tid == 0) {
+      P.detJ[e] = g.det;
+      if (!ok) atomicOr(P.status, 1);
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------------------
+// Facet smoother blocks D_F = sum_{T ni F} (A^d_T)_{FF} and their inverses,
+// and the embedding blocks E_F (facet rows of E u = (u, u_t), eq. defE):
+//   normal rows:     |F| (e_c . n_F) * coefficient of lambda_v in the degree-k
+//                    facet Bernstein basis (facet functions have normal trace
+//                    lambda^beta / |F|);
+//   tangential rows: coefficient of lambda_v in degree k-1 times the
+//                    coordinates of P_t e_c in the tangent basis t_b.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_facet_setup(FacetSetupParams P) {
+  const Sizes s = P.s;
+  const int d = s.d, nv = d + 1, nfb = s.nfb, nd = s.nd;
+  constexpr int FLD = 52;  // leading dimension of the facet block (n_fb <= 51)
+  __shared__ double S[FLD * FLD];
+  __shared__ double W[FLD * FLD];
+  __shared__ double X[3][3];
+  __shared__ double geo[16];
+  for (int64_t g = blockIdx.x; g < P.nff; g += gridDim.x) {
+    for (int idx = threadIdx.x; idx < nfb * nfb; idx += blockDim.x) {
+      int i = idx / nfb, j = idx % nfb;
+      double t = 0.0;
+      for (int side = 0; side < 2; ++side) {
+        int64_t e = P.facet_el[2 * g + side];
+        int sl = P.facet_slot[2 * g + side];
+        t += P.Ad[(size_t)e * nd * nd + (size_t)(sl * nfb + i) * nd + sl * nfb + j];
+      }
+      S[i * FLD + j] = t;
+    }
+    __syncthreads();
+    bool ok = block_cholesky(S, nfb, FLD);
+    for (int idx = threadIdx.x; idx < nfb * nfb; idx += blockDim.x) W[(idx / nfb) * FLD + idx % nfb] = ((idx / nfb) == (idx % nfb)) ? 1.0 : 0.0;
+    __syncthreads();
+    block_trsm_lower(S, FLD, W, FLD, nfb, nfb);
+    for (int idx = threadIdx.x; idx < nfb * nfb; idx += blockDim.x) {
+      int i = idx / nfb, j = idx % nfb;
+      int p0 = i > j ? i : j;
+      double t = 0.0;
+      for (int p = p0; p < nfb; ++p) t += W[p * FLD + i] * W[p * FLD + j];
+      P.Dinv[(size_t)g * nfb * nfb + idx] = t;
+      P.Dinv32[(size_t)g * nfb * nfb + idx] = (float)t;
+    }
+    // facet geometry from the first neighbour's sorted vertices
+    if (threadIdx.x == 0) {
+      if (!ok) atomicOr(P.status, 2);
+      int64_t e = P.facet_el[2 * g];
+      int sl = P.facet_slot[2 * g];
+      int c = 0;
+      for (int j = 0; j < nv; ++j)
+        if (j != sl) {
+          int v = P.elem_verts[e * nv + j];
+          for (int r = 0; r < 3; ++r) X[c][r] = r < d ? P.coords[(size_t)v * d + r] : 0.0;
+          ++c;
+        }
+      double t1[3], t2[3], n[3];
+      for (int r = 0; r < 3; ++r) { t1[r] = X[1][r] - X[0][r]; t2[r] = (d == 3) ? X[2][r] - X[0][r] : 0.0; }
+      double area;
+      if (d == 2) {
+        n[0] = t1[1]; n[1] = -t1[0]; n[2] = 0.0;
+        area = sqrt(t1[0] * t1[0] + t1[1] * t1[1]);
+      } else {
+        n[0] = t1[1] * t2[2] - t1[2] * t2[1];
+        n[1] = t1[2] * t2[0] - t1[0] * t2[2];
+        n[2] = t1[0] * t2[1] - t1[1] * t2[0];
+        area = 0.5 * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      }
+      double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      for (int r = 0; r < 3; ++r) geo[r] = n[r] / nn;
+      geo[3] = area;
+      // tangential coordinates of P_t e_c: solve Gram(t) a = (t_b . e_c)
+      if (d == 2) {
+        double tt = t1[0] * t1[0] + t1[1] * t1[1];
+        for (int cc = 0; cc < 2; ++cc) geo[4 + cc] = t1[cc] / tt;   // a_0(c)
+      } else {
+        double g11 = t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2];
+        double g12 = t1[0] * t2[0] + t1[1] * t2[1] + t1[2] * t2[2];
+        double g22 = t2[0] * t2[0] + t2[1] * t2[1] + t2[2] * t2[2];
+        double det = g11 * g22 - g12 * g12;
+        for (int cc = 0; cc < 3; ++cc) {
+          double r1 = t1[cc], r2 = t2[cc];
+          geo[4 + cc] = (g22 * r1 - g12 * r2) / det;        // a_0(c)
+          geo[7 + cc] = (-g12 * r1 + g11 * r2) / det;       // a_1(c)
+        }
+      }
+    }
+    __syncthreads();
+    const int dd = d * d;
+    for (int idx = threadIdx.x; idx < nfb * dd; idx += blockDim.x) {
+      int q = idx / dd, vc = idx % dd, v = vc / d, c = vc % d;
+      double val;
+      if (q < s.nF) {
+        val = geo[3] * geo[c] * P.rcn[q * d + v];
+      } else {
+        int j = q - s.nF, b = j / s.nFkm1, gm = j % s.nFkm1;
+        val = P.rct[gm * d + v] * geo[4 + 3 * b + c];
+      }
+      P.EF[(size_t)g * nfb * dd + idx] = val;
+      P.EF32[(size_t)g * nfb * dd + idx] = (float)val;
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------------------
+// P1 multigrid setup on the vertex lattice.  Stencil entry index of offset
+// o in {-1,0,1}^d: sum_a (o_a + 1) 3^a; blocks are d x d (row comp, col comp).
+// --------------------------------------------------------------------------
+__device__ inline void lat_coords(int64_t v, const int* N, int c[3]) {
+  c[0] = (int)(v % N[0]);
+  c[1] = (int)((v / N[0]) % N[1]);
+  c[2] = (int)(v / ((int64_t)N[0] * N[1]));
+}
+
+__device__ inline bool lat_interior(const int c[3], const int* n, int d) {
+  for (int a = 0; a < d; ++a)
+    if (c[a] <= 0 || c[a] >= n[a]) return false;
+  return true;
+}
+
+// A-bar stencil on the finest level: vertex-centric sum over incident elements
+// of nu_T int eps(lambda_v e_c) : eps(lambda_w e_e).
+__global__ void k_p1_assemble(P1Params P) {
+  const int d = P.d, nv = d + 1, st = d == 3 ? 27 : 9, dd = d * d;
+  int N[3] = {P.n[0] + 1, P.n[1] + 1, P.n[2] + 1};
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < P.nvert; v += (int64_t)gridDim.x * blockDim.x) {
+    double* Av = P.A + (size_t)v * st * dd;
+    for (int i = 0; i < st * dd; ++i) Av[i] = 0.0;
+    int cv[3];
+    lat_coords(v, N, cv);
+    for (int p = P.vert_elem_off[v]; p < P.vert_elem_off[v + 1]; ++p) {
+      int64_t e = P.vert_elem[p];
+      // geometry
+      double X[4][3], J[3][3], Ji[3][3];
+      for (int j = 0; j < nv; ++j) {
+        int vv = P.elem_verts[e * nv + j];
+        for (int r = 0; r < 3; ++r) X[j][r] = r < d ? P.coords[(size_t)vv * d + r] : 0.0;
+      }
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) J[r][c] = (r < d && c < d) ? X[c + 1][r] - X[0][r] : (r == c ? 1.0 : 0.0);
+      double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                   J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+      Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+      Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+      Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+      Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+      Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+      Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+      Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+      Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+      double vol = fabs(det) / (d == 2 ? 2.0 : 6.0);
+      double gl[4][3];
+      for (int r = 0; r < 3; ++r) {
+        gl[0][r] = 0.0;
+        for (int j = 1; j < nv; ++j) { gl[j][r] = r < d ? Ji[j - 1][r] : 0.0; gl[0][r] -= gl[j][r]; }
+      }
+      int lv = 0;
+      for (int j = 0; j < nv; ++j)
+        if (P.elem_verts[e * nv + j] == v) lv = j;
+      double w = P.nu[e] * vol;
+      for (int j = 0; j < nv; ++j) {
+        int cw[3];
+        lat_coords(P.elem_verts[e * nv + j], N, cw);
+        int o = 0, pw = 1;
+        for (int a = 0; a < d; ++a) { o += (cw[a] - cv[a] + 1) * pw; pw *= 3; }
+        double gg = 0.0;
+        for (int r = 0; r < d; ++r) gg += gl[lv][r] * gl[j][r];
+        for (int c = 0; c < d; ++c)
+          for (int ee = 0; ee < d; ++ee)
+            Av[o * dd + c * d + ee] += w * 0.5 * ((c == ee ? gg : 0.0) + gl[j][c] * gl[lv][ee]);
+      }
+    }
+  }
+}
+
+// l1 block-Jacobi inverse: D_v = A_vv + diag(sum over free w != v of |A_vw| row sums).
+__global__ void k_mg_l1(MGSetupParams P) {
+  const int d = P.d, st = d == 3 ? 27 : 9, dd = d * d;
+  int N[3] = {P.n[0] + 1, P.n[1] + 1, P.n[2] + 1};
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < P.nvert; v += (int64_t)gridDim.x * blockDim.x) {
+    int cv[3];
+    lat_coords(v, N, cv);
+    double Dm[3][3] = {};
+    if (lat_interior(cv, P.n, d)) {
+      const double* Av = P.A + (size_t)v * st * dd;
+      int center = d == 3 ? 13 : 4;
+      for (int c = 0; c < d; ++c)
+        for (int e = 0; e < d; ++e) Dm[c][e] = Av[center * dd + c * d + e];
+      for (int o = 0; o < st; ++o) {
+        if (o == center) continue;
+        int cw[3] = {cv[0] + o % 3 - 1, cv[1] + (o / 3) % 3 - 1, cv[2] + (o / 9) - 1};
+        if (d == 2) cw[2] = 0;
+        if (!lat_interior(cw, P.n, d)) continue;
+        for (int c = 0; c < d; ++c) {
+          double sacc = 0.0;
+          for (int e = 0; e < d; ++e) sacc += fabs(Av[o * dd + c * d + e]);
+          Dm[c][c] += sacc;
+        }
+      }
+    } else {
+      for (int c = 0; c < d; ++c) Dm[c][c] = 1.0;
+    }
+    double inv[3][3];
+    if (d == 2) {
+      double det = Dm[0][0] * Dm[1][1] - Dm[0][1] * Dm[1][0];
+      inv[0][0] = Dm[1][1] / det; inv[0][1] = -Dm[0][1] / det;
+      inv[1][0] = -Dm[1][0] / det; inv[1][1] = Dm[0][0] / det;
+    } else {
+      double det = Dm[0][0] * (Dm[1][1] * Dm[2][2] - Dm[1][2] * Dm[2][1]) - Dm[0][1] * (Dm[1][0] * Dm[2][2] - Dm[1][2] * Dm[2][0]) +
+                   Dm[0][2] * (Dm[1][0] * Dm[2][1] - Dm[1][1] * Dm[2][0]);
+      inv[0][0] = (Dm[1][1] * Dm[2][2] - Dm[1][2] * Dm[2][1]) / det;
+      inv[0][1] = (Dm[0][2] * Dm[2][1] - Dm[0][1] * Dm[2][2]) / det;
+      inv[0][2] = (Dm[0][1] * Dm[1][2] - Dm[0][2] * Dm[1][1]) / det;
+      inv[1][0] = (Dm[1][2] * Dm[2][0] - Dm[1][0] * Dm[2][2]) / det;
+      inv[1][1] = (Dm[0][0] * Dm[2][2] - Dm[0][2] * Dm[2][0]) / det;
+      inv[1][2] = (Dm[0][2] * Dm[1][0] - Dm[0][0] * Dm[1][2]) / det;
+      inv[2][0] = (Dm[1][0] * Dm[2][1] - Dm[1][1] * Dm[2][0]) / det;
+      inv[2][1] = (Dm[0][1] * Dm[2][0] - Dm[0][0] * Dm[2][1]) / det;
+      inv[2][2] = (Dm[0][0] * Dm[1][1] - Dm[0][1] * Dm[1][0]) / det;
+    }
+    for (int c = 0; c < d; ++c)
+      for (int e = 0; e < d; ++e) {
+        P.Dinv[(size_t)v * dd + c * d + e] = inv[c][e];
+        P.Dinv32[(size_t)v * dd + c * d + e] = (float)inv[c][e];
+      }
+  }
+}
+
+__device__ inline int coarse_pos(int I, int n) { return (2 * I < n) ? 2 * I : n; }
+
+// interpolation weight P(i, I) along one axis with n fine intervals
+__device__ inline double w1d(int i, int I, int n) {
+  int c = coarse_pos(I, n);
+  if (i == c) return 1.0;
+  bool is_coarse = (i % 2 == 0) || (i == n);
+  if (!is_coarse && (i - c == 1 || c - i == 1)) return 0.5;
+  return 0.0;
+}
+
+// Galerkin coarse operator A_c = P^T A P restricted to interior vertices.
+__global__ void k_mg_rap(MGSetupParams P) {
+  const int d = P.d, st = d == 3 ? 27 : 9, dd = d * d;
+  int Nf[3] = {P.n[0] + 1, P.n[1] + 1, P.n[2] + 1};
+  int Nc[3] = {P.nc[0] + 1, P.nc[1] + 1, P.nc[2] + 1};
+  for (int64_t V = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; V < P.nvert_c; V += (int64_t)gridDim.x * blockDim.x) {
+    double* Ac = P.Ac + (size_t)V * st * dd;
+    for (int i = 0; i < st * dd; ++i) Ac[i] = 0.0;
+    int CI[3];
+    lat_coords(V, Nc, CI);
+    if (!lat_interior(CI, P.nc, d)) continue;
+    int base[3] = {coarse_pos(CI[0], P.n[0]), coarse_pos(CI[1], P.n[1]), d == 3 ? coarse_pos(CI[2], P.n[2]) : 0};
+    for (int fo = 0; fo < st; ++fo) {
+      int fi[3] = {base[0] + fo % 3 - 1, base[1] + (fo / 3) % 3 - 1, base[2] + fo / 9 - 1};
+      if (d == 2) fi[2] = 0;
+      if (!lat_interior(fi, P.n, d)) continue;
+      double wI = 1.0;
+      for (int a = 0; a < d; ++a) wI *= w1d(fi[a], CI[a], P.n[a]);
+      if (wI == 0.0) continue;
+      int64_t fiv = fi[0] + (int64_t)Nf[0] * (fi[1] + (int64_t)Nf[1] * fi[2]);
+      const double* Af = P.A + (size_t)fiv * st * dd;
+      for (int so = 0; so < st; ++so) {
+        int fj[3] = {fi[0] + so % 3 - 1, fi[1] + (so / 3) % 3 - 1, fi[2] + so / 9 - 1};
+        if (d == 2) fj[2] = 0;
+        if (!lat_interior(fj, P.n, d)) continue;
+        for (int co = 0; co < st; ++co) {
+          int CJ[3] = {CI[0] + co % 3 - 1, CI[1] + (co / 3) % 3 - 1, CI[2] + co / 9 - 1};
+          if (d == 2) CJ[2] = 0;
+          if (!lat_interior(CJ, P.nc, d)) continue;
+          double wJ = 1.0;
+          for (int a = 0; a < d; ++a) wJ *= w1d(fj[a], CJ[a], P.n[a]);
+          if (wJ == 0.0) continue;
+          for (int c = 0; c < dd; ++c) Ac[co * dd + c] += wI * wJ * Af[so * dd + c];
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_to_f32(const double* a, float* b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = (float)a[i];
+}
+
+// Coarsest level: dense matrix over the free dofs, then its inverse (one block).
+__global__ void k_coarse_gather(MGSetupParams P, double* Cd) {
+  const int d = P.d, st = d == 3 ? 27 : 9, dd = d * d;
+  int N[3] = {P.n[0] + 1, P.n[1] + 1, P.n[2] + 1};
+  int64_t nc = P.ncd;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < nc * nc; idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = idx / nc, j = idx % nc;
+    int64_t vi = P.cmap[i] / d, vj = P.cmap[j] / d;
+    int ci = P.cmap[i] % d, cj = P.cmap[j] % d;
+    int a[3], b[3];
+    lat_coords(vi, N, a);
+    lat_coords(vj, N, b);
+    double v = 0.0;
+    bool near = true;
+    int o = 0, pw = 1;
+    for (int ax = 0; ax < d; ++ax) {
+      int df = b[ax] - a[ax];
+      if (df < -1 || df > 1) near = false;
+      o += (df + 1) * pw;
+      pw *= 3;
+    }
+    if (near) v = P.A[(size_t)vi * st * dd + o * dd + ci * d + cj];
+    Cd[idx] = v;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_coarse_invert(double* C, double* W, double* Cinv, int64_t n, int* status) {
+  // Cholesky in place (lower), L^{-1} into W, Cinv = L^{-T} L^{-1}.
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int64_t j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double v = C[j * n + j];
+      if (!(v > 0.0)) { bad = 1; v = 1.0; }
+      C[j * n + j] = sqrt(v);
+    }
+    __syncthreads();
+    double piv = C[j * n + j];
+    for (int64_t i = j + 1 + threadIdx.x; i < n; i += blockDim.x) C[i * n + j] /= piv;
+    __syncthreads();
+    int64_t m = n - j - 1;
+    for (int64_t idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      int64_t i = j + 1 + idx / m, c = j + 1 + idx % m;
+      if (c <= i) C[i * n + c] -= C[i * n + j] * C[c * n + j];
+    }
+    __syncthreads();
+  }
+  for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+    for (int64_t i = 0; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      if (i > c)
+        for (int64_t p = c; p < i; ++p) t -= C[i * n + p] * W[p * n + c];
+      W[i * n + c] = (i < c) ? 0.0 : t / C[i * n + i];
+    }
+  }
+  __syncthreads();
+  for (int64_t idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    int64_t i = idx / n, j = idx % n;
+    int64_t p0 = i > j ? i : j;
+    double t = 0.0;
+    for (int64_t p = p0; p < n; ++p) t += W[p * n + i] * W[p * n + j];
+    Cinv[idx] = t;
+  }
+  if (threadIdx.x == 0 && bad) atomicOr(status, 4);
+}
+
+// Load vector (f, phi) with f the degree-m lattice interpolant (caller vertex
+// order, mapped to the sorted order through the element's permutation).
+__global__ void __launch_bounds__(256) k_load(CondParams C, SolveParams P, const int32_t* __restrict__ elem_perm,
+                                              const int32_t* __restrict__ latmap, const double* __restrict__ rRf,
+                                              const double* __restrict__ f, double* __restrict__ b,
+                                              double* __restrict__ escr) {
+  const Sizes s = C.s;
+  const int d = s.d, nb = s.nb, nd = s.nd;
+  __shared__ ElemGeo g;
+  __shared__ double Jf[128][3];
+  const int tid = threadIdx.x;
+  for (int64_t e = blockIdx.x; e < C.ne; e += gridDim.x) {
+    if (tid == 0) element_geometry(C, e, g);
+    __syncthreads();
+    const int pr = elem_perm[e];
+    for (int lc = tid; lc < s.nlat; lc += blockDim.x) {
+      int ls = latmap[(size_t)pr * s.nlat + lc];
+      for (int r = 0; r < d; ++r) {
+        double t = 0.0;
+        for (int a = 0; a < d; ++a) t += g.J[a][r] * f[((size_t)e * s.nlat + lc) * d + a];
+        Jf[ls][r] = t;
+      }
+    }
+    __syncthreads();
+    const double adet = fabs(g.det);
+    for (int row = tid; row < nb + nd; row += blockDim.x) {
+      int iu = -1;
+      double sc = 1.0;
+      if (row < nb) { iu = row; sc = adet; }
+      else {
+        int rr = row - nb, ff = rr / s.nfb, q = rr % s.nfb;
+        if (q < s.nF) { iu = nb + ff * s.nF + q; sc = adet / g.det; }
+      }
+      double acc = 0.0;
+      if (iu >= 0)
+        for (int l = 0; l < s.nlat; ++l)
+          for (int r = 0; r < d; ++r) acc += Jf[l][r] * rRf[((size_t)l * s.nu + iu) * d + r];
+      acc *= sc;
+      if (row < nb) b[e * nb + row] = acc;
+      else escr[e * nd + row - nb] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_check_nu(const double* nu, int64_t n, int* status) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v = nu[i];
+    if (!(v > 0.0) || !(v < 1e300)) atomicOr(status, 8);
+  }
+}
+
+// Mean of the pressure: red[0] = sum_T |T| sum_q p_q pmom_q, red[1] = |Omega|,
+// then p -= mean * pconst (the coefficients of p = 1).
+__global__ void __launch_bounds__(256) k_pmean_reduce(SolveParams P, const double* __restrict__ pmom,
+                                                      const double* __restrict__ x, double* red) {
+  __shared__ double sh[2][256];
+  const Sizes s = P.s;
+  const double fd = s.d == 2 ? 2.0 : 6.0;
+  double a = 0.0, v = 0.0;
+  for (int64_t e = threadIdx.x; e < P.ne; e += 256) {
+    double vol = fabs(P.detJ[e]) / fd;
+    double t = 0.0;
+    for (int q = 0; q < s.np; ++q) t += pmom[q] * x[P.off_p + e * s.np + q];
+    a += vol * t;
+    v += vol;
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) red[0] = sh[0][0] / sh[1][0];
+}
+
+__global__ void k_pmean_sub(SolveParams P, const double* __restrict__ pconst, const double* __restrict__ red,
+                            double* __restrict__ x) {
+  const int np = P.s.np;
+  const double m = red[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < P.ne * np; i += (int64_t)gridDim.x * blockDim.x)
+    x[P.off_p + i] -= m * pconst[i % np];
+}
+
+static int sgrid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65535 * 8));
+}
+
+void launch_condense(hipStream_t st, const CondParams& P, int nslots) {
+  hipLaunchKernelGGL(k_condense, dim3(nslots), dim3(256), 0, st, P);
+}
+void launch_facet_setup(hipStream_t st, const FacetSetupParams& P) {
+  hipLaunchKernelGGL(k_facet_setup, dim3((int)std::min<int64_t>(P.nff, 1 << 20)), dim3(256), 0, st, P);
+}
+void launch_p1_assemble(hipStream_t st, const P1Params& P) {
+  hipLaunchKernelGGL(k_p1_assemble, dim3(sgrid(P.nvert)), dim3(256), 0, st, P);
+}
+void launch_mg_l1(hipStream_t st, const MGSetupParams& P) {
+  hipLaunchKernelGGL(k_mg_l1, dim3(sgrid(P.nvert)), dim3(256), 0, st, P);
+}
+void launch_mg_rap(hipStream_t st, const MGSetupParams& P) {
+  hipLaunchKernelGGL(k_mg_rap, dim3(sgrid(P.nvert_c)), dim3(256), 0, st, P);
+}
+void launch_coarse(hipStream_t st, const MGSetupParams& P, double* Cd, double* W, double* Cinv, int* status) {
+  hipLaunchKernelGGL(k_coarse_gather, dim3(sgrid(P.ncd * P.ncd)), dim3(256), 0, st, P, Cd);
+  hipLaunchKernelGGL(k_coarse_invert, dim3(1), dim3(1024), 0, st, Cd, W, Cinv, P.ncd, status);
+}
+void launch_to_f32(hipStream_t st, const double* a, float* b, int64_t n) {
+  hipLaunchKernelGGL(k_to_f32, dim3(sgrid(n)), dim3(256), 0, st, a, b, n);
+}
+void launch_load(hipStream_t st, const CondParams& C, const SolveParams& P, const int32_t* elem_perm,
+                 const int32_t* latmap, const double* rRf, const double* f, double* b, double* escr) {
+  hipLaunchKernelGGL(k_load, dim3((int)std::min<int64_t>(C.ne, 1 << 20)), dim3(256), 0, st, C, P, elem_perm, latmap,
+                     rRf, f, b, escr);
+}
+void launch_check_nu(hipStream_t st, const double* nu, int64_t n, int* status) {
+  hipLaunchKernelGGL(k_check_nu, dim3(sgrid(n)), dim3(256), 0, st, nu, n, status);
+}
+void launch_pressure_mean(hipStream_t st, const SolveParams& P, const double* pmom, const double* pconst, double* x,
+                          double* red) {
+  hipLaunchKernelGGL(k_pmean_reduce, dim3(1), dim3(256), 0, st, P, pmom, (const double*)x, red);
+  hipLaunchKernelGGL(k_pmean_sub, dim3(sgrid(P.ne * P.s.np)), dim3(256), 0, st, P, pconst, (const double*)red, x);
+}
+
+}  // namespace mcs

@@ -1,0 +1,678 @@
+// Solve-phase kernels: element-by-element application of the condensed
+// operator through its bubble factorisation (eq. factorSsigma), the pressure
+// coupling B (eq. femSPmat), the pieces of A-hat_ext^{-1} (Sec. 6.1), coloured
+// facet block Gauss-Seidel sweeps (Theorem aux_pc_schur, Corollary
+// aux_pc_mult), the embedding E^d (eq. defED), the P1 lattice V-cycle, and
+// vector reductions for MINRES.
+//
+// Layout of element operators (element-major, row-major inside an element):
+//   Ad  [nd][nd] symmetric;  H [nb][nd];  Ht [nd][nb] (= H^T);
+//   Aoo [nb][nb], Aooinv [nb][nb] symmetric;  Dinv [nfb][nfb] symmetric.
+// Every thread of an element / facet block reads one column of a symmetric
+// matrix (= one row), so consecutive threads read consecutive addresses.
+#include "kernels_common.h"
+#include "launch.h"
+
+namespace mcs {
+
+template <typename R>
+__device__ inline void gather_elem_d(const SolveParams& P, const R* __restrict__ x, int64_t e, R* xd) {
+  const Sizes& s = P.s;
+  const int nv = s.d + 1;
+  for (int t = threadIdx.x; t < s.nd; t += blockDim.x) {
+    int f = t / s.nfb, q = t % s.nfb;
+    int g = P.elem_ff[e * nv + f];
+    xd[t] = g >= 0 ? x[P.off_f + (int64_t)g * s.nfb + q] : R(0);
+  }
+}
+
+// B_T[q][row] for a reordered local velocity row (bubble or facet normal dof);
+// returns 0 for tangential rows.  B = -(div phi, lambda^gamma), phi = s J phi^.
+__device__ inline double Bentry(const SolveParams& P, double det, int q, int row) {
+  const Sizes& s = P.s;
+  int iu;
+  double sc;
+  if (row < s.nb) {
+    iu = row;
+    sc = -fabs(det);
+  } else {
+    int r = row - s.nb, f = r / s.nfb, qq = r % s.nfb;
+    if (qq >= s.nF) return 0.0;
+    iu = s.nb + f * s.nF + qq;
+    sc = det > 0 ? -1.0 : 1.0;
+  }
+  return sc * P.rBp[(size_t)q * s.nu + iu];
+}
+
+// flags: 1 = velocity block A (factorised), 2 = + B^T p, 4 = p <- B u, 8 = A^d only
+template <typename R>
+__global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, OpPtrs<R> O, const R* __restrict__ x,
+                                                    R* __restrict__ y, R* __restrict__ escr, int flags) {
+  const Sizes s = P.s;
+  const int nb = s.nb, nd = s.nd, np = s.np;
+  __shared__ R xd[MAXND], xo[MAXNB], zo[MAXNB], wo[MAXNB];
+  __shared__ R xp[MAXNP];
+  const int tid = threadIdx.x;
+  for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
+    const double det = P.detJ[e];
+    gather_elem_d(P, x, e, xd);
+    if (tid < nb) xo[tid] = x[e * nb + tid];
+    if (tid < np) xp[tid] = x[P.off_p + e * np + tid];
+    __syncthreads();
+    const bool doA = flags & 1, doBT = flags & 2, doBu = flags & 4, onlyAd = flags & 8;
+    if (doA && !onlyAd) {
+      const R* Ht = O.Ht + (size_t)e * nb * nd;
+      if (tid < nb) {
+        R acc = xo[tid];
+        for (int j = 0; j < nd; ++j) acc += Ht[(size_t)j * nb + tid] * xd[j];
+        zo[tid] = acc;
+      }
+      __syncthreads();
+      const R* Aoo = O.Aoo + (size_t)e * nb * nb;
+      if (tid < nb) {
+        R acc = 0;
+        for (int j = 0; j < nb; ++j) acc += Aoo[(size_t)j * nb + tid] * zo[j];
+        wo[tid] = acc;
+      }
+      __syncthreads();
+    }
+    if (tid < nd) {
+      R acc = 0;
+      if (doA) {
+        const R* Ad = O.Ad + (size_t)e * nd * nd;
+        for (int j = 0; j < nd; ++j) acc += Ad[(size_t)j * nd + tid] * xd[j];
+        if (!onlyAd) {
+          const R* H = O.H + (size_t)e * nb * nd;
+          for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd + tid] * wo[i];
+        }
+      }
+      if (doBT) {
+        double b = 0.0;
+        for (int q = 0; q < np; ++q) b += Bentry(P, det, q, nb + tid) * (double)xp[q];
+        acc += (R)b;
+      }
+      escr[e * nd + tid] = acc;
+    }
+    if (!onlyAd && tid < nb) {
+      R acc = (doA) ? wo[tid] : R(0);
+      if (doBT) {
+        double b = 0.0;
+        for (int q = 0; q < np; ++q) b += Bentry(P, det, q, tid) * (double)xp[q];
+        acc += (R)b;
+      }
+      y[e * nb + tid] = acc;
+    }
+    if (doBu && tid < np) {
+      double acc = 0.0;
+      for (int i = 0; i < nb; ++i) acc += Bentry(P, det, tid, i) * (double)xo[i];
+      for (int t = 0; t < nd; ++t) acc += Bentry(P, det, tid, nb + t) * (double)xd[t];
+      y[P.off_p + e * np + tid] = (R)acc;
+    } else if (!onlyAd && tid < np && (flags & 16)) {
+      y[P.off_p + e * np + tid] = R(0);
+    }
+    __syncthreads();
+  }
+}
+
+// y_F = base_F + sign * (escr[T1][F] + escr[T2][F]) for every free facet dof.
+template <typename R>
+__global__ void k_facet_sum(SolveParams P, const R* __restrict__ escr, const R* __restrict__ base, R sign,
+                            R* __restrict__ y) {
+  const Sizes s = P.s;
+  const int64_t n = P.nff * s.nfb;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t g = idx / s.nfb;
+    int q = (int)(idx % s.nfb);
+    int64_t e1 = P.facet_el[2 * g], e2 = P.facet_el[2 * g + 1];
+    int s1 = P.facet_slot[2 * g], s2 = P.facet_slot[2 * g + 1];
+    R v = escr[e1 * s.nd + s1 * s.nfb + q] + escr[e2 * s.nd + s2 * s.nfb + q];
+    R b = base ? base[P.off_f + idx] : R(0);
+    y[P.off_f + idx] = b + sign * v;
+  }
+}
+
+// A-hat_ext^{-1}, first part: escr_T = H_T^T r_o,T;  t_o = Aoo^{-1} r_o.
+template <typename R>
+__global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, const R* __restrict__ r,
+                                                 R* __restrict__ to, R* __restrict__ escr) {
+  const Sizes s = P.s;
+  const int nb = s.nb, nd = s.nd;
+  __shared__ R ro[MAXNB];
+  const int tid = threadIdx.x;
+  for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
+    if (tid < nb) ro[tid] = r[e * nb + tid];
+    __syncthreads();
+    if (tid < nd) {
+      const R* H = O.H + (size_t)e * nb * nd;
+      R acc = 0;
+      for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd + tid] * ro[i];
+      escr[e * nd + tid] = acc;
+    }
+    if (tid < nb) {
+      const R* Ai = O.Aooinv + (size_t)e * nb * nb;
+      R acc = 0;
+      for (int j = 0; j < nb; ++j) acc += Ai[(size_t)j * nb + tid] * ro[j];
+      to[e * nb + tid] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// A-hat_ext^{-1}, last part: y_o = t_o - H_T t_d,T.
+template <typename R>
+__global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, const R* __restrict__ t,
+                                                  const R* __restrict__ to, R* __restrict__ y) {
+  const Sizes s = P.s;
+  const int nb = s.nb, nd = s.nd;
+  __shared__ R td[MAXND];
+  const int tid = threadIdx.x;
+  for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
+    gather_elem_d(P, t, e, td);
+    __syncthreads();
+    if (tid < nb) {
+      const R* Ht = O.Ht + (size_t)e * nb * nd;
+      R acc = to[e * nb + tid];
+      for (int j = 0; j < nd; ++j) acc -= Ht[(size_t)j * nb + tid] * td[j];
+      y[e * nb + tid] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// One colour phase of block Gauss-Seidel on A^d:
+//   x_F += D_F^{-1} (s_F - sum_{T ni F} (A^d_T x_T)_F)  for all facets F of the colour.
+template <typename R>
+__global__ void __launch_bounds__(256) k_smooth_phase(SolveParams P, OpPtrs<R> O, int32_t c0, int32_t c1,
+                                                      R* __restrict__ x, const R* __restrict__ srhs) {
+  const Sizes s = P.s;
+  const int nd = s.nd, nfb = s.nfb, nv = s.d + 1;
+  __shared__ R xs[2][MAXND];
+  __shared__ R red[256];
+  __shared__ R rr[MAXNFB];
+  const int tid = threadIdx.x;
+  const int parts = 128 / nfb;   // >= 2 for nfb <= 64
+  for (int64_t ci = c0 + blockIdx.x; ci < c1; ci += gridDim.x) {
+    const int64_t g = P.colour_facets[ci];
+    for (int side = 0; side < 2; ++side) {
+      int64_t e = P.facet_el[2 * g + side];
+      for (int t = tid; t < nd; t += blockDim.x) {
+        int f = t / nfb, q = t % nfb;
+        int gg = P.elem_ff[e * nv + f];
+        xs[side][t] = gg >= 0 ? x[P.off_f + (int64_t)gg * nfb + q] : R(0);
+      }
+    }
+    __syncthreads();
+    {
+      int side = tid >> 7, loc = tid & 127;
+      int q = loc % nfb, part = loc / nfb;
+      R acc = 0;
+      if (part < parts) {
+        int64_t e = P.facet_el[2 * g + side];
+        int sl = P.facet_slot[2 * g + side];
+        const R* Ad = O.Ad + (size_t)e * nd * nd + sl * nfb + q;
+        for (int j = part; j < nd; j += parts) acc += Ad[(size_t)j * nd] * xs[side][j];
+      }
+      red[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < nfb) {
+      R acc = srhs[P.off_f + g * nfb + tid];
+      for (int side = 0; side < 2; ++side)
+        for (int part = 0; part < parts; ++part) acc -= red[side * 128 + part * nfb + tid];
+      rr[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < nfb) {
+      const R* Di = O.Dinv + (size_t)g * nfb * nfb;
+      R acc = 0;
+      for (int j = 0; j < nfb; ++j) acc += Di[(size_t)j * nfb + tid] * rr[j];
+      x[P.off_f + g * nfb + tid] += acc;
+    }
+    __syncthreads();
+  }
+}
+
+// E^d^T, facet part: fscr[g][v*d + c] = sum_q EF[g][q][v*d+c] r_F[q].
+template <typename R>
+__global__ void k_edt_facet(SolveParams P, OpPtrs<R> O, const R* __restrict__ r, R* __restrict__ fscr) {
+  const Sizes s = P.s;
+  const int dd = s.d * s.d;
+  const int64_t n = P.nff * dd;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t g = idx / dd;
+    int t = (int)(idx % dd);
+    const R* E = O.EF + (size_t)g * s.nfb * dd + t;
+    const R* rf = r + P.off_f + g * s.nfb;
+    R acc = 0;
+    for (int q = 0; q < s.nfb; ++q) acc += E[(size_t)q * dd] * rf[q];
+    fscr[idx] = acc;
+  }
+}
+
+// E^d^T, vertex part: b[lat(v)][c] = sum over incident (facet, slot) entries.
+template <typename R>
+__global__ void k_edt_vertex(int d, int64_t nfv, const int32_t* __restrict__ vinc_off, const int32_t* __restrict__ vinc,
+                             const int32_t* __restrict__ free_to_lat, const R* __restrict__ fscr, R* __restrict__ b,
+                             int compact) {
+  const int dd = d * d;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < nfv * d; idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t v = idx / d;
+    int c = (int)(idx % d);
+    R acc = 0;
+    for (int p = vinc_off[v]; p < vinc_off[v + 1]; ++p) {
+      int64_t g = vinc[2 * p];
+      int sl = vinc[2 * p + 1];
+      acc += fscr[g * dd + sl * d + c];
+    }
+    if (compact) b[idx] = acc;
+    else b[(int64_t)free_to_lat[v] * d + c] = acc;
+  }
+}
+
+// E^d: y_F (+)= sum_{v,c} EF[g][q][v*d+c] x[v][c]  (x lattice-indexed or compact).
+template <typename R>
+__global__ void k_ed_facet(SolveParams P, OpPtrs<R> O, const int32_t* __restrict__ facet_vfree,
+                           const int32_t* __restrict__ free_to_lat, const R* __restrict__ x0, R* __restrict__ y,
+                           int add, int compact) {
+  const Sizes s = P.s;
+  const int d = s.d, dd = d * d;
+  const int64_t n = P.nff * s.nfb;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t g = idx / s.nfb;
+    int q = (int)(idx % s.nfb);
+    const R* E = O.EF + ((size_t)g * s.nfb + q) * dd;
+    R acc = 0;
+    for (int v = 0; v < d; ++v) {
+      int fv = facet_vfree[g * d + v];
+      if (fv < 0) continue;
+      int64_t base = compact ? (int64_t)fv * d : (int64_t)free_to_lat[fv] * d;
+      for (int c = 0; c < d; ++c) acc += E[v * d + c] * x0[base + c];
+    }
+    if (add) y[P.off_f + idx] += acc;
+    else y[P.off_f + idx] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- multigrid
+__device__ inline void mg_coords(int64_t v, const int* n, int c[3]) {
+  int N0 = n[0] + 1, N1 = n[1] + 1;
+  c[0] = (int)(v % N0);
+  c[1] = (int)((v / N0) % N1);
+  c[2] = (int)(v / ((int64_t)N0 * N1));
+}
+__device__ inline bool mg_interior(const int c[3], const int* n, int d) {
+  for (int a = 0; a < d; ++a)
+    if (c[a] <= 0 || c[a] >= n[a]) return false;
+  return true;
+}
+
+// mode 0: x = Dinv b;  mode 1: r = b - A x;  mode 2: x += Dinv (b - A x)
+template <typename R>
+__global__ void k_mg_point(int d, MGLevelDev L, int mode) {
+  const int st = d == 3 ? 27 : 9, dd = d * d;
+  const R* A = (const R*)L.A;
+  const R* Di = (const R*)L.Dinv;
+  R* x = (R*)L.x;
+  const R* b = (const R*)L.b;
+  R* r = (R*)L.r;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < L.nvert; v += (int64_t)gridDim.x * blockDim.x) {
+    int c[3];
+    mg_coords(v, L.n, c);
+    if (!mg_interior(c, L.n, d)) {
+      if (mode == 1)
+        for (int k = 0; k < d; ++k) r[v * d + k] = R(0);
+      continue;
+    }
+    R res[3];
+    for (int k = 0; k < d; ++k) res[k] = b[v * d + k];
+    if (mode != 0) {
+      const R* Av = A + (size_t)v * st * dd;
+      for (int o = 0; o < st; ++o) {
+        int w[3] = {c[0] + o % 3 - 1, c[1] + (o / 3) % 3 - 1, d == 3 ? c[2] + o / 9 - 1 : 0};
+        if (!mg_interior(w, L.n, d)) continue;
+        int64_t wi = w[0] + (int64_t)(L.n[0] + 1) * (w[1] + (int64_t)(L.n[1] + 1) * w[2]);
+        for (int k = 0; k < d; ++k)
+          for (int m = 0; m < d; ++m) res[k] -= Av[o * dd + k * d + m] * x[wi * d + m];
+      }
+    }
+    if (mode == 1) {
+      for (int k = 0; k < d; ++k) r[v * d + k] = res[k];
+    } else {
+      const R* D = Di + (size_t)v * dd;
+      R upd[3];
+      for (int k = 0; k < d; ++k) {
+        upd[k] = 0;
+        for (int m = 0; m < d; ++m) upd[k] += D[k * d + m] * res[m];
+      }
+      for (int k = 0; k < d; ++k) x[v * d + k] = (mode == 0 ? R(0) : x[v * d + k]) + upd[k];
+    }
+  }
+}
+
+__device__ inline int mg_cpos(int I, int n) { return (2 * I < n) ? 2 * I : n; }
+__device__ inline double mg_w(int i, int I, int n) {
+  int c = mg_cpos(I, n);
+  if (i == c) return 1.0;
+  bool is_coarse = (i % 2 == 0) || (i == n);
+  if (!is_coarse && (i - c == 1 || c - i == 1)) return 0.5;
+  return 0.0;
+}
+
+// b_c = P^T r_f (interior coarse vertices).
+template <typename R>
+__global__ void k_mg_restrict(int d, MGLevelDev F, MGLevelDev C) {
+  const R* r = (const R*)F.r;
+  R* bc = (R*)C.b;
+  const int st = d == 3 ? 27 : 9;
+  for (int64_t V = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; V < C.nvert; V += (int64_t)gridDim.x * blockDim.x) {
+    int CI[3];
+    mg_coords(V, C.n, CI);
+    R acc[3] = {0, 0, 0};
+    if (mg_interior(CI, C.n, d)) {
+      int base[3] = {mg_cpos(CI[0], F.n[0]), mg_cpos(CI[1], F.n[1]), d == 3 ? mg_cpos(CI[2], F.n[2]) : 0};
+      for (int o = 0; o < st; ++o) {
+        int fi[3] = {base[0] + o % 3 - 1, base[1] + (o / 3) % 3 - 1, d == 3 ? base[2] + o / 9 - 1 : 0};
+        if (!mg_interior(fi, F.n, d)) continue;
+        double w = 1.0;
+        for (int a = 0; a < d; ++a) w *= mg_w(fi[a], CI[a], F.n[a]);
+        if (w == 0.0) continue;
+        int64_t fv = fi[0] + (int64_t)(F.n[0] + 1) * (fi[1] + (int64_t)(F.n[1] + 1) * fi[2]);
+        for (int k = 0; k < d; ++k) acc[k] += (R)w * r[fv * d + k];
+      }
+    }
+    for (int k = 0; k < d; ++k) bc[V * d + k] = acc[k];
+  }
+}
+
+// x_f += P x_c (interior fine vertices).
+template <typename R>
+__global__ void k_mg_prolong(int d, MGLevelDev F, MGLevelDev C) {
+  R* x = (R*)F.x;
+  const R* xc = (const R*)C.x;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < F.nvert; v += (int64_t)gridDim.x * blockDim.x) {
+    int fi[3];
+    mg_coords(v, F.n, fi);
+    if (!mg_interior(fi, F.n, d)) continue;
+    R acc[3] = {0, 0, 0};
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      if (a < d) { lo[a] = fi[a] / 2 - 1; hi[a] = fi[a] / 2 + 1; if (lo[a] < 0) lo[a] = 0; if (hi[a] > C.n[a]) hi[a] = C.n[a]; }
+      else { lo[a] = 0; hi[a] = 0; }
+    }
+    for (int I2 = lo[2]; I2 <= hi[2]; ++I2)
+      for (int I1 = lo[1]; I1 <= hi[1]; ++I1)
+        for (int I0 = lo[0]; I0 <= hi[0]; ++I0) {
+          int CI[3] = {I0, I1, I2};
+          if (!mg_interior(CI, C.n, d)) continue;
+          double w = 1.0;
+          for (int a = 0; a < d; ++a) w *= mg_w(fi[a], CI[a], F.n[a]);
+          if (w == 0.0) continue;
+          int64_t cv = I0 + (int64_t)(C.n[0] + 1) * (I1 + (int64_t)(C.n[1] + 1) * I2);
+          for (int k = 0; k < d; ++k) acc[k] += (R)w * xc[cv * d + k];
+        }
+    for (int k = 0; k < d; ++k) x[v * d + k] += acc[k];
+  }
+}
+
+// Coarsest level: x = C^{-1} b over the free dofs (FP64 accumulation).
+template <typename R>
+__global__ void k_mg_coarse(int64_t nc, const double* __restrict__ Cinv, const int32_t* __restrict__ cmap, MGLevelDev L) {
+  const R* b = (const R*)L.b;
+  R* x = (R*)L.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nc; i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int64_t j = 0; j < nc; ++j) acc += Cinv[j * nc + i] * (double)b[cmap[j]];
+    x[cmap[i]] = (R)acc;
+  }
+}
+
+// ------------------------------------------------------------ pressure parts
+// y_p = M_p^{-1} (r_p - B a) with M_p^{-1} = (nu_T/|det J|) Mp^-1_ref.
+template <typename R>
+__global__ void __launch_bounds__(256) k_elem_press(SolveParams P, const R* __restrict__ a, const R* __restrict__ r,
+                                                    R* __restrict__ y, int with_B) {
+  const Sizes s = P.s;
+  const int nb = s.nb, nd = s.nd, np = s.np;
+  __shared__ R ad[MAXND], ao[MAXNB];
+  __shared__ double bp[MAXNP];
+  const int tid = threadIdx.x;
+  for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
+    const double det = P.detJ[e];
+    if (with_B) {
+      gather_elem_d(P, a, e, ad);
+      if (tid < nb) ao[tid] = a[e * nb + tid];
+    }
+    __syncthreads();
+    if (tid < np) {
+      double acc = (double)r[P.off_p + e * np + tid];
+      if (with_B) {
+        for (int i = 0; i < nb; ++i) acc -= Bentry(P, det, tid, i) * (double)ao[i];
+        for (int t = 0; t < nd; ++t) acc -= Bentry(P, det, tid, nb + t) * (double)ad[t];
+      }
+      bp[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < np) {
+      double sc = P.nu[e] / fabs(det);
+      double acc = 0.0;
+      for (int j = 0; j < np; ++j) acc += P.rMpinv[tid * np + j] * bp[j];
+      y[P.off_p + e * np + tid] = (R)(sc * acc);
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------- vectors
+template <typename R>
+__global__ void k_axpby(int64_t n, double a, const R* __restrict__ x, double b, R* __restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (R)(a * (double)x[i] + (b == 0.0 ? 0.0 : b * (double)y[i]));
+}
+
+template <typename R>
+__global__ void k_fill(int64_t n, R v, R* __restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = v;
+}
+
+template <typename A, typename B>
+__global__ void k_convert(int64_t n, const A* __restrict__ x, B* __restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = (B)x[i];
+}
+
+// Deterministic two-stage dot product: partial sums per block, FP64.
+template <typename R>
+__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const R* __restrict__ x, const R* __restrict__ y,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += (double)x[i] * (double)y[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_sum_partials(int n, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// MINRES direction / iterate update: w_new = a v + b w1 + c w2 (stored in w1), x += phi w_new.
+template <typename R>
+__global__ void k_minres_w(int64_t n, const R* __restrict__ v, R* __restrict__ w1, const R* __restrict__ w2,
+                           R* __restrict__ x, double a, double b, double c, double phi) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double wn = a * (double)v[i] + b * (double)w1[i] + c * (double)w2[i];
+    w1[i] = (R)wn;
+    x[i] = (R)((double)x[i] + phi * wn);
+  }
+}
+
+// y (double) += a * x (R)  /  y (B) = a * x (A)
+template <typename A, typename B>
+__global__ void k_scale_convert(int64_t n, double a, const A* __restrict__ x, B* __restrict__ y, int add) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v = a * (double)x[i];
+    y[i] = add ? (B)((double)y[i] + v) : (B)v;
+  }
+}
+
+// compact P1 vector (free vertices) <-> lattice-indexed vector
+template <typename R>
+__global__ void k_scatter_compact(int64_t nfv, int d, const int32_t* __restrict__ f2l, const R* __restrict__ c,
+                                  R* __restrict__ lat) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nfv * d; i += (int64_t)gridDim.x * blockDim.x)
+    lat[(int64_t)f2l[i / d] * d + i % d] = c[i];
+}
+template <typename R>
+__global__ void k_gather_compact(int64_t nfv, int d, const int32_t* __restrict__ f2l, const R* __restrict__ lat,
+                                 R* __restrict__ c) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nfv * d; i += (int64_t)gridDim.x * blockDim.x)
+    c[i] = lat[(int64_t)f2l[i / d] * d + i % d];
+}
+
+// ------------------------------------------------------------------ launchers
+static int grid_for(int64_t n, int per = 256) {
+  int64_t g = (n + per - 1) / per;
+  if (g > 65535 * 8) g = 65535 * 8;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+static int elem_grid(int64_t ne) { return (int)std::min<int64_t>(ne, 1 << 20); }
+
+template <typename R>
+void launch_elem_apply(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* x, R* y, R* escr, int flags) {
+  hipLaunchKernelGGL(k_elem_apply<R>, dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, x, y, escr, flags);
+}
+template <typename R>
+void launch_facet_sum(hipStream_t st, const SolveParams& P, const R* escr, const R* base, R sign, R* y) {
+  hipLaunchKernelGGL(k_facet_sum<R>, dim3(grid_for(P.nff * P.s.nfb)), dim3(256), 0, st, P, escr, base, sign, y);
+}
+template <typename R>
+void launch_ext_pre(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* to, R* escr) {
+  hipLaunchKernelGGL(k_ext_pre<R>, dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, r, to, escr);
+}
+template <typename R>
+void launch_ext_post(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* t, const R* to, R* y) {
+  hipLaunchKernelGGL(k_ext_post<R>, dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
+}
+template <typename R>
+void launch_smooth_phase(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
+                         const R* s) {
+  if (c1 <= c0) return;
+  hipLaunchKernelGGL(k_smooth_phase<R>, dim3((int)std::min<int64_t>(c1 - c0, 1 << 20)), dim3(256), 0, st, P, O, c0, c1, x, s);
+}
+template <typename R>
+void launch_edt(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* fscr, int64_t nfv,
+                const int32_t* vinc_off, const int32_t* vinc, const int32_t* free_to_lat, R* b, int compact) {
+  hipLaunchKernelGGL(k_edt_facet<R>, dim3(grid_for(P.nff * P.s.d * P.s.d)), dim3(256), 0, st, P, O, r, fscr);
+  hipLaunchKernelGGL(k_edt_vertex<R>, dim3(grid_for(nfv * P.s.d)), dim3(256), 0, st, P.s.d, nfv, vinc_off, vinc,
+                     free_to_lat, (const R*)fscr, b, compact);
+}
+template <typename R>
+void launch_ed(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const int32_t* facet_vfree,
+               const int32_t* free_to_lat, const R* x0, R* y, int add, int compact) {
+  hipLaunchKernelGGL(k_ed_facet<R>, dim3(grid_for(P.nff * P.s.nfb)), dim3(256), 0, st, P, O, facet_vfree, free_to_lat,
+                     x0, y, add, compact);
+}
+template <typename R>
+void launch_mg_point(hipStream_t st, int d, const MGLevelDev& L, int mode) {
+  hipLaunchKernelGGL(k_mg_point<R>, dim3(grid_for(L.nvert)), dim3(256), 0, st, d, L, mode);
+}
+template <typename R>
+void launch_mg_restrict(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C) {
+  hipLaunchKernelGGL(k_mg_restrict<R>, dim3(grid_for(C.nvert)), dim3(256), 0, st, d, F, C);
+}
+template <typename R>
+void launch_mg_prolong(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C) {
+  hipLaunchKernelGGL(k_mg_prolong<R>, dim3(grid_for(F.nvert)), dim3(256), 0, st, d, F, C);
+}
+template <typename R>
+void launch_mg_coarse(hipStream_t st, int64_t nc, const double* Cinv, const int32_t* cmap, const MGLevelDev& L) {
+  hipLaunchKernelGGL(k_mg_coarse<R>, dim3(grid_for(nc, 64)), dim3(64), 0, st, nc, Cinv, cmap, L);
+}
+template <typename R>
+void launch_elem_press(hipStream_t st, const SolveParams& P, const R* a, const R* r, R* y, int with_B) {
+  hipLaunchKernelGGL(k_elem_press<R>, dim3(elem_grid(P.ne)), dim3(256), 0, st, P, a, r, y, with_B);
+}
+template <typename R>
+void launch_axpby(hipStream_t st, int64_t n, double a, const R* x, double b, R* y) {
+  hipLaunchKernelGGL(k_axpby<R>, dim3(grid_for(n)), dim3(256), 0, st, n, a, x, b, y);
+}
+template <typename R>
+void launch_fill(hipStream_t st, int64_t n, R v, R* y) {
+  hipLaunchKernelGGL(k_fill<R>, dim3(grid_for(n)), dim3(256), 0, st, n, v, y);
+}
+template <typename A, typename B>
+void launch_convert(hipStream_t st, int64_t n, const A* x, B* y) {
+  hipLaunchKernelGGL((k_convert<A, B>), dim3(grid_for(n)), dim3(256), 0, st, n, x, y);
+}
+template <typename R>
+void launch_dot(hipStream_t st, int64_t n, const R* x, const R* y, double* part, double* out) {
+  int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(k_dot_partial<R>, dim3(nb), dim3(256), 0, st, n, x, y, part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, nb, (const double*)part, out);
+}
+
+template <typename R>
+void launch_scatter_compact(hipStream_t st, int64_t nfv, int d, const int32_t* f2l, const R* c, R* lat) {
+  hipLaunchKernelGGL(k_scatter_compact<R>, dim3(grid_for(nfv * d)), dim3(256), 0, st, nfv, d, f2l, c, lat);
+}
+template <typename R>
+void launch_gather_compact(hipStream_t st, int64_t nfv, int d, const int32_t* f2l, const R* lat, R* c) {
+  hipLaunchKernelGGL(k_gather_compact<R>, dim3(grid_for(nfv * d)), dim3(256), 0, st, nfv, d, f2l, lat, c);
+}
+template <typename R>
+void launch_minres_w(hipStream_t st, int64_t n, const R* v, R* w1, const R* w2, R* x, double a, double b, double c,
+                     double phi) {
+  hipLaunchKernelGGL(k_minres_w<R>, dim3(grid_for(n)), dim3(256), 0, st, n, v, w1, w2, x, a, b, c, phi);
+}
+template <typename A, typename B>
+void launch_scale_convert(hipStream_t st, int64_t n, double a, const A* x, B* y, int add) {
+  hipLaunchKernelGGL((k_scale_convert<A, B>), dim3(grid_for(n)), dim3(256), 0, st, n, a, x, y, add);
+}
+
+#define MCS_INST(R)                                                                                             \
+  template void launch_elem_apply<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, R*, R*, int); \
+  template void launch_facet_sum<R>(hipStream_t, const SolveParams&, const R*, const R*, R, R*);               \
+  template void launch_ext_pre<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, R*, R*);        \
+  template void launch_ext_post<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, const R*, R*); \
+  template void launch_smooth_phase<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, int32_t, int32_t, R*, \
+                                       const R*);                                                              \
+  template void launch_edt<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, R*, int64_t,         \
+                              const int32_t*, const int32_t*, const int32_t*, R*, int);                        \
+  template void launch_ed<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const int32_t*, const int32_t*, \
+                             const R*, R*, int, int);                                                          \
+  template void launch_mg_point<R>(hipStream_t, int, const MGLevelDev&, int);                                  \
+  template void launch_mg_restrict<R>(hipStream_t, int, const MGLevelDev&, const MGLevelDev&);                 \
+  template void launch_mg_prolong<R>(hipStream_t, int, const MGLevelDev&, const MGLevelDev&);                  \
+  template void launch_mg_coarse<R>(hipStream_t, int64_t, const double*, const int32_t*, const MGLevelDev&);   \
+  template void launch_elem_press<R>(hipStream_t, const SolveParams&, const R*, const R*, R*, int);            \
+  template void launch_axpby<R>(hipStream_t, int64_t, double, const R*, double, R*);                           \
+  template void launch_fill<R>(hipStream_t, int64_t, R, R*);                                                   \
+  template void launch_dot<R>(hipStream_t, int64_t, const R*, const R*, double*, double*);                  \
+  template void launch_minres_w<R>(hipStream_t, int64_t, const R*, R*, const R*, R*, double, double, double, double); \
+  template void launch_scatter_compact<R>(hipStream_t, int64_t, int, const int32_t*, const R*, R*);             \
+  template void launch_gather_compact<R>(hipStream_t, int64_t, int, const int32_t*, const R*, R*);
+
+MCS_INST(double)
+MCS_INST(float)
+template void launch_convert<double, float>(hipStream_t, int64_t, const double*, float*);
+template void launch_convert<float, double>(hipStream_t, int64_t, const float*, double*);
+template void launch_scale_convert<double, float>(hipStream_t, int64_t, double, const double*, float*, int);
+template void launch_scale_convert<float, double>(hipStream_t, int64_t, double, const float*, double*, int);
+template void launch_scale_convert<double, double>(hipStream_t, int64_t, double, const double*, double*, int);
+
+}  // namespace mcs

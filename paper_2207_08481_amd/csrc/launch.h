@@ -1,0 +1,68 @@
+// Host-side launch wrappers of the solve kernels (defined in kernels_solve.hip).
+#pragma once
+#include "kernels_common.h"
+
+namespace mcs {
+
+template <typename R>
+void launch_elem_apply(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* x, R* y, R* escr, int flags);
+template <typename R>
+void launch_facet_sum(hipStream_t st, const SolveParams& P, const R* escr, const R* base, R sign, R* y);
+template <typename R>
+void launch_ext_pre(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* to, R* escr);
+template <typename R>
+void launch_ext_post(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* t, const R* to, R* y);
+template <typename R>
+void launch_smooth_phase(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
+                         const R* s);
+template <typename R>
+void launch_edt(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* fscr, int64_t nfv,
+                const int32_t* vinc_off, const int32_t* vinc, const int32_t* free_to_lat, R* b, int compact);
+template <typename R>
+void launch_ed(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const int32_t* facet_vfree,
+               const int32_t* free_to_lat, const R* x0, R* y, int add, int compact);
+template <typename R>
+void launch_mg_point(hipStream_t st, int d, const MGLevelDev& L, int mode);
+template <typename R>
+void launch_mg_restrict(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C);
+template <typename R>
+void launch_mg_prolong(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C);
+template <typename R>
+void launch_mg_coarse(hipStream_t st, int64_t nc, const double* Cinv, const int32_t* cmap, const MGLevelDev& L);
+template <typename R>
+void launch_elem_press(hipStream_t st, const SolveParams& P, const R* a, const R* r, R* y, int with_B);
+template <typename R>
+void launch_axpby(hipStream_t st, int64_t n, double a, const R* x, double b, R* y);
+template <typename R>
+void launch_fill(hipStream_t st, int64_t n, R v, R* y);
+template <typename A, typename B>
+void launch_convert(hipStream_t st, int64_t n, const A* x, B* y);
+template <typename R>
+void launch_dot(hipStream_t st, int64_t n, const R* x, const R* y, double* part, double* out);
+
+template <typename R>
+void launch_minres_w(hipStream_t st, int64_t n, const R* v, R* w1, const R* w2, R* x, double a, double b, double c,
+                     double phi);
+template <typename A, typename B>
+void launch_scale_convert(hipStream_t st, int64_t n, double a, const A* x, B* y, int add);
+
+template <typename R>
+void launch_scatter_compact(hipStream_t st, int64_t nfv, int d, const int32_t* f2l, const R* c, R* lat);
+template <typename R>
+void launch_gather_compact(hipStream_t st, int64_t nfv, int d, const int32_t* f2l, const R* lat, R* c);
+
+// setup (kernels_setup.hip)
+void launch_condense(hipStream_t st, const CondParams& P, int nslots);
+void launch_facet_setup(hipStream_t st, const FacetSetupParams& P);
+void launch_p1_assemble(hipStream_t st, const P1Params& P);
+void launch_mg_l1(hipStream_t st, const MGSetupParams& P);
+void launch_mg_rap(hipStream_t st, const MGSetupParams& P);
+void launch_coarse(hipStream_t st, const MGSetupParams& P, double* Cd, double* W, double* Cinv, int* status);
+void launch_to_f32(hipStream_t st, const double* a, float* b, int64_t n);
+void launch_load(hipStream_t st, const CondParams& C, const SolveParams& P, const int32_t* elem_perm,
+                 const int32_t* latmap, const double* rRf, const double* f, double* b, double* escr);
+void launch_check_nu(hipStream_t st, const double* nu, int64_t n, int* status);
+void launch_pressure_mean(hipStream_t st, const SolveParams& P, const double* pmom, const double* pconst, double* x,
+                          double* red);
+
+}  // namespace mcs

@@ -1,0 +1,147 @@
+// Internal declarations of the MCS solver library (host + device).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mcs.h"
+
+namespace mcs {
+
+void set_error(const char* fmt, ...);
+
+// ---------------------------------------------------------------------------
+// Local sizes of the spaces (Sec. 3) for dimension d and order k.
+// ---------------------------------------------------------------------------
+struct Sizes {
+  int d, k, m;        // dimension, order, lattice degree of f
+  int nv;             // d + 1 vertices
+  int ns, nsm1;       // dim P^k(T), dim P^{k-1}(T)
+  int nFk, nFkm1;     // dim P^k(F), dim P^{k-1}(F)
+  int nu, nb, nF, nh, nfb, nd, nA, np;  // BDM, bubbles, facet normal, facet tangential, block, A^d, A, pressure
+  int nsym, nskew;    // orthonormal trace-free basis: symmetric / skew parts
+  int nsig;           // reduced sigma columns: nsym * ns + nskew * (ns - nsm1)
+  int nlam;           // nt-degree constraints: (d+1)(d-1)(nFk - nFkm1)
+  int nlat;           // lattice points of degree m
+};
+Sizes make_sizes(int d, int k);
+
+// ---------------------------------------------------------------------------
+// Reference-element tables (host computed once per (d, k), uploaded).
+// All integrals are over the reference simplex T^ = conv{0, e_1..e_d} or its
+// facets, with the reference measure.  Basis conventions:
+//   phi^_i (BDM, n_u): bubbles first, lambda^alpha (e_a - e_s0); then facet f
+//     functions (-1)^f (d-1)! lambda^beta (e_j0 - e_f).  Physical:
+//     bubbles J phi^, facet functions J phi^ / det J.
+//   psi^_a (n_s): L2(T^)/|T^|-orthonormal, degree graded (first nsm1 span P^{k-1}).
+//   q^ (facet, nFk - nFkm1): L2(F^)/|F^|-orthonormal basis of P^k(F) minus P^{k-1}(F).
+//   pressure lambda^gamma, |gamma| = k-1; lattice Lagrange L^_l (sorted order).
+// ---------------------------------------------------------------------------
+struct RefTables {
+  Sizes s;
+  std::vector<double> V;     // [nu][ns][d][d]      int psi_a d_s phi_{i,r}
+  std::vector<double> Bf;    // [nv][nu][ns][d]     int_{F_f} psi_a phi_{i,r}
+  std::vector<double> U;     // [nv][nFkm1][ns]     int_{F_f} psi_a lambda_F^gamma
+  std::vector<double> L;     // [nv][nq][ns]        int_{F_f} q_q psi_a
+  std::vector<double> D;     // [nu][nu]            int div phi_i div phi_j
+  std::vector<double> Bp;    // [np][nu]            int div phi_i lambda^gamma_q
+  std::vector<double> Mp;    // [np][np]            int lambda^gamma lambda^gamma'
+  std::vector<double> Mpinv; // [np][np]
+  std::vector<double> Rf;    // [nlat][nu][d]       int L_l phi_{i,r}
+  std::vector<int32_t> latmap; // [(d+1)!][nlat]   caller lattice index -> sorted lattice index
+  std::vector<double> cn;    // [nFk][d]            lambda_v (facet vertex v) in degree-k facet Bernstein
+  std::vector<double> ct;    // [nFkm1][d]          lambda_v in degree k-1 facet Bernstein
+  std::vector<double> pconst;// [np]                coefficients of p = 1
+  std::vector<double> pmom;  // [np]                int_T^ lambda^gamma / |T^|
+  double facet_measure[4];   // |F^_f|
+};
+RefTables build_ref_tables(int d, int k);
+int perm_index(const int* perm, int nv);   // rank of a permutation of 0..nv-1
+
+// ---------------------------------------------------------------------------
+// Multigrid lattice level.
+// ---------------------------------------------------------------------------
+struct MGLevel {
+  int n[3];           // intervals per axis (n[2] = 0 in 2D)
+  int64_t nvert;      // lattice vertices (incl. boundary)
+  int64_t off_A, off_Dinv, off_x, off_b, off_r;   // workspace offsets (bytes)
+  int64_t nfree;      // free dofs
+};
+
+// Device pointers of one problem (all inside the caller workspace).
+struct DevPtrs {
+  // topology
+  int32_t* elem_ff;       // [ne][nv] free facet id or -1
+  int32_t* elem_verts;    // [ne][nv] sorted global vertex ids
+  int32_t* elem_perm;     // [ne] permutation rank of sorted order w.r.t. caller order
+  int32_t* facet_el;      // [nff][2] neighbour elements (ascending)
+  int32_t* facet_slot;    // [nff][2] local facet index in each neighbour
+  int32_t* colour_facets; // [nff] facets sorted by colour
+  int32_t* facet_vfree;   // [nff][d] free P1 vertex ids of the facet's sorted vertices (-1)
+  int32_t* vinc_off;      // [nfv+1] free vertex -> incident (facet, slot) CSR
+  int32_t* vinc;          // [ninc][2]
+  int32_t* vert_elem_off; // [nvert+1] lattice vertex -> incident elements CSR
+  int32_t* vert_elem;     // [nve]
+  double* coords;         // [nvert][d]
+  int32_t* vfree_of_lat;  // [nvert] lattice vertex -> free P1 vertex or -1
+  int32_t* free_to_lat;   // [nfv] free P1 vertex -> lattice vertex
+  // reference tables
+  double *rV, *rBf, *rU, *rL, *rD, *rBp, *rMp, *rMpinv, *rRf, *rcn, *rct, *rpconst, *rpmom;
+  int32_t* rlatmap;
+  // element operators
+  double *nu, *detJ;
+  double *Ad, *H, *Ht, *Aoo, *Aooinv;
+  float *Ad32, *H32, *Ht32, *Aoo32, *Aooinv32;
+  double *Dinv, *EF;
+  float *Dinv32, *EF32;
+  // multigrid coarsest
+  double* Cinv;           // [nc][nc]
+  int32_t* cmap;          // [nc] coarsest free dof -> lattice dof index
+  // scratch
+  double* cscratch;       // condensation scratch (slots)
+  double* escr;           // [ne][nd] element vector scratch (double, reused as float)
+  double* escr2;          // [ne][nd]
+  double* fscr;           // [nff][d*d]
+  double* red;            // reduction partials
+  double* scal;           // scalar block (64 doubles)
+  double* vec;            // MINRES / preconditioner work vectors (FP64), nvec64 * ndof
+  float* vec32;           // FP32 work vectors, nvec32 * ndof
+  double* p1;             // P1 work vectors (FP64) 4 * np1
+  float* p132;            // P1 work vectors FP32
+};
+
+}  // namespace mcs
+
+struct mcs_problem {
+  mcs::Sizes sz;
+  mcs_options opt;
+  int d;
+  int64_t ne, nvert, nff, nfv;          // elements, vertices, free facets, free vertices
+  int lattice[3];
+  int ncol;
+  std::vector<int32_t> colour_off;      // [ncol+1]
+  std::vector<int32_t> h_colour;        // [nff] colour of facet
+  std::vector<int32_t> h_colour_facets, h_elem_ff, h_elem_verts, h_elem_perm, h_facet_el,
+      h_facet_slot, h_facet_vfree, h_vinc_off, h_vinc, h_vert_elem_off, h_vert_elem,
+      h_vfree_of_lat, h_free_to_lat;
+  std::vector<double> h_coords;
+  mcs::RefTables ref;
+  std::vector<mcs::MGLevel> mg;         // fine .. coarsest
+  int64_t nc;                            // coarsest free dofs
+  std::vector<int32_t> h_cmap;
+  int64_t ndof, off_f, off_p, np1;
+  int64_t n_slots;                       // condensation workgroup slots
+  int64_t slot_doubles;
+  int64_t nred;
+  int nvec64, nvec32;
+  size_t ws_bytes;
+  // binding
+  void* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int device = -1;
+  bool condensed = false;
+  mcs::DevPtrs p;
+  std::vector<std::pair<std::string, int64_t>> offsets;  // name -> byte offset
+};

@@ -1,0 +1,519 @@
+// Reference-element tables for the MCS element kernels (host, computed once
+// per dimension and order).  Integrals use collapsed (Duffy) Gauss-Legendre
+// rules on the reference simplex and its facets, exact for the polynomial
+// degrees involved (<= 2k+1).
+//
+// Spaces (Sec. 3 of the paper): BDM^k velocity split into normal bubbles and
+// facet functions (Sec. 4.2, "Static condensation of high order velocity
+// functions"), hat V_h facet tangential fields, P^{k-1} pressure, trace-free
+// stress polynomials P^k(T, D) described by an orthonormal scalar basis, and
+// the top-degree facet polynomials that define the nt-trace constraint of
+// Sigma_h (eq. fes_Sigma).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <numeric>
+#include <stdexcept>
+
+#include "mcs_internal.h"
+
+namespace mcs {
+
+namespace {
+
+using MI = std::vector<int>;
+
+void multi_rec(int nvars, int degree, MI& cur, std::vector<MI>& out) {
+  if (nvars == 1) {
+    cur.push_back(degree);
+    out.push_back(cur);
+    cur.pop_back();
+    return;
+  }
+  for (int a = degree; a >= 0; --a) {
+    cur.push_back(a);
+    multi_rec(nvars - 1, degree - a, cur, out);
+    cur.pop_back();
+  }
+}
+
+// Multi-indices of N^nvars with |alpha| = degree, lexicographically descending.
+std::vector<MI> multi_indices(int nvars, int degree) {
+  std::vector<MI> out;
+  MI cur;
+  multi_rec(nvars, degree, cur, out);
+  return out;
+}
+
+int64_t binom(int n, int r) {
+  if (r < 0 || r > n) return 0;
+  int64_t v = 1;
+  for (int i = 1; i <= r; ++i) v = v * (n - r + i) / i;
+  return v;
+}
+
+double fact(int n) {
+  double v = 1;
+  for (int i = 2; i <= n; ++i) v *= i;
+  return v;
+}
+
+// Gauss-Legendre nodes/weights on [0, 1] (Newton iteration on P_n).
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pn = (n == 1) ? z : p1;
+      double pnm1 = (n == 1) ? 1.0 : p0;
+      double dp = n * (z * pn - pnm1) / (z * z - 1.0);
+      double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int j = 2; j <= n; ++j) {
+      double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    double pn = (n == 1) ? z : p1;
+    double pnm1 = (n == 1) ? 1.0 : p0;
+    double dp = n * (z * pn - pnm1) / (z * z - 1.0);
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // 2/((1-z^2) P'^2) scaled by 1/2
+  }
+}
+
+struct Rule {
+  std::vector<std::vector<double>> lam;  // barycentric coordinates (dim+1)
+  std::vector<double> w;                 // weights, sum = 1/dim!
+};
+
+// Collapsed rule on the reference dim-simplex, n points per direction.
+Rule simplex_rule(int dim, int n) {
+  std::vector<double> g, gw;
+  gauss_legendre01(n, g, gw);
+  Rule R;
+  if (dim == 1) {
+    for (int i = 0; i < n; ++i) {
+      R.lam.push_back({1.0 - g[i], g[i]});
+      R.w.push_back(gw[i]);
+    }
+  } else if (dim == 2) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double x = g[i], y = g[j] * (1.0 - g[i]);
+        R.lam.push_back({1.0 - x - y, x, y});
+        R.w.push_back(gw[i] * gw[j] * (1.0 - g[i]));
+      }
+  } else {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        for (int l = 0; l < n; ++l) {
+          double x = g[i], y = g[j] * (1.0 - g[i]), z = g[l] * (1.0 - g[i]) * (1.0 - g[j]);
+          R.lam.push_back({1.0 - x - y - z, x, y, z});
+          R.w.push_back(gw[i] * gw[j] * gw[l] * (1.0 - g[i]) * (1.0 - g[i]) * (1.0 - g[j]));
+        }
+  }
+  return R;
+}
+
+double mono(const std::vector<double>& lam, const MI& a) {
+  double v = 1.0;
+  for (size_t j = 0; j < a.size(); ++j)
+    for (int p = 0; p < a[j]; ++p) v *= lam[j];
+  return v;
+}
+
+// d/dxhat_s of lambda^alpha on the reference simplex (lambda_0 = 1 - sum x).
+void mono_grad(const std::vector<double>& lam, const MI& a, int d, double* g) {
+  for (int s = 0; s < d; ++s) g[s] = 0.0;
+  for (int j = 0; j <= d; ++j) {
+    if (a[j] == 0) continue;
+    MI b = a;
+    b[j] -= 1;
+    double v = a[j] * mono(lam, b);
+    if (j == 0)
+      for (int s = 0; s < d; ++s) g[s] -= v;
+    else
+      g[j - 1] += v;
+  }
+}
+
+// Cholesky of an SPD matrix (row-major n x n) and inverse of its factor.
+std::vector<double> inverse_cholesky_factor(std::vector<double> G, int n) {
+  for (int j = 0; j < n; ++j) {
+    double s = G[j * n + j];
+    for (int p = 0; p < j; ++p) s -= G[j * n + p] * G[j * n + p];
+    if (s <= 0) throw std::runtime_error("reference Gram matrix not SPD");
+    double l = std::sqrt(s);
+    G[j * n + j] = l;
+    for (int i = j + 1; i < n; ++i) {
+      double t = G[i * n + j];
+      for (int p = 0; p < j; ++p) t -= G[i * n + p] * G[j * n + p];
+      G[i * n + j] = t / l;
+    }
+    for (int i = 0; i < j; ++i) G[i * n + j] = 0.0;
+  }
+  // invert lower triangular L
+  std::vector<double> Li(n * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int p = 0; p < i; ++p) t -= G[i * n + p] * Li[p * n + c];
+      Li[i * n + c] = t / G[i * n + i];
+    }
+  }
+  return Li;
+}
+
+std::vector<double> dense_inverse(std::vector<double> A, int n) {
+  std::vector<double> I(n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0) throw std::runtime_error("singular reference matrix");
+    if (piv != c)
+      for (int j = 0; j < n; ++j) {
+        std::swap(A[c * n + j], A[piv * n + j]);
+        std::swap(I[c * n + j], I[piv * n + j]);
+      }
+    double inv = 1.0 / A[c * n + c];
+    for (int j = 0; j < n; ++j) {
+      A[c * n + j] *= inv;
+      I[c * n + j] *= inv;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = A[r * n + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        A[r * n + j] -= f * A[c * n + j];
+        I[r * n + j] -= f * I[c * n + j];
+      }
+    }
+  }
+  return I;
+}
+
+// Degree-graded monomials x^e (|e| <= k) in nvar variables.
+std::vector<MI> graded_monomials(int nvar, int k) {
+  std::vector<MI> out;
+  for (int deg = 0; deg <= k; ++deg)
+    for (auto& e : multi_indices(nvar, deg)) out.push_back(e);
+  return out;
+}
+
+double xmono(const double* x, const MI& e) {
+  double v = 1.0;
+  for (size_t j = 0; j < e.size(); ++j)
+    for (int p = 0; p < e[j]; ++p) v *= x[j];
+  return v;
+}
+
+// Orthonormal, degree-graded basis of P^k in nvar variables on the reference
+// nvar-simplex w.r.t. (1/|T|) int: returns coefficient matrix C (n x n) so that
+// psi_a(x) = sum_e C[a][e] x^e.
+std::vector<double> orthonormal_basis(int nvar, int k, std::vector<MI>& mons) {
+  mons = graded_monomials(nvar, k);
+  int n = (int)mons.size();
+  Rule R = simplex_rule(nvar, k + 2);
+  double meas = 1.0 / fact(nvar);
+  std::vector<double> G(n * n, 0.0);
+  for (size_t q = 0; q < R.w.size(); ++q) {
+    const double* x = &R.lam[q][1];
+    std::vector<double> v(n);
+    for (int a = 0; a < n; ++a) v[a] = xmono(x, mons[a]);
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) G[a * n + b] += R.w[q] * v[a] * v[b] / meas;
+  }
+  return inverse_cholesky_factor(G, n);
+}
+
+}  // namespace
+
+Sizes make_sizes(int d, int k) {
+  Sizes s{};
+  s.d = d;
+  s.k = k;
+  s.m = k + 1;
+  s.nv = d + 1;
+  s.ns = (int)binom(k + d, d);
+  s.nsm1 = (int)binom(k - 1 + d, d);
+  s.nFk = (int)binom(k + d - 1, d - 1);
+  s.nFkm1 = (int)binom(k - 1 + d - 1, d - 1);
+  s.nu = d * s.ns;
+  s.nF = s.nFk;
+  s.nb = s.nu - (d + 1) * s.nF;
+  s.nh = (d - 1) * s.nFkm1;
+  s.nfb = s.nF + s.nh;
+  s.nd = (d + 1) * s.nfb;
+  s.nA = s.nu + (d + 1) * s.nh;
+  s.np = s.nsm1;
+  s.nsym = d * (d + 1) / 2 - 1;
+  s.nskew = d * (d - 1) / 2;
+  s.nsig = s.nsym * s.ns + s.nskew * (s.ns - s.nsm1);
+  s.nlam = (d + 1) * (d - 1) * (s.nFk - s.nFkm1);
+  s.nlat = (int)binom(s.m + d, d);
+  return s;
+}
+
+int perm_index(const int* perm, int nv) {
+  // rank among permutations of 0..nv-1 in lexicographic order
+  int r = 0;
+  for (int i = 0; i < nv; ++i) {
+    int smaller = 0;
+    for (int j = i + 1; j < nv; ++j)
+      if (perm[j] < perm[i]) ++smaller;
+    r = r * (nv - i) + smaller;
+  }
+  return r;
+}
+
+RefTables build_ref_tables(int d, int k) {
+  RefTables T;
+  Sizes s = make_sizes(d, k);
+  T.s = s;
+  const int nv = s.nv;
+
+  // ---------------- velocity basis description
+  struct VFun {
+    MI alpha;
+    double w[3];  // constant vector (reference), scaled
+  };
+  std::vector<VFun> phis;
+  auto evec = [&](int j, double* out) {  // reference vertex coordinates
+    for (int r = 0; r < d; ++r) out[r] = (j > 0 && r == j - 1) ? 1.0 : 0.0;
+  };
+  for (auto& a : multi_indices(nv, k)) {
+    std::vector<int> S;
+    for (int j = 0; j < nv; ++j)
+      if (a[j] > 0) S.push_back(j);
+    if (S.size() < 2) continue;
+    for (size_t t = 1; t < S.size(); ++t) {
+      VFun f;
+      f.alpha = a;
+      double ea[3], e0[3];
+      evec(S[t], ea);
+      evec(S[0], e0);
+      for (int r = 0; r < 3; ++r) f.w[r] = r < d ? ea[r] - e0[r] : 0.0;
+      phis.push_back(f);
+    }
+  }
+  if ((int)phis.size() != s.nb) throw std::runtime_error("bubble count mismatch");
+  for (int f = 0; f < nv; ++f) {
+    std::vector<int> fv;
+    for (int j = 0; j < nv; ++j)
+      if (j != f) fv.push_back(j);
+    double sign = (f % 2 == 0) ? 1.0 : -1.0;
+    for (auto& beta : multi_indices(d, k)) {
+      VFun F;
+      F.alpha.assign(nv, 0);
+      for (int j = 0; j < d; ++j) F.alpha[fv[j]] = beta[j];
+      int j0 = -1;
+      for (int j = 0; j < d; ++j)
+        if (beta[j] > 0) {
+          j0 = fv[j];
+          break;
+        }
+      double ej[3], ef[3];
+      evec(j0, ej);
+      evec(f, ef);
+      for (int r = 0; r < 3; ++r) F.w[r] = r < d ? sign * fact(d - 1) * (ej[r] - ef[r]) : 0.0;
+      phis.push_back(F);
+    }
+  }
+  if ((int)phis.size() != s.nu) throw std::runtime_error("BDM count mismatch");
+
+  auto phi_eval = [&](const std::vector<double>& lam, double* val /*[nu][d]*/,
+                      double* grad /*[nu][d][d]*/, double* div /*[nu]*/) {
+    for (int i = 0; i < s.nu; ++i) {
+      double m = mono(lam, phis[i].alpha);
+      double g[3];
+      mono_grad(lam, phis[i].alpha, d, g);
+      double dv = 0;
+      for (int r = 0; r < d; ++r) {
+        if (val) val[i * d + r] = m * phis[i].w[r];
+        for (int c = 0; c < d; ++c)
+          if (grad) grad[(i * d + r) * d + c] = phis[i].w[r] * g[c];
+        dv += phis[i].w[r] * g[r];
+      }
+      if (div) div[i] = dv;
+    }
+  };
+
+  // ---------------- orthonormal psi (volume) and top-degree q (facet)
+  std::vector<MI> mons;
+  std::vector<double> Cpsi = orthonormal_basis(d, k, mons);
+  auto psi_eval = [&](const std::vector<double>& lam, double* out) {
+    const double* x = &lam[1];
+    std::vector<double> mv(s.ns);
+    for (int e = 0; e < s.ns; ++e) mv[e] = xmono(x, mons[e]);
+    for (int a = 0; a < s.ns; ++a) {
+      double t = 0;
+      for (int e = 0; e <= a; ++e) t += Cpsi[a * s.ns + e] * mv[e];
+      out[a] = t;
+    }
+  };
+  std::vector<MI> fmons;
+  std::vector<double> Cq = orthonormal_basis(d - 1, k, fmons);
+  const int nq = s.nFk - s.nFkm1;
+  auto q_eval = [&](const std::vector<double>& mu, double* out) {  // mu: facet barycentrics (d)
+    const double* x = &mu[1];
+    std::vector<double> mv(s.nFk);
+    for (int e = 0; e < s.nFk; ++e) mv[e] = xmono(x, fmons[e]);
+    for (int qq = 0; qq < nq; ++qq) {
+      int a = s.nFkm1 + qq;
+      double t = 0;
+      for (int e = 0; e <= a; ++e) t += Cq[a * s.nFk + e] * mv[e];
+      out[qq] = t;
+    }
+  };
+
+  auto Ip = multi_indices(nv, k - 1);   // pressure
+  auto IFg = multi_indices(d, k - 1);   // facet tangential scalar part
+
+  // ---------------- lattice Lagrange basis (sorted order), degree m
+  auto Ilat = multi_indices(nv, s.m);
+  const int nlat = (int)Ilat.size();
+  std::vector<double> Vl(nlat * nlat);
+  for (int l = 0; l < nlat; ++l) {
+    std::vector<double> lam(nv);
+    for (int j = 0; j < nv; ++j) lam[j] = double(Ilat[l][j]) / s.m;
+    for (int a = 0; a < nlat; ++a) Vl[l * nlat + a] = mono(lam, Ilat[a]);
+  }
+  std::vector<double> Vinv = dense_inverse(Vl, nlat);  // [alpha][l]
+
+  // ---------------- volume integrals
+  T.V.assign((size_t)s.nu * s.ns * d * d, 0.0);
+  T.D.assign((size_t)s.nu * s.nu, 0.0);
+  T.Bp.assign((size_t)s.np * s.nu, 0.0);
+  T.Mp.assign((size_t)s.np * s.np, 0.0);
+  T.Rf.assign((size_t)nlat * s.nu * d, 0.0);
+  {
+    Rule R = simplex_rule(d, k + 3);
+    std::vector<double> val(s.nu * d), grad(s.nu * d * d), dv(s.nu), ps(s.ns), pp(s.np),
+        Ll(nlat);
+    for (size_t q = 0; q < R.w.size(); ++q) {
+      const auto& lam = R.lam[q];
+      double w = R.w[q];
+      phi_eval(lam, val.data(), grad.data(), dv.data());
+      psi_eval(lam, ps.data());
+      for (int g = 0; g < s.np; ++g) pp[g] = mono(lam, Ip[g]);
+      for (int l = 0; l < nlat; ++l) {
+        double t = 0;
+        for (int a = 0; a < nlat; ++a) t += Vinv[a * nlat + l] * mono(lam, Ilat[a]);
+        Ll[l] = t;
+      }
+      for (int i = 0; i < s.nu; ++i) {
+        for (int a = 0; a < s.ns; ++a)
+          for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c)
+              T.V[((size_t(i) * s.ns + a) * d + r) * d + c] += w * ps[a] * grad[(i * d + r) * d + c];
+        for (int j = 0; j < s.nu; ++j) T.D[i * s.nu + j] += w * dv[i] * dv[j];
+        for (int g = 0; g < s.np; ++g) T.Bp[g * s.nu + i] += w * dv[i] * pp[g];
+        for (int l = 0; l < nlat; ++l)
+          for (int r = 0; r < d; ++r) T.Rf[(size_t(l) * s.nu + i) * d + r] += w * Ll[l] * val[i * d + r];
+      }
+      for (int g = 0; g < s.np; ++g)
+        for (int h = 0; h < s.np; ++h) T.Mp[g * s.np + h] += w * pp[g] * pp[h];
+    }
+  }
+  T.Mpinv = dense_inverse(T.Mp, s.np);
+
+  // ---------------- facet integrals
+  T.Bf.assign((size_t)nv * s.nu * s.ns * d, 0.0);
+  T.U.assign((size_t)nv * s.nFkm1 * s.ns, 0.0);
+  T.L.assign((size_t)nv * nq * s.ns, 0.0);
+  {
+    Rule R = simplex_rule(d - 1, k + 3);
+    for (int f = 0; f < nv; ++f) {
+      std::vector<int> fv;
+      for (int j = 0; j < nv; ++j)
+        if (j != f) fv.push_back(j);
+      double meas = (f == 0) ? std::sqrt(double(d)) / fact(d - 1) : 1.0 / fact(d - 1);
+      T.facet_measure[f] = meas;
+      std::vector<double> val(s.nu * d), ps(s.ns), qv(nq);
+      for (size_t q = 0; q < R.w.size(); ++q) {
+        const auto& mu = R.lam[q];
+        double w = R.w[q] * fact(d - 1) * meas;
+        std::vector<double> lam(nv, 0.0);
+        for (int j = 0; j < d; ++j) lam[fv[j]] = mu[j];
+        phi_eval(lam, val.data(), nullptr, nullptr);
+        psi_eval(lam, ps.data());
+        q_eval(mu, qv.data());
+        for (int i = 0; i < s.nu; ++i)
+          for (int a = 0; a < s.ns; ++a)
+            for (int r = 0; r < d; ++r)
+              T.Bf[((size_t(f) * s.nu + i) * s.ns + a) * d + r] += w * ps[a] * val[i * d + r];
+        for (int g = 0; g < s.nFkm1; ++g) {
+          double m = mono(mu, IFg[g]);
+          for (int a = 0; a < s.ns; ++a) T.U[(size_t(f) * s.nFkm1 + g) * s.ns + a] += w * ps[a] * m;
+        }
+        for (int qq = 0; qq < nq; ++qq)
+          for (int a = 0; a < s.ns; ++a) T.L[(size_t(f) * nq + qq) * s.ns + a] += w * qv[qq] * ps[a];
+      }
+    }
+  }
+
+  // ---------------- lattice permutation maps
+  {
+    std::vector<int> perm(nv);
+    std::iota(perm.begin(), perm.end(), 0);
+    int nperm = (int)fact(nv);
+    T.latmap.assign((size_t)nperm * nlat, -1);
+    std::map<MI, int> idx;
+    for (int l = 0; l < nlat; ++l) idx[Ilat[l]] = l;
+    do {
+      int r = perm_index(perm.data(), nv);
+      for (int l = 0; l < nlat; ++l) {
+        MI b(nv);
+        for (int j = 0; j < nv; ++j) b[j] = Ilat[l][perm[j]];
+        T.latmap[(size_t)r * nlat + l] = idx[b];
+      }
+    } while (std::next_permutation(perm.begin(), perm.end()));
+  }
+
+  // ---------------- embedding coefficients: lambda_v in facet Bernstein
+  {
+    auto IFk = multi_indices(d, k);
+    T.cn.assign((size_t)s.nFk * d, 0.0);
+    for (int b = 0; b < s.nFk; ++b)
+      for (int v = 0; v < d; ++v) {
+        if (IFk[b][v] < 1) continue;
+        double den = 1.0;
+        for (int j = 0; j < d; ++j) den *= fact(IFk[b][j] - (j == v ? 1 : 0));
+        T.cn[b * d + v] = fact(k - 1) / den;
+      }
+    T.ct.assign((size_t)s.nFkm1 * d, 0.0);
+    for (int g = 0; g < s.nFkm1; ++g)
+      for (int v = 0; v < d; ++v) {
+        if (IFg[g][v] < 1) continue;
+        double den = 1.0;
+        for (int j = 0; j < d; ++j) den *= fact(IFg[g][j] - (j == v ? 1 : 0));
+        T.ct[g * d + v] = fact(k - 2) / den;
+      }
+  }
+  T.pconst.resize(s.np);
+  T.pmom.resize(s.np);
+  for (int g = 0; g < s.np; ++g) {
+    double den = 1.0;
+    for (int j = 0; j < nv; ++j) den *= fact(Ip[g][j]);
+    T.pconst[g] = fact(k - 1) / den;
+    T.pmom[g] = fact(d) * den / fact(k - 1 + d);
+  }
+  return T;
+}
+
+}  // namespace mcs

@@ -1,0 +1,255 @@
+"""ctypes binding of libmcs.so (the C ABI declared in include/mcs.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  PyTorch provides device memory (the workspace and vectors) and the
+stream.  The binding refuses to run when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcs.so")
+
+# status codes (mcs_status)
+OK = 0
+STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_MESH", -3: "ERR_WORKSPACE", -4: "ERR_NOT_SPD",
+          -5: "ERR_NOT_CONVERGED", -6: "ERR_BREAKDOWN", -7: "ERR_NONFINITE", -8: "ERR_STATE",
+          -9: "ERR_HIP", -10: "ERR_UNSUPPORTED"}
+F64, F32 = 0, 1
+OP = {"K": 0, "A": 1, "ADELTA": 2, "B": 3, "BT": 4}
+PC = {"KHAT": 0, "AEXT": 1, "ADELTA_MULT": 2, "SMOOTH_FWD": 3, "SMOOTH_BWD": 4, "AUX": 5,
+      "EDELTA": 6, "EDELTA_T": 7, "MG": 8, "MP_INV": 9}
+
+# exported symbols of include/mcs.h
+SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
+           "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
+           "mcs_get_topology", "mcs_destroy", "mcs_status_string", "mcs_last_error"]
+
+
+class MCSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_vertices", C.c_int32), ("vertices_host", C.c_void_p),
+                ("n_elements", C.c_int32), ("elements_host", C.c_void_p), ("lattice", C.c_int32 * 3)]
+
+
+class Options(C.Structure):
+    _fields_ = [("order", C.c_int32), ("precision", C.c_int32), ("smoothing_steps", C.c_int32),
+                ("max_it", C.c_int32), ("tol", C.c_double), ("inner_tol", C.c_double),
+                ("max_outer", C.c_int32), ("coarse_max", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_dof", C.c_int64), ("n_bubble_dofs", C.c_int64), ("n_facet_dofs", C.c_int64),
+                ("n_pressure_dofs", C.c_int64), ("n_p1_dofs", C.c_int64), ("off_facet", C.c_int64),
+                ("off_pressure", C.c_int64), ("n_bub", C.c_int32), ("n_F", C.c_int32),
+                ("n_hat", C.c_int32), ("n_fb", C.c_int32), ("n_p", C.c_int32), ("n_lat", C.c_int32),
+                ("n_free_facets", C.c_int32), ("n_colours", C.c_int32), ("n_mg_levels", C.c_int32),
+                ("workspace_bytes", C.c_size_t)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("outer_steps", C.c_int32),
+                ("rel_precond_residual", C.c_double), ("rel_residual", C.c_double),
+                ("t_solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmcs.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} not found: build it with paper_2207_08481_amd/build.py")
+    lib = C.CDLL(path)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.mcs_plan.argtypes = [C.POINTER(Mesh), C.POINTER(Options), C.POINTER(vp), C.POINTER(Info)]
+    lib.mcs_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    lib.mcs_condense.argtypes = [vp, vp]
+    lib.mcs_load.argtypes = [vp, vp, vp]
+    lib.mcs_apply.argtypes = [vp, i32, i32, vp, vp]
+    lib.mcs_precond_apply.argtypes = [vp, i32, i32, vp, vp]
+    lib.mcs_solve.argtypes = [vp, vp, vp, C.POINTER(SolveInfo)]
+    lib.mcs_solve_rhs.argtypes = [vp, vp, vp, C.POINTER(SolveInfo)]
+    lib.mcs_normalize_pressure.argtypes = [vp, vp]
+    lib.mcs_get_array.argtypes = [vp, C.c_char_p, C.POINTER(vp), C.POINTER(i64)]
+    lib.mcs_get_topology.argtypes = [vp, vp, vp]
+    lib.mcs_destroy.argtypes = [vp]
+    lib.mcs_destroy.restype = None
+    lib.mcs_status_string.argtypes = [i32]
+    lib.mcs_status_string.restype = C.c_char_p
+    lib.mcs_last_error.argtypes = []
+    lib.mcs_last_error.restype = C.c_char_p
+    for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
+                 "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
+                 "mcs_get_topology"):
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise MCSError(rc, _lib.mcs_last_error().decode())
+
+
+class _CudaArray:
+    """Minimal __cuda_array_interface__ wrapper around a device pointer."""
+
+    def __init__(self, ptr, n, typestr):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False),
+                                         "version": 3, "strides": None}
+
+
+@dataclass
+class ProblemSpec:
+    vertices: np.ndarray
+    elements: np.ndarray
+    lattice: tuple
+    order: int
+
+
+class Problem:
+    """One MCS Stokes problem: plan (host), bind (device workspace), condense,
+    solve.  Names follow the C ABI."""
+
+    def __init__(self, vertices, elements, lattice, order, precision=0, smoothing_steps=2,
+                 tol=1e-10, max_it=2000, inner_tol=1e-5, max_outer=10, coarse_max=1500):
+        lib = load_library()
+        self._lib = lib
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        e = np.ascontiguousarray(elements, dtype=np.int32)
+        self.dim = v.shape[1]
+        self._v, self._e = v, e
+        lat = list(lattice) + [1] * (3 - len(lattice))
+        self._mesh = Mesh(self.dim, v.shape[0], v.ctypes.data, e.shape[0], e.ctypes.data,
+                          (C.c_int32 * 3)(*lat))
+        self._opt = Options(order, precision, smoothing_steps, max_it, tol, inner_tol, max_outer,
+                            coarse_max)
+        self.info = Info()
+        h = C.c_void_p()
+        _check(lib.mcs_plan(C.byref(self._mesh), C.byref(self._opt), C.byref(h), C.byref(self.info)))
+        self._h = h
+        self.workspace = None
+        self.order = order
+        self.n_elements = e.shape[0]
+
+    # ------------------------------------------------------------------ host
+    @property
+    def n_dof(self):
+        return self.info.n_dof
+
+    def topology(self):
+        colour = np.zeros(self.info.n_free_facets, dtype=np.int32)
+        eff = np.zeros(self.n_elements * (self.dim + 1), dtype=np.int32)
+        _check(self._lib.mcs_get_topology(self._h, colour.ctypes.data, eff.ctypes.data))
+        return colour, eff.reshape(self.n_elements, self.dim + 1)
+
+    # ---------------------------------------------------------------- device
+    def bind(self, device="cuda:0"):
+        import torch
+        dev = torch.device(device)
+        torch.cuda.set_device(dev)
+        self.device = dev
+        self.workspace = torch.empty(self.info.workspace_bytes, dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev)
+        _check(self._lib.mcs_bind(self._h, self.workspace.data_ptr(), self.info.workspace_bytes,
+                                  self.stream.cuda_stream))
+        return self
+
+    def condense(self, nu):
+        import torch
+        nu = torch.as_tensor(nu, dtype=torch.float64, device=self.device).contiguous()
+        if nu.numel() == 1:
+            nu = nu.expand(self.n_elements).contiguous()
+        self._nu = nu
+        _check(self._lib.mcs_condense(self._h, nu.data_ptr()))
+
+    def vector(self, dtype=None):
+        import torch
+        return torch.zeros(self.n_dof, dtype=dtype or torch.float64, device=self.device)
+
+    def load(self, f_lattice):
+        import torch
+        f = torch.as_tensor(f_lattice, dtype=torch.float64, device=self.device).contiguous()
+        b = self.vector()
+        _check(self._lib.mcs_load(self._h, f.data_ptr(), b.data_ptr()))
+        return b
+
+    @staticmethod
+    def _dt(t):
+        import torch
+        return F64 if t.dtype == torch.float64 else F32
+
+    def apply(self, op, x, y=None):
+        if y is None:
+            y = x.new_zeros(self.n_dof)
+        _check(self._lib.mcs_apply(self._h, OP[op], self._dt(x), x.data_ptr(), y.data_ptr()))
+        return y
+
+    def precond_apply(self, op, r, z=None, out_len=None):
+        if z is None:
+            n = out_len if out_len is not None else (
+                self.info.n_p1_dofs if op in ("EDELTA_T", "MG") else self.n_dof)
+            z = r.new_zeros(n)
+        _check(self._lib.mcs_precond_apply(self._h, PC[op], self._dt(r), r.data_ptr(), z.data_ptr()))
+        return z
+
+    def solve(self, f_lattice):
+        import torch
+        f = torch.as_tensor(f_lattice, dtype=torch.float64, device=self.device).contiguous()
+        x = self.vector()
+        si = SolveInfo()
+        rc = self._lib.mcs_solve(self._h, f.data_ptr(), x.data_ptr(), C.byref(si))
+        _check(rc)
+        return x, si.as_dict()
+
+    def solve_rhs(self, b):
+        x = self.vector()
+        si = SolveInfo()
+        _check(self._lib.mcs_solve_rhs(self._h, b.data_ptr(), x.data_ptr(), C.byref(si)))
+        return x, si.as_dict()
+
+    def normalize_pressure(self, x):
+        _check(self._lib.mcs_normalize_pressure(self._h, x.data_ptr()))
+        return x
+
+    def get_array(self, name):
+        """torch view of an internal workspace array (float64 unless '32')."""
+        import torch
+        p = C.c_void_p()
+        n = C.c_int64()
+        _check(self._lib.mcs_get_array(self._h, name.encode(), C.byref(p), C.byref(n)))
+        if name in ("colour_facets", "elem_ff"):
+            typestr = "<i4"
+        elif name.endswith("32"):
+            typestr = "<f4"
+        else:
+            typestr = "<f8"
+        return torch.as_tensor(_CudaArray(p.value, n.value, typestr), device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mcs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

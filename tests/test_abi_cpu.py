@@ -1,0 +1,130 @@
+"""CPU checks of the C ABI library: it loads, exports every function declared
+in include/mcs.h, and its host planning (topology, dof counts, colouring,
+multigrid plan, error codes) agrees with the oracle and the definitions.
+No compute calls (no GPU here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2207_08481_amd", "libmcs.so")
+HEADER = os.path.join(ROOT, "include", "mcs.h")
+
+needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libmcs.so not built")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcs_[a-z_0-9]+)\s*\(", txt)))
+
+
+@needs_lib
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2207_08481_amd.mcs import SYMBOLS
+    assert sorted(SYMBOLS) == names
+
+
+@needs_lib
+@pytest.mark.parametrize("d,n,k", [(2, 4, 2), (2, 3, 4), (3, 2, 2), (3, 3, 3), (3, 2, 5)])
+def test_plan_sizes_and_topology(d, n, k):
+    from paper_2207_08481_amd import Problem
+    from oracle.topology import Topology
+    from oracle.element import expected_dims
+    mesh = W.unit_square_mesh(n) if d == 2 else W.unit_cube_mesh(n)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, k)
+    topo = Topology(mesh.vertices, mesh.elements)
+    dims = expected_dims(d, k)
+    i = pb.info
+    assert i.n_bub == dims["n_bub"] and i.n_F == dims["n_F"] and i.n_hat == dims["n_hat"]
+    assert i.n_p == dims["n_p"]
+    assert i.n_free_facets == topo.n_free_facets
+    ne = mesh.n_elements
+    assert i.n_dof == ne * dims["n_bub"] + topo.n_free_facets * dims["n_fb"] + ne * dims["n_p"]
+    assert i.n_p1_dofs == d * len(topo.free_vertices)
+    colour, eff = pb.topology()
+    assert np.array_equal(colour, topo.colour)
+    ff = np.where(topo.free_facet_of[topo.elem_facets] >= 0, topo.free_facet_of[topo.elem_facets], -1)
+    assert np.array_equal(eff, ff)
+    # colouring validity: facets of one element have distinct colours
+    for e in range(ne):
+        cs = [colour[g] for g in eff[e] if g >= 0]
+        assert len(cs) == len(set(cs))
+    assert i.workspace_bytes > 0
+
+
+@needs_lib
+def test_paper_scale_dof_count():
+    """32^3 x 6 tets, k = 4: 26,327,040 free dofs (2 n_fb + n_bub + n_p per tet asymptotically)."""
+    from paper_2207_08481_amd import Problem
+    mesh = W.unit_cube_mesh(32)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 4)
+    assert pb.info.n_dof == 26327040
+    assert pb.info.n_colours == 4
+    assert pb.info.n_mg_levels == 3
+
+
+@needs_lib
+def test_multigrid_levels_rule():
+    from paper_2207_08481_amd import Problem
+    mesh = W.unit_cube_mesh(16)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 2)
+    assert pb.info.n_mg_levels == 2        # 15^3*3 = 10125 > 1500 -> 7^3*3 = 1029
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, coarse_max=100)
+    assert pb.info.n_mg_levels == 3
+
+
+@needs_lib
+def test_error_codes():
+    from paper_2207_08481_amd.mcs import Problem, MCSError
+    mesh = W.unit_cube_mesh(2)
+    with pytest.raises(MCSError) as ex:
+        Problem(mesh.vertices, mesh.elements, mesh.lattice, 1)
+    assert ex.value.status == -1
+    with pytest.raises(MCSError) as ex:
+        Problem(mesh.vertices, mesh.elements, mesh.lattice, 6)
+    assert ex.value.status == -10
+    bad = mesh.elements.copy()
+    bad[0, 1] = bad[0, 0]
+    with pytest.raises(MCSError) as ex:
+        Problem(mesh.vertices, bad, mesh.lattice, 2)
+    assert ex.value.status == -2
+    flat = mesh.vertices.copy()
+    flat[:, 2] = 0.0
+    with pytest.raises(MCSError) as ex:
+        Problem(flat, mesh.elements, mesh.lattice, 2)
+    assert ex.value.status == -2
+    with pytest.raises(MCSError) as ex:
+        Problem(mesh.vertices, mesh.elements, (3, 3, 4), 2)
+    assert ex.value.status == -2
+    nanv = mesh.vertices.copy()
+    nanv[3, 0] = np.nan
+    with pytest.raises(MCSError) as ex:
+        Problem(nanv, mesh.elements, mesh.lattice, 2)
+    assert ex.value.status == -1
+    with pytest.raises(MCSError) as ex:
+        Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, precision=3)
+    assert ex.value.status == -1
+
+
+@needs_lib
+def test_unbound_calls_are_refused():
+    from paper_2207_08481_amd.mcs import Problem, load_library
+    import ctypes as C
+    mesh = W.unit_square_mesh(2)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 2)
+    lib = load_library()
+    rc = lib.mcs_condense(pb._h, C.c_void_p(0))
+    assert rc == -8          # not bound to a workspace
+    rc = lib.mcs_bind(pb._h, C.c_void_p(0), 0, C.c_void_p(0))
+    assert rc == -3          # workspace missing
