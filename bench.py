@@ -1,0 +1,190 @@
+"""Benchmark of the MCS Stokes hot path on one MI355X.
+
+A step is one pass of the whole path on one synthetic problem that is already
+resident in HBM: element matrices and static condensation, smoother / embedding
+/ multigrid setup (mcs_condense), load assembly and the preconditioned MINRES
+solve with pressure normalisation (mcs_solve).  The metric is the paper's
+DOF-iterations per second of the solve phase, #D * #IT / t_sol, with #D the
+free dofs of V_h x hat V_h x Q_h and t_sol the solve time without setup (the
+paper separates t_sup and t_sol).  Setup and total times are reported beside it.
+
+Prints one JSON line.  Extra objects:
+  roofline      the coloured block Gauss-Seidel phase kernel (the dominant
+                kernel): algorithmic bytes per launch / its average launch
+                duration, timed live with HIP events around every launch
+                inside the timed steps (mcs_timer_*), against 8 TB/s HBM.
+  cpu_baseline  the FP64 oracle timed on the host on a bounded sample of the
+                same workload recipe (a smaller cube, a few MINRES iterations),
+                single threaded.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+WORKLOADS = {
+    # name: (workload key in workloads.py, precision, description)
+    "cube16_k3": ("cube16_k3", 0, "unit cube 16^3 x 6 tets (24,576), k=3, nu=1, curl of 8 random sin^2 modes, FP64, tol 1e-10"),
+    "cube32_k4_mixed": ("cube32_k4_lognormal", 1, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 contrast), random smooth f, FP32 inner + FP64 refinement, tol 1e-10"),
+    "cube32_k4_fp64": ("cube32_k4_lognormal", 0, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 contrast), random smooth f, FP64, tol 1e-10"),
+    "square8_k2": ("square8_k2", 0, "unit square 8x8 x 2 triangles, k=2, nu=1, FP64, tol 1e-10"),
+}
+
+
+def cpu_baseline(seconds_hint=20.0):
+    """Time the oracle (as it stands) on a bounded sample in a child process:
+    the same cube recipe (k=3, nu=1, curl modes) on 3^3 x 6 tets, 40 MINRES
+    iterations; single-threaded BLAS.  Returns the cpu_baseline object."""
+    code = r'''
+import sys, time, json
+sys.path.insert(0, %r)
+import numpy as np, workloads as W
+from oracle.system import GlobalSystem
+from oracle.precond import Preconditioner
+from oracle.minres import minres
+wl = W.workload("cube16_k3", n=3)
+m = wl["mesh"]
+gs = GlobalSystem(m.vertices, m.elements, wl["nu"], wl["k"], wl["f_lattice"])
+pc = Preconditioner(gs, m.lattice)
+K = gs.assemble_K(); b = gs.assemble_rhs()
+t = time.perf_counter()
+x, info = minres(lambda v: K @ v, pc.apply, b, tol=1e-30, max_it=40)
+dt = time.perf_counter() - t
+print(json.dumps({"ndof": gs.n_dof, "its": info["iterations"], "t": dt}))
+''' % ROOT
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=600)
+    if out.returncode != 0:
+        return {"value": None, "unit": "DOF-iterations/s", "cores": 1, "kind": "oracle",
+                "sample": "failed: " + out.stderr[-300:]}
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": r["ndof"] * r["its"] / r["t"], "unit": "DOF-iterations/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"FP64 oracle MINRES, {r['its']} iterations on the 3^3 x 6-tet cube of the same "
+                      f"recipe (k=3, nu=1, {r['ndof']} dofs), {r['t']:.1f} s, 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cube16_k3", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times (calibrates "
+                         "FETCH_SIZE / WRITE_SIZE counters against a plain copy of known size)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
+              "not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2207_08481_amd import Problem
+
+    key, precision, desc = WORKLOADS[args.workload]
+    log(f"workload {args.workload}")
+    wl = W.workload(key)
+    mesh = wl["mesh"]
+    k = wl["k"]
+    dev = "cuda:0"
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, k, precision=precision,
+                 tol=1e-10, max_it=5000).bind(dev)
+    nu = torch.as_tensor(wl["nu"], device=dev)
+    f = torch.as_tensor(wl["f_lattice"], device=dev)
+    ndof = pb.n_dof
+    log(f"planned: {ndof} dofs, workspace {pb.info.workspace_bytes / 1e9:.1f} GB")
+
+    def step():
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        pb.condense(nu)
+        ev1.record()
+        x, si = pb.solve(f)
+        torch.cuda.synchronize()
+        log(f"step: setup {ev0.elapsed_time(ev1):.1f} ms, {si['iterations']} iterations, "
+            f"solve {si['t_solve_ms']:.1f} ms, rel {si['rel_precond_residual']:.2e}")
+        return ev0.elapsed_time(ev1), si
+
+    for _ in range(args.warmup):
+        step()
+    pb.timer_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_sup = t_sol = 0.0
+    its = 0
+    infos = []
+    for _ in range(args.steps):
+        ts, si = step()
+        t_sup += ts
+        t_sol += si["t_solve_ms"]
+        its += si["iterations"]
+        infos.append(si)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, klaunch, kbytes = pb.timer_read()
+    pb.timer_enable(False)
+
+    value = ndof * its / (t_sol / 1e3)
+    avg_launch_ms = kms / max(klaunch, 1)
+    bytes_per_launch = kbytes / max(klaunch, 1)
+    achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_smooth_phase (one colour of one block Gauss-Seidel sweep)",
+                "avg_launch_us": round(avg_launch_ms * 1e3, 2), "launches": klaunch,
+                "bytes_per_launch": int(bytes_per_launch)}
+    out = {
+        "metric": "DOF-iterations/s of preconditioned MCS solve",
+        "value": value,
+        "unit": "DOF-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n_dof": ndof, "tets": mesh.n_elements, "order": k,
+                   "iterations_per_solve": its / args.steps,
+                   "t_sup_ms": t_sup / args.steps, "t_sol_ms": t_sol / args.steps,
+                   "rel_precond_residual": infos[-1]["rel_precond_residual"],
+                   "rel_residual": infos[-1]["rel_residual"],
+                   "outer_steps": infos[-1]["outer_steps"]},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    if args.copy_calib_mb:
+        n = args.copy_calib_mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+
+if __name__ == "__main__":
+    main()

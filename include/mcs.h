@@ -123,7 +123,7 @@ typedef struct {
   double tol;               /* relative tolerance (preconditioned residual / error target) */
   double inner_tol;         /* precision 1: inner MINRES relative tolerance (1e-5) */
   int32_t max_outer;        /* precision 1: refinement step limit (10) */
-  int32_t coarse_max;       /* multigrid: coarsest level when free dofs <= coarse_max (1500) */
+  int32_t coarse_max;       /* multigrid: coarsest level when free dofs <= coarse_max (512) */
 } mcs_options;
 
 typedef struct {
@@ -200,6 +200,18 @@ int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count)
  * free facet ids (-1: Dirichlet facet), for tests.  Arrays sized n_free_facets
  * and n_elements*(dim+1). */
 int mcs_get_topology(const mcs_problem* pb, int32_t* colour_host, int32_t* elem_ff_host);
+
+/* Measurement hook for the dominant solve kernel.  While enabled, every launch
+ * of the coloured block Gauss-Seidel phase kernel (one colour of one sweep of
+ * A-hat^d_m, Corollary aux_pc_mult) is bracketed by HIP events on the
+ * problem's stream.  mcs_timer_read returns the accumulated kernel time, the
+ * number of launches and their algorithmic HBM bytes: per facet of the
+ * colour, the facet's rows of A^d_T of both neighbours (2 n_fb n_d words),
+ * D_F^{-1} (n_fb^2), the right-hand side and the updated block (3 n_fb), the
+ * gathered neighbour vectors (2 n_d) and the index words.  Enabling resets the
+ * counters.  [sync on read] */
+int mcs_timer_enable(mcs_problem* pb, int enable);
+int mcs_timer_read(mcs_problem* pb, double* total_ms, int64_t* launches, double* bytes);
 
 void mcs_destroy(mcs_problem* pb);
 const char* mcs_status_string(int status);

@@ -72,7 +72,7 @@ def interp_1d(n):
 
 
 class P1Multigrid:
-    def __init__(self, Abar, lattice, d, coarse_max=1500):
+    def __init__(self, Abar, lattice, d, coarse_max=512):
         """Abar over free lattice vertices (interior), dof = d*free_vertex + c."""
         self.d = d
         self.levels = []
@@ -229,7 +229,7 @@ def assemble_p1(gs):
 # ---------------------------------------------------------------------------
 
 class Preconditioner:
-    def __init__(self, gs, lattice, smoothing_steps=2, coarse_max=1500):
+    def __init__(self, gs, lattice, smoothing_steps=2, coarse_max=512):
         self.gs = gs
         topo = gs.topo
         d = gs.d

@@ -67,11 +67,11 @@ template <typename R>
 OpPtrs<R> op_ptrs(mcs_problem* pb);
 template <>
 OpPtrs<double> op_ptrs<double>(mcs_problem* pb) {
-  return {pb->p.Ad, pb->p.H, pb->p.Ht, pb->p.Aoo, pb->p.Aooinv, pb->p.Dinv, pb->p.EF};
+  return {pb->p.Ad, pb->p.H, pb->p.Ht, pb->p.Aoo, pb->p.Aooinv, pb->p.Dinv, pb->p.EF, pb->p.W};
 }
 template <>
 OpPtrs<float> op_ptrs<float>(mcs_problem* pb) {
-  return {pb->p.Ad32, pb->p.H32, pb->p.Ht32, pb->p.Aoo32, pb->p.Aooinv32, pb->p.Dinv32, pb->p.EF32};
+  return {pb->p.Ad32, pb->p.H32, pb->p.Ht32, pb->p.Aoo32, pb->p.Aooinv32, pb->p.Dinv32, pb->p.EF32, pb->p.W32};
 }
 
 template <typename R>
@@ -97,6 +97,16 @@ std::vector<MGLevelDev> mg_levels(mcs_problem* pb) {
     out.push_back(L);
   }
   return out;
+}
+
+// Accumulates the elapsed time of recorded (start, stop) event pairs; the
+// caller has synchronised the stream.
+void timer_flush(mcs_problem* pb) {
+  for (size_t i = 0; i < pb->tpending; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pb->tev[2 * i], pb->tev[2 * i + 1]) == hipSuccess) pb->t_ms += ms;
+  }
+  pb->tpending = 0;
 }
 
 template <typename R>
@@ -139,11 +149,31 @@ struct Ctx {
     launch_mg_point<R>(st, d, L[l], 2);
   }
 
-  void sweeps(R* x, const R* s, bool forward) {
+  // `smoothing_steps` block Gauss-Seidel sweeps on A^d (colours ascending or
+  // descending); y holds the element products A^d_T x_T and is kept current.
+  void sweeps(R* x, const R* s, R* y, bool forward) {
+    const Sizes& z = pb->sz;
+    const double per_facet = double(2 * z.nfb * z.nd + z.nfb * z.nfb + 4 * z.nd + 5 * z.nfb) * sizeof(R) +
+                             double(6) * 4.0;
     for (int it = 0; it < pb->opt.smoothing_steps; ++it)
       for (int cc = 0; cc < pb->ncol; ++cc) {
         int c = forward ? cc : pb->ncol - 1 - cc;
-        launch_smooth_phase<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s);
+        if (pb->timer_on) {
+          size_t k = 2 * pb->tpending;
+          while (pb->tev.size() < k + 2) {
+            hipEvent_t e;
+            hipEventCreate(&e);
+            pb->tev.push_back(e);
+          }
+          hipEventRecord(pb->tev[k], st);
+          launch_smooth_phase<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y);
+          hipEventRecord(pb->tev[k + 1], st);
+          pb->tpending++;
+          pb->t_launches++;
+          pb->t_bytes += per_facet * (pb->colour_off[c + 1] - pb->colour_off[c]);
+        } else {
+          launch_smooth_phase<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y);
+        }
       }
   }
 
@@ -154,15 +184,18 @@ struct Ctx {
     launch_ed<R>(st, P, O, pb->p.facet_vfree, pb->p.free_to_lat, (const R*)L[0].x, z, add, 0);
   }
 
-  // x = A-hat^d_m^{-1} s (facet parts; x fully overwritten)
+  // x = A-hat^d_m^{-1} s (facet parts; x fully overwritten):
+  //   forward sweeps from x = 0; r = s - A^d x (from the maintained products);
+  //   x += E^d C^{-1} E^d^T r (products updated through W_T); backward sweeps.
   void ad_mult_inv(const R* s, R* x) {
     R* tmp = v(PTMP);
     launch_fill<R>(st, n, R(0), x);
-    sweeps(x, s, true);
-    launch_elem_apply<R>(st, P, O, x, x, escr, 1 | 8);
+    launch_fill<R>(st, pb->ne * pb->sz.nd, R(0), escr);
+    sweeps(x, s, escr, true);
     launch_facet_sum<R>(st, P, escr, s, R(-1), tmp);
     aux(tmp, x, 1);
-    sweeps(x, s, false);
+    launch_ycorr<R>(st, P, O.W, pb->p.elem_verts, pb->p.vfree_of_lat, (const R*)L[0].x, escr);
+    sweeps(x, s, escr, false);
   }
 
   // y = A-hat_ext^{-1} r (velocity parts; pressure part of y set to 0)
@@ -192,12 +225,15 @@ struct Ctx {
     launch_dot<R>(st, n, a, b, pb->p.red, pb->p.scal);
     hipMemcpyAsync(host, pb->p.scal, sizeof(double), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
+    timer_flush(pb);
     return *host;
   }
 
   // Preconditioned MINRES from x = 0 for K x = b.  Returns status.
-  int minres(const R* b, R* x, double tol, int maxit, double stop_beta1, int* its, double* rel, double* beta1_out,
-             double* host) {
+  // Stops when ||r||_{K-hat^{-1}} <= max(tol * beta1, abs_stop); returns
+  // immediately (0 iterations) when beta1 <= stop_beta1.
+  int minres(const R* b, R* x, double tol, int maxit, double stop_beta1, double abs_stop, int* its, double* rel,
+             double* beta1_out, double* host) {
     R *r1 = v(VR1), *r2 = v(VR2), *y = v(VY), *vv = v(VV), *w1 = v(VW1), *w2 = v(VW2), *kv = v(VKV);
     launch_fill<R>(st, n, R(0), x);
     launch_fill<R>(st, n, R(0), r1);
@@ -243,7 +279,7 @@ struct Ctx {
       std::swap(w1, w2);
       *its = it;
       *rel = phibar / beta1;
-      if (phibar <= tol * beta1) return MCS_OK;
+      if (phibar <= std::max(tol * beta1, abs_stop)) return MCS_OK;
     }
     return MCS_ERR_NOT_CONVERGED;
   }
@@ -408,6 +444,8 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   p.EF = ws_ptr<double>(pb, "EF");
   p.Dinv32 = ws_ptr<float>(pb, "Dinv32");
   p.EF32 = ws_ptr<float>(pb, "EF32");
+  p.W = ws_ptr<double>(pb, "W");
+  p.W32 = ws_ptr<float>(pb, "W32");
   p.Cinv = ws_ptr<double>(pb, "Cinv");
   p.cmap = ws_ptr<int32_t>(pb, "cmap");
   p.cscratch = ws_ptr<double>(pb, "cscratch");
@@ -529,6 +567,7 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   F.EF32 = p.EF32;
   F.status = status;
   if (pb->nff > 0) launch_facet_setup(st, F);
+  launch_wsetup(st, F, p.elem_ff, pb->ne, p.W, p.W32);
 
   // P1 multigrid hierarchy
   const int d = pb->d, stn = d == 3 ? 27 : 9;
@@ -644,7 +683,8 @@ int precond_op(mcs_problem* pb, int op, const void* rv, void* zv) {
     case MCS_PC_SMOOTH_FWD:
     case MCS_PC_SMOOTH_BWD:
       launch_fill<R>(c.st, c.n, R(0), z);
-      c.sweeps(z, r, op == MCS_PC_SMOOTH_FWD);
+      launch_fill<R>(c.st, pb->ne * pb->sz.nd, R(0), c.escr);
+      c.sweeps(z, r, c.escr, op == MCS_PC_SMOOTH_FWD);
       break;
     case MCS_PC_AUX:
       launch_fill<R>(c.st, c.n, R(0), z);
@@ -748,7 +788,7 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
   if (pb->opt.precision == 0) {
     int its = 0;
     double rel = 0, b1 = 0;
-    rc = c64.minres(b, x, pb->opt.tol, pb->opt.max_it, -1.0, &its, &rel, &b1, host);
+    rc = c64.minres(b, x, pb->opt.tol, pb->opt.max_it, -1.0, -1.0, &its, &rel, &b1, host);
     inf.iterations = its;
     inf.outer_steps = 1;
     inf.rel_precond_residual = rel;
@@ -775,8 +815,11 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
       launch_scale_convert<double, float>(st, n, 1.0 / rn, r64, r32, 0);
       int its = 0;
       double irel = 0, b1 = 0;
+      // skip when the outer residual is already small enough; otherwise reduce
+      // by inner_tol, or only as far as the outer target needs (with margin 4)
       double stop = (beta0 > 0) ? pb->opt.tol * beta0 / rn : -1.0;
-      int irc = c32.minres(r32, d32, pb->opt.inner_tol, pb->opt.max_it, stop, &its, &irel, &b1, host);
+      double abs_stop = (beta0 > 0) ? 0.25 * pb->opt.tol * beta0 / rn : -1.0;
+      int irc = c32.minres(r32, d32, pb->opt.inner_tol, pb->opt.max_it, stop, abs_stop, &its, &irel, &b1, host);
       if (beta0 < 0) beta0 = b1 * rn;
       rel = b1 * rn / beta0;
       total += its;
@@ -868,6 +911,29 @@ int mcs_get_topology(const mcs_problem* pb, int32_t* colour_host, int32_t* elem_
   }
   if (colour_host) std::copy(pb->h_colour.begin(), pb->h_colour.end(), colour_host);
   if (elem_ff_host) std::copy(pb->h_elem_ff.begin(), pb->h_elem_ff.end(), elem_ff_host);
+  return MCS_OK;
+}
+
+int mcs_timer_enable(mcs_problem* pb, int enable) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(pb->stream));
+  timer_flush(pb);
+  pb->timer_on = enable != 0;
+  pb->t_ms = 0.0;
+  pb->t_bytes = 0.0;
+  pb->t_launches = 0;
+  return MCS_OK;
+}
+
+int mcs_timer_read(mcs_problem* pb, double* total_ms, int64_t* launches, double* bytes) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(pb->stream));
+  timer_flush(pb);
+  if (total_ms) *total_ms = pb->t_ms;
+  if (launches) *launches = pb->t_launches;
+  if (bytes) *bytes = pb->t_bytes;
   return MCS_OK;
 }
 

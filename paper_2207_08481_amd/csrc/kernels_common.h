@@ -81,7 +81,7 @@ struct SolveParams {
 
 template <typename R>
 struct OpPtrs {
-  const R *Ad, *H, *Ht, *Aoo, *Aooinv, *Dinv, *EF;
+  const R *Ad, *H, *Ht, *Aoo, *Aooinv, *Dinv, *EF, *W;
 };
 
 struct MGLevelDev {

@@ -899,4 +899,34 @@ void launch_pressure_mean(hipStream_t st, const SolveParams& P, const double* pm
   hipLaunchKernelGGL(k_pmean_sub, dim3(sgrid(P.ne * P.s.np)), dim3(256), 0, st, P, pconst, (const double*)red, x);
 }
 
+// W_T = A^d_T E_T: the element's A^d times its rows of the embedding E^d
+// (facet blocks E_F placed at the element's local vertices).  Layout
+// W[e][m][t], m = local vertex * d + component, t = row of A^d_T.
+__global__ void __launch_bounds__(256) k_wsetup(FacetSetupParams P, const int32_t* __restrict__ elem_ff, int64_t ne,
+                                                double* __restrict__ W, float* __restrict__ W32) {
+  const Sizes s = P.s;
+  const int d = s.d, nv = d + 1, nvd = nv * d, nd = s.nd, nfb = s.nfb, dd = d * d;
+  for (int64_t e = blockIdx.x; e < ne; e += gridDim.x) {
+    for (int idx = threadIdx.x; idx < nd * nvd; idx += blockDim.x) {
+      const int m = idx / nd, t = idx % nd;
+      const int vl = m / d, c = m % d;
+      const double* Arow = P.Ad + ((size_t)e * nd + t) * nd;
+      double acc = 0.0;
+      for (int f = 0; f < nv; ++f) {
+        const int g = elem_ff[e * nv + f];
+        if (g < 0 || vl == f) continue;
+        const int v = vl < f ? vl : vl - 1;
+        const double* E = P.EF + (size_t)g * nfb * dd + v * d + c;
+        for (int q = 0; q < nfb; ++q) acc += Arow[f * nfb + q] * E[(size_t)q * dd];
+      }
+      W[((size_t)e * nvd + m) * nd + t] = acc;
+      W32[((size_t)e * nvd + m) * nd + t] = (float)acc;
+    }
+  }
+}
+
+void launch_wsetup(hipStream_t st, const FacetSetupParams& P, const int32_t* elem_ff, int64_t ne, double* W, float* W32) {
+  hipLaunchKernelGGL(k_wsetup, dim3((int)std::min<int64_t>(ne, 1 << 20)), dim3(256), 0, st, P, elem_ff, ne, W, W32);
+}
+
 }  // namespace mcs

@@ -179,56 +179,91 @@ __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, co
   }
 }
 
-// One colour phase of block Gauss-Seidel on A^d:
-//   x_F += D_F^{-1} (s_F - sum_{T ni F} (A^d_T x_T)_F)  for all facets F of the colour.
 template <typename R>
-__global__ void __launch_bounds__(256) k_smooth_phase(SolveParams P, OpPtrs<R> O, int32_t c0, int32_t c1,
-                                                      R* __restrict__ x, const R* __restrict__ srhs) {
-  const Sizes s = P.s;
-  const int nd = s.nd, nfb = s.nfb, nv = s.d + 1;
-  __shared__ R xs[2][MAXND];
-  __shared__ R red[256];
-  __shared__ R rr[MAXNFB];
+__device__ inline R wave_sum(R v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One colour phase of block Gauss-Seidel on A^d with maintained element
+// products y_T = A^d_T x_T (race free: facets of one colour share no element):
+//   r_F = s_F - y_T1[F] - y_T2[F];  delta = D_F^{-1} r_F;  x_F += delta;
+//   y_Ti += A^d_Ti[:, F] delta   (columns of F = rows of F, A^d symmetric).
+// Threads [0, n_d) own the rows of the first neighbour, [n_d, 2 n_d) those of
+// the second; each thread loads its n_fb matrix entries before the short
+// dependent chain (residual -> D_F^{-1} -> update) starts.
+template <typename R, int NFB>
+__global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, int32_t c0, int32_t c1,
+                                                  R* __restrict__ x, const R* __restrict__ srhs, R* __restrict__ y) {
+  const int nd = P.s.nd;
+  __shared__ R rr[NFB];
+  __shared__ R dl[NFB];
+  __shared__ R dsh[NFB * NFB];
   const int tid = threadIdx.x;
-  const int parts = 128 / nfb;   // >= 2 for nfb <= 64
+  const int side = tid >= nd ? 1 : 0;
+  const int t = tid - side * nd;
+  const bool is_row = tid < 2 * nd;
   for (int64_t ci = c0 + blockIdx.x; ci < c1; ci += gridDim.x) {
     const int64_t g = P.colour_facets[ci];
-    for (int side = 0; side < 2; ++side) {
-      int64_t e = P.facet_el[2 * g + side];
-      for (int t = tid; t < nd; t += blockDim.x) {
-        int f = t / nfb, q = t % nfb;
-        int gg = P.elem_ff[e * nv + f];
-        xs[side][t] = gg >= 0 ? x[P.off_f + (int64_t)gg * nfb + q] : R(0);
-      }
+    int64_t e = 0;
+    R a[NFB];
+    R yv = R(0);
+    if (is_row) {
+      e = P.facet_el[2 * g + side];
+      const int sl = P.facet_slot[2 * g + side];
+      const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
+#pragma unroll
+      for (int q = 0; q < NFB; ++q) a[q] = Ab[(size_t)q * nd];
+      yv = y[e * nd + t];
     }
-    __syncthreads();
     {
-      int side = tid >> 7, loc = tid & 127;
-      int q = loc % nfb, part = loc / nfb;
-      R acc = 0;
-      if (part < parts) {
-        int64_t e = P.facet_el[2 * g + side];
-        int sl = P.facet_slot[2 * g + side];
-        const R* Ad = O.Ad + (size_t)e * nd * nd + sl * nfb + q;
-        for (int j = part; j < nd; j += parts) acc += Ad[(size_t)j * nd] * xs[side][j];
-      }
-      red[tid] = acc;
+      const R* Di = O.Dinv + (size_t)g * NFB * NFB;
+      for (int i = tid; i < NFB * NFB; i += blockDim.x) dsh[i] = Di[i];
+    }
+    if (tid < NFB) {
+      const int64_t e1 = P.facet_el[2 * g], e2 = P.facet_el[2 * g + 1];
+      const int s1 = P.facet_slot[2 * g], s2 = P.facet_slot[2 * g + 1];
+      rr[tid] = srhs[P.off_f + g * NFB + tid] - y[e1 * nd + s1 * NFB + tid] - y[e2 * nd + s2 * NFB + tid];
     }
     __syncthreads();
-    if (tid < nfb) {
-      R acc = srhs[P.off_f + g * nfb + tid];
-      for (int side = 0; side < 2; ++side)
-        for (int part = 0; part < parts; ++part) acc -= red[side * 128 + part * nfb + tid];
-      rr[tid] = acc;
+    if (tid < NFB) {
+      R acc = R(0);
+#pragma unroll
+      for (int j = 0; j < NFB; ++j) acc += dsh[j * NFB + tid] * rr[j];
+      dl[tid] = acc;
+      x[P.off_f + g * NFB + tid] += acc;
     }
     __syncthreads();
-    if (tid < nfb) {
-      const R* Di = O.Dinv + (size_t)g * nfb * nfb;
-      R acc = 0;
-      for (int j = 0; j < nfb; ++j) acc += Di[(size_t)j * nfb + tid] * rr[j];
-      x[P.off_f + g * nfb + tid] += acc;
+    if (is_row) {
+#pragma unroll
+      for (int q = 0; q < NFB; ++q) yv += a[q] * dl[q];
+      y[e * nd + t] = yv;
     }
     __syncthreads();
+  }
+}
+
+// y_T += W_T c_T with W_T = A^d_T E_T (E_T: the element's rows of E^d) and
+// c_T the P1 coarse correction at the element's vertices (lattice vector; the
+// Dirichlet vertices carry no value and are skipped, their lattice entries are
+// never written): keeps y_T = A^d_T x_T after x += E^d c.
+template <typename R>
+__global__ void k_elem_ycorr(SolveParams P, const R* __restrict__ W, const int32_t* __restrict__ elem_verts,
+                             const int32_t* __restrict__ vfree_of_lat, const R* __restrict__ x0, R* __restrict__ y) {
+  const int d = P.s.d, nv = d + 1, nvd = nv * d, nd = P.s.nd;
+  const int64_t n = P.ne * nd;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = idx / nd;
+    const int t = (int)(idx % nd);
+    const R* We = W + (size_t)e * nvd * nd + t;
+    R acc = R(0);
+    for (int vl = 0; vl < nv; ++vl) {
+      const int64_t v = elem_verts[e * nv + vl];
+      if (vfree_of_lat[v] < 0) continue;
+      for (int c = 0; c < d; ++c) acc += We[(size_t)(vl * d + c) * nd] * x0[v * d + c];
+    }
+    y[idx] += acc;
   }
 }
 
@@ -414,42 +449,53 @@ __global__ void k_mg_prolong(int d, MGLevelDev F, MGLevelDev C) {
   }
 }
 
-// Coarsest level: x = C^{-1} b over the free dofs (FP64 accumulation).
+// Coarsest level: x = C^{-1} b over the free dofs (FP64 accumulation), one
+// wave per row of the (symmetric) inverse.
 template <typename R>
 __global__ void k_mg_coarse(int64_t nc, const double* __restrict__ Cinv, const int32_t* __restrict__ cmap, MGLevelDev L) {
   const R* b = (const R*)L.b;
   R* x = (R*)L.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nc; i += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wpb = blockDim.x >> 6;
+  for (int64_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < nc; i += (int64_t)gridDim.x * wpb) {
     double acc = 0.0;
-    for (int64_t j = 0; j < nc; ++j) acc += Cinv[j * nc + i] * (double)b[cmap[j]];
-    x[cmap[i]] = (R)acc;
+    for (int64_t j = lane; j < nc; j += 64) acc += Cinv[i * nc + j] * (double)b[cmap[j]];
+    acc = wave_sum(acc);
+    if (lane == 0) x[cmap[i]] = (R)acc;
   }
 }
 
 // ------------------------------------------------------------ pressure parts
 // y_p = M_p^{-1} (r_p - B a) with M_p^{-1} = (nu_T/|det J|) Mp^-1_ref.
+// B a is computed by all threads (one velocity row each) and reduced in LDS.
 template <typename R>
 __global__ void __launch_bounds__(256) k_elem_press(SolveParams P, const R* __restrict__ a, const R* __restrict__ r,
                                                     R* __restrict__ y, int with_B) {
   const Sizes s = P.s;
-  const int nb = s.nb, nd = s.nd, np = s.np;
-  __shared__ R ad[MAXND], ao[MAXNB];
+  const int nb = s.nb, nd = s.nd, np = s.np, nv = s.d + 1;
+  __shared__ double part[4][MAXNP];
   __shared__ double bp[MAXNP];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     const double det = P.detJ[e];
-    if (with_B) {
-      gather_elem_d(P, a, e, ad);
-      if (tid < nb) ao[tid] = a[e * nb + tid];
-    }
-    __syncthreads();
-    if (tid < np) {
-      double acc = (double)r[P.off_p + e * np + tid];
+    // each wave owns a set of pressure rows; lanes run over velocity rows
+    for (int q = wave; q < np; q += 4) {
+      double acc = 0.0;
       if (with_B) {
-        for (int i = 0; i < nb; ++i) acc -= Bentry(P, det, tid, i) * (double)ao[i];
-        for (int t = 0; t < nd; ++t) acc -= Bentry(P, det, tid, nb + t) * (double)ad[t];
+        for (int row = lane; row < nb + nd; row += 64) {
+          double av;
+          if (row < nb) av = (double)a[e * nb + row];
+          else {
+            int t = row - nb, f = t / s.nfb, qq = t % s.nfb;
+            if (qq >= s.nF) continue;
+            int gg = P.elem_ff[e * nv + f];
+            av = gg >= 0 ? (double)a[P.off_f + (int64_t)gg * s.nfb + qq] : 0.0;
+          }
+          acc += Bentry(P, det, q, row) * av;
+        }
+        acc = wave_sum(acc);
       }
-      bp[tid] = acc;
+      if (lane == 0) bp[q] = (double)r[P.off_p + e * np + q] - acc;
     }
     __syncthreads();
     if (tid < np) {
@@ -570,9 +616,27 @@ void launch_ext_post(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, c
 }
 template <typename R>
 void launch_smooth_phase(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
-                         const R* s) {
+                         const R* s, R* y) {
   if (c1 <= c0) return;
-  hipLaunchKernelGGL(k_smooth_phase<R>, dim3((int)std::min<int64_t>(c1 - c0, 1 << 20)), dim3(256), 0, st, P, O, c0, c1, x, s);
+  const int threads = (int)std::min<int64_t>(512, ((2 * P.s.nd + 63) / 64) * 64);
+  dim3 grid((int)std::min<int64_t>(c1 - c0, 1 << 20)), block(threads);
+  switch (P.s.nfb) {
+    case 5: hipLaunchKernelGGL((k_smooth_y<R, 5>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
+    case 7: hipLaunchKernelGGL((k_smooth_y<R, 7>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
+    case 9: hipLaunchKernelGGL((k_smooth_y<R, 9>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
+    case 11: hipLaunchKernelGGL((k_smooth_y<R, 11>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
+    case 12: hipLaunchKernelGGL((k_smooth_y<R, 12>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
+    case 22: hipLaunchKernelGGL((k_smooth_y<R, 22>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
+    case 35: hipLaunchKernelGGL((k_smooth_y<R, 35>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
+    case 51: hipLaunchKernelGGL((k_smooth_y<R, 51>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
+    default: break;
+  }
+}
+template <typename R>
+void launch_ycorr(hipStream_t st, const SolveParams& P, const R* W, const int32_t* elem_verts,
+                  const int32_t* vfree_of_lat, const R* x0, R* y) {
+  hipLaunchKernelGGL(k_elem_ycorr<R>, dim3(grid_for(P.ne * P.s.nd)), dim3(256), 0, st, P, W, elem_verts, vfree_of_lat,
+                     x0, y);
 }
 template <typename R>
 void launch_edt(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* fscr, int64_t nfv,
@@ -601,7 +665,7 @@ void launch_mg_prolong(hipStream_t st, int d, const MGLevelDev& F, const MGLevel
 }
 template <typename R>
 void launch_mg_coarse(hipStream_t st, int64_t nc, const double* Cinv, const int32_t* cmap, const MGLevelDev& L) {
-  hipLaunchKernelGGL(k_mg_coarse<R>, dim3(grid_for(nc, 64)), dim3(64), 0, st, nc, Cinv, cmap, L);
+  hipLaunchKernelGGL(k_mg_coarse<R>, dim3(grid_for(nc, 4)), dim3(256), 0, st, nc, Cinv, cmap, L);
 }
 template <typename R>
 void launch_elem_press(hipStream_t st, const SolveParams& P, const R* a, const R* r, R* y, int with_B) {
@@ -650,7 +714,9 @@ void launch_scale_convert(hipStream_t st, int64_t n, double a, const A* x, B* y,
   template void launch_ext_pre<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, R*, R*);        \
   template void launch_ext_post<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, const R*, R*); \
   template void launch_smooth_phase<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, int32_t, int32_t, R*, \
-                                       const R*);                                                              \
+                                       const R*, R*);                                                          \
+  template void launch_ycorr<R>(hipStream_t, const SolveParams&, const R*, const int32_t*, const int32_t*,       \
+                                const R*, R*);                                                                  \
   template void launch_edt<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, R*, int64_t,         \
                               const int32_t*, const int32_t*, const int32_t*, R*, int);                        \
   template void launch_ed<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const int32_t*, const int32_t*, \

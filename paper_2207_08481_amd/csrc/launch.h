@@ -14,7 +14,10 @@ template <typename R>
 void launch_ext_post(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* t, const R* to, R* y);
 template <typename R>
 void launch_smooth_phase(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
-                         const R* s);
+                         const R* s, R* y);
+template <typename R>
+void launch_ycorr(hipStream_t st, const SolveParams& P, const R* W, const int32_t* elem_verts,
+                  const int32_t* vfree_of_lat, const R* x0, R* y);
 template <typename R>
 void launch_edt(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* fscr, int64_t nfv,
                 const int32_t* vinc_off, const int32_t* vinc, const int32_t* free_to_lat, R* b, int compact);
@@ -54,6 +57,7 @@ void launch_gather_compact(hipStream_t st, int64_t nfv, int d, const int32_t* f2
 // setup (kernels_setup.hip)
 void launch_condense(hipStream_t st, const CondParams& P, int nslots);
 void launch_facet_setup(hipStream_t st, const FacetSetupParams& P);
+void launch_wsetup(hipStream_t st, const FacetSetupParams& P, const int32_t* elem_ff, int64_t ne, double* W, float* W32);
 void launch_p1_assemble(hipStream_t st, const P1Params& P);
 void launch_mg_l1(hipStream_t st, const MGSetupParams& P);
 void launch_mg_rap(hipStream_t st, const MGSetupParams& P);

@@ -94,8 +94,8 @@ struct DevPtrs {
   double *nu, *detJ;
   double *Ad, *H, *Ht, *Aoo, *Aooinv;
   float *Ad32, *H32, *Ht32, *Aoo32, *Aooinv32;
-  double *Dinv, *EF;
-  float *Dinv32, *EF32;
+  double *Dinv, *EF, *W;
+  float *Dinv32, *EF32, *W32;
   // multigrid coarsest
   double* Cinv;           // [nc][nc]
   int32_t* cmap;          // [nc] coarsest free dof -> lattice dof index
@@ -143,5 +143,14 @@ struct mcs_problem {
   int device = -1;
   bool condensed = false;
   mcs::DevPtrs p;
+  // kernel timer (smoother phase launches)
+  bool timer_on = false;
+  std::vector<hipEvent_t> tev;        // pairs (start, stop)
+  size_t tpending = 0;
+  double t_ms = 0.0, t_bytes = 0.0;
+  int64_t t_launches = 0;
+  ~mcs_problem() {
+    for (auto e : tev) hipEventDestroy(e);
+  }
   std::vector<std::pair<std::string, int64_t>> offsets;  // name -> byte offset
 };

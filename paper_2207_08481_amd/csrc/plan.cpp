@@ -69,7 +69,7 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
   if (!(pb->opt.tol > 0)) pb->opt.tol = 1e-10;
   if (!(pb->opt.inner_tol > 0)) pb->opt.inner_tol = 1e-5;
   if (pb->opt.max_outer <= 0) pb->opt.max_outer = 10;
-  if (pb->opt.coarse_max <= 0) pb->opt.coarse_max = 1500;
+  if (pb->opt.coarse_max <= 0) pb->opt.coarse_max = 512;
   if (pb->opt.precision != 0 && pb->opt.precision != 1) {
     set_error("precision must be 0 or 1");
     return MCS_ERR_ARG;
@@ -369,6 +369,8 @@ int layout_workspace(mcs_problem* pb) {
   L.add("EF", Dd(nff * s.nfb * d * d));
   L.add("Dinv32", Ff(nff * s.nfb * s.nfb));
   L.add("EF32", Ff(nff * s.nfb * d * d));
+  L.add("W", Dd(ne * (d + 1) * d * s.nd));
+  L.add("W32", Ff(ne * (d + 1) * d * s.nd));
   const int st = d == 3 ? 27 : 9;
   for (size_t l = 0; l < pb->mg.size(); ++l) {
     MGLevel& M = pb->mg[l];

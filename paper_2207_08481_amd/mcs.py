@@ -28,7 +28,8 @@ PC = {"KHAT": 0, "AEXT": 1, "ADELTA_MULT": 2, "SMOOTH_FWD": 3, "SMOOTH_BWD": 4, 
 # exported symbols of include/mcs.h
 SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
            "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
-           "mcs_get_topology", "mcs_destroy", "mcs_status_string", "mcs_last_error"]
+           "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_destroy",
+           "mcs_status_string", "mcs_last_error"]
 
 
 class MCSError(RuntimeError):
@@ -89,6 +90,8 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_normalize_pressure.argtypes = [vp, vp]
     lib.mcs_get_array.argtypes = [vp, C.c_char_p, C.POINTER(vp), C.POINTER(i64)]
     lib.mcs_get_topology.argtypes = [vp, vp, vp]
+    lib.mcs_timer_enable.argtypes = [vp, i32]
+    lib.mcs_timer_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_destroy.argtypes = [vp]
     lib.mcs_destroy.restype = None
     lib.mcs_status_string.argtypes = [i32]
@@ -97,7 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_last_error.restype = C.c_char_p
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
                  "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
-                 "mcs_get_topology"):
+                 "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -129,7 +132,7 @@ class Problem:
     solve.  Names follow the C ABI."""
 
     def __init__(self, vertices, elements, lattice, order, precision=0, smoothing_steps=2,
-                 tol=1e-10, max_it=2000, inner_tol=1e-5, max_outer=10, coarse_max=1500):
+                 tol=1e-10, max_it=2000, inner_tol=1e-5, max_outer=10, coarse_max=512):
         lib = load_library()
         self._lib = lib
         v = np.ascontiguousarray(vertices, dtype=np.float64)
@@ -242,6 +245,17 @@ class Problem:
         else:
             typestr = "<f8"
         return torch.as_tensor(_CudaArray(p.value, n.value, typestr), device=self.device)
+
+    def timer_enable(self, on=True):
+        _check(self._lib.mcs_timer_enable(self._h, 1 if on else 0))
+
+    def timer_read(self):
+        """(total kernel ms, launches, algorithmic bytes) of the timed smoother launches."""
+        ms = C.c_double()
+        n = C.c_int64()
+        b = C.c_double()
+        _check(self._lib.mcs_timer_read(self._h, C.byref(ms), C.byref(n), C.byref(b)))
+        return ms.value, n.value, b.value
 
     def close(self):
         if getattr(self, "_h", None):

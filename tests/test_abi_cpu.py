@@ -71,7 +71,7 @@ def test_paper_scale_dof_count():
     pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 4)
     assert pb.info.n_dof == 26327040
     assert pb.info.n_colours == 4
-    assert pb.info.n_mg_levels == 3
+    assert pb.info.n_mg_levels == 4
 
 
 @needs_lib
@@ -79,9 +79,9 @@ def test_multigrid_levels_rule():
     from paper_2207_08481_amd import Problem
     mesh = W.unit_cube_mesh(16)
     pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 2)
-    assert pb.info.n_mg_levels == 2        # 15^3*3 = 10125 > 1500 -> 7^3*3 = 1029
-    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, coarse_max=100)
-    assert pb.info.n_mg_levels == 3
+    assert pb.info.n_mg_levels == 3        # 15^3*3 = 10125 -> 7^3*3 = 1029 > 512 -> 3^3*3 = 81
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, coarse_max=2000)
+    assert pb.info.n_mg_levels == 2
 
 
 @needs_lib

@@ -25,7 +25,7 @@ def _need_gpu():
 _cache = {}
 
 
-def setup_case(d, n, k, nu_kind="one", coarse_max=1500, smoothing_steps=2):
+def setup_case(d, n, k, nu_kind="one", coarse_max=512, smoothing_steps=2):
     key = (d, n, k, nu_kind, coarse_max, smoothing_steps)
     if key in _cache:
         return _cache[key]
@@ -128,7 +128,7 @@ def test_apply_operators(d, n, k):
     assert _rel(y32, K @ x) < 1e-5
 
 
-@pytest.mark.parametrize("d,n,k,cm", [(2, 2, 2, 1500), (2, 4, 2, 20), (3, 2, 2, 1500), (3, 1, 3, 1500)])
+@pytest.mark.parametrize("d,n,k,cm", [(2, 2, 2, 512), (2, 4, 2, 20), (3, 2, 2, 512), (3, 1, 3, 512)])
 def test_preconditioner_pieces(d, n, k, cm):
     c = setup_case(d, n, k, coarse_max=cm)
     pb, gs, pc = c["pb"], c["gs"], c["pc"]

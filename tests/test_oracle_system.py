@@ -20,7 +20,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 _cache = {}
 
 
-def problem(d, n, k, nu=1.0, force=None, coarse_max=1500):
+def problem(d, n, k, nu=1.0, force=None, coarse_max=512):
     key = (d, n, k, nu, force, coarse_max)
     if key in _cache:
         return _cache[key]
@@ -269,7 +269,7 @@ def _dense_op(fun, n, idx):
     return M
 
 
-@pytest.mark.parametrize("d,n,k,cm", [(2, 4, 2, 20), (3, 2, 2, 1500)])
+@pytest.mark.parametrize("d,n,k,cm", [(2, 4, 2, 20), (3, 2, 2, 512)])
 def test_aux_space_preconditioner_bounds(d, n, k, cm):
     """Corollary aux_pc_mult: A^d <= A-hat^d_m, i.e. the eigenvalues of
     A-hat^d_m^{-1} A^d lie in (0, 1]; A-hat^d_m^{-1} is symmetric."""
