@@ -44,6 +44,21 @@ WORKLOADS = {
 }
 
 
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the smoother kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (calibrated against a plain copy), or None when
+    no record exists for this workload or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_smooth_y_{workload}_traffic.json")
+    if precision != 0 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return round(rec["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(seconds_hint=20.0):
     """Time the oracle (as it stands) on a bounded sample in a child process:
     the same cube recipe (k=3, nu=1, curl modes) on 3^3 x 6 tets, 40 MINRES
@@ -143,12 +158,13 @@ def main():
     kms, klaunch, kbytes = pb.timer_read()
     pb.timer_enable(False)
 
+    traffic = measured_traffic(args.workload, precision)
     value = ndof * its / (t_sol / 1e3)
     avg_launch_ms = kms / max(klaunch, 1)
     bytes_per_launch = kbytes / max(klaunch, 1)
     achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_smooth_phase (one colour of one block Gauss-Seidel sweep)",
                 "avg_launch_us": round(avg_launch_ms * 1e3, 2), "launches": klaunch,
                 "bytes_per_launch": int(bytes_per_launch)}
