@@ -26,87 +26,145 @@ __device__ inline void gather_elem_d(const SolveParams& P, const R* __restrict__
   }
 }
 
-// B_T[q][row] for a reordered local velocity row (bubble or facet normal dof);
-// returns 0 for tangential rows.  B = -(div phi, lambda^gamma), phi = s J phi^.
-__device__ inline double Bentry(const SolveParams& P, double det, int q, int row) {
-  const Sizes& s = P.s;
-  int iu;
-  double sc;
-  if (row < s.nb) {
-    iu = row;
-    sc = -fabs(det);
-  } else {
-    int r = row - s.nb, f = r / s.nfb, qq = r % s.nfb;
-    if (qq >= s.nF) return 0.0;
-    iu = s.nb + f * s.nF + qq;
-    sc = det > 0 ? -1.0 : 1.0;
-  }
-  return sc * P.rBp[(size_t)q * s.nu + iu];
+template <typename R>
+__device__ inline R wave_sum(R v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
-// flags: 1 = velocity block A (factorised), 2 = + B^T p, 4 = p <- B u, 8 = A^d only
+// sum over the 32 lanes of a half-wave group
+template <typename R>
+__device__ inline R group32_sum(R v) {
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 32);
+  return v;
+}
+
+// Per-workgroup table of the velocity rows of an element (reordered local
+// order): original BDM index (or -1 for tangential rows) and the kind of
+// scale in phi = s J phi^ (0: bubble, s = 1; 1: facet function, s = 1/det J).
+__device__ inline void build_rowmap(const Sizes& s, int* rmap) {
+  for (int row = threadIdx.x; row < s.nb + s.nd; row += blockDim.x) {
+    int iu = -1;
+    if (row < s.nb) iu = row;
+    else {
+      int r = row - s.nb, f = r / s.nfb, qq = r % s.nfb;
+      if (qq < s.nF) iu = s.nb + f * s.nF + qq;
+    }
+    rmap[row] = iu;
+  }
+}
+
+// flags: 1 = velocity block A (factorised), 2 = + B^T p, 4 = p <- B u, 8 = A^d only,
+// 16 = write zero pressure rows when B u is not requested.
+// Phase 1 runs A^d x_d (threads [0, n_d)) concurrently with the partial sums of
+// H x_d (the remaining threads); phase 2 finishes z_o = x_o + H x_d and
+// w_o = A_oo z_o; phase 3 adds H^T w_o and the pressure coupling.
+// B_T[q][row] = -s |det J| Bp^[q][iu(row)] (s = 1 bubble, 1/det J facet row).
 template <typename R>
 __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, OpPtrs<R> O, const R* __restrict__ x,
                                                     R* __restrict__ y, R* __restrict__ escr, int flags) {
   const Sizes s = P.s;
-  const int nb = s.nb, nd = s.nd, np = s.np;
+  const int nb = s.nb, nd = s.nd, np = s.np, nu = s.nu;
   __shared__ R xd[MAXND], xo[MAXNB], zo[MAXNB], wo[MAXNB];
   __shared__ R xp[MAXNP];
-  const int tid = threadIdx.x;
+  __shared__ R zpart[256];
+  __shared__ int rmap[MAXNB + MAXND];
+  __shared__ double us[MAXNB + MAXND];   // scaled velocity for B u, indexed by BDM index
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool doA = flags & 1, doBT = flags & 2, doBu = flags & 4, onlyAd = flags & 8;
+  const bool doH = doA && !onlyAd;
+  build_rowmap(s, rmap);
+  const int nhelp = 256 - nd;                    // threads not owning an A^d row
+  const int parts = nhelp >= nb ? nhelp / nb : 1;
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     const double det = P.detJ[e];
+    const double sb = -fabs(det), sf = det > 0 ? -1.0 : 1.0;
     gather_elem_d(P, x, e, xd);
     if (tid < nb) xo[tid] = x[e * nb + tid];
     if (tid < np) xp[tid] = x[P.off_p + e * np + tid];
     __syncthreads();
-    const bool doA = flags & 1, doBT = flags & 2, doBu = flags & 4, onlyAd = flags & 8;
-    if (doA && !onlyAd) {
+    R accA = R(0);
+    if (tid < nd) {
+      if (doA) {
+        const R* Ad = O.Ad + (size_t)e * nd * nd + tid;
+#pragma unroll 8
+        for (int j = 0; j < nd; ++j) accA += Ad[(size_t)j * nd] * xd[j];
+      }
+    } else if (doH) {
+      const int h = tid - nd;
       const R* Ht = O.Ht + (size_t)e * nb * nd;
+      if (nhelp >= nb) {
+        const int i = h % nb, part = h / nb;
+        R acc = R(0);
+        if (part < parts)
+          for (int j = part; j < nd; j += parts) acc += Ht[(size_t)j * nb + i] * xd[j];
+        zpart[h] = acc;
+      } else {
+        for (int i = h; i < nb; i += nhelp) {
+          R acc = R(0);
+          for (int j = 0; j < nd; ++j) acc += Ht[(size_t)j * nb + i] * xd[j];
+          zpart[i] = acc;   // parts == 1: slot i
+        }
+      }
+    }
+    if (doBu) {
+      for (int row = tid; row < nb + nd; row += blockDim.x) {
+        int iu = rmap[row];
+        if (iu >= 0) us[iu] = (row < nb ? sb * (double)xo[row] : sf * (double)xd[row - nb]);
+      }
+    }
+    __syncthreads();
+    if (doH) {
       if (tid < nb) {
         R acc = xo[tid];
-        for (int j = 0; j < nd; ++j) acc += Ht[(size_t)j * nb + tid] * xd[j];
+        for (int pp = 0; pp < parts; ++pp) acc += zpart[pp * nb + tid];
         zo[tid] = acc;
       }
       __syncthreads();
-      const R* Aoo = O.Aoo + (size_t)e * nb * nb;
       if (tid < nb) {
-        R acc = 0;
-        for (int j = 0; j < nb; ++j) acc += Aoo[(size_t)j * nb + tid] * zo[j];
+        const R* Aoo = O.Aoo + (size_t)e * nb * nb + tid;
+        R acc = R(0);
+#pragma unroll 4
+        for (int j = 0; j < nb; ++j) acc += Aoo[(size_t)j * nb] * zo[j];
         wo[tid] = acc;
       }
       __syncthreads();
     }
     if (tid < nd) {
-      R acc = 0;
-      if (doA) {
-        const R* Ad = O.Ad + (size_t)e * nd * nd;
-        for (int j = 0; j < nd; ++j) acc += Ad[(size_t)j * nd + tid] * xd[j];
-        if (!onlyAd) {
-          const R* H = O.H + (size_t)e * nb * nd;
-          for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd + tid] * wo[i];
-        }
+      R acc = accA;
+      if (doH) {
+        const R* H = O.H + (size_t)e * nb * nd + tid;
+#pragma unroll 4
+        for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd] * wo[i];
       }
       if (doBT) {
-        double b = 0.0;
-        for (int q = 0; q < np; ++q) b += Bentry(P, det, q, nb + tid) * (double)xp[q];
-        acc += (R)b;
+        const int iu = rmap[nb + tid];
+        if (iu >= 0) {
+          double b = 0.0;
+          for (int q = 0; q < np; ++q) b += P.rBp[(size_t)q * nu + iu] * (double)xp[q];
+          acc += (R)(sf * b);
+        }
       }
       escr[e * nd + tid] = acc;
     }
     if (!onlyAd && tid < nb) {
-      R acc = (doA) ? wo[tid] : R(0);
+      R acc = doH ? wo[tid] : R(0);
       if (doBT) {
         double b = 0.0;
-        for (int q = 0; q < np; ++q) b += Bentry(P, det, q, tid) * (double)xp[q];
-        acc += (R)b;
+        for (int q = 0; q < np; ++q) b += P.rBp[(size_t)q * nu + tid] * (double)xp[q];
+        acc += (R)(sb * b);
       }
       y[e * nb + tid] = acc;
     }
-    if (doBu && tid < np) {
-      double acc = 0.0;
-      for (int i = 0; i < nb; ++i) acc += Bentry(P, det, tid, i) * (double)xo[i];
-      for (int t = 0; t < nd; ++t) acc += Bentry(P, det, tid, nb + t) * (double)xd[t];
-      y[P.off_p + e * np + tid] = (R)acc;
+    if (doBu) {
+      for (int q = wave; q < np; q += 4) {
+        double acc = 0.0;
+        for (int iu = lane; iu < nu; iu += 64) acc += P.rBp[(size_t)q * nu + iu] * us[iu];
+        acc = wave_sum(acc);
+        if (lane == 0) y[P.off_p + e * np + q] = (R)acc;
+      }
     } else if (!onlyAd && tid < np && (flags & 16)) {
       y[P.off_p + e * np + tid] = R(0);
     }
@@ -131,7 +189,9 @@ __global__ void k_facet_sum(SolveParams P, const R* __restrict__ escr, const R* 
   }
 }
 
-// A-hat_ext^{-1}, first part: escr_T = H_T^T r_o,T;  t_o = Aoo^{-1} r_o.
+// A-hat_ext^{-1}, first part: escr_T = H_T^T r_o,T (threads [0, n_d));
+// t_o = Aoo^{-1} r_o (the following n_o threads, or the first ones when
+// n_d + n_o exceeds the block).
 template <typename R>
 __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, const R* __restrict__ r,
                                                  R* __restrict__ to, R* __restrict__ escr) {
@@ -139,51 +199,60 @@ __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, con
   const int nb = s.nb, nd = s.nd;
   __shared__ R ro[MAXNB];
   const int tid = threadIdx.x;
+  const int ob = (nd + nb <= 256) ? nd : 0;      // first thread of the A_oo^{-1} product
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     if (tid < nb) ro[tid] = r[e * nb + tid];
     __syncthreads();
     if (tid < nd) {
-      const R* H = O.H + (size_t)e * nb * nd;
-      R acc = 0;
-      for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd + tid] * ro[i];
+      const R* H = O.H + (size_t)e * nb * nd + tid;
+      R acc = R(0);
+#pragma unroll 4
+      for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd] * ro[i];
       escr[e * nd + tid] = acc;
     }
-    if (tid < nb) {
-      const R* Ai = O.Aooinv + (size_t)e * nb * nb;
-      R acc = 0;
-      for (int j = 0; j < nb; ++j) acc += Ai[(size_t)j * nb + tid] * ro[j];
-      to[e * nb + tid] = acc;
+    if (tid >= ob && tid < ob + nb) {
+      const int i = tid - ob;
+      const R* Ai = O.Aooinv + (size_t)e * nb * nb + i;
+      R acc = R(0);
+#pragma unroll 4
+      for (int j = 0; j < nb; ++j) acc += Ai[(size_t)j * nb] * ro[j];
+      to[e * nb + i] = acc;
     }
     __syncthreads();
   }
 }
 
-// A-hat_ext^{-1}, last part: y_o = t_o - H_T t_d,T.
+// A-hat_ext^{-1}, last part: y_o = t_o - H_T t_d,T; the n_d-long sums are split
+// over all threads and reduced in LDS.
 template <typename R>
 __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, const R* __restrict__ t,
                                                   const R* __restrict__ to, R* __restrict__ y) {
   const Sizes s = P.s;
   const int nb = s.nb, nd = s.nd;
   __shared__ R td[MAXND];
+  __shared__ R part[256];
   const int tid = threadIdx.x;
+  const int parts = 256 / nb;
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     gather_elem_d(P, t, e, td);
     __syncthreads();
+    {
+      const int i = tid % nb, pp = tid / nb;
+      R acc = R(0);
+      if (pp < parts) {
+        const R* Ht = O.Ht + (size_t)e * nb * nd + i;
+        for (int j = pp; j < nd; j += parts) acc += Ht[(size_t)j * nb] * td[j];
+      }
+      part[tid] = acc;
+    }
+    __syncthreads();
     if (tid < nb) {
-      const R* Ht = O.Ht + (size_t)e * nb * nd;
       R acc = to[e * nb + tid];
-      for (int j = 0; j < nd; ++j) acc -= Ht[(size_t)j * nb + tid] * td[j];
+      for (int pp = 0; pp < parts; ++pp) acc -= part[pp * nb + tid];
       y[e * nb + tid] = acc;
     }
     __syncthreads();
   }
-}
-
-template <typename R>
-__device__ inline R wave_sum(R v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
 }
 
 // One colour phase of block Gauss-Seidel on A^d with maintained element
@@ -341,45 +410,52 @@ __device__ inline bool mg_interior(const int c[3], const int* n, int d) {
   return true;
 }
 
-// mode 0: x = Dinv b;  mode 1: r = b - A x;  mode 2: x += Dinv (b - A x)
+// mode 0: x = Dinv b;  mode 1: r = b - A x;  mode 2: x += Dinv (b - A x).
+// One 32-lane group per vertex, one stencil tap per lane.
 template <typename R>
-__global__ void k_mg_point(int d, MGLevelDev L, int mode) {
+__global__ void __launch_bounds__(256) k_mg_point(int d, MGLevelDev L, int mode) {
   const int st = d == 3 ? 27 : 9, dd = d * d;
   const R* A = (const R*)L.A;
   const R* Di = (const R*)L.Dinv;
   R* x = (R*)L.x;
   const R* b = (const R*)L.b;
   R* r = (R*)L.r;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < L.nvert; v += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 31;
+  const int64_t gpb = blockDim.x >> 5;
+  for (int64_t v = blockIdx.x * gpb + (threadIdx.x >> 5); v < L.nvert; v += (int64_t)gridDim.x * gpb) {
     int c[3];
     mg_coords(v, L.n, c);
-    if (!mg_interior(c, L.n, d)) {
-      if (mode == 1)
-        for (int k = 0; k < d; ++k) r[v * d + k] = R(0);
-      continue;
-    }
-    R res[3];
-    for (int k = 0; k < d; ++k) res[k] = b[v * d + k];
-    if (mode != 0) {
-      const R* Av = A + (size_t)v * st * dd;
-      for (int o = 0; o < st; ++o) {
-        int w[3] = {c[0] + o % 3 - 1, c[1] + (o / 3) % 3 - 1, d == 3 ? c[2] + o / 9 - 1 : 0};
-        if (!mg_interior(w, L.n, d)) continue;
-        int64_t wi = w[0] + (int64_t)(L.n[0] + 1) * (w[1] + (int64_t)(L.n[1] + 1) * w[2]);
+    const bool inner = mg_interior(c, L.n, d);
+    R part[3] = {R(0), R(0), R(0)};
+    if (inner && mode != 0 && lane < st) {
+      const int o = lane;
+      int w[3] = {c[0] + o % 3 - 1, c[1] + (o / 3) % 3 - 1, d == 3 ? c[2] + o / 9 - 1 : 0};
+      if (mg_interior(w, L.n, d)) {
+        const int64_t wi = w[0] + (int64_t)(L.n[0] + 1) * (w[1] + (int64_t)(L.n[1] + 1) * w[2]);
+        const R* Av = A + ((size_t)v * st + o) * dd;
         for (int k = 0; k < d; ++k)
-          for (int m = 0; m < d; ++m) res[k] -= Av[o * dd + k * d + m] * x[wi * d + m];
+          for (int m = 0; m < d; ++m) part[k] += Av[k * d + m] * x[wi * d + m];
       }
     }
-    if (mode == 1) {
-      for (int k = 0; k < d; ++k) r[v * d + k] = res[k];
-    } else {
-      const R* D = Di + (size_t)v * dd;
-      R upd[3];
-      for (int k = 0; k < d; ++k) {
-        upd[k] = 0;
-        for (int m = 0; m < d; ++m) upd[k] += D[k * d + m] * res[m];
+    for (int k = 0; k < d; ++k) part[k] = group32_sum(part[k]);
+    if (lane == 0) {
+      if (!inner) {
+        if (mode == 1)
+          for (int k = 0; k < d; ++k) r[v * d + k] = R(0);
+      } else {
+        R res[3];
+        for (int k = 0; k < d; ++k) res[k] = b[v * d + k] - part[k];
+        if (mode == 1) {
+          for (int k = 0; k < d; ++k) r[v * d + k] = res[k];
+        } else {
+          const R* D = Di + (size_t)v * dd;
+          for (int k = 0; k < d; ++k) {
+            R u = R(0);
+            for (int m = 0; m < d; ++m) u += D[k * d + m] * res[m];
+            x[v * d + k] = (mode == 0 ? R(0) : x[v * d + k]) + u;
+          }
+        }
       }
-      for (int k = 0; k < d; ++k) x[v * d + k] = (mode == 0 ? R(0) : x[v * d + k]) + upd[k];
     }
   }
 }
@@ -393,59 +469,70 @@ __device__ inline double mg_w(int i, int I, int n) {
   return 0.0;
 }
 
-// b_c = P^T r_f (interior coarse vertices).
+// b_c = P^T r_f (interior coarse vertices); one 32-lane group per coarse vertex.
 template <typename R>
-__global__ void k_mg_restrict(int d, MGLevelDev F, MGLevelDev C) {
+__global__ void __launch_bounds__(256) k_mg_restrict(int d, MGLevelDev F, MGLevelDev C) {
   const R* r = (const R*)F.r;
   R* bc = (R*)C.b;
   const int st = d == 3 ? 27 : 9;
-  for (int64_t V = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; V < C.nvert; V += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 31;
+  const int64_t gpb = blockDim.x >> 5;
+  for (int64_t V = blockIdx.x * gpb + (threadIdx.x >> 5); V < C.nvert; V += (int64_t)gridDim.x * gpb) {
     int CI[3];
     mg_coords(V, C.n, CI);
-    R acc[3] = {0, 0, 0};
-    if (mg_interior(CI, C.n, d)) {
+    const bool inner = mg_interior(CI, C.n, d);
+    R acc[3] = {R(0), R(0), R(0)};
+    if (inner && lane < st) {
+      const int o = lane;
       int base[3] = {mg_cpos(CI[0], F.n[0]), mg_cpos(CI[1], F.n[1]), d == 3 ? mg_cpos(CI[2], F.n[2]) : 0};
-      for (int o = 0; o < st; ++o) {
-        int fi[3] = {base[0] + o % 3 - 1, base[1] + (o / 3) % 3 - 1, d == 3 ? base[2] + o / 9 - 1 : 0};
-        if (!mg_interior(fi, F.n, d)) continue;
+      int fi[3] = {base[0] + o % 3 - 1, base[1] + (o / 3) % 3 - 1, d == 3 ? base[2] + o / 9 - 1 : 0};
+      if (mg_interior(fi, F.n, d)) {
         double w = 1.0;
         for (int a = 0; a < d; ++a) w *= mg_w(fi[a], CI[a], F.n[a]);
-        if (w == 0.0) continue;
-        int64_t fv = fi[0] + (int64_t)(F.n[0] + 1) * (fi[1] + (int64_t)(F.n[1] + 1) * fi[2]);
-        for (int k = 0; k < d; ++k) acc[k] += (R)w * r[fv * d + k];
+        if (w != 0.0) {
+          const int64_t fv = fi[0] + (int64_t)(F.n[0] + 1) * (fi[1] + (int64_t)(F.n[1] + 1) * fi[2]);
+          for (int k = 0; k < d; ++k) acc[k] = (R)w * r[fv * d + k];
+        }
       }
     }
-    for (int k = 0; k < d; ++k) bc[V * d + k] = acc[k];
+    for (int k = 0; k < d; ++k) acc[k] = group32_sum(acc[k]);
+    if (lane == 0)
+      for (int k = 0; k < d; ++k) bc[V * d + k] = inner ? acc[k] : R(0);
   }
 }
 
-// x_f += P x_c (interior fine vertices).
+// x_f += P x_c (interior fine vertices); one 32-lane group per fine vertex, one
+// candidate coarse vertex per lane.
 template <typename R>
-__global__ void k_mg_prolong(int d, MGLevelDev F, MGLevelDev C) {
+__global__ void __launch_bounds__(256) k_mg_prolong(int d, MGLevelDev F, MGLevelDev C) {
   R* x = (R*)F.x;
   const R* xc = (const R*)C.x;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < F.nvert; v += (int64_t)gridDim.x * blockDim.x) {
+  const int st = d == 3 ? 27 : 9;
+  const int lane = threadIdx.x & 31;
+  const int64_t gpb = blockDim.x >> 5;
+  for (int64_t v = blockIdx.x * gpb + (threadIdx.x >> 5); v < F.nvert; v += (int64_t)gridDim.x * gpb) {
     int fi[3];
     mg_coords(v, F.n, fi);
-    if (!mg_interior(fi, F.n, d)) continue;
-    R acc[3] = {0, 0, 0};
-    int lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-      if (a < d) { lo[a] = fi[a] / 2 - 1; hi[a] = fi[a] / 2 + 1; if (lo[a] < 0) lo[a] = 0; if (hi[a] > C.n[a]) hi[a] = C.n[a]; }
-      else { lo[a] = 0; hi[a] = 0; }
-    }
-    for (int I2 = lo[2]; I2 <= hi[2]; ++I2)
-      for (int I1 = lo[1]; I1 <= hi[1]; ++I1)
-        for (int I0 = lo[0]; I0 <= hi[0]; ++I0) {
-          int CI[3] = {I0, I1, I2};
-          if (!mg_interior(CI, C.n, d)) continue;
-          double w = 1.0;
-          for (int a = 0; a < d; ++a) w *= mg_w(fi[a], CI[a], F.n[a]);
-          if (w == 0.0) continue;
-          int64_t cv = I0 + (int64_t)(C.n[0] + 1) * (I1 + (int64_t)(C.n[1] + 1) * I2);
-          for (int k = 0; k < d; ++k) acc[k] += (R)w * xc[cv * d + k];
+    const bool inner = mg_interior(fi, F.n, d);
+    R acc[3] = {R(0), R(0), R(0)};
+    if (inner && lane < st) {
+      const int o = lane;
+      int CI[3] = {fi[0] / 2 - 1 + o % 3, fi[1] / 2 - 1 + (o / 3) % 3, d == 3 ? fi[2] / 2 - 1 + o / 9 : 0};
+      bool ok = true;
+      for (int a = 0; a < d; ++a)
+        if (CI[a] < 0 || CI[a] > C.n[a]) ok = false;
+      if (ok && mg_interior(CI, C.n, d)) {
+        double w = 1.0;
+        for (int a = 0; a < d; ++a) w *= mg_w(fi[a], CI[a], F.n[a]);
+        if (w != 0.0) {
+          const int64_t cv = CI[0] + (int64_t)(C.n[0] + 1) * (CI[1] + (int64_t)(C.n[1] + 1) * CI[2]);
+          for (int k = 0; k < d; ++k) acc[k] = (R)w * xc[cv * d + k];
         }
-    for (int k = 0; k < d; ++k) x[v * d + k] += acc[k];
+      }
+    }
+    for (int k = 0; k < d; ++k) acc[k] = group32_sum(acc[k]);
+    if (lane == 0 && inner)
+      for (int k = 0; k < d; ++k) x[v * d + k] += acc[k];
   }
 }
 
@@ -466,33 +553,36 @@ __global__ void k_mg_coarse(int64_t nc, const double* __restrict__ Cinv, const i
 }
 
 // ------------------------------------------------------------ pressure parts
-// y_p = M_p^{-1} (r_p - B a) with M_p^{-1} = (nu_T/|det J|) Mp^-1_ref.
-// B a is computed by all threads (one velocity row each) and reduced in LDS.
+// y_p = M_p^{-1} (r_p - B a) with M_p^{-1} = (nu_T/|det J|) Mp^-1_ref; the
+// velocity is gathered once (scaled by the Piola factors of B), then each
+// wave reduces one pressure row at a time.
 template <typename R>
 __global__ void __launch_bounds__(256) k_elem_press(SolveParams P, const R* __restrict__ a, const R* __restrict__ r,
                                                     R* __restrict__ y, int with_B) {
   const Sizes s = P.s;
-  const int nb = s.nb, nd = s.nd, np = s.np, nv = s.d + 1;
-  __shared__ double part[4][MAXNP];
+  const int nb = s.nb, nd = s.nd, np = s.np, nu = s.nu;
+  __shared__ double us[MAXNB + MAXND];
   __shared__ double bp[MAXNP];
+  __shared__ int rmap[MAXNB + MAXND];
+  __shared__ R ad[MAXND];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  build_rowmap(s, rmap);
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     const double det = P.detJ[e];
-    // each wave owns a set of pressure rows; lanes run over velocity rows
+    if (with_B) {
+      const double sb = -fabs(det), sf = det > 0 ? -1.0 : 1.0;
+      gather_elem_d(P, a, e, ad);
+      __syncthreads();
+      for (int row = tid; row < nb + nd; row += blockDim.x) {
+        int iu = rmap[row];
+        if (iu >= 0) us[iu] = (row < nb ? sb * (double)a[e * nb + row] : sf * (double)ad[row - nb]);
+      }
+    }
+    __syncthreads();
     for (int q = wave; q < np; q += 4) {
       double acc = 0.0;
       if (with_B) {
-        for (int row = lane; row < nb + nd; row += 64) {
-          double av;
-          if (row < nb) av = (double)a[e * nb + row];
-          else {
-            int t = row - nb, f = t / s.nfb, qq = t % s.nfb;
-            if (qq >= s.nF) continue;
-            int gg = P.elem_ff[e * nv + f];
-            av = gg >= 0 ? (double)a[P.off_f + (int64_t)gg * s.nfb + qq] : 0.0;
-          }
-          acc += Bentry(P, det, q, row) * av;
-        }
+        for (int iu = lane; iu < nu; iu += 64) acc += P.rBp[(size_t)q * nu + iu] * us[iu];
         acc = wave_sum(acc);
       }
       if (lane == 0) bp[q] = (double)r[P.off_p + e * np + q] - acc;
@@ -653,15 +743,15 @@ void launch_ed(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const i
 }
 template <typename R>
 void launch_mg_point(hipStream_t st, int d, const MGLevelDev& L, int mode) {
-  hipLaunchKernelGGL(k_mg_point<R>, dim3(grid_for(L.nvert)), dim3(256), 0, st, d, L, mode);
+  hipLaunchKernelGGL(k_mg_point<R>, dim3(grid_for(L.nvert, 8)), dim3(256), 0, st, d, L, mode);
 }
 template <typename R>
 void launch_mg_restrict(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C) {
-  hipLaunchKernelGGL(k_mg_restrict<R>, dim3(grid_for(C.nvert)), dim3(256), 0, st, d, F, C);
+  hipLaunchKernelGGL(k_mg_restrict<R>, dim3(grid_for(C.nvert, 8)), dim3(256), 0, st, d, F, C);
 }
 template <typename R>
 void launch_mg_prolong(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C) {
-  hipLaunchKernelGGL(k_mg_prolong<R>, dim3(grid_for(F.nvert)), dim3(256), 0, st, d, F, C);
+  hipLaunchKernelGGL(k_mg_prolong<R>, dim3(grid_for(F.nvert, 8)), dim3(256), 0, st, d, F, C);
 }
 template <typename R>
 void launch_mg_coarse(hipStream_t st, int64_t nc, const double* Cinv, const int32_t* cmap, const MGLevelDev& L) {
