@@ -67,11 +67,11 @@ template <typename R>
 OpPtrs<R> op_ptrs(mcs_problem* pb);
 template <>
 OpPtrs<double> op_ptrs<double>(mcs_problem* pb) {
-  return {pb->p.Ad, pb->p.H, pb->p.Ht, pb->p.Aoo, pb->p.Aooinv, pb->p.Dinv, pb->p.EF, pb->p.W};
+  return {pb->p.Ad, pb->p.H, pb->p.Aoo, pb->p.Aooinv, pb->p.Dinv, pb->p.EF, pb->p.W};
 }
 template <>
 OpPtrs<float> op_ptrs<float>(mcs_problem* pb) {
-  return {pb->p.Ad32, pb->p.H32, pb->p.Ht32, pb->p.Aoo32, pb->p.Aooinv32, pb->p.Dinv32, pb->p.EF32, pb->p.W32};
+  return {pb->p.Ad32, pb->p.H32, pb->p.Aoo32, pb->p.Aooinv32, pb->p.Dinv32, pb->p.EF32, pb->p.W32};
 }
 
 template <typename R>
@@ -432,12 +432,10 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   p.detJ = ws_ptr<double>(pb, "detJ");
   p.Ad = ws_ptr<double>(pb, "Ad");
   p.H = ws_ptr<double>(pb, "H");
-  p.Ht = ws_ptr<double>(pb, "Ht");
   p.Aoo = ws_ptr<double>(pb, "Aoo");
   p.Aooinv = ws_ptr<double>(pb, "Aooinv");
   p.Ad32 = ws_ptr<float>(pb, "Ad32");
   p.H32 = ws_ptr<float>(pb, "H32");
-  p.Ht32 = ws_ptr<float>(pb, "Ht32");
   p.Aoo32 = ws_ptr<float>(pb, "Aoo32");
   p.Aooinv32 = ws_ptr<float>(pb, "Aooinv32");
   p.Dinv = ws_ptr<double>(pb, "Dinv");
@@ -540,12 +538,10 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   C.detJ = p.detJ;
   C.Ad = p.Ad;
   C.H = p.H;
-  C.Ht = p.Ht;
   C.Aoo = p.Aoo;
   C.Aooinv = p.Aooinv;
   C.Ad32 = p.Ad32;
   C.H32 = p.H32;
-  C.Ht32 = p.Ht32;
   C.Aoo32 = p.Aoo32;
   C.Aooinv32 = p.Aooinv32;
   C.status = status;
@@ -890,7 +886,7 @@ int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count)
   struct E {
     const char* n;
     int64_t cnt;
-  } table[] = {{"Ad", pb->ne * s.nd * s.nd},   {"H", pb->ne * s.nb * s.nd},       {"Ht", pb->ne * s.nb * s.nd},
+  } table[] = {{"Ad", pb->ne * s.nd * s.nd},   {"H", pb->ne * s.nb * s.nd},
                {"Aoo", pb->ne * s.nb * s.nb},  {"Aooinv", pb->ne * s.nb * s.nb},  {"Dinv", pb->nff * s.nfb * s.nfb},
                {"EF", pb->nff * s.nfb * pb->d * pb->d}, {"Ad32", pb->ne * s.nd * s.nd}, {"H32", pb->ne * s.nb * s.nd},
                {"detJ", pb->ne},               {"colour_facets", pb->nff},        {"elem_ff", pb->ne * (pb->d + 1)}};

@@ -20,8 +20,8 @@ struct CondParams {
   double facet_measure[4];
   double* scratch;
   double* detJ;
-  double *Ad, *H, *Ht, *Aoo, *Aooinv;
-  float *Ad32, *H32, *Ht32, *Aoo32, *Aooinv32;
+  double *Ad, *H, *Aoo, *Aooinv;
+  float *Ad32, *H32, *Aoo32, *Aooinv32;
   int* status;
 };
 
@@ -81,7 +81,7 @@ struct SolveParams {
 
 template <typename R>
 struct OpPtrs {
-  const R *Ad, *H, *Ht, *Aoo, *Aooinv, *Dinv, *EF, *W;
+  const R *Ad, *H, *Aoo, *Aooinv, *Dinv, *EF, *W;
 };
 
 struct MGLevelDev {

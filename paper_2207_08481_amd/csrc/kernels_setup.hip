@@ -367,8 +367,9 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
       P.Aooinv[(size_t)e * nb * nb + idx] = Wk[idx];
       P.Aooinv32[(size_t)e * nb * nb + idx] = (float)Wk[idx];
     }
-    // Ht[n][m] = sum_k A[nb+n][k] Aooinv[m][k]   (nd x nb)
-    double* Ht = P.Ht + (size_t)e * nb * nd;
+    // Ht[n][m] = sum_k A[nb+n][k] Aooinv[m][k]   (nd x nb), kept in the slot
+    // scratch (the sigma columns G are no longer needed)
+    double* Ht = G;
     for (int m0 = 0; m0 < nd; m0 += 64)
       for (int n0 = 0; n0 < nb; n0 += 64) {
         double acc[4][4];
@@ -380,7 +381,6 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
             if (r < nd && c < nb) {
               double v = acc[i][j];
               Ht[(size_t)r * nb + c] = v;
-              P.Ht32[(size_t)e * nb * nd + (size_t)r * nb + c] = (float)v;
               P.H[(size_t)e * nb * nd + (size_t)c * nd + r] = v;
               P.H32[(size_t)e * nb * nd + (size_t)c * nd + r] = (float)v;
             }

@@ -6,10 +6,11 @@
 // vector reductions for MINRES.
 //
 // Layout of element operators (element-major, row-major inside an element):
-//   Ad  [nd][nd] symmetric;  H [nb][nd];  Ht [nd][nb] (= H^T);
+//   Ad  [nd][nd] symmetric;  H [nb][nd];
 //   Aoo [nb][nb], Aooinv [nb][nb] symmetric;  Dinv [nfb][nfb] symmetric.
-// Every thread of an element / facet block reads one column of a symmetric
-// matrix (= one row), so consecutive threads read consecutive addresses.
+// Products with a symmetric matrix give each thread one column (= one row),
+// so consecutive threads read consecutive addresses; products with the rows
+// of H give each wave one row, lanes over its contiguous columns.
 #include "kernels_common.h"
 #include "launch.h"
 
@@ -41,6 +42,34 @@ __device__ inline R group32_sum(R v) {
   return v;
 }
 
+template <int L, typename R>
+__device__ inline R group_sum(R v) {
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
+  return v;
+}
+
+// Row products of a row-major nrow x ncol matrix with an LDS vector: threads
+// [t0, t0 + nthr) form groups of L lanes, one group per row (lanes over the
+// contiguous columns); epi(i, sum) runs on the group's first lane.  The row
+// loop is uniform over the participating waves (t0, nthr multiples of 64).
+template <int L, typename R, typename F>
+__device__ inline void rows_times(const R* __restrict__ M, int nrow, int ncol, const R* v, int t0, int nthr,
+                                  F epi) {
+  const int t = threadIdx.x - t0;
+  const int g = t / L, l = t % L, ng = nthr / L;
+  for (int i0 = 0; i0 < nrow; i0 += ng) {
+    const int i = i0 + g;
+    R acc = R(0);
+    if (i < nrow) {
+      const R* Mi = M + (size_t)i * ncol;
+      for (int j = l; j < ncol; j += L) acc += Mi[j] * v[j];
+    }
+    acc = group_sum<L>(acc);
+    if (l == 0 && i < nrow) epi(i, acc);
+  }
+}
+
 // Per-workgroup table of the velocity rows of an element (reordered local
 // order): original BDM index (or -1 for tangential rows) and the kind of
 // scale in phi = s J phi^ (0: bubble, s = 1; 1: facet function, s = 1/det J).
@@ -58,9 +87,10 @@ __device__ inline void build_rowmap(const Sizes& s, int* rmap) {
 
 // flags: 1 = velocity block A (factorised), 2 = + B^T p, 4 = p <- B u, 8 = A^d only,
 // 16 = write zero pressure rows when B u is not requested.
-// Phase 1 runs A^d x_d (threads [0, n_d)) concurrently with the partial sums of
-// H x_d (the remaining threads); phase 2 finishes z_o = x_o + H x_d and
-// w_o = A_oo z_o; phase 3 adds H^T w_o and the pressure coupling.
+// Phase 1: the first ceil(n_d/64) waves form A^d x_d (one row per thread,
+// A^d symmetric so its columns are contiguous) while the remaining waves form
+// z_o = x_o + H x_d (16-lane groups per row of H); phase 2: w_o = A_oo z_o;
+// phase 3: H^T w_o (one column per thread) and the pressure coupling.
 // B_T[q][row] = -s |det J| Bp^[q][iu(row)] (s = 1 bubble, 1/det J facet row).
 template <typename R>
 __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, OpPtrs<R> O, const R* __restrict__ x,
@@ -69,15 +99,14 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, OpPtrs<R> O, 
   const int nb = s.nb, nd = s.nd, np = s.np, nu = s.nu;
   __shared__ R xd[MAXND], xo[MAXNB], zo[MAXNB], wo[MAXNB];
   __shared__ R xp[MAXNP];
-  __shared__ R zpart[256];
   __shared__ int rmap[MAXNB + MAXND];
-  __shared__ double us[MAXNB + MAXND];   // scaled velocity for B u, indexed by BDM index
+  __shared__ double us[MAXNB + MAXND];   // Piola-scaled velocity for B u, by BDM index
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool doA = flags & 1, doBT = flags & 2, doBu = flags & 4, onlyAd = flags & 8;
   const bool doH = doA && !onlyAd;
   build_rowmap(s, rmap);
-  const int nhelp = 256 - nd;                    // threads not owning an A^d row
-  const int parts = nhelp >= nb ? nhelp / nb : 1;
+  const int tA = ((nd + 63) >> 6) << 6;          // threads of the A^d product
+  const bool overlap = tA < 256;
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     const double det = P.detJ[e];
     const double sb = -fabs(det), sf = det > 0 ? -1.0 : 1.0;
@@ -85,29 +114,16 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, OpPtrs<R> O, 
     if (tid < nb) xo[tid] = x[e * nb + tid];
     if (tid < np) xp[tid] = x[P.off_p + e * np + tid];
     __syncthreads();
-    R accA = R(0);
+    const R* He = O.H + (size_t)e * nb * nd;
+    R acc = R(0);
     if (tid < nd) {
       if (doA) {
         const R* Ad = O.Ad + (size_t)e * nd * nd + tid;
 #pragma unroll 8
-        for (int j = 0; j < nd; ++j) accA += Ad[(size_t)j * nd] * xd[j];
+        for (int j = 0; j < nd; ++j) acc += Ad[(size_t)j * nd] * xd[j];
       }
-    } else if (doH) {
-      const int h = tid - nd;
-      const R* Ht = O.Ht + (size_t)e * nb * nd;
-      if (nhelp >= nb) {
-        const int i = h % nb, part = h / nb;
-        R acc = R(0);
-        if (part < parts)
-          for (int j = part; j < nd; j += parts) acc += Ht[(size_t)j * nb + i] * xd[j];
-        zpart[h] = acc;
-      } else {
-        for (int i = h; i < nb; i += nhelp) {
-          R acc = R(0);
-          for (int j = 0; j < nd; ++j) acc += Ht[(size_t)j * nb + i] * xd[j];
-          zpart[i] = acc;   // parts == 1: slot i
-        }
-      }
+    } else if (doH && overlap && tid >= tA) {
+      rows_times<16>(He, nb, nd, xd, tA, 256 - tA, [&](int i, R v) { zo[i] = xo[i] + v; });
     }
     if (doBu) {
       for (int row = tid; row < nb + nd; row += blockDim.x) {
@@ -115,27 +131,18 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, OpPtrs<R> O, 
         if (iu >= 0) us[iu] = (row < nb ? sb * (double)xo[row] : sf * (double)xd[row - nb]);
       }
     }
+    if (doH && !overlap) {
+      __syncthreads();
+      rows_times<16>(He, nb, nd, xd, 0, 256, [&](int i, R v) { zo[i] = xo[i] + v; });
+    }
     __syncthreads();
     if (doH) {
-      if (tid < nb) {
-        R acc = xo[tid];
-        for (int pp = 0; pp < parts; ++pp) acc += zpart[pp * nb + tid];
-        zo[tid] = acc;
-      }
-      __syncthreads();
-      if (tid < nb) {
-        const R* Aoo = O.Aoo + (size_t)e * nb * nb + tid;
-        R acc = R(0);
-#pragma unroll 4
-        for (int j = 0; j < nb; ++j) acc += Aoo[(size_t)j * nb] * zo[j];
-        wo[tid] = acc;
-      }
+      rows_times<8>(O.Aoo + (size_t)e * nb * nb, nb, nb, zo, 0, 256, [&](int i, R v) { wo[i] = v; });
       __syncthreads();
     }
     if (tid < nd) {
-      R acc = accA;
       if (doH) {
-        const R* H = O.H + (size_t)e * nb * nd + tid;
+        const R* H = He + tid;
 #pragma unroll 4
         for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd] * wo[i];
       }
@@ -150,20 +157,20 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, OpPtrs<R> O, 
       escr[e * nd + tid] = acc;
     }
     if (!onlyAd && tid < nb) {
-      R acc = doH ? wo[tid] : R(0);
+      R a = doH ? wo[tid] : R(0);
       if (doBT) {
         double b = 0.0;
         for (int q = 0; q < np; ++q) b += P.rBp[(size_t)q * nu + tid] * (double)xp[q];
-        acc += (R)(sb * b);
+        a += (R)(sb * b);
       }
-      y[e * nb + tid] = acc;
+      y[e * nb + tid] = a;
     }
     if (doBu) {
       for (int q = wave; q < np; q += 4) {
-        double acc = 0.0;
-        for (int iu = lane; iu < nu; iu += 64) acc += P.rBp[(size_t)q * nu + iu] * us[iu];
-        acc = wave_sum(acc);
-        if (lane == 0) y[P.off_p + e * np + q] = (R)acc;
+        double a = 0.0;
+        for (int iu = lane; iu < nu; iu += 64) a += P.rBp[(size_t)q * nu + iu] * us[iu];
+        a = wave_sum(a);
+        if (lane == 0) y[P.off_p + e * np + q] = (R)a;
       }
     } else if (!onlyAd && tid < np && (flags & 16)) {
       y[P.off_p + e * np + tid] = R(0);
@@ -189,9 +196,9 @@ __global__ void k_facet_sum(SolveParams P, const R* __restrict__ escr, const R* 
   }
 }
 
-// A-hat_ext^{-1}, first part: escr_T = H_T^T r_o,T (threads [0, n_d));
-// t_o = Aoo^{-1} r_o (the following n_o threads, or the first ones when
-// n_d + n_o exceeds the block).
+// A-hat_ext^{-1}, first part: escr_T = H_T^T r_o,T (threads [0, n_d), one
+// column of H_T each); t_o = Aoo^{-1} r_o (the following n_o threads, or the
+// first ones when n_d + n_o exceeds the block).
 template <typename R>
 __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, const R* __restrict__ r,
                                                  R* __restrict__ to, R* __restrict__ escr) {
@@ -199,7 +206,7 @@ __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, con
   const int nb = s.nb, nd = s.nd;
   __shared__ R ro[MAXNB];
   const int tid = threadIdx.x;
-  const int ob = (nd + nb <= 256) ? nd : 0;      // first thread of the A_oo^{-1} product
+  const int ob = (nd + nb <= 256) ? nd : 0;
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     if (tid < nb) ro[tid] = r[e * nb + tid];
     __syncthreads();
@@ -222,35 +229,18 @@ __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, con
   }
 }
 
-// A-hat_ext^{-1}, last part: y_o = t_o - H_T t_d,T; the n_d-long sums are split
-// over all threads and reduced in LDS.
+// A-hat_ext^{-1}, last part: y_o = t_o - H_T t_d,T (8-lane groups per row of H_T).
 template <typename R>
 __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, const R* __restrict__ t,
                                                   const R* __restrict__ to, R* __restrict__ y) {
   const Sizes s = P.s;
   const int nb = s.nb, nd = s.nd;
   __shared__ R td[MAXND];
-  __shared__ R part[256];
-  const int tid = threadIdx.x;
-  const int parts = 256 / nb;
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     gather_elem_d(P, t, e, td);
     __syncthreads();
-    {
-      const int i = tid % nb, pp = tid / nb;
-      R acc = R(0);
-      if (pp < parts) {
-        const R* Ht = O.Ht + (size_t)e * nb * nd + i;
-        for (int j = pp; j < nd; j += parts) acc += Ht[(size_t)j * nb] * td[j];
-      }
-      part[tid] = acc;
-    }
-    __syncthreads();
-    if (tid < nb) {
-      R acc = to[e * nb + tid];
-      for (int pp = 0; pp < parts; ++pp) acc -= part[pp * nb + tid];
-      y[e * nb + tid] = acc;
-    }
+    rows_times<8>(O.H + (size_t)e * nb * nd, nb, nd, td, 0, 256,
+                  [&](int i, R v) { y[e * nb + i] = to[e * nb + i] - v; });
     __syncthreads();
   }
 }

@@ -92,8 +92,8 @@ struct DevPtrs {
   int32_t* rlatmap;
   // element operators
   double *nu, *detJ;
-  double *Ad, *H, *Ht, *Aoo, *Aooinv;
-  float *Ad32, *H32, *Ht32, *Aoo32, *Aooinv32;
+  double *Ad, *H, *Aoo, *Aooinv;
+  float *Ad32, *H32, *Aoo32, *Aooinv32;
   double *Dinv, *EF, *W;
   float *Dinv32, *EF32, *W32;
   // multigrid coarsest

@@ -357,12 +357,10 @@ int layout_workspace(mcs_problem* pb) {
   L.add("detJ", Dd(ne));
   L.add("Ad", Dd(ne * s.nd * s.nd));
   L.add("H", Dd(ne * s.nb * s.nd));
-  L.add("Ht", Dd(ne * s.nb * s.nd));
   L.add("Aoo", Dd(ne * s.nb * s.nb));
   L.add("Aooinv", Dd(ne * s.nb * s.nb));
   L.add("Ad32", Ff(ne * s.nd * s.nd));
   L.add("H32", Ff(ne * s.nb * s.nd));
-  L.add("Ht32", Ff(ne * s.nb * s.nd));
   L.add("Aoo32", Ff(ne * s.nb * s.nb));
   L.add("Aooinv32", Ff(ne * s.nb * s.nb));
   L.add("Dinv", Dd(nff * s.nfb * s.nfb));
