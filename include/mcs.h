@@ -192,8 +192,9 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
 int mcs_normalize_pressure(mcs_problem* pb, double* x);
 
 /* Device pointer and element count of an internal array, for inspection:
- * name in {"Ad", "H", "Aoo", "Aooinv", "Dinv", "EF", "colour", "elem_ff",
- * "Ad32", "H32"}.  The memory belongs to the caller's workspace. */
+ * name in {"Ad", "H", "Aoo", "Aooinv", "Dinv", "EF", "Ad32", "H32", "detJ",
+ * "colour_facets", "elem_ff", "W", "Cinv", "mgA0"}.  The memory belongs to
+ * the caller's workspace. */
 int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count);
 
 /* Host copy of the facet colour of each free facet, and of each element's
@@ -216,6 +217,65 @@ int mcs_timer_read(mcs_problem* pb, double* total_ms, int64_t* launches, double*
 void mcs_destroy(mcs_problem* pb);
 const char* mcs_status_string(int status);
 const char* mcs_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent problems (meshes, orders, viscosities, forces)
+ * solved together.  Members with the same dimension and order form a group;
+ * a group is one union of its members' elements, facets and lattices, so
+ * every kernel of the path runs once per group over all of its members.  The
+ * MINRES recurrences run per member with device-resident scalars, members
+ * leave the iteration one by one (their work is masked out), and the
+ * iterations of all groups are replayed as one captured HIP graph.  Every
+ * member's arithmetic is the same whatever the other members are: per-member
+ * reductions run over tiles that never straddle two members, in a fixed
+ * order.  The method per member is the one of mcs_solve (Sec. 4.2, eq.
+ * mhatinvfactor, Corollary aux_pc_mult); precision 1 refines every member in
+ * FP64 with its own stopping test.
+ * ------------------------------------------------------------------------- */
+typedef struct mcs_batch mcs_batch;
+
+typedef struct {
+  int32_t n_problems;
+  int32_t n_groups;         /* distinct (dim, order) pairs */
+  int64_t n_dof_total;      /* sum of the members' n_dof */
+  size_t workspace_bytes;   /* bytes the caller must provide to mcs_batch_bind */
+} mcs_batch_info;
+
+/* Host only.  Plans n >= 1 members: meshes[i] with order orders[i]; the other
+ * options (precision, tolerances, smoothing, limits) are shared.  Errors as
+ * mcs_plan, naming the member. */
+int mcs_batch_plan(const mcs_mesh* meshes, const int32_t* orders, int32_t n, const mcs_options* options,
+                   mcs_batch** out, mcs_batch_info* info);
+
+/* Sizes of member i in its own layout (the layout of mcs_plan's info). */
+int mcs_batch_member_info(const mcs_batch* b, int32_t i, mcs_info* info);
+
+/* Binds the batch to the current device, a caller-owned workspace of at least
+ * info.workspace_bytes bytes (256-byte aligned) and a stream (hipStream_t,
+ * may be NULL); each group also gets a library-created stream of default
+ * priority, joined to the given one around every call.  [sync] */
+int mcs_batch_bind(mcs_batch* b, void* workspace, size_t bytes, void* stream);
+
+/* Condensation and preconditioner setup of every member (mcs_condense).
+ * nu_host: host array of n device pointers, member i's viscosities
+ * [n_elements_i].  [sync]  Errors name the member. */
+int mcs_batch_condense(mcs_batch* b, const double* const* nu_host);
+
+/* Solves every member (mcs_solve semantics, pressure mean zero).  f_host and
+ * x_host: host arrays of n device pointers, member i's force values
+ * [n_elements_i][n_lat][dim] and its solution double[n_dof_i] in its own
+ * layout.  infos: host array of n entries or NULL; t_solve_ms is the batch's
+ * wall time.  Returns MCS_OK when every member converged, else the first
+ * failing member's status (each member's own status is in infos).  [sync] */
+int mcs_batch_solve(mcs_batch* b, const double* const* f_host, double* const* x_host, mcs_solve_info* infos);
+
+/* Execution mode of mcs_batch_solve: use_graph = 1 (default) replays each run
+ * of `chunk` MINRES iterations of all groups as one captured HIP graph;
+ * use_graph = 0 launches the same kernels one by one.  chunk is a positive
+ * multiple of 6 (default 6).  Both modes give identical results. */
+int mcs_batch_set_mode(mcs_batch* b, int use_graph, int chunk);
+
+void mcs_batch_destroy(mcs_batch* b);
 
 #ifdef __cplusplus
 }

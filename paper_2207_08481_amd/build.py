@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcs.so")
-SOURCES = ["refel.cpp", "plan.cpp", "kernels_setup.hip", "kernels_solve.hip", "driver.hip"]
+SOURCES = ["refel.cpp", "plan.cpp", "kernels_setup.hip", "kernels_solve.hip", "kernels_batch.hip", "driver.hip",
+           "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MCS_OFFLOAD_ARCH", "gfx950")
 
@@ -20,7 +21,7 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 5) -> str:
+def build(verbose: bool = False, jobs: int = 7) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     procs = []

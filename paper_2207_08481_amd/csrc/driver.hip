@@ -12,8 +12,7 @@
 #include <cstring>
 #include <new>
 
-#include "kernels_common.h"
-#include "launch.h"
+#include "ctx.h"
 
 namespace mcs {
 int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb);
@@ -34,256 +33,6 @@ using namespace mcs;
   } while (0)
 
 namespace {
-
-// work-vector slots
-enum { VX = 0, VR1, VR2, VY, VV, VW1, VW2, VKV, PA1, PG, PS, PT, PT1, PTMP, PB1, VB64, VR64, VX64, VT64, NVEC };
-
-template <typename T>
-T* ws_ptr(mcs_problem* pb, const char* name) {
-  int64_t off = offset_of(pb, name);
-  return off < 0 ? nullptr : reinterpret_cast<T*>(static_cast<char*>(pb->ws) + off);
-}
-
-SolveParams solve_params(mcs_problem* pb) {
-  SolveParams P{};
-  P.s = pb->sz;
-  P.ne = pb->ne;
-  P.nff = pb->nff;
-  P.off_f = pb->off_f;
-  P.off_p = pb->off_p;
-  P.ndof = pb->ndof;
-  P.elem_ff = pb->p.elem_ff;
-  P.facet_el = pb->p.facet_el;
-  P.facet_slot = pb->p.facet_slot;
-  P.colour_facets = pb->p.colour_facets;
-  P.detJ = pb->p.detJ;
-  P.nu = pb->p.nu;
-  P.rBp = pb->p.rBp;
-  P.rMpinv = pb->p.rMpinv;
-  return P;
-}
-
-template <typename R>
-OpPtrs<R> op_ptrs(mcs_problem* pb);
-template <>
-OpPtrs<double> op_ptrs<double>(mcs_problem* pb) {
-  return {pb->p.Ad, pb->p.H, pb->p.Aoo, pb->p.Aooinv, pb->p.Dinv, pb->p.EF, pb->p.W};
-}
-template <>
-OpPtrs<float> op_ptrs<float>(mcs_problem* pb) {
-  return {pb->p.Ad32, pb->p.H32, pb->p.Aoo32, pb->p.Aooinv32, pb->p.Dinv32, pb->p.EF32, pb->p.W32};
-}
-
-template <typename R>
-std::vector<MGLevelDev> mg_levels(mcs_problem* pb) {
-  std::vector<MGLevelDev> out;
-  const int d = pb->d, st = d == 3 ? 27 : 9;
-  char* base = static_cast<char*>(pb->ws);
-  for (auto& M : pb->mg) {
-    MGLevelDev L{};
-    for (int a = 0; a < 3; ++a) L.n[a] = M.n[a];
-    L.nvert = M.nvert;
-    size_t nA = (size_t)M.nvert * st * d * d, nD = (size_t)M.nvert * d * d;
-    if (sizeof(R) == 8) {
-      L.A = base + M.off_A;
-      L.Dinv = base + M.off_Dinv;
-    } else {
-      L.A = base + M.off_A + nA * 8;
-      L.Dinv = base + M.off_Dinv + nD * 8;
-    }
-    L.x = base + M.off_x;
-    L.b = base + M.off_b;
-    L.r = base + M.off_r;
-    out.push_back(L);
-  }
-  return out;
-}
-
-// Accumulates the elapsed time of recorded (start, stop) event pairs; the
-// caller has synchronised the stream.
-void timer_flush(mcs_problem* pb) {
-  for (size_t i = 0; i < pb->tpending; ++i) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, pb->tev[2 * i], pb->tev[2 * i + 1]) == hipSuccess) pb->t_ms += ms;
-  }
-  pb->tpending = 0;
-}
-
-template <typename R>
-struct Ctx {
-  mcs_problem* pb;
-  hipStream_t st;
-  SolveParams P;
-  OpPtrs<R> O;
-  std::vector<MGLevelDev> L;
-  R* base;
-  R* escr;
-  R* fscr;
-  int64_t n;
-  explicit Ctx(mcs_problem* p) : pb(p), st(p->stream), P(solve_params(p)), O(op_ptrs<R>(p)), L(mg_levels<R>(p)) {
-    n = p->ndof;
-    base = sizeof(R) == 8 ? reinterpret_cast<R*>(p->p.vec) : reinterpret_cast<R*>(p->p.vec32);
-    escr = reinterpret_cast<R*>(p->p.escr);
-    fscr = reinterpret_cast<R*>(p->p.fscr);
-  }
-  R* v(int i) { return base + (int64_t)i * n; }
-
-  // y = op x on full vectors; flags of k_elem_apply.
-  void apply(const R* x, R* y, int flags) {
-    if (flags & 8) launch_fill<R>(st, n, R(0), y);
-    launch_elem_apply<R>(st, P, O, x, y, escr, flags);
-    launch_facet_sum<R>(st, P, escr, nullptr, R(1), y);
-  }
-
-  void vcycle(size_t l) {
-    const int d = pb->d;
-    if (l + 1 == L.size()) {
-      launch_mg_coarse<R>(st, pb->nc, pb->p.Cinv, pb->p.cmap, L[l]);
-      return;
-    }
-    launch_mg_point<R>(st, d, L[l], 0);
-    launch_mg_point<R>(st, d, L[l], 1);
-    launch_mg_restrict<R>(st, d, L[l], L[l + 1]);
-    vcycle(l + 1);
-    launch_mg_prolong<R>(st, d, L[l], L[l + 1]);
-    launch_mg_point<R>(st, d, L[l], 2);
-  }
-
-  // `smoothing_steps` block Gauss-Seidel sweeps on A^d (colours ascending or
-  // descending); y holds the element products A^d_T x_T and is kept current.
-  void sweeps(R* x, const R* s, R* y, bool forward) {
-    const Sizes& z = pb->sz;
-    const double per_facet = double(2 * z.nfb * z.nd + z.nfb * z.nfb + 4 * z.nd + 5 * z.nfb) * sizeof(R) +
-                             double(6) * 4.0;
-    for (int it = 0; it < pb->opt.smoothing_steps; ++it)
-      for (int cc = 0; cc < pb->ncol; ++cc) {
-        int c = forward ? cc : pb->ncol - 1 - cc;
-        if (pb->timer_on) {
-          size_t k = 2 * pb->tpending;
-          while (pb->tev.size() < k + 2) {
-            hipEvent_t e;
-            hipEventCreate(&e);
-            pb->tev.push_back(e);
-          }
-          hipEventRecord(pb->tev[k], st);
-          launch_smooth_phase<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y);
-          hipEventRecord(pb->tev[k + 1], st);
-          pb->tpending++;
-          pb->t_launches++;
-          pb->t_bytes += per_facet * (pb->colour_off[c + 1] - pb->colour_off[c]);
-        } else {
-          launch_smooth_phase<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y);
-        }
-      }
-  }
-
-  // z_d = E^d C^{-1} E^d^T r_d  (added to z if add)
-  void aux(const R* r, R* z, int add) {
-    launch_edt<R>(st, P, O, r, fscr, pb->nfv, pb->p.vinc_off, pb->p.vinc, pb->p.free_to_lat, (R*)L[0].b, 0);
-    vcycle(0);
-    launch_ed<R>(st, P, O, pb->p.facet_vfree, pb->p.free_to_lat, (const R*)L[0].x, z, add, 0);
-  }
-
-  // x = A-hat^d_m^{-1} s (facet parts; x fully overwritten):
-  //   forward sweeps from x = 0; r = s - A^d x (from the maintained products);
-  //   x += E^d C^{-1} E^d^T r (products updated through W_T); backward sweeps.
-  void ad_mult_inv(const R* s, R* x) {
-    R* tmp = v(PTMP);
-    launch_fill<R>(st, n, R(0), x);
-    launch_fill<R>(st, pb->ne * pb->sz.nd, R(0), escr);
-    sweeps(x, s, escr, true);
-    launch_facet_sum<R>(st, P, escr, s, R(-1), tmp);
-    aux(tmp, x, 1);
-    launch_ycorr<R>(st, P, O.W, pb->p.elem_verts, pb->p.vfree_of_lat, (const R*)L[0].x, escr);
-    sweeps(x, s, escr, false);
-  }
-
-  // y = A-hat_ext^{-1} r (velocity parts; pressure part of y set to 0)
-  void ext_inv(const R* r, R* y) {
-    R *S = v(PS), *T = v(PT), *T1 = v(PT1);
-    launch_ext_pre<R>(st, P, O, r, T1, escr);
-    launch_facet_sum<R>(st, P, escr, r, R(-1), S);
-    ad_mult_inv(S, T);
-    launch_ext_post<R>(st, P, O, T, T1, y);
-    launch_axpby<R>(st, pb->nff * pb->sz.nfb, 1.0, T + pb->off_f, 0.0, y + pb->off_f);
-    launch_fill<R>(st, pb->ndof - pb->off_p, R(0), y + pb->off_p);
-  }
-
-  // z = K-hat^{-1} r:  a = A^{-1} r_u;  z_p = M_p^{-1}(r_p - B a);  z_u = a - A^{-1} B^T z_p
-  void khat(const R* r, R* z) {
-    R *A1 = v(PA1), *G = v(PG), *B1 = v(PB1);
-    ext_inv(r, A1);
-    launch_elem_press<R>(st, P, A1, r, z, 1);
-    launch_elem_apply<R>(st, P, O, z, G, escr, 2 | 16);
-    launch_facet_sum<R>(st, P, escr, nullptr, R(1), G);
-    ext_inv(G, B1);
-    launch_axpby<R>(st, pb->off_p, 1.0, A1, 0.0, z);
-    launch_axpby<R>(st, pb->off_p, -1.0, B1, 1.0, z);
-  }
-
-  double dot(const R* a, const R* b, double* host) {
-    launch_dot<R>(st, n, a, b, pb->p.red, pb->p.scal);
-    hipMemcpyAsync(host, pb->p.scal, sizeof(double), hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
-    timer_flush(pb);
-    return *host;
-  }
-
-  // Preconditioned MINRES from x = 0 for K x = b.  Returns status.
-  // Stops when ||r||_{K-hat^{-1}} <= max(tol * beta1, abs_stop); returns
-  // immediately (0 iterations) when beta1 <= stop_beta1.
-  int minres(const R* b, R* x, double tol, int maxit, double stop_beta1, double abs_stop, int* its, double* rel,
-             double* beta1_out, double* host) {
-    R *r1 = v(VR1), *r2 = v(VR2), *y = v(VY), *vv = v(VV), *w1 = v(VW1), *w2 = v(VW2), *kv = v(VKV);
-    launch_fill<R>(st, n, R(0), x);
-    launch_fill<R>(st, n, R(0), r1);
-    launch_fill<R>(st, n, R(0), w1);
-    launch_fill<R>(st, n, R(0), w2);
-    launch_axpby<R>(st, n, 1.0, b, 0.0, r2);
-    khat(r2, y);
-    double b2 = dot(r2, y, host);
-    *its = 0;
-    if (!std::isfinite(b2)) return MCS_ERR_NONFINITE;
-    if (b2 < 0) return MCS_ERR_BREAKDOWN;
-    double beta1 = std::sqrt(b2);
-    *beta1_out = beta1;
-    *rel = 0.0;
-    if (beta1 == 0.0 || beta1 <= stop_beta1) return MCS_OK;
-    double beta = beta1, oldb = 0.0, dbar = 0.0, eps = 0.0, phibar = beta1, cs = -1.0, sn = 0.0;
-    for (int it = 1; it <= maxit; ++it) {
-      launch_axpby<R>(st, n, 1.0 / beta, y, 0.0, vv);
-      apply(vv, kv, 1 | 2 | 4);
-      if (it > 1) launch_axpby<R>(st, n, -beta / oldb, r1, 1.0, kv);
-      double alpha = dot(vv, kv, host);
-      launch_axpby<R>(st, n, -alpha / beta, r2, 1.0, kv);
-      std::swap(r1, r2);   // r1 <- r2
-      std::swap(r2, kv);   // r2 <- new residual, kv <- old r1 buffer (free)
-      khat(r2, y);
-      oldb = beta;
-      double bb = dot(r2, y, host);
-      if (!std::isfinite(bb) || !std::isfinite(alpha)) return MCS_ERR_NONFINITE;
-      if (bb < 0) return MCS_ERR_BREAKDOWN;
-      beta = std::sqrt(bb);
-      double oldeps = eps;
-      double delta = cs * dbar + sn * alpha;
-      double gbar = sn * dbar - cs * alpha;
-      eps = sn * beta;
-      dbar = -cs * beta;
-      double gamma = std::hypot(gbar, beta);
-      if (gamma == 0.0) gamma = 1e-300;
-      cs = gbar / gamma;
-      sn = beta / gamma;
-      double phi = cs * phibar;
-      phibar = sn * phibar;
-      launch_minres_w<R>(st, n, vv, w1, w2, x, 1.0 / gamma, -oldeps / gamma, -delta / gamma, phi);
-      std::swap(w1, w2);
-      *its = it;
-      *rel = phibar / beta1;
-      if (phibar <= std::max(tol * beta1, abs_stop)) return MCS_OK;
-    }
-    return MCS_ERR_NOT_CONVERGED;
-  }
-};
 
 int check_bound(mcs_problem* pb) {
   if (!pb) {
@@ -492,10 +241,29 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   HIPCHK(up(p.rpmom, r.pmom.data(), r.pmom.size() * 8));
   HIPCHK(up(p.rlatmap, r.latmap.data(), r.latmap.size() * 4));
   HIPCHK(up(p.cmap, pb->h_cmap.data(), pb->h_cmap.size() * 4));
-  // multigrid lattice vectors start (and stay) zero on the boundary
+  // multigrid lattice vectors start (and stay) zero on the boundary; block tables
   const int d = pb->d;
   for (auto& M : pb->mg) {
     char* base = static_cast<char*>(pb->ws);
+    std::vector<MGBlockDev> tab(M.blocks.size());
+    for (size_t j = 0; j < M.blocks.size(); ++j) {
+      const MGBlock& B = M.blocks[j];
+      MGBlockDev& T = tab[j];
+      for (int a = 0; a < 3; ++a) {
+        T.n[a] = B.n[a];
+        T.nc3[a] = B.nc3[a];
+      }
+      T.prob = B.prob;
+      T.voff = B.voff;
+      T.nvert = B.nvert;
+      T.cvoff = B.cvoff;
+      T.nvert_c = B.nvert_c;
+      T.nc = B.nc;
+      T.cmap_off = B.cmap_off;
+      T.cinv_off = B.cinv_off;
+    }
+    HIPCHK(up(base + M.off_blk, tab.data(), tab.size() * sizeof(MGBlockDev)));
+    HIPCHK(hipStreamSynchronize(st));   // tab is a local host buffer
     HIPCHK(hipMemsetAsync(base + M.off_x, 0, (size_t)M.nvert * d * 8, st));
     HIPCHK(hipMemsetAsync(base + M.off_b, 0, (size_t)M.nvert * d * 8, st));
     HIPCHK(hipMemsetAsync(base + M.off_r, 0, (size_t)M.nvert * d * 8, st));
@@ -570,8 +338,10 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   char* base = static_cast<char*>(pb->ws);
   P1Params A{};
   A.d = d;
-  for (int a = 0; a < 3; ++a) A.n[a] = pb->mg[0].n[a];
-  A.nvert = pb->mg[0].nvert;
+  A.nblk = (int)pb->mg[0].blocks.size();
+  A.blk = reinterpret_cast<const MGBlockDev*>(base + pb->mg[0].off_blk);
+  A.maxv = 0;
+  for (auto& B : pb->mg[0].blocks) A.maxv = std::max(A.maxv, B.nvert);
   A.vert_elem_off = p.vert_elem_off;
   A.vert_elem = p.vert_elem;
   A.elem_verts = p.elem_verts;
@@ -579,34 +349,40 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   A.nu = p.nu;
   A.A = reinterpret_cast<double*>(base + pb->mg[0].off_A);
   launch_p1_assemble(st, A);
+  const int64_t scratch_doubles = pb->n_slots * pb->slot_doubles;
   for (size_t l = 0; l < pb->mg.size(); ++l) {
     MGLevel& M = pb->mg[l];
     MGSetupParams S{};
     S.d = d;
-    for (int a = 0; a < 3; ++a) S.n[a] = M.n[a];
-    S.nvert = M.nvert;
+    S.nblk = (int)M.blocks.size();
+    S.ncont = M.ncont;
+    S.blk = reinterpret_cast<const MGBlockDev*>(base + M.off_blk);
+    S.maxv = M.maxv;
+    S.maxvc = M.maxvc;
+    S.maxnc = M.maxnc;
     S.A = reinterpret_cast<double*>(base + M.off_A);
     S.Dinv = reinterpret_cast<double*>(base + M.off_Dinv);
     S.Dinv32 = reinterpret_cast<float*>(base + M.off_Dinv + (size_t)M.nvert * d * d * 8);
+    S.cmap = p.cmap;
     size_t nA = (size_t)M.nvert * stn * d * d;
-    if (l + 1 < pb->mg.size()) {
-      MGLevel& Mc = pb->mg[l + 1];
-      for (int a = 0; a < 3; ++a) S.nc[a] = Mc.n[a];
-      S.nvert_c = Mc.nvert;
-      S.Ac = reinterpret_cast<double*>(base + Mc.off_A);
+    if (M.ncont > 0) {
+      S.Ac = reinterpret_cast<double*>(base + pb->mg[l + 1].off_A);
       launch_mg_l1(st, S);
       launch_mg_rap(st, S);
-    } else {
-      S.ncd = pb->nc;
-      S.cmap = p.cmap;
-      // dense coarse matrix and its Cholesky workspace borrow the condensation scratch
-      double* Cd = p.cscratch;
-      double* W = p.cscratch + (size_t)pb->nc * pb->nc;
-      if ((int64_t)(2 * pb->nc * pb->nc) > pb->n_slots * pb->slot_doubles) {
+    }
+    // dense coarsest solves, in chunks whose matrices and Cholesky workspaces
+    // fit the condensation scratch
+    for (int j0 = M.ncont; j0 < S.nblk;) {
+      const int64_t base_off = M.blocks[j0].cinv_off;
+      int j1 = j0;
+      while (j1 < S.nblk && 2 * (M.blocks[j1].cinv_off + M.blocks[j1].nc * M.blocks[j1].nc - base_off) <= scratch_doubles)
+        ++j1;
+      if (j1 == j0) {
         set_error("coarsest level too large for the scratch area");
         return MCS_ERR_WORKSPACE;
       }
-      if (pb->nc > 0) launch_coarse(st, S, Cd, W, p.Cinv, status);
+      launch_coarse(st, S, j0 - M.ncont, j1 - j0, base_off, p.cscratch, p.Cinv, status);
+      j0 = j1;
     }
     launch_to_f32(st, reinterpret_cast<double*>(base + M.off_A),
                   reinterpret_cast<float*>(base + M.off_A + nA * 8), (int64_t)nA);
@@ -889,7 +665,9 @@ int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count)
   } table[] = {{"Ad", pb->ne * s.nd * s.nd},   {"H", pb->ne * s.nb * s.nd},
                {"Aoo", pb->ne * s.nb * s.nb},  {"Aooinv", pb->ne * s.nb * s.nb},  {"Dinv", pb->nff * s.nfb * s.nfb},
                {"EF", pb->nff * s.nfb * pb->d * pb->d}, {"Ad32", pb->ne * s.nd * s.nd}, {"H32", pb->ne * s.nb * s.nd},
-               {"detJ", pb->ne},               {"colour_facets", pb->nff},        {"elem_ff", pb->ne * (pb->d + 1)}};
+               {"detJ", pb->ne},               {"colour_facets", pb->nff},        {"elem_ff", pb->ne * (pb->d + 1)},
+               {"W", pb->ne * (pb->d + 1) * pb->d * s.nd}, {"Cinv", pb->ncinv},
+               {"mgA0", pb->mg[0].nvert * (pb->d == 3 ? 27 : 9) * pb->d * pb->d}};
   for (auto& e : table)
     if (!strcmp(e.n, name)) {
       *ptr = ws_ptr<char>(pb, name);

@@ -41,10 +41,44 @@ struct FacetSetupParams {
   int* status;
 };
 
+// One lattice block of a multigrid level (see MGBlock).
+struct MGBlockDev {
+  int n[3];
+  int nc3[3];
+  int prob, pad_;
+  int64_t voff, nvert, cvoff, nvert_c, nc, cmap_off, cinv_off;
+};
+
+// Loads a block descriptor (same address in every lane) and moves its fields
+// to scalar registers, so that the index arithmetic on them stays scalar.
+__device__ inline int uni32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int64_t uni64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline MGBlockDev load_block(const MGBlockDev* p) {
+  MGBlockDev b = *p;
+  for (int a = 0; a < 3; ++a) {
+    b.n[a] = uni32(b.n[a]);
+    b.nc3[a] = uni32(b.nc3[a]);
+  }
+  b.prob = uni32(b.prob);
+  b.voff = uni64(b.voff);
+  b.nvert = uni64(b.nvert);
+  b.cvoff = uni64(b.cvoff);
+  b.nvert_c = uni64(b.nvert_c);
+  b.nc = uni64(b.nc);
+  b.cmap_off = uni64(b.cmap_off);
+  b.cinv_off = uni64(b.cinv_off);
+  return b;
+}
+
 struct P1Params {
   int d;
-  int n[3];
-  int64_t nvert;
+  int nblk;                   // all blocks of the finest level
+  const MGBlockDev* blk;
+  int64_t maxv;
   const int32_t* vert_elem_off;
   const int32_t* vert_elem;
   const int32_t* elem_verts;
@@ -55,11 +89,11 @@ struct P1Params {
 
 struct MGSetupParams {
   int d;
-  int n[3];       // fine intervals
-  int nc[3];      // coarse intervals
-  int64_t nvert, nvert_c, ncd;
-  const double* A;
-  double* Ac;
+  int nblk, ncont;            // blocks of the level; the first ncont continue
+  const MGBlockDev* blk;
+  int64_t maxv, maxvc, maxnc;
+  const double* A;            // this level's stencil
+  double* Ac;                 // next level's stencil
   double* Dinv;
   float* Dinv32;
   const int32_t* cmap;
@@ -77,7 +111,20 @@ struct SolveParams {
   const double* nu;
   const double* rBp;
   const double* rMpinv;
+  // union of several problems: member of each element / free facet and a
+  // per-member activity flag; work of inactive members is skipped.  active ==
+  // nullptr: every member is active.
+  const int32_t* elem_prob;
+  const int32_t* facet_prob;
+  const int32_t* active;
 };
+
+__device__ inline bool elem_off(const SolveParams& P, int64_t e) {
+  return P.active && !P.active[P.elem_prob[e]];
+}
+__device__ inline bool facet_off(const SolveParams& P, int64_t g) {
+  return P.active && !P.active[P.facet_prob[g]];
+}
 
 template <typename R>
 struct OpPtrs {
@@ -85,11 +132,44 @@ struct OpPtrs {
 };
 
 struct MGLevelDev {
-  int n[3];
-  int64_t nvert;
+  int nblk, ncont;            // blocks of the level; the first ncont continue
+  const MGBlockDev* blk;
+  int64_t maxv, maxvc, maxnc;
   const void* A;      // stencil (R)
   const void* Dinv;   // (R)
   void *x, *b, *r;    // lattice vectors (R)
+  const int32_t* active;  // per-member activity (nullptr: all active)
+};
+
+// ---------------------------------------------------------------------------
+// Batched solves: the global vectors of a union are cut into tiles that never
+// straddle two member problems (per member: its bubble, facet and pressure
+// sections, in that order), so per-member reductions are sums over the
+// member's own tiles in a fixed order, independent of the other members.
+// ---------------------------------------------------------------------------
+struct SegTile {
+  int32_t prob, len;
+  int64_t start;
+};
+
+// Per-member MINRES scalars, stored field-major: st[field * nprob + member].
+enum {
+  ST_BETA = 0, ST_OLDB, ST_DBAR, ST_EPS, ST_PHIBAR, ST_CS, ST_SN, ST_BETA1, ST_STOP, ST_ALPHA, ST_BB,
+  ST_CW0, ST_CW1, ST_CW2, ST_PHI, ST_REL, ST_TOL, ST_ABS, ST_SB1, ST_RN, ST_NFIELD
+};
+
+struct SegDev {
+  int nprob;
+  int64_t ntiles;
+  const SegTile* tiles;
+  const int32_t* tile_off;   // [nprob+1]
+  double* partial;           // [ntiles]
+  double* st;                // [ST_NFIELD][nprob]
+  int32_t* active;           // mask used by this operation
+  int32_t* its;              // iterations of the current MINRES
+  int32_t* status;           // mcs_status per member
+  int32_t* done;             // set when a member leaves the iteration
+  int maxit;
 };
 
 }  // namespace mcs

@@ -325,7 +325,9 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
         for (int i = 0; i < 4; ++i)
           for (int j = 0; j < 4; ++j) {
             int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
-            if (r < s.nA && c < s.nA) {
+            // upper triangle only (in a diagonal block the (c, r) thread would
+            // write the mirrored pair too): one writer per entry pair
+            if (r < s.nA && c < s.nA && r <= c) {
               double v = cf * (acc[i][j] - acc2[i][j]);
               // A^div on velocity rows
               int ir = -1, ic = -1;
@@ -542,14 +544,17 @@ __device__ inline bool lat_interior(const int c[3], const int* n, int d) {
 
 // A-bar stencil on the finest level: vertex-centric sum over incident elements
 // of nu_T int eps(lambda_v e_c) : eps(lambda_w e_e).
+// One lattice block per blockIdx.y (all blocks of the finest level).
 __global__ void k_p1_assemble(P1Params P) {
   const int d = P.d, nv = d + 1, st = d == 3 ? 27 : 9, dd = d * d;
-  int N[3] = {P.n[0] + 1, P.n[1] + 1, P.n[2] + 1};
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < P.nvert; v += (int64_t)gridDim.x * blockDim.x) {
+  const MGBlockDev B = load_block(P.blk + (blockIdx.y));
+  int N[3] = {B.n[0] + 1, B.n[1] + 1, B.n[2] + 1};
+  for (int64_t lv_ = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; lv_ < B.nvert; lv_ += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = B.voff + lv_;
     double* Av = P.A + (size_t)v * st * dd;
     for (int i = 0; i < st * dd; ++i) Av[i] = 0.0;
     int cv[3];
-    lat_coords(v, N, cv);
+    lat_coords(lv_, N, cv);
     for (int p = P.vert_elem_off[v]; p < P.vert_elem_off[v + 1]; ++p) {
       int64_t e = P.vert_elem[p];
       // geometry
@@ -583,7 +588,7 @@ __global__ void k_p1_assemble(P1Params P) {
       double w = P.nu[e] * vol;
       for (int j = 0; j < nv; ++j) {
         int cw[3];
-        lat_coords(P.elem_verts[e * nv + j], N, cw);
+        lat_coords(P.elem_verts[e * nv + j] - B.voff, N, cw);
         int o = 0, pw = 1;
         for (int a = 0; a < d; ++a) { o += (cw[a] - cv[a] + 1) * pw; pw *= 3; }
         double gg = 0.0;
@@ -596,15 +601,18 @@ __global__ void k_p1_assemble(P1Params P) {
   }
 }
 
-// l1 block-Jacobi inverse: D_v = A_vv + diag(sum over free w != v of |A_vw| row sums).
+// l1 block-Jacobi inverse: D_v = A_vv + diag(sum over free w != v of |A_vw| row sums),
+// on the continuing blocks of a level (one block per blockIdx.y).
 __global__ void k_mg_l1(MGSetupParams P) {
   const int d = P.d, st = d == 3 ? 27 : 9, dd = d * d;
-  int N[3] = {P.n[0] + 1, P.n[1] + 1, P.n[2] + 1};
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < P.nvert; v += (int64_t)gridDim.x * blockDim.x) {
+  const MGBlockDev B = load_block(P.blk + (blockIdx.y));
+  int N[3] = {B.n[0] + 1, B.n[1] + 1, B.n[2] + 1};
+  for (int64_t lv_ = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; lv_ < B.nvert; lv_ += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = B.voff + lv_;
     int cv[3];
-    lat_coords(v, N, cv);
+    lat_coords(lv_, N, cv);
     double Dm[3][3] = {};
-    if (lat_interior(cv, P.n, d)) {
+    if (lat_interior(cv, B.n, d)) {
       const double* Av = P.A + (size_t)v * st * dd;
       int center = d == 3 ? 13 : 4;
       for (int c = 0; c < d; ++c)
@@ -613,7 +621,7 @@ __global__ void k_mg_l1(MGSetupParams P) {
         if (o == center) continue;
         int cw[3] = {cv[0] + o % 3 - 1, cv[1] + (o / 3) % 3 - 1, cv[2] + (o / 9) - 1};
         if (d == 2) cw[2] = 0;
-        if (!lat_interior(cw, P.n, d)) continue;
+        if (!lat_interior(cw, B.n, d)) continue;
         for (int c = 0; c < d; ++c) {
           double sacc = 0.0;
           for (int e = 0; e < d; ++e) sacc += fabs(Av[o * dd + c * d + e]);
@@ -660,42 +668,49 @@ __device__ inline double w1d(int i, int I, int n) {
   return 0.0;
 }
 
-// Galerkin coarse operator A_c = P^T A P restricted to interior vertices.
-__global__ void k_mg_rap(MGSetupParams P) {
+// Galerkin coarse operator A_c = P^T A P restricted to interior vertices, on
+// the continuing blocks of a level (one block per blockIdx.y).  One 32-lane
+// group per coarse vertex; lane co forms the coupling to the coarse
+// neighbour co:  A_c[I][co] = sum_{i, j} P(i, I) A[i][j] P(j, I + co).
+__global__ void __launch_bounds__(256) k_mg_rap(MGSetupParams P) {
   const int d = P.d, st = d == 3 ? 27 : 9, dd = d * d;
-  int Nf[3] = {P.n[0] + 1, P.n[1] + 1, P.n[2] + 1};
-  int Nc[3] = {P.nc[0] + 1, P.nc[1] + 1, P.nc[2] + 1};
-  for (int64_t V = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; V < P.nvert_c; V += (int64_t)gridDim.x * blockDim.x) {
-    double* Ac = P.Ac + (size_t)V * st * dd;
-    for (int i = 0; i < st * dd; ++i) Ac[i] = 0.0;
+  const MGBlockDev B = load_block(P.blk + (blockIdx.y));
+  int Nf[3] = {B.n[0] + 1, B.n[1] + 1, B.n[2] + 1};
+  int Nc[3] = {B.nc3[0] + 1, B.nc3[1] + 1, B.nc3[2] + 1};
+  const int co = threadIdx.x & 31;
+  const int64_t gpb = blockDim.x >> 5;
+  for (int64_t V = blockIdx.x * gpb + (threadIdx.x >> 5); V < B.nvert_c; V += (int64_t)gridDim.x * gpb) {
+    if (co >= st) continue;
+    double acc[9];
+    for (int c = 0; c < dd; ++c) acc[c] = 0.0;
     int CI[3];
     lat_coords(V, Nc, CI);
-    if (!lat_interior(CI, P.nc, d)) continue;
-    int base[3] = {coarse_pos(CI[0], P.n[0]), coarse_pos(CI[1], P.n[1]), d == 3 ? coarse_pos(CI[2], P.n[2]) : 0};
-    for (int fo = 0; fo < st; ++fo) {
-      int fi[3] = {base[0] + fo % 3 - 1, base[1] + (fo / 3) % 3 - 1, base[2] + fo / 9 - 1};
-      if (d == 2) fi[2] = 0;
-      if (!lat_interior(fi, P.n, d)) continue;
-      double wI = 1.0;
-      for (int a = 0; a < d; ++a) wI *= w1d(fi[a], CI[a], P.n[a]);
-      if (wI == 0.0) continue;
-      int64_t fiv = fi[0] + (int64_t)Nf[0] * (fi[1] + (int64_t)Nf[1] * fi[2]);
-      const double* Af = P.A + (size_t)fiv * st * dd;
-      for (int so = 0; so < st; ++so) {
-        int fj[3] = {fi[0] + so % 3 - 1, fi[1] + (so / 3) % 3 - 1, fi[2] + so / 9 - 1};
-        if (d == 2) fj[2] = 0;
-        if (!lat_interior(fj, P.n, d)) continue;
-        for (int co = 0; co < st; ++co) {
-          int CJ[3] = {CI[0] + co % 3 - 1, CI[1] + (co / 3) % 3 - 1, CI[2] + co / 9 - 1};
-          if (d == 2) CJ[2] = 0;
-          if (!lat_interior(CJ, P.nc, d)) continue;
+    int CJ[3] = {CI[0] + co % 3 - 1, CI[1] + (co / 3) % 3 - 1, CI[2] + co / 9 - 1};
+    if (d == 2) CJ[2] = 0;
+    if (lat_interior(CI, B.nc3, d) && lat_interior(CJ, B.nc3, d)) {
+      int base[3] = {coarse_pos(CI[0], B.n[0]), coarse_pos(CI[1], B.n[1]), d == 3 ? coarse_pos(CI[2], B.n[2]) : 0};
+      for (int fo = 0; fo < st; ++fo) {
+        int fi[3] = {base[0] + fo % 3 - 1, base[1] + (fo / 3) % 3 - 1, base[2] + fo / 9 - 1};
+        if (d == 2) fi[2] = 0;
+        if (!lat_interior(fi, B.n, d)) continue;
+        double wI = 1.0;
+        for (int a = 0; a < d; ++a) wI *= w1d(fi[a], CI[a], B.n[a]);
+        if (wI == 0.0) continue;
+        const int64_t fiv = B.voff + fi[0] + (int64_t)Nf[0] * (fi[1] + (int64_t)Nf[1] * fi[2]);
+        const double* Af = P.A + (size_t)fiv * st * dd;
+        for (int so = 0; so < st; ++so) {
+          int fj[3] = {fi[0] + so % 3 - 1, fi[1] + (so / 3) % 3 - 1, fi[2] + so / 9 - 1};
+          if (d == 2) fj[2] = 0;
+          if (!lat_interior(fj, B.n, d)) continue;
           double wJ = 1.0;
-          for (int a = 0; a < d; ++a) wJ *= w1d(fj[a], CJ[a], P.n[a]);
+          for (int a = 0; a < d; ++a) wJ *= w1d(fj[a], CJ[a], B.n[a]);
           if (wJ == 0.0) continue;
-          for (int c = 0; c < dd; ++c) Ac[co * dd + c] += wI * wJ * Af[so * dd + c];
+          for (int c = 0; c < dd; ++c) acc[c] += wI * wJ * Af[so * dd + c];
         }
       }
     }
+    double* Ac = P.Ac + (size_t)(B.cvoff + V) * st * dd + co * dd;
+    for (int c = 0; c < dd; ++c) Ac[c] = acc[c];
   }
 }
 
@@ -703,15 +718,21 @@ __global__ void k_to_f32(const double* a, float* b, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = (float)a[i];
 }
 
-// Coarsest level: dense matrix over the free dofs, then its inverse (one block).
-__global__ void k_coarse_gather(MGSetupParams P, double* Cd) {
+// Coarsest levels: dense matrix over the free dofs of each coarsest block
+// (blocks jb .. of the level, one per blockIdx.y), then its inverse (one
+// workgroup per block).  Cd/W of block j start at scratch + 2 (cinv_off_j -
+// base).
+__global__ void k_coarse_gather(MGSetupParams P, int jb, int64_t base, double* scratch) {
   const int d = P.d, st = d == 3 ? 27 : 9, dd = d * d;
-  int N[3] = {P.n[0] + 1, P.n[1] + 1, P.n[2] + 1};
-  int64_t nc = P.ncd;
+  const MGBlockDev B = load_block(P.blk + (P.ncont + jb + blockIdx.y));
+  int N[3] = {B.n[0] + 1, B.n[1] + 1, B.n[2] + 1};
+  const int64_t nc = B.nc;
+  const int32_t* cmap = P.cmap + B.cmap_off;
+  double* Cd = scratch + 2 * (B.cinv_off - base);
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < nc * nc; idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t i = idx / nc, j = idx % nc;
-    int64_t vi = P.cmap[i] / d, vj = P.cmap[j] / d;
-    int ci = P.cmap[i] % d, cj = P.cmap[j] % d;
+    int64_t vi = cmap[i] / d, vj = cmap[j] / d;
+    int ci = cmap[i] % d, cj = cmap[j] % d;
     int a[3], b[3];
     lat_coords(vi, N, a);
     lat_coords(vj, N, b);
@@ -724,13 +745,19 @@ __global__ void k_coarse_gather(MGSetupParams P, double* Cd) {
       o += (df + 1) * pw;
       pw *= 3;
     }
-    if (near) v = P.A[(size_t)vi * st * dd + o * dd + ci * d + cj];
+    if (near) v = P.A[(size_t)(B.voff + vi) * st * dd + o * dd + ci * d + cj];
     Cd[idx] = v;
   }
 }
 
-__global__ void __launch_bounds__(1024) k_coarse_invert(double* C, double* W, double* Cinv, int64_t n, int* status) {
+__global__ void __launch_bounds__(1024) k_coarse_invert(MGSetupParams P, int jb, int64_t base, double* scratch,
+                                                         double* Cinv_all, int* status) {
   // Cholesky in place (lower), L^{-1} into W, Cinv = L^{-T} L^{-1}.
+  const MGBlockDev B = load_block(P.blk + (P.ncont + jb + blockIdx.x));
+  const int64_t n = B.nc;
+  double* C = scratch + 2 * (B.cinv_off - base);
+  double* W = C + n * n;
+  double* Cinv = Cinv_all + B.cinv_off;
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
@@ -869,18 +896,28 @@ void launch_condense(hipStream_t st, const CondParams& P, int nslots) {
 void launch_facet_setup(hipStream_t st, const FacetSetupParams& P) {
   hipLaunchKernelGGL(k_facet_setup, dim3((int)std::min<int64_t>(P.nff, 1 << 20)), dim3(256), 0, st, P);
 }
+static unsigned ygrid(int64_t n, int per, int cap = 4096) {
+  int64_t g = (n + per - 1) / per;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
 void launch_p1_assemble(hipStream_t st, const P1Params& P) {
-  hipLaunchKernelGGL(k_p1_assemble, dim3(sgrid(P.nvert)), dim3(256), 0, st, P);
+  if (P.nblk == 0) return;
+  hipLaunchKernelGGL(k_p1_assemble, dim3(ygrid(P.maxv, 256), P.nblk), dim3(256), 0, st, P);
 }
 void launch_mg_l1(hipStream_t st, const MGSetupParams& P) {
-  hipLaunchKernelGGL(k_mg_l1, dim3(sgrid(P.nvert)), dim3(256), 0, st, P);
+  if (P.ncont == 0) return;
+  hipLaunchKernelGGL(k_mg_l1, dim3(ygrid(P.maxv, 256), P.ncont), dim3(256), 0, st, P);
 }
 void launch_mg_rap(hipStream_t st, const MGSetupParams& P) {
-  hipLaunchKernelGGL(k_mg_rap, dim3(sgrid(P.nvert_c)), dim3(256), 0, st, P);
+  if (P.ncont == 0) return;
+  hipLaunchKernelGGL(k_mg_rap, dim3(ygrid(P.maxvc, 8), P.ncont), dim3(256), 0, st, P);
 }
-void launch_coarse(hipStream_t st, const MGSetupParams& P, double* Cd, double* W, double* Cinv, int* status) {
-  hipLaunchKernelGGL(k_coarse_gather, dim3(sgrid(P.ncd * P.ncd)), dim3(256), 0, st, P, Cd);
-  hipLaunchKernelGGL(k_coarse_invert, dim3(1), dim3(1024), 0, st, Cd, W, Cinv, P.ncd, status);
+void launch_coarse(hipStream_t st, const MGSetupParams& P, int jb, int nj, int64_t base, double* scratch,
+                   double* Cinv, int* status) {
+  if (nj == 0) return;
+  hipLaunchKernelGGL(k_coarse_gather, dim3(ygrid(P.maxnc * P.maxnc, 256, 1024), nj), dim3(256), 0, st, P, jb, base,
+                     scratch);
+  hipLaunchKernelGGL(k_coarse_invert, dim3(nj), dim3(1024), 0, st, P, jb, base, scratch, Cinv, status);
 }
 void launch_to_f32(hipStream_t st, const double* a, float* b, int64_t n) {
   hipLaunchKernelGGL(k_to_f32, dim3(sgrid(n)), dim3(256), 0, st, a, b, n);

@@ -108,6 +108,7 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, OpPtrs<R> O, 
   const int tA = ((nd + 63) >> 6) << 6;          // threads of the A^d product
   const bool overlap = tA < 256;
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
+    if (elem_off(P, e)) continue;
     const double det = P.detJ[e];
     const double sb = -fabs(det), sf = det > 0 ? -1.0 : 1.0;
     gather_elem_d(P, x, e, xd);
@@ -187,6 +188,7 @@ __global__ void k_facet_sum(SolveParams P, const R* __restrict__ escr, const R* 
   const int64_t n = P.nff * s.nfb;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t g = idx / s.nfb;
+    if (facet_off(P, g)) continue;
     int q = (int)(idx % s.nfb);
     int64_t e1 = P.facet_el[2 * g], e2 = P.facet_el[2 * g + 1];
     int s1 = P.facet_slot[2 * g], s2 = P.facet_slot[2 * g + 1];
@@ -208,6 +210,7 @@ __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, con
   const int tid = threadIdx.x;
   const int ob = (nd + nb <= 256) ? nd : 0;
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
+    if (elem_off(P, e)) continue;
     if (tid < nb) ro[tid] = r[e * nb + tid];
     __syncthreads();
     if (tid < nd) {
@@ -237,6 +240,7 @@ __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, co
   const int nb = s.nb, nd = s.nd;
   __shared__ R td[MAXND];
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
+    if (elem_off(P, e)) continue;
     gather_elem_d(P, t, e, td);
     __syncthreads();
     rows_times<8>(O.H + (size_t)e * nb * nd, nb, nd, td, 0, 256,
@@ -265,6 +269,7 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
   const bool is_row = tid < 2 * nd;
   for (int64_t ci = c0 + blockIdx.x; ci < c1; ci += gridDim.x) {
     const int64_t g = P.colour_facets[ci];
+    if (facet_off(P, g)) continue;
     int64_t e = 0;
     R a[NFB];
     R yv = R(0);
@@ -314,6 +319,7 @@ __global__ void k_elem_ycorr(SolveParams P, const R* __restrict__ W, const int32
   const int64_t n = P.ne * nd;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = idx / nd;
+    if (elem_off(P, e)) continue;
     const int t = (int)(idx % nd);
     const R* We = W + (size_t)e * nvd * nd + t;
     R acc = R(0);
@@ -334,6 +340,7 @@ __global__ void k_edt_facet(SolveParams P, OpPtrs<R> O, const R* __restrict__ r,
   const int64_t n = P.nff * dd;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t g = idx / dd;
+    if (facet_off(P, g)) continue;
     int t = (int)(idx % dd);
     const R* E = O.EF + (size_t)g * s.nfb * dd + t;
     const R* rf = r + P.off_f + g * s.nfb;
@@ -373,6 +380,7 @@ __global__ void k_ed_facet(SolveParams P, OpPtrs<R> O, const int32_t* __restrict
   const int64_t n = P.nff * s.nfb;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t g = idx / s.nfb;
+    if (facet_off(P, g)) continue;
     int q = (int)(idx % s.nfb);
     const R* E = O.EF + ((size_t)g * s.nfb + q) * dd;
     R acc = 0;
@@ -400,11 +408,15 @@ __device__ inline bool mg_interior(const int c[3], const int* n, int d) {
   return true;
 }
 
-// mode 0: x = Dinv b;  mode 1: r = b - A x;  mode 2: x += Dinv (b - A x).
-// One 32-lane group per vertex, one stencil tap per lane.
+// Multigrid kernels run over the lattice blocks of a level, one block per
+// blockIdx.y; vertex indices are block-local plus the block's offset.
+// mode 0: x = Dinv b;  mode 1: r = b - A x;  mode 2: x += Dinv (b - A x), on
+// the continuing blocks.  One 32-lane group per vertex, one stencil tap per lane.
 template <typename R>
 __global__ void __launch_bounds__(256) k_mg_point(int d, MGLevelDev L, int mode) {
   const int st = d == 3 ? 27 : 9, dd = d * d;
+  const MGBlockDev B = load_block(L.blk + (blockIdx.y));
+  if (L.active && !L.active[B.prob]) return;
   const R* A = (const R*)L.A;
   const R* Di = (const R*)L.Dinv;
   R* x = (R*)L.x;
@@ -412,16 +424,17 @@ __global__ void __launch_bounds__(256) k_mg_point(int d, MGLevelDev L, int mode)
   R* r = (R*)L.r;
   const int lane = threadIdx.x & 31;
   const int64_t gpb = blockDim.x >> 5;
-  for (int64_t v = blockIdx.x * gpb + (threadIdx.x >> 5); v < L.nvert; v += (int64_t)gridDim.x * gpb) {
+  for (int64_t lv_ = blockIdx.x * gpb + (threadIdx.x >> 5); lv_ < B.nvert; lv_ += (int64_t)gridDim.x * gpb) {
+    const int64_t v = B.voff + lv_;
     int c[3];
-    mg_coords(v, L.n, c);
-    const bool inner = mg_interior(c, L.n, d);
+    mg_coords(lv_, B.n, c);
+    const bool inner = mg_interior(c, B.n, d);
     R part[3] = {R(0), R(0), R(0)};
     if (inner && mode != 0 && lane < st) {
       const int o = lane;
       int w[3] = {c[0] + o % 3 - 1, c[1] + (o / 3) % 3 - 1, d == 3 ? c[2] + o / 9 - 1 : 0};
-      if (mg_interior(w, L.n, d)) {
-        const int64_t wi = w[0] + (int64_t)(L.n[0] + 1) * (w[1] + (int64_t)(L.n[1] + 1) * w[2]);
+      if (mg_interior(w, B.n, d)) {
+        const int64_t wi = B.voff + w[0] + (int64_t)(B.n[0] + 1) * (w[1] + (int64_t)(B.n[1] + 1) * w[2]);
         const R* Av = A + ((size_t)v * st + o) * dd;
         for (int k = 0; k < d; ++k)
           for (int m = 0; m < d; ++m) part[k] += Av[k * d + m] * x[wi * d + m];
@@ -459,86 +472,98 @@ __device__ inline double mg_w(int i, int I, int n) {
   return 0.0;
 }
 
-// b_c = P^T r_f (interior coarse vertices); one 32-lane group per coarse vertex.
+// b_c = P^T r_f (interior coarse vertices of each continuing block); one
+// 32-lane group per coarse vertex.
 template <typename R>
 __global__ void __launch_bounds__(256) k_mg_restrict(int d, MGLevelDev F, MGLevelDev C) {
   const R* r = (const R*)F.r;
   R* bc = (R*)C.b;
   const int st = d == 3 ? 27 : 9;
+  const MGBlockDev B = load_block(F.blk + (blockIdx.y));
+  if (F.active && !F.active[B.prob]) return;
   const int lane = threadIdx.x & 31;
   const int64_t gpb = blockDim.x >> 5;
-  for (int64_t V = blockIdx.x * gpb + (threadIdx.x >> 5); V < C.nvert; V += (int64_t)gridDim.x * gpb) {
+  for (int64_t V = blockIdx.x * gpb + (threadIdx.x >> 5); V < B.nvert_c; V += (int64_t)gridDim.x * gpb) {
     int CI[3];
-    mg_coords(V, C.n, CI);
-    const bool inner = mg_interior(CI, C.n, d);
+    mg_coords(V, B.nc3, CI);
+    const bool inner = mg_interior(CI, B.nc3, d);
     R acc[3] = {R(0), R(0), R(0)};
     if (inner && lane < st) {
       const int o = lane;
-      int base[3] = {mg_cpos(CI[0], F.n[0]), mg_cpos(CI[1], F.n[1]), d == 3 ? mg_cpos(CI[2], F.n[2]) : 0};
+      int base[3] = {mg_cpos(CI[0], B.n[0]), mg_cpos(CI[1], B.n[1]), d == 3 ? mg_cpos(CI[2], B.n[2]) : 0};
       int fi[3] = {base[0] + o % 3 - 1, base[1] + (o / 3) % 3 - 1, d == 3 ? base[2] + o / 9 - 1 : 0};
-      if (mg_interior(fi, F.n, d)) {
+      if (mg_interior(fi, B.n, d)) {
         double w = 1.0;
-        for (int a = 0; a < d; ++a) w *= mg_w(fi[a], CI[a], F.n[a]);
+        for (int a = 0; a < d; ++a) w *= mg_w(fi[a], CI[a], B.n[a]);
         if (w != 0.0) {
-          const int64_t fv = fi[0] + (int64_t)(F.n[0] + 1) * (fi[1] + (int64_t)(F.n[1] + 1) * fi[2]);
+          const int64_t fv = B.voff + fi[0] + (int64_t)(B.n[0] + 1) * (fi[1] + (int64_t)(B.n[1] + 1) * fi[2]);
           for (int k = 0; k < d; ++k) acc[k] = (R)w * r[fv * d + k];
         }
       }
     }
     for (int k = 0; k < d; ++k) acc[k] = group32_sum(acc[k]);
     if (lane == 0)
-      for (int k = 0; k < d; ++k) bc[V * d + k] = inner ? acc[k] : R(0);
+      for (int k = 0; k < d; ++k) bc[(B.cvoff + V) * d + k] = inner ? acc[k] : R(0);
   }
 }
 
-// x_f += P x_c (interior fine vertices); one 32-lane group per fine vertex, one
-// candidate coarse vertex per lane.
+// x_f += P x_c (interior fine vertices of each continuing block); one 32-lane
+// group per fine vertex, one candidate coarse vertex per lane.
 template <typename R>
 __global__ void __launch_bounds__(256) k_mg_prolong(int d, MGLevelDev F, MGLevelDev C) {
   R* x = (R*)F.x;
   const R* xc = (const R*)C.x;
   const int st = d == 3 ? 27 : 9;
+  const MGBlockDev B = load_block(F.blk + (blockIdx.y));
+  if (F.active && !F.active[B.prob]) return;
   const int lane = threadIdx.x & 31;
   const int64_t gpb = blockDim.x >> 5;
-  for (int64_t v = blockIdx.x * gpb + (threadIdx.x >> 5); v < F.nvert; v += (int64_t)gridDim.x * gpb) {
+  for (int64_t lv_ = blockIdx.x * gpb + (threadIdx.x >> 5); lv_ < B.nvert; lv_ += (int64_t)gridDim.x * gpb) {
     int fi[3];
-    mg_coords(v, F.n, fi);
-    const bool inner = mg_interior(fi, F.n, d);
+    mg_coords(lv_, B.n, fi);
+    const bool inner = mg_interior(fi, B.n, d);
     R acc[3] = {R(0), R(0), R(0)};
     if (inner && lane < st) {
       const int o = lane;
       int CI[3] = {fi[0] / 2 - 1 + o % 3, fi[1] / 2 - 1 + (o / 3) % 3, d == 3 ? fi[2] / 2 - 1 + o / 9 : 0};
       bool ok = true;
       for (int a = 0; a < d; ++a)
-        if (CI[a] < 0 || CI[a] > C.n[a]) ok = false;
-      if (ok && mg_interior(CI, C.n, d)) {
+        if (CI[a] < 0 || CI[a] > B.nc3[a]) ok = false;
+      if (ok && mg_interior(CI, B.nc3, d)) {
         double w = 1.0;
-        for (int a = 0; a < d; ++a) w *= mg_w(fi[a], CI[a], F.n[a]);
+        for (int a = 0; a < d; ++a) w *= mg_w(fi[a], CI[a], B.n[a]);
         if (w != 0.0) {
-          const int64_t cv = CI[0] + (int64_t)(C.n[0] + 1) * (CI[1] + (int64_t)(C.n[1] + 1) * CI[2]);
+          const int64_t cv = B.cvoff + CI[0] + (int64_t)(B.nc3[0] + 1) * (CI[1] + (int64_t)(B.nc3[1] + 1) * CI[2]);
           for (int k = 0; k < d; ++k) acc[k] = (R)w * xc[cv * d + k];
         }
       }
     }
     for (int k = 0; k < d; ++k) acc[k] = group32_sum(acc[k]);
     if (lane == 0 && inner)
-      for (int k = 0; k < d; ++k) x[v * d + k] += acc[k];
+      for (int k = 0; k < d; ++k) x[(B.voff + lv_) * d + k] += acc[k];
   }
 }
 
-// Coarsest level: x = C^{-1} b over the free dofs (FP64 accumulation), one
-// wave per row of the (symmetric) inverse.
+// Coarsest blocks of a level: x = C^{-1} b over each block's free dofs (FP64
+// accumulation), one wave per row of the (symmetric) inverse; blockIdx.y runs
+// over the level's coarsest blocks.
 template <typename R>
-__global__ void k_mg_coarse(int64_t nc, const double* __restrict__ Cinv, const int32_t* __restrict__ cmap, MGLevelDev L) {
+__global__ void k_mg_coarse(const double* __restrict__ Cinv_all, const int32_t* __restrict__ cmap_all, int d,
+                            MGLevelDev L) {
   const R* b = (const R*)L.b;
   R* x = (R*)L.x;
+  const MGBlockDev B = load_block(L.blk + (L.ncont + blockIdx.y));
+  if (L.active && !L.active[B.prob]) return;
+  const int64_t nc = B.nc, o = B.voff * d;
+  const double* Cinv = Cinv_all + B.cinv_off;
+  const int32_t* cmap = cmap_all + B.cmap_off;
   const int lane = threadIdx.x & 63;
   const int64_t wpb = blockDim.x >> 6;
   for (int64_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < nc; i += (int64_t)gridDim.x * wpb) {
     double acc = 0.0;
-    for (int64_t j = lane; j < nc; j += 64) acc += Cinv[i * nc + j] * (double)b[cmap[j]];
+    for (int64_t j = lane; j < nc; j += 64) acc += Cinv[i * nc + j] * (double)b[o + cmap[j]];
     acc = wave_sum(acc);
-    if (lane == 0) x[cmap[i]] = (R)acc;
+    if (lane == 0) x[o + cmap[i]] = (R)acc;
   }
 }
 
@@ -558,6 +583,7 @@ __global__ void __launch_bounds__(256) k_elem_press(SolveParams P, const R* __re
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   build_rowmap(s, rmap);
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
+    if (elem_off(P, e)) continue;
     const double det = P.detJ[e];
     if (with_B) {
       const double sb = -fabs(det), sf = det > 0 ? -1.0 : 1.0;
@@ -731,21 +757,30 @@ void launch_ed(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const i
   hipLaunchKernelGGL(k_ed_facet<R>, dim3(grid_for(P.nff * P.s.nfb)), dim3(256), 0, st, P, O, facet_vfree, free_to_lat,
                      x0, y, add, compact);
 }
+static unsigned mg_grid(int64_t n, int per) {
+  int64_t g = (n + per - 1) / per;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
 template <typename R>
 void launch_mg_point(hipStream_t st, int d, const MGLevelDev& L, int mode) {
-  hipLaunchKernelGGL(k_mg_point<R>, dim3(grid_for(L.nvert, 8)), dim3(256), 0, st, d, L, mode);
+  if (L.ncont == 0) return;
+  hipLaunchKernelGGL(k_mg_point<R>, dim3(mg_grid(L.maxv, 8), L.ncont), dim3(256), 0, st, d, L, mode);
 }
 template <typename R>
 void launch_mg_restrict(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C) {
-  hipLaunchKernelGGL(k_mg_restrict<R>, dim3(grid_for(C.nvert, 8)), dim3(256), 0, st, d, F, C);
+  if (F.ncont == 0) return;
+  hipLaunchKernelGGL(k_mg_restrict<R>, dim3(mg_grid(F.maxvc, 8), F.ncont), dim3(256), 0, st, d, F, C);
 }
 template <typename R>
 void launch_mg_prolong(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C) {
-  hipLaunchKernelGGL(k_mg_prolong<R>, dim3(grid_for(F.nvert, 8)), dim3(256), 0, st, d, F, C);
+  if (F.ncont == 0) return;
+  hipLaunchKernelGGL(k_mg_prolong<R>, dim3(mg_grid(F.maxv, 8), F.ncont), dim3(256), 0, st, d, F, C);
 }
 template <typename R>
-void launch_mg_coarse(hipStream_t st, int64_t nc, const double* Cinv, const int32_t* cmap, const MGLevelDev& L) {
-  hipLaunchKernelGGL(k_mg_coarse<R>, dim3(grid_for(nc, 4)), dim3(256), 0, st, nc, Cinv, cmap, L);
+void launch_mg_coarse(hipStream_t st, const double* Cinv, const int32_t* cmap, int d, const MGLevelDev& L) {
+  const int nco = L.nblk - L.ncont;
+  if (nco == 0) return;
+  hipLaunchKernelGGL(k_mg_coarse<R>, dim3(mg_grid(L.maxnc, 4), nco), dim3(256), 0, st, Cinv, cmap, d, L);
 }
 template <typename R>
 void launch_elem_press(hipStream_t st, const SolveParams& P, const R* a, const R* r, R* y, int with_B) {
@@ -804,7 +839,7 @@ void launch_scale_convert(hipStream_t st, int64_t n, double a, const A* x, B* y,
   template void launch_mg_point<R>(hipStream_t, int, const MGLevelDev&, int);                                  \
   template void launch_mg_restrict<R>(hipStream_t, int, const MGLevelDev&, const MGLevelDev&);                 \
   template void launch_mg_prolong<R>(hipStream_t, int, const MGLevelDev&, const MGLevelDev&);                  \
-  template void launch_mg_coarse<R>(hipStream_t, int64_t, const double*, const int32_t*, const MGLevelDev&);   \
+  template void launch_mg_coarse<R>(hipStream_t, const double*, const int32_t*, int, const MGLevelDev&);       \
   template void launch_elem_press<R>(hipStream_t, const SolveParams&, const R*, const R*, R*, int);            \
   template void launch_axpby<R>(hipStream_t, int64_t, double, const R*, double, R*);                           \
   template void launch_fill<R>(hipStream_t, int64_t, R, R*);                                                   \

@@ -31,7 +31,7 @@ void launch_mg_restrict(hipStream_t st, int d, const MGLevelDev& F, const MGLeve
 template <typename R>
 void launch_mg_prolong(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C);
 template <typename R>
-void launch_mg_coarse(hipStream_t st, int64_t nc, const double* Cinv, const int32_t* cmap, const MGLevelDev& L);
+void launch_mg_coarse(hipStream_t st, const double* Cinv, const int32_t* cmap, int d, const MGLevelDev& L);
 template <typename R>
 void launch_elem_press(hipStream_t st, const SolveParams& P, const R* a, const R* r, R* y, int with_B);
 template <typename R>
@@ -61,12 +61,31 @@ void launch_wsetup(hipStream_t st, const FacetSetupParams& P, const int32_t* ele
 void launch_p1_assemble(hipStream_t st, const P1Params& P);
 void launch_mg_l1(hipStream_t st, const MGSetupParams& P);
 void launch_mg_rap(hipStream_t st, const MGSetupParams& P);
-void launch_coarse(hipStream_t st, const MGSetupParams& P, double* Cd, double* W, double* Cinv, int* status);
+void launch_coarse(hipStream_t st, const MGSetupParams& P, int jb, int nj, int64_t base, double* scratch,
+                   double* Cinv, int* status);
 void launch_to_f32(hipStream_t st, const double* a, float* b, int64_t n);
 void launch_load(hipStream_t st, const CondParams& C, const SolveParams& P, const int32_t* elem_perm,
                  const int32_t* latmap, const double* rRf, const double* f, double* b, double* escr);
 void launch_check_nu(hipStream_t st, const double* nu, int64_t n, int* status);
 void launch_pressure_mean(hipStream_t st, const SolveParams& P, const double* pmom, const double* pconst, double* x,
                           double* red);
+
+// batched MINRES (kernels_batch.hip)
+template <typename R>
+void launch_seg_dot(hipStream_t st, const SegDev& S, const R* a, const R* b, int field);
+template <typename R>
+void launch_seg_scale(hipStream_t st, const SegDev& S, const R* src, R* dst, int field, int inv);
+template <typename R>
+void launch_seg_axpy_ratio(hipStream_t st, const SegDev& S, const R* x, R* y, int num, int den, int min_its);
+template <typename R>
+void launch_seg_w(hipStream_t st, const SegDev& S, const R* v, R* w1, const R* w2, R* x);
+template <typename A, typename B>
+void launch_seg_scale_convert(hipStream_t st, const SegDev& S, const A* x, B* y, int field, int inv, int add);
+void launch_seg_sub(hipStream_t st, const SegDev& S, const double* a, const double* b, double* y);
+void launch_mr_init(hipStream_t st, const SegDev& S);
+void launch_mr_update(hipStream_t st, const SegDev& S);
+void launch_mr_retire(hipStream_t st, const SegDev& S);
+void launch_batch_pmean(hipStream_t st, const SolveParams& P, int nprob, const int64_t* pe0, const double* pmom,
+                        const double* pconst, double* x);
 
 }  // namespace mcs

@@ -61,13 +61,34 @@ RefTables build_ref_tables(int d, int k);
 int perm_index(const int* perm, int nv);   // rank of a permutation of 0..nv-1
 
 // ---------------------------------------------------------------------------
-// Multigrid lattice level.
+// Multigrid.  Every problem has its own lattice hierarchy (fine .. coarsest);
+// a union of problems keeps, per level, one lattice block per problem that
+// still has that level.  Blocks whose problem continues to a coarser level
+// are smoothed and restricted there; a block on its problem's coarsest level
+// is solved densely.
 // ---------------------------------------------------------------------------
-struct MGLevel {
+struct LatLevel {
   int n[3];           // intervals per axis (n[2] = 0 in 2D)
   int64_t nvert;      // lattice vertices (incl. boundary)
-  int64_t off_A, off_Dinv, off_x, off_b, off_r;   // workspace offsets (bytes)
   int64_t nfree;      // free dofs
+};
+
+struct MGBlock {
+  int prob;
+  int n[3];
+  int64_t nvert, voff;          // vertices, first vertex in the level arrays
+  int coarsest;
+  int nc3[3];                   // continuing: intervals of the next level
+  int64_t nvert_c, cvoff;       // continuing: next-level vertices and offset
+  int64_t nc, cmap_off, cinv_off;  // coarsest: free dofs, offsets in cmap / Cinv
+};
+
+struct MGLevel {
+  int64_t nvert;                // all blocks of the level
+  std::vector<MGBlock> blocks;  // continuing blocks first, then coarsest ones
+  int ncont;
+  int64_t maxv, maxvc, maxnc;   // largest block: vertices, next-level vertices, coarse dofs
+  int64_t off_A, off_Dinv, off_x, off_b, off_r, off_blk;   // workspace offsets (bytes)
 };
 
 // Device pointers of one problem (all inside the caller workspace).
@@ -128,9 +149,16 @@ struct mcs_problem {
       h_vfree_of_lat, h_free_to_lat;
   std::vector<double> h_coords;
   mcs::RefTables ref;
-  std::vector<mcs::MGLevel> mg;         // fine .. coarsest
-  int64_t nc;                            // coarsest free dofs
-  std::vector<int32_t> h_cmap;
+  std::vector<mcs::MGLevel> mg;         // fine .. coarsest over all member problems
+  int64_t nc;                            // coarsest free dofs, summed over problems
+  int64_t ncinv;                         // sum of nc_i^2 (dense coarse inverses)
+  std::vector<int32_t> h_cmap;           // per problem: coarsest free dof -> block-local lattice dof
+  // member problems (one for a single problem; several for a union of
+  // problems with the same dimension and order)
+  int nprob = 1;
+  std::vector<int64_t> pe0, pf0, pv0, pfv0;   // [nprob+1] element / free facet / vertex / free vertex offsets
+  std::vector<std::vector<mcs::LatLevel>> plev;  // per problem: lattice hierarchy
+  std::vector<std::vector<int32_t>> pcmap;      // per problem: coarsest free dof -> local lattice dof
   int64_t ndof, off_f, off_p, np1;
   int64_t n_slots;                       // condensation workgroup slots
   int64_t slot_doubles;

@@ -11,7 +11,7 @@
 #include <numeric>
 #include <stdexcept>
 
-#include "mcs_internal.h"
+#include "kernels_common.h"
 
 namespace mcs {
 
@@ -45,6 +45,65 @@ int64_t coarse_count(int n) {  // coarse points of n intervals: 0,2,4,.. plus n
 }
 
 }  // namespace
+
+// Multigrid levels of all member problems: level l holds one lattice block
+// per problem whose hierarchy reaches l, vertices in problem order; the
+// block list puts the continuing blocks first.
+void build_mg(mcs_problem* pb) {
+  int L = 0;
+  for (auto& lv : pb->plev) L = std::max(L, (int)lv.size());
+  pb->mg.assign(L, MGLevel{});
+  std::vector<std::vector<int64_t>> voff(L, std::vector<int64_t>(pb->nprob, -1));
+  for (int l = 0; l < L; ++l) {
+    int64_t off = 0;
+    for (int i = 0; i < pb->nprob; ++i)
+      if ((int)pb->plev[i].size() > l) {
+        voff[l][i] = off;
+        off += pb->plev[i][l].nvert;
+      }
+    pb->mg[l].nvert = off;
+  }
+  pb->nc = 0;
+  pb->ncinv = 0;
+  pb->h_cmap.clear();
+  for (int l = 0; l < L; ++l) {
+    MGLevel& M = pb->mg[l];
+    std::vector<MGBlock> cont, coarse;
+    for (int i = 0; i < pb->nprob; ++i) {
+      const auto& lv = pb->plev[i];
+      if ((int)lv.size() <= l) continue;
+      MGBlock B{};
+      B.prob = i;
+      for (int a = 0; a < 3; ++a) B.n[a] = lv[l].n[a];
+      B.nvert = lv[l].nvert;
+      B.voff = voff[l][i];
+      B.coarsest = (l + 1 == (int)lv.size()) ? 1 : 0;
+      if (!B.coarsest) {
+        for (int a = 0; a < 3; ++a) B.nc3[a] = lv[l + 1].n[a];
+        B.nvert_c = lv[l + 1].nvert;
+        B.cvoff = voff[l + 1][i];
+        cont.push_back(B);
+      } else {
+        B.nc = lv[l].nfree;
+        B.cmap_off = pb->nc;
+        B.cinv_off = pb->ncinv;
+        pb->nc += B.nc;
+        pb->ncinv += B.nc * B.nc;
+        pb->h_cmap.insert(pb->h_cmap.end(), pb->pcmap[i].begin(), pb->pcmap[i].end());
+        coarse.push_back(B);
+      }
+    }
+    M.ncont = (int)cont.size();
+    M.blocks = cont;
+    M.blocks.insert(M.blocks.end(), coarse.begin(), coarse.end());
+    M.maxv = M.maxvc = M.maxnc = 0;
+    for (auto& B : cont) {
+      M.maxv = std::max(M.maxv, B.nvert);
+      M.maxvc = std::max(M.maxvc, B.nvert_c);
+    }
+    for (auto& B : coarse) M.maxnc = std::max(M.maxnc, B.nc);
+  }
+}
 
 // Builds everything the device needs except the numerical tables.
 int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) {
@@ -276,25 +335,24 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
       return MCS_ERR_MESH;
     }
   }
-  pb->mg.clear();
+  pb->plev.assign(1, {});
+  pb->pcmap.assign(1, {});
   {
     int n[3] = {pb->lattice[0] - 1, pb->lattice[1] - 1, d == 3 ? pb->lattice[2] - 1 : 0};
     while (true) {
-      MGLevel L{};
+      LatLevel L{};
       L.n[0] = n[0];
       L.n[1] = n[1];
       L.n[2] = n[2];
       L.nvert = (int64_t)(n[0] + 1) * (n[1] + 1) * (d == 3 ? n[2] + 1 : 1);
       L.nfree = (int64_t)(n[0] - 1) * (n[1] - 1) * (d == 3 ? n[2] - 1 : 1) * d;
-      pb->mg.push_back(L);
+      pb->plev[0].push_back(L);
       int nmin = std::min(n[0], n[1]);
       if (d == 3) nmin = std::min(nmin, n[2]);
       if (L.nfree <= pb->opt.coarse_max || nmin <= 2) break;
       for (int a = 0; a < d; ++a) n[a] = (int)coarse_count(n[a]) - 1;
     }
-    const MGLevel& C = pb->mg.back();
-    pb->nc = C.nfree;
-    pb->h_cmap.clear();
+    const LatLevel& C = pb->plev[0].back();
     int N0 = C.n[0] + 1, N1 = C.n[1] + 1;
     for (int64_t v = 0; v < C.nvert; ++v) {
       int c[3] = {int(v % N0), int((v / N0) % N1), int(v / ((int64_t)N0 * N1))};
@@ -302,15 +360,120 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
       for (int a = 0; a < d; ++a)
         if (c[a] == 0 || c[a] == C.n[a]) interior = false;
       if (interior)
-        for (int cc = 0; cc < d; ++cc) pb->h_cmap.push_back((int32_t)(v * d + cc));
+        for (int cc = 0; cc < d; ++cc) pb->pcmap[0].push_back((int32_t)(v * d + cc));
     }
   }
+  pb->nprob = 1;
+  pb->pe0 = {0, ne};
+  pb->pf0 = {0, nff};
+  pb->pv0 = {0, nvert};
+  pb->pfv0 = {0, nfv};
+  build_mg(pb);
 
   // ---- global layout
   pb->off_f = ne * s.nb;
   pb->off_p = pb->off_f + nff * s.nfb;
   pb->ndof = pb->off_p + ne * s.np;
   pb->np1 = nfv * d;
+  return MCS_OK;
+}
+
+// Union of planned problems with the same dimension, order and options: the
+// host arrays are the members' arrays concatenated in member order, with
+// element, facet, vertex and free-vertex indices shifted by the member's
+// offsets.  Facet colours are kept (a colour class of the union is the union
+// of the members' classes), so every member sees exactly its own topology.
+int plan_union(const std::vector<const mcs_problem*>& parts, mcs_problem* u) {
+  if (parts.empty()) {
+    set_error("empty union");
+    return MCS_ERR_ARG;
+  }
+  const mcs_problem* p0 = parts[0];
+  for (auto* q : parts)
+    if (q->d != p0->d || q->sz.k != p0->sz.k) {
+      set_error("union members must share dimension and order");
+      return MCS_ERR_ARG;
+    }
+  const int d = p0->d, nv = d + 1;
+  u->sz = p0->sz;
+  u->opt = p0->opt;
+  u->d = d;
+  for (int a = 0; a < 3; ++a) u->lattice[a] = 0;
+  u->nprob = (int)parts.size();
+  u->pe0.assign(1, 0);
+  u->pf0.assign(1, 0);
+  u->pv0.assign(1, 0);
+  u->pfv0.assign(1, 0);
+  u->plev.clear();
+  u->pcmap.clear();
+  u->ncol = 0;
+  for (auto* q : parts) {
+    u->pe0.push_back(u->pe0.back() + q->ne);
+    u->pf0.push_back(u->pf0.back() + q->nff);
+    u->pv0.push_back(u->pv0.back() + q->nvert);
+    u->pfv0.push_back(u->pfv0.back() + q->nfv);
+    u->plev.push_back(q->plev[0]);
+    u->pcmap.push_back(q->pcmap[0]);
+    u->ncol = std::max(u->ncol, q->ncol);
+  }
+  const int np = u->nprob;
+  u->ne = u->pe0[np];
+  u->nff = u->pf0[np];
+  u->nvert = u->pv0[np];
+  u->nfv = u->pfv0[np];
+  auto cat = [&](auto member, auto& out, auto shift) {
+    out.clear();
+    for (int i = 0; i < np; ++i) {
+      const auto& src = parts[i]->*member;
+      for (auto v : src) out.push_back(shift(i, v));
+    }
+  };
+  auto keep = [](int, int32_t v) { return v; };
+  cat(&mcs_problem::h_elem_ff, u->h_elem_ff, [&](int i, int32_t g) { return g >= 0 ? (int32_t)(g + u->pf0[i]) : g; });
+  cat(&mcs_problem::h_elem_verts, u->h_elem_verts, [&](int i, int32_t v) { return (int32_t)(v + u->pv0[i]); });
+  cat(&mcs_problem::h_elem_perm, u->h_elem_perm, keep);
+  cat(&mcs_problem::h_facet_el, u->h_facet_el, [&](int i, int32_t e) { return (int32_t)(e + u->pe0[i]); });
+  cat(&mcs_problem::h_facet_slot, u->h_facet_slot, keep);
+  cat(&mcs_problem::h_colour, u->h_colour, keep);
+  cat(&mcs_problem::h_facet_vfree, u->h_facet_vfree, [&](int i, int32_t v) { return v >= 0 ? (int32_t)(v + u->pfv0[i]) : v; });
+  cat(&mcs_problem::h_vfree_of_lat, u->h_vfree_of_lat, [&](int i, int32_t v) { return v >= 0 ? (int32_t)(v + u->pfv0[i]) : v; });
+  cat(&mcs_problem::h_free_to_lat, u->h_free_to_lat, [&](int i, int32_t v) { return (int32_t)(v + u->pv0[i]); });
+  u->h_coords.clear();
+  for (auto* q : parts) u->h_coords.insert(u->h_coords.end(), q->h_coords.begin(), q->h_coords.end());
+  // CSR arrays: free vertex -> (facet, slot) and vertex -> elements
+  u->h_vinc_off.assign(1, 0);
+  u->h_vinc.clear();
+  u->h_vert_elem_off.assign(1, 0);
+  u->h_vert_elem.clear();
+  for (int i = 0; i < np; ++i) {
+    const mcs_problem* q = parts[i];
+    const int32_t b0 = u->h_vinc_off.back();
+    for (int64_t v = 0; v < q->nfv; ++v) u->h_vinc_off.push_back(b0 + q->h_vinc_off[v + 1]);
+    for (size_t t = 0; t < q->h_vinc.size(); t += 2) {
+      u->h_vinc.push_back((int32_t)(q->h_vinc[t] + u->pf0[i]));
+      u->h_vinc.push_back(q->h_vinc[t + 1]);
+    }
+    const int32_t e0 = u->h_vert_elem_off.back();
+    for (int64_t v = 0; v < q->nvert; ++v) u->h_vert_elem_off.push_back(e0 + q->h_vert_elem_off[v + 1]);
+    for (auto e : q->h_vert_elem) u->h_vert_elem.push_back((int32_t)(e + u->pe0[i]));
+  }
+  // colour classes
+  const int64_t nff = u->nff;
+  u->colour_off.assign(u->ncol + 1, 0);
+  for (int64_t g = 0; g < nff; ++g) u->colour_off[u->h_colour[g] + 1]++;
+  for (int c = 0; c < u->ncol; ++c) u->colour_off[c + 1] += u->colour_off[c];
+  u->h_colour_facets.resize(nff);
+  {
+    std::vector<int32_t> pos(u->colour_off.begin(), u->colour_off.end() - 1);
+    for (int64_t g = 0; g < nff; ++g) u->h_colour_facets[pos[u->h_colour[g]]++] = (int32_t)g;
+  }
+  build_mg(u);
+  const Sizes& s = u->sz;
+  u->off_f = u->ne * s.nb;
+  u->off_p = u->off_f + nff * s.nfb;
+  u->ndof = u->off_p + u->ne * s.np;
+  u->np1 = u->nfv * d;
+  (void)nv;
   return MCS_OK;
 }
 
@@ -383,8 +546,10 @@ int layout_workspace(mcs_problem* pb) {
     M.off_b = L.add(nm, Dd(M.nvert * d));
     snprintf(nm, sizeof nm, "mgr%zu", l);
     M.off_r = L.add(nm, Dd(M.nvert * d));
+    snprintf(nm, sizeof nm, "mgblk%zu", l);
+    M.off_blk = L.add(nm, sizeof(MGBlockDev) * M.blocks.size());
   }
-  L.add("Cinv", Dd(pb->nc * pb->nc));
+  L.add("Cinv", Dd(pb->ncinv));
   L.add("cmap", I(pb->nc));
   pb->n_slots = std::min<int64_t>(ne, 2048);
   pb->slot_doubles = (int64_t)s.nA * s.nsig + (int64_t)s.nlam * s.nsig * 2 + (int64_t)s.nA * s.nlam +

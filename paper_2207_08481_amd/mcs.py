@@ -29,7 +29,9 @@ PC = {"KHAT": 0, "AEXT": 1, "ADELTA_MULT": 2, "SMOOTH_FWD": 3, "SMOOTH_BWD": 4, 
 SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
            "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
            "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_destroy",
-           "mcs_status_string", "mcs_last_error"]
+           "mcs_status_string", "mcs_last_error",
+           "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
+           "mcs_batch_solve", "mcs_batch_set_mode", "mcs_batch_destroy"]
 
 
 class MCSError(RuntimeError):
@@ -67,6 +69,11 @@ class SolveInfo(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class BatchInfo(C.Structure):
+    _fields_ = [("n_problems", C.c_int32), ("n_groups", C.c_int32), ("n_dof_total", C.c_int64),
+                ("workspace_bytes", C.c_size_t)]
+
+
 _lib = None
 
 
@@ -98,9 +105,20 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_status_string.restype = C.c_char_p
     lib.mcs_last_error.argtypes = []
     lib.mcs_last_error.restype = C.c_char_p
+    lib.mcs_batch_plan.argtypes = [C.POINTER(Mesh), vp, i32, C.POINTER(Options), C.POINTER(vp),
+                                   C.POINTER(BatchInfo)]
+    lib.mcs_batch_member_info.argtypes = [vp, i32, C.POINTER(Info)]
+    lib.mcs_batch_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    lib.mcs_batch_condense.argtypes = [vp, vp]
+    lib.mcs_batch_solve.argtypes = [vp, vp, vp, vp]
+    lib.mcs_batch_set_mode.argtypes = [vp, i32, i32]
+    lib.mcs_batch_destroy.argtypes = [vp]
+    lib.mcs_batch_destroy.restype = None
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
                  "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
-                 "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read"):
+                 "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_batch_plan",
+                 "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
+                 "mcs_batch_set_mode"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -260,6 +278,97 @@ class Problem:
     def close(self):
         if getattr(self, "_h", None):
             self._lib.mcs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr_array(tensors):
+    arr = (C.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+    return arr
+
+
+class Batch:
+    """Many independent problems solved together (mcs_batch_*): members with
+    the same dimension and order share every kernel launch; MINRES runs per
+    member.  meshes: list of (vertices, elements, lattice); orders: list of k."""
+
+    def __init__(self, meshes, orders, precision=1, smoothing_steps=2, tol=1e-8, max_it=2000,
+                 inner_tol=1e-5, max_outer=10, coarse_max=512):
+        lib = load_library()
+        self._lib = lib
+        self._keep = []
+        arr = (Mesh * len(meshes))()
+        self.dims, self.n_elements = [], []
+        for i, (v, e, lat) in enumerate(meshes):
+            v = np.ascontiguousarray(v, dtype=np.float64)
+            e = np.ascontiguousarray(e, dtype=np.int32)
+            self._keep += [v, e]
+            lat = list(lat) + [1] * (3 - len(lat))
+            arr[i] = Mesh(v.shape[1], v.shape[0], v.ctypes.data, e.shape[0], e.ctypes.data, (C.c_int32 * 3)(*lat))
+            self.dims.append(v.shape[1])
+            self.n_elements.append(e.shape[0])
+        self._meshes = arr
+        self.orders = [int(k) for k in orders]
+        ords = np.asarray(self.orders, dtype=np.int32)
+        self._keep.append(ords)
+        self._opt = Options(0, precision, smoothing_steps, max_it, tol, inner_tol, max_outer, coarse_max)
+        self.info = BatchInfo()
+        h = C.c_void_p()
+        _check(lib.mcs_batch_plan(arr, ords.ctypes.data, len(meshes), C.byref(self._opt), C.byref(h),
+                                  C.byref(self.info)))
+        self._h = h
+        self.n = len(meshes)
+        self.members = []
+        for i in range(self.n):
+            mi = Info()
+            _check(lib.mcs_batch_member_info(h, i, C.byref(mi)))
+            self.members.append(mi)
+
+    def bind(self, device="cuda:0"):
+        import torch
+        dev = torch.device(device)
+        torch.cuda.set_device(dev)
+        self.device = dev
+        self.workspace = torch.empty(self.info.workspace_bytes, dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev)
+        _check(self._lib.mcs_batch_bind(self._h, self.workspace.data_ptr(), self.info.workspace_bytes,
+                                        self.stream.cuda_stream))
+        return self
+
+    def set_mode(self, use_graph=True, chunk=6):
+        _check(self._lib.mcs_batch_set_mode(self._h, 1 if use_graph else 0, chunk))
+
+    def condense(self, nus):
+        import torch
+        ts = []
+        for i, nu in enumerate(nus):
+            t = torch.as_tensor(nu, dtype=torch.float64, device=self.device).contiguous()
+            if t.numel() == 1:
+                t = t.expand(self.n_elements[i]).contiguous()
+            ts.append(t)
+        self._nus = ts
+        _check(self._lib.mcs_batch_condense(self._h, _ptr_array(ts)))
+
+    def solve(self, forces):
+        """Returns (list of solution tensors in each member's own layout, list of info dicts)."""
+        import torch
+        fs = [torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous() for f in forces]
+        xs = [torch.zeros(m.n_dof, dtype=torch.float64, device=self.device) for m in self.members]
+        infos = (SolveInfo * self.n)()
+        rc = self._lib.mcs_batch_solve(self._h, _ptr_array(fs), _ptr_array(xs), infos)
+        out = [infos[i].as_dict() for i in range(self.n)]
+        if rc != OK and rc != -5:
+            _check(rc)
+        return xs, out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mcs_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

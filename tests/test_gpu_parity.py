@@ -242,3 +242,25 @@ def test_lognormal_viscosity_parity():
     x, si = pb.solve(torch.as_tensor(c["f"], device="cuda:0"))
     assert si["status"] == 0
     assert _rel(x.cpu().numpy(), xd) < 1e-7
+
+
+def test_condensation_is_bitwise_reproducible():
+    """Two binds of the same problem (different workspaces) and two condense
+    calls on one bind produce bitwise identical operators and preconditioner
+    data (every entry has exactly one writer)."""
+    _need_gpu()
+    from paper_2207_08481_amd import Problem
+    mesh = W.unit_cube_mesh(3)
+    nu = torch.full((mesh.n_elements,), 0.37, dtype=torch.float64, device="cuda:0")
+    names = ["detJ", "Ad", "H", "Aoo", "Aooinv", "Dinv", "EF", "W", "Cinv", "mgA0"]
+    outs = []
+    keep = []
+    for _ in range(2):
+        pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 3).bind("cuda:0")
+        keep.append(pb)
+        for _ in range(2):
+            pb.condense(nu)
+            outs.append({n: pb.get_array(n).clone() for n in names})
+    for o in outs[1:]:
+        for n in names:
+            assert torch.equal(o[n], outs[0][n]), n

@@ -298,3 +298,27 @@ def workload(name: str, **kw):
         f = force.f(lattice_points(mesh, k + 1))
         return dict(mesh=mesh, nu=nu, k=k, f_lattice=f, solution=None, tol=1e-8)
     raise KeyError(name)
+
+
+def batch_members(n_members: int = 256, seed: int = 5, n_min: int = 4, n_max: int = 16, orders=(2, 3, 4),
+                  nu_sigma: float = 0.5):
+    """Member recipe of a batch of independent cube problems: n_i =
+    round(exp(U[ln n_min, ln n_max])) cubes per axis (6 n_i^3 tets), k_i uniform
+    in `orders`, nu_i = exp(N(0, nu_sigma^2)) constant per member, and the
+    seed of the member's random smooth force.  Returns a list of dicts
+    (n, k, nu, force_seed); meshes and forces are built on demand by
+    batch_member()."""
+    rng = np.random.default_rng(seed)
+    ns = np.rint(np.exp(rng.uniform(math.log(n_min), math.log(n_max), n_members))).astype(int)
+    ks = rng.choice(np.asarray(orders), size=n_members)
+    nus = np.exp(nu_sigma * rng.standard_normal(n_members))
+    return [dict(n=int(ns[i]), k=int(ks[i]), nu=float(nus[i]), force_seed=1000 + seed * 7919 + i)
+            for i in range(n_members)]
+
+
+def batch_member(spec: dict):
+    """Mesh, per-element viscosity and degree-(k+1) lattice force of one batch member."""
+    mesh = unit_cube_mesh(spec["n"])
+    nu = np.full(mesh.n_elements, spec["nu"])
+    f = RandomForce(3, seed=spec["force_seed"]).f(lattice_points(mesh, spec["k"] + 1))
+    return dict(mesh=mesh, nu=nu, k=spec["k"], f_lattice=f)
