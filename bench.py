@@ -41,6 +41,10 @@ WORKLOADS = {
     "cube32_k4_mixed": ("cube32_k4_lognormal", 1, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 contrast), random smooth f, FP32 inner + FP64 refinement, tol 1e-10"),
     "cube32_k4_fp64": ("cube32_k4_lognormal", 0, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 contrast), random smooth f, FP64, tol 1e-10"),
     "square8_k2": ("square8_k2", 0, "unit square 8x8 x 2 triangles, k=2, nu=1, FP64, tol 1e-10"),
+    "batch256_mixed": ("batch", 1, "batch of 256 unit-cube problems, n^3 x 6 tets with n = round(exp(U[ln 4, ln 16])), "
+                                   "k uniform in {2,3,4}, nu = exp(N(0, 0.5^2)) per problem, random smooth forces; "
+                                   "FP32 inner MINRES + FP64 refinement per problem, tol 1e-8; iterations of all "
+                                   "groups replayed from one captured HIP graph"),
 }
 
 
@@ -93,6 +97,101 @@ print(json.dumps({"ndof": gs.n_dof, "its": info["iterations"], "t": dt}))
                       f"recipe (k=3, nu=1, {r['ndof']} dofs), {r['t']:.1f} s, 1 thread"}
 
 
+def run_batch(args, precision, desc):
+    """Batch of independent problems (mcs_batch_*): a step is condensation +
+    solve of every member.  value = sum_i #D_i #IT_i / t_sol (batch wall time of
+    the solve phase).  The timed steps replay the captured graph; the roofline
+    of the smoother kernel comes from one more solve of the same batch with the
+    kernel timer on (launch by launch)."""
+    import torch
+    import workloads as W
+    from paper_2207_08481_amd import Batch
+    log("batch members (host)")
+    specs = W.batch_members(256, seed=5)
+    members = [W.batch_member(sp) for sp in specs]
+    dev = "cuda:0"
+    b = Batch([(m["mesh"].vertices, m["mesh"].elements, m["mesh"].lattice) for m in members],
+              [m["k"] for m in members], precision=precision, tol=1e-8, max_it=5000)
+    log(f"planned: {b.info.n_problems} problems, {b.info.n_groups} groups, {b.info.n_dof_total} dofs, "
+        f"workspace {b.info.workspace_bytes / 1e9:.1f} GB")
+    b.bind(dev)
+    nus = [torch.as_tensor(m["nu"], device=dev) for m in members]
+    fs = [torch.as_tensor(m["f_lattice"], device=dev) for m in members]
+    ndofs = [mi.n_dof for mi in b.members]
+
+    def step():
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        b.condense(nus)
+        ev1.record()
+        torch.cuda.synchronize()
+        xs, infos = b.solve(fs)
+        bad = [i for i, inf in enumerate(infos) if inf["status"] != 0]
+        its = sum(inf["iterations"] for inf in infos)
+        dofits = sum(n * inf["iterations"] for n, inf in zip(ndofs, infos))
+        t_sol = infos[0]["t_solve_ms"]
+        log(f"step: setup {ev0.elapsed_time(ev1):.1f} ms, solve {t_sol:.1f} ms, member iterations "
+            f"min {min(i['iterations'] for i in infos)} max {max(i['iterations'] for i in infos)}, "
+            f"not converged {len(bad)}")
+        return ev0.elapsed_time(ev1), t_sol, dofits, its, infos
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_sup = t_sol = dofits = 0.0
+    its = 0
+    infos = None
+    for _ in range(args.steps):
+        ts, tsol, di, it, infos = step()
+        t_sup += ts
+        t_sol += tsol
+        dofits += di
+        its += it
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log("roofline solve (kernel timer on)")
+    b.timer_enable(True)
+    b.solve(fs)
+    kms, klaunch, kbytes = b.timer_read()
+    b.timer_enable(False)
+    avg_launch_ms = kms / max(klaunch, 1)
+    bytes_per_launch = kbytes / max(klaunch, 1)
+    achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
+    rel = [inf["rel_residual"] for inf in infos]
+    out = {
+        "metric": "DOF-iterations/s of preconditioned MCS solve",
+        "value": dofits / (t_sol / 1e3),
+        "unit": "DOF-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n_problems": b.info.n_problems, "n_dof_total": b.info.n_dof_total,
+                   "groups": b.info.n_groups, "member_iterations_sum": its / args.steps,
+                   "solves_per_s": b.info.n_problems / (t_sol / args.steps / 1e3),
+                   "t_sup_ms": t_sup / args.steps, "t_sol_ms": t_sol / args.steps,
+                   "max_rel_residual": max(rel),
+                   "not_converged": sum(1 for inf in infos if inf["status"] != 0)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_smooth_phase, FP32 (one colour of one block Gauss-Seidel sweep, all groups)",
+                     "avg_launch_us": round(avg_launch_ms * 1e3, 2), "launches": klaunch,
+                     "bytes_per_launch": int(bytes_per_launch),
+                     "note": "measured in one extra launch-by-launch solve of the same batch"},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +215,8 @@ def main():
 
     key, precision, desc = WORKLOADS[args.workload]
     log(f"workload {args.workload}")
+    if key == "batch":
+        return run_batch(args, precision, desc)
     wl = W.workload(key)
     mesh = wl["mesh"]
     k = wl["k"]

@@ -209,7 +209,8 @@ int mcs_get_topology(const mcs_problem* pb, int32_t* colour_host, int32_t* elem_
  * number of launches and their algorithmic HBM bytes: per facet of the
  * colour, the facet's rows of A^d_T of both neighbours (2 n_fb n_d words),
  * D_F^{-1} (n_fb^2), the right-hand side and the updated block (3 n_fb), the
- * gathered neighbour vectors (2 n_d) and the index words.  Enabling resets the
+ * gathered neighbour vectors (2 n_d) and the index words, counted on the
+ * device over the facet blocks actually processed.  Enabling resets the
  * counters.  [sync on read] */
 int mcs_timer_enable(mcs_problem* pb, int enable);
 int mcs_timer_read(mcs_problem* pb, double* total_ms, int64_t* launches, double* bytes);
@@ -274,6 +275,12 @@ int mcs_batch_solve(mcs_batch* b, const double* const* f_host, double* const* x_
  * use_graph = 0 launches the same kernels one by one.  chunk is a positive
  * multiple of 6 (default 6).  Both modes give identical results. */
 int mcs_batch_set_mode(mcs_batch* b, int use_graph, int chunk);
+
+/* Smoother timing over all groups (see mcs_timer_enable; the bytes count
+ * only the facet blocks of members still iterating).  While enabled,
+ * mcs_batch_solve launches kernels one by one (no graph).  [sync] */
+int mcs_batch_timer_enable(mcs_batch* b, int enable);
+int mcs_batch_timer_read(mcs_batch* b, double* total_ms, int64_t* launches, double* bytes);
 
 void mcs_batch_destroy(mcs_batch* b);
 

@@ -118,6 +118,7 @@ struct mcs_batch {
   int device = -1;
   bool condensed = false;
   int use_graph = 1, chunk = 6;
+  bool timer = false;               // smoother timing: launches one by one
   hipGraphExec_t gexec[2] = {nullptr, nullptr};   // inner iteration chunk, FP64 / FP32
   ~mcs_batch() {
     for (auto& g : gexec)
@@ -224,14 +225,21 @@ int any_set(mcs_batch* B, int which, bool* any) {
 template <typename R>
 int run_iterations(mcs_batch* B, std::vector<GroupRun<R>>& runs, int maxit) {
   const int prec = sizeof(R) == 8 ? 0 : 1;
+  // With the kernel timer on, the groups run one after another so that each
+  // timed launch has the device to itself.
   auto enqueue_chunk = [&]() -> int {
     int rc = fork(B);
     if (rc) return rc;
-    for (auto& r : runs)
-      for (int i = 0; i < B->chunk; ++i) r.iteration();
+    for (size_t g = 0; g < runs.size(); ++g) {
+      if (B->timer && g > 0) {
+        HIPCHK(hipEventRecord(runs[g - 1].G->ev_join, runs[g - 1].G->stream));
+        HIPCHK(hipStreamWaitEvent(runs[g].G->stream, runs[g - 1].G->ev_join, 0));
+      }
+      for (int i = 0; i < B->chunk; ++i) runs[g].iteration();
+    }
     return join(B);
   };
-  if (B->use_graph && !B->gexec[prec]) {
+  if (B->use_graph && !B->timer && !B->gexec[prec]) {
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(B->main, hipStreamCaptureModeThreadLocal));
     int rc = enqueue_chunk();
@@ -242,13 +250,14 @@ int run_iterations(mcs_batch* B, std::vector<GroupRun<R>>& runs, int maxit) {
     hipGraphDestroy(graph);
     HIPCHK(e);
   }
+  const bool graph = B->use_graph && !B->timer;
   const int max_chunks = maxit / B->chunk + 2;
   for (int k = 0; k < max_chunks; ++k) {
     bool any = false;
     int rc = any_set(B, 0, &any);
     if (rc) return rc;
     if (!any) return MCS_OK;
-    if (B->use_graph) {
+    if (graph) {
       HIPCHK(hipGraphLaunch(B->gexec[prec], B->main));
     } else {
       rc = enqueue_chunk();
@@ -533,7 +542,7 @@ int mcs_batch_solve(mcs_batch* B, const double* const* f, double* const* xo, mcs
     for (int j = 0; j < G.np(); ++j)
       HIPCHK(hipMemcpyAsync(G.fun + u->pe0[j] * per, f[G.members[j]], (u->pe0[j + 1] - u->pe0[j]) * per * 8,
                             hipMemcpyDeviceToDevice, G.stream));
-    int rc = mcs_load(u, G.fun, u->p.vec + (int64_t)VB64 * u->ndof);
+    int rc = mcs_load(u, G.fun, Ctx<double>(u).v(VB64));
     if (rc) return rc;
   }
   for (auto& G : B->groups) HIPCHK(hipStreamSynchronize(G.stream));
@@ -557,7 +566,7 @@ int mcs_batch_solve(mcs_batch* B, const double* const* f, double* const* xo, mcs
       rc = upload_fields(G, {ST_TOL, ST_ABS, ST_SB1});
       if (rc) return rc;
       mcs_problem* u = G.u.get();
-      runs.emplace_back(&G, o.max_it, u->p.vec + (int64_t)VX * u->ndof);
+      runs.emplace_back(&G, o.max_it, Ctx<double>(u).v(VX));
     }
     for (auto& r : runs) r.start(r.c.v(VB64));
     for (auto& G : B->groups) {
@@ -771,6 +780,41 @@ int mcs_batch_solve(mcs_batch* B, const double* const* f, double* const* xo, mcs
     }
   if (infos) std::copy(inf.begin(), inf.end(), infos);
   return rc;
+}
+
+int mcs_batch_timer_enable(mcs_batch* B, int enable) {
+  if (!B || !B->ws) {
+    set_error("batch is not bound");
+    return B ? MCS_ERR_STATE : MCS_ERR_ARG;
+  }
+  for (auto& G : B->groups) {
+    int rc = mcs_timer_enable(G.u.get(), enable);
+    if (rc) return rc;
+  }
+  B->timer = enable != 0;
+  return MCS_OK;
+}
+
+int mcs_batch_timer_read(mcs_batch* B, double* total_ms, int64_t* launches, double* bytes) {
+  if (!B || !B->ws) {
+    set_error("batch is not bound");
+    return B ? MCS_ERR_STATE : MCS_ERR_ARG;
+  }
+  double ms = 0.0, by = 0.0;
+  int64_t n = 0;
+  for (auto& G : B->groups) {
+    double m = 0.0, b = 0.0;
+    int64_t l = 0;
+    int rc = mcs_timer_read(G.u.get(), &m, &l, &b);
+    if (rc) return rc;
+    ms += m;
+    by += b;
+    n += l;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = n;
+  if (bytes) *bytes = by;
+  return MCS_OK;
 }
 
 void mcs_batch_destroy(mcs_batch* B) { delete B; }

@@ -49,11 +49,13 @@ template <typename R>
 OpPtrs<R> op_ptrs(mcs_problem* pb);
 template <>
 inline OpPtrs<double> op_ptrs<double>(mcs_problem* pb) {
-  return {pb->p.Ad, pb->p.H, pb->p.Aoo, pb->p.Aooinv, pb->p.Dinv, pb->p.EF, pb->p.W};
+  return {pb->p.Ad, pb->p.H, pb->p.Aoo, pb->p.Aooinv, pb->p.Dinv, pb->p.EF, pb->p.W,
+          pb->p.Ad32, pb->p.Adl, pb->p.H32, pb->p.Hl, pb->p.Aoo32, pb->p.Aool};
 }
 template <>
 inline OpPtrs<float> op_ptrs<float>(mcs_problem* pb) {
-  return {pb->p.Ad32, pb->p.H32, pb->p.Aoo32, pb->p.Aooinv32, pb->p.Dinv32, pb->p.EF32, pb->p.W32};
+  return {pb->p.Ad32, pb->p.H32, pb->p.Aoo32, pb->p.Aooinv32, pb->p.Dinv32, pb->p.EF32, pb->p.W32,
+          nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 }
 
 template <typename R>
@@ -85,6 +87,19 @@ std::vector<MGLevelDev> mg_levels(mcs_problem* pb) {
   return out;
 }
 
+// Algorithmic HBM bytes of one facet block of the smoother kernel with
+// words of wsize bytes: the facet's rows of A^d_T of both neighbours
+// (2 n_fb n_d), D_F^{-1} (n_fb^2), the right-hand side and the updated block
+// (3 n_fb), the neighbours' maintained products read and written (4 n_d),
+// two more block reads (2 n_fb) and six index words.
+inline double smooth_bytes_per_facet(const Sizes& z, int wsize) {
+  return double(2 * z.nfb * z.nd + z.nfb * z.nfb + 4 * z.nd + 5 * z.nfb) * wsize + 6.0 * 4.0;
+}
+// device counters of processed facet blocks: 256 counters (stride 16) for
+// FP64 launches, then 256 for FP32 launches
+constexpr int WCOUNT = 2 * 256 * 16;
+inline unsigned long long* work_counters(mcs_problem* pb) { return pb->p.wcount; }
+
 // Accumulates the elapsed time of recorded (start, stop) event pairs; the
 // caller has synchronised the stream.
 inline void timer_flush(mcs_problem* pb) {
@@ -108,7 +123,8 @@ struct Ctx {
   int64_t n;
   explicit Ctx(mcs_problem* p) : pb(p), st(p->stream), P(solve_params(p)), O(op_ptrs<R>(p)), L(mg_levels<R>(p)) {
     n = p->ndof;
-    base = sizeof(R) == 8 ? reinterpret_cast<R*>(p->p.vec) : reinterpret_cast<R*>(p->p.vec32);
+    base = sizeof(R) == 8 ? reinterpret_cast<R*>(p->p.vec) - (int64_t)p->vbase64 * p->ndof
+                          : reinterpret_cast<R*>(p->p.vec32);
     escr = reinterpret_cast<R*>(p->p.escr);
     fscr = reinterpret_cast<R*>(p->p.fscr);
   }
@@ -146,9 +162,8 @@ struct Ctx {
   // `smoothing_steps` block Gauss-Seidel sweeps on A^d (colours ascending or
   // descending); y holds the element products A^d_T x_T and is kept current.
   void sweeps(R* x, const R* s, R* y, bool forward) {
-    const Sizes& z = pb->sz;
-    const double per_facet = double(2 * z.nfb * z.nd + z.nfb * z.nfb + 4 * z.nd + 5 * z.nfb) * sizeof(R) +
-                             double(6) * 4.0;
+    SolveParams Pt = P;
+    if (pb->timer_on) Pt.work_count = work_counters(pb) + (sizeof(R) == 8 ? 0 : 256 * 16);
     for (int it = 0; it < pb->opt.smoothing_steps; ++it)
       for (int cc = 0; cc < pb->ncol; ++cc) {
         int c = forward ? cc : pb->ncol - 1 - cc;
@@ -160,11 +175,10 @@ struct Ctx {
             pb->tev.push_back(e);
           }
           hipEventRecord(pb->tev[k], st);
-          launch_smooth_phase<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y);
+          launch_smooth_phase<R>(st, Pt, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y);
           hipEventRecord(pb->tev[k + 1], st);
           pb->tpending++;
           pb->t_launches++;
-          pb->t_bytes += per_facet * (pb->colour_off[c + 1] - pb->colour_off[c]);
         } else {
           launch_smooth_phase<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y);
         }

@@ -193,6 +193,10 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   p.EF32 = ws_ptr<float>(pb, "EF32");
   p.W = ws_ptr<double>(pb, "W");
   p.W32 = ws_ptr<float>(pb, "W32");
+  p.Adl = ws_ptr<float>(pb, "Adl");
+  p.Hl = ws_ptr<float>(pb, "Hl");
+  p.Aool = ws_ptr<float>(pb, "Aool");
+  p.adtmp = ws_ptr<double>(pb, "adtmp");
   p.Cinv = ws_ptr<double>(pb, "Cinv");
   p.cmap = ws_ptr<int32_t>(pb, "cmap");
   p.cscratch = ws_ptr<double>(pb, "cscratch");
@@ -201,6 +205,7 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   p.fscr = ws_ptr<double>(pb, "fscr");
   p.red = ws_ptr<double>(pb, "red");
   p.scal = ws_ptr<double>(pb, "scal");
+  p.wcount = ws_ptr<unsigned long long>(pb, "wcount");
   p.vec = ws_ptr<double>(pb, "vec");
   p.vec32 = ws_ptr<float>(pb, "vec32");
   p.p1 = ws_ptr<double>(pb, "p1");
@@ -312,6 +317,11 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   C.H32 = p.H32;
   C.Aoo32 = p.Aoo32;
   C.Aooinv32 = p.Aooinv32;
+  C.Adl = p.Adl;
+  C.Hl = p.Hl;
+  C.Aool = p.Aool;
+  C.adtmp = p.adtmp;
+  C.adtmp_stride = (int64_t)pb->sz.nd * pb->sz.nd;
   C.status = status;
   launch_condense(st, C, (int)pb->n_slots);
 
@@ -323,6 +333,8 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   F.elem_verts = p.elem_verts;
   F.coords = p.coords;
   F.Ad = p.Ad;
+  F.Adh = p.Ad32;
+  F.Adl = p.Adl;
   F.rcn = p.rcn;
   F.rct = p.rct;
   F.Dinv = p.Dinv;
@@ -520,7 +532,13 @@ int mcs_precond_apply(mcs_problem* pb, int op, int dt, const void* r, void* z) {
     set_error("null vector");
     return MCS_ERR_ARG;
   }
-  if (dt == MCS_F64) return precond_op<double>(pb, op, r, z);
+  if (dt == MCS_F64) {
+    if (pb->lean) {
+      set_error("precision 1 keeps the preconditioner in FP32 only");
+      return MCS_ERR_STATE;
+    }
+    return precond_op<double>(pb, op, r, z);
+  }
   if (dt == MCS_F32) return precond_op<float>(pb, op, r, z);
   set_error("unknown dtype %d", dt);
   return MCS_ERR_ARG;
@@ -645,7 +663,7 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
 int mcs_solve(mcs_problem* pb, const double* f_lattice, double* x, mcs_solve_info* info) {
   int rc = check_bound(pb);
   if (rc) return rc;
-  double* b = pb->p.vec + (int64_t)VB64 * pb->ndof;
+  double* b = Ctx<double>(pb).v(VB64);
   rc = mcs_load(pb, f_lattice, b);
   if (rc) return rc;
   return mcs_solve_rhs(pb, b, x, info);
@@ -672,6 +690,10 @@ int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count)
     if (!strcmp(e.n, name)) {
       *ptr = ws_ptr<char>(pb, name);
       *count = e.cnt;
+      if (!*ptr) {
+        set_error("array '%s' is not stored in this layout", name);
+        return MCS_ERR_STATE;
+      }
       return MCS_OK;
     }
   set_error("unknown array '%s'", name);
@@ -697,6 +719,8 @@ int mcs_timer_enable(mcs_problem* pb, int enable) {
   pb->t_ms = 0.0;
   pb->t_bytes = 0.0;
   pb->t_launches = 0;
+  HIPCHK(hipMemsetAsync(work_counters(pb), 0, WCOUNT * sizeof(unsigned long long), pb->stream));
+  HIPCHK(hipStreamSynchronize(pb->stream));
   return MCS_OK;
 }
 
@@ -705,6 +729,14 @@ int mcs_timer_read(mcs_problem* pb, double* total_ms, int64_t* launches, double*
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(pb->stream));
   timer_flush(pb);
+  std::vector<unsigned long long> wc(WCOUNT);
+  HIPCHK(hipMemcpy(wc.data(), work_counters(pb), WCOUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  unsigned long long cnt[2] = {0, 0};
+  for (int i = 0; i < 256; ++i) {
+    cnt[0] += wc[i * 16];
+    cnt[1] += wc[256 * 16 + i * 16];
+  }
+  pb->t_bytes = cnt[0] * smooth_bytes_per_facet(pb->sz, 8) + cnt[1] * smooth_bytes_per_facet(pb->sz, 4);
   if (total_ms) *total_ms = pb->t_ms;
   if (launches) *launches = pb->t_launches;
   if (bytes) *bytes = pb->t_bytes;

@@ -22,6 +22,13 @@ struct CondParams {
   double* detJ;
   double *Ad, *H, *Aoo, *Aooinv;
   float *Ad32, *H32, *Aoo32, *Aooinv32;
+  // split storage (FP32 work precision with FP64 refinement): the FP64
+  // arrays Ad, H, Aoo, Aooinv are absent; hi = the FP32 copy, lo = the FP32
+  // rounding of the remainder, so hi + lo reproduces the FP64 value to ~2^-48.
+  // A^d is formed in a per-slot FP64 buffer adtmp first.
+  float *Adl, *Hl, *Aool;
+  double* adtmp;
+  int64_t adtmp_stride;
   int* status;
 };
 
@@ -32,7 +39,8 @@ struct FacetSetupParams {
   const int32_t* facet_slot;
   const int32_t* elem_verts;
   const double* coords;
-  const double* Ad;
+  const double* Ad;              // FP64 A^d, or nullptr: hi + lo in Adh, Adl
+  const float *Adh, *Adl;
   const double *rcn, *rct;
   double* Dinv;
   float* Dinv32;
@@ -117,6 +125,10 @@ struct SolveParams {
   const int32_t* elem_prob;
   const int32_t* facet_prob;
   const int32_t* active;
+  // measurement: when set, the smoother kernel counts the facet blocks it
+  // processes, spread over 256 counters 128 bytes apart (workgroup w adds to
+  // counter w mod 256)
+  unsigned long long* work_count;
 };
 
 __device__ inline bool elem_off(const SolveParams& P, int64_t e) {
@@ -129,6 +141,20 @@ __device__ inline bool facet_off(const SolveParams& P, int64_t g) {
 template <typename R>
 struct OpPtrs {
   const R *Ad, *H, *Aoo, *Aooinv, *Dinv, *EF, *W;
+  // split storage of A^d, H, A_oo (R = double with Ad == nullptr)
+  const float *hAd, *lAd, *hH, *lH, *hAoo, *lAoo;
+};
+
+// Matrix entry accessors: plain arrays, or FP64 values kept as FP32 hi + lo.
+template <typename R>
+struct MatP {
+  const R* p;
+  __device__ R operator()(size_t i) const { return p[i]; }
+};
+struct MatHL {
+  const float* h;
+  const float* l;
+  __device__ double operator()(size_t i) const { return (double)h[i] + (double)l[i]; }
 };
 
 struct MGLevelDev {

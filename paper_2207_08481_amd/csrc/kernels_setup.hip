@@ -349,8 +349,10 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
       int i = idx / nb, j = idx % nb;
       double v = A[(size_t)i * s.nA + j];
       Wk[idx] = v;
-      P.Aoo[(size_t)e * nb * nb + idx] = v;
-      P.Aoo32[(size_t)e * nb * nb + idx] = (float)v;
+      const float hv = (float)v;
+      if (P.Aoo) P.Aoo[(size_t)e * nb * nb + idx] = v;
+      P.Aoo32[(size_t)e * nb * nb + idx] = hv;
+      if (P.Aool) P.Aool[(size_t)e * nb * nb + idx] = (float)(v - (double)hv);
     }
     __syncthreads();
     ok = block_cholesky(Wk, nb, nb) && ok;
@@ -366,7 +368,7 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
     }
     __syncthreads();
     for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
-      P.Aooinv[(size_t)e * nb * nb + idx] = Wk[idx];
+      if (P.Aooinv) P.Aooinv[(size_t)e * nb * nb + idx] = Wk[idx];
       P.Aooinv32[(size_t)e * nb * nb + idx] = (float)Wk[idx];
     }
     // Ht[n][m] = sum_k A[nb+n][k] Aooinv[m][k]   (nd x nb), kept in the slot
@@ -383,13 +385,17 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
             if (r < nd && c < nb) {
               double v = acc[i][j];
               Ht[(size_t)r * nb + c] = v;
-              P.H[(size_t)e * nb * nd + (size_t)c * nd + r] = v;
-              P.H32[(size_t)e * nb * nd + (size_t)c * nd + r] = (float)v;
+              const size_t hi = (size_t)e * nb * nd + (size_t)c * nd + r;
+              const float hv = (float)v;
+              if (P.H) P.H[hi] = v;
+              P.H32[hi] = hv;
+              if (P.Hl) P.Hl[hi] = (float)(v - (double)hv);
             }
           }
       }
     __syncthreads();
-    // Ad = A_dd - A_do Ht^T
+    // Ad = A_dd - A_do Ht^T   (in the FP64 array, or the slot's FP64 buffer)
+    double* Ade = P.Ad ? P.Ad + (size_t)e * nd * nd : P.adtmp + (size_t)blockIdx.x * P.adtmp_stride;
     for (int m0 = 0; m0 < nd; m0 += 64)
       for (int n0 = 0; n0 < nd; n0 += 64) {
         double acc[4][4];
@@ -400,21 +406,26 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
             int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
             if (r < nd && c < nd) {
               double v = A[(size_t)(nb + r) * s.nA + nb + c] - acc[i][j];
-              P.Ad[(size_t)e * nd * nd + (size_t)r * nd + c] = v;
+              Ade[(size_t)r * nd + c] = v;
             }
           }
       }
     __syncthreads();
-    // symmetrise Ad exactly and write the FP32 copy
-    double* Ade = P.Ad + (size_t)e * nd * nd;
+    // symmetrise Ad exactly and write the FP32 copy (and the low parts)
     for (int idx = tid; idx < nd * nd; idx += blockDim.x) {
       int r = idx / nd, c = idx % nd;
       if (c < r) continue;
       double v = 0.5 * (Ade[(size_t)r * nd + c] + Ade[(size_t)c * nd + r]);
       Ade[(size_t)r * nd + c] = v;
       Ade[(size_t)c * nd + r] = v;
-      P.Ad32[(size_t)e * nd * nd + (size_t)r * nd + c] = (float)v;
-      P.Ad32[(size_t)e * nd * nd + (size_t)c * nd + r] = (float)v;
+      const float hv = (float)v;
+      P.Ad32[(size_t)e * nd * nd + (size_t)r * nd + c] = hv;
+      P.Ad32[(size_t)e * nd * nd + (size_t)c * nd + r] = hv;
+      if (P.Adl) {
+        const float lv = (float)(v - (double)hv);
+        P.Adl[(size_t)e * nd * nd + (size_t)r * nd + c] = lv;
+        P.Adl[(size_t)e * nd * nd + (size_t)c * nd + r] = lv;
+      }
     }
     if (tid == 0) {
       P.detJ[e] = g.det;
@@ -448,7 +459,8 @@ __global__ void __launch_bounds__(256) k_facet_setup(FacetSetupParams P) {
       for (int side = 0; side < 2; ++side) {
         int64_t e = P.facet_el[2 * g + side];
         int sl = P.facet_slot[2 * g + side];
-        t += P.Ad[(size_t)e * nd * nd + (size_t)(sl * nfb + i) * nd + sl * nfb + j];
+        const size_t ai = (size_t)e * nd * nd + (size_t)(sl * nfb + i) * nd + sl * nfb + j;
+        t += P.Ad ? P.Ad[ai] : (double)P.Adh[ai] + (double)P.Adl[ai];
       }
       S[i * FLD + j] = t;
     }
@@ -462,7 +474,7 @@ __global__ void __launch_bounds__(256) k_facet_setup(FacetSetupParams P) {
       int p0 = i > j ? i : j;
       double t = 0.0;
       for (int p = p0; p < nfb; ++p) t += W[p * FLD + i] * W[p * FLD + j];
-      P.Dinv[(size_t)g * nfb * nfb + idx] = t;
+      if (P.Dinv) P.Dinv[(size_t)g * nfb * nfb + idx] = t;
       P.Dinv32[(size_t)g * nfb * nfb + idx] = (float)t;
     }
     // facet geometry from the first neighbour's sorted vertices
@@ -947,16 +959,20 @@ __global__ void __launch_bounds__(256) k_wsetup(FacetSetupParams P, const int32_
     for (int idx = threadIdx.x; idx < nd * nvd; idx += blockDim.x) {
       const int m = idx / nd, t = idx % nd;
       const int vl = m / d, c = m % d;
-      const double* Arow = P.Ad + ((size_t)e * nd + t) * nd;
+      const size_t a0 = ((size_t)e * nd + t) * nd;
       double acc = 0.0;
       for (int f = 0; f < nv; ++f) {
         const int g = elem_ff[e * nv + f];
         if (g < 0 || vl == f) continue;
         const int v = vl < f ? vl : vl - 1;
         const double* E = P.EF + (size_t)g * nfb * dd + v * d + c;
-        for (int q = 0; q < nfb; ++q) acc += Arow[f * nfb + q] * E[(size_t)q * dd];
+        for (int q = 0; q < nfb; ++q) {
+          const size_t ai = a0 + f * nfb + q;
+          const double a = P.Ad ? P.Ad[ai] : (double)P.Adh[ai] + (double)P.Adl[ai];
+          acc += a * E[(size_t)q * dd];
+        }
       }
-      W[((size_t)e * nvd + m) * nd + t] = acc;
+      if (W) W[((size_t)e * nvd + m) * nd + t] = acc;
       W32[((size_t)e * nvd + m) * nd + t] = (float)acc;
     }
   }

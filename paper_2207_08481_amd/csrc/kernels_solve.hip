@@ -53,17 +53,16 @@ __device__ inline R group_sum(R v) {
 // [t0, t0 + nthr) form groups of L lanes, one group per row (lanes over the
 // contiguous columns); epi(i, sum) runs on the group's first lane.  The row
 // loop is uniform over the participating waves (t0, nthr multiples of 64).
-template <int L, typename R, typename F>
-__device__ inline void rows_times(const R* __restrict__ M, int nrow, int ncol, const R* v, int t0, int nthr,
-                                  F epi) {
+template <int L, typename MA, typename R, typename F>
+__device__ inline void rows_times(MA M, size_t m0, int nrow, int ncol, const R* v, int t0, int nthr, F epi) {
   const int t = threadIdx.x - t0;
   const int g = t / L, l = t % L, ng = nthr / L;
   for (int i0 = 0; i0 < nrow; i0 += ng) {
     const int i = i0 + g;
     R acc = R(0);
     if (i < nrow) {
-      const R* Mi = M + (size_t)i * ncol;
-      for (int j = l; j < ncol; j += L) acc += Mi[j] * v[j];
+      const size_t mi = m0 + (size_t)i * ncol;
+      for (int j = l; j < ncol; j += L) acc += M(mi + j) * v[j];
     }
     acc = group_sum<L>(acc);
     if (l == 0 && i < nrow) epi(i, acc);
@@ -92,8 +91,8 @@ __device__ inline void build_rowmap(const Sizes& s, int* rmap) {
 // z_o = x_o + H x_d (16-lane groups per row of H); phase 2: w_o = A_oo z_o;
 // phase 3: H^T w_o (one column per thread) and the pressure coupling.
 // B_T[q][row] = -s |det J| Bp^[q][iu(row)] (s = 1 bubble, 1/det J facet row).
-template <typename R>
-__global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, OpPtrs<R> O, const R* __restrict__ x,
+template <typename R, typename MA>
+__global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH, MA MAoo, const R* __restrict__ x,
                                                     R* __restrict__ y, R* __restrict__ escr, int flags) {
   const Sizes s = P.s;
   const int nb = s.nb, nd = s.nd, np = s.np, nu = s.nu;
@@ -115,16 +114,16 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, OpPtrs<R> O, 
     if (tid < nb) xo[tid] = x[e * nb + tid];
     if (tid < np) xp[tid] = x[P.off_p + e * np + tid];
     __syncthreads();
-    const R* He = O.H + (size_t)e * nb * nd;
+    const size_t h0 = (size_t)e * nb * nd;
     R acc = R(0);
     if (tid < nd) {
       if (doA) {
-        const R* Ad = O.Ad + (size_t)e * nd * nd + tid;
+        const size_t a0 = (size_t)e * nd * nd + tid;
 #pragma unroll 8
-        for (int j = 0; j < nd; ++j) acc += Ad[(size_t)j * nd] * xd[j];
+        for (int j = 0; j < nd; ++j) acc += MAd(a0 + (size_t)j * nd) * xd[j];
       }
     } else if (doH && overlap && tid >= tA) {
-      rows_times<16>(He, nb, nd, xd, tA, 256 - tA, [&](int i, R v) { zo[i] = xo[i] + v; });
+      rows_times<16>(MH, h0, nb, nd, xd, tA, 256 - tA, [&](int i, R v) { zo[i] = xo[i] + v; });
     }
     if (doBu) {
       for (int row = tid; row < nb + nd; row += blockDim.x) {
@@ -134,18 +133,17 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, OpPtrs<R> O, 
     }
     if (doH && !overlap) {
       __syncthreads();
-      rows_times<16>(He, nb, nd, xd, 0, 256, [&](int i, R v) { zo[i] = xo[i] + v; });
+      rows_times<16>(MH, h0, nb, nd, xd, 0, 256, [&](int i, R v) { zo[i] = xo[i] + v; });
     }
     __syncthreads();
     if (doH) {
-      rows_times<8>(O.Aoo + (size_t)e * nb * nb, nb, nb, zo, 0, 256, [&](int i, R v) { wo[i] = v; });
+      rows_times<8>(MAoo, (size_t)e * nb * nb, nb, nb, zo, 0, 256, [&](int i, R v) { wo[i] = v; });
       __syncthreads();
     }
     if (tid < nd) {
       if (doH) {
-        const R* H = He + tid;
 #pragma unroll 4
-        for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd] * wo[i];
+        for (int i = 0; i < nb; ++i) acc += MH(h0 + tid + (size_t)i * nd) * wo[i];
       }
       if (doBT) {
         const int iu = rmap[nb + tid];
@@ -243,7 +241,7 @@ __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, co
     if (elem_off(P, e)) continue;
     gather_elem_d(P, t, e, td);
     __syncthreads();
-    rows_times<8>(O.H + (size_t)e * nb * nd, nb, nd, td, 0, 256,
+    rows_times<8>(MatP<R>{O.H}, (size_t)e * nb * nd, nb, nd, td, 0, 256,
                   [&](int i, R v) { y[e * nb + i] = to[e * nb + i] - v; });
     __syncthreads();
   }
@@ -270,6 +268,7 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
   for (int64_t ci = c0 + blockIdx.x; ci < c1; ci += gridDim.x) {
     const int64_t g = P.colour_facets[ci];
     if (facet_off(P, g)) continue;
+    if (P.work_count && threadIdx.x == 0) atomicAdd(P.work_count + (blockIdx.x & 255) * 16, 1ull);
     int64_t e = 0;
     R a[NFB];
     R yv = R(0);
@@ -706,7 +705,15 @@ static int elem_grid(int64_t ne) { return (int)std::min<int64_t>(ne, 1 << 20); }
 
 template <typename R>
 void launch_elem_apply(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* x, R* y, R* escr, int flags) {
-  hipLaunchKernelGGL(k_elem_apply<R>, dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, x, y, escr, flags);
+  if constexpr (sizeof(R) == 8) {
+    if (!O.Ad) {   // split storage: FP64 entries as FP32 hi + lo
+      hipLaunchKernelGGL((k_elem_apply<R, MatHL>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, MatHL{O.hAd, O.lAd},
+                         MatHL{O.hH, O.lH}, MatHL{O.hAoo, O.lAoo}, x, y, escr, flags);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_elem_apply<R, MatP<R>>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, MatP<R>{O.Ad},
+                     MatP<R>{O.H}, MatP<R>{O.Aoo}, x, y, escr, flags);
 }
 template <typename R>
 void launch_facet_sum(hipStream_t st, const SolveParams& P, const R* escr, const R* base, R sign, R* y) {

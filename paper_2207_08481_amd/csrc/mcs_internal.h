@@ -117,6 +117,8 @@ struct DevPtrs {
   float *Ad32, *H32, *Aoo32, *Aooinv32;
   double *Dinv, *EF, *W;
   float *Dinv32, *EF32, *W32;
+  float *Adl, *Hl, *Aool;   // low parts of the split storage (lean layout)
+  double* adtmp;            // per-slot FP64 A^d buffer of the condensation (lean layout)
   // multigrid coarsest
   double* Cinv;           // [nc][nc]
   int32_t* cmap;          // [nc] coarsest free dof -> lattice dof index
@@ -126,7 +128,8 @@ struct DevPtrs {
   double* escr2;          // [ne][nd]
   double* fscr;           // [nff][d*d]
   double* red;            // reduction partials
-  double* scal;           // scalar block (64 doubles)
+  double* scal;           // scalar block (256 doubles)
+  unsigned long long* wcount;  // smoother work counters (measurement)
   double* vec;            // MINRES / preconditioner work vectors (FP64), nvec64 * ndof
   float* vec32;           // FP32 work vectors, nvec32 * ndof
   double* p1;             // P1 work vectors (FP64) 4 * np1
@@ -164,6 +167,11 @@ struct mcs_problem {
   int64_t slot_doubles;
   int64_t nred;
   int nvec64, nvec32;
+  // Lean layout (precision 1): A^d, H, A_oo stored once as FP32 hi + lo; no
+  // FP64 preconditioner data; FP64 work vectors only for the refinement,
+  // slots vbase64 .. vbase64 + nvec64 - 1.
+  bool lean = false;
+  int vbase64 = 0;
   size_t ws_bytes;
   // binding
   void* ws = nullptr;

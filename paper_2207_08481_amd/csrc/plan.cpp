@@ -518,19 +518,31 @@ int layout_workspace(mcs_problem* pb) {
   L.add("rlatmap", I(r.latmap.size()));
   L.add("nu", Dd(ne));
   L.add("detJ", Dd(ne));
-  L.add("Ad", Dd(ne * s.nd * s.nd));
-  L.add("H", Dd(ne * s.nb * s.nd));
-  L.add("Aoo", Dd(ne * s.nb * s.nb));
-  L.add("Aooinv", Dd(ne * s.nb * s.nb));
+  // Precision 1 needs FP64 operators only for the outer residual: A^d, H,
+  // A_oo as FP32 hi + lo pairs (hi doubles as the FP32 operator), no FP64
+  // preconditioner data.
+  pb->lean = pb->opt.precision == 1;
+  if (!pb->lean) {
+    L.add("Ad", Dd(ne * s.nd * s.nd));
+    L.add("H", Dd(ne * s.nb * s.nd));
+    L.add("Aoo", Dd(ne * s.nb * s.nb));
+    L.add("Aooinv", Dd(ne * s.nb * s.nb));
+  }
   L.add("Ad32", Ff(ne * s.nd * s.nd));
   L.add("H32", Ff(ne * s.nb * s.nd));
   L.add("Aoo32", Ff(ne * s.nb * s.nb));
   L.add("Aooinv32", Ff(ne * s.nb * s.nb));
-  L.add("Dinv", Dd(nff * s.nfb * s.nfb));
+  if (pb->lean) {
+    L.add("Adl", Ff(ne * s.nd * s.nd));
+    L.add("Hl", Ff(ne * s.nb * s.nd));
+    L.add("Aool", Ff(ne * s.nb * s.nb));
+  } else {
+    L.add("Dinv", Dd(nff * s.nfb * s.nfb));
+  }
   L.add("EF", Dd(nff * s.nfb * d * d));
   L.add("Dinv32", Ff(nff * s.nfb * s.nfb));
   L.add("EF32", Ff(nff * s.nfb * d * d));
-  L.add("W", Dd(ne * (d + 1) * d * s.nd));
+  if (!pb->lean) L.add("W", Dd(ne * (d + 1) * d * s.nd));
   L.add("W32", Ff(ne * (d + 1) * d * s.nd));
   const int st = d == 3 ? 27 : 9;
   for (size_t l = 0; l < pb->mg.size(); ++l) {
@@ -555,13 +567,18 @@ int layout_workspace(mcs_problem* pb) {
   pb->slot_doubles = (int64_t)s.nA * s.nsig + (int64_t)s.nlam * s.nsig * 2 + (int64_t)s.nA * s.nlam +
                      (int64_t)s.nA * s.nA + (int64_t)s.nlam * s.nlam + (int64_t)s.nb * s.nb * 2 + 64;
   L.add("cscratch", Dd(pb->n_slots * pb->slot_doubles));
+  if (pb->lean) L.add("adtmp", Dd(pb->n_slots * s.nd * s.nd));
   L.add("escr", Dd(ne * s.nd));
   L.add("escr2", Dd(ne * s.nd));
   L.add("fscr", Dd(nff * d * d));
   pb->nred = 4096;
   L.add("red", Dd(pb->nred));
   L.add("scal", Dd(256));
-  pb->nvec64 = 24;
+  L.add("wcount", 2 * 256 * 16 * 8);
+  // FP64 slots: the MINRES and K-hat vectors, then b, r, x, K x of the
+  // refinement (the only ones the lean layout keeps)
+  pb->vbase64 = pb->lean ? 15 : 0;
+  pb->nvec64 = pb->lean ? 4 : 24;
   pb->nvec32 = 20;
   L.add("vec", Dd(pb->ndof * pb->nvec64));
   L.add("vec32", Ff(pb->ndof * pb->nvec32));

@@ -31,7 +31,8 @@ SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs
            "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_destroy",
            "mcs_status_string", "mcs_last_error",
            "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
-           "mcs_batch_solve", "mcs_batch_set_mode", "mcs_batch_destroy"]
+           "mcs_batch_solve", "mcs_batch_set_mode", "mcs_batch_timer_enable", "mcs_batch_timer_read",
+           "mcs_batch_destroy"]
 
 
 class MCSError(RuntimeError):
@@ -112,13 +113,15 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_batch_condense.argtypes = [vp, vp]
     lib.mcs_batch_solve.argtypes = [vp, vp, vp, vp]
     lib.mcs_batch_set_mode.argtypes = [vp, i32, i32]
+    lib.mcs_batch_timer_enable.argtypes = [vp, i32]
+    lib.mcs_batch_timer_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_batch_destroy.argtypes = [vp]
     lib.mcs_batch_destroy.restype = None
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
                  "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
                  "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
-                 "mcs_batch_set_mode"):
+                 "mcs_batch_set_mode", "mcs_batch_timer_enable", "mcs_batch_timer_read"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -342,6 +345,16 @@ class Batch:
 
     def set_mode(self, use_graph=True, chunk=6):
         _check(self._lib.mcs_batch_set_mode(self._h, 1 if use_graph else 0, chunk))
+
+    def timer_enable(self, on=True):
+        _check(self._lib.mcs_batch_timer_enable(self._h, 1 if on else 0))
+
+    def timer_read(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        b = C.c_double()
+        _check(self._lib.mcs_batch_timer_read(self._h, C.byref(ms), C.byref(n), C.byref(b)))
+        return ms.value, n.value, b.value
 
     def condense(self, nus):
         import torch

@@ -264,3 +264,31 @@ def test_condensation_is_bitwise_reproducible():
     for o in outs[1:]:
         for n in names:
             assert torch.equal(o[n], outs[0][n]), n
+
+
+def test_lean_layout_operators():
+    """Precision 1 keeps A^d, H, A_oo as FP32 hi + lo pairs: its FP64 K apply
+    (used for the refinement residual) matches the FP64 layout to 1e-13, its
+    FP32 K apply is bitwise the FP32 operator of the FP64 layout, and its FP32
+    preconditioner agrees to FP32 round-off; the FP64 preconditioner is refused."""
+    _need_gpu()
+    from paper_2207_08481_amd import Problem
+    from paper_2207_08481_amd.mcs import MCSError
+    c = setup_case(3, 2, 3)
+    m = c["mesh"]
+    lean = Problem(m.vertices, m.elements, m.lattice, 3, precision=1).bind("cuda:0")
+    lean.condense(torch.as_tensor(c["nu"], device="cuda:0"))
+    full = c["pb"]
+    g = torch.Generator(device="cpu").manual_seed(7)
+    x = torch.randn(full.n_dof, generator=g, dtype=torch.float64).to("cuda:0")
+    y_full = full.apply("K", x)
+    y_lean = lean.apply("K", x)
+    assert ((y_lean - y_full).norm() / y_full.norm()).item() < 1e-13
+    x32 = x.float()
+    assert torch.equal(full.apply("K", x32), lean.apply("K", x32))
+    z_full = full.precond_apply("KHAT", x32)
+    z_lean = lean.precond_apply("KHAT", x32)
+    assert ((z_lean - z_full).norm() / z_full.norm()).item() < 1e-5
+    with pytest.raises(MCSError):
+        lean.precond_apply("KHAT", x)
+    assert lean.info.workspace_bytes < full.info.workspace_bytes
