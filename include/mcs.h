@@ -284,6 +284,63 @@ int mcs_batch_timer_read(mcs_batch* b, double* total_ms, int64_t* launches, doub
 
 void mcs_batch_destroy(mcs_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of solve requests under an HBM budget.
+ * A server owns a caller-provided device arena (its memory budget) and a
+ * scheduler thread.  Requests are queued on submit (their host data is
+ * copied); the scheduler takes waiting requests in arrival order into a
+ * micro-batch while their standalone footprint (workspace + inputs +
+ * solution, known from planning) fits the largest free block of the arena,
+ * and runs it on a worker thread with the batch solver.  Up to max_inflight
+ * micro-batches run at once, each on its own streams, so requests arriving
+ * while others are on the device are admitted as soon as a slot and memory
+ * are free and their work overlaps with the running batches.  A request's
+ * result is the same alone or in any mix (see the batch section).  A request
+ * that cannot fit even an empty arena fails with MCS_ERR_WORKSPACE.
+ * ------------------------------------------------------------------------- */
+typedef struct mcs_server mcs_server;
+
+typedef struct {
+  int32_t status;           /* mcs_status; 1 while pending */
+  int32_t iterations, outer_steps;
+  int32_t batch_size;       /* members of the micro-batch that solved it */
+  double rel_residual, rel_precond_residual;
+  double queue_ms;          /* submit -> start of its micro-batch */
+  double solve_ms;          /* iteration wall time of its micro-batch */
+  double latency_ms;        /* submit -> result on the host */
+} mcs_request_info;
+
+typedef struct {
+  size_t arena_bytes, arena_used, arena_peak;
+  int64_t batches, solved, waiting;
+  int32_t inflight;
+} mcs_server_stats_t;
+
+/* options: shared solver options (order ignored: per request).  arena: device
+ * memory of the current device, 4096-byte aligned, owned by the caller and
+ * kept alive until mcs_server_destroy returns. */
+int mcs_server_create(const mcs_options* options, void* arena, size_t arena_bytes, int32_t max_inflight,
+                      int32_t max_batch, mcs_server** out);
+
+/* Queues a solve: mesh (as mcs_plan), order, nu_host[n_elements], f_host
+ * [n_elements][n_lat][dim] (host memory, copied).  Plans the request on the
+ * calling thread (errors as mcs_plan). */
+int mcs_server_submit(mcs_server* s, const mcs_mesh* mesh, int32_t order, const double* nu_host,
+                      const double* f_host, int64_t* id);
+
+/* done = 1 once the request's result is on the host. */
+int mcs_server_poll(mcs_server* s, int64_t id, int32_t* done);
+
+/* Blocks until the request is done, copies its solution (double[n_dof], the
+ * layout of mcs_plan; may be NULL) and info, and forgets the request.
+ * Returns the request's status. */
+int mcs_server_wait(mcs_server* s, int64_t id, double* x_host, mcs_request_info* info);
+
+int mcs_server_stats(mcs_server* s, mcs_server_stats_t* stats);
+
+/* Solves every queued request, waits for them, stops the scheduler. */
+void mcs_server_destroy(mcs_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,4 +5,4 @@ discretisation with its conforming auxiliary-space preconditioner
 The numerical path lives in libmcs.so (HIP kernels for gfx950 behind the C ABI
 of include/mcs.h); `mcs.Problem` is its Python binding.
 """
-from .mcs import Batch, Problem, load_library, MCSError, OP, PC  # noqa: F401
+from .mcs import Batch, Problem, Server, load_library, MCSError, OP, PC  # noqa: F401

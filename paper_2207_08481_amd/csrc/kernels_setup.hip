@@ -54,6 +54,40 @@ __device__ void tile_nt(const double* __restrict__ A, int lda, const double* __r
   }
 }
 
+// acc = A(m0.., :) * B(:, n0..) for row-major A (M x K, lda) and B (K x N, ldb).
+__device__ void tile_nn(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
+                        int m0, int n0, int M, int N, int K, double acc[4][4], double* lds) {
+  double* la = lds;            // [16][64]
+  double* lb = lds + 16 * 64;  // [16][64]
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int idx = tid; idx < 1024; idx += 256) {
+      int r = idx >> 4, kk = idx & 15;
+      int gm = m0 + r, gk = k0 + kk;
+      la[kk * 64 + r] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : 0.0;
+      int kb = idx >> 6, c = idx & 63;
+      int gkb = k0 + kb, gn = n0 + c;
+      lb[kb * 64 + c] = (gkb < K && gn < N) ? B[(size_t)gkb * ldb + gn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = la[kk * 64 + ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = lb[kk * 64 + tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+}
+
 // In-place Cholesky (lower) of an n x n row-major SPD matrix in memory
 // visible to the block; returns false on breakdown.  Upper part zeroed.
 __device__ bool block_cholesky(double* S, int n, int ld) {
@@ -313,14 +347,28 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
           }
       }
     __syncthreads();
-    // A = A^div + (nu/|T|) (G G^T - Y Y^T)
+    // R = G (I - Q^T Q) = G - Y Q  (in place of G): the sigma columns with the
+    // nt-constraint directions projected out
+    for (int m0 = 0; m0 < s.nA; m0 += 64)
+      for (int n0 = 0; n0 < s.nsig; n0 += 64) {
+        double acc[4][4];
+        tile_nn(Y, s.nlam, Lm, s.nsig, m0, n0, s.nA, s.nsig, s.nlam, acc, lds);
+        const int tx = tid & 15, ty = tid >> 4;
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) {
+            int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
+            if (r < s.nA && c < s.nsig) G[(size_t)r * s.nsig + c] -= acc[i][j];
+          }
+      }
+    __syncthreads();
+    // A = A^div + (nu/|T|) R R^T   (= G (I - Q^T Q) G^T without the
+    // cancellation of two large Gram matrices)
     const double nuT = P.nu[e];
     const double cf = nuT / g.vol;
     for (int m0 = 0; m0 < s.nA; m0 += 64)
       for (int n0 = m0; n0 < s.nA; n0 += 64) {
-        double acc[4][4], acc2[4][4];
+        double acc[4][4];
         tile_nt(G, s.nsig, G, s.nsig, m0, n0, s.nA, s.nA, s.nsig, acc, lds);
-        tile_nt(Y, s.nlam, Y, s.nlam, m0, n0, s.nA, s.nA, s.nlam, acc2, lds);
         const int tx = tid & 15, ty = tid >> 4;
         for (int i = 0; i < 4; ++i)
           for (int j = 0; j < 4; ++j) {
@@ -328,7 +376,7 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
             // upper triangle only (in a diagonal block the (c, r) thread would
             // write the mirrored pair too): one writer per entry pair
             if (r < s.nA && c < s.nA && r <= c) {
-              double v = cf * (acc[i][j] - acc2[i][j]);
+              double v = cf * acc[i][j];
               // A^div on velocity rows
               int ir = -1, ic = -1;
               double sr = 1.0, sc2 = 1.0;

@@ -149,33 +149,6 @@ void mono_grad(const std::vector<double>& lam, const MI& a, int d, double* g) {
   }
 }
 
-// Cholesky of an SPD matrix (row-major n x n) and inverse of its factor.
-std::vector<double> inverse_cholesky_factor(std::vector<double> G, int n) {
-  for (int j = 0; j < n; ++j) {
-    double s = G[j * n + j];
-    for (int p = 0; p < j; ++p) s -= G[j * n + p] * G[j * n + p];
-    if (s <= 0) throw std::runtime_error("reference Gram matrix not SPD");
-    double l = std::sqrt(s);
-    G[j * n + j] = l;
-    for (int i = j + 1; i < n; ++i) {
-      double t = G[i * n + j];
-      for (int p = 0; p < j; ++p) t -= G[i * n + p] * G[j * n + p];
-      G[i * n + j] = t / l;
-    }
-    for (int i = 0; i < j; ++i) G[i * n + j] = 0.0;
-  }
-  // invert lower triangular L
-  std::vector<double> Li(n * n, 0.0);
-  for (int c = 0; c < n; ++c) {
-    for (int i = 0; i < n; ++i) {
-      double t = (i == c) ? 1.0 : 0.0;
-      for (int p = 0; p < i; ++p) t -= G[i * n + p] * Li[p * n + c];
-      Li[i * n + c] = t / G[i * n + i];
-    }
-  }
-  return Li;
-}
-
 std::vector<double> dense_inverse(std::vector<double> A, int n) {
   std::vector<double> I(n * n, 0.0);
   for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
@@ -207,38 +180,112 @@ std::vector<double> dense_inverse(std::vector<double> A, int n) {
   return I;
 }
 
-// Degree-graded monomials x^e (|e| <= k) in nvar variables.
-std::vector<MI> graded_monomials(int nvar, int k) {
-  std::vector<MI> out;
-  for (int deg = 0; deg <= k; ++deg)
-    for (auto& e : multi_indices(nvar, deg)) out.push_back(e);
-  return out;
-}
+// Orthonormal, degree-graded basis of P^k on the reference nvar-simplex
+// w.r.t. (1/|T|) int, as coefficients over the degree-k Bernstein polynomials
+// B_beta = k!/beta! lambda^beta (beta over nvar+1 barycentric components):
+// psi_a = sum_beta C[a][beta] B_beta.  Built degree by degree: the Bernstein
+// polynomials of degree j = 0..k (raised to degree k) are orthonormalised
+// against all earlier functions by Gram-Schmidt, twice, in extended precision
+// with the exact Gram matrix; the functions that add nothing (already in the
+// span of lower degrees) are dropped.  So psi_0 .. psi_{dim P^{k-1} - 1} span
+// P^{k-1} and the rest is its orthogonal complement in P^k.  (A Cholesky
+// factor of the monomial Gram matrix would lose orthogonality: its condition
+// number is ~5e10 at k = 5 in 3D.)
+struct PolyBasis {
+  int nvar = 0, k = 0, n = 0;
+  std::vector<MI> bern;          // degree-k multi-indices (nvar+1 components)
+  std::vector<long double> C;    // [n][n]
+  std::vector<long double> bfac; // k!/beta!
+  // values of all psi_a at barycentric point lam (nvar+1 components)
+  void eval(const std::vector<double>& lam, double* out) const {
+    std::vector<long double> b(n);
+    for (int j = 0; j < n; ++j) {
+      long double v = bfac[j];
+      for (int t = 0; t <= nvar; ++t)
+        for (int p = 0; p < bern[j][t]; ++p) v *= (long double)lam[t];
+      b[j] = v;
+    }
+    for (int a = 0; a < n; ++a) {
+      long double t = 0;
+      for (int j = 0; j < n; ++j) t += C[(size_t)a * n + j] * b[j];
+      out[a] = (double)t;
+    }
+  }
+};
 
-double xmono(const double* x, const MI& e) {
-  double v = 1.0;
-  for (size_t j = 0; j < e.size(); ++j)
-    for (int p = 0; p < e[j]; ++p) v *= x[j];
+long double lfact(int n) {
+  long double v = 1;
+  for (int i = 2; i <= n; ++i) v *= i;
   return v;
 }
 
-// Orthonormal, degree-graded basis of P^k in nvar variables on the reference
-// nvar-simplex w.r.t. (1/|T|) int: returns coefficient matrix C (n x n) so that
-// psi_a(x) = sum_e C[a][e] x^e.
-std::vector<double> orthonormal_basis(int nvar, int k, std::vector<MI>& mons) {
-  mons = graded_monomials(nvar, k);
-  int n = (int)mons.size();
-  Rule R = simplex_rule(nvar, k + 2);
-  double meas = 1.0 / fact(nvar);
-  std::vector<double> G(n * n, 0.0);
-  for (size_t q = 0; q < R.w.size(); ++q) {
-    const double* x = &R.lam[q][1];
-    std::vector<double> v(n);
-    for (int a = 0; a < n; ++a) v[a] = xmono(x, mons[a]);
-    for (int a = 0; a < n; ++a)
-      for (int b = 0; b < n; ++b) G[a * n + b] += R.w[q] * v[a] * v[b] / meas;
+PolyBasis orthonormal_basis(int nvar, int k) {
+  PolyBasis P;
+  P.nvar = nvar;
+  P.k = k;
+  P.bern = multi_indices(nvar + 1, k);
+  const int n = (int)P.bern.size();
+  P.n = n;
+  std::map<MI, int> idx;
+  for (int j = 0; j < n; ++j) idx[P.bern[j]] = j;
+  P.bfac.resize(n);
+  for (int j = 0; j < n; ++j) {
+    long double den = 1;
+    for (int t = 0; t <= nvar; ++t) den *= lfact(P.bern[j][t]);
+    P.bfac[j] = lfact(k) / den;
   }
-  return inverse_cholesky_factor(G, n);
+  // exact Gram matrix: (1/|T|) int B_a B_b = (k!)^2/(a! b!) (a+b)! nvar! / (2k+nvar)!
+  std::vector<long double> G((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      long double v = P.bfac[i] * P.bfac[j] * lfact(nvar) / lfact(2 * k + nvar);
+      for (int t = 0; t <= nvar; ++t) v *= lfact(P.bern[i][t] + P.bern[j][t]);
+      G[(size_t)i * n + j] = v;
+    }
+  auto dot = [&](const std::vector<long double>& x, const std::vector<long double>& y) {
+    long double s = 0;
+    for (int i = 0; i < n; ++i) {
+      long double t = 0;
+      for (int j = 0; j < n; ++j) t += G[(size_t)i * n + j] * y[j];
+      s += x[i] * t;
+    }
+    return s;
+  };
+  std::vector<std::vector<long double>> Q;
+  for (int deg = 0; deg <= k; ++deg) {
+    for (auto& g : multi_indices(nvar + 1, deg)) {
+      // B^deg_g raised to degree k: sum over h (|h| = k - deg) of
+      // (deg!/g!) ((k-deg)!/h!) / (k!/(g+h)!) B^k_{g+h}
+      std::vector<long double> v(n, 0.0L);
+      long double cg = lfact(deg);
+      for (int t = 0; t <= nvar; ++t) cg /= lfact(g[t]);
+      for (auto& h : multi_indices(nvar + 1, k - deg)) {
+        MI gh(nvar + 1);
+        long double ch = lfact(k - deg);
+        for (int t = 0; t <= nvar; ++t) {
+          gh[t] = g[t] + h[t];
+          ch /= lfact(h[t]);
+        }
+        const int j = idx[gh];
+        v[j] += cg * ch / P.bfac[j];
+      }
+      const long double n0 = std::sqrt(dot(v, v));
+      for (int pass = 0; pass < 2; ++pass)
+        for (auto& q : Q) {
+          const long double c = dot(q, v);
+          for (int i = 0; i < n; ++i) v[i] -= c * q[i];
+        }
+      const long double nv = std::sqrt(dot(v, v));
+      if (nv < 1e-9L * n0) continue;   // in the span of the lower degrees
+      for (int i = 0; i < n; ++i) v[i] /= nv;
+      Q.push_back(v);
+    }
+  }
+  if ((int)Q.size() != n) throw std::runtime_error("orthonormal basis: wrong dimension");
+  P.C.resize((size_t)n * n);
+  for (int a = 0; a < n; ++a)
+    for (int j = 0; j < n; ++j) P.C[(size_t)a * n + j] = Q[a][j];
+  return P;
 }
 
 }  // namespace
@@ -354,31 +401,14 @@ RefTables build_ref_tables(int d, int k) {
   };
 
   // ---------------- orthonormal psi (volume) and top-degree q (facet)
-  std::vector<MI> mons;
-  std::vector<double> Cpsi = orthonormal_basis(d, k, mons);
-  auto psi_eval = [&](const std::vector<double>& lam, double* out) {
-    const double* x = &lam[1];
-    std::vector<double> mv(s.ns);
-    for (int e = 0; e < s.ns; ++e) mv[e] = xmono(x, mons[e]);
-    for (int a = 0; a < s.ns; ++a) {
-      double t = 0;
-      for (int e = 0; e <= a; ++e) t += Cpsi[a * s.ns + e] * mv[e];
-      out[a] = t;
-    }
-  };
-  std::vector<MI> fmons;
-  std::vector<double> Cq = orthonormal_basis(d - 1, k, fmons);
+  const PolyBasis Bpsi = orthonormal_basis(d, k);
+  auto psi_eval = [&](const std::vector<double>& lam, double* out) { Bpsi.eval(lam, out); };
+  const PolyBasis Bq = orthonormal_basis(d - 1, k);
   const int nq = s.nFk - s.nFkm1;
   auto q_eval = [&](const std::vector<double>& mu, double* out) {  // mu: facet barycentrics (d)
-    const double* x = &mu[1];
-    std::vector<double> mv(s.nFk);
-    for (int e = 0; e < s.nFk; ++e) mv[e] = xmono(x, fmons[e]);
-    for (int qq = 0; qq < nq; ++qq) {
-      int a = s.nFkm1 + qq;
-      double t = 0;
-      for (int e = 0; e <= a; ++e) t += Cq[a * s.nFk + e] * mv[e];
-      out[qq] = t;
-    }
+    std::vector<double> all(s.nFk);
+    Bq.eval(mu, all.data());
+    for (int qq = 0; qq < nq; ++qq) out[qq] = all[s.nFkm1 + qq];
   };
 
   auto Ip = multi_indices(nv, k - 1);   // pressure

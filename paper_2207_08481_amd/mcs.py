@@ -32,7 +32,8 @@ SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs
            "mcs_status_string", "mcs_last_error",
            "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
            "mcs_batch_solve", "mcs_batch_set_mode", "mcs_batch_timer_enable", "mcs_batch_timer_read",
-           "mcs_batch_destroy"]
+           "mcs_batch_destroy", "mcs_server_create", "mcs_server_submit", "mcs_server_poll",
+           "mcs_server_wait", "mcs_server_stats", "mcs_server_destroy"]
 
 
 class MCSError(RuntimeError):
@@ -65,6 +66,23 @@ class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("outer_steps", C.c_int32),
                 ("rel_precond_residual", C.c_double), ("rel_residual", C.c_double),
                 ("t_solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("outer_steps", C.c_int32),
+                ("batch_size", C.c_int32), ("rel_residual", C.c_double), ("rel_precond_residual", C.c_double),
+                ("queue_ms", C.c_double), ("solve_ms", C.c_double), ("latency_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("arena_bytes", C.c_size_t), ("arena_used", C.c_size_t), ("arena_peak", C.c_size_t),
+                ("batches", C.c_int64), ("solved", C.c_int64), ("waiting", C.c_int64), ("inflight", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -117,11 +135,19 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_batch_timer_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_batch_destroy.argtypes = [vp]
     lib.mcs_batch_destroy.restype = None
+    lib.mcs_server_create.argtypes = [C.POINTER(Options), vp, C.c_size_t, i32, i32, C.POINTER(vp)]
+    lib.mcs_server_submit.argtypes = [vp, C.POINTER(Mesh), i32, vp, vp, C.POINTER(i64)]
+    lib.mcs_server_poll.argtypes = [vp, i64, C.POINTER(i32)]
+    lib.mcs_server_wait.argtypes = [vp, i64, vp, C.POINTER(RequestInfo)]
+    lib.mcs_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    lib.mcs_server_destroy.argtypes = [vp]
+    lib.mcs_server_destroy.restype = None
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
                  "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
                  "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
-                 "mcs_batch_set_mode", "mcs_batch_timer_enable", "mcs_batch_timer_read"):
+                 "mcs_batch_set_mode", "mcs_batch_timer_enable", "mcs_batch_timer_read", "mcs_server_create",
+                 "mcs_server_submit", "mcs_server_poll", "mcs_server_wait", "mcs_server_stats"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -382,6 +408,71 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             self._lib.mcs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching solve server (mcs_server_*): requests are queued,
+    admitted in micro-batches against a device arena of `arena_bytes` (the HBM
+    budget) and solved by the batch solver on library threads; up to
+    max_inflight micro-batches run at once.  The calls release the GIL."""
+
+    def __init__(self, arena_bytes, device="cuda:0", max_inflight=2, max_batch=64, precision=1,
+                 smoothing_steps=2, tol=1e-8, max_it=5000, inner_tol=1e-5, max_outer=10, coarse_max=512):
+        import torch
+        lib = load_library()
+        self._lib = lib
+        dev = torch.device(device)
+        torch.cuda.set_device(dev)
+        self.device = dev
+        self._arena = torch.empty(arena_bytes + 4096, dtype=torch.uint8, device=dev)
+        base = self._arena.data_ptr()
+        aligned = (base + 4095) // 4096 * 4096
+        self._opt = Options(0, precision, smoothing_steps, max_it, tol, inner_tol, max_outer, coarse_max)
+        torch.cuda.synchronize()
+        h = C.c_void_p()
+        _check(lib.mcs_server_create(C.byref(self._opt), aligned, arena_bytes, max_inflight, max_batch,
+                                     C.byref(h)))
+        self._h = h
+
+    def submit(self, vertices, elements, lattice, order, nu, f_lattice):
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        e = np.ascontiguousarray(elements, dtype=np.int32)
+        nu = np.ascontiguousarray(np.broadcast_to(np.asarray(nu, dtype=np.float64), (e.shape[0],)))
+        f = np.ascontiguousarray(f_lattice, dtype=np.float64)
+        lat = list(lattice) + [1] * (3 - len(lattice))
+        mesh = Mesh(v.shape[1], v.shape[0], v.ctypes.data, e.shape[0], e.ctypes.data, (C.c_int32 * 3)(*lat))
+        rid = C.c_int64()
+        _check(self._lib.mcs_server_submit(self._h, C.byref(mesh), order, nu.ctypes.data, f.ctypes.data,
+                                           C.byref(rid)))
+        return rid.value
+
+    def poll(self, rid):
+        d = C.c_int32()
+        _check(self._lib.mcs_server_poll(self._h, rid, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self, rid, n_dof):
+        """Blocks until request rid is done; returns (solution numpy array, info dict)."""
+        x = np.zeros(n_dof, dtype=np.float64)
+        info = RequestInfo()
+        self._lib.mcs_server_wait(self._h, rid, x.ctypes.data, C.byref(info))
+        return x, info.as_dict()
+
+    def stats(self):
+        st = ServerStats()
+        _check(self._lib.mcs_server_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mcs_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -322,3 +322,25 @@ def batch_member(spec: dict):
     nu = np.full(mesh.n_elements, spec["nu"])
     f = RandomForce(3, seed=spec["force_seed"]).f(lattice_points(mesh, spec["k"] + 1))
     return dict(mesh=mesh, nu=nu, k=spec["k"], f_lattice=f)
+
+
+def serving_requests(n_requests: int, seed: int = 6, t_min: float = 1e3, t_max: float = 2e5, orders=(2, 3, 4, 5),
+                     contrast: float = 1e3):
+    """Request recipe of the serving stream: T ~ logU[t_min, t_max] tets, a
+    unit cube of n = max(2, round((T/6)^(1/3))) cubes per axis, k uniform in
+    `orders`, per-tet lognormal viscosity clipped to `contrast`, random smooth
+    force; each request carries its own seeds.  Returns a list of dicts."""
+    rng = np.random.default_rng(seed)
+    ts = np.exp(rng.uniform(math.log(t_min), math.log(t_max), n_requests))
+    ns = np.maximum(2, np.rint(np.cbrt(ts / 6.0))).astype(int)
+    ks = rng.choice(np.asarray(orders), size=n_requests)
+    return [dict(n=int(ns[i]), k=int(ks[i]), nu_seed=20000 + seed * 7919 + i, force_seed=40000 + seed * 7919 + i,
+                 contrast=contrast) for i in range(n_requests)]
+
+
+def serving_request(spec: dict):
+    """Mesh, per-element viscosity and degree-(k+1) lattice force of one request."""
+    mesh = unit_cube_mesh(spec["n"])
+    nu = lognormal_nu(mesh.n_elements, seed=spec["nu_seed"], contrast=spec["contrast"])
+    f = RandomForce(3, seed=spec["force_seed"]).f(lattice_points(mesh, spec["k"] + 1))
+    return dict(mesh=mesh, nu=nu, k=spec["k"], f_lattice=f)
