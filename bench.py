@@ -41,6 +41,10 @@ WORKLOADS = {
     "cube32_k4_mixed": ("cube32_k4_lognormal", 1, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 contrast), random smooth f, FP32 inner + FP64 refinement, tol 1e-10"),
     "cube32_k4_fp64": ("cube32_k4_lognormal", 0, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 contrast), random smooth f, FP64, tol 1e-10"),
     "square8_k2": ("square8_k2", 0, "unit square 8x8 x 2 triangles, k=2, nu=1, FP64, tol 1e-10"),
+    "serve": ("serve", 1, "serving stream: requests on unit cubes of T ~ logU[1e3, 2e5] tets (n = max(2, round((T/6)^(1/3)))), "
+                          "k uniform in {2,3,4,5}, per-tet lognormal nu clipped to 1e3 contrast, random smooth forces, "
+                          "tol 1e-8, FP32 inner + FP64 refinement; closed-loop saturation first, then Poisson arrivals "
+                          "at 0.7 x the saturated rate; continuous batching under an HBM arena budget"),
     "batch256_mixed": ("batch", 1, "batch of 256 unit-cube problems, n^3 x 6 tets with n = round(exp(U[ln 4, ln 16])), "
                                    "k uniform in {2,3,4}, nu = exp(N(0, 0.5^2)) per problem, random smooth forces; "
                                    "FP32 inner MINRES + FP64 refinement per problem, tol 1e-8; iterations of all "
@@ -192,6 +196,112 @@ def run_batch(args, precision, desc):
     print(json.dumps(out), flush=True)
 
 
+def run_serve(args, precision, desc):
+    """Serving stream (mcs_server_*).  Phase 1 (closed loop): n_closed
+    requests submitted at once; saturated solves/s = n_closed / makespan.
+    Phase 2 (open loop): n_open requests with Poisson arrivals at 0.7 x the
+    saturated rate; value = completed solves / elapsed, with p50/p99 of the
+    per-request latency (submit -> solution on the host, planning included)."""
+    import threading
+    import numpy as np
+    import workloads as W
+    from paper_2207_08481_amd import Problem, Server
+    rng = np.random.default_rng(7)
+    n_closed, n_open = args.serve_closed, args.serve_requests
+    specs = W.serving_requests(n_closed + n_open, seed=6)
+    log(f"serving: generating {len(specs)} requests (host)")
+    reqs = []
+    for sp in specs:
+        r = W.serving_request(sp)
+        m = r["mesh"]
+        r["n_dof"] = Problem(m.vertices, m.elements, m.lattice, r["k"]).n_dof
+        reqs.append(r)
+    srv = Server(int(args.serve_arena_gb * (1 << 30)), max_inflight=args.serve_inflight, max_batch=64,
+                 precision=precision, tol=1e-8, max_it=5000)
+
+    def submit(r):
+        m = r["mesh"]
+        return srv.submit(m.vertices, m.elements, m.lattice, r["k"], r["nu"], r["f_lattice"])
+
+    results = {}
+
+    def waiter(i, rid, n_dof):
+        results[i] = srv.wait(rid, n_dof)[1]
+        r = results[i]
+        log(f"request {i} (n={specs[i]['n']}, k={specs[i]['k']}) done: status {r['status']}, "
+            f"{r['iterations']} its, batch {r['batch_size']}, latency {r['latency_ms']:.0f} ms")
+
+    # phase 1: closed loop
+    log(f"closed loop: {n_closed} requests at once")
+    t0 = time.perf_counter()
+    ths = []
+    for i in range(n_closed):
+        rid = submit(reqs[i])
+        th = threading.Thread(target=waiter, args=(i, rid, reqs[i]["n_dof"]))
+        th.start()
+        ths.append(th)
+    for th in ths:
+        th.join()
+    sat = n_closed / (time.perf_counter() - t0)
+    log(f"saturated: {sat:.3f} solves/s")
+    # phase 2: Poisson arrivals
+    lam = 0.7 * sat
+    log(f"open loop: {n_open} requests, Poisson rate {lam:.3f}/s")
+    gaps = rng.exponential(1.0 / lam, n_open)
+    t0 = time.perf_counter()
+    t_next = t0
+    ths = []
+    for j in range(n_open):
+        i = n_closed + j
+        t_next += gaps[j]
+        dt = t_next - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        rid = submit(reqs[i])
+        th = threading.Thread(target=waiter, args=(i, rid, reqs[i]["n_dof"]))
+        th.start()
+        ths.append(th)
+        if (j + 1) % 8 == 0:
+            log(f"submitted {j + 1}/{n_open}, completed {sum(1 for q in results if q >= n_closed)}")
+    for th in ths:
+        th.join()
+    wall = time.perf_counter() - t0
+    lat = np.array([results[n_closed + j]["latency_ms"] for j in range(n_open)])
+    qms = np.array([results[n_closed + j]["queue_ms"] for j in range(n_open)])
+    bsz = np.array([results[n_closed + j]["batch_size"] for j in range(n_open)])
+    its = np.array([results[n_closed + j]["iterations"] for j in range(n_open)])
+    ndof = np.array([reqs[n_closed + j]["n_dof"] for j in range(n_open)])
+    ok = sum(1 for j in range(n_open) if results[n_closed + j]["status"] == 0)
+    st = srv.stats()
+    srv.close()
+    out = {
+        "metric": "solves/s of served MCS solves (p50/p99 latency beside)",
+        "value": n_open / wall,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": n_open,
+        "warmup": n_closed,
+        "ms_per_step": wall * 1e3 / n_open,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "requests_open_loop": n_open, "requests_closed_loop": n_closed,
+                   "saturated_solves_per_s": sat, "arrival_rate_per_s": lam,
+                   "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+                   "queue_ms_p50": float(np.percentile(qms, 50)), "mean_batch_size": float(bsz.mean()),
+                   "dof_iterations_per_s": float((ndof * its).sum() / wall), "converged": ok,
+                   "arena_gb": args.serve_arena_gb, "arena_peak_gb": st["arena_peak"] / 1e9,
+                   "max_inflight": args.serve_inflight, "batches": st["batches"]},
+        "roofline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +312,10 @@ def main():
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (calibrates "
                          "FETCH_SIZE / WRITE_SIZE counters against a plain copy of known size)")
+    ap.add_argument("--serve-requests", type=int, default=32, help="serve: open-loop requests")
+    ap.add_argument("--serve-closed", type=int, default=12, help="serve: closed-loop requests")
+    ap.add_argument("--serve-arena-gb", type=float, default=200.0, help="serve: HBM budget (GB)")
+    ap.add_argument("--serve-inflight", type=int, default=3, help="serve: concurrent micro-batches")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
@@ -217,6 +331,8 @@ def main():
     log(f"workload {args.workload}")
     if key == "batch":
         return run_batch(args, precision, desc)
+    if key == "serve":
+        return run_serve(args, precision, desc)
     wl = W.workload(key)
     mesh = wl["mesh"]
     k = wl["k"]

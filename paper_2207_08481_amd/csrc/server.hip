@@ -311,6 +311,7 @@ int mcs_server_submit(mcs_server* s, const mcs_mesh* mesh, int32_t order, const 
     return MCS_ERR_ARG;
   }
   std::unique_ptr<Request> r(new Request());
+  r->t_submit = clk::now();   // latency includes the planning below
   const int d = mesh->dim;
   r->dim = d;
   r->order = order;
@@ -339,7 +340,6 @@ int mcs_server_submit(mcs_server* s, const mcs_mesh* mesh, int32_t order, const 
   r->info.status = 1;   // pending
   std::lock_guard<std::mutex> lk(s->mu);
   r->id = s->next_id++;
-  r->t_submit = clk::now();
   *id = r->id;
   s->waiting.push_back(r.get());
   s->reqs[r->id] = std::move(r);
