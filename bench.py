@@ -182,7 +182,8 @@ def run_batch(args, precision, desc):
                    "solves_per_s": b.info.n_problems / (t_sol / args.steps / 1e3),
                    "t_sup_ms": t_sup / args.steps, "t_sol_ms": t_sol / args.steps,
                    "max_rel_residual": max(rel),
-                   "not_converged": sum(1 for inf in infos if inf["status"] != 0)},
+                   "not_converged": sum(1 for inf in infos if inf["status"] != 0),
+                   "smoother_launch_per_group": b.launch_configs(1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_smooth_phase, FP32 (one colour of one block Gauss-Seidel sweep, all groups)",
@@ -338,7 +339,7 @@ def main():
     k = wl["k"]
     dev = "cuda:0"
     pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, k, precision=precision,
-                 tol=1e-10, max_it=5000).bind(dev)
+                 tol=1e-10, max_it=5000, autotune=1).bind(dev)
     nu = torch.as_tensor(wl["nu"], device=dev)
     f = torch.as_tensor(wl["f_lattice"], device=dev)
     ndof = pb.n_dof
@@ -403,7 +404,8 @@ def main():
                    "t_sup_ms": t_sup / args.steps, "t_sol_ms": t_sol / args.steps,
                    "rel_precond_residual": infos[-1]["rel_precond_residual"],
                    "rel_residual": infos[-1]["rel_residual"],
-                   "outer_steps": infos[-1]["outer_steps"]},
+                   "outer_steps": infos[-1]["outer_steps"],
+                   "smoother_launch": pb.launch_config(0 if precision == 0 else 1)},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

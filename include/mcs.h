@@ -124,6 +124,7 @@ typedef struct {
   double inner_tol;         /* precision 1: inner MINRES relative tolerance (1e-5) */
   int32_t max_outer;        /* precision 1: refinement step limit (10) */
   int32_t coarse_max;       /* multigrid: coarsest level when free dofs <= coarse_max (512) */
+  int32_t autotune;         /* 1: the first mcs_condense times the smoother's launch shapes and keeps the fastest */
 } mcs_options;
 
 typedef struct {
@@ -215,6 +216,13 @@ int mcs_get_topology(const mcs_problem* pb, int32_t* colour_host, int32_t* elem_
 int mcs_timer_enable(mcs_problem* pb, int enable);
 int mcs_timer_read(mcs_problem* pb, double* total_ms, int64_t* launches, double* bytes);
 
+/* Launch shape of the coloured block Gauss-Seidel phase kernel for work
+ * precision dt (MCS_F64 / MCS_F32): facet blocks per workgroup (1 or 2) and
+ * the grid cap (0: one workgroup per facet block); us = the tuner's measured
+ * time per launch of the largest colour (0 if not tuned).  The shapes the
+ * autotuner tries are bitwise equivalent. */
+int mcs_get_launch_config(const mcs_problem* pb, int dt, int32_t* facets_per_block, int64_t* grid_cap, double* us);
+
 void mcs_destroy(mcs_problem* pb);
 const char* mcs_status_string(int status);
 const char* mcs_last_error(void);
@@ -275,6 +283,11 @@ int mcs_batch_solve(mcs_batch* b, const double* const* f_host, double* const* x_
  * use_graph = 0 launches the same kernels one by one.  chunk is a positive
  * multiple of 6 (default 6).  Both modes give identical results. */
 int mcs_batch_set_mode(mcs_batch* b, int use_graph, int chunk);
+
+/* Launch configuration of group g (0 <= g < n_groups) for work precision dt:
+ * its dimension and order, and the smoother launch shape (mcs_get_launch_config). */
+int mcs_batch_launch_config(const mcs_batch* b, int32_t g, int dt, int32_t* dim, int32_t* order,
+                            int32_t* facets_per_block, int64_t* grid_cap, double* us);
 
 /* Smoother timing over all groups (see mcs_timer_enable; the bytes count
  * only the facet blocks of members still iterating).  While enabled,

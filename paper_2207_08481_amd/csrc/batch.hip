@@ -782,6 +782,18 @@ int mcs_batch_solve(mcs_batch* B, const double* const* f, double* const* xo, mcs
   return rc;
 }
 
+int mcs_batch_launch_config(const mcs_batch* B, int32_t g, int dt, int32_t* dim, int32_t* order,
+                            int32_t* facets_per_block, int64_t* grid_cap, double* us) {
+  if (!B || g < 0 || g >= (int32_t)B->groups.size()) {
+    set_error("batch launch config: bad group");
+    return MCS_ERR_ARG;
+  }
+  const mcs_problem* u = B->groups[g].u.get();
+  if (dim) *dim = u->d;
+  if (order) *order = u->sz.k;
+  return mcs_get_launch_config(u, dt, facets_per_block, grid_cap, us);
+}
+
 int mcs_batch_timer_enable(mcs_batch* B, int enable) {
   if (!B || !B->ws) {
     set_error("batch is not bound");

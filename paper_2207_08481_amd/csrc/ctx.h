@@ -164,6 +164,8 @@ struct Ctx {
   void sweeps(R* x, const R* s, R* y, bool forward) {
     SolveParams Pt = P;
     if (pb->timer_on) Pt.work_count = work_counters(pb) + (sizeof(R) == 8 ? 0 : 256 * 16);
+    const int fpw = pb->tune_fpw[sizeof(R) == 8 ? 0 : 1];
+    const int64_t cap = pb->tune_cap[sizeof(R) == 8 ? 0 : 1];
     for (int it = 0; it < pb->opt.smoothing_steps; ++it)
       for (int cc = 0; cc < pb->ncol; ++cc) {
         int c = forward ? cc : pb->ncol - 1 - cc;
@@ -175,12 +177,12 @@ struct Ctx {
             pb->tev.push_back(e);
           }
           hipEventRecord(pb->tev[k], st);
-          launch_smooth_phase<R>(st, Pt, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y);
+          launch_smooth_phase<R>(st, Pt, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y, fpw, cap);
           hipEventRecord(pb->tev[k + 1], st);
           pb->tpending++;
           pb->t_launches++;
         } else {
-          launch_smooth_phase<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y);
+          launch_smooth_phase<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y, fpw, cap);
         }
       }
   }

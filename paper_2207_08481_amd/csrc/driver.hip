@@ -34,6 +34,68 @@ using namespace mcs;
 
 namespace {
 
+// Smoother launch-shape tuner: times every candidate shape on the largest
+// colour (scratch vectors, one warm-up and three timed launches) and keeps the
+// fastest for work precision R.
+template <typename R>
+int tune_smoother_precision(mcs_problem* pb, int slot) {
+  Ctx<R> c(pb);
+  int best_col = -1;
+  int64_t nbest = 0;
+  for (int col = 0; col < pb->ncol; ++col) {
+    const int64_t n = pb->colour_off[col + 1] - pb->colour_off[col];
+    if (n > nbest) {
+      nbest = n;
+      best_col = col;
+    }
+  }
+  if (best_col < 0) return MCS_OK;
+  hipStream_t st = c.st;
+  R* x = c.v(PT);
+  R* sv = c.v(PS);
+  R* y = c.escr;
+  launch_fill<R>(st, c.n, R(0), x);
+  launch_fill<R>(st, c.n, R(0), sv);
+  launch_fill<R>(st, pb->ne * pb->sz.nd, R(0), y);
+  const int T1 = smooth_team_threads(pb->sz.nd);
+  std::vector<std::pair<int, int64_t>> cand;
+  for (int fpw : {1, 2}) {
+    if (fpw == 2 && 2 * T1 > 512) continue;
+    for (int64_t cap : {int64_t(0), int64_t(2048), int64_t(4096), int64_t(8192)}) cand.push_back({fpw, cap});
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int32_t c0 = pb->colour_off[best_col], c1 = pb->colour_off[best_col + 1];
+  double best = 1e300;
+  for (auto& cf : cand) {
+    launch_smooth_phase<R>(st, c.P, c.O, c0, c1, x, sv, y, cf.first, cf.second);
+    HIPCHK(hipEventRecord(e0, st));
+    for (int r = 0; r < 3; ++r) launch_smooth_phase<R>(st, c.P, c.O, c0, c1, x, sv, y, cf.first, cf.second);
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    const double us = ms * 1e3 / 3.0;
+    if (us < best) {
+      best = us;
+      pb->tune_fpw[slot] = cf.first;
+      pb->tune_cap[slot] = cf.second;
+      pb->tune_us[slot] = us;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return MCS_OK;
+}
+
+int tune_smoother(mcs_problem* pb) {
+  int rc = MCS_OK;
+  if (!pb->lean) rc = tune_smoother_precision<double>(pb, 0);
+  if (rc) return rc;
+  return tune_smoother_precision<float>(pb, 1);
+}
+
 int check_bound(mcs_problem* pb) {
   if (!pb) {
     set_error("null problem");
@@ -401,6 +463,10 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   }
   rc = sync_status(pb, "condense");
   if (rc) return rc;
+  if (pb->opt.autotune && pb->tune_us[1] == 0.0) {   // once per plan; later condensations reuse it
+    rc = tune_smoother(pb);
+    if (rc) return rc;
+  }
   pb->condensed = true;
   return MCS_OK;
 }
@@ -740,6 +806,18 @@ int mcs_timer_read(mcs_problem* pb, double* total_ms, int64_t* launches, double*
   if (total_ms) *total_ms = pb->t_ms;
   if (launches) *launches = pb->t_launches;
   if (bytes) *bytes = pb->t_bytes;
+  return MCS_OK;
+}
+
+int mcs_get_launch_config(const mcs_problem* pb, int dt, int32_t* facets_per_block, int64_t* grid_cap, double* us) {
+  if (!pb || (dt != MCS_F64 && dt != MCS_F32)) {
+    set_error("launch config: bad argument");
+    return MCS_ERR_ARG;
+  }
+  const int slot = dt == MCS_F64 ? 0 : 1;
+  if (facets_per_block) *facets_per_block = pb->tune_fpw[slot];
+  if (grid_cap) *grid_cap = pb->tune_cap[slot];
+  if (us) *us = pb->tune_us[slot];
   return MCS_OK;
 }
 

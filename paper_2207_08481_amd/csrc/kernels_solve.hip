@@ -251,28 +251,35 @@ __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, co
 // products y_T = A^d_T x_T (race free: facets of one colour share no element):
 //   r_F = s_F - y_T1[F] - y_T2[F];  delta = D_F^{-1} r_F;  x_F += delta;
 //   y_Ti += A^d_Ti[:, F] delta   (columns of F = rows of F, A^d symmetric).
-// Threads [0, n_d) own the rows of the first neighbour, [n_d, 2 n_d) those of
-// the second; each thread loads its n_fb matrix entries before the short
-// dependent chain (residual -> D_F^{-1} -> update) starts.
-template <typename R, int NFB>
+// A workgroup holds FPW facet teams of T1 = round_up(2 n_d, 64) threads; in a
+// team, threads [0, n_d) own the rows of the first neighbour and [n_d, 2 n_d)
+// those of the second; each thread loads its n_fb matrix entries before the
+// short dependent chain (residual -> D_F^{-1} -> update) starts.  Workgroups
+// loop over the colour's facets in steps of the grid, so the launch shape
+// (FPW, grid) changes only which team handles a facet, never the arithmetic.
+template <typename R, int NFB, int FPW>
 __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, int32_t c0, int32_t c1,
-                                                  R* __restrict__ x, const R* __restrict__ srhs, R* __restrict__ y) {
+                                                  R* __restrict__ x, const R* __restrict__ srhs, R* __restrict__ y,
+                                                  int T1) {
   const int nd = P.s.nd;
-  __shared__ R rr[NFB];
-  __shared__ R dl[NFB];
-  __shared__ R dsh[NFB * NFB];
-  const int tid = threadIdx.x;
+  __shared__ R rr[FPW][NFB];
+  __shared__ R dl[FPW][NFB];
+  __shared__ R dsh[FPW][NFB * NFB];
+  const int h = threadIdx.x / T1;
+  const int tid = threadIdx.x - h * T1;
   const int side = tid >= nd ? 1 : 0;
   const int t = tid - side * nd;
   const bool is_row = tid < 2 * nd;
-  for (int64_t ci = c0 + blockIdx.x; ci < c1; ci += gridDim.x) {
-    const int64_t g = P.colour_facets[ci];
-    if (facet_off(P, g)) continue;
-    if (P.work_count && threadIdx.x == 0) atomicAdd(P.work_count + (blockIdx.x & 255) * 16, 1ull);
+  for (int64_t base = c0 + (int64_t)blockIdx.x * FPW; base < c1; base += (int64_t)gridDim.x * FPW) {
+    const int64_t ci = base + h;
+    bool work = ci < c1;
+    const int64_t g = work ? P.colour_facets[ci] : 0;
+    if (work && facet_off(P, g)) work = false;
+    if (work && P.work_count && tid == 0) atomicAdd(P.work_count + (blockIdx.x & 255) * 16, 1ull);
     int64_t e = 0;
     R a[NFB];
     R yv = R(0);
-    if (is_row) {
+    if (work && is_row) {
       e = P.facet_el[2 * g + side];
       const int sl = P.facet_slot[2 * g + side];
       const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
@@ -280,27 +287,27 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
       for (int q = 0; q < NFB; ++q) a[q] = Ab[(size_t)q * nd];
       yv = y[e * nd + t];
     }
-    {
+    if (work) {
       const R* Di = O.Dinv + (size_t)g * NFB * NFB;
-      for (int i = tid; i < NFB * NFB; i += blockDim.x) dsh[i] = Di[i];
+      for (int i = tid; i < NFB * NFB; i += T1) dsh[h][i] = Di[i];
     }
-    if (tid < NFB) {
+    if (work && tid < NFB) {
       const int64_t e1 = P.facet_el[2 * g], e2 = P.facet_el[2 * g + 1];
       const int s1 = P.facet_slot[2 * g], s2 = P.facet_slot[2 * g + 1];
-      rr[tid] = srhs[P.off_f + g * NFB + tid] - y[e1 * nd + s1 * NFB + tid] - y[e2 * nd + s2 * NFB + tid];
+      rr[h][tid] = srhs[P.off_f + g * NFB + tid] - y[e1 * nd + s1 * NFB + tid] - y[e2 * nd + s2 * NFB + tid];
     }
     __syncthreads();
-    if (tid < NFB) {
+    if (work && tid < NFB) {
       R acc = R(0);
 #pragma unroll
-      for (int j = 0; j < NFB; ++j) acc += dsh[j * NFB + tid] * rr[j];
-      dl[tid] = acc;
+      for (int j = 0; j < NFB; ++j) acc += dsh[h][j * NFB + tid] * rr[h][j];
+      dl[h][tid] = acc;
       x[P.off_f + g * NFB + tid] += acc;
     }
     __syncthreads();
-    if (is_row) {
+    if (work && is_row) {
 #pragma unroll
-      for (int q = 0; q < NFB; ++q) yv += a[q] * dl[q];
+      for (int q = 0; q < NFB; ++q) yv += a[q] * dl[h][q];
       y[e * nd + t] = yv;
     }
     __syncthreads();
@@ -727,21 +734,34 @@ template <typename R>
 void launch_ext_post(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* t, const R* to, R* y) {
   hipLaunchKernelGGL(k_ext_post<R>, dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
 }
+// facets_per_block (1 or 2) and grid_cap choose the launch shape; every
+// shape gives the same result.
+template <typename R, int NFB>
+static void smooth_launch(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
+                          const R* s, R* y, int fpw, int64_t cap, int T1) {
+  const int64_t blocks = std::min<int64_t>((c1 - c0 + fpw - 1) / fpw, cap);
+  if (fpw == 2)
+    hipLaunchKernelGGL((k_smooth_y<R, NFB, 2>), dim3((unsigned)blocks), dim3(2 * T1), 0, st, P, O, c0, c1, x, s, y, T1);
+  else
+    hipLaunchKernelGGL((k_smooth_y<R, NFB, 1>), dim3((unsigned)blocks), dim3(T1), 0, st, P, O, c0, c1, x, s, y, T1);
+}
+int smooth_team_threads(int nd) { return ((2 * nd + 63) / 64) * 64; }
 template <typename R>
 void launch_smooth_phase(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
-                         const R* s, R* y) {
+                         const R* s, R* y, int fpw, int64_t cap) {
   if (c1 <= c0) return;
-  const int threads = (int)std::min<int64_t>(512, ((2 * P.s.nd + 63) / 64) * 64);
-  dim3 grid((int)std::min<int64_t>(c1 - c0, 1 << 20)), block(threads);
+  const int T1 = smooth_team_threads(P.s.nd);
+  if (fpw != 2 || 2 * T1 > 512) fpw = 1;
+  if (cap <= 0) cap = 1 << 20;
   switch (P.s.nfb) {
-    case 5: hipLaunchKernelGGL((k_smooth_y<R, 5>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
-    case 7: hipLaunchKernelGGL((k_smooth_y<R, 7>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
-    case 9: hipLaunchKernelGGL((k_smooth_y<R, 9>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
-    case 11: hipLaunchKernelGGL((k_smooth_y<R, 11>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
-    case 12: hipLaunchKernelGGL((k_smooth_y<R, 12>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
-    case 22: hipLaunchKernelGGL((k_smooth_y<R, 22>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
-    case 35: hipLaunchKernelGGL((k_smooth_y<R, 35>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
-    case 51: hipLaunchKernelGGL((k_smooth_y<R, 51>), grid, block, 0, st, P, O, c0, c1, x, s, y); break;
+    case 5: smooth_launch<R, 5>(st, P, O, c0, c1, x, s, y, fpw, cap, T1); break;
+    case 7: smooth_launch<R, 7>(st, P, O, c0, c1, x, s, y, fpw, cap, T1); break;
+    case 9: smooth_launch<R, 9>(st, P, O, c0, c1, x, s, y, fpw, cap, T1); break;
+    case 11: smooth_launch<R, 11>(st, P, O, c0, c1, x, s, y, fpw, cap, T1); break;
+    case 12: smooth_launch<R, 12>(st, P, O, c0, c1, x, s, y, fpw, cap, T1); break;
+    case 22: smooth_launch<R, 22>(st, P, O, c0, c1, x, s, y, fpw, cap, T1); break;
+    case 35: smooth_launch<R, 35>(st, P, O, c0, c1, x, s, y, 1, cap, T1); break;
+    case 51: smooth_launch<R, 51>(st, P, O, c0, c1, x, s, y, 1, cap, T1); break;
     default: break;
   }
 }
@@ -836,7 +856,7 @@ void launch_scale_convert(hipStream_t st, int64_t n, double a, const A* x, B* y,
   template void launch_ext_pre<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, R*, R*);        \
   template void launch_ext_post<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, const R*, R*); \
   template void launch_smooth_phase<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, int32_t, int32_t, R*, \
-                                       const R*, R*);                                                          \
+                                       const R*, R*, int, int64_t);                                            \
   template void launch_ycorr<R>(hipStream_t, const SolveParams&, const R*, const int32_t*, const int32_t*,       \
                                 const R*, R*);                                                                  \
   template void launch_edt<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, R*, int64_t,         \

@@ -14,7 +14,8 @@ template <typename R>
 void launch_ext_post(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* t, const R* to, R* y);
 template <typename R>
 void launch_smooth_phase(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
-                         const R* s, R* y);
+                         const R* s, R* y, int facets_per_block = 1, int64_t grid_cap = 0);
+int smooth_team_threads(int nd);
 template <typename R>
 void launch_ycorr(hipStream_t st, const SolveParams& P, const R* W, const int32_t* elem_verts,
                   const int32_t* vfree_of_lat, const R* x0, R* y);

@@ -179,6 +179,11 @@ struct mcs_problem {
   int device = -1;
   bool condensed = false;
   mcs::DevPtrs p;
+  // launch shape of the smoother colour phase per work precision [FP64, FP32]
+  // (set by the autotuner; every shape gives the same result)
+  int tune_fpw[2] = {1, 1};
+  int64_t tune_cap[2] = {0, 0};
+  double tune_us[2] = {0.0, 0.0};
   // kernel timer (smoother phase launches)
   bool timer_on = false;
   std::vector<hipEvent_t> tev;        // pairs (start, stop)

@@ -28,10 +28,11 @@ PC = {"KHAT": 0, "AEXT": 1, "ADELTA_MULT": 2, "SMOOTH_FWD": 3, "SMOOTH_BWD": 4, 
 # exported symbols of include/mcs.h
 SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
            "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
-           "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_destroy",
+           "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_destroy",
            "mcs_status_string", "mcs_last_error",
            "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
-           "mcs_batch_solve", "mcs_batch_set_mode", "mcs_batch_timer_enable", "mcs_batch_timer_read",
+           "mcs_batch_solve", "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable",
+           "mcs_batch_timer_read",
            "mcs_batch_destroy", "mcs_server_create", "mcs_server_submit", "mcs_server_poll",
            "mcs_server_wait", "mcs_server_stats", "mcs_server_destroy"]
 
@@ -50,7 +51,7 @@ class Mesh(C.Structure):
 class Options(C.Structure):
     _fields_ = [("order", C.c_int32), ("precision", C.c_int32), ("smoothing_steps", C.c_int32),
                 ("max_it", C.c_int32), ("tol", C.c_double), ("inner_tol", C.c_double),
-                ("max_outer", C.c_int32), ("coarse_max", C.c_int32)]
+                ("max_outer", C.c_int32), ("coarse_max", C.c_int32), ("autotune", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -118,6 +119,9 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_get_topology.argtypes = [vp, vp, vp]
     lib.mcs_timer_enable.argtypes = [vp, i32]
     lib.mcs_timer_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
+    lib.mcs_get_launch_config.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i64), C.POINTER(C.c_double)]
+    lib.mcs_batch_launch_config.argtypes = [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                            C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_destroy.argtypes = [vp]
     lib.mcs_destroy.restype = None
     lib.mcs_status_string.argtypes = [i32]
@@ -144,9 +148,10 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_server_destroy.restype = None
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
                  "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
-                 "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_batch_plan",
+                 "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
-                 "mcs_batch_set_mode", "mcs_batch_timer_enable", "mcs_batch_timer_read", "mcs_server_create",
+                 "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable", "mcs_batch_timer_read",
+                 "mcs_server_create",
                  "mcs_server_submit", "mcs_server_poll", "mcs_server_wait", "mcs_server_stats"):
         getattr(lib, name).restype = i32
     _lib = lib
@@ -179,7 +184,7 @@ class Problem:
     solve.  Names follow the C ABI."""
 
     def __init__(self, vertices, elements, lattice, order, precision=0, smoothing_steps=2,
-                 tol=1e-10, max_it=2000, inner_tol=1e-5, max_outer=10, coarse_max=512):
+                 tol=1e-10, max_it=2000, inner_tol=1e-5, max_outer=10, coarse_max=512, autotune=0):
         lib = load_library()
         self._lib = lib
         v = np.ascontiguousarray(vertices, dtype=np.float64)
@@ -190,7 +195,7 @@ class Problem:
         self._mesh = Mesh(self.dim, v.shape[0], v.ctypes.data, e.shape[0], e.ctypes.data,
                           (C.c_int32 * 3)(*lat))
         self._opt = Options(order, precision, smoothing_steps, max_it, tol, inner_tol, max_outer,
-                            coarse_max)
+                            coarse_max, autotune)
         self.info = Info()
         h = C.c_void_p()
         _check(lib.mcs_plan(C.byref(self._mesh), C.byref(self._opt), C.byref(h), C.byref(self.info)))
@@ -293,6 +298,11 @@ class Problem:
             typestr = "<f8"
         return torch.as_tensor(_CudaArray(p.value, n.value, typestr), device=self.device)
 
+    def launch_config(self, dt=F64):
+        f, c, us = C.c_int32(), C.c_int64(), C.c_double()
+        _check(self._lib.mcs_get_launch_config(self._h, dt, C.byref(f), C.byref(c), C.byref(us)))
+        return {"facets_per_block": f.value, "grid_cap": c.value, "us_per_launch": us.value}
+
     def timer_enable(self, on=True):
         _check(self._lib.mcs_timer_enable(self._h, 1 if on else 0))
 
@@ -327,7 +337,7 @@ class Batch:
     member.  meshes: list of (vertices, elements, lattice); orders: list of k."""
 
     def __init__(self, meshes, orders, precision=1, smoothing_steps=2, tol=1e-8, max_it=2000,
-                 inner_tol=1e-5, max_outer=10, coarse_max=512):
+                 inner_tol=1e-5, max_outer=10, coarse_max=512, autotune=1):
         lib = load_library()
         self._lib = lib
         self._keep = []
@@ -345,7 +355,7 @@ class Batch:
         self.orders = [int(k) for k in orders]
         ords = np.asarray(self.orders, dtype=np.int32)
         self._keep.append(ords)
-        self._opt = Options(0, precision, smoothing_steps, max_it, tol, inner_tol, max_outer, coarse_max)
+        self._opt = Options(0, precision, smoothing_steps, max_it, tol, inner_tol, max_outer, coarse_max, autotune)
         self.info = BatchInfo()
         h = C.c_void_p()
         _check(lib.mcs_batch_plan(arr, ords.ctypes.data, len(meshes), C.byref(self._opt), C.byref(h),
@@ -371,6 +381,18 @@ class Batch:
 
     def set_mode(self, use_graph=True, chunk=6):
         _check(self._lib.mcs_batch_set_mode(self._h, 1 if use_graph else 0, chunk))
+
+    def launch_configs(self, dt=F32):
+        """Per group: dimension, order and the smoother launch shape chosen by the tuner."""
+        out = []
+        for g in range(self.info.n_groups):
+            d, k, f = C.c_int32(), C.c_int32(), C.c_int32()
+            c, us = C.c_int64(), C.c_double()
+            _check(self._lib.mcs_batch_launch_config(self._h, g, dt, C.byref(d), C.byref(k), C.byref(f), C.byref(c),
+                                                     C.byref(us)))
+            out.append({"dim": d.value, "order": k.value, "facets_per_block": f.value, "grid_cap": c.value,
+                        "us_per_launch": us.value})
+        return out
 
     def timer_enable(self, on=True):
         _check(self._lib.mcs_batch_timer_enable(self._h, 1 if on else 0))
@@ -424,7 +446,8 @@ class Server:
     max_inflight micro-batches run at once.  The calls release the GIL."""
 
     def __init__(self, arena_bytes, device="cuda:0", max_inflight=2, max_batch=64, precision=1,
-                 smoothing_steps=2, tol=1e-8, max_it=5000, inner_tol=1e-5, max_outer=10, coarse_max=512):
+                 smoothing_steps=2, tol=1e-8, max_it=5000, inner_tol=1e-5, max_outer=10, coarse_max=512,
+                 autotune=0):
         import torch
         lib = load_library()
         self._lib = lib
@@ -434,7 +457,7 @@ class Server:
         self._arena = torch.empty(arena_bytes + 4096, dtype=torch.uint8, device=dev)
         base = self._arena.data_ptr()
         aligned = (base + 4095) // 4096 * 4096
-        self._opt = Options(0, precision, smoothing_steps, max_it, tol, inner_tol, max_outer, coarse_max)
+        self._opt = Options(0, precision, smoothing_steps, max_it, tol, inner_tol, max_outer, coarse_max, autotune)
         torch.cuda.synchronize()
         h = C.c_void_p()
         _check(lib.mcs_server_create(C.byref(self._opt), aligned, arena_bytes, max_inflight, max_batch,

@@ -315,3 +315,26 @@ def test_solve_high_order(d, n, k):
     assert si["status"] == 0, si
     eu, ep = _l2_rel(gs, x.cpu().numpy(), gs.direct_solve())
     assert eu < max(2e-12, 3 * fu) and ep < max(2e-11, 3 * fp), (eu, ep, fu, fp, si)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autotuned_launch_shapes_give_identical_results(precision):
+    """The tuner only picks the smoother's launch shape (facet blocks per
+    workgroup, grid cap); the solution is bitwise the same as with the default
+    shape."""
+    _need_gpu()
+    from paper_2207_08481_amd import Problem
+    c = setup_case(3, 2, 2)
+    m = c["mesh"]
+    xs = []
+    for tune in (0, 1):
+        pb = Problem(m.vertices, m.elements, m.lattice, 2, precision=precision, autotune=tune).bind("cuda:0")
+        pb.condense(torch.as_tensor(c["nu"], device="cuda:0"))
+        cfg = pb.launch_config(1)
+        assert cfg["facets_per_block"] in (1, 2)
+        if tune:
+            assert cfg["us_per_launch"] > 0
+        x, si = pb.solve(torch.as_tensor(c["f"], device="cuda:0"))
+        assert si["status"] == 0
+        xs.append(x)
+    assert torch.equal(xs[0], xs[1])
