@@ -189,6 +189,16 @@ int mcs_solve(mcs_problem* pb, const double* f_lattice, double* x, mcs_solve_inf
 /* Same as mcs_solve with a given right-hand side b (device double[n_dof]). */
 int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* info);
 
+/* Point values of a solution, for comparisons that do not depend on the
+ * basis: u_h and p_h of x (device double[n_dof]) at n_pts points of every
+ * element, given as barycentric coordinates ref_pts_host[n_pts][dim+1] (host)
+ * w.r.t. the element's vertices in the order of `elements`.  u_vals (device)
+ * [n_elements][n_pts][dim], p_vals (device) [n_elements][n_pts].  u_h is the
+ * BDM field (Sec. 3, V_h); u-hat lives on facets only.  n_pts <= 1024
+ * (3D) / 1365 (2D).  [sync] */
+int mcs_eval(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_pts_host, double* u_vals,
+             double* p_vals);
+
 /* Subtracts the mean of the pressure from x (device double[n_dof]). */
 int mcs_normalize_pressure(mcs_problem* pb, double* x);
 

@@ -238,6 +238,8 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   p.rct = ws_ptr<double>(pb, "rct");
   p.rpconst = ws_ptr<double>(pb, "rpconst");
   p.rpmom = ws_ptr<double>(pb, "rpmom");
+  p.rphi = ws_ptr<double>(pb, "rphi");
+  p.rpidx = ws_ptr<double>(pb, "rpidx");
   p.rlatmap = ws_ptr<int32_t>(pb, "rlatmap");
   p.nu = ws_ptr<double>(pb, "nu");
   p.detJ = ws_ptr<double>(pb, "detJ");
@@ -306,6 +308,8 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   HIPCHK(up(p.rct, r.ct.data(), r.ct.size() * 8));
   HIPCHK(up(p.rpconst, r.pconst.data(), r.pconst.size() * 8));
   HIPCHK(up(p.rpmom, r.pmom.data(), r.pmom.size() * 8));
+  HIPCHK(up(p.rphi, r.phi.data(), r.phi.size() * 8));
+  HIPCHK(up(p.rpidx, r.pidx.data(), r.pidx.size() * 8));
   HIPCHK(up(p.rlatmap, r.latmap.data(), r.latmap.size() * 4));
   HIPCHK(up(p.cmap, pb->h_cmap.data(), pb->h_cmap.size() * 4));
   // multigrid lattice vectors start (and stay) zero on the boundary; block tables
@@ -806,6 +810,23 @@ int mcs_timer_read(mcs_problem* pb, double* total_ms, int64_t* launches, double*
   if (total_ms) *total_ms = pb->t_ms;
   if (launches) *launches = pb->t_launches;
   if (bytes) *bytes = pb->t_bytes;
+  return MCS_OK;
+}
+
+int mcs_eval(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_pts_host, double* u_vals,
+             double* p_vals) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  const int nv = pb->d + 1;
+  if (!x || !ref_pts_host || !u_vals || !p_vals || n_pts <= 0 || (int64_t)n_pts * nv > pb->nred) {
+    set_error("mcs_eval: null pointer or n_pts outside 1..%lld", (long long)(pb->nred / nv));
+    return MCS_ERR_ARG;
+  }
+  HIPCHK(hipMemcpyAsync(pb->p.red, ref_pts_host, (size_t)n_pts * nv * 8, hipMemcpyHostToDevice, pb->stream));
+  SolveParams P = solve_params(pb);
+  launch_eval(pb->stream, P, pb->p.coords, pb->p.elem_verts, pb->p.elem_perm, pb->p.rphi, pb->p.rpidx, n_pts,
+              pb->p.red, x, u_vals, p_vals);
+  HIPCHK(hipStreamSynchronize(pb->stream));
   return MCS_OK;
 }
 

@@ -620,6 +620,87 @@ __global__ void __launch_bounds__(256) k_elem_press(SolveParams P, const R* __re
   }
 }
 
+// ------------------------------------------------------------ point values
+// u and p of a solution x at barycentric points given w.r.t. each element's
+// vertices in the caller's order (pts [npts][nv]); one workgroup per element,
+// one thread per point.  Velocity basis (sorted vertices, J = [x_j - x_0]):
+// bubbles lambda^alpha J w, facet functions lambda^beta J w / det J (w the
+// reference vector of the function, rphi); pressure lambda^gamma.
+__global__ void k_eval(SolveParams P, const double* __restrict__ coords, const int32_t* __restrict__ elem_verts,
+                       const int32_t* __restrict__ elem_perm, const double* __restrict__ rphi,
+                       const double* __restrict__ rpidx, int npts, const double* __restrict__ pts,
+                       const double* __restrict__ x, double* __restrict__ u, double* __restrict__ p) {
+  const Sizes s = P.s;
+  const int d = s.d, nv = d + 1;
+  for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
+    // caller order of the sorted vertices: decode the permutation rank
+    int perm[4], avail[4];
+    {
+      int r = elem_perm[e], dig[4];
+      for (int i = nv - 1; i >= 0; --i) {
+        dig[i] = r % (nv - i);
+        r /= (nv - i);
+      }
+      for (int i = 0; i < nv; ++i) avail[i] = i;
+      int na = nv;
+      for (int i = 0; i < nv; ++i) {
+        perm[i] = avail[dig[i]];
+        for (int j = dig[i]; j + 1 < na; ++j) avail[j] = avail[j + 1];
+        --na;
+      }
+    }
+    double X[4][3], J[3][3];
+    for (int j = 0; j < nv; ++j) {
+      const int v = elem_verts[e * nv + j];
+      for (int r = 0; r < 3; ++r) X[j][r] = r < d ? coords[(size_t)v * d + r] : 0.0;
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) J[r][c] = (r < d && c < d) ? X[c + 1][r] - X[0][r] : 0.0;
+    const double idet = 1.0 / P.detJ[e];
+    for (int q = threadIdx.x; q < npts; q += blockDim.x) {
+      double lam[4];
+      for (int j = 0; j < nv; ++j) lam[j] = pts[q * nv + perm[j]];
+      double uv[3] = {0.0, 0.0, 0.0};
+      for (int i = 0; i < s.nu; ++i) {
+        double c;
+        if (i < s.nb) {
+          c = x[e * s.nb + i];
+        } else {
+          const int f = (i - s.nb) / s.nF, qq = (i - s.nb) % s.nF;
+          const int g = P.elem_ff[e * nv + f];
+          c = g >= 0 ? x[P.off_f + (int64_t)g * s.nfb + qq] * idet : 0.0;
+        }
+        if (c == 0.0) continue;
+        const double* ph = rphi + (size_t)i * (nv + 3);
+        double m = 1.0;
+        for (int j = 0; j < nv; ++j)
+          for (int t = 0; t < (int)ph[j]; ++t) m *= lam[j];
+        for (int r = 0; r < d; ++r) {
+          double jw = 0.0;
+          for (int cc = 0; cc < d; ++cc) jw += J[r][cc] * ph[nv + cc];
+          uv[r] += c * m * jw;
+        }
+      }
+      double pv = 0.0;
+      for (int g = 0; g < s.np; ++g) {
+        double m = 1.0;
+        for (int j = 0; j < nv; ++j)
+          for (int t = 0; t < (int)rpidx[g * nv + j]; ++t) m *= lam[j];
+        pv += x[P.off_p + e * s.np + g] * m;
+      }
+      for (int r = 0; r < d; ++r) u[((size_t)e * npts + q) * d + r] = uv[r];
+      p[(size_t)e * npts + q] = pv;
+    }
+  }
+}
+
+void launch_eval(hipStream_t st, const SolveParams& P, const double* coords, const int32_t* elem_verts,
+                 const int32_t* elem_perm, const double* rphi, const double* rpidx, int npts, const double* pts,
+                 const double* x, double* u, double* p) {
+  hipLaunchKernelGGL(k_eval, dim3((unsigned)std::min<int64_t>(P.ne, 1 << 20)), dim3(64), 0, st, P, coords,
+                     elem_verts, elem_perm, rphi, rpidx, npts, pts, x, u, p);
+}
+
 // ----------------------------------------------------------------- vectors
 template <typename R>
 __global__ void k_axpby(int64_t n, double a, const R* __restrict__ x, double b, R* __restrict__ y) {

@@ -71,6 +71,10 @@ void launch_check_nu(hipStream_t st, const double* nu, int64_t n, int* status);
 void launch_pressure_mean(hipStream_t st, const SolveParams& P, const double* pmom, const double* pconst, double* x,
                           double* red);
 
+void launch_eval(hipStream_t st, const SolveParams& P, const double* coords, const int32_t* elem_verts,
+                 const int32_t* elem_perm, const double* rphi, const double* rpidx, int npts, const double* pts,
+                 const double* x, double* u, double* p);
+
 // batched MINRES (kernels_batch.hip)
 template <typename R>
 void launch_seg_dot(hipStream_t st, const SegDev& S, const R* a, const R* b, int field);

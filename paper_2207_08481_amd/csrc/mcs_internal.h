@@ -55,6 +55,8 @@ struct RefTables {
   std::vector<double> ct;    // [nFkm1][d]          lambda_v in degree k-1 facet Bernstein
   std::vector<double> pconst;// [np]                coefficients of p = 1
   std::vector<double> pmom;  // [np]                int_T^ lambda^gamma / |T^|
+  std::vector<double> phi;   // [nu][nv + 3]        BDM function i: alpha (nv), reference vector w (3)
+  std::vector<double> pidx;  // [np][nv]            pressure multi-indices gamma
   double facet_measure[4];   // |F^_f|
 };
 RefTables build_ref_tables(int d, int k);
@@ -109,7 +111,7 @@ struct DevPtrs {
   int32_t* vfree_of_lat;  // [nvert] lattice vertex -> free P1 vertex or -1
   int32_t* free_to_lat;   // [nfv] free P1 vertex -> lattice vertex
   // reference tables
-  double *rV, *rBf, *rU, *rL, *rD, *rBp, *rMp, *rMpinv, *rRf, *rcn, *rct, *rpconst, *rpmom;
+  double *rV, *rBf, *rU, *rL, *rD, *rBp, *rMp, *rMpinv, *rRf, *rcn, *rct, *rpconst, *rpmom, *rphi, *rpidx;
   int32_t* rlatmap;
   // element operators
   double *nu, *detJ;

@@ -515,6 +515,8 @@ int layout_workspace(mcs_problem* pb) {
   L.add("rct", Dd(r.ct.size()));
   L.add("rpconst", Dd(r.pconst.size()));
   L.add("rpmom", Dd(r.pmom.size()));
+  L.add("rphi", Dd(r.phi.size()));
+  L.add("rpidx", Dd(r.pidx.size()));
   L.add("rlatmap", I(r.latmap.size()));
   L.add("nu", Dd(ne));
   L.add("detJ", Dd(ne));

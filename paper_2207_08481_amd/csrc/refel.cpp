@@ -535,6 +535,15 @@ RefTables build_ref_tables(int d, int k) {
         T.ct[g * d + v] = fact(k - 2) / den;
       }
   }
+  // basis descriptions for point evaluation
+  T.phi.assign((size_t)s.nu * (nv + 3), 0.0);
+  for (int i = 0; i < s.nu; ++i) {
+    for (int j = 0; j < nv; ++j) T.phi[(size_t)i * (nv + 3) + j] = phis[i].alpha[j];
+    for (int r = 0; r < 3; ++r) T.phi[(size_t)i * (nv + 3) + nv + r] = phis[i].w[r];
+  }
+  T.pidx.assign((size_t)s.np * nv, 0.0);
+  for (int g = 0; g < s.np; ++g)
+    for (int j = 0; j < nv; ++j) T.pidx[(size_t)g * nv + j] = Ip[g][j];
   T.pconst.resize(s.np);
   T.pmom.resize(s.np);
   for (int g = 0; g < s.np; ++g) {

@@ -27,7 +27,7 @@ PC = {"KHAT": 0, "AEXT": 1, "ADELTA_MULT": 2, "SMOOTH_FWD": 3, "SMOOTH_BWD": 4, 
 
 # exported symbols of include/mcs.h
 SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
-           "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
+           "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_get_array",
            "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_destroy",
            "mcs_status_string", "mcs_last_error",
            "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_solve.argtypes = [vp, vp, vp, C.POINTER(SolveInfo)]
     lib.mcs_solve_rhs.argtypes = [vp, vp, vp, C.POINTER(SolveInfo)]
     lib.mcs_normalize_pressure.argtypes = [vp, vp]
+    lib.mcs_eval.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.mcs_get_array.argtypes = [vp, C.c_char_p, C.POINTER(vp), C.POINTER(i64)]
     lib.mcs_get_topology.argtypes = [vp, vp, vp]
     lib.mcs_timer_enable.argtypes = [vp, i32]
@@ -147,7 +148,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_server_destroy.argtypes = [vp]
     lib.mcs_server_destroy.restype = None
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
-                 "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_get_array",
+                 "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_get_array",
                  "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
                  "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable", "mcs_batch_timer_read",
@@ -279,6 +280,17 @@ class Problem:
         si = SolveInfo()
         _check(self._lib.mcs_solve_rhs(self._h, b.data_ptr(), x.data_ptr(), C.byref(si)))
         return x, si.as_dict()
+
+    def eval(self, x, ref_pts):
+        """(u [n_e, n_pts, dim], p [n_e, n_pts]) of x at barycentric points
+        ref_pts [n_pts, dim+1] w.r.t. each element's vertices in caller order."""
+        import torch
+        pts = np.ascontiguousarray(ref_pts, dtype=np.float64)
+        npts = pts.shape[0]
+        u = torch.zeros((self.n_elements, npts, self.dim), dtype=torch.float64, device=self.device)
+        p = torch.zeros((self.n_elements, npts), dtype=torch.float64, device=self.device)
+        _check(self._lib.mcs_eval(self._h, x.data_ptr(), npts, pts.ctypes.data, u.data_ptr(), p.data_ptr()))
+        return u, p
 
     def normalize_pressure(self, x):
         _check(self._lib.mcs_normalize_pressure(self._h, x.data_ptr()))

@@ -338,3 +338,24 @@ def test_autotuned_launch_shapes_give_identical_results(precision):
         assert si["status"] == 0
         xs.append(x)
     assert torch.equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 2, 2), (3, 1, 3), (3, 2, 2)])
+def test_point_values_match_oracle(d, n, k):
+    """mcs_eval: u_h and p_h of a coefficient vector at barycentric points
+    given in the caller's vertex order equal the oracle's evaluation of the
+    same coefficients in its (sorted-vertex) basis."""
+    c = setup_case(d, n, k)
+    pb, gs, mesh = c["pb"], c["gs"], c["mesh"]
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(gs.n_dof)
+    pts = rng.dirichlet(np.ones(d + 1), size=5)
+    u, p = pb.eval(torch.as_tensor(x, device="cuda:0"), pts)
+    u, p = u.cpu().numpy(), p.cpu().numpy()
+    for e in range(gs.n_e):
+        caller = list(mesh.elements[e])
+        srt = sorted(caller)
+        lam = pts[:, [caller.index(v) for v in srt]]
+        uo, po = gs.eval_element(x, e, lam)
+        assert np.abs(u[e] - uo).max() <= 1e-12 * max(1.0, np.abs(uo).max()), e
+        assert np.abs(p[e] - po).max() <= 1e-12 * max(1.0, np.abs(po).max()), e
