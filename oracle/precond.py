@@ -11,6 +11,10 @@ for the double Schur complement A^d -- oracle (FP64, sequential).
   block per free facet holding its normal and tangential dofs), s sweeps in
   colour order, then the coarse correction E^d C^{-1} E^d^T on the residual,
   then s sweeps in reverse colour order (the adjoint smoother).
+* Additive variant (Sec. 5.2, the additive auxiliary-space preconditioner of
+  Theorem aux_pc / Lemma add_to_mult): A-hat^d_a^{-1} = S^{-1} + E^d C^{-1} E^d^T
+  with S the l1 block-Jacobi smoother, S_F = D_F + diag(sum_{j not in F}
+  |A^d_{ij}|) for the rows i of facet block F, so that A^d <= S.
 * E^d: rows of the embedding E u = (u, u_t) of continuous P1 (eq. defE) for the
   facet dofs (eq. defED).
 * C: one symmetric V(1,1) multigrid cycle for A-bar, the P1 form
@@ -229,11 +233,13 @@ def assemble_p1(gs):
 # ---------------------------------------------------------------------------
 
 class Preconditioner:
-    def __init__(self, gs, lattice, smoothing_steps=2, coarse_max=512):
+    def __init__(self, gs, lattice, smoothing_steps=2, coarse_max=512, variant="multiplicative"):
+        assert variant in ("multiplicative", "additive")
         self.gs = gs
         topo = gs.topo
         d = gs.d
         self.steps = smoothing_steps
+        self.variant = variant
         nfb = gs.nfb
         # assembled double Schur complement A^d on the facet dofs
         blocks_r, blocks_c, blocks_v = [], [], []
@@ -251,6 +257,15 @@ class Preconditioner:
             fd = gs.facet_dofs(g)
             D = self.Ad[fd][:, fd].toarray()
             self.Dinv.append(np.linalg.inv(D))
+        # l1 block-Jacobi smoother of the additive variant
+        self.Sinv = []
+        if variant == "additive":
+            absA = abs(self.Ad).tocsr()
+            for g in range(topo.n_free_facets):
+                fd = gs.facet_dofs(g)
+                D = self.Ad[fd][:, fd].toarray()
+                off = np.asarray(absA[fd].sum(axis=1)).ravel() - np.abs(D).sum(axis=1)
+                self.Sinv.append(np.linalg.inv(D + np.diag(off)))
         self.colour_lists = [np.nonzero(topo.colour == c)[0] for c in range(topo.n_colours)]
         # auxiliary space
         self.E = embedding(gs, full=False)
@@ -290,6 +305,22 @@ class Preconditioner:
             x = self.backward_sweep(x, s)
         return x
 
+    def l1_jacobi(self, s):
+        """S^{-1} s, block by block (the additive variant's smoother)."""
+        gs = self.gs
+        z = np.zeros_like(s)
+        for g in range(gs.topo.n_free_facets):
+            fd = gs.facet_dofs(g)
+            z[fd] = self.Sinv[g] @ s[fd]
+        return z
+
+    def Ad_add_inv(self, s):
+        """A-hat^d_a^{-1} s = S^{-1} s + E^d C^{-1} E^d^T s."""
+        return self.l1_jacobi(s) + self.aux_correction(s)
+
+    def Ad_inv(self, s):
+        return self.Ad_add_inv(s) if self.variant == "additive" else self.Ad_mult_inv(s)
+
     def A_ext_inv(self, r):
         """A-hat_ext^{-1} r for a velocity vector r (pressure part ignored/zero):
         s = r_d - sum_T H_T^T r_o,T;  t = A-hat^d_m^{-1} s;
@@ -304,7 +335,7 @@ class Preconditioner:
             m = ld >= 0
             contrib = es["H"].T @ ro
             np.add.at(s, ld[m], -contrib[m])
-        t = self.Ad_mult_inv(s)
+        t = self.Ad_inv(s)
         y = np.zeros(gs.n_dof)
         y[gs.off_f:gs.off_p] = t[gs.off_f:gs.off_p]
         for e, es in enumerate(gs.elems):

@@ -348,3 +348,40 @@ def test_preconditioned_minres_matches_direct(d, n, k):
     assert info["converged"]
     xd = gs.direct_solve()
     assert np.linalg.norm(gs.normalize_pressure(x) - xd) < 1e-9 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("d,n,k,cm", [(2, 4, 2, 20), (3, 2, 2, 512)])
+def test_additive_asp_bounds(d, n, k, cm):
+    """Additive variant (Sec. 5.2, Theorem aux_pc): the l1 block-Jacobi smoother
+    dominates A^d (eigenvalues of S^{-1} A^d in (0, 1]) and the additive
+    preconditioner S^{-1} + E^d C^{-1} E^d^T is symmetric with eigenvalues of
+    A-hat^d_a^{-1} A^d in (0, 2] (each of its two terms contributes at most 1)."""
+    mesh, gs, _ = problem(d, n, k)
+    pc = Preconditioner(gs, mesh.lattice, coarse_max=cm, variant="additive")
+    idx = np.arange(gs.off_f, gs.off_p)
+    Ad = pc.Ad.toarray()[np.ix_(idx, idx)]
+    S = _dense_op(pc.l1_jacobi, gs.n_dof, idx)
+    lam_s = np.linalg.eigvals(S @ Ad).real
+    assert lam_s.min() > 0 and lam_s.max() <= 1 + 1e-10
+    P = _dense_op(pc.Ad_add_inv, gs.n_dof, idx)
+    assert np.allclose(P, P.T, atol=1e-10 * np.abs(P).max())
+    lam = np.linalg.eigvals(P @ Ad).real
+    assert lam.min() > 1e-8 and lam.max() <= 2 + 1e-9
+
+
+def test_additive_needs_more_iterations_than_multiplicative():
+    """The paper's smoothing comparison (Table ST_smoothing): the multiplicative
+    auxiliary-space preconditioner needs fewer MINRES iterations than the
+    additive one with an l1 block smoother; both reach the direct solution."""
+    mesh, gs, _ = problem(3, 2, 2)
+    K = gs.assemble_K()
+    b = gs.assemble_rhs()
+    xd = gs.direct_solve()
+    its = {}
+    for variant in ("multiplicative", "additive"):
+        pc = Preconditioner(gs, mesh.lattice, variant=variant)
+        x, info = minres(lambda v: K @ v, pc.apply, b, tol=1e-10, max_it=2000)
+        x = gs.normalize_pressure(x)
+        assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
+        its[variant] = info["iterations"]
+    assert its["multiplicative"] < its["additive"], its
