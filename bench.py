@@ -41,6 +41,9 @@ WORKLOADS = {
     "cube32_k4_mixed": ("cube32_k4_lognormal", 1, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 contrast), random smooth f, FP32 inner + FP64 refinement, tol 1e-10"),
     "cube32_k4_fp64": ("cube32_k4_lognormal", 0, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 contrast), random smooth f, FP64, tol 1e-10"),
     "square8_k2": ("square8_k2", 0, "unit square 8x8 x 2 triangles, k=2, nu=1, FP64, tol 1e-10"),
+    "cube16_k3_additive": ("cube16_k3", 0, "unit cube 16^3 x 6 tets (24,576), k=3, nu=1, curl of 8 random sin^2 modes, "
+                                           "FP64, tol 1e-10; additive auxiliary-space preconditioner with the l1 facet "
+                                           "block-Jacobi smoother"),
     "serve": ("serve", 1, "serving stream: requests on unit cubes of T ~ logU[1e3, 2e5] tets (n = max(2, round((T/6)^(1/3)))), "
                           "k uniform in {2,3,4,5}, per-tet lognormal nu clipped to 1e3 contrast, random smooth forces, "
                           "tol 1e-8, FP32 inner + FP64 refinement; closed-loop saturation first, then Poisson arrivals "
@@ -338,8 +341,9 @@ def main():
     mesh = wl["mesh"]
     k = wl["k"]
     dev = "cuda:0"
+    smoother = 1 if args.workload.endswith("_additive") else 0
     pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, k, precision=precision,
-                 tol=1e-10, max_it=5000, autotune=1).bind(dev)
+                 tol=1e-10, max_it=5000, autotune=1, smoother=smoother).bind(dev)
     nu = torch.as_tensor(wl["nu"], device=dev)
     f = torch.as_tensor(wl["f_lattice"], device=dev)
     ndof = pb.n_dof

@@ -96,7 +96,7 @@ typedef enum {
 typedef enum {
   MCS_PC_KHAT = 0,        /* z = K-hat^{-1} r (eq. mhatinvfactor)                   */
   MCS_PC_AEXT = 1,        /* z_u = A-hat_ext^{-1} r_u (Sec. 6.1)                    */
-  MCS_PC_ADELTA_MULT = 2, /* z_d = A-hat^d_m^{-1} r_d (Corollary aux_pc_mult)       */
+  MCS_PC_ADELTA_MULT = 2, /* z_d = A-hat^d^{-1} r_d of the chosen smoother option  */
   MCS_PC_SMOOTH_FWD = 3,  /* z_d = `smoothing_steps` forward block-GS sweeps, x0=0  */
   MCS_PC_SMOOTH_BWD = 4,  /* same with the colours in reverse order                  */
   MCS_PC_AUX = 5,         /* z_d = E^d C^{-1} E^d^T r_d                              */
@@ -125,6 +125,10 @@ typedef struct {
   int32_t max_outer;        /* precision 1: refinement step limit (10) */
   int32_t coarse_max;       /* multigrid: coarsest level when free dofs <= coarse_max (512) */
   int32_t autotune;         /* 1: the first mcs_condense times the smoother's launch shapes and keeps the fastest */
+  int32_t smoother;         /* auxiliary-space preconditioner of A^d (Sec. 5.2):
+                               0: multiplicative, coloured facet block Gauss-Seidel (Corollary aux_pc_mult);
+                               1: additive, l1 facet block Jacobi S: A-hat^d^{-1} = S^{-1} + E^d C^{-1} E^d^T
+                                  (Theorem aux_pc), S_F = D_F + diag(sum_{j not in F} |A^d_ij|) */
 } mcs_options;
 
 typedef struct {

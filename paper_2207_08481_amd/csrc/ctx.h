@@ -197,6 +197,19 @@ struct Ctx {
   // x = A-hat^d_m^{-1} s (facet parts; x fully overwritten):
   //   forward sweeps from x = 0; r = s - A^d x (from the maintained products);
   //   x += E^d C^{-1} E^d^T r (products updated through W_T); backward sweeps.
+  // x = A-hat^d^{-1} s of the chosen variant: multiplicative (block
+  // Gauss-Seidel sweeps around the coarse correction) or additive
+  // (S^{-1} s + E^d C^{-1} E^d^T s with the l1 block Jacobi S).
+  void ad_inv(const R* s, R* x) {
+    if (pb->opt.smoother == 1) {
+      launch_fill<R>(st, n, R(0), x);
+      launch_block_jacobi<R>(st, P, O, s, x);
+      aux(s, x, 1);
+      return;
+    }
+    ad_mult_inv(s, x);
+  }
+
   void ad_mult_inv(const R* s, R* x) {
     R* tmp = v(PTMP);
     launch_fill<R>(st, n, R(0), x);
@@ -213,7 +226,7 @@ struct Ctx {
     R *S = v(PS), *T = v(PT), *T1 = v(PT1);
     launch_ext_pre<R>(st, P, O, r, T1, escr);
     launch_facet_sum<R>(st, P, escr, r, R(-1), S);
-    ad_mult_inv(S, T);
+    ad_inv(S, T);
     launch_ext_post<R>(st, P, O, T, T1, y);
     launch_axpby<R>(st, pb->nff * pb->sz.nfb, 1.0, T + pb->off_f, 0.0, y + pb->off_f);
     launch_fill<R>(st, pb->ndof - pb->off_p, R(0), y + pb->off_p);

@@ -401,6 +401,8 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   F.Ad = p.Ad;
   F.Adh = p.Ad32;
   F.Adl = p.Adl;
+  F.elem_ff = p.elem_ff;
+  F.l1 = pb->opt.smoother == 1 ? 1 : 0;
   F.rcn = p.rcn;
   F.rct = p.rct;
   F.Dinv = p.Dinv;
@@ -533,7 +535,7 @@ int precond_op(mcs_problem* pb, int op, const void* rv, void* zv) {
   switch (op) {
     case MCS_PC_KHAT: c.khat(r, z); break;
     case MCS_PC_AEXT: c.ext_inv(r, z); break;
-    case MCS_PC_ADELTA_MULT: c.ad_mult_inv(r, z); break;
+    case MCS_PC_ADELTA_MULT: c.ad_inv(r, z); break;
     case MCS_PC_SMOOTH_FWD:
     case MCS_PC_SMOOTH_BWD:
       launch_fill<R>(c.st, c.n, R(0), z);

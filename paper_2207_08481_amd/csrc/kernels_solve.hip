@@ -314,6 +314,24 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
   }
 }
 
+// z_F = S_F^{-1} r_F for every free facet block (S_F^{-1} stored in Dinv; the
+// l1 block Jacobi of the additive variant); one thread per row of a block.
+template <typename R>
+__global__ void k_block_jacobi(SolveParams P, OpPtrs<R> O, const R* __restrict__ r, R* __restrict__ z) {
+  const int nfb = P.s.nfb;
+  const int64_t n = P.nff * nfb;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = idx / nfb;
+    if (facet_off(P, g)) continue;
+    const int i = (int)(idx % nfb);
+    const R* Di = O.Dinv + (size_t)g * nfb * nfb + i;
+    const R* rf = r + P.off_f + g * nfb;
+    R acc = R(0);
+    for (int j = 0; j < nfb; ++j) acc += Di[(size_t)j * nfb] * rf[j];
+    z[P.off_f + idx] = acc;
+  }
+}
+
 // y_T += W_T c_T with W_T = A^d_T E_T (E_T: the element's rows of E^d) and
 // c_T the P1 coarse correction at the element's vertices (lattice vector; the
 // Dirichlet vertices carry no value and are skipped, their lattice entries are
@@ -847,6 +865,10 @@ void launch_smooth_phase(hipStream_t st, const SolveParams& P, const OpPtrs<R>& 
   }
 }
 template <typename R>
+void launch_block_jacobi(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* z) {
+  hipLaunchKernelGGL(k_block_jacobi<R>, dim3(grid_for(P.nff * P.s.nfb)), dim3(256), 0, st, P, O, r, z);
+}
+template <typename R>
 void launch_ycorr(hipStream_t st, const SolveParams& P, const R* W, const int32_t* elem_verts,
                   const int32_t* vfree_of_lat, const R* x0, R* y) {
   hipLaunchKernelGGL(k_elem_ycorr<R>, dim3(grid_for(P.ne * P.s.nd)), dim3(256), 0, st, P, W, elem_verts, vfree_of_lat,
@@ -938,6 +960,7 @@ void launch_scale_convert(hipStream_t st, int64_t n, double a, const A* x, B* y,
   template void launch_ext_post<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, const R*, R*); \
   template void launch_smooth_phase<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, int32_t, int32_t, R*, \
                                        const R*, R*, int, int64_t);                                            \
+  template void launch_block_jacobi<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, R*);      \
   template void launch_ycorr<R>(hipStream_t, const SolveParams&, const R*, const int32_t*, const int32_t*,       \
                                 const R*, R*);                                                                  \
   template void launch_edt<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, R*, int64_t,         \

@@ -17,6 +17,8 @@ void launch_smooth_phase(hipStream_t st, const SolveParams& P, const OpPtrs<R>& 
                          const R* s, R* y, int facets_per_block = 1, int64_t grid_cap = 0);
 int smooth_team_threads(int nd);
 template <typename R>
+void launch_block_jacobi(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* z);
+template <typename R>
 void launch_ycorr(hipStream_t st, const SolveParams& P, const R* W, const int32_t* elem_verts,
                   const int32_t* vfree_of_lat, const R* x0, R* y);
 template <typename R>

@@ -51,7 +51,8 @@ class Mesh(C.Structure):
 class Options(C.Structure):
     _fields_ = [("order", C.c_int32), ("precision", C.c_int32), ("smoothing_steps", C.c_int32),
                 ("max_it", C.c_int32), ("tol", C.c_double), ("inner_tol", C.c_double),
-                ("max_outer", C.c_int32), ("coarse_max", C.c_int32), ("autotune", C.c_int32)]
+                ("max_outer", C.c_int32), ("coarse_max", C.c_int32), ("autotune", C.c_int32),
+                ("smoother", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -185,7 +186,8 @@ class Problem:
     solve.  Names follow the C ABI."""
 
     def __init__(self, vertices, elements, lattice, order, precision=0, smoothing_steps=2,
-                 tol=1e-10, max_it=2000, inner_tol=1e-5, max_outer=10, coarse_max=512, autotune=0):
+                 tol=1e-10, max_it=2000, inner_tol=1e-5, max_outer=10, coarse_max=512, autotune=0,
+                 smoother=0):
         lib = load_library()
         self._lib = lib
         v = np.ascontiguousarray(vertices, dtype=np.float64)
@@ -196,7 +198,7 @@ class Problem:
         self._mesh = Mesh(self.dim, v.shape[0], v.ctypes.data, e.shape[0], e.ctypes.data,
                           (C.c_int32 * 3)(*lat))
         self._opt = Options(order, precision, smoothing_steps, max_it, tol, inner_tol, max_outer,
-                            coarse_max, autotune)
+                            coarse_max, autotune, smoother)
         self.info = Info()
         h = C.c_void_p()
         _check(lib.mcs_plan(C.byref(self._mesh), C.byref(self._opt), C.byref(h), C.byref(self.info)))
@@ -349,7 +351,7 @@ class Batch:
     member.  meshes: list of (vertices, elements, lattice); orders: list of k."""
 
     def __init__(self, meshes, orders, precision=1, smoothing_steps=2, tol=1e-8, max_it=2000,
-                 inner_tol=1e-5, max_outer=10, coarse_max=512, autotune=1):
+                 inner_tol=1e-5, max_outer=10, coarse_max=512, autotune=1, smoother=0):
         lib = load_library()
         self._lib = lib
         self._keep = []
@@ -367,7 +369,8 @@ class Batch:
         self.orders = [int(k) for k in orders]
         ords = np.asarray(self.orders, dtype=np.int32)
         self._keep.append(ords)
-        self._opt = Options(0, precision, smoothing_steps, max_it, tol, inner_tol, max_outer, coarse_max, autotune)
+        self._opt = Options(0, precision, smoothing_steps, max_it, tol, inner_tol, max_outer, coarse_max, autotune,
+                            smoother)
         self.info = BatchInfo()
         h = C.c_void_p()
         _check(lib.mcs_batch_plan(arr, ords.ctypes.data, len(meshes), C.byref(self._opt), C.byref(h),
@@ -459,7 +462,7 @@ class Server:
 
     def __init__(self, arena_bytes, device="cuda:0", max_inflight=2, max_batch=64, precision=1,
                  smoothing_steps=2, tol=1e-8, max_it=5000, inner_tol=1e-5, max_outer=10, coarse_max=512,
-                 autotune=0):
+                 autotune=0, smoother=0):
         import torch
         lib = load_library()
         self._lib = lib
@@ -469,7 +472,8 @@ class Server:
         self._arena = torch.empty(arena_bytes + 4096, dtype=torch.uint8, device=dev)
         base = self._arena.data_ptr()
         aligned = (base + 4095) // 4096 * 4096
-        self._opt = Options(0, precision, smoothing_steps, max_it, tol, inner_tol, max_outer, coarse_max, autotune)
+        self._opt = Options(0, precision, smoothing_steps, max_it, tol, inner_tol, max_outer, coarse_max, autotune,
+                            smoother)
         torch.cuda.synchronize()
         h = C.c_void_p()
         _check(lib.mcs_server_create(C.byref(self._opt), aligned, arena_bytes, max_inflight, max_batch,
