@@ -70,6 +70,27 @@ def measured_traffic(workload, precision):
     return round(rec["traffic_bytes_per_launch"])
 
 
+def device_copy_gbs(dev, mib=2048, reps=10):
+    """Bytes moved (read + write) per second by a plain device-to-device copy
+    of `mib` MiB, outside the timed region: the practical HBM rate the
+    roofline fraction can be read against."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * n * 8 / (ms / 1e3) / 1e9
+
+
 def cpu_baseline(seconds_hint=20.0):
     """Time the oracle (as it stands) on a bounded sample in a child process:
     the same cube recipe (k=3, nu=1, curl modes) on 3^3 x 6 tets, 40 MINRES
@@ -381,6 +402,7 @@ def main():
     pb.timer_enable(False)
 
     traffic = measured_traffic(args.workload, precision)
+    copy_gbs = device_copy_gbs(dev)
     value = ndof * its / (t_sol / 1e3)
     avg_launch_ms = kms / max(klaunch, 1)
     bytes_per_launch = kbytes / max(klaunch, 1)
@@ -389,7 +411,8 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_smooth_phase (one colour of one block Gauss-Seidel sweep)",
                 "avg_launch_us": round(avg_launch_ms * 1e3, 2), "launches": klaunch,
-                "bytes_per_launch": int(bytes_per_launch)}
+                "bytes_per_launch": int(bytes_per_launch),
+                "device_copy_gbs": round(copy_gbs, 1), "frac_of_device_copy": round(achieved / copy_gbs, 4)}
     out = {
         "metric": "DOF-iterations/s of preconditioned MCS solve",
         "value": value,
