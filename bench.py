@@ -42,7 +42,7 @@ WORKLOADS = {
     "cube32_k4_fp64": ("cube32_k4_lognormal", 0, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 contrast), random smooth f, FP64, tol 1e-10"),
     "square8_k2": ("square8_k2", 0, "unit square 8x8 x 2 triangles, k=2, nu=1, FP64, tol 1e-10"),
     "cube16_k3_additive": ("cube16_k3", 0, "unit cube 16^3 x 6 tets (24,576), k=3, nu=1, curl of 8 random sin^2 modes, "
-                                           "FP64, tol 1e-10; additive auxiliary-space preconditioner with the l1 facet "
+                                           "FP64, tol 1e-10; additive auxiliary-space preconditioner with the facet "
                                            "block-Jacobi smoother"),
     "serve": ("serve", 1, "serving stream: requests on unit cubes of T ~ logU[1e3, 2e5] tets (n = max(2, round((T/6)^(1/3)))), "
                           "k uniform in {2,3,4,5}, per-tet lognormal nu clipped to 1e3 contrast, random smooth forces, "
@@ -55,19 +55,23 @@ WORKLOADS = {
 }
 
 
-def measured_traffic(workload, precision):
-    """HBM bytes per launch of the smoother kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs (calibrated against a plain copy), or None when
-    no record exists for this workload or the kernel source changed since."""
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (calibrated against a plain copy), or None when no record
+    covers this kernel and workload or the kernel source changed since."""
+    import glob
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_smooth_y_{workload}_traffic.json")
-    if precision != 0 or not os.path.exists(path):
+    if precision != 0:
         return None
-    rec = json.load(open(path))
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
-        return None
-    return round(rec["traffic_bytes_per_launch"])
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json"))):
+        rec = json.load(open(path))
+        if not rec["kernel"].startswith(kernel) or workload not in rec.get("workloads", [rec.get("workload")]):
+            continue
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+            return None
+        return round(rec["traffic_bytes_per_launch"])
+    return None
 
 
 def device_copy_gbs(dev, mib=2048, reps=10):
@@ -210,7 +214,7 @@ def run_batch(args, precision, desc):
                    "smoother_launch_per_group": b.launch_configs(1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_smooth_phase, FP32 (one colour of one block Gauss-Seidel sweep, all groups)",
+                     "kernel": "k_smooth_y, FP32 (one colour of one block Gauss-Seidel sweep, all groups)",
                      "avg_launch_us": round(avg_launch_ms * 1e3, 2), "launches": klaunch,
                      "bytes_per_launch": int(bytes_per_launch),
                      "note": "measured in one extra launch-by-launch solve of the same batch"},
@@ -398,21 +402,33 @@ def main():
         infos.append(si)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kms, klaunch, kbytes = pb.timer_read()
+    timed = {kern: pb.timer_read(kern) for kern in ("smooth", "kapply")}
     pb.timer_enable(False)
 
-    traffic = measured_traffic(args.workload, precision)
     copy_gbs = device_copy_gbs(dev)
     value = ndof * its / (t_sol / 1e3)
-    avg_launch_ms = kms / max(klaunch, 1)
-    bytes_per_launch = kbytes / max(klaunch, 1)
-    achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_smooth_phase (one colour of one block Gauss-Seidel sweep)",
+
+    def roof(kern, name, traffic):
+        kms, klaunch, kbytes = timed[kern]
+        avg_launch_ms = kms / klaunch
+        bytes_per_launch = kbytes / klaunch
+        achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
                 "avg_launch_us": round(avg_launch_ms * 1e3, 2), "launches": klaunch,
-                "bytes_per_launch": int(bytes_per_launch),
+                "bytes_per_launch": int(bytes_per_launch), "share_of_t_sol": round(kms / t_sol, 4),
                 "device_copy_gbs": round(copy_gbs, 1), "frac_of_device_copy": round(achieved / copy_gbs, 4)}
+
+    kapply_name = "k_elem_apply (operator apply K x)"
+    if smoother == 0:
+        # the block Gauss-Seidel colour phase dominates the multiplicative solve
+        roofline = roof("smooth", "k_smooth_y (one colour of one block Gauss-Seidel sweep)",
+                        measured_traffic("k_smooth_y", args.workload, precision))
+        secondary = roof("kapply", kapply_name, measured_traffic("k_elem_apply", args.workload, precision))
+    else:
+        # no Gauss-Seidel phases: the operator apply is the largest kernel
+        roofline = roof("kapply", kapply_name, measured_traffic("k_elem_apply", args.workload, precision))
+        secondary = None
     out = {
         "metric": "DOF-iterations/s of preconditioned MCS solve",
         "value": value,
@@ -435,6 +451,8 @@ def main():
                    "smoother_launch": pb.launch_config(0 if precision == 0 else 1)},
         "roofline": roofline,
     }
+    if secondary:
+        out["roofline_secondary"] = secondary
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline()

@@ -127,8 +127,8 @@ typedef struct {
   int32_t autotune;         /* 1: the first mcs_condense times the smoother's launch shapes and keeps the fastest */
   int32_t smoother;         /* auxiliary-space preconditioner of A^d (Sec. 5.2):
                                0: multiplicative, coloured facet block Gauss-Seidel (Corollary aux_pc_mult);
-                               1: additive, l1 facet block Jacobi S: A-hat^d^{-1} = S^{-1} + E^d C^{-1} E^d^T
-                                  (Theorem aux_pc), S_F = D_F + diag(sum_{j not in F} |A^d_ij|) */
+                               1: additive, facet block Jacobi D = blockdiag(D_F):
+                                  A-hat^d^{-1} = D^{-1} + E^d C^{-1} E^d^T (Theorem aux_pc_schur) */
 } mcs_options;
 
 typedef struct {
@@ -217,18 +217,25 @@ int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count)
  * and n_elements*(dim+1). */
 int mcs_get_topology(const mcs_problem* pb, int32_t* colour_host, int32_t* elem_ff_host);
 
-/* Measurement hook for the dominant solve kernel.  While enabled, every launch
- * of the coloured block Gauss-Seidel phase kernel (one colour of one sweep of
- * A-hat^d_m, Corollary aux_pc_mult) is bracketed by HIP events on the
- * problem's stream.  mcs_timer_read returns the accumulated kernel time, the
- * number of launches and their algorithmic HBM bytes: per facet of the
- * colour, the facet's rows of A^d_T of both neighbours (2 n_fb n_d words),
- * D_F^{-1} (n_fb^2), the right-hand side and the updated block (3 n_fb), the
- * gathered neighbour vectors (2 n_d) and the index words, counted on the
- * device over the facet blocks actually processed.  Enabling resets the
- * counters.  [sync on read] */
+/* Measurement hook for the dominant solve kernels.  While enabled, every
+ * launch of a timed kernel is bracketed by HIP events on the problem's stream.
+ * mcs_timer_read returns, for one kernel, the accumulated kernel time, the
+ * number of launches and their algorithmic HBM bytes:
+ *   MCS_TIMER_SMOOTH: the coloured block Gauss-Seidel phase kernel (one colour
+ *     of one sweep of A-hat^d_m, Corollary aux_pc_mult).  Per facet of the
+ *     colour: the facet's rows of A^d_T of both neighbours (2 n_fb n_d words),
+ *     D_F^{-1} (n_fb^2), the right-hand side and the updated block (3 n_fb),
+ *     the gathered neighbour vectors (2 n_d) and the index words, counted on
+ *     the device over the facet blocks actually processed.
+ *   MCS_TIMER_KAPPLY: the operator apply K x of MINRES (eq. femSPmat through
+ *     eq. factorSsigma).  Per element: A^d_T, H_T and A_oo,T as stored
+ *     (n_d^2 + n_b n_d + n_b^2 words), the gathered inputs and written outputs
+ *     (2 (n_d + n_b + n_p) words), the free facet ids and det J.
+ * Enabling resets the counters.  kernel outside the two values:
+ * MCS_ERR_ARG.  [sync on read] */
+enum { MCS_TIMER_SMOOTH = 0, MCS_TIMER_KAPPLY = 1 };
 int mcs_timer_enable(mcs_problem* pb, int enable);
-int mcs_timer_read(mcs_problem* pb, double* total_ms, int64_t* launches, double* bytes);
+int mcs_timer_read(mcs_problem* pb, int32_t kernel, double* total_ms, int64_t* launches, double* bytes);
 
 /* Launch shape of the coloured block Gauss-Seidel phase kernel for work
  * precision dt (MCS_F64 / MCS_F32): facet blocks per workgroup (1 or 2) and

@@ -12,9 +12,8 @@ for the double Schur complement A^d -- oracle (FP64, sequential).
   colour order, then the coarse correction E^d C^{-1} E^d^T on the residual,
   then s sweeps in reverse colour order (the adjoint smoother).
 * Additive variant (Sec. 5.2, the additive auxiliary-space preconditioner of
-  Theorem aux_pc / Lemma add_to_mult): A-hat^d_a^{-1} = S^{-1} + E^d C^{-1} E^d^T
-  with S the l1 block-Jacobi smoother, S_F = D_F + diag(sum_{j not in F}
-  |A^d_{ij}|) for the rows i of facet block F, so that A^d <= S.
+  Theorem aux_pc_schur): A-hat^d_a^{-1} = D^{-1} + E^d C^{-1} E^d^T with D the
+  facet block Jacobi preconditioner, one block D_F per free facet.
 * E^d: rows of the embedding E u = (u, u_t) of continuous P1 (eq. defE) for the
   facet dofs (eq. defED).
 * C: one symmetric V(1,1) multigrid cycle for A-bar, the P1 form
@@ -257,15 +256,6 @@ class Preconditioner:
             fd = gs.facet_dofs(g)
             D = self.Ad[fd][:, fd].toarray()
             self.Dinv.append(np.linalg.inv(D))
-        # l1 block-Jacobi smoother of the additive variant
-        self.Sinv = []
-        if variant == "additive":
-            absA = abs(self.Ad).tocsr()
-            for g in range(topo.n_free_facets):
-                fd = gs.facet_dofs(g)
-                D = self.Ad[fd][:, fd].toarray()
-                off = np.asarray(absA[fd].sum(axis=1)).ravel() - np.abs(D).sum(axis=1)
-                self.Sinv.append(np.linalg.inv(D + np.diag(off)))
         self.colour_lists = [np.nonzero(topo.colour == c)[0] for c in range(topo.n_colours)]
         # auxiliary space
         self.E = embedding(gs, full=False)
@@ -305,18 +295,18 @@ class Preconditioner:
             x = self.backward_sweep(x, s)
         return x
 
-    def l1_jacobi(self, s):
-        """S^{-1} s, block by block (the additive variant's smoother)."""
+    def block_jacobi(self, s):
+        """D^{-1} s, facet block by facet block (the additive variant's smoother)."""
         gs = self.gs
         z = np.zeros_like(s)
         for g in range(gs.topo.n_free_facets):
             fd = gs.facet_dofs(g)
-            z[fd] = self.Sinv[g] @ s[fd]
+            z[fd] = self.Dinv[g] @ s[fd]
         return z
 
     def Ad_add_inv(self, s):
-        """A-hat^d_a^{-1} s = S^{-1} s + E^d C^{-1} E^d^T s."""
-        return self.l1_jacobi(s) + self.aux_correction(s)
+        """A-hat^d_a^{-1} s = D^{-1} s + E^d C^{-1} E^d^T s."""
+        return self.block_jacobi(s) + self.aux_correction(s)
 
     def Ad_inv(self, s):
         return self.Ad_add_inv(s) if self.variant == "additive" else self.Ad_mult_inv(s)

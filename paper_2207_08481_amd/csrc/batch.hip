@@ -817,7 +817,7 @@ int mcs_batch_timer_read(mcs_batch* B, double* total_ms, int64_t* launches, doub
   for (auto& G : B->groups) {
     double m = 0.0, b = 0.0;
     int64_t l = 0;
-    int rc = mcs_timer_read(G.u.get(), &m, &l, &b);
+    int rc = mcs_timer_read(G.u.get(), MCS_TIMER_SMOOTH, &m, &l, &b);
     if (rc) return rc;
     ms += m;
     by += b;

@@ -100,14 +100,42 @@ inline double smooth_bytes_per_facet(const Sizes& z, int wsize) {
 constexpr int WCOUNT = 2 * 256 * 16;
 inline unsigned long long* work_counters(mcs_problem* pb) { return pb->p.wcount; }
 
+// Algorithmic bytes of one element of the operator apply K x (k_elem_apply
+// with A, B^T p and B u): A^d_T, H_T and A_oo,T as stored (n_d^2 + n_b n_d +
+// n_b^2 words), the gathered inputs and written outputs (2 (n_d + n_b + n_p)
+// words), the free facet ids and det J.
+inline double kapply_bytes_per_elem(const Sizes& z, int d, int wsize) {
+  return double(z.nd * z.nd + z.nb * z.nd + z.nb * z.nb + 2 * (z.nd + z.nb + z.np)) * wsize + 4.0 * (d + 1) + 8.0;
+}
+
 // Accumulates the elapsed time of recorded (start, stop) event pairs; the
 // caller has synchronised the stream.
 inline void timer_flush(mcs_problem* pb) {
   for (size_t i = 0; i < pb->tpending; ++i) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, pb->tev[2 * i], pb->tev[2 * i + 1]) == hipSuccess) pb->t_ms += ms;
+    if (hipEventElapsedTime(&ms, pb->tev[2 * i], pb->tev[2 * i + 1]) == hipSuccess) pb->t_ms[pb->tkind[i]] += ms;
   }
   pb->tpending = 0;
+}
+
+// Records the start event of a timed launch of kernel `kind` on stream st.
+inline void timer_start(mcs_problem* pb, hipStream_t st, int kind) {
+  const size_t k = pb->tpending;
+  while (pb->tev.size() < 2 * k + 2) {
+    hipEvent_t e;
+    hipEventCreate(&e);
+    pb->tev.push_back(e);
+  }
+  if (pb->tkind.size() < k + 1) pb->tkind.resize(k + 1);
+  pb->tkind[k] = kind;
+  hipEventRecord(pb->tev[2 * k], st);
+}
+
+inline void timer_stop(mcs_problem* pb, hipStream_t st) {
+  const int kind = pb->tkind[pb->tpending];
+  hipEventRecord(pb->tev[2 * pb->tpending + 1], st);
+  pb->tpending++;
+  pb->t_launches[kind]++;
 }
 
 template <typename R>
@@ -141,7 +169,14 @@ struct Ctx {
   // y = op x on full vectors; flags of k_elem_apply.
   void apply(const R* x, R* y, int flags) {
     if (flags & 8) launch_fill<R>(st, n, R(0), y);
+    // the timer takes the full operator apply of a single problem (no masks)
+    const bool timed = pb->timer_on && flags == (1 | 2 | 4) && !P.active;
+    if (timed) {
+      timer_start(pb, st, 1);
+      pb->t_bytes[1] += pb->ne * kapply_bytes_per_elem(pb->sz, pb->d, sizeof(R));
+    }
     launch_elem_apply<R>(st, P, O, x, y, escr, flags);
+    if (timed) timer_stop(pb, st);
     launch_facet_sum<R>(st, P, escr, nullptr, R(1), y);
   }
 
@@ -170,17 +205,9 @@ struct Ctx {
       for (int cc = 0; cc < pb->ncol; ++cc) {
         int c = forward ? cc : pb->ncol - 1 - cc;
         if (pb->timer_on) {
-          size_t k = 2 * pb->tpending;
-          while (pb->tev.size() < k + 2) {
-            hipEvent_t e;
-            hipEventCreate(&e);
-            pb->tev.push_back(e);
-          }
-          hipEventRecord(pb->tev[k], st);
+          timer_start(pb, st, 0);
           launch_smooth_phase<R>(st, Pt, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y, fpw, cap);
-          hipEventRecord(pb->tev[k + 1], st);
-          pb->tpending++;
-          pb->t_launches++;
+          timer_stop(pb, st);
         } else {
           launch_smooth_phase<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y, fpw, cap);
         }
@@ -199,7 +226,7 @@ struct Ctx {
   //   x += E^d C^{-1} E^d^T r (products updated through W_T); backward sweeps.
   // x = A-hat^d^{-1} s of the chosen variant: multiplicative (block
   // Gauss-Seidel sweeps around the coarse correction) or additive
-  // (S^{-1} s + E^d C^{-1} E^d^T s with the l1 block Jacobi S).
+  // (D^{-1} s + E^d C^{-1} E^d^T s with the facet block Jacobi D).
   void ad_inv(const R* s, R* x) {
     if (pb->opt.smoother == 1) {
       launch_fill<R>(st, n, R(0), x);

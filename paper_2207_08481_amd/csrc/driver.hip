@@ -401,8 +401,6 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   F.Ad = p.Ad;
   F.Adh = p.Ad32;
   F.Adl = p.Adl;
-  F.elem_ff = p.elem_ff;
-  F.l1 = pb->opt.smoother == 1 ? 1 : 0;
   F.rcn = p.rcn;
   F.rct = p.rct;
   F.Dinv = p.Dinv;
@@ -788,17 +786,23 @@ int mcs_timer_enable(mcs_problem* pb, int enable) {
   HIPCHK(hipStreamSynchronize(pb->stream));
   timer_flush(pb);
   pb->timer_on = enable != 0;
-  pb->t_ms = 0.0;
-  pb->t_bytes = 0.0;
-  pb->t_launches = 0;
+  for (int i = 0; i < 2; ++i) {
+    pb->t_ms[i] = 0.0;
+    pb->t_bytes[i] = 0.0;
+    pb->t_launches[i] = 0;
+  }
   HIPCHK(hipMemsetAsync(work_counters(pb), 0, WCOUNT * sizeof(unsigned long long), pb->stream));
   HIPCHK(hipStreamSynchronize(pb->stream));
   return MCS_OK;
 }
 
-int mcs_timer_read(mcs_problem* pb, double* total_ms, int64_t* launches, double* bytes) {
+int mcs_timer_read(mcs_problem* pb, int32_t kernel, double* total_ms, int64_t* launches, double* bytes) {
   int rc = check_bound(pb);
   if (rc) return rc;
+  if (kernel != MCS_TIMER_SMOOTH && kernel != MCS_TIMER_KAPPLY) {
+    set_error("mcs_timer_read: kernel must be MCS_TIMER_SMOOTH or MCS_TIMER_KAPPLY");
+    return MCS_ERR_ARG;
+  }
   HIPCHK(hipStreamSynchronize(pb->stream));
   timer_flush(pb);
   std::vector<unsigned long long> wc(WCOUNT);
@@ -808,10 +812,10 @@ int mcs_timer_read(mcs_problem* pb, double* total_ms, int64_t* launches, double*
     cnt[0] += wc[i * 16];
     cnt[1] += wc[256 * 16 + i * 16];
   }
-  pb->t_bytes = cnt[0] * smooth_bytes_per_facet(pb->sz, 8) + cnt[1] * smooth_bytes_per_facet(pb->sz, 4);
-  if (total_ms) *total_ms = pb->t_ms;
-  if (launches) *launches = pb->t_launches;
-  if (bytes) *bytes = pb->t_bytes;
+  pb->t_bytes[0] = cnt[0] * smooth_bytes_per_facet(pb->sz, 8) + cnt[1] * smooth_bytes_per_facet(pb->sz, 4);
+  if (total_ms) *total_ms = pb->t_ms[kernel];
+  if (launches) *launches = pb->t_launches[kernel];
+  if (bytes) *bytes = pb->t_bytes[kernel];
   return MCS_OK;
 }
 

@@ -41,8 +41,6 @@ struct FacetSetupParams {
   const double* coords;
   const double* Ad;              // FP64 A^d, or nullptr: hi + lo in Adh, Adl
   const float *Adh, *Adl;
-  const int32_t* elem_ff;        // element -> free facet id (-1: Dirichlet)
-  int l1;                        // 1: D_F + l1 off-block row sums (additive variant)
   const double *rcn, *rct;
   double* Dinv;
   float* Dinv32;

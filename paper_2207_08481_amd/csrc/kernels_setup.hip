@@ -510,22 +510,6 @@ __global__ void __launch_bounds__(256) k_facet_setup(FacetSetupParams P) {
         const size_t ai = (size_t)e * nd * nd + (size_t)(sl * nfb + i) * nd + sl * nfb + j;
         t += P.Ad ? P.Ad[ai] : (double)P.Adh[ai] + (double)P.Adl[ai];
       }
-      if (P.l1 && i == j) {
-        // l1 block Jacobi: add the absolute row sum of row i over the other
-        // free facet blocks of both neighbours (the off-block part of A^d)
-        for (int side = 0; side < 2; ++side) {
-          const int64_t e = P.facet_el[2 * g + side];
-          const int sl = P.facet_slot[2 * g + side];
-          const size_t r0 = (size_t)e * nd * nd + (size_t)(sl * nfb + i) * nd;
-          for (int f = 0; f < nv; ++f) {
-            if (f == sl || P.elem_ff[e * nv + f] < 0) continue;
-            for (int q = 0; q < nfb; ++q) {
-              const size_t ai = r0 + f * nfb + q;
-              t += fabs(P.Ad ? P.Ad[ai] : (double)P.Adh[ai] + (double)P.Adl[ai]);
-            }
-          }
-        }
-      }
       S[i * FLD + j] = t;
     }
     __syncthreads();

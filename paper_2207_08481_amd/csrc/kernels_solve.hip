@@ -314,8 +314,8 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
   }
 }
 
-// z_F = S_F^{-1} r_F for every free facet block (S_F^{-1} stored in Dinv; the
-// l1 block Jacobi of the additive variant); one thread per row of a block.
+// z_F = D_F^{-1} r_F for every free facet block: the facet block Jacobi of the
+// additive variant (Theorem aux_pc_schur); one thread per row of a block.
 template <typename R>
 __global__ void k_block_jacobi(SolveParams P, OpPtrs<R> O, const R* __restrict__ r, R* __restrict__ z) {
   const int nfb = P.s.nfb;

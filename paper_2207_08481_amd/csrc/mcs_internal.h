@@ -186,12 +186,13 @@ struct mcs_problem {
   int tune_fpw[2] = {1, 1};
   int64_t tune_cap[2] = {0, 0};
   double tune_us[2] = {0.0, 0.0};
-  // kernel timer (smoother phase launches)
+  // kernel timer: [0] smoother phase launches, [1] K apply launches
   bool timer_on = false;
   std::vector<hipEvent_t> tev;        // pairs (start, stop)
+  std::vector<int> tkind;             // timed kernel of each pending pair
   size_t tpending = 0;
-  double t_ms = 0.0, t_bytes = 0.0;
-  int64_t t_launches = 0;
+  double t_ms[2] = {0.0, 0.0}, t_bytes[2] = {0.0, 0.0};
+  int64_t t_launches[2] = {0, 0};
   ~mcs_problem() {
     for (auto e : tev) hipEventDestroy(e);
   }

@@ -134,7 +134,7 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
     return MCS_ERR_ARG;
   }
   if (pb->opt.smoother != 0 && pb->opt.smoother != 1) {
-    set_error("smoother must be 0 (multiplicative, block Gauss-Seidel) or 1 (additive, l1 block Jacobi)");
+    set_error("smoother must be 0 (multiplicative, block Gauss-Seidel) or 1 (additive, facet block Jacobi)");
     return MCS_ERR_ARG;
   }
   pb->sz = make_sizes(d, k);

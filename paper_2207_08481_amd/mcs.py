@@ -120,7 +120,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_get_array.argtypes = [vp, C.c_char_p, C.POINTER(vp), C.POINTER(i64)]
     lib.mcs_get_topology.argtypes = [vp, vp, vp]
     lib.mcs_timer_enable.argtypes = [vp, i32]
-    lib.mcs_timer_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
+    lib.mcs_timer_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_get_launch_config.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_batch_launch_config.argtypes = [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
                                             C.POINTER(i64), C.POINTER(C.c_double)]
@@ -320,12 +320,15 @@ class Problem:
     def timer_enable(self, on=True):
         _check(self._lib.mcs_timer_enable(self._h, 1 if on else 0))
 
-    def timer_read(self):
-        """(total kernel ms, launches, algorithmic bytes) of the timed smoother launches."""
+    def timer_read(self, kernel="smooth"):
+        """(total kernel ms, launches, algorithmic bytes) of the timed launches of
+        one kernel: "smooth" (block Gauss-Seidel colour phase) or "kapply"
+        (operator apply K x)."""
         ms = C.c_double()
         n = C.c_int64()
         b = C.c_double()
-        _check(self._lib.mcs_timer_read(self._h, C.byref(ms), C.byref(n), C.byref(b)))
+        kid = {"smooth": 0, "kapply": 1}[kernel]
+        _check(self._lib.mcs_timer_read(self._h, kid, C.byref(ms), C.byref(n), C.byref(b)))
         return ms.value, n.value, b.value
 
     def close(self):

@@ -363,8 +363,8 @@ def test_point_values_match_oracle(d, n, k):
 
 @pytest.mark.parametrize("d,n,k,cm", [(2, 4, 2, 20), (3, 2, 2, 512), (3, 2, 3, 512)])
 def test_additive_variant_parity(d, n, k, cm):
-    """smoother = 1 (additive auxiliary-space preconditioner with the l1 block
-    Jacobi smoother) against the oracle's additive variant: A-hat^d^{-1},
+    """smoother = 1 (additive auxiliary-space preconditioner with the facet
+    block Jacobi smoother) against the oracle's additive variant: A-hat^d^{-1},
     A-hat_ext^{-1}, K-hat^{-1} (FP64 and FP32), and the MINRES iteration count
     (+-1) and solution of a solve."""
     _need_gpu()
@@ -404,3 +404,28 @@ def test_additive_variant_parity(d, n, k, cm):
     its, ito = si["iterations"], info["iterations"]
     assert abs(its - ito) <= max(1, 0.02 * ito), (its, ito)
     assert _rel(x.cpu().numpy(), xo) < 1e-8
+
+
+def test_kernel_timer_counts():
+    """The measurement hook: smoother phase launches come in whole sweeps
+    (smoothing_steps x n_colours per A-hat^d_m application, four applications
+    per K-hat^{-1}), one operator apply per MINRES iteration (and one for the
+    final true residual), and the bytes of
+    the operator apply are launches x elements x the per-element count
+    (n_d^2 + n_b n_d + n_b^2 + 2 (n_d + n_b + n_p)) words + 4 (d+1) + 8."""
+    c = setup_case(3, 2, 3)
+    pb, info = c["pb"], c["pb"].info
+    pb.timer_enable(True)
+    _, si = pb.solve(torch.as_tensor(c["f"], device="cuda:0"))
+    sm = pb.timer_read("smooth")
+    ka = pb.timer_read("kapply")
+    pb.timer_enable(False)
+    assert si["status"] == 0
+    per_pc = 4 * 2 * info.n_colours
+    assert sm[1] > 0 and sm[1] % per_pc == 0 and sm[0] > 0
+    # one apply per iteration and one for the true residual b - K x at the end
+    assert ka[1] == si["iterations"] + 1 and ka[0] > 0
+    nb, nfb, npr = info.n_bub, info.n_fb, info.n_p
+    nd = 4 * nfb
+    per_elem = 8 * (nd * nd + nb * nd + nb * nb + 2 * (nd + nb + npr)) + 4 * 4 + 8
+    assert ka[2] == pytest.approx(ka[1] * c["mesh"].n_elements * per_elem, rel=1e-12)

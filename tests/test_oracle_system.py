@@ -352,21 +352,44 @@ def test_preconditioned_minres_matches_direct(d, n, k):
 
 @pytest.mark.parametrize("d,n,k,cm", [(2, 4, 2, 20), (3, 2, 2, 512)])
 def test_additive_asp_bounds(d, n, k, cm):
-    """Additive variant (Sec. 5.2, Theorem aux_pc): the l1 block-Jacobi smoother
-    dominates A^d (eigenvalues of S^{-1} A^d in (0, 1]) and the additive
-    preconditioner S^{-1} + E^d C^{-1} E^d^T is symmetric with eigenvalues of
-    A-hat^d_a^{-1} A^d in (0, 2] (each of its two terms contributes at most 1)."""
+    """Additive variant (Sec. 5.2, Theorem aux_pc_schur) with the facet block
+    Jacobi D.  Facets of one colour share no element, so A^d restricted to a
+    colour is block diagonal and Cauchy-Schwarz over the colours gives
+    A^d <= n_colours D: the eigenvalues of D^{-1} A^d lie in (0, n_colours] and
+    those of (D^{-1} + E^d C^{-1} E^d^T) A^d in (0, n_colours + 1] (the coarse
+    term adds at most 1 since E^d^T A^d E^d <= A-bar <= C).  The diagonal blocks
+    of D^{-1} A^d are identities."""
     mesh, gs, _ = problem(d, n, k)
     pc = Preconditioner(gs, mesh.lattice, coarse_max=cm, variant="additive")
+    nc = gs.topo.n_colours
     idx = np.arange(gs.off_f, gs.off_p)
     Ad = pc.Ad.toarray()[np.ix_(idx, idx)]
-    S = _dense_op(pc.l1_jacobi, gs.n_dof, idx)
-    lam_s = np.linalg.eigvals(S @ Ad).real
-    assert lam_s.min() > 0 and lam_s.max() <= 1 + 1e-10
+    Dinv = _dense_op(pc.block_jacobi, gs.n_dof, idx)
+    DA = Dinv @ Ad
+    for g in range(gs.topo.n_free_facets):
+        fd = gs.facet_dofs(g) - gs.off_f
+        assert np.allclose(DA[np.ix_(fd, fd)], np.eye(len(fd)), atol=1e-9)
+    lam_s = np.linalg.eigvals(DA).real
+    assert lam_s.min() > 0 and lam_s.max() <= nc + 1e-9
     P = _dense_op(pc.Ad_add_inv, gs.n_dof, idx)
     assert np.allclose(P, P.T, atol=1e-10 * np.abs(P).max())
     lam = np.linalg.eigvals(P @ Ad).real
-    assert lam.min() > 1e-8 and lam.max() <= 2 + 1e-9
+    assert lam.min() > 1e-8 and lam.max() <= nc + 1 + 1e-9
+
+
+def test_additive_asp_mesh_independent():
+    """Theorem aux_pc_schur bounds the condition number of the additive
+    preconditioner independently of h: halving h (2D, k=2, n = 4 -> 8) leaves
+    the spectral condition number of A-hat^d_a^{-1} A^d within 25%."""
+    kap = []
+    for n in (4, 8):
+        mesh, gs, _ = problem(2, n, 2)
+        pc = Preconditioner(gs, mesh.lattice, variant="additive")
+        idx = np.arange(gs.off_f, gs.off_p)
+        Ad = pc.Ad.toarray()[np.ix_(idx, idx)]
+        lam = np.sort(np.linalg.eigvals(_dense_op(pc.Ad_add_inv, gs.n_dof, idx) @ Ad).real)
+        kap.append(lam[-1] / lam[0])
+    assert kap[1] <= 1.25 * kap[0], kap
 
 
 def test_additive_needs_more_iterations_than_multiplicative():
