@@ -341,3 +341,28 @@ def element_system(X, nu, k, f_lattice_sorted=None, lattice_sorted=None, m=None,
     if keep_blocks:
         out.update(Z=Z, Mss=Mss, Bws=Bws, Bsig=Bsig, Dm=Dm, Kn=Kn)
     return out
+
+
+def recover_stress(ed, nu, k, u_local):
+    """Stress and vorticity of one element from its velocity (Sec. 4.2: after
+    the condensed solve, sigma_h and omega_h follow from the local problems
+    eq. projection).  With M and B_sigma of eq. bigfemSPmat the element rows
+    read M (sigma, omega) + B_sigma^T (u, uhat) = 0, so
+    (sigma, omega) = -M^{-1} B_sigma^T (u, uhat).
+
+    u_local: velocity coefficients in the local order of the matrix 'A'
+    ([Phi | Vhat]).  Returns coefficient arrays over lambda^alpha (sorted
+    vertices): S (|I_k|, d, d) for sigma_h and W (|I_{k-1}|, d, d) for
+    omega_h."""
+    es = element_system(ed, nu, k, keep_blocks=True)
+    Z, Mss, Bws, Bsig, Dm, Kn = es["Z"], es["Mss"], es["Bws"], es["Bsig"], es["Dm"], es["Kn"]
+    n_sig, n_om = Z.shape[1], Bws.shape[0]
+    M = np.block([[-Mss, Bws.T], [Bws, np.zeros((n_om, n_om))]])
+    rhs = np.concatenate([Bsig.T @ np.asarray(u_local, dtype=np.float64), np.zeros(n_om)])
+    sol = -np.linalg.solve(M, rhs)
+    n_I = len(multi_indices(ed.d + 1, k))
+    cs = (Z @ sol[:n_sig]).reshape(n_I, len(Dm))           # (alpha, m)
+    S = np.einsum("am,mrs->ars", cs, Dm)
+    cw = sol[n_sig:].reshape(-1, len(Kn))                    # (gamma, n)
+    W = np.einsum("gn,nrs->grs", cw, Kn)
+    return S, W

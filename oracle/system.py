@@ -182,3 +182,22 @@ class GlobalSystem:
         cp = x[self.pressure_dofs(e)]
         p = evaluate(cp, self.d + 1, self.k - 1, lam)
         return u, p
+
+    def local_velocity(self, x, e):
+        """Velocity coefficients of element e in the local order of its matrix
+        'A' ([Phi | Vhat]); Dirichlet dofs are zero."""
+        ld = self.local_dofs(e)
+        coef = np.where(ld >= 0, x[np.maximum(ld, 0)], 0.0)
+        orig = np.zeros(len(ld))
+        orig[self.elems[e]["perm"]] = coef
+        return orig
+
+    def eval_stress_element(self, x, e, lam):
+        """Values (sigma_h, omega_h) recovered in element e (eq. projection) at
+        barycentric points lam (n, d+1) w.r.t. the sorted vertices; each of
+        shape (n, d, d)."""
+        from .element import recover_stress
+        from .poly import evaluate
+        es = self.elems[e]
+        S, W = recover_stress(es["ed"], self.nu[e], self.k, self.local_velocity(x, e))
+        return evaluate(S, self.d + 1, self.k, lam), evaluate(W, self.d + 1, self.k - 1, lam)
