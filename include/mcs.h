@@ -199,9 +199,22 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
  * w.r.t. the element's vertices in the order of `elements`.  u_vals (device)
  * [n_elements][n_pts][dim], p_vals (device) [n_elements][n_pts].  u_h is the
  * BDM field (Sec. 3, V_h); u-hat lives on facets only.  n_pts <= 1024
- * (3D) / 1365 (2D).  [sync] */
+ * (3D) / 1365 (2D).  Needs mcs_condense first (det J): MCS_ERR_STATE.  [sync] */
 int mcs_eval(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_pts_host, double* u_vals,
              double* p_vals);
+
+/* Stress and vorticity recovered from a solution (Sec. 4.2: after the
+ * condensed solve, sigma_h in Sigma_h and omega_h in W_h follow element by
+ * element from the local problems eq. projection, with the element's u_h,
+ * u-hat_h and viscosity).  Point values at the same kind of points as
+ * mcs_eval: x (device double[n_dof]); ref_pts_host[n_pts][dim+1] (host);
+ * sigma_vals and omega_vals (device) [n_elements][n_pts][dim][dim], row-major
+ * matrices.  For conforming velocity data sigma_h = -nu dev eps(u_h) and
+ * omega_h = kappa(curl u_h) (Lemma SPD).  Needs mcs_condense first
+ * (MCS_ERR_STATE); n_pts as for mcs_eval (MCS_ERR_ARG).  Uses the
+ * condensation scratch.  [sync] */
+int mcs_eval_stress(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_pts_host,
+                    double* sigma_vals, double* omega_vals);
 
 /* Subtracts the mean of the pressure from x (device double[n_dof]). */
 int mcs_normalize_pressure(mcs_problem* pb, double* x);
@@ -342,6 +355,7 @@ typedef struct {
   double queue_ms;          /* submit -> start of its micro-batch */
   double solve_ms;          /* iteration wall time of its micro-batch */
   double latency_ms;        /* submit -> result on the host */
+  char message[160];        /* error text when status < 0 */
 } mcs_request_info;
 
 typedef struct {

@@ -240,6 +240,7 @@ int run_iterations(mcs_batch* B, std::vector<GroupRun<R>>& runs, int maxit) {
     return join(B);
   };
   if (B->use_graph && !B->timer && !B->gexec[prec]) {
+    ApiLock lock(device_api_mutex());
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(B->main, hipStreamCaptureModeThreadLocal));
     int rc = enqueue_chunk();
@@ -416,6 +417,7 @@ int mcs_batch_set_mode(mcs_batch* B, int use_graph, int chunk) {
     set_error("batch mode: chunk must be a positive multiple of 6");
     return MCS_ERR_ARG;
   }
+  ApiLock lock(device_api_mutex());
   if (chunk != B->chunk)
     for (auto& g : B->gexec)
       if (g) {
@@ -428,6 +430,7 @@ int mcs_batch_set_mode(mcs_batch* B, int use_graph, int chunk) {
 }
 
 int mcs_batch_bind(mcs_batch* B, void* workspace, size_t bytes, void* stream) {
+  ApiLock lock(device_api_mutex());
   if (!B) {
     set_error("null batch");
     return MCS_ERR_ARG;
@@ -829,6 +832,9 @@ int mcs_batch_timer_read(mcs_batch* B, double* total_ms, int64_t* launches, doub
   return MCS_OK;
 }
 
-void mcs_batch_destroy(mcs_batch* B) { delete B; }
+void mcs_batch_destroy(mcs_batch* B) {
+  ApiLock lock(device_api_mutex());
+  delete B;
+}
 
 }  // extern "C"

@@ -122,6 +122,7 @@ inline void timer_flush(mcs_problem* pb) {
 inline void timer_start(mcs_problem* pb, hipStream_t st, int kind) {
   const size_t k = pb->tpending;
   while (pb->tev.size() < 2 * k + 2) {
+    ApiLock lock(device_api_mutex());
     hipEvent_t e;
     hipEventCreate(&e);
     pb->tev.push_back(e);

@@ -63,9 +63,20 @@ int tune_smoother_precision(mcs_problem* pb, int slot) {
     if (fpw == 2 && 2 * T1 > 512) continue;
     for (int64_t cap : {int64_t(0), int64_t(2048), int64_t(4096), int64_t(8192)}) cand.push_back({fpw, cap});
   }
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  struct Events {  // released on every return path
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      ApiLock lock(device_api_mutex());
+      for (auto x : e)
+        if (x) hipEventDestroy(x);
+    }
+  } ev;
+  {
+    ApiLock lock(device_api_mutex());
+    HIPCHK(hipEventCreate(&ev.e[0]));
+    HIPCHK(hipEventCreate(&ev.e[1]));
+  }
+  hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
   const int32_t c0 = pb->colour_off[best_col], c1 = pb->colour_off[best_col + 1];
   double best = 1e300;
   for (auto& cf : cand) {
@@ -84,8 +95,6 @@ int tune_smoother_precision(mcs_problem* pb, int slot) {
       pb->tune_us[slot] = us;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   return MCS_OK;
 }
 
@@ -112,7 +121,8 @@ int sync_status(mcs_problem* pb, const char* what) {
   HIPCHK(hipStreamSynchronize(pb->stream));
   HIPCHK(hipGetLastError());
   int st = 0;
-  HIPCHK(hipMemcpy(&st, pb->p.scal + 200, sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(&st, pb->p.scal + 200, sizeof(int), hipMemcpyDeviceToHost, pb->stream));
+  HIPCHK(hipStreamSynchronize(pb->stream));
   if (st & 8) {
     set_error("%s: viscosity must be positive and finite", what);
     return MCS_ERR_ARG;
@@ -198,6 +208,7 @@ int mcs_plan(const mcs_mesh* mesh, const mcs_options* options, mcs_problem** out
 }
 
 int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
+  ApiLock lock(device_api_mutex());
   if (!pb) {
     set_error("null problem");
     return MCS_ERR_ARG;
@@ -240,6 +251,8 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   p.rpmom = ws_ptr<double>(pb, "rpmom");
   p.rphi = ws_ptr<double>(pb, "rphi");
   p.rpidx = ws_ptr<double>(pb, "rpidx");
+  p.rpsi = ws_ptr<double>(pb, "rpsi");
+  p.rpsib = ws_ptr<double>(pb, "rpsib");
   p.rlatmap = ws_ptr<int32_t>(pb, "rlatmap");
   p.nu = ws_ptr<double>(pb, "nu");
   p.detJ = ws_ptr<double>(pb, "detJ");
@@ -310,6 +323,8 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   HIPCHK(up(p.rpmom, r.pmom.data(), r.pmom.size() * 8));
   HIPCHK(up(p.rphi, r.phi.data(), r.phi.size() * 8));
   HIPCHK(up(p.rpidx, r.pidx.data(), r.pidx.size() * 8));
+  HIPCHK(up(p.rpsi, r.psi.data(), r.psi.size() * 8));
+  HIPCHK(up(p.rpsib, r.psib.data(), r.psib.size() * 8));
   HIPCHK(up(p.rlatmap, r.latmap.data(), r.latmap.size() * 4));
   HIPCHK(up(p.cmap, pb->h_cmap.data(), pb->h_cmap.size() * 4));
   // multigrid lattice vectors start (and stay) zero on the boundary; block tables
@@ -344,6 +359,28 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   return MCS_OK;
 }
 
+// Geometry, reference tables, viscosity and slot scratch of the element kernels.
+static CondParams cond_params(mcs_problem* pb, int* status) {
+  DevPtrs& p = pb->p;
+  CondParams C{};
+  C.s = pb->sz;
+  C.ne = pb->ne;
+  C.slot_doubles = pb->slot_doubles;
+  C.elem_verts = p.elem_verts;
+  C.coords = p.coords;
+  C.nu = p.nu;
+  C.rV = p.rV;
+  C.rBf = p.rBf;
+  C.rU = p.rU;
+  C.rL = p.rL;
+  C.rD = p.rD;
+  for (int f = 0; f < 4; ++f) C.facet_measure[f] = pb->ref.facet_measure[f];
+  C.scratch = p.cscratch;
+  C.detJ = p.detJ;
+  C.status = status;
+  return C;
+}
+
 int mcs_condense(mcs_problem* pb, const double* nu) {
   int rc = check_bound(pb);
   if (rc) return rc;
@@ -360,21 +397,7 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   rc = sync_status(pb, "condense");
   if (rc) return rc;
 
-  CondParams C{};
-  C.s = pb->sz;
-  C.ne = pb->ne;
-  C.slot_doubles = pb->slot_doubles;
-  C.elem_verts = p.elem_verts;
-  C.coords = p.coords;
-  C.nu = p.nu;
-  C.rV = p.rV;
-  C.rBf = p.rBf;
-  C.rU = p.rU;
-  C.rL = p.rL;
-  C.rD = p.rD;
-  for (int f = 0; f < 4; ++f) C.facet_measure[f] = pb->ref.facet_measure[f];
-  C.scratch = p.cscratch;
-  C.detJ = p.detJ;
+  CondParams C = cond_params(pb, status);
   C.Ad = p.Ad;
   C.H = p.H;
   C.Aoo = p.Aoo;
@@ -388,7 +411,6 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   C.Aool = p.Aool;
   C.adtmp = p.adtmp;
   C.adtmp_stride = (int64_t)pb->sz.nd * pb->sz.nd;
-  C.status = status;
   launch_condense(st, C, (int)pb->n_slots);
 
   FacetSetupParams F{};
@@ -638,8 +660,19 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
     set_error("null vector");
     return MCS_ERR_ARG;
   }
-  double* host = nullptr;
-  HIPCHK(hipHostMalloc((void**)&host, 64));
+  // pinned scalars of the host-side recurrences, released on every return path
+  struct Pinned {
+    double* p = nullptr;
+    ~Pinned() {
+      ApiLock lock(device_api_mutex());
+      if (p) hipHostFree(p);
+    }
+  } pin;
+  {
+    ApiLock lock(device_api_mutex());
+    HIPCHK(hipHostMalloc((void**)&pin.p, 64));
+  }
+  double* host = pin.p;
   hipStream_t st = pb->stream;
   const int64_t n = pb->ndof;
   mcs_solve_info inf{};
@@ -718,7 +751,6 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
   SolveParams P = solve_params(pb);
   launch_pressure_mean(st, P, pb->p.rpmom, pb->p.rpconst, x, pb->p.red);
   hipError_t he = hipStreamSynchronize(st);
-  hipHostFree(host);
   if (he != hipSuccess) {
     set_error("HIP error '%s' in solve", hipGetErrorString(he));
     return MCS_ERR_HIP;
@@ -806,7 +838,9 @@ int mcs_timer_read(mcs_problem* pb, int32_t kernel, double* total_ms, int64_t* l
   HIPCHK(hipStreamSynchronize(pb->stream));
   timer_flush(pb);
   std::vector<unsigned long long> wc(WCOUNT);
-  HIPCHK(hipMemcpy(wc.data(), work_counters(pb), WCOUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(wc.data(), work_counters(pb), WCOUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         pb->stream));
+  HIPCHK(hipStreamSynchronize(pb->stream));
   unsigned long long cnt[2] = {0, 0};
   for (int i = 0; i < 256; ++i) {
     cnt[0] += wc[i * 16];
@@ -823,6 +857,10 @@ int mcs_eval(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_
              double* p_vals) {
   int rc = check_bound(pb);
   if (rc) return rc;
+  if (!pb->condensed) {  // the Piola factors use det J from the condensation
+    set_error("mcs_eval: call mcs_condense first");
+    return MCS_ERR_STATE;
+  }
   const int nv = pb->d + 1;
   if (!x || !ref_pts_host || !u_vals || !p_vals || n_pts <= 0 || (int64_t)n_pts * nv > pb->nred) {
     set_error("mcs_eval: null pointer or n_pts outside 1..%lld", (long long)(pb->nred / nv));
@@ -834,6 +872,39 @@ int mcs_eval(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_
               pb->p.red, x, u_vals, p_vals);
   HIPCHK(hipStreamSynchronize(pb->stream));
   return MCS_OK;
+}
+
+int mcs_eval_stress(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_pts_host,
+                    double* sigma_vals, double* omega_vals) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  if (!pb->condensed) {
+    set_error("mcs_eval_stress: call mcs_condense first");
+    return MCS_ERR_STATE;
+  }
+  const int nv = pb->d + 1;
+  if (!x || !ref_pts_host || !sigma_vals || !omega_vals || n_pts <= 0 || (int64_t)n_pts * nv > pb->nred) {
+    set_error("mcs_eval_stress: null pointer or n_pts outside 1..%lld", (long long)(pb->nred / nv));
+    return MCS_ERR_ARG;
+  }
+  hipStream_t st = pb->stream;
+  int* status = reinterpret_cast<int*>(pb->p.scal + 200);
+  HIPCHK(hipMemsetAsync(status, 0, sizeof(int), st));
+  HIPCHK(hipMemcpyAsync(pb->p.red, ref_pts_host, (size_t)n_pts * nv * 8, hipMemcpyHostToDevice, st));
+  StressParams S{};
+  S.C = cond_params(pb, status);
+  S.x = x;
+  S.elem_ff = pb->p.elem_ff;
+  S.elem_perm = pb->p.elem_perm;
+  S.off_f = pb->off_f;
+  S.rpsi = pb->p.rpsi;
+  S.rpsib = pb->p.rpsib;
+  S.npts = n_pts;
+  S.pts = pb->p.red;
+  S.sig = sigma_vals;
+  S.om = omega_vals;
+  launch_stress(st, S, (int)pb->n_slots);
+  return sync_status(pb, "mcs_eval_stress");
 }
 
 int mcs_get_launch_config(const mcs_problem* pb, int dt, int32_t* facets_per_block, int64_t* grid_cap, double* us) {
@@ -848,6 +919,9 @@ int mcs_get_launch_config(const mcs_problem* pb, int dt, int32_t* facets_per_blo
   return MCS_OK;
 }
 
-void mcs_destroy(mcs_problem* pb) { delete pb; }
+void mcs_destroy(mcs_problem* pb) {
+  ApiLock lock(device_api_mutex());
+  delete pb;
+}
 
 }  // extern "C"

@@ -32,6 +32,19 @@ struct CondParams {
   int* status;
 };
 
+// Stress and vorticity recovery (eq. projection) at reference points.
+struct StressParams {
+  CondParams C;                  // geometry, reference tables, nu, slot scratch
+  const double* x;               // global coefficient vector
+  const int32_t* elem_ff;
+  const int32_t* elem_perm;
+  int64_t off_f;
+  const double *rpsi, *rpsib;    // psi_a in monomial form, multi-indices
+  int npts;
+  const double* pts;             // [npts][nv] barycentric, caller vertex order
+  double *sig, *om;              // [ne][npts][d][d]
+};
+
 struct FacetSetupParams {
   Sizes s;
   int64_t nff;

@@ -222,9 +222,132 @@ __device__ void element_geometry(const CondParams& P, int64_t e, ElemGeo& g) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_condense(CondParams P) {
+// --------------------------------------------------------------------------
+// Pieces shared by the condensation and the stress recovery.
+// --------------------------------------------------------------------------
+// Geometry of element e and the coefficient tables of the stress basis:
+// sEm[m] = J^T D_m J^{-T}; sW[f][m] = (|F_f| / |F^_f|) J^T (tangential part of
+// D_m n_f); sTd[f][b][m] = t_b . D_m n_f.  Block-wide; ends synchronised.
+__device__ __forceinline__ void stress_tables(const CondParams& P, int64_t e, ElemGeo& g, double (*sEm)[3][3],
+                                              double (*sW)[8][3], double (*sTd)[2][8]) {
   const Sizes s = P.s;
   const int d = s.d, nv = d + 1, nD = s.nsym + s.nskew;
+  const int tid = threadIdx.x;
+  if (tid == 0) element_geometry(P, e, g);
+  __syncthreads();
+  for (int idx = tid; idx < nD * nv; idx += blockDim.x) {
+    int m = idx % nD, f = idx / nD;
+    double D[3][3];
+    dm_basis(d, m, D);
+    if (f == 0) {  // Em = J^T D_m J^{-T}
+      for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+          double t = 0.0;
+          for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) t += g.J[a][r] * D[a][b] * g.Ji[c][b];
+          sEm[m][r][c] = t;
+        }
+    }
+    double Dn[3] = {0, 0, 0}, nDn = 0.0;
+    for (int a = 0; a < d; ++a) {
+      for (int b = 0; b < d; ++b) Dn[a] += D[a][b] * g.n[f][b];
+      nDn += g.n[f][a] * Dn[a];
+    }
+    double Pt[3];
+    for (int a = 0; a < d; ++a) Pt[a] = Dn[a] - g.n[f][a] * nDn;
+    double sc = g.area[f] / P.facet_measure[f];
+    for (int r = 0; r < d; ++r) {
+      double t = 0.0;
+      for (int a = 0; a < d; ++a) t += g.J[a][r] * Pt[a];
+      sW[f][m][r] = sc * t;
+    }
+    for (int b = 0; b < d - 1; ++b) {
+      double t = 0.0;
+      for (int a = 0; a < d; ++a) t += g.t[f][b][a] * Dn[a];
+      sTd[f][b][m] = t;
+    }
+  }
+  __syncthreads();
+}
+
+// Column c of the reduced stress space -> (trace-free basis index m, scalar
+// index a): every psi_a for the symmetric D_m, only the top-degree psi_a for
+// the skew D_m.
+__device__ __forceinline__ void sig_col(const Sizes& s, int c, int& m, int& a) {
+  const int ntop = s.ns - s.nsm1;
+  if (c < s.nsym * s.ns) {
+    m = c / s.ns;
+    a = c % s.ns;
+  } else {
+    const int cc = c - s.nsym * s.ns;
+    m = s.nsym + cc / ntop;
+    a = s.nsm1 + cc % ntop;
+  }
+}
+
+// G[i, (m, a)] = b(psi_a D_m, phi_i) for the local velocity row i (order:
+// bubbles, then per facet its normal functions and tangential functions).
+__device__ __forceinline__ double g_entry(const CondParams& P, const ElemGeo& g, const double (*sEm)[3][3],
+                                          const double (*sW)[8][3], const double (*sTd)[2][8], int i, int m, int a,
+                                          double adet, double idet) {
+  const Sizes s = P.s;
+  const int d = s.d, nv = d + 1;
+  int iu = -1, f = 0, q = 0;
+  double sc = 1.0;
+  if (i < s.nb) iu = i;
+  else {
+    f = (i - s.nb) / s.nfb;
+    q = (i - s.nb) % s.nfb;
+    if (q < s.nF) { iu = s.nb + f * s.nF + q; sc = idet; }
+  }
+  if (iu >= 0) {
+    double t = 0.0;
+    const double* Vp = P.rV + ((size_t)iu * s.ns + a) * d * d;
+    for (int r = 0; r < d; ++r)
+      for (int c2 = 0; c2 < d; ++c2) t += sEm[m][r][c2] * Vp[r * d + c2];
+    t *= -adet;
+    for (int ff = 0; ff < nv; ++ff) {
+      const double* Bp = P.rBf + (((size_t)ff * s.nu + iu) * s.ns + a) * d;
+      for (int r = 0; r < d; ++r) t += sW[ff][m][r] * Bp[r];
+    }
+    return sc * t;
+  }
+  const int j = q - s.nF, b = j / s.nFkm1, gm = j % s.nFkm1;
+  return -(g.area[f] / P.facet_measure[f]) * sTd[f][b][m] * P.rU[((size_t)f * s.nFkm1 + gm) * s.ns + a];
+}
+
+// Lambda (the top-degree nt-trace moments of the reduced stress columns),
+// made row-orthonormal in place by two Cholesky-QR passes (Lm: nlam x nsig,
+// sS: 48 x 48 LDS).  Returns false on a Cholesky breakdown.
+__device__ __forceinline__ bool lambda_q(const CondParams& P, const double (*sTd)[2][8], double* Lm, double* sS) {
+  const Sizes s = P.s;
+  const int d = s.d, nq = s.nFk - s.nFkm1;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < s.nlam * s.nsig; idx += blockDim.x) {
+    int l = idx / s.nsig, m, a;
+    sig_col(s, idx % s.nsig, m, a);
+    int qq = l % nq, fb = l / nq, f = fb / (d - 1), b = fb % (d - 1);
+    Lm[idx] = sTd[f][b][m] * P.rL[((size_t)f * nq + qq) * s.ns + a];
+  }
+  __syncthreads();
+  bool ok = true;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int idx = tid; idx < s.nlam * s.nlam; idx += blockDim.x) {
+      int i = idx / s.nlam, j = idx % s.nlam;
+      double t = 0.0;
+      for (int c = 0; c < s.nsig; ++c) t += Lm[i * s.nsig + c] * Lm[j * s.nsig + c];
+      sS[i * 48 + j] = t;
+    }
+    __syncthreads();
+    ok = block_cholesky(sS, s.nlam, 48) && ok;
+    block_trsm_lower(sS, 48, Lm, s.nsig, s.nlam, s.nsig);
+  }
+  return ok;
+}
+
+__global__ void __launch_bounds__(256) k_condense(CondParams P) {
+  const Sizes s = P.s;
+  const int d = s.d;
   const int tid = threadIdx.x;
   __shared__ ElemGeo g;
   __shared__ double sEm[8][3][3];
@@ -232,8 +355,6 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
   __shared__ double sTd[4][2][8];
   __shared__ double sS[48 * 48];
   __shared__ double lds[2 * 16 * 64];
-  const int nq = s.nFk - s.nFkm1;
-  const int ntop = s.ns - s.nsm1;
   double* scr = P.scratch + (size_t)blockIdx.x * P.slot_doubles;
   double* G = scr;                                   // nA x nsig
   double* Lm = G + (size_t)s.nA * s.nsig;            // nlam x nsig
@@ -243,97 +364,15 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
   double* Wk = Ai + (size_t)s.nb * s.nb;             // nb x nb
 
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
-    if (tid == 0) element_geometry(P, e, g);
-    __syncthreads();
-    // coefficient tables
-    for (int idx = tid; idx < nD * nv; idx += blockDim.x) {
-      int m = idx % nD, f = idx / nD;
-      double D[3][3];
-      dm_basis(d, m, D);
-      if (f == 0) {  // Em = J^T D_m J^{-T}
-        for (int r = 0; r < d; ++r)
-          for (int c = 0; c < d; ++c) {
-            double t = 0.0;
-            for (int a = 0; a < d; ++a)
-              for (int b = 0; b < d; ++b) t += g.J[a][r] * D[a][b] * g.Ji[c][b];
-            sEm[m][r][c] = t;
-          }
-      }
-      double Dn[3] = {0, 0, 0}, nDn = 0.0;
-      for (int a = 0; a < d; ++a) {
-        for (int b = 0; b < d; ++b) Dn[a] += D[a][b] * g.n[f][b];
-        nDn += g.n[f][a] * Dn[a];
-      }
-      double Pt[3];
-      for (int a = 0; a < d; ++a) Pt[a] = Dn[a] - g.n[f][a] * nDn;
-      double sc = g.area[f] / P.facet_measure[f];
-      for (int r = 0; r < d; ++r) {
-        double t = 0.0;
-        for (int a = 0; a < d; ++a) t += g.J[a][r] * Pt[a];
-        sW[f][m][r] = sc * t;
-      }
-      for (int b = 0; b < d - 1; ++b) {
-        double t = 0.0;
-        for (int a = 0; a < d; ++a) t += g.t[f][b][a] * Dn[a];
-        sTd[f][b][m] = t;
-      }
-    }
-    __syncthreads();
+    stress_tables(P, e, g, sEm, sW, sTd);
     const double adet = fabs(g.det), idet = 1.0 / g.det;
-    // G (reordered local rows) and Lambda
+    // G (reordered local rows)
     for (int64_t idx = tid; idx < (int64_t)s.nA * s.nsig; idx += blockDim.x) {
-      int i = (int)(idx / s.nsig), c = (int)(idx % s.nsig);
-      int m, a;
-      if (c < s.nsym * s.ns) { m = c / s.ns; a = c % s.ns; }
-      else { int cc = c - s.nsym * s.ns; m = s.nsym + cc / ntop; a = s.nsm1 + cc % ntop; }
-      double val;
-      int iu = -1, f = 0, q = 0;
-      double sc = 1.0;
-      if (i < s.nb) iu = i;
-      else {
-        f = (i - s.nb) / s.nfb;
-        q = (i - s.nb) % s.nfb;
-        if (q < s.nF) { iu = s.nb + f * s.nF + q; sc = idet; }
-      }
-      if (iu >= 0) {
-        double t = 0.0;
-        const double* Vp = P.rV + ((size_t)iu * s.ns + a) * d * d;
-        for (int r = 0; r < d; ++r)
-          for (int c2 = 0; c2 < d; ++c2) t += sEm[m][r][c2] * Vp[r * d + c2];
-        t *= -adet;
-        for (int ff = 0; ff < nv; ++ff) {
-          const double* Bp = P.rBf + (((size_t)ff * s.nu + iu) * s.ns + a) * d;
-          for (int r = 0; r < d; ++r) t += sW[ff][m][r] * Bp[r];
-        }
-        val = sc * t;
-      } else {
-        int j = q - s.nF, b = j / s.nFkm1, gm = j % s.nFkm1;
-        val = -(g.area[f] / P.facet_measure[f]) * sTd[f][b][m] * P.rU[((size_t)f * s.nFkm1 + gm) * s.ns + a];
-      }
-      G[idx] = val;
+      int i = (int)(idx / s.nsig), m, a;
+      sig_col(s, (int)(idx % s.nsig), m, a);
+      G[idx] = g_entry(P, g, sEm, sW, sTd, i, m, a, adet, idet);
     }
-    for (int idx = tid; idx < s.nlam * s.nsig; idx += blockDim.x) {
-      int l = idx / s.nsig, c = idx % s.nsig;
-      int m, a;
-      if (c < s.nsym * s.ns) { m = c / s.ns; a = c % s.ns; }
-      else { int cc = c - s.nsym * s.ns; m = s.nsym + cc / ntop; a = s.nsm1 + cc % ntop; }
-      int qq = l % nq, fb = l / nq, f = fb / (d - 1), b = fb % (d - 1);
-      Lm[idx] = sTd[f][b][m] * P.rL[((size_t)f * nq + qq) * s.ns + a];
-    }
-    __syncthreads();
-    // two Cholesky-QR passes: rows of Lm become orthonormal
-    bool ok = true;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int idx = tid; idx < s.nlam * s.nlam; idx += blockDim.x) {
-        int i = idx / s.nlam, j = idx % s.nlam;
-        double t = 0.0;
-        for (int c = 0; c < s.nsig; ++c) t += Lm[i * s.nsig + c] * Lm[j * s.nsig + c];
-        sS[i * 48 + j] = t;
-      }
-      __syncthreads();
-      ok = block_cholesky(sS, s.nlam, 48) && ok;
-      block_trsm_lower(sS, 48, Lm, s.nsig, s.nlam, s.nsig);
-    }
+    bool ok = lambda_q(P, sTd, Lm, sS);
     // Y = G Q^T
     for (int n0 = 0; n0 < s.nlam; n0 += 64)
       for (int m0 = 0; m0 < s.nA; m0 += 64) {
@@ -945,6 +984,132 @@ __global__ void k_pmean_sub(SolveParams P, const double* __restrict__ pconst, co
     x[P.off_p + i] -= m * pconst[i % np];
 }
 
+// --------------------------------------------------------------------------
+// Stress and vorticity recovery (Sec. 4.2, eq. projection) at reference
+// points.  In the orthonormal stress basis psi_a D_m (mass matrix (|T|/nu) I)
+// the local problems give, with g = G^T u over the reduced columns,
+//     sigma = (nu/|T|) (I - Q^T Q) g,
+// and the multiplier omega in W_h = P^{k-1}(T, K) has the coefficients
+// -(1/|T|) b(psi_a D_m, u) on the skew D_m and the psi_a of degree < k (these
+// columns are exactly the ones the reduced space leaves out).  One workgroup
+// per element; the slot scratch holds Q and the small vectors.
+// --------------------------------------------------------------------------
+constexpr int MAXNS = 56;  // dim P^5 in 3D
+
+__global__ void __launch_bounds__(256) k_stress(StressParams S) {
+  const CondParams& P = S.C;
+  const Sizes s = P.s;
+  const int d = s.d, nv = d + 1, tid = threadIdx.x;
+  const int nW = s.nskew * s.nsm1;
+  __shared__ ElemGeo g;
+  __shared__ double sEm[8][3][3];
+  __shared__ double sW[4][8][3];
+  __shared__ double sTd[4][2][8];
+  __shared__ double sS[48 * 48];
+  double* Lm = P.scratch + (size_t)blockIdx.x * P.slot_doubles;  // nlam x nsig
+  double* ul = Lm + (size_t)s.nlam * s.nsig;                      // nA
+  double* gs = ul + s.nA;                                         // nsig
+  double* tq = gs + s.nsig;                                       // nlam
+  double* wc = tq + s.nlam;                                       // nskew x nsm1
+  for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
+    stress_tables(P, e, g, sEm, sW, sTd);
+    const double adet = fabs(g.det), idet = 1.0 / g.det;
+    for (int i = tid; i < s.nA; i += blockDim.x) {
+      double v = 0.0;
+      if (i < s.nb) {
+        v = S.x[e * s.nb + i];
+      } else {
+        const int f = (i - s.nb) / s.nfb, q = (i - s.nb) % s.nfb;
+        const int gf = S.elem_ff[e * nv + f];
+        if (gf >= 0) v = S.x[S.off_f + (int64_t)gf * s.nfb + q];
+      }
+      ul[i] = v;
+    }
+    const bool ok = lambda_q(P, sTd, Lm, sS);  // synchronises: ul visible
+    for (int c = tid; c < s.nsig + nW; c += blockDim.x) {
+      int m, a;
+      if (c < s.nsig) sig_col(s, c, m, a);
+      else { m = s.nsym + (c - s.nsig) / s.nsm1; a = (c - s.nsig) % s.nsm1; }
+      double t = 0.0;
+      for (int i = 0; i < s.nA; ++i) t += g_entry(P, g, sEm, sW, sTd, i, m, a, adet, idet) * ul[i];
+      if (c < s.nsig) gs[c] = t;
+      else wc[c - s.nsig] = -t / g.vol;
+    }
+    __syncthreads();
+    for (int l = tid; l < s.nlam; l += blockDim.x) {
+      double t = 0.0;
+      for (int c = 0; c < s.nsig; ++c) t += Lm[(size_t)l * s.nsig + c] * gs[c];
+      tq[l] = t;
+    }
+    __syncthreads();
+    const double cf = P.nu[e] / g.vol;
+    for (int c = tid; c < s.nsig; c += blockDim.x) {
+      double t = gs[c];
+      for (int l = 0; l < s.nlam; ++l) t -= Lm[(size_t)l * s.nsig + c] * tq[l];
+      gs[c] = cf * t;
+    }
+    __syncthreads();
+    // caller order of the sorted vertices
+    int perm[4];
+    {
+      int r = S.elem_perm[e], dig[4], avail[4];
+      for (int i = nv - 1; i >= 0; --i) {
+        dig[i] = r % (nv - i);
+        r /= (nv - i);
+      }
+      for (int i = 0; i < nv; ++i) avail[i] = i;
+      int na = nv;
+      for (int i = 0; i < nv; ++i) {
+        perm[i] = avail[dig[i]];
+        for (int j = dig[i]; j + 1 < na; ++j) avail[j] = avail[j + 1];
+        --na;
+      }
+    }
+    for (int q = tid; q < S.npts; q += blockDim.x) {
+      double lam[4], mono[MAXNS], psi[MAXNS];
+      for (int j = 0; j < nv; ++j) lam[j] = S.pts[q * nv + perm[j]];
+      for (int j = 0; j < s.ns; ++j) {
+        double v = 1.0;
+        for (int t = 0; t < nv; ++t)
+          for (int p = 0; p < (int)S.rpsib[j * nv + t]; ++p) v *= lam[t];
+        mono[j] = v;
+      }
+      for (int a = 0; a < s.ns; ++a) {
+        double v = 0.0;
+        for (int j = 0; j < s.ns; ++j) v += S.rpsi[(size_t)a * s.ns + j] * mono[j];
+        psi[a] = v;
+      }
+      double sg[3][3] = {}, om[3][3] = {};
+      const int ntop = s.ns - s.nsm1;
+      for (int m = 0; m < s.nsym + s.nskew; ++m) {
+        double cs = 0.0, cw = 0.0;
+        if (m < s.nsym) {
+          for (int a = 0; a < s.ns; ++a) cs += gs[m * s.ns + a] * psi[a];
+        } else {
+          const int mk = m - s.nsym;
+          for (int a = 0; a < ntop; ++a) cs += gs[s.nsym * s.ns + mk * ntop + a] * psi[s.nsm1 + a];
+          for (int a = 0; a < s.nsm1; ++a) cw += wc[mk * s.nsm1 + a] * psi[a];
+        }
+        double D[3][3];
+        dm_basis(d, m, D);
+        for (int r = 0; r < d; ++r)
+          for (int c = 0; c < d; ++c) {
+            sg[r][c] += cs * D[r][c];
+            om[r][c] += cw * D[r][c];
+          }
+      }
+      const size_t o = ((size_t)e * S.npts + q) * d * d;
+      for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+          S.sig[o + r * d + c] = sg[r][c];
+          S.om[o + r * d + c] = om[r][c];
+        }
+    }
+    if (tid == 0 && !ok) atomicOr(P.status, 1);
+    __syncthreads();
+  }
+}
+
 static int sgrid(int64_t n) {
   int64_t g = (n + 255) / 256;
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65535 * 8));
@@ -952,6 +1117,9 @@ static int sgrid(int64_t n) {
 
 void launch_condense(hipStream_t st, const CondParams& P, int nslots) {
   hipLaunchKernelGGL(k_condense, dim3(nslots), dim3(256), 0, st, P);
+}
+void launch_stress(hipStream_t st, const StressParams& S, int nslots) {
+  hipLaunchKernelGGL(k_stress, dim3(nslots), dim3(256), 0, st, S);
 }
 void launch_facet_setup(hipStream_t st, const FacetSetupParams& P) {
   hipLaunchKernelGGL(k_facet_setup, dim3((int)std::min<int64_t>(P.nff, 1 << 20)), dim3(256), 0, st, P);

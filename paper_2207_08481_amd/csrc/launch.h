@@ -59,6 +59,7 @@ void launch_gather_compact(hipStream_t st, int64_t nfv, int d, const int32_t* f2
 
 // setup (kernels_setup.hip)
 void launch_condense(hipStream_t st, const CondParams& P, int nslots);
+void launch_stress(hipStream_t st, const StressParams& S, int nslots);
 void launch_facet_setup(hipStream_t st, const FacetSetupParams& P);
 void launch_wsetup(hipStream_t st, const FacetSetupParams& P, const int32_t* elem_ff, int64_t ne, double* W, float* W32);
 void launch_p1_assemble(hipStream_t st, const P1Params& P);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -11,6 +12,14 @@
 namespace mcs {
 
 void set_error(const char* fmt, ...);
+
+// Host calls that may synchronise implicitly with other streams of the device
+// (creating and releasing streams, events, graphs and pinned memory,
+// synchronous copies) take this process-wide lock, and so does every stream
+// capture, so that no capture in one thread overlaps such a call from
+// another thread.  Recursive: batch binding binds its member problems.
+std::recursive_mutex& device_api_mutex();
+using ApiLock = std::lock_guard<std::recursive_mutex>;
 
 // ---------------------------------------------------------------------------
 // Local sizes of the spaces (Sec. 3) for dimension d and order k.
@@ -57,6 +66,8 @@ struct RefTables {
   std::vector<double> pmom;  // [np]                int_T^ lambda^gamma / |T^|
   std::vector<double> phi;   // [nu][nv + 3]        BDM function i: alpha (nv), reference vector w (3)
   std::vector<double> pidx;  // [np][nv]            pressure multi-indices gamma
+  std::vector<double> psi;   // [ns][ns]            psi_a = sum_j psi[a][j] lambda^{beta_j}
+  std::vector<double> psib;  // [ns][nv]            degree-k multi-indices beta_j
   double facet_measure[4];   // |F^_f|
 };
 RefTables build_ref_tables(int d, int k);
@@ -111,7 +122,7 @@ struct DevPtrs {
   int32_t* vfree_of_lat;  // [nvert] lattice vertex -> free P1 vertex or -1
   int32_t* free_to_lat;   // [nfv] free P1 vertex -> lattice vertex
   // reference tables
-  double *rV, *rBf, *rU, *rL, *rD, *rBp, *rMp, *rMpinv, *rRf, *rcn, *rct, *rpconst, *rpmom, *rphi, *rpidx;
+  double *rV, *rBf, *rU, *rL, *rD, *rBp, *rMp, *rMpinv, *rRf, *rcn, *rct, *rpconst, *rpmom, *rphi, *rpidx, *rpsi, *rpsib;
   int32_t* rlatmap;
   // element operators
   double *nu, *detJ;

@@ -26,6 +26,11 @@ void set_error(const char* fmt, ...) {
 
 const char* last_error() { return g_err; }
 
+std::recursive_mutex& device_api_mutex() {
+  static std::recursive_mutex m;
+  return m;
+}
+
 namespace {
 
 struct Layout {
@@ -521,6 +526,8 @@ int layout_workspace(mcs_problem* pb) {
   L.add("rpmom", Dd(r.pmom.size()));
   L.add("rphi", Dd(r.phi.size()));
   L.add("rpidx", Dd(r.pidx.size()));
+  L.add("rpsi", Dd(r.psi.size()));
+  L.add("rpsib", Dd(r.psib.size()));
   L.add("rlatmap", I(r.latmap.size()));
   L.add("nu", Dd(ne));
   L.add("detJ", Dd(ne));

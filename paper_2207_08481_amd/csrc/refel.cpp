@@ -541,6 +541,14 @@ RefTables build_ref_tables(int d, int k) {
     for (int j = 0; j < nv; ++j) T.phi[(size_t)i * (nv + 3) + j] = phis[i].alpha[j];
     for (int r = 0; r < 3; ++r) T.phi[(size_t)i * (nv + 3) + nv + r] = phis[i].w[r];
   }
+  // psi_a in monomial form over the degree-k barycentric powers (the
+  // Bernstein factors k!/beta! folded in), for point values of the stress
+  T.psi.assign((size_t)s.ns * s.ns, 0.0);
+  T.psib.assign((size_t)s.ns * nv, 0.0);
+  for (int a = 0; a < s.ns; ++a)
+    for (int j = 0; j < s.ns; ++j) T.psi[(size_t)a * s.ns + j] = (double)(Bpsi.C[(size_t)a * s.ns + j] * Bpsi.bfac[j]);
+  for (int j = 0; j < s.ns; ++j)
+    for (int t = 0; t < nv; ++t) T.psib[(size_t)j * nv + t] = Bpsi.bern[j][t];
   T.pidx.assign((size_t)s.np * nv, 0.0);
   for (int g = 0; g < s.np; ++g)
     for (int j = 0; j < nv; ++j) T.pidx[(size_t)g * nv + j] = Ip[g][j];

@@ -154,11 +154,13 @@ void mcs_server::run_batch(std::vector<Request*> rs, size_t off, size_t bytes) {
     auto t = clk::now();
     for (auto* r : rs) {
       r->t_done = t;
-      if (status != MCS_OK) r->info.status = status;
+      if (status != MCS_OK) {
+        r->info.status = status;
+        snprintf(r->info.message, sizeof(r->info.message), "%s", msg ? msg : "");
+      }
       r->info.latency_ms = ms_between(r->t_submit, t);
       r->done = true;
     }
-    (void)msg;
     arena.release(off, bytes);
     inflight--;
     solved += n;
@@ -200,9 +202,13 @@ void mcs_server::run_batch(std::vector<Request*> rs, size_t off, size_t bytes) {
     io += round_up(r->f.size() * 8, 256);
     double* dx = reinterpret_cast<double*>(io);
     io += round_up(infos[i].n_dof * 8, 256);
-    if (hipMemcpy(dnu, r->nu.data(), ne * 8, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(df, r->f.data(), r->f.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
-      return done(MCS_ERR_HIP, "input upload failed");
+    bool up_ok;
+    {
+      ApiLock lock(device_api_mutex());
+      up_ok = hipMemcpy(dnu, r->nu.data(), ne * 8, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(df, r->f.data(), r->f.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (!up_ok) return done(MCS_ERR_HIP, "input upload failed");
     nu[i] = dnu;
     f[i] = df;
     x[i] = dx;
@@ -216,8 +222,12 @@ void mcs_server::run_batch(std::vector<Request*> rs, size_t off, size_t bytes) {
   for (int i = 0; i < n; ++i) {
     Request* r = rs[i];
     r->x.resize(infos[i].n_dof);
-    if (hipMemcpy(r->x.data(), x[i], infos[i].n_dof * 8, hipMemcpyDeviceToHost) != hipSuccess)
-      return done(MCS_ERR_HIP, "result download failed");
+    bool down_ok;
+    {
+      ApiLock lock(device_api_mutex());
+      down_ok = hipMemcpy(r->x.data(), x[i], infos[i].n_dof * 8, hipMemcpyDeviceToHost) == hipSuccess;
+    }
+    if (!down_ok) return done(MCS_ERR_HIP, "result download failed");
     r->info.status = si[i].status;
     r->info.iterations = si[i].iterations;
     r->info.outer_steps = si[i].outer_steps;

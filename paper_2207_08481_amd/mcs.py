@@ -27,7 +27,7 @@ PC = {"KHAT": 0, "AEXT": 1, "ADELTA_MULT": 2, "SMOOTH_FWD": 3, "SMOOTH_BWD": 4, 
 
 # exported symbols of include/mcs.h
 SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
-           "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_get_array",
+           "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_get_array",
            "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_destroy",
            "mcs_status_string", "mcs_last_error",
            "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
@@ -76,10 +76,13 @@ class SolveInfo(C.Structure):
 class RequestInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("outer_steps", C.c_int32),
                 ("batch_size", C.c_int32), ("rel_residual", C.c_double), ("rel_precond_residual", C.c_double),
-                ("queue_ms", C.c_double), ("solve_ms", C.c_double), ("latency_ms", C.c_double)]
+                ("queue_ms", C.c_double), ("solve_ms", C.c_double), ("latency_ms", C.c_double),
+                ("message", C.c_char * 160)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["message"] = d["message"].decode(errors="replace")
+        return d
 
 
 class ServerStats(C.Structure):
@@ -117,6 +120,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_solve_rhs.argtypes = [vp, vp, vp, C.POINTER(SolveInfo)]
     lib.mcs_normalize_pressure.argtypes = [vp, vp]
     lib.mcs_eval.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.mcs_eval_stress.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.mcs_get_array.argtypes = [vp, C.c_char_p, C.POINTER(vp), C.POINTER(i64)]
     lib.mcs_get_topology.argtypes = [vp, vp, vp]
     lib.mcs_timer_enable.argtypes = [vp, i32]
@@ -149,7 +153,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_server_destroy.argtypes = [vp]
     lib.mcs_server_destroy.restype = None
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
-                 "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_get_array",
+                 "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_get_array",
                  "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
                  "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable", "mcs_batch_timer_read",
@@ -293,6 +297,21 @@ class Problem:
         p = torch.zeros((self.n_elements, npts), dtype=torch.float64, device=self.device)
         _check(self._lib.mcs_eval(self._h, x.data_ptr(), npts, pts.ctypes.data, u.data_ptr(), p.data_ptr()))
         return u, p
+
+    def eval_stress(self, x, ref_pts):
+        """(sigma, omega), each [n_e, n_pts, dim, dim]: the stress and vorticity
+        recovered from x (local problems of the condensation) at barycentric
+        points ref_pts [n_pts, dim+1] w.r.t. each element's vertices in caller
+        order."""
+        import torch
+        pts = np.ascontiguousarray(ref_pts, dtype=np.float64)
+        npts = pts.shape[0]
+        shape = (self.n_elements, npts, self.dim, self.dim)
+        sig = torch.zeros(shape, dtype=torch.float64, device=self.device)
+        om = torch.zeros(shape, dtype=torch.float64, device=self.device)
+        _check(self._lib.mcs_eval_stress(self._h, x.data_ptr(), npts, pts.ctypes.data, sig.data_ptr(),
+                                         om.data_ptr()))
+        return sig, om
 
     def normalize_pressure(self, x):
         _check(self._lib.mcs_normalize_pressure(self._h, x.data_ptr()))

@@ -130,10 +130,10 @@ def test_micro_batches_overlap():
         time.sleep(0.002)
     for j, rid in ids:
         _, info = srv.wait(rid, n_dof(request(j)))
-        assert info["status"] == 0
+        assert info["status"] == 0, info
     from paper_2207_08481_amd import Problem
     nd_big = Problem(big.vertices, big.elements, big.lattice, 4).n_dof
     _, info = srv.wait(rid_big, nd_big)
-    assert info["status"] == 0
+    assert info["status"] == 0, info
     assert seen == 2, seen
     srv.close()
