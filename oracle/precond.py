@@ -14,6 +14,15 @@ for the double Schur complement A^d -- oracle (FP64, sequential).
 * Additive variant (Sec. 5.2, the additive auxiliary-space preconditioner of
   Theorem aux_pc_schur): A-hat^d_a^{-1} = D^{-1} + E^d C^{-1} E^d^T with D the
   facet block Jacobi preconditioner, one block D_F per free facet.
+* Full-system variant (Sec. 5.2, Theorem aux_pc with the Gauss-Seidel form of
+  Corollary aux_pc_mult; the paper's Table ST_full_vs_cond compares it with the
+  condensed one): A-hat is applied to the whole velocity block A without the
+  bubble factorisation.  Overlapping blocks, one per facet F of the mesh
+  (Dirichlet facets included), each holding the free dofs of F and the bubble
+  dofs of the elements adjacent to F; s block Gauss-Seidel sweeps in colour
+  order (a greedy colouring of all facets in canonical order in which facets
+  of one element differ), the coarse correction E C^{-1} E^T with the full
+  embedding (bubble rows included), s sweeps in reverse colour order.
 * E^d: rows of the embedding E u = (u, u_t) of continuous P1 (eq. defE) for the
   facet dofs (eq. defED).
 * C: one symmetric V(1,1) multigrid cycle for A-bar, the P1 form
@@ -115,8 +124,12 @@ class P1Multigrid:
         return Dinv
 
     def _jacobi(self, lvl, r):
+        """Block l1-Jacobi step; r is a vector or a matrix of columns."""
         d = self.d
-        return np.einsum("vab,vb->va", lvl["Dinv"], r.reshape(-1, d)).ravel()
+        if r.ndim == 1:
+            return np.einsum("vab,vb->va", lvl["Dinv"], r.reshape(-1, d)).ravel()
+        m = r.shape[1]
+        return np.einsum("vab,vbm->vam", lvl["Dinv"], r.reshape(-1, d, m)).reshape(-1, m)
 
     def vcycle(self, b, level=0):
         lvl = self.levels[level]
@@ -233,7 +246,7 @@ def assemble_p1(gs):
 
 class Preconditioner:
     def __init__(self, gs, lattice, smoothing_steps=2, coarse_max=512, variant="multiplicative"):
-        assert variant in ("multiplicative", "additive")
+        assert variant in ("multiplicative", "additive", "full")
         self.gs = gs
         topo = gs.topo
         d = gs.d
@@ -263,6 +276,69 @@ class Preconditioner:
         self.mg = P1Multigrid(self.Abar, lattice, d, coarse_max=coarse_max)
         # element-local pressure mass inverses
         self.Mp_inv = [np.linalg.inv(es["Mp"]) for es in gs.elems]
+        if variant == "full":
+            self._setup_full()
+
+    def _setup_full(self):
+        """Velocity block A, overlapping facet blocks and their inverses, the
+        all-facet colouring and the full embedding (full-system variant)."""
+        gs, topo = self.gs, self.gs.topo
+        nb = gs.nb
+        K = gs.assemble_K().tocsr()
+        self.Afull = K[:gs.off_p][:, :gs.off_p].tocsr()
+        self.blocks, self.Binv = [], []
+        for f in range(topo.n_facets):
+            g = topo.free_facet_of[f]
+            dofs = list(gs.facet_dofs(g)) if g >= 0 else []
+            for (t, _i) in topo.facet_neighbors[f]:
+                dofs += list(range(t * nb, (t + 1) * nb))
+            dofs = np.asarray(sorted(dofs), dtype=np.int64)
+            self.blocks.append(dofs)
+            self.Binv.append(np.linalg.inv(self.Afull[dofs][:, dofs].toarray()))
+        # greedy colouring of all facets: facets of one element differ
+        colour = -np.ones(topo.n_facets, dtype=np.int64)
+        for f in range(topo.n_facets):
+            used = {int(colour[f2]) for (t, _i) in topo.facet_neighbors[f] for f2 in topo.elem_facets[t]
+                    if f2 != f and colour[f2] >= 0}
+            c = 0
+            while c in used:
+                c += 1
+            colour[f] = c
+        self.full_colour = colour
+        self.full_colour_lists = [np.nonzero(colour == c)[0] for c in range(int(colour.max()) + 1)]
+        self.Efull = embedding(gs, full=True)
+
+    def full_smooth(self, x, s, order):
+        for c in order:
+            for f in self.full_colour_lists[c]:
+                B = self.blocks[f]
+                r = s[B] - self.Afull[B] @ x[:self.gs.off_p]
+                x[B] += self.Binv[f] @ r
+        return x
+
+    def A_full_inv(self, r):
+        """A-hat^{-1} r of the full-system variant (velocity parts; x^0 = 0;
+        s forward sweeps; coarse correction on the residual; s backward
+        sweeps).  r is a vector or a matrix whose columns are treated alike."""
+        gs = self.gs
+        s = np.zeros(r.shape)
+        s[:gs.off_p] = r[:gs.off_p]
+        x = np.zeros(r.shape)
+        nc = len(self.full_colour_lists)
+        for _ in range(self.steps):
+            x = self.full_smooth(x, s, range(nc))
+        res = np.zeros(r.shape)
+        res[:gs.off_p] = s[:gs.off_p] - self.Afull @ x[:gs.off_p]
+        x = x + self.Efull @ self.mg.vcycle(self.Efull.T @ res)
+        for _ in range(self.steps):
+            x = self.full_smooth(x, s, range(nc - 1, -1, -1))
+        x[gs.off_p:] = 0.0
+        return x
+
+    def A_hat_inv(self, r):
+        """The A-hat^{-1} inside K-hat^{-1}: through the condensed system
+        (A-hat_ext) or, for the full-system variant, directly."""
+        return self.A_full_inv(r) if self.variant == "full" else self.A_ext_inv(r)
 
     # ---- pieces ---------------------------------------------------------
     def smooth(self, x, s, order):
@@ -371,11 +447,11 @@ class Preconditioner:
         gs = self.gs
         ru = r.copy()
         ru[gs.off_p:] = 0.0
-        a = self.A_ext_inv(ru)
+        a = self.A_hat_inv(ru)
         rp = np.zeros(gs.n_dof)
         rp[gs.off_p:] = r[gs.off_p:]
         yp = self.Mp_inv_apply(rp - self.B_apply(a))
-        yu = a - self.A_ext_inv(self.BT_apply(yp))
+        yu = a - self.A_hat_inv(self.BT_apply(yp))
         y = yu
         y[gs.off_p:] = yp[gs.off_p:]
         return y

@@ -408,3 +408,66 @@ def test_additive_needs_more_iterations_than_multiplicative():
         assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
         its[variant] = info["iterations"]
     assert its["multiplicative"] < its["additive"], its
+
+
+@pytest.mark.parametrize("d,n,k,cm", [(2, 4, 2, 20), (3, 2, 2, 512)])
+def test_full_system_asp_bounds(d, n, k, cm):
+    """Full-system variant (Theorem aux_pc with the Gauss-Seidel smoother of
+    Corollary aux_pc_mult): blocks of one colour share no element, so their
+    coupling in A vanishes and a colour phase is exact; the symmetric
+    multiplicative preconditioner satisfies A <= A-hat (eigenvalues of
+    A-hat^{-1} A in (0, 1], using E^T A E = A-bar <= C with the full
+    embedding)."""
+    mesh, gs, _ = problem(d, n, k)
+    pc = Preconditioner(gs, mesh.lattice, coarse_max=cm, variant="full")
+    A = pc.Afull.toarray()
+    for lst in pc.full_colour_lists:
+        for i, f in enumerate(lst):
+            for g in lst[i + 1:]:
+                assert not np.any(A[np.ix_(pc.blocks[f], pc.blocks[g])]), (f, g)
+    # every velocity dof lies in some block (bubbles in d+1 overlapping ones)
+    cover = np.zeros(gs.off_p, dtype=int)
+    for B in pc.blocks:
+        cover[B] += 1
+    assert cover[:gs.off_f].min() == d + 1 and cover[gs.off_f:].min() == 1
+    idx = np.arange(gs.off_p)
+    P = pc.A_full_inv(np.eye(gs.n_dof)[:, idx])[idx]
+    assert np.allclose(P, P.T, atol=1e-10 * np.abs(P).max())
+    lam = np.linalg.eigvals(P @ A).real
+    assert lam.min() > 1e-8 and lam.max() <= 1 + 1e-9
+
+
+def test_full_system_asp_columns_match_vectors():
+    """The matrix form of A_full_inv (several right-hand sides at once, used
+    to form dense operators) equals column-by-column application."""
+    mesh, gs, _ = problem(2, 4, 2)
+    pc = Preconditioner(gs, mesh.lattice, variant="full")
+    R = np.random.default_rng(1).standard_normal((gs.n_dof, 3))
+    Y = pc.A_full_inv(R)
+    for j in range(3):
+        assert np.allclose(Y[:, j], pc.A_full_inv(R[:, j].copy()), rtol=1e-12, atol=1e-12 * np.abs(Y).max())
+
+
+def test_full_system_asp_mesh_independent():
+    """Theorem aux_pc: the condition number of the full-system preconditioner
+    does not grow with 1/h (2D, k = 2, n = 4 -> 8: within 25%)."""
+    kap = []
+    for n in (4, 8):
+        mesh, gs, _ = problem(2, n, 2)
+        pc = Preconditioner(gs, mesh.lattice, variant="full")
+        idx = np.arange(gs.off_p)
+        P = pc.A_full_inv(np.eye(gs.n_dof)[:, idx])[idx]
+        lam = np.sort(np.linalg.eigvals(P @ pc.Afull.toarray()).real)
+        kap.append(lam[-1] / lam[0])
+    assert kap[1] <= 1.25 * kap[0], kap
+
+
+def test_full_system_asp_solves():
+    """MINRES with the full-system variant reaches the direct solution."""
+    mesh, gs, _ = problem(3, 2, 2)
+    K = gs.assemble_K()
+    pc = Preconditioner(gs, mesh.lattice, variant="full")
+    x, info = minres(lambda v: K @ v, pc.apply, gs.assemble_rhs(), tol=1e-10, max_it=2000)
+    xd = gs.direct_solve()
+    assert np.linalg.norm(gs.normalize_pressure(x) - xd) <= 1e-7 * np.linalg.norm(xd)
+    assert info["iterations"] < 200
