@@ -128,7 +128,15 @@ typedef struct {
   int32_t smoother;         /* auxiliary-space preconditioner of A^d (Sec. 5.2):
                                0: multiplicative, coloured facet block Gauss-Seidel (Corollary aux_pc_mult);
                                1: additive, facet block Jacobi D = blockdiag(D_F):
-                                  A-hat^d^{-1} = D^{-1} + E^d C^{-1} E^d^T (Theorem aux_pc_schur) */
+                                  A-hat^d^{-1} = D^{-1} + E^d C^{-1} E^d^T (Theorem aux_pc_schur);
+                               2: full system (Theorem aux_pc, Gauss-Seidel form of Corollary aux_pc_mult):
+                                  A-hat of the whole velocity block A instead of A-hat_ext, overlapping
+                                  blocks per facet (its free dofs and the bubbles of its neighbours,
+                                  Dirichlet facets included) swept in the colours of a greedy colouring of
+                                  all facets, around E C^{-1} E^T with the full embedding.  Single
+                                  problems, precision 0, n_fb + 2 n_b <= 64 (2D k <= 5, 3D k <= 3);
+                                  otherwise MCS_ERR_UNSUPPORTED.  mcs_precond_apply(MCS_PC_AEXT) then
+                                  applies this A-hat^{-1}. */
 } mcs_options;
 
 typedef struct {
@@ -230,6 +238,12 @@ int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count)
  * and n_elements*(dim+1). */
 int mcs_get_topology(const mcs_problem* pb, int32_t* colour_host, int32_t* elem_ff_host);
 
+/* Blocks of the full-system variant (smoother 2), one per facet of the mesh in
+ * canonical order (facets sorted by their sorted vertex ids): their number,
+ * and, when colour_host (host int32[n_blocks]) is given, the colour of each
+ * (greedy in canonical order; facets of one element differ).  Host only. */
+int mcs_get_full_colouring(const mcs_problem* pb, int64_t* n_blocks, int32_t* colour_host);
+
 /* Measurement hook for the dominant solve kernels.  While enabled, every
  * launch of a timed kernel is bracketed by HIP events on the problem's stream.
  * mcs_timer_read returns, for one kernel, the accumulated kernel time, the
@@ -244,8 +258,10 @@ int mcs_get_topology(const mcs_problem* pb, int32_t* colour_host, int32_t* elem_
  *     eq. factorSsigma).  Per element: A^d_T, H_T and A_oo,T as stored
  *     (n_d^2 + n_b n_d + n_b^2 words), the gathered inputs and written outputs
  *     (2 (n_d + n_b + n_p) words), the free facet ids and det J.
- * Enabling resets the counters.  kernel outside the two values:
- * MCS_ERR_ARG.  [sync on read] */
+ * enable = 0 switches the timer off; enable = p >= 1 times one call in p (all
+ * launches of a sampled sweep call, every p-th operator apply), so that the
+ * event records disturb a timed run little.  Enabling resets the counters.
+ * kernel outside the two values, enable < 0: MCS_ERR_ARG.  [sync on read] */
 enum { MCS_TIMER_SMOOTH = 0, MCS_TIMER_KAPPLY = 1 };
 int mcs_timer_enable(mcs_problem* pb, int enable);
 int mcs_timer_read(mcs_problem* pb, int32_t kernel, double* total_ms, int64_t* launches, double* bytes);

@@ -287,6 +287,10 @@ int mcs_batch_plan(const mcs_mesh* meshes, const int32_t* orders, int32_t n, con
     set_error("batch plan: null argument or empty batch");
     return MCS_ERR_ARG;
   }
+  if (options->smoother == 2) {
+    set_error("batch plan: the full-system variant (smoother 2) is for single problems");
+    return MCS_ERR_UNSUPPORTED;
+  }
   *out = nullptr;
   std::unique_ptr<mcs_batch> B(new (std::nothrow) mcs_batch());
   if (!B) {

@@ -171,7 +171,7 @@ struct Ctx {
   void apply(const R* x, R* y, int flags) {
     if (flags & 8) launch_fill<R>(st, n, R(0), y);
     // the timer takes the full operator apply of a single problem (no masks)
-    const bool timed = pb->timer_on && flags == (1 | 2 | 4) && !P.active;
+    const bool timed = pb->timer_on && flags == (1 | 2 | 4) && !P.active && pb->t_tick[1]++ % pb->timer_period == 0;
     if (timed) {
       timer_start(pb, st, 1);
       pb->t_bytes[1] += pb->ne * kapply_bytes_per_elem(pb->sz, pb->d, sizeof(R));
@@ -199,13 +199,15 @@ struct Ctx {
   // descending); y holds the element products A^d_T x_T and is kept current.
   void sweeps(R* x, const R* s, R* y, bool forward) {
     SolveParams Pt = P;
-    if (pb->timer_on) Pt.work_count = work_counters(pb) + (sizeof(R) == 8 ? 0 : 256 * 16);
+    // the timer samples one call in timer_period (all launches of that call)
+    const bool timed = pb->timer_on && pb->t_tick[0]++ % pb->timer_period == 0;
+    if (timed) Pt.work_count = work_counters(pb) + (sizeof(R) == 8 ? 0 : 256 * 16);
     const int fpw = pb->tune_fpw[sizeof(R) == 8 ? 0 : 1];
     const int64_t cap = pb->tune_cap[sizeof(R) == 8 ? 0 : 1];
     for (int it = 0; it < pb->opt.smoothing_steps; ++it)
       for (int cc = 0; cc < pb->ncol; ++cc) {
         int c = forward ? cc : pb->ncol - 1 - cc;
-        if (pb->timer_on) {
+        if (timed) {
           timer_start(pb, st, 0);
           launch_smooth_phase<R>(st, Pt, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y, fpw, cap);
           timer_stop(pb, st);
@@ -249,8 +251,67 @@ struct Ctx {
     sweeps(x, s, escr, false);
   }
 
-  // y = A-hat_ext^{-1} r (velocity parts; pressure part of y set to 0)
+  FullDev full_dev() const {
+    FullDev F{};
+    F.nblk = pb->nblk;
+    F.nbk = pb->sz.nfb + 2 * pb->sz.nb;
+    F.blk_el = pb->p.blk_el;
+    F.blk_slot = pb->p.blk_slot;
+    F.blk_g = pb->p.blk_g;
+    F.colour_blocks = pb->p.colour_blocks;
+    F.A = pb->p.Afull;
+    F.Binv = pb->p.Binv;
+    F.W = pb->p.Wfull;
+    F.Eo = pb->p.Eo;
+    F.Eo_ref = pb->p.Eoref;
+    return F;
+  }
+
+  // y = A-hat^{-1} r of the full-system variant (velocity parts; pressure
+  // part of y set to 0): x = 0; forward overlapping block Gauss-Seidel
+  // sweeps; coarse correction with the full embedding on r - A x; backward
+  // sweeps.  FP64 only (the planner refuses other precisions).
+  void full_inv(const R* r, R* y) {
+    if constexpr (sizeof(R) == 8) {
+      const FullDev F = full_dev();
+      double* yf = pb->p.yfull;
+      double* tmp = v(PTMP);
+      launch_fill<R>(st, n, R(0), y);
+      launch_fill<double>(st, pb->ne * pb->sz.nA, 0.0, yf);
+      full_sweeps(F, y, r, yf, true);
+      launch_full_resid(st, P, r, yf, tmp);
+      launch_edt<R>(st, P, O, tmp, fscr, pb->nfv, pb->p.vinc_off, pb->p.vinc, pb->p.free_to_lat, (R*)L[0].b, 0);
+      launch_full_edt(st, P, F, tmp, pb->p.eto, pb->nvert, pb->p.vert_elem_off, pb->p.vert_elem, pb->p.elem_verts,
+                      pb->p.vfree_of_lat, (double*)L[0].b);
+      vcycle(0);
+      launch_ed<R>(st, P, O, pb->p.facet_vfree, pb->p.free_to_lat, (const R*)L[0].x, y, 1, 0);
+      launch_full_ed(st, P, F, pb->p.elem_verts, pb->p.vfree_of_lat, (const double*)L[0].x, y, yf);
+      full_sweeps(F, y, r, yf, false);
+      launch_fill<R>(st, pb->ndof - pb->off_p, R(0), y + pb->off_p);
+    }
+  }
+
+  void full_sweeps(const FullDev& F, double* x, const double* s, double* yf, bool forward) {
+    const bool timed = pb->timer_on && pb->t_tick[0]++ % pb->timer_period == 0;
+    for (int it = 0; it < pb->opt.smoothing_steps; ++it)
+      for (int cc = 0; cc < pb->ncol_full; ++cc) {
+        const int c = forward ? cc : pb->ncol_full - 1 - cc;
+        if (timed) {
+          timer_start(pb, st, 0);
+          pb->t_bytes[0] += pb->full_colour_bytes[c];
+        }
+        launch_full_smooth(st, P, F, pb->colour_off_full[c], pb->colour_off_full[c + 1], x, s, yf);
+        if (timed) timer_stop(pb, st);
+      }
+  }
+
+  // y = A-hat_ext^{-1} r (velocity parts; pressure part of y set to 0); the
+  // full-system variant replaces it by its own A-hat^{-1}
   void ext_inv(const R* r, R* y) {
+    if (pb->opt.smoother == 2) {
+      full_inv(r, y);
+      return;
+    }
     R *S = v(PS), *T = v(PT), *T1 = v(PT1);
     launch_ext_pre<R>(st, P, O, r, T1, escr);
     launch_facet_sum<R>(st, P, escr, r, R(-1), S);

@@ -283,6 +283,17 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   p.red = ws_ptr<double>(pb, "red");
   p.scal = ws_ptr<double>(pb, "scal");
   p.wcount = ws_ptr<unsigned long long>(pb, "wcount");
+  p.blk_el = ws_ptr<int32_t>(pb, "blk_el");
+  p.blk_slot = ws_ptr<int32_t>(pb, "blk_slot");
+  p.blk_g = ws_ptr<int32_t>(pb, "blk_g");
+  p.colour_blocks = ws_ptr<int32_t>(pb, "colour_blocks");
+  p.Afull = ws_ptr<double>(pb, "Afull");
+  p.Binv = ws_ptr<double>(pb, "Binv");
+  p.Wfull = ws_ptr<double>(pb, "Wfull");
+  p.Eo = ws_ptr<double>(pb, "Eo");
+  p.Eoref = ws_ptr<double>(pb, "Eoref");
+  p.yfull = ws_ptr<double>(pb, "yfull");
+  p.eto = ws_ptr<double>(pb, "eto");
   p.vec = ws_ptr<double>(pb, "vec");
   p.vec32 = ws_ptr<float>(pb, "vec32");
   p.p1 = ws_ptr<double>(pb, "p1");
@@ -327,6 +338,13 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   HIPCHK(up(p.rpsib, r.psib.data(), r.psib.size() * 8));
   HIPCHK(up(p.rlatmap, r.latmap.data(), r.latmap.size() * 4));
   HIPCHK(up(p.cmap, pb->h_cmap.data(), pb->h_cmap.size() * 4));
+  if (p.blk_el) {
+    HIPCHK(up(p.blk_el, pb->h_blk_el.data(), pb->h_blk_el.size() * 4));
+    HIPCHK(up(p.blk_slot, pb->h_blk_slot.data(), pb->h_blk_slot.size() * 4));
+    HIPCHK(up(p.blk_g, pb->h_blk_g.data(), pb->h_blk_g.size() * 4));
+    HIPCHK(up(p.colour_blocks, pb->h_colour_blocks.data(), pb->h_colour_blocks.size() * 4));
+    HIPCHK(up(p.Eoref, r.Eo.data(), r.Eo.size() * 8));
+  }
   // multigrid lattice vectors start (and stay) zero on the boundary; block tables
   const int d = pb->d;
   for (auto& M : pb->mg) {
@@ -411,6 +429,7 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   C.Aool = p.Aool;
   C.adtmp = p.adtmp;
   C.adtmp_stride = (int64_t)pb->sz.nd * pb->sz.nd;
+  C.Afull = p.Afull;
   launch_condense(st, C, (int)pb->n_slots);
 
   FacetSetupParams F{};
@@ -432,6 +451,10 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   F.status = status;
   if (pb->nff > 0) launch_facet_setup(st, F);
   launch_wsetup(st, F, p.elem_ff, pb->ne, p.W, p.W32);
+  if (pb->opt.smoother == 2) {
+    Ctx<double> c(pb);
+    launch_full_setup(st, pb->sz, pb->ne, c.full_dev(), p.elem_verts, p.coords, p.elem_ff, p.EF, status);
+  }
 
   // P1 multigrid hierarchy
   const int d = pb->d, stn = d == 3 ? 27 : 9;
@@ -802,6 +825,16 @@ int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count)
   return MCS_ERR_ARG;
 }
 
+int mcs_get_full_colouring(const mcs_problem* pb, int64_t* n_blocks, int32_t* colour_host) {
+  if (!pb || !n_blocks) {
+    set_error("null argument");
+    return MCS_ERR_ARG;
+  }
+  *n_blocks = pb->nblk;
+  if (colour_host) std::copy(pb->h_blk_colour.begin(), pb->h_blk_colour.end(), colour_host);
+  return MCS_OK;
+}
+
 int mcs_get_topology(const mcs_problem* pb, int32_t* colour_host, int32_t* elem_ff_host) {
   if (!pb) {
     set_error("null problem");
@@ -817,7 +850,13 @@ int mcs_timer_enable(mcs_problem* pb, int enable) {
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(pb->stream));
   timer_flush(pb);
+  if (enable < 0) {
+    set_error("mcs_timer_enable: enable must be 0 (off) or a sampling period >= 1");
+    return MCS_ERR_ARG;
+  }
   pb->timer_on = enable != 0;
+  pb->timer_period = enable > 0 ? enable : 1;
+  pb->t_tick[0] = pb->t_tick[1] = 0;
   for (int i = 0; i < 2; ++i) {
     pb->t_ms[i] = 0.0;
     pb->t_bytes[i] = 0.0;
@@ -846,10 +885,13 @@ int mcs_timer_read(mcs_problem* pb, int32_t kernel, double* total_ms, int64_t* l
     cnt[0] += wc[i * 16];
     cnt[1] += wc[256 * 16 + i * 16];
   }
-  pb->t_bytes[0] = cnt[0] * smooth_bytes_per_facet(pb->sz, 8) + cnt[1] * smooth_bytes_per_facet(pb->sz, 4);
+  // smoother bytes: counted on the device for the condensed sweeps, on the
+  // host (per colour phase) for the full-system sweeps
+  const double smooth_bytes =
+      pb->t_bytes[0] + cnt[0] * smooth_bytes_per_facet(pb->sz, 8) + cnt[1] * smooth_bytes_per_facet(pb->sz, 4);
   if (total_ms) *total_ms = pb->t_ms[kernel];
   if (launches) *launches = pb->t_launches[kernel];
-  if (bytes) *bytes = pb->t_bytes[kernel];
+  if (bytes) *bytes = kernel == MCS_TIMER_SMOOTH ? smooth_bytes : pb->t_bytes[kernel];
   return MCS_OK;
 }
 

@@ -27,6 +27,7 @@ struct CondParams {
   // rounding of the remainder, so hi + lo reproduces the FP64 value to ~2^-48.
   // A^d is formed in a per-slot FP64 buffer adtmp first.
   float *Adl, *Hl, *Aool;
+  double* Afull;                 // optional: A_T itself (full-system variant)
   double* adtmp;
   int64_t adtmp_stride;
   int* status;
@@ -150,6 +151,24 @@ __device__ inline bool elem_off(const SolveParams& P, int64_t e) {
 __device__ inline bool facet_off(const SolveParams& P, int64_t g) {
   return P.active && !P.active[P.facet_prob[g]];
 }
+
+// Full-system variant: overlapping blocks, one per facet of the mesh
+// (Dirichlet facets included), holding the facet's free dofs and the bubbles
+// of its neighbours; the velocity block A_T per element (reordered local
+// order, FP64) and the bubble rows of the embedding E.
+struct FullDev {
+  int64_t nblk;
+  int nbk;                        // block stride n_fb + 2 n_b
+  const int32_t* blk_el;          // [nblk][2] neighbours (-1: none)
+  const int32_t* blk_slot;        // [nblk][2] local facet index in the neighbour
+  const int32_t* blk_g;           // [nblk] free facet id or -1
+  const int32_t* colour_blocks;   // blocks sorted by colour
+  const double* A;                // [ne][nA][nA]
+  double* Binv;                   // [nblk][nbk][nbk]
+  double* W;                      // [ne][(d+1)d][nA]  A_T E_T
+  double* Eo;                     // [ne][n_b][(d+1)d] bubble rows of E_T
+  const double* Eo_ref;           // [d+1][d][n_b]     lambda_v e_r on the reference element
+};
 
 template <typename R>
 struct OpPtrs {

@@ -430,6 +430,8 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
           }
       }
     __syncthreads();
+    if (P.Afull)
+      for (int idx = tid; idx < s.nA * s.nA; idx += blockDim.x) P.Afull[(size_t)e * s.nA * s.nA + idx] = A[idx];
     // condensation II: Aoo = A[0:nb,0:nb]
     const int nb = s.nb, nd = s.nd;
     for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
@@ -1110,6 +1112,126 @@ __global__ void __launch_bounds__(256) k_stress(StressParams S) {
   }
 }
 
+// --------------------------------------------------------------------------
+// Full-system variant (Theorem aux_pc): overlapping facet blocks of A, the
+// bubble rows of the embedding E and W_T = A_T E_T.
+// --------------------------------------------------------------------------
+// Local rows of entry j of block b in its two neighbours (-1: not there):
+// facet dofs first, then the bubbles of the first and of the second neighbour.
+__device__ inline void full_entry(const Sizes& s, int nf, int s0, int s1, bool two, int j, int& l0, int& l1) {
+  if (j < nf) {
+    l0 = s.nb + s0 * s.nfb + j;
+    l1 = two ? s.nb + s1 * s.nfb + j : -1;
+  } else if (j < nf + s.nb) {
+    l0 = j - nf;
+    l1 = -1;
+  } else {
+    l0 = -1;
+    l1 = j - nf - s.nb;
+  }
+}
+
+// Binv[b] = D_B^{-1}, D_B = A restricted to the dofs of block b (assembled
+// from the neighbours' A_T; bubbles of different elements do not couple).
+__global__ void __launch_bounds__(256) k_full_blocks(Sizes s, FullDev F, int* status) {
+  constexpr int FLD = 64;
+  __shared__ double S[FLD * FLD];
+  __shared__ double W[FLD * FLD];
+  const int nA = s.nA, nbk = F.nbk;
+  for (int64_t b = blockIdx.x; b < F.nblk; b += gridDim.x) {
+    const int64_t e0 = F.blk_el[2 * b], e1 = F.blk_el[2 * b + 1];
+    const int s0 = F.blk_slot[2 * b], s1 = F.blk_slot[2 * b + 1];
+    const bool two = e1 >= 0;
+    const int nf = F.blk_g[b] >= 0 ? s.nfb : 0;
+    const int m = nf + s.nb * (two ? 2 : 1);
+    const double* A0 = F.A + (size_t)e0 * nA * nA;
+    const double* A1 = two ? F.A + (size_t)e1 * nA * nA : nullptr;
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      const int i = idx / m, j = idx % m;
+      int a0, a1, c0, c1;
+      full_entry(s, nf, s0, s1, two, i, a0, a1);
+      full_entry(s, nf, s0, s1, two, j, c0, c1);
+      double v = 0.0;
+      if (a0 >= 0 && c0 >= 0) v += A0[(size_t)a0 * nA + c0];
+      if (a1 >= 0 && c1 >= 0) v += A1[(size_t)a1 * nA + c1];
+      S[i * FLD + j] = v;
+    }
+    __syncthreads();
+    const bool ok = block_cholesky(S, m, FLD);
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) W[(idx / m) * FLD + idx % m] = (idx / m == idx % m) ? 1.0 : 0.0;
+    __syncthreads();
+    block_trsm_lower(S, FLD, W, FLD, m, m);
+    for (int idx = threadIdx.x; idx < nbk * nbk; idx += blockDim.x) {
+      const int i = idx / nbk, j = idx % nbk;
+      double t = 0.0;
+      if (i < m && j < m) {
+        const int p0 = i > j ? i : j;
+        for (int p = p0; p < m; ++p) t += W[p * FLD + i] * W[p * FLD + j];
+      }
+      F.Binv[(size_t)b * nbk * nbk + idx] = t;
+    }
+    if (threadIdx.x == 0 && !ok) atomicOr(status, 2);
+    __syncthreads();
+  }
+}
+
+// Bubble rows of E_T: Eo[e][i][vl*d + c] = sum_r (J^{-1})_{r c} Eo_ref[vl][r][i]
+// (lambda_v e_c = J (lambda_v J^{-1} e_c) and bubbles map as phi = J phi^).
+__global__ void k_full_eo(Sizes s, int64_t ne, FullDev F, const int32_t* __restrict__ elem_verts,
+                          const double* __restrict__ coords) {
+  const int d = s.d, nv = d + 1, nvd = nv * d;
+  const int64_t n = ne * s.nb * nvd;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = idx / (s.nb * nvd);
+    const int i = (int)((idx / nvd) % s.nb), m = (int)(idx % nvd), vl = m / d, c = m % d;
+    double X[4][3], J[3][3];
+    for (int j = 0; j < nv; ++j) {
+      const int v = elem_verts[e * nv + j];
+      for (int r = 0; r < 3; ++r) X[j][r] = r < d ? coords[(size_t)v * d + r] : 0.0;
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) J[r][q] = (r < d && q < d) ? X[q + 1][r] - X[0][r] : (r == q ? 1.0 : 0.0);
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    // column c of J^{-1} (cofactors)
+    double Jic[3];
+    {
+      const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+      for (int r = 0; r < 3; ++r) {
+        const int r1 = (r + 1) % 3, r2 = (r + 2) % 3;
+        Jic[r] = (J[c1][r1] * J[c2][r2] - J[c1][r2] * J[c2][r1]) / det;
+      }
+    }
+    double t = 0.0;
+    for (int r = 0; r < d; ++r) t += Jic[r] * F.Eo_ref[((size_t)vl * d + r) * s.nb + i];
+    F.Eo[idx] = t;
+  }
+}
+
+// W[e][m][row] = sum_j A_T[row][j] E_T[j][m] over the bubble rows (Eo) and the
+// facet rows of the free facets (EF).
+__global__ void __launch_bounds__(256) k_full_w(Sizes s, int64_t ne, FullDev F, const int32_t* __restrict__ elem_ff,
+                                                const double* __restrict__ EF) {
+  const int d = s.d, nv = d + 1, nvd = nv * d, nA = s.nA, nfb = s.nfb, dd = d * d;
+  for (int64_t e = blockIdx.x; e < ne; e += gridDim.x) {
+    for (int idx = threadIdx.x; idx < nA * nvd; idx += blockDim.x) {
+      const int m = idx / nA, row = idx % nA;
+      const int vl = m / d, c = m % d;
+      const double* Ar = F.A + ((size_t)e * nA + row) * nA;
+      double acc = 0.0;
+      for (int j = 0; j < s.nb; ++j) acc += Ar[j] * F.Eo[((size_t)e * s.nb + j) * nvd + m];
+      for (int f = 0; f < nv; ++f) {
+        const int g = elem_ff[e * nv + f];
+        if (g < 0 || vl == f) continue;
+        const int v = vl < f ? vl : vl - 1;
+        const double* E = EF + (size_t)g * nfb * dd + v * d + c;
+        for (int q = 0; q < nfb; ++q) acc += Ar[s.nb + f * nfb + q] * E[(size_t)q * dd];
+      }
+      F.W[((size_t)e * nvd + m) * nA + row] = acc;
+    }
+  }
+}
+
 static int sgrid(int64_t n) {
   int64_t g = (n + 255) / 256;
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65535 * 8));
@@ -1117,6 +1239,12 @@ static int sgrid(int64_t n) {
 
 void launch_condense(hipStream_t st, const CondParams& P, int nslots) {
   hipLaunchKernelGGL(k_condense, dim3(nslots), dim3(256), 0, st, P);
+}
+void launch_full_setup(hipStream_t st, const Sizes& s, int64_t ne, const FullDev& F, const int32_t* elem_verts,
+                       const double* coords, const int32_t* elem_ff, const double* EF, int* status) {
+  hipLaunchKernelGGL(k_full_eo, dim3(sgrid(ne * s.nb * (s.d + 1) * s.d)), dim3(256), 0, st, s, ne, F, elem_verts, coords);
+  hipLaunchKernelGGL(k_full_blocks, dim3((unsigned)std::min<int64_t>(F.nblk, 1 << 20)), dim3(256), 0, st, s, F, status);
+  hipLaunchKernelGGL(k_full_w, dim3((unsigned)std::min<int64_t>(ne, 1 << 20)), dim3(256), 0, st, s, ne, F, elem_ff, EF);
 }
 void launch_stress(hipStream_t st, const StressParams& S, int nslots) {
   hipLaunchKernelGGL(k_stress, dim3(nslots), dim3(256), 0, st, S);

@@ -801,11 +801,189 @@ __global__ void k_gather_compact(int64_t nfv, int d, const int32_t* __restrict__
 }
 
 // ------------------------------------------------------------------ launchers
+// ------------------------------------------------ full-system variant (FP64)
+// One colour phase of overlapping block Gauss-Seidel on A (Theorem aux_pc,
+// Corollary aux_pc_mult): per block (a facet with its free dofs and the
+// bubbles of its neighbours) r_B = s_B - (A x)_B from the maintained element
+// products y_T = A_T x_T, x_B += D_B^{-1} r_B, then y_T += A_T[:, B] delta for
+// both neighbours.  Blocks of one colour share no element.
+__device__ inline int64_t full_dof(const SolveParams& P, const FullDev& F, int nf, int g, int64_t e0, int64_t e1,
+                                   int j) {
+  const Sizes& s = P.s;
+  if (j < nf) return P.off_f + (int64_t)g * s.nfb + j;
+  if (j < nf + s.nb) return e0 * s.nb + (j - nf);
+  return e1 * s.nb + (j - nf - s.nb);
+}
+
+__global__ void __launch_bounds__(256) k_full_smooth(SolveParams P, FullDev F, int c0, int c1, double* __restrict__ x,
+                                                     const double* __restrict__ sv, double* __restrict__ y) {
+  const Sizes s = P.s;
+  const int nA = s.nA, nb = s.nb, nfb = s.nfb, nbk = F.nbk, tid = threadIdx.x;
+  __shared__ double r[64], dl[64];
+  for (int64_t i = c0 + blockIdx.x; i < c1; i += gridDim.x) {
+    const int64_t b = F.colour_blocks[i];
+    const int64_t e0 = F.blk_el[2 * b], e1 = F.blk_el[2 * b + 1];
+    const int s0 = F.blk_slot[2 * b], s1 = F.blk_slot[2 * b + 1];
+    const int g = F.blk_g[b];
+    const int nside = e1 >= 0 ? 2 : 1;
+    const int nf = g >= 0 ? nfb : 0;
+    const int m = nf + nb * nside;
+    if (tid < m) {
+      double yy;
+      if (tid < nf) yy = y[e0 * nA + nb + s0 * nfb + tid] + y[e1 * nA + nb + s1 * nfb + tid];
+      else if (tid < nf + nb) yy = y[e0 * nA + tid - nf];
+      else yy = y[e1 * nA + tid - nf - nb];
+      r[tid] = sv[full_dof(P, F, nf, g, e0, e1, tid)] - yy;
+    }
+    __syncthreads();
+    if (tid < m) {
+      const double* Bi = F.Binv + (size_t)b * nbk * nbk + tid;   // symmetric: column tid
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += Bi[(size_t)j * nbk] * r[j];
+      dl[tid] = acc;
+      x[full_dof(P, F, nf, g, e0, e1, tid)] += acc;
+    }
+    __syncthreads();
+    for (int t = tid; t < nside * nA; t += blockDim.x) {
+      const int side = t / nA, row = t % nA;
+      const int64_t e = side ? e1 : e0;
+      const int sl = side ? s1 : s0;
+      const double* Ae = F.A + (size_t)e * nA * nA + row;   // A_T symmetric: rows as columns
+      double acc = 0.0;
+      for (int q = 0; q < nf; ++q) acc += Ae[(size_t)(nb + sl * nfb + q) * nA] * dl[q];
+      const int o = nf + side * nb;
+      for (int j = 0; j < nb; ++j) acc += Ae[(size_t)j * nA] * dl[o + j];
+      y[e * nA + row] += acc;
+    }
+    __syncthreads();
+  }
+}
+
+// r = s - A x on the velocity dofs, from the maintained products.
+__global__ void k_full_resid(SolveParams P, int nA, const double* __restrict__ sv, const double* __restrict__ y,
+                             double* __restrict__ r) {
+  const Sizes s = P.s;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < P.off_p;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double yy;
+    if (idx < P.off_f) {
+      yy = y[(idx / s.nb) * nA + idx % s.nb];
+    } else {
+      const int64_t g = (idx - P.off_f) / s.nfb;
+      const int q = (int)((idx - P.off_f) % s.nfb);
+      yy = y[(int64_t)P.facet_el[2 * g] * nA + s.nb + P.facet_slot[2 * g] * s.nfb + q] +
+           y[(int64_t)P.facet_el[2 * g + 1] * nA + s.nb + P.facet_slot[2 * g + 1] * s.nfb + q];
+    }
+    r[idx] = sv[idx] - yy;
+  }
+}
+
+// E^T, bubble rows: eto[e][m] = sum_i Eo[e][i][m] r_o,e[i].
+__global__ void k_full_edt(SolveParams P, FullDev F, const double* __restrict__ r, double* __restrict__ eto) {
+  const Sizes s = P.s;
+  const int nvd = (s.d + 1) * s.d;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < P.ne * nvd;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = idx / nvd;
+    const int m = (int)(idx % nvd);
+    const double* E = F.Eo + (size_t)e * s.nb * nvd + m;
+    double acc = 0.0;
+    for (int i = 0; i < s.nb; ++i) acc += E[(size_t)i * nvd] * r[e * s.nb + i];
+    eto[idx] = acc;
+  }
+}
+
+// b[v][c] += sum over the elements at lattice vertex v of eto[e][vl*d + c]
+// (free vertices only; fixed order).
+__global__ void k_full_edt_vertex(int d, int64_t nvert, const int32_t* __restrict__ vert_elem_off,
+                                  const int32_t* __restrict__ vert_elem, const int32_t* __restrict__ elem_verts,
+                                  const int32_t* __restrict__ vfree_of_lat, const double* __restrict__ eto,
+                                  double* __restrict__ b) {
+  const int nv = d + 1, nvd = nv * d;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < nvert * d;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = idx / d;
+    const int c = (int)(idx % d);
+    if (vfree_of_lat[v] < 0) continue;
+    double acc = 0.0;
+    for (int p = vert_elem_off[v]; p < vert_elem_off[v + 1]; ++p) {
+      const int64_t e = vert_elem[p];
+      for (int vl = 0; vl < nv; ++vl)
+        if (elem_verts[e * nv + vl] == v) acc += eto[e * nvd + vl * d + c];
+    }
+    b[idx] += acc;
+  }
+}
+
+// E, bubble rows: x_o,e[i] += sum_{vl,c} Eo[e][i][vl*d + c] x0[v][c].
+__global__ void k_full_ed(SolveParams P, FullDev F, const int32_t* __restrict__ elem_verts,
+                          const int32_t* __restrict__ vfree_of_lat, const double* __restrict__ x0,
+                          double* __restrict__ x) {
+  const Sizes s = P.s;
+  const int d = s.d, nv = d + 1, nvd = nv * d;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < P.ne * s.nb;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = idx / s.nb;
+    const double* E = F.Eo + (size_t)idx * nvd;
+    double acc = 0.0;
+    for (int vl = 0; vl < nv; ++vl) {
+      const int64_t v = elem_verts[e * nv + vl];
+      if (vfree_of_lat[v] < 0) continue;
+      for (int c = 0; c < d; ++c) acc += E[vl * d + c] * x0[v * d + c];
+    }
+    x[idx] += acc;
+  }
+}
+
+// y_T += W_T x0_T after the coarse correction (W_T = A_T E_T).
+__global__ void k_full_ycorr(SolveParams P, FullDev F, const int32_t* __restrict__ elem_verts,
+                             const int32_t* __restrict__ vfree_of_lat, const double* __restrict__ x0,
+                             double* __restrict__ y) {
+  const Sizes s = P.s;
+  const int d = s.d, nv = d + 1, nvd = nv * d, nA = s.nA;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < P.ne * nA;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = idx / nA;
+    const int t = (int)(idx % nA);
+    const double* We = F.W + (size_t)e * nvd * nA + t;
+    double acc = 0.0;
+    for (int vl = 0; vl < nv; ++vl) {
+      const int64_t v = elem_verts[e * nv + vl];
+      if (vfree_of_lat[v] < 0) continue;
+      for (int c = 0; c < d; ++c) acc += We[(size_t)(vl * d + c) * nA] * x0[v * d + c];
+    }
+    y[idx] += acc;
+  }
+}
+
 static int grid_for(int64_t n, int per = 256) {
   int64_t g = (n + per - 1) / per;
   if (g > 65535 * 8) g = 65535 * 8;
   if (g < 1) g = 1;
   return (int)g;
+}
+
+void launch_full_smooth(hipStream_t st, const SolveParams& P, const FullDev& F, int c0, int c1, double* x,
+                        const double* sv, double* y) {
+  if (c1 <= c0) return;
+  hipLaunchKernelGGL(k_full_smooth, dim3((unsigned)std::min(c1 - c0, 1 << 20)), dim3(256), 0, st, P, F, c0, c1, x, sv, y);
+}
+void launch_full_resid(hipStream_t st, const SolveParams& P, const double* sv, const double* y, double* r) {
+  hipLaunchKernelGGL(k_full_resid, dim3(grid_for(P.off_p)), dim3(256), 0, st, P, P.s.nA, sv, y, r);
+}
+void launch_full_edt(hipStream_t st, const SolveParams& P, const FullDev& F, const double* r, double* eto,
+                     int64_t nvert, const int32_t* vert_elem_off, const int32_t* vert_elem, const int32_t* elem_verts,
+                     const int32_t* vfree_of_lat, double* b) {
+  const int d = P.s.d;
+  hipLaunchKernelGGL(k_full_edt, dim3(grid_for(P.ne * (d + 1) * d)), dim3(256), 0, st, P, F, r, eto);
+  hipLaunchKernelGGL(k_full_edt_vertex, dim3(grid_for(nvert * d)), dim3(256), 0, st, d, nvert, vert_elem_off, vert_elem,
+                     elem_verts, vfree_of_lat, eto, b);
+}
+void launch_full_ed(hipStream_t st, const SolveParams& P, const FullDev& F, const int32_t* elem_verts,
+                    const int32_t* vfree_of_lat, const double* x0, double* x, double* y) {
+  hipLaunchKernelGGL(k_full_ed, dim3(grid_for(P.ne * P.s.nb)), dim3(256), 0, st, P, F, elem_verts, vfree_of_lat, x0, x);
+  hipLaunchKernelGGL(k_full_ycorr, dim3(grid_for(P.ne * P.s.nA)), dim3(256), 0, st, P, F, elem_verts, vfree_of_lat, x0,
+                     y);
 }
 static int elem_grid(int64_t ne) { return (int)std::min<int64_t>(ne, 1 << 20); }
 

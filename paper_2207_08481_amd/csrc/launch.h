@@ -60,6 +60,17 @@ void launch_gather_compact(hipStream_t st, int64_t nfv, int d, const int32_t* f2
 // setup (kernels_setup.hip)
 void launch_condense(hipStream_t st, const CondParams& P, int nslots);
 void launch_stress(hipStream_t st, const StressParams& S, int nslots);
+void launch_full_smooth(hipStream_t st, const SolveParams& P, const FullDev& F, int c0, int c1, double* x,
+                        const double* sv, double* y);
+void launch_full_resid(hipStream_t st, const SolveParams& P, const double* sv, const double* y, double* r);
+void launch_full_edt(hipStream_t st, const SolveParams& P, const FullDev& F, const double* r, double* eto,
+                     int64_t nvert, const int32_t* vert_elem_off, const int32_t* vert_elem, const int32_t* elem_verts,
+                     const int32_t* vfree_of_lat, double* b);
+// x_o += E_o x0 (bubble rows of the embedding) and y += W x0
+void launch_full_ed(hipStream_t st, const SolveParams& P, const FullDev& F, const int32_t* elem_verts,
+                    const int32_t* vfree_of_lat, const double* x0, double* x, double* y);
+void launch_full_setup(hipStream_t st, const Sizes& s, int64_t ne, const FullDev& F, const int32_t* elem_verts,
+                       const double* coords, const int32_t* elem_ff, const double* EF, int* status);
 void launch_facet_setup(hipStream_t st, const FacetSetupParams& P);
 void launch_wsetup(hipStream_t st, const FacetSetupParams& P, const int32_t* elem_ff, int64_t ne, double* W, float* W32);
 void launch_p1_assemble(hipStream_t st, const P1Params& P);

@@ -66,6 +66,7 @@ struct RefTables {
   std::vector<double> pmom;  // [np]                int_T^ lambda^gamma / |T^|
   std::vector<double> phi;   // [nu][nv + 3]        BDM function i: alpha (nv), reference vector w (3)
   std::vector<double> pidx;  // [np][nv]            pressure multi-indices gamma
+  std::vector<double> Eo;    // [nv][d][nb]         bubble coefficients of lambda_v e_r
   std::vector<double> psi;   // [ns][ns]            psi_a = sum_j psi[a][j] lambda^{beta_j}
   std::vector<double> psib;  // [ns][nv]            degree-k multi-indices beta_j
   double facet_measure[4];   // |F^_f|
@@ -143,6 +144,11 @@ struct DevPtrs {
   double* red;            // reduction partials
   double* scal;           // scalar block (256 doubles)
   unsigned long long* wcount;  // smoother work counters (measurement)
+  // full-system variant (smoother 2)
+  int32_t *blk_el, *blk_slot, *blk_g, *colour_blocks;
+  double *Afull, *Binv, *Wfull, *Eo, *Eoref;
+  double* yfull;          // [ne][nA] maintained products A_T x_T
+  double* eto;            // [ne][(d+1)d] bubble part of E^T r
   double* vec;            // MINRES / preconditioner work vectors (FP64), nvec64 * ndof
   float* vec32;           // FP32 work vectors, nvec32 * ndof
   double* p1;             // P1 work vectors (FP64) 4 * np1
@@ -164,6 +170,12 @@ struct mcs_problem {
       h_facet_slot, h_facet_vfree, h_vinc_off, h_vinc, h_vert_elem_off, h_vert_elem,
       h_vfree_of_lat, h_free_to_lat;
   std::vector<double> h_coords;
+  // full-system variant: one overlapping block per facet of the mesh in
+  // canonical facet order, coloured so that facets of one element differ
+  int64_t nblk = 0;
+  int ncol_full = 0;
+  std::vector<int32_t> h_blk_el, h_blk_slot, h_blk_g, h_blk_colour, colour_off_full, h_colour_blocks;
+  std::vector<double> full_colour_bytes;  // algorithmic bytes of one colour phase (FP64)
   mcs::RefTables ref;
   std::vector<mcs::MGLevel> mg;         // fine .. coarsest over all member problems
   int64_t nc;                            // coarsest free dofs, summed over problems
@@ -199,6 +211,8 @@ struct mcs_problem {
   double tune_us[2] = {0.0, 0.0};
   // kernel timer: [0] smoother phase launches, [1] K apply launches
   bool timer_on = false;
+  int timer_period = 1;               // time one call in timer_period
+  int64_t t_tick[2] = {0, 0};         // calls seen per kernel kind
   std::vector<hipEvent_t> tev;        // pairs (start, stop)
   std::vector<int> tkind;             // timed kernel of each pending pair
   size_t tpending = 0;

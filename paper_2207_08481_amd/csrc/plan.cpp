@@ -138,11 +138,19 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
     set_error("precision must be 0 or 1");
     return MCS_ERR_ARG;
   }
-  if (pb->opt.smoother != 0 && pb->opt.smoother != 1) {
-    set_error("smoother must be 0 (multiplicative, block Gauss-Seidel) or 1 (additive, facet block Jacobi)");
+  if (pb->opt.smoother < 0 || pb->opt.smoother > 2) {
+    set_error("smoother must be 0 (multiplicative, block Gauss-Seidel), 1 (additive, facet block Jacobi) or 2 "
+              "(full system, overlapping block Gauss-Seidel)");
     return MCS_ERR_ARG;
   }
   pb->sz = make_sizes(d, k);
+  if (pb->opt.smoother == 2) {
+    const int nbk = pb->sz.nfb + 2 * pb->sz.nb;
+    if (pb->opt.precision != 0 || nbk > 64) {
+      set_error("the full-system variant needs precision 0 and blocks of at most 64 dofs (n_fb + 2 n_b = %d)", nbk);
+      return MCS_ERR_UNSUPPORTED;
+    }
+  }
   const Sizes& s = pb->sz;
   const int nv = d + 1;
   const int64_t ne = mesh->n_elements, nvert = mesh->n_vertices;
@@ -226,7 +234,13 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
     }
     if (j - i == 1) {
       for (int c = 0; c < d; ++c) vbound[fl[i].v[c]] = 1;
+      pb->h_blk_el.insert(pb->h_blk_el.end(), {fl[i].e, -1});
+      pb->h_blk_slot.insert(pb->h_blk_slot.end(), {(int32_t)fl[i].slot, -1});
+      pb->h_blk_g.push_back(-1);
     } else {
+      pb->h_blk_el.insert(pb->h_blk_el.end(), {fl[i].e, fl[i + 1].e});
+      pb->h_blk_slot.insert(pb->h_blk_slot.end(), {(int32_t)fl[i].slot, (int32_t)fl[i + 1].slot});
+      pb->h_blk_g.push_back((int32_t)free_fv.size());
       int32_t g = (int32_t)free_fv.size();
       free_fv.push_back(fl[i].v);
       pb->h_facet_el.push_back(fl[i].e);
@@ -266,6 +280,54 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
   {
     std::vector<int32_t> pos(pb->colour_off.begin(), pb->colour_off.end() - 1);
     for (int64_t g = 0; g < nff; ++g) pb->h_colour_facets[pos[pb->h_colour[g]]++] = (int32_t)g;
+  }
+
+  // ---- blocks of the full-system variant: greedy colouring of all facets in
+  // canonical order, the smallest colour not used by a facet of a neighbour
+  pb->nblk = (int64_t)pb->h_blk_g.size();
+  {
+    const int64_t nblk = pb->nblk;
+    std::vector<int32_t> elem_blk(ne * nv, -1);
+    for (int64_t b = 0; b < nblk; ++b)
+      for (int side = 0; side < 2; ++side)
+        if (pb->h_blk_el[2 * b + side] >= 0) elem_blk[pb->h_blk_el[2 * b + side] * nv + pb->h_blk_slot[2 * b + side]] = (int32_t)b;
+    pb->h_blk_colour.assign(nblk, -1);
+    int nc = 0;
+    for (int64_t b = 0; b < nblk; ++b) {
+      uint32_t used = 0;
+      for (int side = 0; side < 2; ++side) {
+        const int64_t e = pb->h_blk_el[2 * b + side];
+        if (e < 0) continue;
+        for (int i = 0; i < nv; ++i) {
+          const int32_t b2 = elem_blk[e * nv + i];
+          if (b2 != b && pb->h_blk_colour[b2] >= 0) used |= 1u << pb->h_blk_colour[b2];
+        }
+      }
+      int c = 0;
+      while (used & (1u << c)) ++c;
+      pb->h_blk_colour[b] = c;
+      nc = std::max(nc, c + 1);
+    }
+    pb->ncol_full = nc;
+    pb->colour_off_full.assign(nc + 1, 0);
+    for (int64_t b = 0; b < nblk; ++b) pb->colour_off_full[pb->h_blk_colour[b] + 1]++;
+    for (int c = 0; c < nc; ++c) pb->colour_off_full[c + 1] += pb->colour_off_full[c];
+    pb->h_colour_blocks.resize(nblk);
+    std::vector<int32_t> pos(pb->colour_off_full.begin(), pb->colour_off_full.end() - 1);
+    for (int64_t b = 0; b < nblk; ++b) pb->h_colour_blocks[pos[pb->h_blk_colour[b]]++] = (int32_t)b;
+    // algorithmic bytes of a colour phase: per block its inverse (m^2), the
+    // columns of A_T of both neighbours for its dofs in that element
+    // ((n_F-dofs + n_b) x n_A each), the gathered products and the updated x
+    const Sizes& z = pb->sz;
+    pb->full_colour_bytes.assign(nc, 0.0);
+    for (int64_t b = 0; b < nblk; ++b) {
+      const int nf = pb->h_blk_g[b] >= 0 ? z.nfb : 0;
+      const int nside = pb->h_blk_el[2 * b + 1] >= 0 ? 2 : 1;
+      const int m = nf + nside * z.nb;
+      const double words = (double)m * m + (double)nside * (nf + z.nb) * z.nA + 2.0 * nside * (nf + z.nb) + 3.0 * m +
+                           2.0 * nside * z.nA;
+      pb->full_colour_bytes[pb->h_blk_colour[b]] += 8.0 * words + 4.0 * 5;
+    }
   }
 
   // ---- free vertices (P1 auxiliary space)
@@ -588,6 +650,20 @@ int layout_workspace(mcs_problem* pb) {
   L.add("red", Dd(pb->nred));
   L.add("scal", Dd(256));
   L.add("wcount", 2 * 256 * 16 * 8);
+  if (pb->opt.smoother == 2) {
+    const int64_t nbk = s.nfb + 2 * s.nb, nvd = (int64_t)(d + 1) * d;
+    L.add("blk_el", I(pb->nblk * 2));
+    L.add("blk_slot", I(pb->nblk * 2));
+    L.add("blk_g", I(pb->nblk));
+    L.add("colour_blocks", I(pb->nblk));
+    L.add("Afull", Dd(ne * s.nA * s.nA));
+    L.add("Binv", Dd(pb->nblk * nbk * nbk));
+    L.add("Wfull", Dd(ne * nvd * s.nA));
+    L.add("Eo", Dd(ne * s.nb * nvd));
+    L.add("Eoref", Dd(nvd * s.nb));
+    L.add("yfull", Dd(ne * s.nA));
+    L.add("eto", Dd(ne * nvd));
+  }
   // FP64 slots: the MINRES and K-hat vectors, then b, r, x, K x of the
   // refinement (the only ones the lean layout keeps)
   pb->vbase64 = pb->lean ? 15 : 0;

@@ -541,6 +541,45 @@ RefTables build_ref_tables(int d, int k) {
     for (int j = 0; j < nv; ++j) T.phi[(size_t)i * (nv + 3) + j] = phis[i].alpha[j];
     for (int r = 0; r < 3; ++r) T.phi[(size_t)i * (nv + 3) + nv + r] = phis[i].w[r];
   }
+  // bubble coefficients of lambda_v e_r (the P1 field of vertex v, component
+  // r, on the reference element) in the BDM basis: lambda_v = lambda_v
+  // (sum_j lambda_j)^(k-1) has the degree-k coefficients (k-1)!/(beta-e_v)!,
+  // and the d basis functions lambda^beta w_i of one monomial span R^d
+  T.Eo.assign((size_t)nv * d * s.nb, 0.0);
+  {
+    std::map<MI, std::vector<int>> by_alpha;
+    for (int i = 0; i < s.nu; ++i) by_alpha[phis[i].alpha].push_back(i);
+    for (auto& beta : multi_indices(nv, k)) {
+      const std::vector<int>& ids = by_alpha.at(beta);
+      if ((int)ids.size() != d) throw std::runtime_error("BDM monomial multiplicity");
+      for (int v = 0; v < nv; ++v) {
+        if (beta[v] == 0) continue;
+        double cf = fact(k - 1);
+        for (int j = 0; j < nv; ++j) cf /= fact(beta[j] - (j == v ? 1 : 0));
+        for (int r = 0; r < d; ++r) {
+          // solve sum_t c_t w_{ids[t]} = cf e_r (d x d, Gaussian elimination with pivoting)
+          double M[3][4];
+          for (int a = 0; a < d; ++a) {
+            for (int t = 0; t < d; ++t) M[a][t] = phis[ids[t]].w[a];
+            M[a][d] = a == r ? cf : 0.0;
+          }
+          for (int c = 0; c < d; ++c) {
+            int p = c;
+            for (int a = c + 1; a < d; ++a)
+              if (std::fabs(M[a][c]) > std::fabs(M[p][c])) p = a;
+            for (int t = 0; t <= d; ++t) std::swap(M[c][t], M[p][t]);
+            for (int a = 0; a < d; ++a) {
+              if (a == c) continue;
+              const double f = M[a][c] / M[c][c];
+              for (int t = c; t <= d; ++t) M[a][t] -= f * M[c][t];
+            }
+          }
+          for (int t = 0; t < d; ++t)
+            if (ids[t] < s.nb) T.Eo[((size_t)v * d + r) * s.nb + ids[t]] = M[t][d] / M[t][t];
+        }
+      }
+    }
+  }
   // psi_a in monomial form over the degree-k barycentric powers (the
   // Bernstein factors k!/beta! folded in), for point values of the stress
   T.psi.assign((size_t)s.ns * s.ns, 0.0);

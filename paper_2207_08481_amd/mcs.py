@@ -28,7 +28,7 @@ PC = {"KHAT": 0, "AEXT": 1, "ADELTA_MULT": 2, "SMOOTH_FWD": 3, "SMOOTH_BWD": 4, 
 # exported symbols of include/mcs.h
 SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
            "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_get_array",
-           "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_destroy",
+           "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_destroy",
            "mcs_status_string", "mcs_last_error",
            "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
            "mcs_batch_solve", "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable",
@@ -123,6 +123,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_eval_stress.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.mcs_get_array.argtypes = [vp, C.c_char_p, C.POINTER(vp), C.POINTER(i64)]
     lib.mcs_get_topology.argtypes = [vp, vp, vp]
+    lib.mcs_get_full_colouring.argtypes = [vp, C.POINTER(i64), vp]
     lib.mcs_timer_enable.argtypes = [vp, i32]
     lib.mcs_timer_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_get_launch_config.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i64), C.POINTER(C.c_double)]
@@ -154,7 +155,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_server_destroy.restype = None
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
                  "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_get_array",
-                 "mcs_get_topology", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_batch_plan",
+                 "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
                  "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable", "mcs_batch_timer_read",
                  "mcs_server_create",
@@ -331,13 +332,22 @@ class Problem:
             typestr = "<f8"
         return torch.as_tensor(_CudaArray(p.value, n.value, typestr), device=self.device)
 
+    def full_colouring(self):
+        """Colour of every block of the full-system variant (canonical facet order)."""
+        n = C.c_int64()
+        _check(self._lib.mcs_get_full_colouring(self._h, C.byref(n), None))
+        col = np.zeros(n.value, dtype=np.int32)
+        _check(self._lib.mcs_get_full_colouring(self._h, C.byref(n), col.ctypes.data))
+        return col
+
     def launch_config(self, dt=F64):
         f, c, us = C.c_int32(), C.c_int64(), C.c_double()
         _check(self._lib.mcs_get_launch_config(self._h, dt, C.byref(f), C.byref(c), C.byref(us)))
         return {"facets_per_block": f.value, "grid_cap": c.value, "us_per_launch": us.value}
 
-    def timer_enable(self, on=True):
-        _check(self._lib.mcs_timer_enable(self._h, 1 if on else 0))
+    def timer_enable(self, on=True, period=1):
+        """Kernel timer on (one call in `period` is timed) or off."""
+        _check(self._lib.mcs_timer_enable(self._h, int(period) if on else 0))
 
     def timer_read(self, kernel="smooth"):
         """(total kernel ms, launches, algorithmic bytes) of the timed launches of

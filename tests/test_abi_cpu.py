@@ -115,6 +115,40 @@ def test_error_codes():
     with pytest.raises(MCSError) as ex:
         Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, precision=3)
     assert ex.value.status == -1
+    # smoother options: 0..2; the full-system variant needs precision 0 and
+    # blocks of at most 64 dofs (3D: k <= 3)
+    with pytest.raises(MCSError) as ex:
+        Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, smoother=3)
+    assert ex.value.status == -1
+    with pytest.raises(MCSError) as ex:
+        Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, precision=1, smoother=2)
+    assert ex.value.status == -10
+    with pytest.raises(MCSError) as ex:
+        Problem(mesh.vertices, mesh.elements, mesh.lattice, 4, smoother=2)
+    assert ex.value.status == -10
+    Problem(mesh.vertices, mesh.elements, mesh.lattice, 3, smoother=2).close()
+
+
+def test_full_system_blocks_and_colouring():
+    """The planner's blocks of the full-system variant: one per facet of the
+    mesh (Dirichlet facets included), coloured greedily in canonical facet
+    order exactly as the oracle colours them."""
+    from paper_2207_08481_amd.mcs import Problem
+    from oracle.topology import Topology
+    for mesh in (W.unit_square_mesh(3), W.unit_cube_mesh(2)):
+        pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, smoother=2)
+        topo = Topology(mesh.vertices, mesh.elements)
+        # greedy colouring of all facets (oracle rule, restated here on the topology)
+        colour = -np.ones(topo.n_facets, dtype=int)
+        for f in range(topo.n_facets):
+            used = {colour[f2] for (t, _i) in topo.facet_neighbors[f] for f2 in topo.elem_facets[t]
+                    if f2 != f and colour[f2] >= 0}
+            c = 0
+            while c in used:
+                c += 1
+            colour[f] = c
+        assert np.array_equal(pb.full_colouring(), colour)
+        pb.close()
 
 
 @needs_lib

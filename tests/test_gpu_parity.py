@@ -531,3 +531,40 @@ def test_stress_recovery_conforming_closed_form(k):
                     np.abs(om[e] - _kappa(curl, 3)).max() / sc)
     print(f"[stress closed form] k={k} interior elements {len(interior)} worst rel {worst:.2e}", flush=True)
     assert worst <= 1e-10
+
+
+@pytest.mark.parametrize("d,n,k,cm", [(2, 4, 2, 20), (3, 2, 2, 512), (3, 2, 3, 512)])
+def test_full_system_variant_parity(d, n, k, cm):
+    """smoother = 2 (full-system auxiliary-space preconditioner: overlapping
+    facet blocks on A swept around the coarse correction with the full
+    embedding) against the oracle's full variant: A-hat^{-1} (through
+    MCS_PC_AEXT), K-hat^{-1}, and the MINRES iteration count (+-1) and
+    solution of a solve."""
+    _need_gpu()
+    from paper_2207_08481_amd import Problem
+    from oracle.precond import Preconditioner
+    from oracle.minres import minres
+    c = setup_case(d, n, k, coarse_max=cm)
+    gs, m = c["gs"], c["mesh"]
+    pc = Preconditioner(gs, m.lattice, coarse_max=cm, variant="full")
+    pb = Problem(m.vertices, m.elements, m.lattice, k, coarse_max=cm, smoother=2, tol=1e-10).bind("cuda:0")
+    pb.condense(torch.as_tensor(c["nu"], device="cuda:0"))
+    assert np.array_equal(pb.full_colouring(), pc.full_colour)
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal(gs.n_dof)
+    rt = torch.as_tensor(r, device="cuda:0")
+    ru = r.copy()
+    ru[gs.off_p:] = 0
+    z = pb.precond_apply("AEXT", rt).cpu().numpy()
+    assert _rel(z[:gs.off_p], pc.A_full_inv(ru)[:gs.off_p]) < 1e-11
+    z = pb.precond_apply("KHAT", rt).cpu().numpy()
+    assert _rel(z, pc.apply(r.copy())) < 1e-11
+    K = c["K"]
+    xo, info = minres(lambda v: K @ v, pc.apply, gs.assemble_rhs(), tol=1e-10, max_it=3000)
+    xo = gs.normalize_pressure(xo)
+    x, si = pb.solve(torch.as_tensor(c["f"], device="cuda:0"))
+    assert si["status"] == 0
+    its, ito = si["iterations"], info["iterations"]
+    assert abs(its - ito) <= max(1, 0.02 * ito), (its, ito)
+    assert _rel(x.cpu().numpy(), xo) < 1e-8
+    pb.close()
