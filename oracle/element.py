@@ -234,7 +234,7 @@ def lattice_bernstein(d, m, lattice_sorted):
 
 
 def element_system(X, nu, k, f_lattice_sorted=None, lattice_sorted=None, m=None,
-                   keep_blocks=False):
+                   keep_blocks=False, pinned=()):
     """All element quantities of the hybridised MCS method on one element.
 
     Returns a dict with
@@ -244,6 +244,11 @@ def element_system(X, nu, k, f_lattice_sorted=None, lattice_sorted=None, m=None,
       'Adiv', 'Mp', 'F' (load, n_u), and the condensation-II blocks in the
       reordered local order [bubbles | facet blocks (normal, tangential)]:
       'perm', 'Aoo', 'Aod', 'H', 'Ad'.
+
+    pinned: local indices of A (original order) whose values are fixed to
+    zero (tangential dofs on an outlet facet); their rows and columns of A are
+    replaced by those of the identity, so that they decouple before the
+    bubbles are condensed.
     """
     ed = X if isinstance(X, ElementData) else element_geometry(X, k)
     d, nv = ed.d, ed.d + 1
@@ -314,6 +319,10 @@ def element_system(X, nu, k, f_lattice_sorted=None, lattice_sorted=None, m=None,
     Adiv_ext[:n_u, :n_u] = Adiv
     A = Adiv_ext - Bfull @ np.linalg.solve(M, Bfull.T)
     A = 0.5 * (A + A.T)
+    for p in pinned:
+        A[p, :] = 0.0
+        A[:, p] = 0.0
+        A[p, p] = 1.0
 
     F = None
     if f_lattice_sorted is not None:

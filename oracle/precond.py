@@ -83,10 +83,19 @@ def interp_1d(n):
     return P
 
 
+def kept_indices(n, lo_free, hi_free):
+    """Lattice indices 0..n of one axis that carry P1 dofs: the interior ones,
+    plus an end whose face is an outlet (not Dirichlet)."""
+    return ([0] if lo_free else []) + list(range(1, n)) + ([n] if hi_free else [])
+
+
 class P1Multigrid:
-    def __init__(self, Abar, lattice, d, coarse_max=512):
-        """Abar over free lattice vertices (interior), dof = d*free_vertex + c."""
+    def __init__(self, Abar, lattice, d, coarse_max=512, face_bc=None):
+        """Abar over the free lattice vertices, dof = d*free_vertex + c: the
+        interior ones, plus those on outlet faces (face_bc[2a + side] == 1)
+        that lie on no Dirichlet face."""
         self.d = d
+        fb = np.zeros(2 * d, dtype=int) if face_bc is None else np.asarray(face_bc)
         self.levels = []
         dims = [n - 1 for n in lattice]          # intervals per axis
         A = Abar.tocsr()
@@ -98,8 +107,12 @@ class P1Multigrid:
                 lvl["chol"] = sla.cho_factor(A.toarray())
                 break
             lvl["Dinv"] = self._l1_block_inverse(A)
-            # prolongation restricted to interior points, tensor product (x fastest)
-            Ps = [interp_1d(n)[1:-1, 1:-1] for n in dims]
+            # prolongation restricted to the free points, tensor product (x fastest)
+            Ps = []
+            for a, n in enumerate(dims):
+                nc = len(coarse_points(n)) - 1
+                Ps.append(interp_1d(n)[np.ix_(kept_indices(n, fb[2 * a], fb[2 * a + 1]),
+                                              kept_indices(nc, fb[2 * a], fb[2 * a + 1]))])
             P = sp.csr_matrix(Ps[0])
             for Pa in Ps[1:]:
                 P = sp.kron(sp.csr_matrix(Pa), P, format="csr")
@@ -208,6 +221,8 @@ def embedding(gs, full=False):
                     base = gs.off_f + g * gs.nfb
                     for q in range(nF):
                         rows.append(base + q); cols.append(col); vals.append(cu[nb + i * nF + q])
+                    if topo.free_outlet[g]:
+                        continue                # pi_0: no tangential rows on outlets
                     for q in range(nh):
                         rows.append(base + nF + q); cols.append(col); vals.append(ch[i][q])
         for i in range(d + 1):
@@ -220,12 +235,38 @@ def embedding(gs, full=False):
     return E
 
 
+# Tangential penalty of A-bar on outlet facets (Lemma outflow): nu C k^2 / h with
+# h = d |T| / |F| the height of the element over the facet.
+OUTLET_PENALTY = 8.0
+
+
+def p1_outlet_penalty(ed, nu, k, i):
+    """nu C k^2/h int_F (lambda_v e_c)_t . (lambda_w e_e)_t over local facet i,
+    as a ((d+1)d)^2 element block (zero outside the facet's vertices)."""
+    d = ed.d
+    n = ed.normals_out[i]
+    Pt = np.eye(d) - np.outer(n, n)
+    h = d * ed.vol / ed.areas[i]
+    cf = nu * OUTLET_PENALTY * k * k / h
+    A = np.zeros(((d + 1) * d, (d + 1) * d))
+    for v in range(d + 1):
+        for w in range(d + 1):
+            if v == i or w == i:
+                continue
+            mass = ed.areas[i] * (2.0 if v == w else 1.0) / (d * (d + 1))
+            A[v * d:(v + 1) * d, w * d:(w + 1) * d] = cf * mass * Pt
+    return A
+
+
 def assemble_p1(gs):
     topo = gs.topo
     d = gs.d
     rows, cols, vals = [], [], []
     for e in range(gs.n_e):
         Ae = p1_element_matrix(gs.elems[e]["ed"], gs.nu[e])
+        for i in range(d + 1):
+            if topo.facet_outlet[topo.elem_facets[e, i]]:
+                Ae = Ae + p1_outlet_penalty(gs.elems[e]["ed"], gs.nu[e], gs.k, i)
         idx = []
         for v in topo.elements[e]:
             fv = topo.free_vertex_of[v]
@@ -273,7 +314,7 @@ class Preconditioner:
         # auxiliary space
         self.E = embedding(gs, full=False)
         self.Abar = assemble_p1(gs)
-        self.mg = P1Multigrid(self.Abar, lattice, d, coarse_max=coarse_max)
+        self.mg = P1Multigrid(self.Abar, lattice, d, coarse_max=coarse_max, face_bc=topo.face_bc)
         # element-local pressure mass inverses
         self.Mp_inv = [np.linalg.inv(es["Mp"]) for es in gs.elems]
         if variant == "full":

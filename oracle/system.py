@@ -11,7 +11,14 @@ K = [[A, B^T], [B, 0]] with A the sigma/omega-condensed velocity block
 (Sec. 4.2) and B the pressure coupling -(div u, q) (weak-form sign of eq.
 discrmixedstressstokesweak).  The pressure is unique up to a constant when all
 of the boundary is Dirichlet (Sec. 1); the direct solve fixes int p = 0 with a
-Lagrange multiplier.
+Lagrange multiplier.  With an outlet Gamma_NT (eq. stokes_NT) it is unique.
+
+Boundary conditions (eq. stokes_D, stokes_NT): faces of the bounding box are
+Dirichlet (default) or outlets.  On an outlet facet the normal dofs are free
+and the tangential dofs are fixed to zero (u_t = 0): they stay in the vector
+layout with identity rows in K.  Dirichlet data g (values on the element
+lattices, like f) is lifted: its facet dofs are the L2 projections of g.n_F
+onto the normal traces and of g_t onto V-hat(F), and b -= K x_D.
 """
 from __future__ import annotations
 
@@ -31,8 +38,8 @@ def _lattice_indices(d, m):
 
 
 class GlobalSystem:
-    def __init__(self, vertices, elements, nu, k, f_lattice=None, m=None):
-        self.topo = topo = Topology(vertices, elements)
+    def __init__(self, vertices, elements, nu, k, f_lattice=None, m=None, face_bc=None, g_lattice=None):
+        self.topo = topo = Topology(vertices, elements, face_bc)
         d = self.d = topo.dim
         self.k = k
         n_e = topo.elements.shape[0]
@@ -49,6 +56,8 @@ class GlobalSystem:
         lat = _lattice_indices(d, self.m)
 
         self.elems = []
+        self.xD = []
+        n_u, nh = dims["n_u"], dims["n_hat"]
         for e in range(n_e):
             X = topo.element_coords(e)
             ed = element_geometry(X, k)
@@ -56,8 +65,45 @@ class GlobalSystem:
             if f_lattice is not None:
                 fl = np.asarray(f_lattice[e], dtype=np.float64)
                 ls = lat[:, topo.perm[e]]
-            es = element_system(ed, self.nu[e], k, fl, ls, self.m)
+            pinned = [n_u + i * nh + j for i in range(d + 1) if topo.facet_outlet[topo.elem_facets[e, i]]
+                      for j in range(nh)]
+            es = element_system(ed, self.nu[e], k, fl, ls, self.m, pinned=pinned)
             self.elems.append(es)
+            xd = np.zeros(n_u + (d + 1) * nh)
+            if g_lattice is not None:
+                for i in range(d + 1):
+                    if topo.facet_dirichlet[topo.elem_facets[e, i]]:
+                        self._lift_facet(ed, np.asarray(g_lattice[e], dtype=np.float64), lat[:, topo.perm[e]], i, xd)
+            self.xD.append(xd)
+
+    def _lift_facet(self, ed, g_lat, lat_sorted, i, xd):
+        """Dirichlet dofs of local facet i from g (values on the element
+        lattice): the normal dofs c with sum_beta c_beta lambda^beta/|F| =
+        L2 projection of g.n_F onto P^k(F), and the tangential dofs as the L2
+        projection of g_t onto V-hat(F)."""
+        from .element import lattice_bernstein
+        from .poly import facet_product_moments
+        d, k, m = self.d, self.k, self.m
+        nv = d + 1
+        gc = lattice_bernstein(d, m, lat_sorted) @ g_lat              # (|I_m|, d) over lambda^alpha
+        nF, nb = self.nF, self.nb
+        n_u = self.dims["n_u"]
+        area = ed.areas[i]
+        # normal part: rows beta of the facet functions of facet i (|beta| = k on the facet)
+        Gmk = facet_product_moments(nv, m, k, i) * area               # int_F lambda^alpha lambda^beta
+        Gkk = facet_product_moments(nv, k, k, i) * area
+        Ik = multi_indices(nv, k)
+        on = [j for j, a in enumerate(Ik) if a[i] == 0]                # facet monomials, lex-descending
+        rhs = (gc @ ed.normals_geo[i]) @ Gmk[:, on]
+        a = np.linalg.solve(Gkk[np.ix_(on, on)], rhs)
+        xd[nb + i * nF: nb + (i + 1) * nF] = area * a
+        # tangential part
+        Gmk1 = facet_product_moments(nv, m, k - 1, i) * area
+        Gk1 = facet_product_moments(nv, k - 1, k - 1, i) * area
+        V = ed.Vhat[i]                                                 # (n_hat, |I_{k-1}|, d)
+        Mf = np.einsum("jgr,gh,lhr->jl", V, Gk1, V)
+        rf = np.einsum("ar,ag,jgr->j", gc, Gmk1, V)
+        xd[n_u + i * self.nh: n_u + (i + 1) * self.nh] = np.linalg.solve(Mf, rf)
 
     # ------------------------------------------------------------------ maps
     def local_dofs(self, e):
@@ -116,11 +162,17 @@ class GlobalSystem:
         return self._scatter(blocks)
 
     def assemble_rhs(self):
+        """Load vector minus K x_D (the lifted Dirichlet data)."""
         b = np.zeros(self.n_dof)
         for e, es in enumerate(self.elems):
             ld = self.local_dofs(e)
+            perm = es["perm"]
             loc = np.zeros(len(ld))
             loc[self.u_to_reordered(e)] = es["F"]
+            xd = self.xD[e]
+            if np.any(xd):
+                loc -= (es["A"] @ xd)[perm]
+                b[self.pressure_dofs(e)] -= es["B"] @ xd[: self.dims["n_u"]]
             msk = ld >= 0
             np.add.at(b, ld[msk], loc[msk])
         return b
@@ -146,7 +198,10 @@ class GlobalSystem:
         return c
 
     def normalize_pressure(self, x):
-        """Subtract the mean of p_h (Sec. 1: p unique up to a constant)."""
+        """Subtract the mean of p_h (Sec. 1: p unique up to a constant); with
+        an outlet the pressure is unique and x is returned unchanged."""
+        if self.topo.has_outlet:
+            return x
         c = self.pressure_mean_functional()
         area = sum(es["ed"].vol for es in self.elems)
         mean = (c @ x) / area
@@ -156,6 +211,8 @@ class GlobalSystem:
         K = self.assemble_K()
         if b is None:
             b = self.assemble_rhs()
+        if self.topo.has_outlet:
+            return spla.splu(K.tocsc()).solve(b)
         c = self.pressure_mean_functional()
         Kc = sp.bmat([[K, sp.csr_matrix(c[:, None])], [sp.csr_matrix(c[None, :]), None]],
                      format="csc")
@@ -171,8 +228,8 @@ class GlobalSystem:
         es = self.elems[e]
         ed = es["ed"]
         ld = self.local_dofs(e)
-        coef = np.where(ld >= 0, x[np.maximum(ld, 0)], 0.0)
         perm = es["perm"]
+        coef = np.where(ld >= 0, x[np.maximum(ld, 0)], 0.0) + self.xD[e][perm]
         u_coef_reordered = coef
         orig = np.zeros(len(perm))
         orig[perm] = u_coef_reordered
@@ -190,7 +247,7 @@ class GlobalSystem:
         coef = np.where(ld >= 0, x[np.maximum(ld, 0)], 0.0)
         orig = np.zeros(len(ld))
         orig[self.elems[e]["perm"]] = coef
-        return orig
+        return orig + self.xD[e]
 
     def eval_stress_element(self, x, e, lam):
         """Values (sigma_h, omega_h) recovered in element e (eq. projection) at

@@ -7,9 +7,13 @@ numbering below is the solver's documented convention):
   is the facet opposite sorted local vertex i;
 * a facet is the sorted tuple of its global vertices; facets are ordered
   lexicographically by that tuple ("canonical order");
-* all of the boundary is Dirichlet (Gamma_D = boundary): boundary facets and
-  boundary vertices carry no free degrees of freedom;
-* free facets are the interior facets in canonical order;
+* boundary facets lie on the faces of the box the mesh fills; each face is
+  Dirichlet (Gamma_D, the default) or an outlet Gamma_NT (u_t = 0 and zero
+  normal stress, eq. stokes_NT); Dirichlet facets carry no free degrees of
+  freedom, outlet facets keep their normal dofs free (their tangential dofs
+  are fixed to zero);
+* free facets are the interior and the outlet facets in canonical order;
+* free vertices (P1 auxiliary space) are those on no Dirichlet facet;
 * facet colouring: greedy in canonical order, smallest colour not used by any
   already coloured free facet that shares an element (so facets of one colour
   never share an element and their smoother blocks are independent).
@@ -20,7 +24,9 @@ import numpy as np
 
 
 class Topology:
-    def __init__(self, vertices: np.ndarray, elements: np.ndarray):
+    def __init__(self, vertices: np.ndarray, elements: np.ndarray, face_bc=None):
+        """face_bc: per face of the bounding box (x-, x+, y-, y+[, z-, z+]) 0
+        for Dirichlet, 1 for an outlet Gamma_NT; default all Dirichlet."""
         self.vertices = np.asarray(vertices, dtype=np.float64)
         self.elements_in = np.asarray(elements, dtype=np.int64)
         self.dim = self.vertices.shape[1]
@@ -41,6 +47,23 @@ class Topology:
         nf = len(keys)
         self.n_facets = nf
         self.facet_boundary = np.array([len(nb) == 1 for nb in self.facet_neighbors])
+        # face of the bounding box that holds each boundary facet
+        lo, hi = self.vertices.min(axis=0), self.vertices.max(axis=0)
+        self.facet_face = -np.ones(nf, dtype=np.int64)
+        for f in np.nonzero(self.facet_boundary)[0]:
+            X = self.vertices[list(keys[f])]
+            for a in range(d):
+                if np.all(X[:, a] == lo[a]):
+                    self.facet_face[f] = 2 * a
+                elif np.all(X[:, a] == hi[a]):
+                    self.facet_face[f] = 2 * a + 1
+            assert self.facet_face[f] >= 0, "boundary facet off the bounding box"
+        bc = np.zeros(2 * d, dtype=np.int64) if face_bc is None else np.asarray(face_bc, dtype=np.int64)
+        assert bc.shape == (2 * d,) and set(bc.tolist()) <= {0, 1}
+        self.face_bc = bc
+        self.facet_outlet = np.array([self.facet_boundary[f] and bc[self.facet_face[f]] == 1 for f in range(nf)])
+        self.facet_dirichlet = self.facet_boundary & ~self.facet_outlet
+        self.has_outlet = bool(self.facet_outlet.any())
         fid = {k: n for n, k in enumerate(keys)}
         self.elem_facets = np.zeros((n_e, d + 1), dtype=np.int64)
         for t in range(n_e):
@@ -49,15 +72,16 @@ class Topology:
                 key = tuple(int(v) for j, v in enumerate(ev) if j != i)
                 self.elem_facets[t, i] = fid[key]
 
-        # free (interior) facets in canonical order
+        # free (interior and outlet) facets in canonical order
         self.free_facet_of = -np.ones(nf, dtype=np.int64)
-        free = np.nonzero(~self.facet_boundary)[0]
+        free = np.nonzero(~self.facet_dirichlet)[0]
         self.free_facet_of[free] = np.arange(len(free))
         self.free_facets = free
         self.n_free_facets = len(free)
 
         # boundary / free vertices
-        bverts = set(int(v) for k in np.asarray(keys)[self.facet_boundary] for v in k)
+        bverts = set(int(v) for k in np.asarray(keys)[self.facet_dirichlet] for v in k)
+        self.free_outlet = self.facet_outlet[free]          # per free facet
         nv = self.vertices.shape[0]
         self.vertex_boundary = np.zeros(nv, dtype=bool)
         self.vertex_boundary[list(bverts)] = True

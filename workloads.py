@@ -26,7 +26,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "Mesh", "unit_square_mesh", "unit_cube_mesh", "lattice_indices",
+    "Mesh", "unit_square_mesh", "unit_cube_mesh", "box_mesh", "PlaneChannel", "lattice_indices",
     "lattice_points", "Manufactured2D", "CurlModes3D", "RandomForce",
     "lognormal_nu", "workload",
 ]
@@ -97,6 +97,87 @@ def unit_cube_mesh(n: int) -> Mesh:
                         tet.append(vid(*c))
                     els.append(tuple(tet))
     return Mesh(3, verts, np.asarray(els, dtype=np.int32), (N, N, N))
+
+
+def box_mesh(cells, lengths) -> Mesh:
+    """Box [0, L_0] x ... split like unit_square_mesh / unit_cube_mesh, with
+    cells[a] intervals on axis a (vertex index: x fastest)."""
+    d = len(cells)
+    if d == 2:
+        m = unit_square_like(cells)
+    else:
+        m = unit_cube_like(cells)
+    m.vertices = m.vertices * np.asarray(lengths, dtype=np.float64)[None, :]
+    return m
+
+
+def unit_square_like(cells) -> Mesh:
+    nx, ny = cells
+    xs, ys = np.linspace(0.0, 1.0, nx + 1), np.linspace(0.0, 1.0, ny + 1)
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    verts = np.stack([X.ravel(), Y.ravel()], axis=1)
+    els = []
+    for j in range(ny):
+        for i in range(nx):
+            v00 = i + (nx + 1) * j
+            v10, v01 = v00 + 1, v00 + (nx + 1)
+            v11 = v01 + 1
+            els.append((v00, v10, v11))
+            els.append((v00, v11, v01))
+    return Mesh(2, verts, np.asarray(els, dtype=np.int32), (nx + 1, ny + 1))
+
+
+def unit_cube_like(cells) -> Mesh:
+    nx, ny, nz = cells
+    xs, ys, zs = (np.linspace(0.0, 1.0, n + 1) for n in cells)
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    verts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+    def vid(i, j, l):
+        return i + (nx + 1) * (j + (ny + 1) * l)
+
+    els = []
+    for l in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                for p in _PERMS3:
+                    c = [i, j, l]
+                    tet = [vid(*c)]
+                    for ax in p:
+                        c = list(c)
+                        c[ax] += 1
+                        tet.append(vid(*c))
+                    els.append(tuple(tet))
+    return Mesh(3, verts, np.asarray(els, dtype=np.int32), (nx + 1, ny + 1, nz + 1))
+
+
+@dataclass
+class PlaneChannel:
+    """Flow between the plates y = 0 and y = 1 of a box [0, L] x [0, 1] (x
+    [0, 1]): u = (4 y (1 - y), 0[, 0]), p = 4 nu (L - x), f = 0.  It solves
+    -div(nu eps(u)) + grad p = 0, div u = 0, with u = 0 on the plates, the
+    profile itself as Dirichlet data on the inlet x = 0 (and on z = 0, 1 in
+    3D), and on the outlet x = L: u_t = 0 and ((sigma + p I) n).n = p = 0."""
+    dim: int
+    nu: float = 1.0
+    L: float = 1.0
+
+    def u(self, X):
+        X = np.asarray(X, dtype=np.float64)
+        out = np.zeros(X.shape)
+        out[..., 0] = 4.0 * X[..., 1] * (1.0 - X[..., 1])
+        return out
+
+    def p(self, X):
+        X = np.asarray(X, dtype=np.float64)
+        return 4.0 * self.nu * (self.L - X[..., 0])
+
+    def f(self, X):
+        return np.zeros(np.asarray(X).shape)
+
+    def face_bc(self):
+        """x- inlet (Dirichlet), x+ outlet, all other faces Dirichlet."""
+        return [0, 1] + [0] * (2 * self.dim - 2)
 
 
 def lattice_indices(dim: int, m: int):
