@@ -113,6 +113,13 @@ typedef struct {
   int32_t n_elements;
   const int32_t* elements_host;  /* [n_elements * (dim+1)] */
   int32_t lattice[3];            /* vertices per axis (unused axes: 1) */
+  int32_t face_bc[6];            /* boundary condition of each face of the box the
+                                    lattice fills: [x-, x+, y-, y+, z-, z+];
+                                    0 = Dirichlet u = g (eq. stokes_D; g = 0 unless
+                                    set by mcs_set_dirichlet), 1 = outlet Gamma_NT:
+                                    u_t = 0 and ((sigma + p I) n).n = 0
+                                    (eq. stokes_NT).  All zero: the whole boundary
+                                    is Dirichlet and p is fixed by mean zero. */
 } mcs_mesh;
 
 typedef struct {
@@ -180,9 +187,22 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream);
  * (Cholesky breakdown of an element or facet block). */
 int mcs_condense(mcs_problem* pb, const double* nu);
 
-/* b = load vector (f, phi_u) in the global layout (zero on uhat and p), from
- * f_lattice (device).  b: device double[n_dof]. */
+/* b = load vector (f, phi_u) in the global layout, from f_lattice (device),
+ * minus K x_D for the Dirichlet data set by mcs_set_dirichlet (without it, b
+ * is zero on uhat and p).  b: device double[n_dof]. */
 int mcs_load(mcs_problem* pb, const double* f_lattice, double* b);
+
+/* Inhomogeneous Dirichlet data u = g on the Dirichlet faces (eq. stokes_D):
+ * g_lattice_host (host) holds g at the degree-m lattice points of every
+ * element ([n_elements][n_lat][dim], caller vertex order, the layout of f;
+ * only the points on Dirichlet facets are read).  On each Dirichlet facet F
+ * its dofs are the L2 projection of g.n_F onto the normal traces
+ * (mu^beta / |F|, |beta| = k) and of g_t onto V-hat(F); the solution is then
+ * the lift x_D plus the free dofs that mcs_solve returns (mcs_load subtracts
+ * K x_D; mcs_eval and mcs_eval_stress include x_D).  g_lattice_host = NULL
+ * returns to homogeneous data.  Needs a bound problem.  [sync]  Errors:
+ * MCS_ERR_ARG for non-finite data. */
+int mcs_set_dirichlet(mcs_problem* pb, const double* g_lattice_host);
 
 /* y = op x (see mcs_op); x, y: device vectors of length n_dof in dtype dt
  * (MCS_F32 uses the FP32 operator copies).  Asynchronous. */

@@ -287,6 +287,12 @@ int mcs_batch_plan(const mcs_mesh* meshes, const int32_t* orders, int32_t n, con
     set_error("batch plan: null argument or empty batch");
     return MCS_ERR_ARG;
   }
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 6; ++a)
+      if (meshes[i].face_bc[a] != 0) {
+        set_error("batch plan: member %d has an outlet face; batches take all-Dirichlet problems", i);
+        return MCS_ERR_UNSUPPORTED;
+      }
   if (options->smoother == 2) {
     set_error("batch plan: the full-system variant (smoother 2) is for single problems");
     return MCS_ERR_UNSUPPORTED;

@@ -227,6 +227,8 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   p.elem_perm = ws_ptr<int32_t>(pb, "elem_perm");
   p.facet_el = ws_ptr<int32_t>(pb, "facet_el");
   p.facet_slot = ws_ptr<int32_t>(pb, "facet_slot");
+  p.facet_out = ws_ptr<int32_t>(pb, "facet_out");
+  p.xD = ws_ptr<double>(pb, "xD");
   p.colour_facets = ws_ptr<int32_t>(pb, "colour_facets");
   p.facet_vfree = ws_ptr<int32_t>(pb, "facet_vfree");
   p.vinc_off = ws_ptr<int32_t>(pb, "vinc_off");
@@ -310,6 +312,7 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   HIPCHK(up(p.elem_perm, pb->h_elem_perm.data(), pb->h_elem_perm.size() * 4));
   HIPCHK(up(p.facet_el, pb->h_facet_el.data(), pb->h_facet_el.size() * 4));
   HIPCHK(up(p.facet_slot, pb->h_facet_slot.data(), pb->h_facet_slot.size() * 4));
+  HIPCHK(up(p.facet_out, pb->h_facet_out.data(), pb->h_facet_out.size() * 4));
   HIPCHK(up(p.colour_facets, pb->h_colour_facets.data(), pb->h_colour_facets.size() * 4));
   HIPCHK(up(p.facet_vfree, pb->h_facet_vfree.data(), pb->h_facet_vfree.size() * 4));
   HIPCHK(up(p.vinc_off, pb->h_vinc_off.data(), pb->h_vinc_off.size() * 4));
@@ -358,6 +361,7 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
         T.nc3[a] = B.nc3[a];
       }
       T.prob = B.prob;
+      T.ffm = B.ffm;
       T.voff = B.voff;
       T.nvert = B.nvert;
       T.cvoff = B.cvoff;
@@ -396,6 +400,8 @@ static CondParams cond_params(mcs_problem* pb, int* status) {
   C.scratch = p.cscratch;
   C.detJ = p.detJ;
   C.status = status;
+  C.elem_ff = p.elem_ff;
+  C.facet_out = pb->has_outlet ? p.facet_out : nullptr;
   return C;
 }
 
@@ -442,6 +448,7 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   F.Ad = p.Ad;
   F.Adh = p.Ad32;
   F.Adl = p.Adl;
+  F.facet_out = pb->has_outlet ? p.facet_out : nullptr;
   F.rcn = p.rcn;
   F.rct = p.rct;
   F.Dinv = p.Dinv;
@@ -471,6 +478,8 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   A.coords = p.coords;
   A.nu = p.nu;
   A.A = reinterpret_cast<double*>(base + pb->mg[0].off_A);
+  A.k = pb->sz.k;
+  A.penalty = OUTLET_PENALTY;
   launch_p1_assemble(st, A);
   const int64_t scratch_doubles = pb->n_slots * pb->slot_doubles;
   for (size_t l = 0; l < pb->mg.size(); ++l) {
@@ -542,7 +551,41 @@ int mcs_load(mcs_problem* pb, const double* f_lattice, double* b) {
   launch_fill<double>(st, pb->ndof, 0.0, b);
   launch_load(st, C, P, p.elem_perm, p.rlatmap, p.rRf, f_lattice, b, p.escr);
   launch_facet_sum<double>(st, P, p.escr, nullptr, 1.0, b);
+  if (pb->has_dirichlet) {
+    // lifted Dirichlet data: b -= K (0 + x_D)
+    Ctx<double> c(pb);
+    c.P.xD = p.xD;
+    double *z = c.v(VT64), *kz = c.v(VR64);
+    launch_fill<double>(st, pb->ndof, 0.0, z);
+    c.apply(z, kz, 1 | 2 | 4);
+    launch_axpby<double>(st, pb->ndof, -1.0, kz, 1.0, b);
+  }
   HIPCHK(hipGetLastError());
+  return MCS_OK;
+}
+
+int mcs_set_dirichlet(mcs_problem* pb, const double* g_lattice_host) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  if (!g_lattice_host) {
+    pb->has_dirichlet = false;
+    return MCS_OK;
+  }
+  std::vector<double> xd;
+  try {
+    dirichlet_lift(pb, g_lattice_host, xd);
+  } catch (const std::exception& ex) {
+    set_error("mcs_set_dirichlet: %s", ex.what());
+    return MCS_ERR_ARG;
+  }
+  for (double v : xd)
+    if (!std::isfinite(v)) {
+      set_error("mcs_set_dirichlet: non-finite boundary data");
+      return MCS_ERR_ARG;
+    }
+  HIPCHK(hipMemcpyAsync(pb->p.xD, xd.data(), xd.size() * 8, hipMemcpyHostToDevice, pb->stream));
+  HIPCHK(hipStreamSynchronize(pb->stream));
+  pb->has_dirichlet = true;
   return MCS_OK;
 }
 
@@ -666,6 +709,7 @@ int mcs_normalize_pressure(mcs_problem* pb, double* x) {
     set_error("mcs_normalize_pressure needs mcs_condense first");
     return MCS_ERR_STATE;
   }
+  if (pb->has_outlet) return MCS_OK;   // p is unique with an outlet
   SolveParams P = solve_params(pb);
   launch_pressure_mean(pb->stream, P, pb->p.rpmom, pb->p.rpconst, x, pb->p.red);
   HIPCHK(hipGetLastError());
@@ -772,7 +816,7 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
     inf.rel_residual = bn > 0 ? std::sqrt(rn / bn) : std::sqrt(rn);
   }
   SolveParams P = solve_params(pb);
-  launch_pressure_mean(st, P, pb->p.rpmom, pb->p.rpconst, x, pb->p.red);
+  if (!pb->has_outlet) launch_pressure_mean(st, P, pb->p.rpmom, pb->p.rpconst, x, pb->p.red);
   hipError_t he = hipStreamSynchronize(st);
   if (he != hipSuccess) {
     set_error("HIP error '%s' in solve", hipGetErrorString(he));
@@ -910,6 +954,7 @@ int mcs_eval(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_
   }
   HIPCHK(hipMemcpyAsync(pb->p.red, ref_pts_host, (size_t)n_pts * nv * 8, hipMemcpyHostToDevice, pb->stream));
   SolveParams P = solve_params(pb);
+  if (pb->has_dirichlet) P.xD = pb->p.xD;
   launch_eval(pb->stream, P, pb->p.coords, pb->p.elem_verts, pb->p.elem_perm, pb->p.rphi, pb->p.rpidx, n_pts,
               pb->p.red, x, u_vals, p_vals);
   HIPCHK(hipStreamSynchronize(pb->stream));
@@ -939,6 +984,7 @@ int mcs_eval_stress(mcs_problem* pb, const double* x, int32_t n_pts, const doubl
   S.elem_ff = pb->p.elem_ff;
   S.elem_perm = pb->p.elem_perm;
   S.off_f = pb->off_f;
+  S.xD = pb->has_dirichlet ? pb->p.xD : nullptr;
   S.rpsi = pb->p.rpsi;
   S.rpsib = pb->p.rpsib;
   S.npts = n_pts;

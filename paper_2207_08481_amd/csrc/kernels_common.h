@@ -7,6 +7,10 @@ namespace mcs {
 constexpr int MAXND = 256;   // max A^d size (k = 5, 3D: 204)
 constexpr int MAXNB = 96;    // max bubbles (84)
 constexpr int MAXNP = 40;    // max pressure dofs (35)
+// C of the tangential penalty nu C k^2 / h on outlet facets in A-bar (Lemma
+// outflow asks for C large enough; with 8 the excess of E^d^T A^d E^d over
+// A-bar stays below 1 % on the tested meshes, k = 2..4)
+constexpr double OUTLET_PENALTY = 8.0;
 constexpr int MAXNFB = 64;   // max facet block (51)
 
 struct CondParams {
@@ -28,6 +32,8 @@ struct CondParams {
   // A^d is formed in a per-slot FP64 buffer adtmp first.
   float *Adl, *Hl, *Aool;
   double* Afull;                 // optional: A_T itself (full-system variant)
+  const int32_t* elem_ff;        // element -> free facet id (-1: Dirichlet)
+  const int32_t* facet_out;      // free facet -> 1 for an outlet facet
   double* adtmp;
   int64_t adtmp_stride;
   int* status;
@@ -41,6 +47,7 @@ struct StressParams {
   const int32_t* elem_perm;
   int64_t off_f;
   const double *rpsi, *rpsib;    // psi_a in monomial form, multi-indices
+  const double* xD;              // Dirichlet dofs per element, or nullptr
   int npts;
   const double* pts;             // [npts][nv] barycentric, caller vertex order
   double *sig, *om;              // [ne][npts][d][d]
@@ -56,6 +63,7 @@ struct FacetSetupParams {
   const double* Ad;              // FP64 A^d, or nullptr: hi + lo in Adh, Adl
   const float *Adh, *Adl;
   const double *rcn, *rct;
+  const int32_t* facet_out;      // 1: outlet facet (pi_0: no tangential rows in E)
   double* Dinv;
   float* Dinv32;
   double* EF;
@@ -67,7 +75,7 @@ struct FacetSetupParams {
 struct MGBlockDev {
   int n[3];
   int nc3[3];
-  int prob, pad_;
+  int prob, ffm;                  // ffm: faces whose vertices carry P1 dofs (outlets)
   int64_t voff, nvert, cvoff, nvert_c, nc, cmap_off, cinv_off;
 };
 
@@ -79,6 +87,19 @@ __device__ inline int64_t uni64(int64_t v) {
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
+// A lattice vertex with coordinates c in a block of n intervals per axis carries
+// P1 dofs when on every axis it is interior or lies on an outlet face (bit 2a
+// of ffm: the face c_a = 0 is an outlet; bit 2a + 1: c_a = n_a); vertices on a
+// Dirichlet face carry none.
+__host__ __device__ inline bool lat_free(const int c[3], const int* n, int d, int ffm) {
+  for (int a = 0; a < d; ++a) {
+    if (c[a] < 0 || c[a] > n[a]) return false;
+    if (c[a] == 0 && !((ffm >> (2 * a)) & 1)) return false;
+    if (c[a] == n[a] && !((ffm >> (2 * a + 1)) & 1)) return false;
+  }
+  return true;
+}
+
 __device__ inline MGBlockDev load_block(const MGBlockDev* p) {
   MGBlockDev b = *p;
   for (int a = 0; a < 3; ++a) {
@@ -86,6 +107,7 @@ __device__ inline MGBlockDev load_block(const MGBlockDev* p) {
     b.nc3[a] = uni32(b.nc3[a]);
   }
   b.prob = uni32(b.prob);
+  b.ffm = uni32(b.ffm);
   b.voff = uni64(b.voff);
   b.nvert = uni64(b.nvert);
   b.cvoff = uni64(b.cvoff);
@@ -107,6 +129,8 @@ struct P1Params {
   const double* coords;
   const double* nu;
   double* A;
+  int k;                      // order (outlet penalty nu C k^2 / h)
+  double penalty;             // C
 };
 
 struct MGSetupParams {
@@ -143,6 +167,9 @@ struct SolveParams {
   // processes, spread over 256 counters 128 bytes apart (workgroup w adds to
   // counter w mod 256)
   unsigned long long* work_count;
+  // Dirichlet dofs per element ([ne][nd]): when set, gathers of facet values
+  // take them for the element's Dirichlet facets (lifting and point values)
+  const double* xD;
 };
 
 __device__ inline bool elem_off(const SolveParams& P, int64_t e) {

@@ -430,6 +430,22 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
           }
       }
     __syncthreads();
+    // tangential dofs of an outlet facet are fixed to zero: identity rows and
+    // columns, so that they decouple before the bubbles are condensed
+    if (P.facet_out) {
+      const int nv = d + 1;
+      auto pinned = [&](int r) {
+        if (r < s.nb) return false;
+        const int f = (r - s.nb) / s.nfb, q = (r - s.nb) % s.nfb;
+        const int gf = P.elem_ff[e * nv + f];
+        return q >= s.nF && gf >= 0 && P.facet_out[gf] != 0;
+      };
+      for (int idx = tid; idx < s.nA * s.nA; idx += blockDim.x) {
+        const int r = idx / s.nA, c = idx % s.nA;
+        if (pinned(r) || pinned(c)) A[idx] = r == c ? 1.0 : 0.0;
+      }
+      __syncthreads();
+    }
     if (P.Afull)
       for (int idx = tid; idx < s.nA * s.nA; idx += blockDim.x) P.Afull[(size_t)e * s.nA * s.nA + idx] = A[idx];
     // condensation II: Aoo = A[0:nb,0:nb]
@@ -547,6 +563,7 @@ __global__ void __launch_bounds__(256) k_facet_setup(FacetSetupParams P) {
       double t = 0.0;
       for (int side = 0; side < 2; ++side) {
         int64_t e = P.facet_el[2 * g + side];
+        if (e < 0) continue;   // outlet facet: one neighbour
         int sl = P.facet_slot[2 * g + side];
         const size_t ai = (size_t)e * nd * nd + (size_t)(sl * nfb + i) * nd + sl * nfb + j;
         t += P.Ad ? P.Ad[ai] : (double)P.Adh[ai] + (double)P.Adl[ai];
@@ -616,6 +633,8 @@ __global__ void __launch_bounds__(256) k_facet_setup(FacetSetupParams P) {
       double val;
       if (q < s.nF) {
         val = geo[3] * geo[c] * P.rcn[q * d + v];
+      } else if (P.facet_out && P.facet_out[g]) {
+        val = 0.0;   // pi_0 (Lemma outflow): the outlet's tangential dofs stay zero
       } else {
         int j = q - s.nF, b = j / s.nFkm1, gm = j % s.nFkm1;
         val = P.rct[gm * d + v] * geo[4 + 3 * b + c];
@@ -637,11 +656,6 @@ __device__ inline void lat_coords(int64_t v, const int* N, int c[3]) {
   c[2] = (int)(v / ((int64_t)N[0] * N[1]));
 }
 
-__device__ inline bool lat_interior(const int c[3], const int* n, int d) {
-  for (int a = 0; a < d; ++a)
-    if (c[a] <= 0 || c[a] >= n[a]) return false;
-  return true;
-}
 
 // A-bar stencil on the finest level: vertex-centric sum over incident elements
 // of nu_T int eps(lambda_v e_c) : eps(lambda_w e_e).
@@ -698,6 +712,61 @@ __global__ void k_p1_assemble(P1Params P) {
           for (int ee = 0; ee < d; ++ee)
             Av[o * dd + c * d + ee] += w * 0.5 * ((c == ee ? gg : 0.0) + gl[j][c] * gl[lv][ee]);
       }
+      // tangential penalty on the element's facets on outlet faces (Lemma
+      // outflow): nu_T C k^2 / h int_F (lambda_v e_c)_t . (lambda_w e_e)_t,
+      // h = d |T| / |F|
+      if (B.ffm)
+        for (int f = 0; f < nv; ++f) {
+          if (f == lv) continue;
+          bool on = false;
+          for (int a = 0; a < d && !on; ++a)
+            for (int side = 0; side < 2 && !on; ++side) {
+              if (!((B.ffm >> (2 * a + side)) & 1)) continue;
+              bool all = true;
+              for (int j = 0; j < nv; ++j) {
+                if (j == f) continue;
+                int cj[3];
+                lat_coords(P.elem_verts[e * nv + j] - B.voff, N, cj);
+                if (cj[a] != (side ? B.n[a] : 0)) all = false;
+              }
+              on = all;
+            }
+          if (!on) continue;
+          int fv[3], m = 0;
+          for (int j = 0; j < nv; ++j)
+            if (j != f) fv[m++] = j;
+          double t1[3], t2[3], nf[3];
+          for (int r = 0; r < 3; ++r) {
+            t1[r] = X[fv[1]][r] - X[fv[0]][r];
+            t2[r] = d == 3 ? X[fv[2]][r] - X[fv[0]][r] : 0.0;
+          }
+          double area;
+          if (d == 2) {
+            nf[0] = t1[1];
+            nf[1] = -t1[0];
+            nf[2] = 0.0;
+          } else {
+            nf[0] = t1[1] * t2[2] - t1[2] * t2[1];
+            nf[1] = t1[2] * t2[0] - t1[0] * t2[2];
+            nf[2] = t1[0] * t2[1] - t1[1] * t2[0];
+          }
+          const double nn = sqrt(nf[0] * nf[0] + nf[1] * nf[1] + nf[2] * nf[2]);
+          area = d == 2 ? nn : 0.5 * nn;
+          for (int r = 0; r < 3; ++r) nf[r] /= nn;
+          const double h = d * vol / area;
+          const double cf = P.nu[e] * P.penalty * P.k * P.k / h;
+          for (int j = 0; j < nv; ++j) {
+            if (j == f) continue;
+            int cw[3];
+            lat_coords(P.elem_verts[e * nv + j] - B.voff, N, cw);
+            int o = 0, pw = 1;
+            for (int a = 0; a < d; ++a) { o += (cw[a] - cv[a] + 1) * pw; pw *= 3; }
+            const double mass = area * (j == lv ? 2.0 : 1.0) / (d * (d + 1));
+            for (int c = 0; c < d; ++c)
+              for (int ee = 0; ee < d; ++ee)
+                Av[o * dd + c * d + ee] += cf * mass * ((c == ee ? 1.0 : 0.0) - nf[c] * nf[ee]);
+          }
+        }
     }
   }
 }
@@ -713,7 +782,7 @@ __global__ void k_mg_l1(MGSetupParams P) {
     int cv[3];
     lat_coords(lv_, N, cv);
     double Dm[3][3] = {};
-    if (lat_interior(cv, B.n, d)) {
+    if (lat_free(cv, B.n, d, B.ffm)) {
       const double* Av = P.A + (size_t)v * st * dd;
       int center = d == 3 ? 13 : 4;
       for (int c = 0; c < d; ++c)
@@ -722,7 +791,7 @@ __global__ void k_mg_l1(MGSetupParams P) {
         if (o == center) continue;
         int cw[3] = {cv[0] + o % 3 - 1, cv[1] + (o / 3) % 3 - 1, cv[2] + (o / 9) - 1};
         if (d == 2) cw[2] = 0;
-        if (!lat_interior(cw, B.n, d)) continue;
+        if (!lat_free(cw, B.n, d, B.ffm)) continue;
         for (int c = 0; c < d; ++c) {
           double sacc = 0.0;
           for (int e = 0; e < d; ++e) sacc += fabs(Av[o * dd + c * d + e]);
@@ -788,12 +857,12 @@ __global__ void __launch_bounds__(256) k_mg_rap(MGSetupParams P) {
     lat_coords(V, Nc, CI);
     int CJ[3] = {CI[0] + co % 3 - 1, CI[1] + (co / 3) % 3 - 1, CI[2] + co / 9 - 1};
     if (d == 2) CJ[2] = 0;
-    if (lat_interior(CI, B.nc3, d) && lat_interior(CJ, B.nc3, d)) {
+    if (lat_free(CI, B.nc3, d, B.ffm) && lat_free(CJ, B.nc3, d, B.ffm)) {
       int base[3] = {coarse_pos(CI[0], B.n[0]), coarse_pos(CI[1], B.n[1]), d == 3 ? coarse_pos(CI[2], B.n[2]) : 0};
       for (int fo = 0; fo < st; ++fo) {
         int fi[3] = {base[0] + fo % 3 - 1, base[1] + (fo / 3) % 3 - 1, base[2] + fo / 9 - 1};
         if (d == 2) fi[2] = 0;
-        if (!lat_interior(fi, B.n, d)) continue;
+        if (!lat_free(fi, B.n, d, B.ffm)) continue;
         double wI = 1.0;
         for (int a = 0; a < d; ++a) wI *= w1d(fi[a], CI[a], B.n[a]);
         if (wI == 0.0) continue;
@@ -802,7 +871,7 @@ __global__ void __launch_bounds__(256) k_mg_rap(MGSetupParams P) {
         for (int so = 0; so < st; ++so) {
           int fj[3] = {fi[0] + so % 3 - 1, fi[1] + (so / 3) % 3 - 1, fi[2] + so / 9 - 1};
           if (d == 2) fj[2] = 0;
-          if (!lat_interior(fj, B.n, d)) continue;
+          if (!lat_free(fj, B.n, d, B.ffm)) continue;
           double wJ = 1.0;
           for (int a = 0; a < d; ++a) wJ *= w1d(fj[a], CJ[a], B.n[a]);
           if (wJ == 0.0) continue;
@@ -1024,6 +1093,7 @@ __global__ void __launch_bounds__(256) k_stress(StressParams S) {
         const int f = (i - s.nb) / s.nfb, q = (i - s.nb) % s.nfb;
         const int gf = S.elem_ff[e * nv + f];
         if (gf >= 0) v = S.x[S.off_f + (int64_t)gf * s.nfb + q];
+        else if (S.xD) v = S.xD[e * s.nd + (i - s.nb)];
       }
       ul[i] = v;
     }
@@ -1121,7 +1191,7 @@ __global__ void __launch_bounds__(256) k_stress(StressParams S) {
 __device__ inline void full_entry(const Sizes& s, int nf, int s0, int s1, bool two, int j, int& l0, int& l1) {
   if (j < nf) {
     l0 = s.nb + s0 * s.nfb + j;
-    l1 = two ? s.nb + s1 * s.nfb + j : -1;
+    l1 = two ? s.nb + s1 * s.nfb + j : -1;   // outlet facets: one neighbour
   } else if (j < nf + s.nb) {
     l0 = j - nf;
     l1 = -1;

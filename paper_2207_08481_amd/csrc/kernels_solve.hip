@@ -23,7 +23,7 @@ __device__ inline void gather_elem_d(const SolveParams& P, const R* __restrict__
   for (int t = threadIdx.x; t < s.nd; t += blockDim.x) {
     int f = t / s.nfb, q = t % s.nfb;
     int g = P.elem_ff[e * nv + f];
-    xd[t] = g >= 0 ? x[P.off_f + (int64_t)g * s.nfb + q] : R(0);
+    xd[t] = g >= 0 ? x[P.off_f + (int64_t)g * s.nfb + q] : (P.xD ? (R)P.xD[e * s.nd + t] : R(0));
   }
 }
 
@@ -190,7 +190,8 @@ __global__ void k_facet_sum(SolveParams P, const R* __restrict__ escr, const R* 
     int q = (int)(idx % s.nfb);
     int64_t e1 = P.facet_el[2 * g], e2 = P.facet_el[2 * g + 1];
     int s1 = P.facet_slot[2 * g], s2 = P.facet_slot[2 * g + 1];
-    R v = escr[e1 * s.nd + s1 * s.nfb + q] + escr[e2 * s.nd + s2 * s.nfb + q];
+    R v = escr[e1 * s.nd + s1 * s.nfb + q];
+    if (e2 >= 0) v += escr[e2 * s.nd + s2 * s.nfb + q];   // outlet facets have one neighbour
     R b = base ? base[P.off_f + idx] : R(0);
     y[P.off_f + idx] = b + sign * v;
   }
@@ -279,7 +280,9 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
     int64_t e = 0;
     R a[NFB];
     R yv = R(0);
-    if (work && is_row) {
+    // an outlet facet has no second neighbour: its rows stay idle
+    const bool row = work && is_row && (side == 0 || P.facet_el[2 * g + 1] >= 0);
+    if (row) {
       e = P.facet_el[2 * g + side];
       const int sl = P.facet_slot[2 * g + side];
       const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
@@ -294,7 +297,9 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
     if (work && tid < NFB) {
       const int64_t e1 = P.facet_el[2 * g], e2 = P.facet_el[2 * g + 1];
       const int s1 = P.facet_slot[2 * g], s2 = P.facet_slot[2 * g + 1];
-      rr[h][tid] = srhs[P.off_f + g * NFB + tid] - y[e1 * nd + s1 * NFB + tid] - y[e2 * nd + s2 * NFB + tid];
+      R r = srhs[P.off_f + g * NFB + tid] - y[e1 * nd + s1 * NFB + tid];
+      if (e2 >= 0) r -= y[e2 * nd + s2 * NFB + tid];
+      rr[h][tid] = r;
     }
     __syncthreads();
     if (work && tid < NFB) {
@@ -305,7 +310,7 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
       x[P.off_f + g * NFB + tid] += acc;
     }
     __syncthreads();
-    if (work && is_row) {
+    if (row) {
 #pragma unroll
       for (int q = 0; q < NFB; ++q) yv += a[q] * dl[h][q];
       y[e * nd + t] = yv;
@@ -426,11 +431,6 @@ __device__ inline void mg_coords(int64_t v, const int* n, int c[3]) {
   c[1] = (int)((v / N0) % N1);
   c[2] = (int)(v / ((int64_t)N0 * N1));
 }
-__device__ inline bool mg_interior(const int c[3], const int* n, int d) {
-  for (int a = 0; a < d; ++a)
-    if (c[a] <= 0 || c[a] >= n[a]) return false;
-  return true;
-}
 
 // Multigrid kernels run over the lattice blocks of a level, one block per
 // blockIdx.y; vertex indices are block-local plus the block's offset.
@@ -452,12 +452,12 @@ __global__ void __launch_bounds__(256) k_mg_point(int d, MGLevelDev L, int mode)
     const int64_t v = B.voff + lv_;
     int c[3];
     mg_coords(lv_, B.n, c);
-    const bool inner = mg_interior(c, B.n, d);
+    const bool inner = lat_free(c, B.n, d, B.ffm);
     R part[3] = {R(0), R(0), R(0)};
     if (inner && mode != 0 && lane < st) {
       const int o = lane;
       int w[3] = {c[0] + o % 3 - 1, c[1] + (o / 3) % 3 - 1, d == 3 ? c[2] + o / 9 - 1 : 0};
-      if (mg_interior(w, B.n, d)) {
+      if (lat_free(w, B.n, d, B.ffm)) {
         const int64_t wi = B.voff + w[0] + (int64_t)(B.n[0] + 1) * (w[1] + (int64_t)(B.n[1] + 1) * w[2]);
         const R* Av = A + ((size_t)v * st + o) * dd;
         for (int k = 0; k < d; ++k)
@@ -510,13 +510,13 @@ __global__ void __launch_bounds__(256) k_mg_restrict(int d, MGLevelDev F, MGLeve
   for (int64_t V = blockIdx.x * gpb + (threadIdx.x >> 5); V < B.nvert_c; V += (int64_t)gridDim.x * gpb) {
     int CI[3];
     mg_coords(V, B.nc3, CI);
-    const bool inner = mg_interior(CI, B.nc3, d);
+    const bool inner = lat_free(CI, B.nc3, d, B.ffm);
     R acc[3] = {R(0), R(0), R(0)};
     if (inner && lane < st) {
       const int o = lane;
       int base[3] = {mg_cpos(CI[0], B.n[0]), mg_cpos(CI[1], B.n[1]), d == 3 ? mg_cpos(CI[2], B.n[2]) : 0};
       int fi[3] = {base[0] + o % 3 - 1, base[1] + (o / 3) % 3 - 1, d == 3 ? base[2] + o / 9 - 1 : 0};
-      if (mg_interior(fi, B.n, d)) {
+      if (lat_free(fi, B.n, d, B.ffm)) {
         double w = 1.0;
         for (int a = 0; a < d; ++a) w *= mg_w(fi[a], CI[a], B.n[a]);
         if (w != 0.0) {
@@ -545,7 +545,7 @@ __global__ void __launch_bounds__(256) k_mg_prolong(int d, MGLevelDev F, MGLevel
   for (int64_t lv_ = blockIdx.x * gpb + (threadIdx.x >> 5); lv_ < B.nvert; lv_ += (int64_t)gridDim.x * gpb) {
     int fi[3];
     mg_coords(lv_, B.n, fi);
-    const bool inner = mg_interior(fi, B.n, d);
+    const bool inner = lat_free(fi, B.n, d, B.ffm);
     R acc[3] = {R(0), R(0), R(0)};
     if (inner && lane < st) {
       const int o = lane;
@@ -553,7 +553,7 @@ __global__ void __launch_bounds__(256) k_mg_prolong(int d, MGLevelDev F, MGLevel
       bool ok = true;
       for (int a = 0; a < d; ++a)
         if (CI[a] < 0 || CI[a] > B.nc3[a]) ok = false;
-      if (ok && mg_interior(CI, B.nc3, d)) {
+      if (ok && lat_free(CI, B.nc3, d, B.ffm)) {
         double w = 1.0;
         for (int a = 0; a < d; ++a) w *= mg_w(fi[a], CI[a], B.n[a]);
         if (w != 0.0) {
@@ -686,7 +686,8 @@ __global__ void k_eval(SolveParams P, const double* __restrict__ coords, const i
         } else {
           const int f = (i - s.nb) / s.nF, qq = (i - s.nb) % s.nF;
           const int g = P.elem_ff[e * nv + f];
-          c = g >= 0 ? x[P.off_f + (int64_t)g * s.nfb + qq] * idet : 0.0;
+          c = g >= 0 ? x[P.off_f + (int64_t)g * s.nfb + qq] * idet
+                     : (P.xD ? P.xD[e * s.nd + f * s.nfb + qq] * idet : 0.0);
         }
         if (c == 0.0) continue;
         const double* ph = rphi + (size_t)i * (nv + 3);
@@ -830,7 +831,7 @@ __global__ void __launch_bounds__(256) k_full_smooth(SolveParams P, FullDev F, i
     const int m = nf + nb * nside;
     if (tid < m) {
       double yy;
-      if (tid < nf) yy = y[e0 * nA + nb + s0 * nfb + tid] + y[e1 * nA + nb + s1 * nfb + tid];
+      if (tid < nf) yy = y[e0 * nA + nb + s0 * nfb + tid] + (e1 >= 0 ? y[e1 * nA + nb + s1 * nfb + tid] : 0.0);
       else if (tid < nf + nb) yy = y[e0 * nA + tid - nf];
       else yy = y[e1 * nA + tid - nf - nb];
       r[tid] = sv[full_dof(P, F, nf, g, e0, e1, tid)] - yy;
@@ -871,8 +872,8 @@ __global__ void k_full_resid(SolveParams P, int nA, const double* __restrict__ s
     } else {
       const int64_t g = (idx - P.off_f) / s.nfb;
       const int q = (int)((idx - P.off_f) % s.nfb);
-      yy = y[(int64_t)P.facet_el[2 * g] * nA + s.nb + P.facet_slot[2 * g] * s.nfb + q] +
-           y[(int64_t)P.facet_el[2 * g + 1] * nA + s.nb + P.facet_slot[2 * g + 1] * s.nfb + q];
+      yy = y[(int64_t)P.facet_el[2 * g] * nA + s.nb + P.facet_slot[2 * g] * s.nfb + q];
+      if (P.facet_el[2 * g + 1] >= 0) yy += y[(int64_t)P.facet_el[2 * g + 1] * nA + s.nb + P.facet_slot[2 * g + 1] * s.nfb + q];
     }
     r[idx] = sv[idx] - yy;
   }

@@ -89,6 +89,7 @@ struct LatLevel {
 
 struct MGBlock {
   int prob;
+  int ffm = 0;                  // outlet faces of the problem (see lat_free)
   int n[3];
   int64_t nvert, voff;          // vertices, first vertex in the level arrays
   int coarsest;
@@ -111,7 +112,9 @@ struct DevPtrs {
   int32_t* elem_ff;       // [ne][nv] free facet id or -1
   int32_t* elem_verts;    // [ne][nv] sorted global vertex ids
   int32_t* elem_perm;     // [ne] permutation rank of sorted order w.r.t. caller order
-  int32_t* facet_el;      // [nff][2] neighbour elements (ascending)
+  int32_t* facet_el;      // [nff][2] neighbour elements (ascending; -1: none, outlet facets)
+  int32_t* facet_out;     // [nff] 1 for an outlet facet
+  double* xD;             // [ne][nd] Dirichlet dofs of the element's Dirichlet facets
   int32_t* facet_slot;    // [nff][2] local facet index in each neighbour
   int32_t* colour_facets; // [nff] facets sorted by colour
   int32_t* facet_vfree;   // [nff][d] free P1 vertex ids of the facet's sorted vertices (-1)
@@ -174,6 +177,13 @@ struct mcs_problem {
   // canonical facet order, coloured so that facets of one element differ
   int64_t nblk = 0;
   int ncol_full = 0;
+  // boundary conditions: outlet faces of each member problem (bits as in
+  // lat_free), whether some facet is an outlet (then p is unique), and the
+  // outlet flag of every free facet
+  std::vector<int> pffm{0};
+  bool has_outlet = false;
+  bool has_dirichlet = false;   // mcs_set_dirichlet was called (xD holds g's dofs)
+  std::vector<int32_t> h_facet_out;
   std::vector<int32_t> h_blk_el, h_blk_slot, h_blk_g, h_blk_colour, colour_off_full, h_colour_blocks;
   std::vector<double> full_colour_bytes;  // algorithmic bytes of one colour phase (FP64)
   mcs::RefTables ref;
@@ -223,3 +233,9 @@ struct mcs_problem {
   }
   std::vector<std::pair<std::string, int64_t>> offsets;  // name -> byte offset
 };
+
+namespace mcs {
+// Dirichlet dofs ([n_e][n_d], element-local facet order) of g given on the
+// element lattices (caller vertex order); see mcs_set_dirichlet.
+void dirichlet_lift(const mcs_problem* pb, const double* g_lattice, std::vector<double>& xD);
+}  // namespace mcs

@@ -79,6 +79,7 @@ void build_mg(mcs_problem* pb) {
       if ((int)lv.size() <= l) continue;
       MGBlock B{};
       B.prob = i;
+      B.ffm = pb->pffm[i];
       for (int a = 0; a < 3; ++a) B.n[a] = lv[l].n[a];
       B.nvert = lv[l].nvert;
       B.voff = voff[l][i];
@@ -126,6 +127,20 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
     set_error("empty mesh");
     return MCS_ERR_ARG;
   }
+  for (int a = 0; a < d; ++a)
+    if (mesh->lattice[a] < 2) {
+      set_error("vertices do not form the declared lattice");
+      return MCS_ERR_MESH;
+    }
+  int ffm = 0;
+  for (int a = 0; a < 2 * d; ++a) {
+    if (mesh->face_bc[a] != 0 && mesh->face_bc[a] != 1) {
+      set_error("face_bc[%d] must be 0 (Dirichlet) or 1 (outlet)", a);
+      return MCS_ERR_ARG;
+    }
+    if (mesh->face_bc[a] == 1) ffm |= 1 << a;
+  }
+  pb->pffm.assign(1, ffm);
   pb->d = d;
   pb->opt = *opt;
   if (pb->opt.smoothing_steps <= 0) pb->opt.smoothing_steps = 2;
@@ -232,11 +247,42 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
       set_error("a facet is shared by more than two elements");
       return MCS_ERR_MESH;
     }
-    if (j - i == 1) {
+    // a boundary facet lies on one face of the lattice box: an outlet face
+    // keeps it as a free facet with one neighbour
+    bool outlet = false;
+    if (j - i == 1)
+      for (int a = 0; a < d; ++a)
+        for (int side = 0; side < 2; ++side) {
+          if (!((ffm >> (2 * a + side)) & 1)) continue;
+          const int target = side ? mesh->lattice[a] - 1 : 0;
+          bool all = true;
+          for (int c = 0; c < d; ++c) {
+            const int64_t v = fl[i].v[c];
+            const int64_t ca = a == 0 ? v % mesh->lattice[0]
+                             : a == 1 ? (v / mesh->lattice[0]) % mesh->lattice[1]
+                                      : v / ((int64_t)mesh->lattice[0] * mesh->lattice[1]);
+            if (ca != target) all = false;
+          }
+          if (all) outlet = true;
+        }
+    if (j - i == 1 && !outlet) {
       for (int c = 0; c < d; ++c) vbound[fl[i].v[c]] = 1;
       pb->h_blk_el.insert(pb->h_blk_el.end(), {fl[i].e, -1});
       pb->h_blk_slot.insert(pb->h_blk_slot.end(), {(int32_t)fl[i].slot, -1});
       pb->h_blk_g.push_back(-1);
+    } else if (j - i == 1) {
+      pb->h_blk_el.insert(pb->h_blk_el.end(), {fl[i].e, -1});
+      pb->h_blk_slot.insert(pb->h_blk_slot.end(), {(int32_t)fl[i].slot, -1});
+      pb->h_blk_g.push_back((int32_t)free_fv.size());
+      const int32_t g = (int32_t)free_fv.size();
+      free_fv.push_back(fl[i].v);
+      pb->h_facet_el.push_back(fl[i].e);
+      pb->h_facet_el.push_back(-1);
+      pb->h_facet_slot.push_back(fl[i].slot);
+      pb->h_facet_slot.push_back(-1);
+      pb->h_facet_out.push_back(1);
+      pb->h_elem_ff[fl[i].e * nv + fl[i].slot] = g;
+      pb->has_outlet = true;
     } else {
       pb->h_blk_el.insert(pb->h_blk_el.end(), {fl[i].e, fl[i + 1].e});
       pb->h_blk_slot.insert(pb->h_blk_slot.end(), {(int32_t)fl[i].slot, (int32_t)fl[i + 1].slot});
@@ -247,6 +293,7 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
       pb->h_facet_el.push_back(fl[i + 1].e);
       pb->h_facet_slot.push_back(fl[i].slot);
       pb->h_facet_slot.push_back(fl[i + 1].slot);
+      pb->h_facet_out.push_back(0);
       pb->h_elem_ff[fl[i].e * nv + fl[i].slot] = g;
       pb->h_elem_ff[fl[i + 1].e * nv + fl[i + 1].slot] = g;
     }
@@ -262,6 +309,7 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
     uint32_t used = 0;
     for (int side = 0; side < 2; ++side) {
       int64_t e = pb->h_facet_el[2 * g + side];
+      if (e < 0) continue;
       for (int i = 0; i < nv; ++i) {
         int32_t g2 = pb->h_elem_ff[e * nv + i];
         if (g2 >= 0 && g2 != g && pb->h_colour[g2] >= 0) used |= 1u << pb->h_colour[g2];
@@ -398,10 +446,8 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
   for (int64_t v = 0; v < nvert; ++v) {
     int c[3] = {int(v % pb->lattice[0]), int((v / pb->lattice[0]) % pb->lattice[1]),
                 int(v / ((int64_t)pb->lattice[0] * pb->lattice[1]))};
-    bool interior = true;
-    for (int a = 0; a < d; ++a)
-      if (c[a] == 0 || c[a] == pb->lattice[a] - 1) interior = false;
-    if (interior != (vfree[v] >= 0)) {
+    const int nint[3] = {pb->lattice[0] - 1, pb->lattice[1] - 1, pb->lattice[2] - 1};
+    if (lat_free(c, nint, d, ffm) != (vfree[v] >= 0)) {
       set_error("boundary of the mesh does not match the lattice boundary");
       return MCS_ERR_MESH;
     }
@@ -416,7 +462,10 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
       L.n[1] = n[1];
       L.n[2] = n[2];
       L.nvert = (int64_t)(n[0] + 1) * (n[1] + 1) * (d == 3 ? n[2] + 1 : 1);
-      L.nfree = (int64_t)(n[0] - 1) * (n[1] - 1) * (d == 3 ? n[2] - 1 : 1) * d;
+      // free vertices per axis: the interior ones plus outlet ends
+      int64_t nf = d;
+      for (int a = 0; a < d; ++a) nf *= n[a] - 1 + ((ffm >> (2 * a)) & 1) + ((ffm >> (2 * a + 1)) & 1);
+      L.nfree = nf;
       pb->plev[0].push_back(L);
       int nmin = std::min(n[0], n[1]);
       if (d == 3) nmin = std::min(nmin, n[2]);
@@ -427,10 +476,7 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
     int N0 = C.n[0] + 1, N1 = C.n[1] + 1;
     for (int64_t v = 0; v < C.nvert; ++v) {
       int c[3] = {int(v % N0), int((v / N0) % N1), int(v / ((int64_t)N0 * N1))};
-      bool interior = true;
-      for (int a = 0; a < d; ++a)
-        if (c[a] == 0 || c[a] == C.n[a]) interior = false;
-      if (interior)
+      if (lat_free(c, C.n, d, ffm))
         for (int cc = 0; cc < d; ++cc) pb->pcmap[0].push_back((int32_t)(v * d + cc));
     }
   }
@@ -471,6 +517,8 @@ int plan_union(const std::vector<const mcs_problem*>& parts, mcs_problem* u) {
   u->d = d;
   for (int a = 0; a < 3; ++a) u->lattice[a] = 0;
   u->nprob = (int)parts.size();
+  u->pffm.clear();
+  for (auto* q : parts) u->pffm.push_back(q->pffm[0]);
   u->pe0.assign(1, 0);
   u->pf0.assign(1, 0);
   u->pv0.assign(1, 0);
@@ -506,6 +554,7 @@ int plan_union(const std::vector<const mcs_problem*>& parts, mcs_problem* u) {
   cat(&mcs_problem::h_facet_el, u->h_facet_el, [&](int i, int32_t e) { return (int32_t)(e + u->pe0[i]); });
   cat(&mcs_problem::h_facet_slot, u->h_facet_slot, keep);
   cat(&mcs_problem::h_colour, u->h_colour, keep);
+  cat(&mcs_problem::h_facet_out, u->h_facet_out, keep);
   cat(&mcs_problem::h_facet_vfree, u->h_facet_vfree, [&](int i, int32_t v) { return v >= 0 ? (int32_t)(v + u->pfv0[i]) : v; });
   cat(&mcs_problem::h_vfree_of_lat, u->h_vfree_of_lat, [&](int i, int32_t v) { return v >= 0 ? (int32_t)(v + u->pfv0[i]) : v; });
   cat(&mcs_problem::h_free_to_lat, u->h_free_to_lat, [&](int i, int32_t v) { return (int32_t)(v + u->pv0[i]); });
@@ -564,6 +613,8 @@ int layout_workspace(mcs_problem* pb) {
   L.add("facet_el", I(nff * 2));
   L.add("facet_slot", I(nff * 2));
   L.add("colour_facets", I(nff));
+  L.add("facet_out", I(nff));
+  L.add("xD", Dd(ne * s.nd));
   L.add("facet_vfree", I(nff * d));
   L.add("vinc_off", I(pb->nfv + 1));
   L.add("vinc", I(pb->h_vinc.size()));

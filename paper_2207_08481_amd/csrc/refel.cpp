@@ -59,6 +59,44 @@ double fact(int n) {
   return v;
 }
 
+// Solves M x = b (n x n, row-major, overwritten) by Gaussian elimination with
+// partial pivoting; b receives x.
+void solve_dense(std::vector<double>& M, int n, std::vector<double>& b) {
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(M[(size_t)r * n + c]) > std::fabs(M[(size_t)p * n + c])) p = r;
+    if (p != c) {
+      for (int t = 0; t < n; ++t) std::swap(M[(size_t)c * n + t], M[(size_t)p * n + t]);
+      std::swap(b[c], b[p]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double f = M[(size_t)r * n + c] / M[(size_t)c * n + c];
+      if (f == 0.0) continue;
+      for (int t = c; t < n; ++t) M[(size_t)r * n + t] -= f * M[(size_t)c * n + t];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    double t = b[c];
+    for (int j = c + 1; j < n; ++j) t -= M[(size_t)c * n + j] * b[j];
+    b[c] = t / M[(size_t)c * n + c];
+  }
+}
+
+// (1/|F|) int_F mu^a mu^b over a simplex with nvar barycentric coordinates
+// (exact: (nvar-1)! (a+b)! / (|a|+|b|+nvar-1)!)
+double simplex_moment2(const MI& a, const MI& b) {
+  const int nvar = (int)a.size();
+  int tot = 0;
+  double num = fact(nvar - 1);
+  for (int j = 0; j < nvar; ++j) {
+    num *= fact(a[j] + b[j]);
+    tot += a[j] + b[j];
+  }
+  return num / fact(tot + nvar - 1);
+}
+
 // Gauss-Legendre nodes/weights on [0, 1] (Newton iteration on P_n).
 void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
   x.assign(n, 0.0);
@@ -600,6 +638,126 @@ RefTables build_ref_tables(int d, int k) {
     T.pmom[g] = fact(d) * den / fact(k - 1 + d);
   }
   return T;
+}
+
+// Dirichlet dofs of every Dirichlet facet from g given on the element
+// lattices (degree m, caller vertex order), per element in the local facet
+// order of the element ([n_e][n_d]): the normal dofs c with
+// sum_beta c_beta mu^beta / |F| the L2 projection of g.n_F onto P^k(F), and
+// the tangential dofs the L2 projection of g_t onto V-hat(F) (basis
+// mu^gamma t_b, t_b = x_{f_b} - x_{f_0}).  g is interpolated on the facet
+// from the lattice points that lie on it.
+void dirichlet_lift(const mcs_problem* pb, const double* g_lattice, std::vector<double>& xD) {
+  const Sizes& s = pb->sz;
+  const int d = pb->d, nv = d + 1, k = s.k, m = s.m;
+  const std::vector<MI> Ilat = multi_indices(nv, m);
+  const int nlat = (int)Ilat.size();
+  const std::vector<MI> Fm = multi_indices(d, m), Fk = multi_indices(d, k), Fk1 = multi_indices(d, k - 1);
+  const int nm = (int)Fm.size(), nk = (int)Fk.size(), ng = (int)Fk1.size();
+  std::map<MI, int> fm_index;
+  for (int j = 0; j < nm; ++j) fm_index[Fm[j]] = j;
+  // facet Vandermonde of degree m at the facet lattice points mu = beta / m,
+  // and the moment matrices
+  std::vector<double> Mkk(nk * nk), Mkm((size_t)nk * nm), Mgg(ng * ng), Mgm((size_t)ng * nm);
+  for (int i = 0; i < nk; ++i) {
+    for (int j = 0; j < nk; ++j) Mkk[i * nk + j] = simplex_moment2(Fk[i], Fk[j]);
+    for (int j = 0; j < nm; ++j) Mkm[(size_t)i * nm + j] = simplex_moment2(Fk[i], Fm[j]);
+  }
+  for (int i = 0; i < ng; ++i) {
+    for (int j = 0; j < ng; ++j) Mgg[i * ng + j] = simplex_moment2(Fk1[i], Fk1[j]);
+    for (int j = 0; j < nm; ++j) Mgm[(size_t)i * nm + j] = simplex_moment2(Fk1[i], Fm[j]);
+  }
+  xD.assign((size_t)pb->ne * s.nd, 0.0);
+  std::vector<double> gp((size_t)nm * d), coef((size_t)nm * d);
+  for (int64_t e = 0; e < pb->ne; ++e) {
+    const int perm = pb->h_elem_perm[e];
+    for (int i = 0; i < nv; ++i) {
+      if (pb->h_elem_ff[e * nv + i] >= 0) continue;   // free (interior or outlet) facet
+      int fv[3], c = 0;
+      for (int j = 0; j < nv; ++j)
+        if (j != i) fv[c++] = j;
+      double X[3][3] = {};
+      for (int j = 0; j < d; ++j)
+        for (int r = 0; r < d; ++r) X[j][r] = pb->h_coords[(size_t)pb->h_elem_verts[e * nv + fv[j]] * d + r];
+      double t[2][3] = {}, n[3] = {}, area;
+      for (int r = 0; r < d; ++r) {
+        t[0][r] = X[1][r] - X[0][r];
+        if (d == 3) t[1][r] = X[2][r] - X[0][r];
+      }
+      if (d == 2) {
+        n[0] = t[0][1];
+        n[1] = -t[0][0];
+      } else {
+        n[0] = t[0][1] * t[1][2] - t[0][2] * t[1][1];
+        n[1] = t[0][2] * t[1][0] - t[0][0] * t[1][2];
+        n[2] = t[0][0] * t[1][1] - t[0][1] * t[1][0];
+      }
+      const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      area = d == 2 ? nn : 0.5 * nn;
+      for (int r = 0; r < 3; ++r) n[r] /= nn;
+      // g at the facet's lattice points (sorted lattice index -> facet index)
+      for (int p = 0; p < nlat; ++p) {
+        const int sidx = pb->ref.latmap[(size_t)perm * nlat + p];
+        const MI& a = Ilat[sidx];
+        if (a[i] != 0) continue;
+        MI fmi;
+        for (int j = 0; j < nv; ++j)
+          if (j != i) fmi.push_back(a[j]);
+        const int q = fm_index.at(fmi);
+        for (int r = 0; r < d; ++r) gp[(size_t)q * d + r] = g_lattice[((size_t)e * nlat + p) * d + r];
+      }
+      // monomial coefficients of the degree-m interpolant on the facet
+      {
+        std::vector<double> V((size_t)nm * nm);
+        for (int q = 0; q < nm; ++q)
+          for (int j = 0; j < nm; ++j) {
+            double v = 1.0;
+            for (int b = 0; b < d; ++b) v *= std::pow((double)Fm[q][b] / m, Fm[j][b]);
+            V[(size_t)q * nm + j] = v;
+          }
+        for (int r = 0; r < d; ++r) {
+          std::vector<double> rhs(nm), Vc = V;
+          for (int q = 0; q < nm; ++q) rhs[q] = gp[(size_t)q * d + r];
+          solve_dense(Vc, nm, rhs);
+          for (int j = 0; j < nm; ++j) coef[(size_t)j * d + r] = rhs[j];
+        }
+      }
+      double* out = &xD[(size_t)e * s.nd + (size_t)i * s.nfb];
+      // normal dofs
+      {
+        std::vector<double> rhs(nk, 0.0), M = Mkk;
+        for (int a = 0; a < nk; ++a)
+          for (int j = 0; j < nm; ++j) {
+            double gn = 0.0;
+            for (int r = 0; r < d; ++r) gn += coef[(size_t)j * d + r] * n[r];
+            rhs[a] += Mkm[(size_t)a * nm + j] * gn;
+          }
+        solve_dense(M, nk, rhs);
+        for (int a = 0; a < nk; ++a) out[a] = area * rhs[a];
+      }
+      // tangential dofs: (T (x) M_gg) c = rhs, T_bb' = t_b . t_b'
+      {
+        const int nt = (d - 1) * ng;
+        std::vector<double> M((size_t)nt * nt), rhs(nt, 0.0);
+        for (int b = 0; b < d - 1; ++b)
+          for (int b2 = 0; b2 < d - 1; ++b2) {
+            double tt = 0.0;
+            for (int r = 0; r < d; ++r) tt += t[b][r] * t[b2][r];
+            for (int g1 = 0; g1 < ng; ++g1)
+              for (int g2 = 0; g2 < ng; ++g2) M[(size_t)(b * ng + g1) * nt + b2 * ng + g2] = tt * Mgg[g1 * ng + g2];
+          }
+        for (int b = 0; b < d - 1; ++b)
+          for (int g1 = 0; g1 < ng; ++g1)
+            for (int j = 0; j < nm; ++j) {
+              double gt = 0.0;
+              for (int r = 0; r < d; ++r) gt += coef[(size_t)j * d + r] * t[b][r];
+              rhs[b * ng + g1] += Mgm[(size_t)g1 * nm + j] * gt;
+            }
+        solve_dense(M, nt, rhs);
+        for (int q = 0; q < nt; ++q) out[s.nF + q] = rhs[q];
+      }
+    }
+  }
 }
 
 }  // namespace mcs

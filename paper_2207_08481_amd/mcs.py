@@ -27,7 +27,8 @@ PC = {"KHAT": 0, "AEXT": 1, "ADELTA_MULT": 2, "SMOOTH_FWD": 3, "SMOOTH_BWD": 4, 
 
 # exported symbols of include/mcs.h
 SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
-           "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_get_array",
+           "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
+                 "mcs_get_array",
            "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_destroy",
            "mcs_status_string", "mcs_last_error",
            "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
@@ -45,7 +46,8 @@ class MCSError(RuntimeError):
 
 class Mesh(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_vertices", C.c_int32), ("vertices_host", C.c_void_p),
-                ("n_elements", C.c_int32), ("elements_host", C.c_void_p), ("lattice", C.c_int32 * 3)]
+                ("n_elements", C.c_int32), ("elements_host", C.c_void_p), ("lattice", C.c_int32 * 3),
+                ("face_bc", C.c_int32 * 6)]
 
 
 class Options(C.Structure):
@@ -121,6 +123,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_normalize_pressure.argtypes = [vp, vp]
     lib.mcs_eval.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.mcs_eval_stress.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.mcs_set_dirichlet.argtypes = [vp, vp]
     lib.mcs_get_array.argtypes = [vp, C.c_char_p, C.POINTER(vp), C.POINTER(i64)]
     lib.mcs_get_topology.argtypes = [vp, vp, vp]
     lib.mcs_get_full_colouring.argtypes = [vp, C.POINTER(i64), vp]
@@ -154,7 +157,8 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_server_destroy.argtypes = [vp]
     lib.mcs_server_destroy.restype = None
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
-                 "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_get_array",
+                 "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
+                 "mcs_get_array",
                  "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
                  "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable", "mcs_batch_timer_read",
@@ -192,7 +196,7 @@ class Problem:
 
     def __init__(self, vertices, elements, lattice, order, precision=0, smoothing_steps=2,
                  tol=1e-10, max_it=2000, inner_tol=1e-5, max_outer=10, coarse_max=512, autotune=0,
-                 smoother=0):
+                 smoother=0, face_bc=None):
         lib = load_library()
         self._lib = lib
         v = np.ascontiguousarray(vertices, dtype=np.float64)
@@ -200,8 +204,9 @@ class Problem:
         self.dim = v.shape[1]
         self._v, self._e = v, e
         lat = list(lattice) + [1] * (3 - len(lattice))
+        fb = list(face_bc) if face_bc is not None else []
         self._mesh = Mesh(self.dim, v.shape[0], v.ctypes.data, e.shape[0], e.ctypes.data,
-                          (C.c_int32 * 3)(*lat))
+                          (C.c_int32 * 3)(*lat), (C.c_int32 * 6)(*(fb + [0] * (6 - len(fb)))))
         self._opt = Options(order, precision, smoothing_steps, max_it, tol, inner_tol, max_outer,
                             coarse_max, autotune, smoother)
         self.info = Info()
@@ -299,6 +304,15 @@ class Problem:
         _check(self._lib.mcs_eval(self._h, x.data_ptr(), npts, pts.ctypes.data, u.data_ptr(), p.data_ptr()))
         return u, p
 
+    def set_dirichlet(self, g_lattice):
+        """Dirichlet data g on the element lattices ([n_e, n_lat, dim], host
+        array like f's values), or None for homogeneous data."""
+        if g_lattice is None:
+            _check(self._lib.mcs_set_dirichlet(self._h, None))
+            return
+        g = np.ascontiguousarray(g_lattice, dtype=np.float64)
+        _check(self._lib.mcs_set_dirichlet(self._h, g.ctypes.data))
+
     def eval_stress(self, x, ref_pts):
         """(sigma, omega), each [n_e, n_pts, dim, dim]: the stress and vorticity
         recovered from x (local problems of the condensation) at barycentric
@@ -383,7 +397,7 @@ class Batch:
     member.  meshes: list of (vertices, elements, lattice); orders: list of k."""
 
     def __init__(self, meshes, orders, precision=1, smoothing_steps=2, tol=1e-8, max_it=2000,
-                 inner_tol=1e-5, max_outer=10, coarse_max=512, autotune=1, smoother=0):
+                 inner_tol=1e-5, max_outer=10, coarse_max=512, autotune=1, smoother=0, face_bcs=None):
         lib = load_library()
         self._lib = lib
         self._keep = []
@@ -394,7 +408,9 @@ class Batch:
             e = np.ascontiguousarray(e, dtype=np.int32)
             self._keep += [v, e]
             lat = list(lat) + [1] * (3 - len(lat))
-            arr[i] = Mesh(v.shape[1], v.shape[0], v.ctypes.data, e.shape[0], e.ctypes.data, (C.c_int32 * 3)(*lat))
+            fb = list(face_bcs[i]) if face_bcs is not None else []
+            arr[i] = Mesh(v.shape[1], v.shape[0], v.ctypes.data, e.shape[0], e.ctypes.data, (C.c_int32 * 3)(*lat),
+                          (C.c_int32 * 6)(*(fb + [0] * (6 - len(fb)))))
             self.dims.append(v.shape[1])
             self.n_elements.append(e.shape[0])
         self._meshes = arr

@@ -209,3 +209,34 @@ def test_batch_members_recipe():
     assert ns.min() >= 4 and ns.max() <= 16
     assert set(m["k"] for m in ms) == {2, 3, 4}
     assert ms == W.batch_members(256, seed=5)
+
+
+def test_outlet_plan_matches_oracle_topology():
+    """Outlet faces (face_bc = 1): the planner's free facets (interior and
+    outlet, canonical order), their colours, the element -> free facet map and
+    the free P1 vertices equal the oracle's topology."""
+    from paper_2207_08481_amd.mcs import Problem
+    from oracle.topology import Topology
+    for cells, fb in (((4, 3), [0, 1, 0, 0]), ((2, 2, 2), [0, 1, 0, 0, 0, 0]), ((3, 2, 2), [1, 0, 0, 0, 0, 1])):
+        mesh = W.box_mesh(cells, (1.0,) * len(cells))
+        d = len(cells)
+        pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, face_bc=fb)
+        topo = Topology(mesh.vertices, mesh.elements, fb)
+        assert pb.info.n_free_facets == topo.n_free_facets
+        assert pb.info.n_p1_dofs == d * len(topo.free_vertices)
+        colour, elem_ff = pb.topology()
+        assert np.array_equal(colour, topo.colour)
+        ref = topo.free_facet_of[topo.elem_facets]
+        assert np.array_equal(elem_ff.reshape(ref.shape), ref)
+        pb.close()
+
+
+def test_outlet_errors():
+    from paper_2207_08481_amd.mcs import Problem, MCSError, Batch
+    mesh = W.box_mesh((2, 2), (1.0, 1.0))
+    with pytest.raises(MCSError) as ex:
+        Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, face_bc=[0, 2, 0, 0])
+    assert ex.value.status == -1
+    with pytest.raises(MCSError) as ex:
+        Batch([(mesh.vertices, mesh.elements, mesh.lattice)], [2], face_bcs=[[0, 1, 0, 0]])
+    assert ex.value.status == -10
