@@ -32,6 +32,7 @@ inline SolveParams solve_params(mcs_problem* pb) {
   P.ne = pb->ne;
   P.nff = pb->nff;
   P.off_f = pb->off_f;
+  P.has_outlet = pb->has_outlet ? 1 : 0;
   P.off_p = pb->off_p;
   P.ndof = pb->ndof;
   P.elem_ff = pb->p.elem_ff;

@@ -167,6 +167,7 @@ struct SolveParams {
   // processes, spread over 256 counters 128 bytes apart (workgroup w adds to
   // counter w mod 256)
   unsigned long long* work_count;
+  int has_outlet;  // some free facets are outlets with one neighbour
   // Dirichlet dofs per element ([ne][nd]): when set, gathers of facet values
   // take them for the element's Dirichlet facets (lifting and point values)
   const double* xD;

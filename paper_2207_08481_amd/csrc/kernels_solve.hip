@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, co
 // short dependent chain (residual -> D_F^{-1} -> update) starts.  Workgroups
 // loop over the colour's facets in steps of the grid, so the launch shape
 // (FPW, grid) changes only which team handles a facet, never the arithmetic.
-template <typename R, int NFB, int FPW>
+template <typename R, int NFB, int FPW, bool OUT>
 __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, int32_t c0, int32_t c1,
                                                   R* __restrict__ x, const R* __restrict__ srhs, R* __restrict__ y,
                                                   int T1) {
@@ -280,10 +280,12 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
     int64_t e = 0;
     R a[NFB];
     R yv = R(0);
-    // an outlet facet has no second neighbour: its rows stay idle
-    const bool row = work && is_row && (side == 0 || P.facet_el[2 * g + 1] >= 0);
+    // OUT: some facets are outlets with no second neighbour (-1); their
+    // second-side rows stay idle
+    bool row = work && is_row;
+    if (row) e = P.facet_el[2 * g + side];
+    if constexpr (OUT) row = row && e >= 0;
     if (row) {
-      e = P.facet_el[2 * g + side];
       const int sl = P.facet_slot[2 * g + side];
       const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
 #pragma unroll
@@ -297,9 +299,13 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
     if (work && tid < NFB) {
       const int64_t e1 = P.facet_el[2 * g], e2 = P.facet_el[2 * g + 1];
       const int s1 = P.facet_slot[2 * g], s2 = P.facet_slot[2 * g + 1];
-      R r = srhs[P.off_f + g * NFB + tid] - y[e1 * nd + s1 * NFB + tid];
-      if (e2 >= 0) r -= y[e2 * nd + s2 * NFB + tid];
-      rr[h][tid] = r;
+      if constexpr (OUT) {
+        R r = srhs[P.off_f + g * NFB + tid] - y[e1 * nd + s1 * NFB + tid];
+        if (e2 >= 0) r -= y[e2 * nd + s2 * NFB + tid];
+        rr[h][tid] = r;
+      } else {
+        rr[h][tid] = srhs[P.off_f + g * NFB + tid] - y[e1 * nd + s1 * NFB + tid] - y[e2 * nd + s2 * NFB + tid];
+      }
     }
     __syncthreads();
     if (work && tid < NFB) {
@@ -1018,10 +1024,20 @@ template <typename R, int NFB>
 static void smooth_launch(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
                           const R* s, R* y, int fpw, int64_t cap, int T1) {
   const int64_t blocks = std::min<int64_t>((c1 - c0 + fpw - 1) / fpw, cap);
-  if (fpw == 2)
-    hipLaunchKernelGGL((k_smooth_y<R, NFB, 2>), dim3((unsigned)blocks), dim3(2 * T1), 0, st, P, O, c0, c1, x, s, y, T1);
-  else
-    hipLaunchKernelGGL((k_smooth_y<R, NFB, 1>), dim3((unsigned)blocks), dim3(T1), 0, st, P, O, c0, c1, x, s, y, T1);
+  if (P.has_outlet) {
+    if (fpw == 2)
+      hipLaunchKernelGGL((k_smooth_y<R, NFB, 2, true>), dim3((unsigned)blocks), dim3(2 * T1), 0, st, P, O, c0, c1, x, s,
+                         y, T1);
+    else
+      hipLaunchKernelGGL((k_smooth_y<R, NFB, 1, true>), dim3((unsigned)blocks), dim3(T1), 0, st, P, O, c0, c1, x, s, y,
+                         T1);
+  } else if (fpw == 2) {
+    hipLaunchKernelGGL((k_smooth_y<R, NFB, 2, false>), dim3((unsigned)blocks), dim3(2 * T1), 0, st, P, O, c0, c1, x, s,
+                       y, T1);
+  } else {
+    hipLaunchKernelGGL((k_smooth_y<R, NFB, 1, false>), dim3((unsigned)blocks), dim3(T1), 0, st, P, O, c0, c1, x, s, y,
+                       T1);
+  }
 }
 int smooth_team_threads(int nd) { return ((2 * nd + 63) / 64) * 64; }
 template <typename R>

@@ -370,6 +370,20 @@ def workload(name: str, **kw):
         nu = np.ones(mesh.n_elements)
         f = sol.f(lattice_points(mesh, k + 1))
         return dict(mesh=mesh, nu=nu, k=k, f_lattice=f, solution=sol, tol=1e-10)
+    if name == "channel_k3":
+        # plane channel flow in a 4 x 1 x 1 box (40 x 10 x 10 cells, 24,000
+        # tets), nu = 1e-3 as in the paper's channel runs: the profile as
+        # Dirichlet data on the inlet and on z = 0, 1, no-slip plates y = 0, 1,
+        # an outlet Gamma_NT at x = 4
+        cells = kw.get("cells", (40, 10, 10))
+        k = kw.get("k", 3)
+        L = 4.0
+        mesh = box_mesh(cells, (L, 1.0, 1.0))
+        sol = PlaneChannel(3, nu=1e-3, L=L)
+        nu = np.full(mesh.n_elements, sol.nu)
+        pts = lattice_points(mesh, k + 1)
+        return dict(mesh=mesh, nu=nu, k=k, f_lattice=sol.f(pts), g_lattice=sol.u(pts), face_bc=sol.face_bc(),
+                    solution=sol, tol=1e-10)
     if name == "cube32_k4_lognormal":
         n = kw.get("n", 32)
         k = kw.get("k", 4)
