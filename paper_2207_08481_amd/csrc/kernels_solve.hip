@@ -283,14 +283,25 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
     // OUT: some facets are outlets with no second neighbour (-1); their
     // second-side rows stay idle
     bool row = work && is_row;
-    if (row) e = P.facet_el[2 * g + side];
-    if constexpr (OUT) row = row && e >= 0;
-    if (row) {
-      const int sl = P.facet_slot[2 * g + side];
-      const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
+    if constexpr (OUT) {
+      if (row) e = P.facet_el[2 * g + side];
+      row = row && e >= 0;
+      if (row) {
+        const int sl = P.facet_slot[2 * g + side];
+        const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
 #pragma unroll
-      for (int q = 0; q < NFB; ++q) a[q] = Ab[(size_t)q * nd];
-      yv = y[e * nd + t];
+        for (int q = 0; q < NFB; ++q) a[q] = Ab[(size_t)q * nd];
+        yv = y[e * nd + t];
+      }
+    } else {
+      if (work && is_row) {
+        e = P.facet_el[2 * g + side];
+        const int sl = P.facet_slot[2 * g + side];
+        const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
+#pragma unroll
+        for (int q = 0; q < NFB; ++q) a[q] = Ab[(size_t)q * nd];
+        yv = y[e * nd + t];
+      }
     }
     if (work) {
       const R* Di = O.Dinv + (size_t)g * NFB * NFB;
