@@ -91,9 +91,10 @@ __device__ inline void build_rowmap(const Sizes& s, int* rmap) {
 // z_o = x_o + H x_d (16-lane groups per row of H); phase 2: w_o = A_oo z_o;
 // phase 3: H^T w_o (one column per thread) and the pressure coupling.
 // B_T[q][row] = -s |det J| Bp^[q][iu(row)] (s = 1 bubble, 1/det J facet row).
-template <typename R, typename MA>
+template <typename R, typename MA, int FL>
 __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH, MA MAoo, const R* __restrict__ x,
                                                     R* __restrict__ y, R* __restrict__ escr, int flags) {
+  if constexpr (FL >= 0) flags = FL;   // specialised instantiations fold the flag tests
   const Sizes s = P.s;
   const int nb = s.nb, nd = s.nd, np = s.np, nu = s.nu;
   __shared__ R xd[MAXND], xo[MAXNB], zo[MAXNB], wo[MAXNB];
@@ -1005,17 +1006,29 @@ void launch_full_ed(hipStream_t st, const SolveParams& P, const FullDev& F, cons
 }
 static int elem_grid(int64_t ne) { return (int)std::min<int64_t>(ne, 1 << 20); }
 
+template <typename R, typename MA>
+static void elem_apply_launch(hipStream_t st, const SolveParams& P, MA Ad, MA H, MA Aoo, const R* x, R* y, R* escr,
+                              int flags) {
+  // the operator apply K x and the B^T-only apply of K-hat^{-1} run every
+  // MINRES iteration: compile-time flags for them
+  if (flags == (1 | 2 | 4))
+    hipLaunchKernelGGL((k_elem_apply<R, MA, 7>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, Ad, H, Aoo, x, y, escr, flags);
+  else if (flags == (2 | 16))
+    hipLaunchKernelGGL((k_elem_apply<R, MA, 18>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, Ad, H, Aoo, x, y, escr,
+                       flags);
+  else
+    hipLaunchKernelGGL((k_elem_apply<R, MA, -1>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, Ad, H, Aoo, x, y, escr,
+                       flags);
+}
 template <typename R>
 void launch_elem_apply(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* x, R* y, R* escr, int flags) {
   if constexpr (sizeof(R) == 8) {
     if (!O.Ad) {   // split storage: FP64 entries as FP32 hi + lo
-      hipLaunchKernelGGL((k_elem_apply<R, MatHL>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, MatHL{O.hAd, O.lAd},
-                         MatHL{O.hH, O.lH}, MatHL{O.hAoo, O.lAoo}, x, y, escr, flags);
+      elem_apply_launch<R, MatHL>(st, P, MatHL{O.hAd, O.lAd}, MatHL{O.hH, O.lH}, MatHL{O.hAoo, O.lAoo}, x, y, escr, flags);
       return;
     }
   }
-  hipLaunchKernelGGL((k_elem_apply<R, MatP<R>>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, MatP<R>{O.Ad},
-                     MatP<R>{O.H}, MatP<R>{O.Aoo}, x, y, escr, flags);
+  elem_apply_launch<R, MatP<R>>(st, P, MatP<R>{O.Ad}, MatP<R>{O.H}, MatP<R>{O.Aoo}, x, y, escr, flags);
 }
 template <typename R>
 void launch_facet_sum(hipStream_t st, const SolveParams& P, const R* escr, const R* base, R sign, R* y) {
