@@ -20,16 +20,58 @@
 namespace mcs {
 
 // --------------------------------------------------------------------------
-// 64x64 output tile of C = A B^T (A: M x K, B: N x K, row-major), 256 threads,
-// 4x4 micro tiles, K panels of 16 staged in LDS.  acc is per thread.
+// 64x64 output tiles of dense products on the FP64 matrix cores, 256 threads:
+// wave w owns the 32x32 quarter (w / 2, w % 2) as 2x2 blocks of the 16x16x4
+// FP64 matrix instruction; K panels of 16 are staged in LDS as [k][64].
+// Operand lanes: A(i, k) in lane i + 16 k, B^T(k, j) in lane j + 16 k;
+// result register r of lane l holds C(l / 16 + 4 r, l % 16) of a block.
+// acc[q], q = 8 bi + 4 bj + r, is C[m0 + tile_row(q)][n0 + tile_col(q)].
 // --------------------------------------------------------------------------
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ inline int tile_row(int q) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  return (w >> 1) * 32 + (q >> 3) * 16 + (l >> 4) + 4 * (q & 3);
+}
+__device__ inline int tile_col(int q) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  return (w & 1) * 32 + ((q >> 2) & 1) * 16 + (l & 15);
+}
+
+// c += la-panel x lb-panel^T for this wave's quarter (one 16-deep panel).
+__device__ inline void tile_panel_mfma(const double* la, const double* lb, dbl4 c[2][2]) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rb = (w >> 1) * 32 + (l & 15), cb = (w & 1) * 32 + (l & 15);
+#pragma unroll
+  for (int k4 = 0; k4 < 16; k4 += 4) {
+    const int kk = (k4 + (l >> 4)) * 64;
+    const double a0 = la[kk + rb], a1 = la[kk + rb + 16];
+    const double b0 = lb[kk + cb], b1 = lb[kk + cb + 16];
+    c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c[0][0], 0, 0, 0);
+    c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c[0][1], 0, 0, 0);
+    c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c[1][0], 0, 0, 0);
+    c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c[1][1], 0, 0, 0);
+  }
+}
+
+__device__ inline void tile_store(const dbl4 c[2][2], double acc[16]) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[bi * 8 + bj * 4 + r] = c[bi][bj][r];
+}
+
+// C = A B^T (A: M x K, B: N x K, row-major): the tile at (m0, n0).
 __device__ void tile_nt(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
-                        int m0, int n0, int M, int N, int K, double acc[4][4], double* lds) {
+                        int m0, int n0, int M, int N, int K, double acc[16], double* lds) {
   double* la = lds;            // [16][64]
   double* lb = lds + 16 * 64;  // [16][64]
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  const int tid = threadIdx.x;
+  dbl4 c[2][2];
+  for (int bi = 0; bi < 2; ++bi)
+    for (int bj = 0; bj < 2; ++bj) c[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += 16) {
     for (int idx = tid; idx < 1024; idx += 256) {
       int r = idx >> 4, kk = idx & 15;
@@ -38,54 +80,35 @@ __device__ void tile_nt(const double* __restrict__ A, int lda, const double* __r
       lb[kk * 64 + r] = (gn < N && gk < K) ? B[(size_t)gn * ldb + gk] : 0.0;
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = la[kk * 64 + ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = lb[kk * 64 + tx * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
+    tile_panel_mfma(la, lb, c);
     __syncthreads();
   }
+  tile_store(c, acc);
 }
 
-// acc = A(m0.., :) * B(:, n0..) for row-major A (M x K, lda) and B (K x N, ldb).
+// C = A B for row-major A (M x K, lda) and B (K x N, ldb): the tile at (m0, n0).
 __device__ void tile_nn(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
-                        int m0, int n0, int M, int N, int K, double acc[4][4], double* lds) {
+                        int m0, int n0, int M, int N, int K, double acc[16], double* lds) {
   double* la = lds;            // [16][64]
   double* lb = lds + 16 * 64;  // [16][64]
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  const int tid = threadIdx.x;
+  dbl4 c[2][2];
+  for (int bi = 0; bi < 2; ++bi)
+    for (int bj = 0; bj < 2; ++bj) c[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += 16) {
     for (int idx = tid; idx < 1024; idx += 256) {
       int r = idx >> 4, kk = idx & 15;
       int gm = m0 + r, gk = k0 + kk;
       la[kk * 64 + r] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : 0.0;
-      int kb = idx >> 6, c = idx & 63;
-      int gkb = k0 + kb, gn = n0 + c;
-      lb[kb * 64 + c] = (gkb < K && gn < N) ? B[(size_t)gkb * ldb + gn] : 0.0;
+      int kb = idx >> 6, cc = idx & 63;
+      int gkb = k0 + kb, gn = n0 + cc;
+      lb[kb * 64 + cc] = (gkb < K && gn < N) ? B[(size_t)gkb * ldb + gn] : 0.0;
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = la[kk * 64 + ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = lb[kk * 64 + tx * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
+    tile_panel_mfma(la, lb, c);
     __syncthreads();
   }
+  tile_store(c, acc);
 }
 
 // In-place Cholesky (lower) of an n x n row-major SPD matrix in memory
@@ -376,28 +399,24 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
     // Y = G Q^T
     for (int n0 = 0; n0 < s.nlam; n0 += 64)
       for (int m0 = 0; m0 < s.nA; m0 += 64) {
-        double acc[4][4];
+        double acc[16];
         tile_nt(G, s.nsig, Lm, s.nsig, m0, n0, s.nA, s.nlam, s.nsig, acc, lds);
-        const int tx = tid & 15, ty = tid >> 4;
-        for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 4; ++j) {
-            int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
-            if (r < s.nA && c < s.nlam) Y[r * s.nlam + c] = acc[i][j];
-          }
+        for (int q = 0; q < 16; ++q) {
+          int r = m0 + tile_row(q), c = n0 + tile_col(q);
+          if (r < s.nA && c < s.nlam) Y[r * s.nlam + c] = acc[q];
+        }
       }
     __syncthreads();
     // R = G (I - Q^T Q) = G - Y Q  (in place of G): the sigma columns with the
     // nt-constraint directions projected out
     for (int m0 = 0; m0 < s.nA; m0 += 64)
       for (int n0 = 0; n0 < s.nsig; n0 += 64) {
-        double acc[4][4];
+        double acc[16];
         tile_nn(Y, s.nlam, Lm, s.nsig, m0, n0, s.nA, s.nsig, s.nlam, acc, lds);
-        const int tx = tid & 15, ty = tid >> 4;
-        for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 4; ++j) {
-            int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
-            if (r < s.nA && c < s.nsig) G[(size_t)r * s.nsig + c] -= acc[i][j];
-          }
+        for (int q = 0; q < 16; ++q) {
+          int r = m0 + tile_row(q), c = n0 + tile_col(q);
+          if (r < s.nA && c < s.nsig) G[(size_t)r * s.nsig + c] -= acc[q];
+        }
       }
     __syncthreads();
     // A = A^div + (nu/|T|) R R^T   (= G (I - Q^T Q) G^T without the
@@ -406,28 +425,26 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
     const double cf = nuT / g.vol;
     for (int m0 = 0; m0 < s.nA; m0 += 64)
       for (int n0 = m0; n0 < s.nA; n0 += 64) {
-        double acc[4][4];
+        double acc[16];
         tile_nt(G, s.nsig, G, s.nsig, m0, n0, s.nA, s.nA, s.nsig, acc, lds);
-        const int tx = tid & 15, ty = tid >> 4;
-        for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 4; ++j) {
-            int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
-            // upper triangle only (in a diagonal block the (c, r) thread would
-            // write the mirrored pair too): one writer per entry pair
-            if (r < s.nA && c < s.nA && r <= c) {
-              double v = cf * acc[i][j];
-              // A^div on velocity rows
-              int ir = -1, ic = -1;
-              double sr = 1.0, sc2 = 1.0;
-              if (r < s.nb) ir = r;
-              else { int f = (r - s.nb) / s.nfb, q = (r - s.nb) % s.nfb; if (q < s.nF) { ir = s.nb + f * s.nF + q; sr = idet; } }
-              if (c < s.nb) ic = c;
-              else { int f = (c - s.nb) / s.nfb, q = (c - s.nb) % s.nfb; if (q < s.nF) { ic = s.nb + f * s.nF + q; sc2 = idet; } }
-              if (ir >= 0 && ic >= 0) v += (nuT / d) * sr * sc2 * adet * P.rD[(size_t)ir * s.nu + ic];
-              A[(size_t)r * s.nA + c] = v;
-              A[(size_t)c * s.nA + r] = v;
-            }
+        for (int q = 0; q < 16; ++q) {
+          int r = m0 + tile_row(q), c = n0 + tile_col(q);
+          // upper triangle only (in a diagonal block the (c, r) thread would
+          // write the mirrored pair too): one writer per entry pair
+          if (r < s.nA && c < s.nA && r <= c) {
+            double v = cf * acc[q];
+            // A^div on velocity rows
+            int ir = -1, ic = -1;
+            double sr = 1.0, sc2 = 1.0;
+            if (r < s.nb) ir = r;
+            else { int f = (r - s.nb) / s.nfb, t = (r - s.nb) % s.nfb; if (t < s.nF) { ir = s.nb + f * s.nF + t; sr = idet; } }
+            if (c < s.nb) ic = c;
+            else { int f = (c - s.nb) / s.nfb, t = (c - s.nb) % s.nfb; if (t < s.nF) { ic = s.nb + f * s.nF + t; sc2 = idet; } }
+            if (ir >= 0 && ic >= 0) v += (nuT / d) * sr * sc2 * adet * P.rD[(size_t)ir * s.nu + ic];
+            A[(size_t)r * s.nA + c] = v;
+            A[(size_t)c * s.nA + r] = v;
           }
+        }
       }
     __syncthreads();
     // tangential dofs of an outlet facet are fixed to zero: identity rows and
@@ -481,39 +498,35 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
     double* Ht = G;
     for (int m0 = 0; m0 < nd; m0 += 64)
       for (int n0 = 0; n0 < nb; n0 += 64) {
-        double acc[4][4];
+        double acc[16];
         tile_nt(A + (size_t)nb * s.nA, s.nA, Wk, nb, m0, n0, nd, nb, nb, acc, lds);
-        const int tx = tid & 15, ty = tid >> 4;
-        for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 4; ++j) {
-            int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
-            if (r < nd && c < nb) {
-              double v = acc[i][j];
-              Ht[(size_t)r * nb + c] = v;
-              const size_t hi = (size_t)e * nb * nd + (size_t)c * nd + r;
-              const float hv = (float)v;
-              if (P.H) P.H[hi] = v;
-              P.H32[hi] = hv;
-              if (P.Hl) P.Hl[hi] = (float)(v - (double)hv);
-            }
+        for (int q = 0; q < 16; ++q) {
+          int r = m0 + tile_row(q), c = n0 + tile_col(q);
+          if (r < nd && c < nb) {
+            double v = acc[q];
+            Ht[(size_t)r * nb + c] = v;
+            const size_t hi = (size_t)e * nb * nd + (size_t)c * nd + r;
+            const float hv = (float)v;
+            if (P.H) P.H[hi] = v;
+            P.H32[hi] = hv;
+            if (P.Hl) P.Hl[hi] = (float)(v - (double)hv);
           }
+        }
       }
     __syncthreads();
     // Ad = A_dd - A_do Ht^T   (in the FP64 array, or the slot's FP64 buffer)
     double* Ade = P.Ad ? P.Ad + (size_t)e * nd * nd : P.adtmp + (size_t)blockIdx.x * P.adtmp_stride;
     for (int m0 = 0; m0 < nd; m0 += 64)
       for (int n0 = 0; n0 < nd; n0 += 64) {
-        double acc[4][4];
+        double acc[16];
         tile_nt(A + (size_t)nb * s.nA, s.nA, Ht, nb, m0, n0, nd, nd, nb, acc, lds);
-        const int tx = tid & 15, ty = tid >> 4;
-        for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 4; ++j) {
-            int r = m0 + ty * 4 + i, c = n0 + tx * 4 + j;
-            if (r < nd && c < nd) {
-              double v = A[(size_t)(nb + r) * s.nA + nb + c] - acc[i][j];
-              Ade[(size_t)r * nd + c] = v;
-            }
+        for (int q = 0; q < 16; ++q) {
+          int r = m0 + tile_row(q), c = n0 + tile_col(q);
+          if (r < nd && c < nd) {
+            double v = A[(size_t)(nb + r) * s.nA + nb + c] - acc[q];
+            Ade[(size_t)r * nd + c] = v;
           }
+        }
       }
     __syncthreads();
     // symmetrise Ad exactly and write the FP32 copy (and the low parts)
