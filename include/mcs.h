@@ -249,7 +249,9 @@ int mcs_normalize_pressure(mcs_problem* pb, double* x);
 
 /* Device pointer and element count of an internal array, for inspection:
  * name in {"Ad", "H", "Aoo", "Aooinv", "Dinv", "EF", "Ad32", "H32", "detJ",
- * "colour_facets", "elem_ff", "W", "Cinv", "mgA0"}.  The memory belongs to
+ * "colour_desc", "elem_ff", "W", "Cinv", "mgA0"}.  "colour_desc" holds four
+ * int32 per free facet in colour order: facet id, its two elements (-1: none)
+ * and their local facet slots packed as s1 | s2 << 8.  The memory belongs to
  * the caller's workspace. */
 int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count);
 

@@ -38,7 +38,7 @@ inline SolveParams solve_params(mcs_problem* pb) {
   P.elem_ff = pb->p.elem_ff;
   P.facet_el = pb->p.facet_el;
   P.facet_slot = pb->p.facet_slot;
-  P.colour_facets = pb->p.colour_facets;
+  P.colour_desc = pb->p.colour_desc;
   P.detJ = pb->p.detJ;
   P.nu = pb->p.nu;
   P.rBp = pb->p.rBp;

@@ -229,7 +229,7 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   p.facet_slot = ws_ptr<int32_t>(pb, "facet_slot");
   p.facet_out = ws_ptr<int32_t>(pb, "facet_out");
   p.xD = ws_ptr<double>(pb, "xD");
-  p.colour_facets = ws_ptr<int32_t>(pb, "colour_facets");
+  p.colour_desc = ws_ptr<int32_t>(pb, "colour_desc");
   p.facet_vfree = ws_ptr<int32_t>(pb, "facet_vfree");
   p.vinc_off = ws_ptr<int32_t>(pb, "vinc_off");
   p.vinc = ws_ptr<int32_t>(pb, "vinc");
@@ -313,7 +313,20 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   HIPCHK(up(p.facet_el, pb->h_facet_el.data(), pb->h_facet_el.size() * 4));
   HIPCHK(up(p.facet_slot, pb->h_facet_slot.data(), pb->h_facet_slot.size() * 4));
   HIPCHK(up(p.facet_out, pb->h_facet_out.data(), pb->h_facet_out.size() * 4));
-  HIPCHK(up(p.colour_facets, pb->h_colour_facets.data(), pb->h_colour_facets.size() * 4));
+  {
+    // colour-ordered facet records, so that a smoother team finds both
+    // neighbours of its facet with one load
+    std::vector<int32_t> desc(pb->h_colour_facets.size() * 4);
+    for (size_t i = 0; i < pb->h_colour_facets.size(); ++i) {
+      const int32_t g = pb->h_colour_facets[i];
+      desc[4 * i] = g;
+      desc[4 * i + 1] = pb->h_facet_el[2 * g];
+      desc[4 * i + 2] = pb->h_facet_el[2 * g + 1];
+      desc[4 * i + 3] = (pb->h_facet_slot[2 * g] & 0xFF) | ((pb->h_facet_slot[2 * g + 1] & 0xFF) << 8);
+    }
+    HIPCHK(up(p.colour_desc, desc.data(), desc.size() * 4));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   HIPCHK(up(p.facet_vfree, pb->h_facet_vfree.data(), pb->h_facet_vfree.size() * 4));
   HIPCHK(up(p.vinc_off, pb->h_vinc_off.data(), pb->h_vinc_off.size() * 4));
   HIPCHK(up(p.vinc, pb->h_vinc.data(), pb->h_vinc.size() * 4));
@@ -852,7 +865,7 @@ int mcs_get_array(mcs_problem* pb, const char* name, void** ptr, int64_t* count)
   } table[] = {{"Ad", pb->ne * s.nd * s.nd},   {"H", pb->ne * s.nb * s.nd},
                {"Aoo", pb->ne * s.nb * s.nb},  {"Aooinv", pb->ne * s.nb * s.nb},  {"Dinv", pb->nff * s.nfb * s.nfb},
                {"EF", pb->nff * s.nfb * pb->d * pb->d}, {"Ad32", pb->ne * s.nd * s.nd}, {"H32", pb->ne * s.nb * s.nd},
-               {"detJ", pb->ne},               {"colour_facets", pb->nff},        {"elem_ff", pb->ne * (pb->d + 1)},
+               {"detJ", pb->ne},               {"colour_desc", pb->nff * 4},        {"elem_ff", pb->ne * (pb->d + 1)},
                {"W", pb->ne * (pb->d + 1) * pb->d * s.nd}, {"Cinv", pb->ncinv},
                {"mgA0", pb->mg[0].nvert * (pb->d == 3 ? 27 : 9) * pb->d * pb->d}};
   for (auto& e : table)

@@ -152,7 +152,9 @@ struct SolveParams {
   const int32_t* elem_ff;
   const int32_t* facet_el;
   const int32_t* facet_slot;
-  const int32_t* colour_facets;
+  // [nff][4] per colour position: facet g, neighbours e1, e2 (-1: none) and
+  // their local facet slots s1 | s2 << 8 (one 16-byte record)
+  const int32_t* colour_desc;
   const double* detJ;
   const double* nu;
   const double* rBp;

@@ -275,42 +275,34 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
   for (int64_t base = c0 + (int64_t)blockIdx.x * FPW; base < c1; base += (int64_t)gridDim.x * FPW) {
     const int64_t ci = base + h;
     bool work = ci < c1;
-    const int64_t g = work ? P.colour_facets[ci] : 0;
+    int4 dsc = {0, 0, 0, 0};
+    if (work) dsc = *reinterpret_cast<const int4*>(P.colour_desc + 4 * ci);
+    const int64_t g = dsc.x;
+    const int64_t e1 = dsc.y, e2 = dsc.z;
+    const int s1 = dsc.w & 0xFF, s2 = (dsc.w >> 8) & 0xFF;
     if (work && facet_off(P, g)) work = false;
     if (work && P.work_count && tid == 0) atomicAdd(P.work_count + (blockIdx.x & 255) * 16, 1ull);
-    int64_t e = 0;
+    const int64_t e = side ? e2 : e1;
+    const int sl = side ? s2 : s1;
     R a[NFB];
     R yv = R(0);
     // OUT: some facets are outlets with no second neighbour (-1); their
     // second-side rows stay idle
     bool row = work && is_row;
-    if constexpr (OUT) {
-      if (row) e = P.facet_el[2 * g + side];
-      row = row && e >= 0;
-      if (row) {
-        const int sl = P.facet_slot[2 * g + side];
-        const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
+    if constexpr (OUT) row = row && e >= 0;
+    if (row) {
+      const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
 #pragma unroll
-        for (int q = 0; q < NFB; ++q) a[q] = Ab[(size_t)q * nd];
-        yv = y[e * nd + t];
-      }
-    } else {
-      if (work && is_row) {
-        e = P.facet_el[2 * g + side];
-        const int sl = P.facet_slot[2 * g + side];
-        const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
-#pragma unroll
-        for (int q = 0; q < NFB; ++q) a[q] = Ab[(size_t)q * nd];
-        yv = y[e * nd + t];
-      }
+      for (int q = 0; q < NFB; ++q) a[q] = Ab[(size_t)q * nd];
+      yv = y[e * nd + t];
     }
     if (work) {
       const R* Di = O.Dinv + (size_t)g * NFB * NFB;
       for (int i = tid; i < NFB * NFB; i += T1) dsh[h][i] = Di[i];
     }
+    R xo = R(0);
     if (work && tid < NFB) {
-      const int64_t e1 = P.facet_el[2 * g], e2 = P.facet_el[2 * g + 1];
-      const int s1 = P.facet_slot[2 * g], s2 = P.facet_slot[2 * g + 1];
+      xo = x[P.off_f + g * NFB + tid];
       if constexpr (OUT) {
         R r = srhs[P.off_f + g * NFB + tid] - y[e1 * nd + s1 * NFB + tid];
         if (e2 >= 0) r -= y[e2 * nd + s2 * NFB + tid];
@@ -325,7 +317,7 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
 #pragma unroll
       for (int j = 0; j < NFB; ++j) acc += dsh[h][j * NFB + tid] * rr[h][j];
       dl[h][tid] = acc;
-      x[P.off_f + g * NFB + tid] += acc;
+      x[P.off_f + g * NFB + tid] = xo + acc;
     }
     __syncthreads();
     if (row) {

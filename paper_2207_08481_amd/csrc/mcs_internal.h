@@ -116,7 +116,7 @@ struct DevPtrs {
   int32_t* facet_out;     // [nff] 1 for an outlet facet
   double* xD;             // [ne][nd] Dirichlet dofs of the element's Dirichlet facets
   int32_t* facet_slot;    // [nff][2] local facet index in each neighbour
-  int32_t* colour_facets; // [nff] facets sorted by colour
+  int32_t* colour_desc;   // [nff][4] facets sorted by colour: g, e1, e2, s1 | s2 << 8
   int32_t* facet_vfree;   // [nff][d] free P1 vertex ids of the facet's sorted vertices (-1)
   int32_t* vinc_off;      // [nfv+1] free vertex -> incident (facet, slot) CSR
   int32_t* vinc;          // [ninc][2]

@@ -612,7 +612,7 @@ int layout_workspace(mcs_problem* pb) {
   L.add("elem_perm", I(ne));
   L.add("facet_el", I(nff * 2));
   L.add("facet_slot", I(nff * 2));
-  L.add("colour_facets", I(nff));
+  L.add("colour_desc", I(nff * 4));
   L.add("facet_out", I(nff));
   L.add("xD", Dd(ne * s.nd));
   L.add("facet_vfree", I(nff * d));

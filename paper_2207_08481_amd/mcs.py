@@ -338,7 +338,7 @@ class Problem:
         p = C.c_void_p()
         n = C.c_int64()
         _check(self._lib.mcs_get_array(self._h, name.encode(), C.byref(p), C.byref(n)))
-        if name in ("colour_facets", "elem_ff"):
+        if name in ("colour_desc", "elem_ff"):
             typestr = "<i4"
         elif name.endswith("32"):
             typestr = "<f4"
