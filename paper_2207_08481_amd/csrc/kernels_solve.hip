@@ -255,77 +255,98 @@ __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, co
 //   y_Ti += A^d_Ti[:, F] delta   (columns of F = rows of F, A^d symmetric).
 // A workgroup holds FPW facet teams of T1 = round_up(2 n_d, 64) threads; in a
 // team, threads [0, n_d) own the rows of the first neighbour and [n_d, 2 n_d)
-// those of the second; each thread loads its n_fb matrix entries before the
-// short dependent chain (residual -> D_F^{-1} -> update) starts.  Workgroups
-// loop over the colour's facets in steps of the grid, so the launch shape
-// (FPW, grid) changes only which team handles a facet, never the arithmetic.
+// those of the second.  Per facet one 16-byte record names both neighbours
+// (loaded one facet ahead); then every load of the facet is issued at once:
+// D_F^{-1} (at most NDV entries per thread, as T1 >= 2 n_d >= 6 n_fb) and the
+// facet's values first, the A^d rows last, so that the residual and
+// D_F^{-1} r_F are formed while the A^d rows are still in flight.  The loads
+// are unconditional, at clamped addresses inside the arrays (lanes without a
+// row, teams past the colour's end, the missing neighbour of an outlet facet),
+// so that the code stays straight and only the stores are predicated.  The
+// LDS buffers alternate between consecutive facets: two barriers per facet.
+// Workgroups loop over the colour's facets in steps of the grid, so the launch
+// shape (FPW, grid) changes only which team handles a facet, never the
+// arithmetic.
 template <typename R, int NFB, int FPW, bool OUT>
 __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, int32_t c0, int32_t c1,
                                                   R* __restrict__ x, const R* __restrict__ srhs, R* __restrict__ y,
                                                   int T1) {
+  constexpr int NDV = (NFB + 5) / 6;
   const int nd = P.s.nd;
-  __shared__ R rr[FPW][NFB];
-  __shared__ R dl[FPW][NFB];
-  __shared__ R dsh[FPW][NFB * NFB];
+  __shared__ R rr[2][FPW][NFB + 1];
+  __shared__ R dl[2][FPW][NFB];
+  // the last entry of rr and dsh takes the writes of lanes without an entry
+  __shared__ R dsh[2][FPW][NFB * NFB + 1];
   const int h = threadIdx.x / T1;
   const int tid = threadIdx.x - h * T1;
   const int side = tid >= nd ? 1 : 0;
-  const int t = tid - side * nd;
   const bool is_row = tid < 2 * nd;
-  for (int64_t base = c0 + (int64_t)blockIdx.x * FPW; base < c1; base += (int64_t)gridDim.x * FPW) {
+  const int t = is_row ? tid - side * nd : nd - 1;
+  const int tq = tid < NFB ? tid : NFB - 1;
+  int buf = 0;
+  const int64_t step = (int64_t)gridDim.x * FPW;
+  auto record = [&](int64_t ci) {
+    return *reinterpret_cast<const int4*>(P.colour_desc + 4 * (ci < c1 ? ci : (int64_t)c1 - 1));
+  };
+  // the record of a team's next facet is loaded one facet ahead
+  int4 next = record(c0 + (int64_t)blockIdx.x * FPW + h);
+  for (int64_t base = c0 + (int64_t)blockIdx.x * FPW; base < c1; base += step, buf ^= 1) {
     const int64_t ci = base + h;
     bool work = ci < c1;
-    int4 dsc = {0, 0, 0, 0};
-    if (work) dsc = *reinterpret_cast<const int4*>(P.colour_desc + 4 * ci);
+    const int4 dsc = next;
+    next = record(ci + step);
     const int64_t g = dsc.x;
-    const int64_t e1 = dsc.y, e2 = dsc.z;
-    const int s1 = dsc.w & 0xFF, s2 = (dsc.w >> 8) & 0xFF;
-    if (work && facet_off(P, g)) work = false;
+    const int64_t e1 = dsc.y;
+    const int s1 = dsc.w & 0xFF;
+    // OUT: an outlet facet has no second neighbour (-1); its second-side rows
+    // read the first neighbour's and store nothing
+    const bool has2 = !OUT || dsc.z >= 0;
+    const int64_t e2 = has2 ? (int64_t)dsc.z : e1;
+    const int s2 = has2 ? (dsc.w >> 8) & 0xFF : s1;
+    if (P.active && work && facet_off(P, g)) work = false;
     if (work && P.work_count && tid == 0) atomicAdd(P.work_count + (blockIdx.x & 255) * 16, 1ull);
     const int64_t e = side ? e2 : e1;
     const int sl = side ? s2 : s1;
-    R a[NFB];
-    R yv = R(0);
-    // OUT: some facets are outlets with no second neighbour (-1); their
-    // second-side rows stay idle
-    bool row = work && is_row;
-    if constexpr (OUT) row = row && e >= 0;
-    if (row) {
-      const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
+    R dv[NDV];
+    const R* Di = O.Dinv + (size_t)g * NFB * NFB;
 #pragma unroll
-      for (int q = 0; q < NFB; ++q) a[q] = Ab[(size_t)q * nd];
-      yv = y[e * nd + t];
+    for (int u = 0; u < NDV; ++u) {
+      const int i = tid + u * T1;
+      dv[u] = Di[i < NFB * NFB ? i : NFB * NFB - 1];
     }
-    if (work) {
-      const R* Di = O.Dinv + (size_t)g * NFB * NFB;
-      for (int i = tid; i < NFB * NFB; i += T1) dsh[h][i] = Di[i];
+    const int64_t fo = P.off_f + g * NFB + tq;
+    const R xo = x[fo];
+    const R sv = srhs[fo];
+    const R y1 = y[e1 * nd + s1 * NFB + tq];
+    const R y2 = y[e2 * nd + s2 * NFB + tq];
+    R yv = y[e * nd + t];
+    R a[NFB];
+    const R* Ab = O.Ad + (size_t)e * nd * nd + (size_t)sl * NFB * nd + t;
+#pragma unroll
+    for (int q = 0; q < NFB; ++q) a[q] = Ab[(size_t)q * nd];
+#pragma unroll
+    for (int u = 0; u < NDV; ++u) {
+      const int i = tid + u * T1;
+      dsh[buf][h][i < NFB * NFB ? i : NFB * NFB] = dv[u];
     }
-    R xo = R(0);
-    if (work && tid < NFB) {
-      xo = x[P.off_f + g * NFB + tid];
-      if constexpr (OUT) {
-        R r = srhs[P.off_f + g * NFB + tid] - y[e1 * nd + s1 * NFB + tid];
-        if (e2 >= 0) r -= y[e2 * nd + s2 * NFB + tid];
-        rr[h][tid] = r;
-      } else {
-        rr[h][tid] = srhs[P.off_f + g * NFB + tid] - y[e1 * nd + s1 * NFB + tid] - y[e2 * nd + s2 * NFB + tid];
-      }
-    }
+    rr[buf][h][tid < NFB ? tid : NFB] = has2 ? sv - y1 - y2 : sv - y1;
     __syncthreads();
-    if (work && tid < NFB) {
+    if (tid < NFB) {
       R acc = R(0);
 #pragma unroll
-      for (int j = 0; j < NFB; ++j) acc += dsh[h][j * NFB + tid] * rr[h][j];
-      dl[h][tid] = acc;
-      x[P.off_f + g * NFB + tid] = xo + acc;
+      for (int j = 0; j < NFB; ++j) acc += dsh[buf][h][j * NFB + tid] * rr[buf][h][j];
+      dl[buf][h][tid] = acc;
+      if (work) x[fo] = xo + acc;
     }
     __syncthreads();
-    if (row) {
+    if (work && is_row && (side == 0 || has2)) {
 #pragma unroll
-      for (int q = 0; q < NFB; ++q) yv += a[q] * dl[h][q];
+      for (int q = 0; q < NFB; ++q) yv += a[q] * dl[buf][h][q];
       y[e * nd + t] = yv;
     }
-    __syncthreads();
+    // no third barrier: the next facet works in the other buffers, and this
+    // one is written again only after the next facet's first barrier, which
+    // every wave reaches after its last read here
   }
 }
 
@@ -1039,21 +1060,27 @@ void launch_ext_post(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, c
 template <typename R, int NFB>
 static void smooth_launch(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
                           const R* s, R* y, int fpw, int64_t cap, int T1) {
+  // two teams per workgroup only for facet blocks up to 22 (LDS of the
+  // double-buffered D_F^{-1})
+  if constexpr (NFB > 22) fpw = 1;
   const int64_t blocks = std::min<int64_t>((c1 - c0 + fpw - 1) / fpw, cap);
-  if (P.has_outlet) {
-    if (fpw == 2)
-      hipLaunchKernelGGL((k_smooth_y<R, NFB, 2, true>), dim3((unsigned)blocks), dim3(2 * T1), 0, st, P, O, c0, c1, x, s,
-                         y, T1);
-    else
-      hipLaunchKernelGGL((k_smooth_y<R, NFB, 1, true>), dim3((unsigned)blocks), dim3(T1), 0, st, P, O, c0, c1, x, s, y,
-                         T1);
-  } else if (fpw == 2) {
-    hipLaunchKernelGGL((k_smooth_y<R, NFB, 2, false>), dim3((unsigned)blocks), dim3(2 * T1), 0, st, P, O, c0, c1, x, s,
-                       y, T1);
-  } else {
+  if constexpr (NFB <= 22) {
+    if (fpw == 2) {
+      if (P.has_outlet)
+        hipLaunchKernelGGL((k_smooth_y<R, NFB, 2, true>), dim3((unsigned)blocks), dim3(2 * T1), 0, st, P, O, c0, c1, x,
+                           s, y, T1);
+      else
+        hipLaunchKernelGGL((k_smooth_y<R, NFB, 2, false>), dim3((unsigned)blocks), dim3(2 * T1), 0, st, P, O, c0, c1,
+                           x, s, y, T1);
+      return;
+    }
+  }
+  if (P.has_outlet)
+    hipLaunchKernelGGL((k_smooth_y<R, NFB, 1, true>), dim3((unsigned)blocks), dim3(T1), 0, st, P, O, c0, c1, x, s, y,
+                       T1);
+  else
     hipLaunchKernelGGL((k_smooth_y<R, NFB, 1, false>), dim3((unsigned)blocks), dim3(T1), 0, st, P, O, c0, c1, x, s, y,
                        T1);
-  }
 }
 int smooth_team_threads(int nd) { return ((2 * nd + 63) / 64) * 64; }
 template <typename R>
