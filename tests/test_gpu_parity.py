@@ -130,6 +130,28 @@ def test_apply_operators(d, n, k):
     assert _rel(y32, K @ x) < 1e-5
 
 
+@pytest.mark.parametrize("k", [2, 3])
+def test_operator_apply_on_many_elements(k):
+    """K x on 750 tetrahedra with lognormal viscosity must equal the sum of
+    the separately applied pieces A u, B^T p and B u (launches with other
+    flags, pinned to the oracle on the small meshes above), FP64 and FP32."""
+    _need_gpu()
+    from paper_2207_08481_amd import Problem
+    mesh = W.unit_cube_mesh(5)
+    print(f"[case] K x pieces, n=5 k={k}", flush=True)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, k).bind("cuda:0")
+    pb.condense(torch.as_tensor(W.lognormal_nu(mesh.n_elements, seed=3), device="cuda:0"))
+    off_p = pb.info.off_pressure
+    x = torch.as_tensor(np.random.default_rng(11).standard_normal(pb.n_dof), device="cuda:0")
+    for xt, tol in ((x, 1e-13), (x.float(), 1e-5)):
+        y = pb.apply("K", xt).double().cpu().numpy()
+        yA = pb.apply("A", xt).double().cpu().numpy()
+        yBT = pb.apply("BT", xt).double().cpu().numpy()
+        yB = pb.apply("B", xt).double().cpu().numpy()
+        ref = np.concatenate([yA[:off_p] + yBT[:off_p], yB[off_p:]])
+        assert _rel(y, ref) < tol
+
+
 @pytest.mark.parametrize("d,n,k,cm", [(2, 2, 2, 512), (2, 4, 2, 20), (3, 2, 2, 512), (3, 1, 3, 512)])
 def test_preconditioner_pieces(d, n, k, cm):
     c = setup_case(d, n, k, coarse_max=cm)
