@@ -101,6 +101,26 @@ def device_copy_gbs(dev, mib=2048, reps=10):
     return 2 * n * 8 / (ms / 1e3) / 1e9
 
 
+def device_read_gbs(dev, mib=4096, reps=10):
+    """Bytes read per second by a plain device reduction (torch sum) over `mib`
+    MiB, outside the timed region: the practical rate of a read-only stream,
+    against which read-dominated kernels such as the colour phase can be set."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    a.sum()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        a.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a
+    return n * 8 / (ms / 1e3) / 1e9
+
+
 def cpu_baseline(seconds_hint=20.0):
     """Time the oracle (as it stands) on a bounded sample in a child process:
     the same cube recipe (k=3, nu=1, curl modes) on 3^3 x 6 tets, 40 MINRES
@@ -432,6 +452,7 @@ def main():
                      "p_max_abs": float(np.abs(p.cpu().numpy() - sol.p(X)).max())}
 
     copy_gbs = device_copy_gbs(dev)
+    read_gbs = device_read_gbs(dev)
     value = ndof * its / (t_sol / 1e3)
 
     def roof(kern, name, traffic):
@@ -446,7 +467,8 @@ def main():
                 # one call in `period` is timed: the kernel's share of the solve
                 # is estimated from the sampled calls scaled by the period
                 "est_share_of_t_sol": round(kms * period / t_sol, 4), "sample_period": period,
-                "device_copy_gbs": round(copy_gbs, 1), "frac_of_device_copy": round(achieved / copy_gbs, 4)}
+                "device_copy_gbs": round(copy_gbs, 1), "frac_of_device_copy": round(achieved / copy_gbs, 4),
+                "device_read_gbs": round(read_gbs, 1), "frac_of_device_read": round(achieved / read_gbs, 4)}
 
     kapply_name = "k_elem_apply (operator apply K x)"
     if smoother == 0:

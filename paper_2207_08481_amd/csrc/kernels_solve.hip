@@ -200,8 +200,11 @@ __global__ void k_facet_sum(SolveParams P, const R* __restrict__ escr, const R* 
 
 // A-hat_ext^{-1}, first part: escr_T = H_T^T r_o,T (threads [0, n_d), one
 // column of H_T each); t_o = Aoo^{-1} r_o (the following n_o threads, or the
-// first ones when n_d + n_o exceeds the block).
-template <typename R>
+// first ones when n_d + n_o exceeds the block).  NR > 0 (n_o <= NR and
+// n_d + n_o <= 256): every thread loads its n_o matrix entries at once, right
+// after r_o, before the barrier (loads past n_o repeat entry n_o - 1 and are
+// not used).
+template <typename R, int NR>
 __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, const R* __restrict__ r,
                                                  R* __restrict__ to, R* __restrict__ escr) {
   const Sizes s = P.s;
@@ -209,31 +212,57 @@ __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, con
   __shared__ R ro[MAXNB];
   const int tid = threadIdx.x;
   const int ob = (nd + nb <= 256) ? nd : 0;
+  const bool hcol = tid < nd, arow = tid >= ob && tid < ob + nb;
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     if (elem_off(P, e)) continue;
-    if (tid < nb) ro[tid] = r[e * nb + tid];
-    __syncthreads();
-    if (tid < nd) {
-      const R* H = O.H + (size_t)e * nb * nd + tid;
-      R acc = R(0);
+    if constexpr (NR > 0) {
+      R rv = R(0);
+      if (tid < nb) rv = r[e * nb + tid];
+      // column tid of H_T (threads < n_d) or row tid - ob of Aoo^{-1}
+      R a[NR];
+      if (hcol || arow) {
+        const R* m = hcol ? O.H + (size_t)e * nb * nd + tid : O.Aooinv + (size_t)e * nb * nb + (tid - ob);
+        const size_t st = hcol ? (size_t)nd : (size_t)nb;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) a[q] = m[(size_t)(q < nb ? q : nb - 1) * st];
+      }
+      if (tid < nb) ro[tid] = rv;
+      __syncthreads();
+      if (hcol || arow) {
+        R acc = R(0);
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+          if (q < nb) acc += a[q] * ro[q];
+        if (hcol) escr[e * nd + tid] = acc;
+        else to[e * nb + tid - ob] = acc;
+      }
+    } else {
+      if (tid < nb) ro[tid] = r[e * nb + tid];
+      __syncthreads();
+      if (hcol) {
+        const R* H = O.H + (size_t)e * nb * nd + tid;
+        R acc = R(0);
 #pragma unroll 4
-      for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd] * ro[i];
-      escr[e * nd + tid] = acc;
-    }
-    if (tid >= ob && tid < ob + nb) {
-      const int i = tid - ob;
-      const R* Ai = O.Aooinv + (size_t)e * nb * nb + i;
-      R acc = R(0);
+        for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd] * ro[i];
+        escr[e * nd + tid] = acc;
+      }
+      if (arow) {
+        const int i = tid - ob;
+        const R* Ai = O.Aooinv + (size_t)e * nb * nb + i;
+        R acc = R(0);
 #pragma unroll 4
-      for (int j = 0; j < nb; ++j) acc += Ai[(size_t)j * nb] * ro[j];
-      to[e * nb + i] = acc;
+        for (int j = 0; j < nb; ++j) acc += Ai[(size_t)j * nb] * ro[j];
+        to[e * nb + i] = acc;
+      }
     }
     __syncthreads();
   }
 }
 
 // A-hat_ext^{-1}, last part: y_o = t_o - H_T t_d,T (8-lane groups per row of H_T).
-template <typename R>
+// NC > 0 (n_d <= 8 NC, n_o <= 32): the 32 groups hold their row's entries
+// in registers, loaded after the facet ids and before the facet values.
+template <typename R, int NC>
 __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, const R* __restrict__ t,
                                                   const R* __restrict__ to, R* __restrict__ y) {
   const Sizes s = P.s;
@@ -241,10 +270,32 @@ __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, co
   __shared__ R td[MAXND];
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     if (elem_off(P, e)) continue;
-    gather_elem_d(P, t, e, td);
-    __syncthreads();
-    rows_times<8>(MatP<R>{O.H}, (size_t)e * nb * nd, nb, nd, td, 0, 256,
-                  [&](int i, R v) { y[e * nb + i] = to[e * nb + i] - v; });
+    if constexpr (NC > 0) {
+      const int g = threadIdx.x >> 3, l = threadIdx.x & 7;
+      const int row = g < nb ? g : nb - 1;
+      const R* h = O.H + (size_t)e * nb * nd + (size_t)row * nd;
+      R a[NC];
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
+        const int j = l + 8 * m;
+        a[m] = h[j < nd ? j : nd - 1];
+      }
+      gather_elem_d(P, t, e, td);
+      __syncthreads();
+      R acc = R(0);
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
+        const int j = l + 8 * m;
+        if (j < nd) acc += a[m] * td[j];
+      }
+      acc = group_sum<8>(acc);
+      if (l == 0 && g < nb) y[e * nb + g] = to[e * nb + g] - acc;
+    } else {
+      gather_elem_d(P, t, e, td);
+      __syncthreads();
+      rows_times<8>(MatP<R>{O.H}, (size_t)e * nb * nd, nb, nd, td, 0, 256,
+                    [&](int i, R v) { y[e * nb + i] = to[e * nb + i] - v; });
+    }
     __syncthreads();
   }
 }
@@ -1049,11 +1100,17 @@ void launch_facet_sum(hipStream_t st, const SolveParams& P, const R* escr, const
 }
 template <typename R>
 void launch_ext_pre(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* to, R* escr) {
-  hipLaunchKernelGGL(k_ext_pre<R>, dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, r, to, escr);
+  if (P.s.nb <= 24 && P.s.nd + P.s.nb <= 256)
+    hipLaunchKernelGGL((k_ext_pre<R, 24>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, r, to, escr);
+  else
+    hipLaunchKernelGGL((k_ext_pre<R, 0>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, r, to, escr);
 }
 template <typename R>
 void launch_ext_post(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* t, const R* to, R* y) {
-  hipLaunchKernelGGL(k_ext_post<R>, dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
+  if (P.s.nb <= 32 && P.s.nd <= 96)
+    hipLaunchKernelGGL((k_ext_post<R, 12>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
+  else
+    hipLaunchKernelGGL((k_ext_post<R, 0>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
 }
 // facets_per_block (1 or 2) and grid_cap choose the launch shape; every
 // shape gives the same result.
