@@ -151,6 +151,10 @@ struct Ctx {
   R* escr;
   R* fscr;
   int64_t n;
+  // device alias of the caller's pinned scalar (set by the solve driver): the
+  // final reduction of a dot product writes there directly, so that reading a
+  // scalar needs no copy launch
+  double* host_dev = nullptr;
   explicit Ctx(mcs_problem* p) : pb(p), st(p->stream), P(solve_params(p)), O(op_ptrs<R>(p)), L(mg_levels<R>(p)) {
     n = p->ndof;
     base = sizeof(R) == 8 ? reinterpret_cast<R*>(p->p.vec) - (int64_t)p->vbase64 * p->ndof
@@ -335,8 +339,12 @@ struct Ctx {
   }
 
   double dot(const R* a, const R* b, double* host) {
-    launch_dot<R>(st, n, a, b, pb->p.red, pb->p.scal);
-    hipMemcpyAsync(host, pb->p.scal, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (host_dev) {
+      launch_dot<R>(st, n, a, b, pb->p.red, host_dev);
+    } else {
+      launch_dot<R>(st, n, a, b, pb->p.red, pb->p.scal);
+      hipMemcpyAsync(host, pb->p.scal, sizeof(double), hipMemcpyDeviceToHost, st);
+    }
     hipStreamSynchronize(st);
     timer_flush(pb);
     return *host;

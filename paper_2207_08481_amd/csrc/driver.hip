@@ -753,11 +753,14 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
     HIPCHK(hipHostMalloc((void**)&pin.p, 64));
   }
   double* host = pin.p;
+  double* host_dev = nullptr;
+  HIPCHK(hipHostGetDevicePointer((void**)&host_dev, host, 0));
   hipStream_t st = pb->stream;
   const int64_t n = pb->ndof;
   mcs_solve_info inf{};
   auto t0 = std::chrono::steady_clock::now();
   Ctx<double> c64(pb);
+  c64.host_dev = host_dev;
   if (pb->opt.precision == 0) {
     int its = 0;
     double rel = 0, b1 = 0;
@@ -767,6 +770,7 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
     inf.rel_precond_residual = rel;
   } else {
     Ctx<float> c32(pb);
+    c32.host_dev = host_dev;
     double* r64 = c64.v(VR64);
     float* r32 = c32.v(VB64);   // slot beyond the FP32 MINRES vectors
     float* d32 = c32.v(VX64);

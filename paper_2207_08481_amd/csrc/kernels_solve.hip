@@ -111,8 +111,10 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
     if (elem_off(P, e)) continue;
     const double det = P.detJ[e];
     const double sb = -fabs(det), sf = det > 0 ? -1.0 : 1.0;
-    gather_elem_d(P, x, e, xd);
-    if (tid < nb) xo[tid] = x[e * nb + tid];
+    if (doA || doBu) {   // B^T p alone needs only the pressure values
+      gather_elem_d(P, x, e, xd);
+      if (tid < nb) xo[tid] = x[e * nb + tid];
+    }
     if (tid < np) xp[tid] = x[P.off_p + e * np + tid];
     __syncthreads();
     const size_t h0 = (size_t)e * nb * nd;
@@ -423,10 +425,10 @@ __global__ void k_block_jacobi(SolveParams P, OpPtrs<R> O, const R* __restrict__
 // c_T the P1 coarse correction at the element's vertices (lattice vector; the
 // Dirichlet vertices carry no value and are skipped, their lattice entries are
 // never written): keeps y_T = A^d_T x_T after x += E^d c.
-template <typename R>
+template <typename R, int D>
 __global__ void k_elem_ycorr(SolveParams P, const R* __restrict__ W, const int32_t* __restrict__ elem_verts,
                              const int32_t* __restrict__ vfree_of_lat, const R* __restrict__ x0, R* __restrict__ y) {
-  const int d = P.s.d, nv = d + 1, nvd = nv * d, nd = P.s.nd;
+  const int d = D > 0 ? D : P.s.d, nv = d + 1, nvd = nv * d, nd = P.s.nd;
   const int64_t n = P.ne * nd;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = idx / nd;
@@ -434,17 +436,32 @@ __global__ void k_elem_ycorr(SolveParams P, const R* __restrict__ W, const int32
     const int t = (int)(idx % nd);
     const R* We = W + (size_t)e * nvd * nd + t;
     R acc = R(0);
-    for (int vl = 0; vl < nv; ++vl) {
-      const int64_t v = elem_verts[e * nv + vl];
-      if (vfree_of_lat[v] < 0) continue;
-      for (int c = 0; c < d; ++c) acc += We[(size_t)(vl * d + c) * nd] * x0[v * d + c];
+    if constexpr (D > 0) {
+      // the (d+1) d entries of the row first, then the vertex ids
+      R wv[(D + 1) * D];
+#pragma unroll
+      for (int i = 0; i < (D + 1) * D; ++i) wv[i] = We[(size_t)i * nd];
+#pragma unroll
+      for (int vl = 0; vl < D + 1; ++vl) {
+        const int64_t v = elem_verts[e * (D + 1) + vl];
+        if (vfree_of_lat[v] < 0) continue;
+#pragma unroll
+        for (int c = 0; c < D; ++c) acc += wv[vl * D + c] * x0[v * D + c];
+      }
+    } else {
+      for (int vl = 0; vl < nv; ++vl) {
+        const int64_t v = elem_verts[e * nv + vl];
+        if (vfree_of_lat[v] < 0) continue;
+        for (int c = 0; c < d; ++c) acc += We[(size_t)(vl * d + c) * nd] * x0[v * d + c];
+      }
     }
     y[idx] += acc;
   }
 }
 
-// E^d^T, facet part: fscr[g][v*d + c] = sum_q EF[g][q][v*d+c] r_F[q].
-template <typename R>
+// E^d^T, facet part: fscr[g][v*d + c] = sum_q EF[g][q][v*d+c] r_F[q].  NFB > 0
+// (= n_fb): a thread's n_fb entries and block values are loaded at once.
+template <typename R, int NFB>
 __global__ void k_edt_facet(SolveParams P, OpPtrs<R> O, const R* __restrict__ r, R* __restrict__ fscr) {
   const Sizes s = P.s;
   const int dd = s.d * s.d;
@@ -456,7 +473,18 @@ __global__ void k_edt_facet(SolveParams P, OpPtrs<R> O, const R* __restrict__ r,
     const R* E = O.EF + (size_t)g * s.nfb * dd + t;
     const R* rf = r + P.off_f + g * s.nfb;
     R acc = 0;
-    for (int q = 0; q < s.nfb; ++q) acc += E[(size_t)q * dd] * rf[q];
+    if constexpr (NFB > 0) {
+      R ev[NFB], rv[NFB];
+#pragma unroll
+      for (int q = 0; q < NFB; ++q) {
+        ev[q] = E[(size_t)q * dd];
+        rv[q] = rf[q];
+      }
+#pragma unroll
+      for (int q = 0; q < NFB; ++q) acc += ev[q] * rv[q];
+    } else {
+      for (int q = 0; q < s.nfb; ++q) acc += E[(size_t)q * dd] * rf[q];
+    }
     fscr[idx] = acc;
   }
 }
@@ -482,12 +510,13 @@ __global__ void k_edt_vertex(int d, int64_t nfv, const int32_t* __restrict__ vin
 }
 
 // E^d: y_F (+)= sum_{v,c} EF[g][q][v*d+c] x[v][c]  (x lattice-indexed or compact).
-template <typename R>
+// D > 0 (= d): the row of EF is loaded before the vertex ids.
+template <typename R, int D>
 __global__ void k_ed_facet(SolveParams P, OpPtrs<R> O, const int32_t* __restrict__ facet_vfree,
                            const int32_t* __restrict__ free_to_lat, const R* __restrict__ x0, R* __restrict__ y,
                            int add, int compact) {
   const Sizes s = P.s;
-  const int d = s.d, dd = d * d;
+  const int d = D > 0 ? D : s.d, dd = d * d;
   const int64_t n = P.nff * s.nfb;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t g = idx / s.nfb;
@@ -495,11 +524,25 @@ __global__ void k_ed_facet(SolveParams P, OpPtrs<R> O, const int32_t* __restrict
     int q = (int)(idx % s.nfb);
     const R* E = O.EF + ((size_t)g * s.nfb + q) * dd;
     R acc = 0;
-    for (int v = 0; v < d; ++v) {
-      int fv = facet_vfree[g * d + v];
-      if (fv < 0) continue;
-      int64_t base = compact ? (int64_t)fv * d : (int64_t)free_to_lat[fv] * d;
-      for (int c = 0; c < d; ++c) acc += E[v * d + c] * x0[base + c];
+    if constexpr (D > 0) {
+      R ev[D * D];
+#pragma unroll
+      for (int i = 0; i < D * D; ++i) ev[i] = E[i];
+#pragma unroll
+      for (int v = 0; v < D; ++v) {
+        const int fv = facet_vfree[g * D + v];
+        if (fv < 0) continue;
+        const int64_t base = compact ? (int64_t)fv * D : (int64_t)free_to_lat[fv] * D;
+#pragma unroll
+        for (int c = 0; c < D; ++c) acc += ev[v * D + c] * x0[base + c];
+      }
+    } else {
+      for (int v = 0; v < d; ++v) {
+        int fv = facet_vfree[g * d + v];
+        if (fv < 0) continue;
+        int64_t base = compact ? (int64_t)fv * d : (int64_t)free_to_lat[fv] * d;
+        for (int c = 0; c < d; ++c) acc += E[v * d + c] * x0[base + c];
+      }
     }
     if (add) y[P.off_f + idx] += acc;
     else y[P.off_f + idx] = acc;
@@ -1166,21 +1209,33 @@ void launch_block_jacobi(hipStream_t st, const SolveParams& P, const OpPtrs<R>& 
 template <typename R>
 void launch_ycorr(hipStream_t st, const SolveParams& P, const R* W, const int32_t* elem_verts,
                   const int32_t* vfree_of_lat, const R* x0, R* y) {
-  hipLaunchKernelGGL(k_elem_ycorr<R>, dim3(grid_for(P.ne * P.s.nd)), dim3(256), 0, st, P, W, elem_verts, vfree_of_lat,
-                     x0, y);
+  const dim3 ge(grid_for(P.ne * P.s.nd)), be(256);
+  if (P.s.d == 3)
+    hipLaunchKernelGGL((k_elem_ycorr<R, 3>), ge, be, 0, st, P, W, elem_verts, vfree_of_lat, x0, y);
+  else
+    hipLaunchKernelGGL((k_elem_ycorr<R, 0>), ge, be, 0, st, P, W, elem_verts, vfree_of_lat, x0, y);
 }
 template <typename R>
 void launch_edt(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* fscr, int64_t nfv,
                 const int32_t* vinc_off, const int32_t* vinc, const int32_t* free_to_lat, R* b, int compact) {
-  hipLaunchKernelGGL(k_edt_facet<R>, dim3(grid_for(P.nff * P.s.d * P.s.d)), dim3(256), 0, st, P, O, r, fscr);
+  const dim3 ge(grid_for(P.nff * P.s.d * P.s.d)), be(256);
+  switch (P.s.nfb) {
+    case 12: hipLaunchKernelGGL((k_edt_facet<R, 12>), ge, be, 0, st, P, O, r, fscr); break;
+    case 22: hipLaunchKernelGGL((k_edt_facet<R, 22>), ge, be, 0, st, P, O, r, fscr); break;
+    case 35: hipLaunchKernelGGL((k_edt_facet<R, 35>), ge, be, 0, st, P, O, r, fscr); break;
+    default: hipLaunchKernelGGL((k_edt_facet<R, 0>), ge, be, 0, st, P, O, r, fscr); break;
+  }
   hipLaunchKernelGGL(k_edt_vertex<R>, dim3(grid_for(nfv * P.s.d)), dim3(256), 0, st, P.s.d, nfv, vinc_off, vinc,
                      free_to_lat, (const R*)fscr, b, compact);
 }
 template <typename R>
 void launch_ed(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const int32_t* facet_vfree,
                const int32_t* free_to_lat, const R* x0, R* y, int add, int compact) {
-  hipLaunchKernelGGL(k_ed_facet<R>, dim3(grid_for(P.nff * P.s.nfb)), dim3(256), 0, st, P, O, facet_vfree, free_to_lat,
-                     x0, y, add, compact);
+  const dim3 ge(grid_for(P.nff * P.s.nfb)), be(256);
+  if (P.s.d == 3)
+    hipLaunchKernelGGL((k_ed_facet<R, 3>), ge, be, 0, st, P, O, facet_vfree, free_to_lat, x0, y, add, compact);
+  else
+    hipLaunchKernelGGL((k_ed_facet<R, 0>), ge, be, 0, st, P, O, facet_vfree, free_to_lat, x0, y, add, compact);
 }
 static unsigned mg_grid(int64_t n, int per) {
   int64_t g = (n + per - 1) / per;
