@@ -126,7 +126,11 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
         for (int j = 0; j < nd; ++j) acc += MAd(a0 + (size_t)j * nd) * xd[j];
       }
     } else if (doH && overlap && tid >= tA) {
-      rows_times<16>(MH, h0, nb, nd, xd, tA, 256 - tA, [&](int i, R v) { zo[i] = xo[i] + v; });
+      // one wave left for H (n_d > 128): 4-lane groups, 16 rows at a time
+      if (256 - tA >= 128)
+        rows_times<16>(MH, h0, nb, nd, xd, tA, 256 - tA, [&](int i, R v) { zo[i] = xo[i] + v; });
+      else
+        rows_times<4>(MH, h0, nb, nd, xd, tA, 256 - tA, [&](int i, R v) { zo[i] = xo[i] + v; });
     }
     if (doBu) {
       for (int row = tid; row < nb + nd; row += blockDim.x) {
@@ -244,7 +248,7 @@ __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, con
       if (hcol) {
         const R* H = O.H + (size_t)e * nb * nd + tid;
         R acc = R(0);
-#pragma unroll 4
+#pragma unroll 8
         for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd] * ro[i];
         escr[e * nd + tid] = acc;
       }
@@ -252,7 +256,7 @@ __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, con
         const int i = tid - ob;
         const R* Ai = O.Aooinv + (size_t)e * nb * nb + i;
         R acc = R(0);
-#pragma unroll 4
+#pragma unroll 8
         for (int j = 0; j < nb; ++j) acc += Ai[(size_t)j * nb] * ro[j];
         to[e * nb + i] = acc;
       }
