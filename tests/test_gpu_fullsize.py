@@ -1,0 +1,150 @@
+"""GPU parity at the benchmark sizes, on sampled outputs the oracle computes
+element by element.
+
+16^3 x 6 tets, k = 3, nu = 1, curl-mode force, FP64 (the default bench
+workload) and 32^3 x 6 tets, k = 4, lognormal nu, random force (the mixed
+precision workload; operators only, FP64 and FP32 storage).  The GPU runs in
+the same launch configuration as the bench (whole mesh, autotuned smoother).
+For seeded samples of elements (always including the first and the last one):
+
+* A^d_T, H_T, A_oo,T against the oracle's element system (1e-10 relative);
+* the bubble rows of the load vector (1e-12);
+* the bubble and pressure rows of K x for a random x: these rows involve only
+  the element's own dofs, so the oracle forms them from its element matrices
+  (1e-12 FP64, 1e-5 FP32);
+* after the full solve (16^3 only), the bubble and pressure rows of the
+  residual b - K x at the sampled elements, formed by the oracle from the GPU
+  solution: below 1e-8 ||b||_2 (the solve reaches about 3e-10 ||b||_2 in the
+  2-norm of the whole residual; the pressure rows are the divergence of u_h).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle_elements(mesh, k, nu, f, sample):
+    """Oracle element systems and global dof maps of the sampled elements."""
+    from oracle.element import element_geometry, element_system, expected_dims
+    from oracle.system import _lattice_indices
+    from oracle.topology import Topology
+    topo = Topology(mesh.vertices, mesh.elements)
+    d = topo.dim
+    dims = expected_dims(d, k)
+    nb, nfb, npr = dims["n_bub"], dims["n_fb"], dims["n_p"]
+    ne = mesh.n_elements
+    off_f = ne * nb
+    off_p = off_f + topo.n_free_facets * nfb
+    lat = _lattice_indices(d, k + 1)
+    out = []
+    for e in sample:
+        ed = element_geometry(topo.element_coords(e), k)
+        es = element_system(ed, float(nu[e]), k, np.asarray(f[e], dtype=np.float64), lat[:, topo.perm[e]], k + 1)
+        ld = list(range(e * nb, (e + 1) * nb))
+        for i in range(d + 1):
+            g = topo.free_facet_of[topo.elem_facets[e, i]]
+            ld += [-1] * nfb if g < 0 else list(range(off_f + g * nfb, off_f + (g + 1) * nfb))
+        perm = es["perm"]
+        inv = np.empty(len(perm), dtype=np.int64)
+        inv[perm] = np.arange(len(perm))
+        Bl = np.zeros((npr, len(ld)))
+        Bl[:, inv[: dims["n_u"]]] = es["B"]
+        F = np.zeros(len(ld))
+        F[inv[: dims["n_u"]]] = es["F"]
+        out.append(dict(e=e, es=es, ld=np.asarray(ld), pd=np.arange(off_p + e * npr, off_p + (e + 1) * npr),
+                        A=es["A"][np.ix_(perm, perm)], Bl=Bl, F=F))
+    return out, dims
+
+
+def _sample(ne, n, seed):
+    rng = np.random.default_rng(seed)
+    return sorted(set([0, ne - 1] + list(rng.choice(ne, n, replace=False))))
+
+
+def _local(x, ld):
+    v = np.zeros(len(ld))
+    m = ld >= 0
+    v[m] = x[ld[m]]
+    return v
+
+
+def _check_elements(pb, elems, dims):
+    nb = dims["n_bub"]
+    nd = len(elems[0]["ld"]) - nb
+    Ad = pb.get_array("Ad").cpu().numpy().reshape(-1, nd, nd)
+    H = pb.get_array("H").cpu().numpy().reshape(-1, nb, nd)
+    Aoo = pb.get_array("Aoo").cpu().numpy().reshape(-1, nb, nb)
+    for it in elems:
+        e, es = it["e"], it["es"]
+        assert np.abs(Ad[e] - es["Ad"]).max() < 1e-10 * np.abs(es["Ad"]).max(), e
+        assert np.abs(Aoo[e] - es["Aoo"]).max() < 1e-10 * np.abs(es["Aoo"]).max(), e
+        assert np.abs(H[e] - es["H"]).max() < 1e-9 * max(np.abs(es["H"]).max(), 1e-30), e
+
+
+def _check_apply(pb, elems, nb, precision_tol, dt):
+    x = np.random.default_rng(21).standard_normal(pb.n_dof)
+    y = pb.apply("K", torch.as_tensor(x, device="cuda:0").to(dt)).double().cpu().numpy()
+    for it in elems:
+        xl = _local(x, it["ld"])
+        xp = x[it["pd"]]
+        ref_o = (it["A"] @ xl + it["Bl"].T @ xp)[:nb]
+        ref_p = it["Bl"] @ xl
+        scale_o = np.abs(it["A"][:nb]).sum(axis=1).max() * np.abs(x).max()
+        scale_p = np.abs(it["Bl"]).sum(axis=1).max() * np.abs(x).max()
+        eo = it["ld"][:nb]
+        assert np.abs(y[eo] - ref_o).max() < precision_tol * scale_o, it["e"]
+        assert np.abs(y[it["pd"]] - ref_p).max() < precision_tol * scale_p, it["e"]
+
+
+def test_cube16_k3_sampled_elements_apply_and_solve():
+    _need_gpu()
+    from paper_2207_08481_amd import Problem
+    wl = W.workload("cube16_k3")
+    mesh, k, nu, f = wl["mesh"], wl["k"], wl["nu"], wl["f_lattice"]
+    print(f"[case] 16^3 x 6 tets, k={k}, FP64", flush=True)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, k).bind("cuda:0")
+    pb.condense(torch.as_tensor(nu, device="cuda:0"))
+    elems, dims = _oracle_elements(mesh, k, nu, f, _sample(mesh.n_elements, 6, 31))
+    nb = dims["n_bub"]
+    _check_elements(pb, elems, dims)
+    b = pb.load(torch.as_tensor(f, device="cuda:0")).cpu().numpy()
+    for it in elems:
+        ref = it["F"][:nb]
+        assert np.abs(b[it["ld"][:nb]] - ref).max() < 1e-12 * max(np.abs(ref).max(), 1e-300), it["e"]
+    _check_apply(pb, elems, nb, 1e-12, torch.float64)
+    x, si = pb.solve(torch.as_tensor(f, device="cuda:0"))
+    assert si["status"] == 0
+    x = x.cpu().numpy()
+    bn = np.linalg.norm(b)
+    for it in elems:
+        xl = _local(x, it["ld"])
+        r_o = it["F"][:nb] - (it["A"] @ xl)[:nb] - (it["Bl"].T @ x[it["pd"]])[:nb]
+        r_p = -(it["Bl"] @ xl)
+        assert np.abs(r_o).max() < 1e-8 * bn, it["e"]
+        assert np.abs(r_p).max() < 1e-8 * bn, it["e"]
+
+
+def test_cube32_k4_sampled_elements_and_apply():
+    _need_gpu()
+    from paper_2207_08481_amd import Problem
+    wl = W.workload("cube32_k4_lognormal")
+    mesh, k, nu, f = wl["mesh"], wl["k"], wl["nu"], wl["f_lattice"]
+    print(f"[case] 32^3 x 6 tets, k={k}, FP64 operators and FP32 copies", flush=True)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, k).bind("cuda:0")
+    pb.condense(torch.as_tensor(nu, device="cuda:0"))
+    elems, dims = _oracle_elements(mesh, k, nu, f, _sample(mesh.n_elements, 4, 32))
+    nb = dims["n_bub"]
+    _check_elements(pb, elems, dims)
+    _check_apply(pb, elems, nb, 1e-12, torch.float64)
+    _check_apply(pb, elems, nb, 1e-5, torch.float32)
+    del pb
+    torch.cuda.empty_cache()
