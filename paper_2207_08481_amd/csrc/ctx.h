@@ -51,12 +51,12 @@ OpPtrs<R> op_ptrs(mcs_problem* pb);
 template <>
 inline OpPtrs<double> op_ptrs<double>(mcs_problem* pb) {
   return {pb->p.Ad, pb->p.H, pb->p.Aoo, pb->p.Aooinv, pb->p.Dinv, pb->p.EF, pb->p.W,
-          pb->p.Ad32, pb->p.Adl, pb->p.H32, pb->p.Hl, pb->p.Aoo32, pb->p.Aool};
+          pb->p.Ad32, pb->p.Adl, pb->p.H32, pb->p.Hl, pb->p.Aoo32, pb->p.Aool, pb->p.DinvP};
 }
 template <>
 inline OpPtrs<float> op_ptrs<float>(mcs_problem* pb) {
   return {pb->p.Ad32, pb->p.H32, pb->p.Aoo32, pb->p.Aooinv32, pb->p.Dinv32, pb->p.EF32, pb->p.W32,
-          nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+          nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, pb->p.DinvP32};
 }
 
 template <typename R>
@@ -90,11 +90,12 @@ std::vector<MGLevelDev> mg_levels(mcs_problem* pb) {
 
 // Algorithmic HBM bytes of one facet block of the smoother kernel with
 // words of wsize bytes: the facet's rows of A^d_T of both neighbours
-// (2 n_fb n_d), D_F^{-1} (n_fb^2), the right-hand side and the updated block
-// (3 n_fb), the neighbours' maintained products read and written (4 n_d),
-// two more block reads (2 n_fb) and six index words.
+// (2 n_fb n_d), the packed upper triangle of D_F^{-1} (n_fb (n_fb + 1) / 2),
+// the right-hand side and the updated block (3 n_fb), the neighbours'
+// maintained products read and written (4 n_d), two more block reads
+// (2 n_fb) and the 16-byte facet record.
 inline double smooth_bytes_per_facet(const Sizes& z, int wsize) {
-  return double(2 * z.nfb * z.nd + z.nfb * z.nfb + 4 * z.nd + 5 * z.nfb) * wsize + 6.0 * 4.0;
+  return double(2 * z.nfb * z.nd + z.nfb * (z.nfb + 1) / 2 + 4 * z.nd + 5 * z.nfb) * wsize + 16.0;
 }
 // device counters of processed facet blocks: 256 counters (stride 16) for
 // FP64 launches, then 256 for FP32 launches

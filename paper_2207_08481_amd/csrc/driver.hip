@@ -269,6 +269,8 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   p.Dinv = ws_ptr<double>(pb, "Dinv");
   p.EF = ws_ptr<double>(pb, "EF");
   p.Dinv32 = ws_ptr<float>(pb, "Dinv32");
+  p.DinvP = ws_ptr<double>(pb, "DinvP");
+  p.DinvP32 = ws_ptr<float>(pb, "DinvP32");
   p.EF32 = ws_ptr<float>(pb, "EF32");
   p.W = ws_ptr<double>(pb, "W");
   p.W32 = ws_ptr<float>(pb, "W32");
@@ -466,6 +468,8 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   F.rct = p.rct;
   F.Dinv = p.Dinv;
   F.Dinv32 = p.Dinv32;
+  F.DinvP = p.DinvP;
+  F.DinvP32 = p.DinvP32;
   F.EF = p.EF;
   F.EF32 = p.EF32;
   F.status = status;

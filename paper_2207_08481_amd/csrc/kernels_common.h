@@ -66,6 +66,8 @@ struct FacetSetupParams {
   const int32_t* facet_out;      // 1: outlet facet (pi_0: no tangential rows in E)
   double* Dinv;
   float* Dinv32;
+  double* DinvP;                 // upper triangles packed row by row (or nullptr)
+  float* DinvP32;
   double* EF;
   float* EF32;
   int* status;
@@ -205,6 +207,9 @@ struct OpPtrs {
   const R *Ad, *H, *Aoo, *Aooinv, *Dinv, *EF, *W;
   // split storage of A^d, H, A_oo (R = double with Ad == nullptr)
   const float *hAd, *lAd, *hH, *lH, *hAoo, *lAoo;
+  // D_F^{-1} (symmetric) as packed upper triangles: entry (i, j), i <= j, at
+  // i n_fb - i (i - 1) / 2 + j - i of the facet's n_fb (n_fb + 1) / 2 words
+  const R* DinvP;
 };
 
 // Matrix entry accessors: plain arrays, or FP64 values kept as FP32 hi + lo.

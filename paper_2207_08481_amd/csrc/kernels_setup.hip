@@ -595,6 +595,11 @@ __global__ void __launch_bounds__(256) k_facet_setup(FacetSetupParams P) {
       for (int p = p0; p < nfb; ++p) t += W[p * FLD + i] * W[p * FLD + j];
       if (P.Dinv) P.Dinv[(size_t)g * nfb * nfb + idx] = t;
       P.Dinv32[(size_t)g * nfb * nfb + idx] = (float)t;
+      if (i <= j) {   // the same sum for (i, j) and (j, i): the matrix is exactly symmetric
+        const size_t pk = (size_t)g * (nfb * (nfb + 1) / 2) + i * nfb - i * (i - 1) / 2 + (j - i);
+        if (P.DinvP) P.DinvP[pk] = t;
+        if (P.DinvP32) P.DinvP32[pk] = (float)t;
+      }
     }
     // facet geometry from the first neighbour's sorted vertices
     if (threadIdx.x == 0) {

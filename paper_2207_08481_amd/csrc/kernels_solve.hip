@@ -314,8 +314,9 @@ __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, co
 // team, threads [0, n_d) own the rows of the first neighbour and [n_d, 2 n_d)
 // those of the second.  Per facet one 16-byte record names both neighbours
 // (loaded one facet ahead); then every load of the facet is issued at once:
-// D_F^{-1} (at most NDV entries per thread, as T1 >= 2 n_d >= 6 n_fb) and the
-// facet's values first, the A^d rows last, so that the residual and
+// D_F^{-1} (its packed upper triangle of NP words, at most NDV per thread as
+// T1 >= 2 n_d >= 6 n_fb, copied to LDS as it is) and the facet's values
+// first, the A^d rows last, so that the residual and
 // D_F^{-1} r_F are formed while the A^d rows are still in flight.  The loads
 // are unconditional, at clamped addresses inside the arrays (lanes without a
 // row, teams past the colour's end, the missing neighbour of an outlet facet),
@@ -328,12 +329,13 @@ template <typename R, int NFB, int FPW, bool OUT>
 __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, int32_t c0, int32_t c1,
                                                   R* __restrict__ x, const R* __restrict__ srhs, R* __restrict__ y,
                                                   int T1) {
-  constexpr int NDV = (NFB + 5) / 6;
+  constexpr int NP = NFB * (NFB + 1) / 2;
+  constexpr int NDV = (NP + 6 * NFB - 1) / (6 * NFB);
   const int nd = P.s.nd;
   __shared__ R rr[2][FPW][NFB + 1];
   __shared__ R dl[2][FPW][NFB];
   // the last entry of rr and dsh takes the writes of lanes without an entry
-  __shared__ R dsh[2][FPW][NFB * NFB + 1];
+  __shared__ R dsh[2][FPW][NP + 1];
   const int h = threadIdx.x / T1;
   const int tid = threadIdx.x - h * T1;
   const int side = tid >= nd ? 1 : 0;
@@ -365,11 +367,11 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
     const int64_t e = side ? e2 : e1;
     const int sl = side ? s2 : s1;
     R dv[NDV];
-    const R* Di = O.Dinv + (size_t)g * NFB * NFB;
+    const R* Di = O.DinvP + (size_t)g * NP;
 #pragma unroll
     for (int u = 0; u < NDV; ++u) {
       const int i = tid + u * T1;
-      dv[u] = Di[i < NFB * NFB ? i : NFB * NFB - 1];
+      dv[u] = Di[i < NP ? i : NP - 1];
     }
     const int64_t fo = P.off_f + g * NFB + tq;
     const R xo = x[fo];
@@ -384,14 +386,19 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
 #pragma unroll
     for (int u = 0; u < NDV; ++u) {
       const int i = tid + u * T1;
-      dsh[buf][h][i < NFB * NFB ? i : NFB * NFB] = dv[u];
+      dsh[buf][h][i < NP ? i : NP] = dv[u];
     }
     rr[buf][h][tid < NFB ? tid : NFB] = has2 ? sv - y1 - y2 : sv - y1;
     __syncthreads();
     if (tid < NFB) {
+      // row tid of D_F^{-1}: (j, tid) from row j's triangle for j < tid, else (tid, j)
+      const int rb = tid * NFB - tid * (tid - 1) / 2 - tid;
       R acc = R(0);
 #pragma unroll
-      for (int j = 0; j < NFB; ++j) acc += dsh[buf][h][j * NFB + tid] * rr[buf][h][j];
+      for (int j = 0; j < NFB; ++j) {
+        const int pk = j < tid ? j * NFB - j * (j - 1) / 2 - j + tid : rb + j;
+        acc += dsh[buf][h][pk] * rr[buf][h][j];
+      }
       dl[buf][h][tid] = acc;
       if (work) x[fo] = xo + acc;
     }

@@ -134,6 +134,8 @@ struct DevPtrs {
   float *Ad32, *H32, *Aoo32, *Aooinv32;
   double *Dinv, *EF, *W;
   float *Dinv32, *EF32, *W32;
+  double* DinvP;            // D_F^{-1} upper triangles, row-major packed (colour phases)
+  float* DinvP32;
   float *Adl, *Hl, *Aool;   // low parts of the split storage (lean layout)
   double* adtmp;            // per-slot FP64 A^d buffer of the condensation (lean layout)
   // multigrid coarsest

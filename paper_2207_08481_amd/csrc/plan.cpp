@@ -664,9 +664,11 @@ int layout_workspace(mcs_problem* pb) {
     L.add("Aool", Ff(ne * s.nb * s.nb));
   } else {
     L.add("Dinv", Dd(nff * s.nfb * s.nfb));
+    L.add("DinvP", Dd(nff * s.nfb * (s.nfb + 1) / 2));
   }
   L.add("EF", Dd(nff * s.nfb * d * d));
   L.add("Dinv32", Ff(nff * s.nfb * s.nfb));
+  L.add("DinvP32", Ff(nff * s.nfb * (s.nfb + 1) / 2));
   L.add("EF32", Ff(nff * s.nfb * d * d));
   if (!pb->lean) L.add("W", Dd(ne * (d + 1) * d * s.nd));
   L.add("W32", Ff(ne * (d + 1) * d * s.nd));
