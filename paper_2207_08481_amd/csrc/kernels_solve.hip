@@ -572,9 +572,9 @@ __device__ inline void mg_coords(int64_t v, const int* n, int c[3]) {
 // blockIdx.y; vertex indices are block-local plus the block's offset.
 // mode 0: x = Dinv b;  mode 1: r = b - A x;  mode 2: x += Dinv (b - A x), on
 // the continuing blocks.  One 32-lane group per vertex, one stencil tap per lane.
-template <typename R>
-__global__ void __launch_bounds__(256) k_mg_point(int d, MGLevelDev L, int mode) {
-  const int st = d == 3 ? 27 : 9, dd = d * d;
+template <typename R, int D>
+__global__ void __launch_bounds__(256) k_mg_point(MGLevelDev L, int mode) {
+  constexpr int d = D, st = D == 3 ? 27 : 9, dd = D * D;
   const MGBlockDev B = load_block(L.blk + (blockIdx.y));
   if (L.active && !L.active[B.prob]) return;
   const R* A = (const R*)L.A;
@@ -589,6 +589,23 @@ __global__ void __launch_bounds__(256) k_mg_point(int d, MGLevelDev L, int mode)
     int c[3];
     mg_coords(lv_, B.n, c);
     const bool inner = lat_free(c, B.n, d, B.ffm);
+    // the vertex's own values (lane 0) are loaded before the stencil products
+    R bv[3] = {R(0), R(0), R(0)}, xv[3] = {R(0), R(0), R(0)}, Dv[9];
+    if (lane == 0 && inner) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (k < d) bv[k] = b[v * d + k];
+      if (mode != 1) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+          if (k < dd) Dv[k] = Di[(size_t)v * dd + k];
+        if (mode == 2) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            if (k < d) xv[k] = x[v * d + k];
+        }
+      }
+    }
     R part[3] = {R(0), R(0), R(0)};
     if (inner && mode != 0 && lane < st) {
       const int o = lane;
@@ -607,15 +624,19 @@ __global__ void __launch_bounds__(256) k_mg_point(int d, MGLevelDev L, int mode)
           for (int k = 0; k < d; ++k) r[v * d + k] = R(0);
       } else {
         R res[3];
-        for (int k = 0; k < d; ++k) res[k] = b[v * d + k] - part[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) res[k] = bv[k] - part[k];
         if (mode == 1) {
           for (int k = 0; k < d; ++k) r[v * d + k] = res[k];
         } else {
-          const R* D = Di + (size_t)v * dd;
-          for (int k = 0; k < d; ++k) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            if (k >= d) break;
             R u = R(0);
-            for (int m = 0; m < d; ++m) u += D[k * d + m] * res[m];
-            x[v * d + k] = (mode == 0 ? R(0) : x[v * d + k]) + u;
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+              if (m < d) u += Dv[k * d + m] * res[m];
+            x[v * d + k] = (mode == 0 ? R(0) : xv[k]) + u;
           }
         }
       }
@@ -739,19 +760,25 @@ __global__ void __launch_bounds__(256) k_elem_press(SolveParams P, const R* __re
   __shared__ double us[MAXNB + MAXND];
   __shared__ double bp[MAXNP];
   __shared__ int rmap[MAXNB + MAXND];
-  __shared__ R ad[MAXND];
+  __shared__ R ad[MAXND], ab[MAXNB];
+  __shared__ double rp[MAXNP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   build_rowmap(s, rmap);
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     if (elem_off(P, e)) continue;
     const double det = P.detJ[e];
+    const double nue = P.nu[e];
+    // the element's own values are loaded with the facet ids, ahead of the
+    // facet values that depend on them
+    if (tid < np) rp[tid] = (double)r[P.off_p + e * np + tid];
     if (with_B) {
       const double sb = -fabs(det), sf = det > 0 ? -1.0 : 1.0;
+      if (tid < nb) ab[tid] = a[e * nb + tid];
       gather_elem_d(P, a, e, ad);
       __syncthreads();
       for (int row = tid; row < nb + nd; row += blockDim.x) {
         int iu = rmap[row];
-        if (iu >= 0) us[iu] = (row < nb ? sb * (double)a[e * nb + row] : sf * (double)ad[row - nb]);
+        if (iu >= 0) us[iu] = (row < nb ? sb * (double)ab[row] : sf * (double)ad[row - nb]);
       }
     }
     __syncthreads();
@@ -761,11 +788,11 @@ __global__ void __launch_bounds__(256) k_elem_press(SolveParams P, const R* __re
         for (int iu = lane; iu < nu; iu += 64) acc += P.rBp[(size_t)q * nu + iu] * us[iu];
         acc = wave_sum(acc);
       }
-      if (lane == 0) bp[q] = (double)r[P.off_p + e * np + q] - acc;
+      if (lane == 0) bp[q] = rp[q] - acc;
     }
     __syncthreads();
     if (tid < np) {
-      double sc = P.nu[e] / fabs(det);
+      double sc = nue / fabs(det);
       double acc = 0.0;
       for (int j = 0; j < np; ++j) acc += P.rMpinv[tid * np + j] * bp[j];
       y[P.off_p + e * np + tid] = (R)(sc * acc);
@@ -1255,7 +1282,11 @@ static unsigned mg_grid(int64_t n, int per) {
 template <typename R>
 void launch_mg_point(hipStream_t st, int d, const MGLevelDev& L, int mode) {
   if (L.ncont == 0) return;
-  hipLaunchKernelGGL(k_mg_point<R>, dim3(mg_grid(L.maxv, 8), L.ncont), dim3(256), 0, st, d, L, mode);
+  const dim3 g(mg_grid(L.maxv, 8), L.ncont), b(256);
+  if (d == 3)
+    hipLaunchKernelGGL((k_mg_point<R, 3>), g, b, 0, st, L, mode);
+  else
+    hipLaunchKernelGGL((k_mg_point<R, 2>), g, b, 0, st, L, mode);
 }
 template <typename R>
 void launch_mg_restrict(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C) {
