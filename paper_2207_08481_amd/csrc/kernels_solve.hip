@@ -510,7 +510,21 @@ __global__ void k_edt_vertex(int d, int64_t nfv, const int32_t* __restrict__ vin
     int64_t v = idx / d;
     int c = (int)(idx % d);
     R acc = 0;
-    for (int p = vinc_off[v]; p < vinc_off[v + 1]; ++p) {
+    // four incidences at a time: their index pairs, then their values, are
+    // loaded together (the sum keeps its order)
+    const int p0 = vinc_off[v], p1 = vinc_off[v + 1];
+    int p = p0;
+    for (; p + 4 <= p1; p += 4) {
+      int2 iv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) iv[u] = make_int2(vinc[2 * (p + u)], vinc[2 * (p + u) + 1]);
+      R fv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) fv[u] = fscr[(int64_t)iv[u].x * dd + iv[u].y * d + c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += fv[u];
+    }
+    for (; p < p1; ++p) {
       int64_t g = vinc[2 * p];
       int sl = vinc[2 * p + 1];
       acc += fscr[g * dd + sl * d + c];
@@ -655,11 +669,11 @@ __device__ inline double mg_w(int i, int I, int n) {
 
 // b_c = P^T r_f (interior coarse vertices of each continuing block); one
 // 32-lane group per coarse vertex.
-template <typename R>
-__global__ void __launch_bounds__(256) k_mg_restrict(int d, MGLevelDev F, MGLevelDev C) {
+template <typename R, int D>
+__global__ void __launch_bounds__(256) k_mg_restrict(MGLevelDev F, MGLevelDev C) {
+  constexpr int d = D, st = D == 3 ? 27 : 9;
   const R* r = (const R*)F.r;
   R* bc = (R*)C.b;
-  const int st = d == 3 ? 27 : 9;
   const MGBlockDev B = load_block(F.blk + (blockIdx.y));
   if (F.active && !F.active[B.prob]) return;
   const int lane = threadIdx.x & 31;
@@ -690,11 +704,11 @@ __global__ void __launch_bounds__(256) k_mg_restrict(int d, MGLevelDev F, MGLeve
 
 // x_f += P x_c (interior fine vertices of each continuing block); one 32-lane
 // group per fine vertex, one candidate coarse vertex per lane.
-template <typename R>
-__global__ void __launch_bounds__(256) k_mg_prolong(int d, MGLevelDev F, MGLevelDev C) {
+template <typename R, int D>
+__global__ void __launch_bounds__(256) k_mg_prolong(MGLevelDev F, MGLevelDev C) {
+  constexpr int d = D, st = D == 3 ? 27 : 9;
   R* x = (R*)F.x;
   const R* xc = (const R*)C.x;
-  const int st = d == 3 ? 27 : 9;
   const MGBlockDev B = load_block(F.blk + (blockIdx.y));
   if (F.active && !F.active[B.prob]) return;
   const int lane = threadIdx.x & 31;
@@ -1291,12 +1305,20 @@ void launch_mg_point(hipStream_t st, int d, const MGLevelDev& L, int mode) {
 template <typename R>
 void launch_mg_restrict(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C) {
   if (F.ncont == 0) return;
-  hipLaunchKernelGGL(k_mg_restrict<R>, dim3(mg_grid(F.maxvc, 8), F.ncont), dim3(256), 0, st, d, F, C);
+  const dim3 g(mg_grid(F.maxvc, 8), F.ncont), b(256);
+  if (d == 3)
+    hipLaunchKernelGGL((k_mg_restrict<R, 3>), g, b, 0, st, F, C);
+  else
+    hipLaunchKernelGGL((k_mg_restrict<R, 2>), g, b, 0, st, F, C);
 }
 template <typename R>
 void launch_mg_prolong(hipStream_t st, int d, const MGLevelDev& F, const MGLevelDev& C) {
   if (F.ncont == 0) return;
-  hipLaunchKernelGGL(k_mg_prolong<R>, dim3(mg_grid(F.maxv, 8), F.ncont), dim3(256), 0, st, d, F, C);
+  const dim3 g(mg_grid(F.maxv, 8), F.ncont), b(256);
+  if (d == 3)
+    hipLaunchKernelGGL((k_mg_prolong<R, 3>), g, b, 0, st, F, C);
+  else
+    hipLaunchKernelGGL((k_mg_prolong<R, 2>), g, b, 0, st, F, C);
 }
 template <typename R>
 void launch_mg_coarse(hipStream_t st, const double* Cinv, const int32_t* cmap, int d, const MGLevelDev& L) {
