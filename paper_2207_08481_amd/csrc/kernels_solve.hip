@@ -414,6 +414,94 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
   }
 }
 
+// The colour phase of k_smooth_y for FP64 entries in 3D with two columns of
+// the facet's row block per thread: every A^d load moves 16 bytes, a team is
+// round_up(n_d, 64) threads (half the waves), and each column is updated in
+// the same order as in k_smooth_y, so the two kernels give identical results.
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+template <int NFB, bool OUT>
+__global__ void __launch_bounds__(256) k_smooth_y2(SolveParams P, OpPtrs<double> O, int32_t c0, int32_t c1,
+                                                   double* __restrict__ x, const double* __restrict__ srhs,
+                                                   double* __restrict__ y) {
+  constexpr int NP = NFB * (NFB + 1) / 2;
+  constexpr int ND = 4 * NFB, NH = ND / 2;     // columns per side, pairs per side
+  constexpr int T1 = ((2 * NH + 63) / 64) * 64;
+  constexpr int NDV = (NP + T1 - 1) / T1;
+  __shared__ double rr[2][NFB + 1];
+  __shared__ double dl[2][NFB];
+  __shared__ double dsh[2][NP + 1];
+  const int tid = threadIdx.x;
+  const int side = tid >= NH ? 1 : 0;
+  const bool is_row = tid < 2 * NH;
+  const int t = is_row ? 2 * (tid - side * NH) : ND - 2;   // first of the thread's two columns
+  const int tq = tid < NFB ? tid : NFB - 1;
+  int buf = 0;
+  const int64_t step = gridDim.x;
+  auto record = [&](int64_t ci) {
+    return *reinterpret_cast<const int4*>(P.colour_desc + 4 * (ci < c1 ? ci : (int64_t)c1 - 1));
+  };
+  int4 next = record(c0 + (int64_t)blockIdx.x);
+  for (int64_t ci = c0 + (int64_t)blockIdx.x; ci < c1; ci += step, buf ^= 1) {
+    bool work = true;
+    const int4 dsc = next;
+    next = record(ci + step);
+    const int64_t g = dsc.x;
+    const int64_t e1 = dsc.y;
+    const int s1 = dsc.w & 0xFF;
+    const bool has2 = !OUT || dsc.z >= 0;
+    const int64_t e2 = has2 ? (int64_t)dsc.z : e1;
+    const int s2 = has2 ? (dsc.w >> 8) & 0xFF : s1;
+    if (P.active && facet_off(P, g)) work = false;
+    if (work && P.work_count && tid == 0) atomicAdd(P.work_count + (blockIdx.x & 255) * 16, 1ull);
+    const int64_t e = side ? e2 : e1;
+    const int sl = side ? s2 : s1;
+    double dv[NDV];
+    const double* Di = O.DinvP + (size_t)g * NP;
+#pragma unroll
+    for (int u = 0; u < NDV; ++u) {
+      const int i = tid + u * T1;
+      dv[u] = Di[i < NP ? i : NP - 1];
+    }
+    const int64_t fo = P.off_f + g * NFB + tq;
+    const double xo = x[fo];
+    const double sv = srhs[fo];
+    const double y1 = y[e1 * ND + s1 * NFB + tq];
+    const double y2 = y[e2 * ND + s2 * NFB + tq];
+    dbl2v yv = *reinterpret_cast<const dbl2v*>(y + e * ND + t);
+    dbl2v a[NFB];
+    const double* Ab = O.Ad + (size_t)e * ND * ND + (size_t)sl * NFB * ND + t;
+#pragma unroll
+    for (int q = 0; q < NFB; ++q) a[q] = *reinterpret_cast<const dbl2v*>(Ab + (size_t)q * ND);
+#pragma unroll
+    for (int u = 0; u < NDV; ++u) {
+      const int i = tid + u * T1;
+      dsh[buf][i < NP ? i : NP] = dv[u];
+    }
+    rr[buf][tid < NFB ? tid : NFB] = has2 ? sv - y1 - y2 : sv - y1;
+    __syncthreads();
+    if (tid < NFB) {
+      const int rb = tid * NFB - tid * (tid - 1) / 2 - tid;
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < NFB; ++j) {
+        const int pk = j < tid ? j * NFB - j * (j - 1) / 2 - j + tid : rb + j;
+        acc += dsh[buf][pk] * rr[buf][j];
+      }
+      dl[buf][tid] = acc;
+      if (work) x[fo] = xo + acc;
+    }
+    __syncthreads();
+    if (work && is_row && (side == 0 || has2)) {
+#pragma unroll
+      for (int q = 0; q < NFB; ++q) {
+        yv.x += a[q].x * dl[buf][q];
+        yv.y += a[q].y * dl[buf][q];
+      }
+      *reinterpret_cast<dbl2v*>(y + e * ND + t) = yv;
+    }
+  }
+}
+
 // z_F = D_F^{-1} r_F for every free facet block: the facet block Jacobi of the
 // additive variant (Theorem aux_pc_schur); one thread per row of a block.
 template <typename R>
@@ -1224,6 +1312,18 @@ static void smooth_launch(hipStream_t st, const SolveParams& P, const OpPtrs<R>&
       else
         hipLaunchKernelGGL((k_smooth_y<R, NFB, 2, false>), dim3((unsigned)blocks), dim3(2 * T1), 0, st, P, O, c0, c1,
                            x, s, y, T1);
+      return;
+    }
+  }
+  if constexpr (sizeof(R) == 8 && (NFB == 12 || NFB == 22)) {
+    // 3D FP64: two columns per thread
+    if (P.s.nd == 4 * NFB && P.s.d == 3) {
+      const unsigned b2 = (unsigned)std::min<int64_t>(c1 - c0, cap);
+      constexpr int T2 = ((4 * NFB + 63) / 64) * 64;
+      if (P.has_outlet)
+        hipLaunchKernelGGL((k_smooth_y2<NFB, true>), dim3(b2), dim3(T2), 0, st, P, O, c0, c1, x, s, y);
+      else
+        hipLaunchKernelGGL((k_smooth_y2<NFB, false>), dim3(b2), dim3(T2), 0, st, P, O, c0, c1, x, s, y);
       return;
     }
   }
