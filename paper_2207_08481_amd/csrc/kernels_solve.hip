@@ -414,22 +414,22 @@ __global__ void __launch_bounds__(512) k_smooth_y(SolveParams P, OpPtrs<R> O, in
   }
 }
 
-// The colour phase of k_smooth_y for FP64 entries in 3D with two columns of
-// the facet's row block per thread: every A^d load moves 16 bytes, a team is
-// round_up(n_d, 64) threads (half the waves), and each column is updated in
+// The colour phase of k_smooth_y in 3D with two columns of the facet's row
+// block per thread: every A^d load moves two words (16 bytes in FP64), a team
+// is round_up(n_d, 64) threads (half the waves), and each column is updated in
 // the same order as in k_smooth_y, so the two kernels give identical results.
-typedef double dbl2v __attribute__((ext_vector_type(2)));
-template <int NFB, bool OUT>
-__global__ void __launch_bounds__(256) k_smooth_y2(SolveParams P, OpPtrs<double> O, int32_t c0, int32_t c1,
-                                                   double* __restrict__ x, const double* __restrict__ srhs,
-                                                   double* __restrict__ y) {
+template <typename R, int NFB, bool OUT>
+__global__ void __launch_bounds__(256) k_smooth_y2(SolveParams P, OpPtrs<R> O, int32_t c0, int32_t c1,
+                                                   R* __restrict__ x, const R* __restrict__ srhs,
+                                                   R* __restrict__ y) {
+  typedef R dbl2v __attribute__((ext_vector_type(2)));
   constexpr int NP = NFB * (NFB + 1) / 2;
   constexpr int ND = 4 * NFB, NH = ND / 2;     // columns per side, pairs per side
   constexpr int T1 = ((2 * NH + 63) / 64) * 64;
   constexpr int NDV = (NP + T1 - 1) / T1;
-  __shared__ double rr[2][NFB + 1];
-  __shared__ double dl[2][NFB];
-  __shared__ double dsh[2][NP + 1];
+  __shared__ R rr[2][NFB + 1];
+  __shared__ R dl[2][NFB];
+  __shared__ R dsh[2][NP + 1];
   const int tid = threadIdx.x;
   const int side = tid >= NH ? 1 : 0;
   const bool is_row = tid < 2 * NH;
@@ -455,21 +455,21 @@ __global__ void __launch_bounds__(256) k_smooth_y2(SolveParams P, OpPtrs<double>
     if (work && P.work_count && tid == 0) atomicAdd(P.work_count + (blockIdx.x & 255) * 16, 1ull);
     const int64_t e = side ? e2 : e1;
     const int sl = side ? s2 : s1;
-    double dv[NDV];
-    const double* Di = O.DinvP + (size_t)g * NP;
+    R dv[NDV];
+    const R* Di = O.DinvP + (size_t)g * NP;
 #pragma unroll
     for (int u = 0; u < NDV; ++u) {
       const int i = tid + u * T1;
       dv[u] = Di[i < NP ? i : NP - 1];
     }
     const int64_t fo = P.off_f + g * NFB + tq;
-    const double xo = x[fo];
-    const double sv = srhs[fo];
-    const double y1 = y[e1 * ND + s1 * NFB + tq];
-    const double y2 = y[e2 * ND + s2 * NFB + tq];
+    const R xo = x[fo];
+    const R sv = srhs[fo];
+    const R y1 = y[e1 * ND + s1 * NFB + tq];
+    const R y2 = y[e2 * ND + s2 * NFB + tq];
     dbl2v yv = *reinterpret_cast<const dbl2v*>(y + e * ND + t);
     dbl2v a[NFB];
-    const double* Ab = O.Ad + (size_t)e * ND * ND + (size_t)sl * NFB * ND + t;
+    const R* Ab = O.Ad + (size_t)e * ND * ND + (size_t)sl * NFB * ND + t;
 #pragma unroll
     for (int q = 0; q < NFB; ++q) a[q] = *reinterpret_cast<const dbl2v*>(Ab + (size_t)q * ND);
 #pragma unroll
@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(256) k_smooth_y2(SolveParams P, OpPtrs<double>
     __syncthreads();
     if (tid < NFB) {
       const int rb = tid * NFB - tid * (tid - 1) / 2 - tid;
-      double acc = 0.0;
+      R acc = R(0);
 #pragma unroll
       for (int j = 0; j < NFB; ++j) {
         const int pk = j < tid ? j * NFB - j * (j - 1) / 2 - j + tid : rb + j;
@@ -1315,15 +1315,15 @@ static void smooth_launch(hipStream_t st, const SolveParams& P, const OpPtrs<R>&
       return;
     }
   }
-  if constexpr (sizeof(R) == 8 && (NFB == 12 || NFB == 22)) {
-    // 3D FP64: two columns per thread
+  if constexpr (NFB == 12 || NFB == 22 || (NFB == 35 && sizeof(R) == 4)) {
+    // 3D: two columns per thread
     if (P.s.nd == 4 * NFB && P.s.d == 3) {
       const unsigned b2 = (unsigned)std::min<int64_t>(c1 - c0, cap);
       constexpr int T2 = ((4 * NFB + 63) / 64) * 64;
       if (P.has_outlet)
-        hipLaunchKernelGGL((k_smooth_y2<NFB, true>), dim3(b2), dim3(T2), 0, st, P, O, c0, c1, x, s, y);
+        hipLaunchKernelGGL((k_smooth_y2<R, NFB, true>), dim3(b2), dim3(T2), 0, st, P, O, c0, c1, x, s, y);
       else
-        hipLaunchKernelGGL((k_smooth_y2<NFB, false>), dim3(b2), dim3(T2), 0, st, P, O, c0, c1, x, s, y);
+        hipLaunchKernelGGL((k_smooth_y2<R, NFB, false>), dim3(b2), dim3(T2), 0, st, P, O, c0, c1, x, s, y);
       return;
     }
   }
