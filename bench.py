@@ -240,7 +240,8 @@ def run_batch(args, precision, desc):
                    "smoother_launch_per_group": b.launch_configs(1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_smooth_y, FP32 (one colour of one block Gauss-Seidel sweep, all groups)",
+                     "kernel": "k_smooth_y2, FP32 (one colour of one block Gauss-Seidel sweep, two columns of the "
+                               "row block per thread, all groups)",
                      "avg_launch_us": round(avg_launch_ms * 1e3, 2), "launches": klaunch,
                      "bytes_per_launch": int(bytes_per_launch),
                      "note": "measured in one extra launch-by-launch solve of the same batch"},
@@ -473,8 +474,9 @@ def main():
     kapply_name = "k_elem_apply (operator apply K x)"
     if smoother == 0:
         # the block Gauss-Seidel colour phase dominates the multiplicative solve
-        roofline = roof("smooth", "k_smooth_y (one colour of one block Gauss-Seidel sweep)",
-                        measured_traffic("k_smooth_y", args.workload, precision))
+        # every bench mesh is 3D with k <= 4: the two-column colour phase
+        roofline = roof("smooth", "k_smooth_y2 (one colour of one block Gauss-Seidel sweep, two columns of the "
+                        "row block per thread)", measured_traffic("k_smooth_y2", args.workload, precision))
         secondary = roof("kapply", kapply_name, measured_traffic("k_elem_apply", args.workload, precision))
     elif smoother == 2:
         # overlapping block Gauss-Seidel on the whole velocity block
