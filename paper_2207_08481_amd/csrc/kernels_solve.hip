@@ -11,6 +11,8 @@
 // Products with a symmetric matrix give each thread one column (= one row),
 // so consecutive threads read consecutive addresses; products with the rows
 // of H give each wave one row, lanes over its contiguous columns.
+#include <type_traits>
+
 #include "kernels_common.h"
 #include "launch.h"
 
@@ -86,12 +88,14 @@ __device__ inline void build_rowmap(const Sizes& s, int* rmap) {
 
 // flags: 1 = velocity block A (factorised), 2 = + B^T p, 4 = p <- B u, 8 = A^d only,
 // 16 = write zero pressure rows when B u is not requested.
-// Phase 1: the first ceil(n_d/64) waves form A^d x_d (one row per thread,
-// A^d symmetric so its columns are contiguous) while the remaining waves form
-// z_o = x_o + H x_d (16-lane groups per row of H); phase 2: w_o = A_oo z_o;
-// phase 3: H^T w_o (one column per thread) and the pressure coupling.
+// Phase 1: the first ceil(n_d / (64 CP)) waves form A^d x_d (CP rows per
+// thread, A^d symmetric so its columns are contiguous; CP = 2 loads two
+// adjacent words at once and passes the second row through LDS) while the
+// remaining waves form z_o = x_o + H x_d (16-lane groups per row of H);
+// phase 2: w_o = A_oo z_o; phase 3: H^T w_o (one column per thread) and the
+// pressure coupling.  Every row is summed in the same order for CP = 1 and 2.
 // B_T[q][row] = -s |det J| Bp^[q][iu(row)] (s = 1 bubble, 1/det J facet row).
-template <typename R, typename MA, int FL>
+template <typename R, typename MA, int FL, int CP>
 __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH, MA MAoo, const R* __restrict__ x,
                                                     R* __restrict__ y, R* __restrict__ escr, int flags) {
   if constexpr (FL >= 0) flags = FL;   // specialised instantiations fold the flag tests
@@ -101,11 +105,12 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
   __shared__ R xp[MAXNP];
   __shared__ int rmap[MAXNB + MAXND];
   __shared__ double us[MAXNB + MAXND];   // Piola-scaled velocity for B u, by BDM index
+  __shared__ R adx[CP == 2 ? MAXND : 1];  // A^d x_d (CP = 2)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool doA = flags & 1, doBT = flags & 2, doBu = flags & 4, onlyAd = flags & 8;
   const bool doH = doA && !onlyAd;
   build_rowmap(s, rmap);
-  const int tA = ((nd + 63) >> 6) << 6;          // threads of the A^d product
+  const int tA = ((nd / CP + 63) >> 6) << 6;     // threads of the A^d product
   const bool overlap = tA < 256;
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     if (elem_off(P, e)) continue;
@@ -119,7 +124,24 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
     __syncthreads();
     const size_t h0 = (size_t)e * nb * nd;
     R acc = R(0);
-    if (tid < nd) {
+    if constexpr (CP == 2) {
+      if (tid < nd / 2) {
+        if (doA) {
+          typedef R r2v __attribute__((ext_vector_type(2)));
+          const R* a0 = MAd.p + (size_t)e * nd * nd + 2 * tid;
+          R acc1 = R(0);
+#pragma unroll 8
+          for (int j = 0; j < nd; ++j) {
+            const r2v v = *reinterpret_cast<const r2v*>(a0 + (size_t)j * nd);
+            acc += v.x * xd[j];
+            acc1 += v.y * xd[j];
+          }
+          adx[2 * tid] = acc;
+          adx[2 * tid + 1] = acc1;
+        }
+      }
+    }
+    if (CP == 1 && tid < nd) {
       if (doA) {
         const size_t a0 = (size_t)e * nd * nd + tid;
 #pragma unroll 8
@@ -148,6 +170,7 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
       __syncthreads();
     }
     if (tid < nd) {
+      if constexpr (CP == 2) acc = doA ? adx[tid] : R(0);
       if (doH) {
 #pragma unroll 4
         for (int i = 0; i < nb; ++i) acc += MH(h0 + tid + (size_t)i * nd) * wo[i];
@@ -1257,15 +1280,21 @@ template <typename R, typename MA>
 static void elem_apply_launch(hipStream_t st, const SolveParams& P, MA Ad, MA H, MA Aoo, const R* x, R* y, R* escr,
                               int flags) {
   // the operator apply K x and the B^T-only apply of K-hat^{-1} run every
-  // MINRES iteration: compile-time flags for them
+  // MINRES iteration: compile-time flags for them; K x with plain storage and
+  // even n_d takes two rows of A^d per thread
+  const dim3 g(elem_grid(P.ne)), b(256);
+  if constexpr (std::is_same<MA, MatP<R>>::value) {
+    if (flags == (1 | 2 | 4) && P.s.nd % 2 == 0) {
+      hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 2>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags);
+      return;
+    }
+  }
   if (flags == (1 | 2 | 4))
-    hipLaunchKernelGGL((k_elem_apply<R, MA, 7>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, Ad, H, Aoo, x, y, escr, flags);
+    hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags);
   else if (flags == (2 | 16))
-    hipLaunchKernelGGL((k_elem_apply<R, MA, 18>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, Ad, H, Aoo, x, y, escr,
-                       flags);
+    hipLaunchKernelGGL((k_elem_apply<R, MA, 18, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags);
   else
-    hipLaunchKernelGGL((k_elem_apply<R, MA, -1>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, Ad, H, Aoo, x, y, escr,
-                       flags);
+    hipLaunchKernelGGL((k_elem_apply<R, MA, -1, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags);
 }
 template <typename R>
 void launch_elem_apply(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* x, R* y, R* escr, int flags) {
