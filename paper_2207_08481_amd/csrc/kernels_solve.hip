@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
   __shared__ R xp[MAXNP];
   __shared__ int rmap[MAXNB + MAXND];
   __shared__ double us[MAXNB + MAXND];   // Piola-scaled velocity for B u, by BDM index
-  __shared__ R adx[CP == 2 ? MAXND : 1];  // A^d x_d (CP = 2)
+  __shared__ R adx[CP > 1 ? MAXND : 1];   // A^d x_d (CP > 1)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool doA = flags & 1, doBT = flags & 2, doBu = flags & 4, onlyAd = flags & 8;
   const bool doH = doA && !onlyAd;
@@ -124,20 +124,22 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
     __syncthreads();
     const size_t h0 = (size_t)e * nb * nd;
     R acc = R(0);
-    if constexpr (CP == 2) {
-      if (tid < nd / 2) {
+    if constexpr (CP > 1) {
+      if (tid < nd / CP) {
         if (doA) {
-          typedef R r2v __attribute__((ext_vector_type(2)));
-          const R* a0 = MAd.p + (size_t)e * nd * nd + 2 * tid;
-          R acc1 = R(0);
+          typedef R rcv __attribute__((ext_vector_type(CP)));
+          const R* a0 = MAd.p + (size_t)e * nd * nd + CP * tid;
+          R ac[CP];
+#pragma unroll
+          for (int c = 0; c < CP; ++c) ac[c] = R(0);
 #pragma unroll 8
           for (int j = 0; j < nd; ++j) {
-            const r2v v = *reinterpret_cast<const r2v*>(a0 + (size_t)j * nd);
-            acc += v.x * xd[j];
-            acc1 += v.y * xd[j];
+            const rcv v = *reinterpret_cast<const rcv*>(a0 + (size_t)j * nd);
+#pragma unroll
+            for (int c = 0; c < CP; ++c) ac[c] += v[c] * xd[j];
           }
-          adx[2 * tid] = acc;
-          adx[2 * tid + 1] = acc1;
+#pragma unroll
+          for (int c = 0; c < CP; ++c) adx[CP * tid + c] = ac[c];
         }
       }
     }
@@ -170,7 +172,7 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
       __syncthreads();
     }
     if (tid < nd) {
-      if constexpr (CP == 2) acc = doA ? adx[tid] : R(0);
+      if constexpr (CP > 1) acc = doA ? adx[tid] : R(0);
       if (doH) {
 #pragma unroll 4
         for (int i = 0; i < nb; ++i) acc += MH(h0 + tid + (size_t)i * nd) * wo[i];
@@ -1284,6 +1286,13 @@ static void elem_apply_launch(hipStream_t st, const SolveParams& P, MA Ad, MA H,
   // even n_d takes two rows of A^d per thread
   const dim3 g(elem_grid(P.ne)), b(256);
   if constexpr (std::is_same<MA, MatP<R>>::value) {
+    // FP32 with n_d divisible by 4: four rows per thread (16-byte loads)
+    if constexpr (sizeof(R) == 4) {
+      if (flags == (1 | 2 | 4) && P.s.nd % 4 == 0) {
+        hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 4>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags);
+        return;
+      }
+    }
     if (flags == (1 | 2 | 4) && P.s.nd % 2 == 0) {
       hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 2>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags);
       return;
