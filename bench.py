@@ -374,8 +374,8 @@ def main():
     ap.add_argument("--serve-inflight", type=int, default=3, help="serve: concurrent micro-batches")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no multi-GPU "
+              "path (no sharding or collectives); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
