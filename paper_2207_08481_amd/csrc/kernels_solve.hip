@@ -291,9 +291,10 @@ __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, con
 }
 
 // A-hat_ext^{-1}, last part: y_o = t_o - H_T t_d,T (8-lane groups per row of H_T).
-// NC > 0 (n_d <= 8 NC, n_o <= 32): the 32 groups hold their row's entries
-// in registers, loaded after the facet ids and before the facet values.
-template <typename R, int NC>
+// NC > 0 (n_d <= 8 NC, n_o <= 32 RPG): the 32 groups hold the entries of their
+// RPG rows (g, g + 32, ...) in registers, loaded after the facet ids and before
+// the facet values.
+template <typename R, int NC, int RPG>
 __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, const R* __restrict__ t,
                                                   const R* __restrict__ to, R* __restrict__ y) {
   const Sizes s = P.s;
@@ -303,24 +304,31 @@ __global__ void __launch_bounds__(256) k_ext_post(SolveParams P, OpPtrs<R> O, co
     if (elem_off(P, e)) continue;
     if constexpr (NC > 0) {
       const int g = threadIdx.x >> 3, l = threadIdx.x & 7;
-      const int row = g < nb ? g : nb - 1;
-      const R* h = O.H + (size_t)e * nb * nd + (size_t)row * nd;
-      R a[NC];
+      R a[RPG][NC];
 #pragma unroll
-      for (int m = 0; m < NC; ++m) {
-        const int j = l + 8 * m;
-        a[m] = h[j < nd ? j : nd - 1];
+      for (int q = 0; q < RPG; ++q) {
+        const int row = g + 32 * q < nb ? g + 32 * q : nb - 1;
+        const R* h = O.H + (size_t)e * nb * nd + (size_t)row * nd;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+          const int j = l + 8 * m;
+          a[q][m] = h[j < nd ? j : nd - 1];
+        }
       }
       gather_elem_d(P, t, e, td);
       __syncthreads();
-      R acc = R(0);
 #pragma unroll
-      for (int m = 0; m < NC; ++m) {
-        const int j = l + 8 * m;
-        if (j < nd) acc += a[m] * td[j];
+      for (int q = 0; q < RPG; ++q) {
+        R acc = R(0);
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+          const int j = l + 8 * m;
+          if (j < nd) acc += a[q][m] * td[j];
+        }
+        acc = group_sum<8>(acc);
+        const int row = g + 32 * q;
+        if (l == 0 && row < nb) y[e * nb + row] = to[e * nb + row] - acc;
       }
-      acc = group_sum<8>(acc);
-      if (l == 0 && g < nb) y[e * nb + g] = to[e * nb + g] - acc;
     } else {
       gather_elem_d(P, t, e, td);
       __syncthreads();
@@ -1329,9 +1337,11 @@ void launch_ext_pre(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, co
 template <typename R>
 void launch_ext_post(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* t, const R* to, R* y) {
   if (P.s.nb <= 32 && P.s.nd <= 96)
-    hipLaunchKernelGGL((k_ext_post<R, 12>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
+    hipLaunchKernelGGL((k_ext_post<R, 12, 1>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
+  else if (P.s.nb <= 64 && P.s.nd <= 144)
+    hipLaunchKernelGGL((k_ext_post<R, 18, 2>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
   else
-    hipLaunchKernelGGL((k_ext_post<R, 0>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
+    hipLaunchKernelGGL((k_ext_post<R, 0, 1>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
 }
 // facets_per_block (1 or 2) and grid_cap choose the launch shape; every
 // shape gives the same result.
