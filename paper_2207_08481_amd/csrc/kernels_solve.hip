@@ -7,10 +7,12 @@
 //
 // Layout of element operators (element-major, row-major inside an element):
 //   Ad  [nd][nd] symmetric;  H [nb][nd];
-//   Aoo [nb][nb], Aooinv [nb][nb] symmetric;  Dinv [nfb][nfb] symmetric.
+//   Aoo [nb][nb], Aooinv [nb][nb] symmetric;  Dinv [nfb][nfb] symmetric, and
+//   DinvP its upper triangle packed row by row (colour phases).
 // Products with a symmetric matrix give each thread one column (= one row),
-// so consecutive threads read consecutive addresses; products with the rows
-// of H give each wave one row, lanes over its contiguous columns.
+// or two or four adjacent ones read with one wider load, so consecutive
+// threads read consecutive addresses; products with the rows of H give each
+// group of lanes one row, lanes over its contiguous columns.
 #include <type_traits>
 
 #include "kernels_common.h"
