@@ -295,6 +295,13 @@ int mcs_timer_read(mcs_problem* pb, int32_t kernel, double* total_ms, int64_t* l
  * autotuner tries are bitwise equivalent. */
 int mcs_get_launch_config(const mcs_problem* pb, int dt, int32_t* facets_per_block, int64_t* grid_cap, double* us);
 
+/* Sets that launch shape for work precision dt: facets_per_block 1 or 2, grid
+ * cap >= 0 (0: one workgroup per facet block).  It holds until the next
+ * mcs_condense with autotune on, which tunes again.  Every shape gives bitwise
+ * the same results; the setter lets a caller fix the shape (or compare them).
+ * Other values: MCS_ERR_ARG. */
+int mcs_set_launch_config(mcs_problem* pb, int dt, int32_t facets_per_block, int64_t grid_cap);
+
 void mcs_destroy(mcs_problem* pb);
 const char* mcs_status_string(int status);
 const char* mcs_last_error(void);

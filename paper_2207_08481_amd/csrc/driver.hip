@@ -1028,6 +1028,18 @@ int mcs_get_launch_config(const mcs_problem* pb, int dt, int32_t* facets_per_blo
   return MCS_OK;
 }
 
+int mcs_set_launch_config(mcs_problem* pb, int dt, int32_t facets_per_block, int64_t grid_cap) {
+  if (!pb || (dt != MCS_F64 && dt != MCS_F32) || (facets_per_block != 1 && facets_per_block != 2) || grid_cap < 0) {
+    set_error("launch config: bad argument");
+    return MCS_ERR_ARG;
+  }
+  const int slot = dt == MCS_F64 ? 0 : 1;
+  pb->tune_fpw[slot] = facets_per_block;
+  pb->tune_cap[slot] = grid_cap;
+  pb->tune_us[slot] = 0.0;
+  return MCS_OK;
+}
+
 void mcs_destroy(mcs_problem* pb) {
   ApiLock lock(device_api_mutex());
   delete pb;

@@ -29,7 +29,8 @@ PC = {"KHAT": 0, "AEXT": 1, "ADELTA_MULT": 2, "SMOOTH_FWD": 3, "SMOOTH_BWD": 4, 
 SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
            "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
                  "mcs_get_array",
-           "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_destroy",
+           "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config",
+           "mcs_set_launch_config", "mcs_destroy",
            "mcs_status_string", "mcs_last_error",
            "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
            "mcs_batch_solve", "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable",
@@ -130,6 +131,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_timer_enable.argtypes = [vp, i32]
     lib.mcs_timer_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_get_launch_config.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i64), C.POINTER(C.c_double)]
+    lib.mcs_set_launch_config.argtypes = [vp, i32, i32, i64]
     lib.mcs_batch_launch_config.argtypes = [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
                                             C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_destroy.argtypes = [vp]
@@ -159,7 +161,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
                  "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
                  "mcs_get_array",
-                 "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_batch_plan",
+                 "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_set_launch_config", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
                  "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable", "mcs_batch_timer_read",
                  "mcs_server_create",
@@ -358,6 +360,10 @@ class Problem:
         f, c, us = C.c_int32(), C.c_int64(), C.c_double()
         _check(self._lib.mcs_get_launch_config(self._h, dt, C.byref(f), C.byref(c), C.byref(us)))
         return {"facets_per_block": f.value, "grid_cap": c.value, "us_per_launch": us.value}
+
+    def set_launch_config(self, facets_per_block, grid_cap=0, dt=F64):
+        """Fixes the colour phase's launch shape (until the next autotuned condense)."""
+        _check(self._lib.mcs_set_launch_config(self._h, dt, facets_per_block, grid_cap))
 
     def timer_enable(self, on=True, period=1):
         """Kernel timer on (one call in `period` is timed) or off."""

@@ -362,6 +362,35 @@ def test_autotuned_launch_shapes_give_identical_results(precision):
     assert torch.equal(xs[0], xs[1])
 
 
+@pytest.mark.parametrize("d,n,k,precision", [(3, 3, 3, 0), (3, 3, 2, 0), (3, 3, 3, 1), (2, 6, 3, 0)])
+def test_colour_phase_kernels_agree_bitwise(d, n, k, precision):
+    """The colour phase runs as the two-column kernel (one facet per
+    workgroup, 3D) or the one-column kernel (two facets per workgroup), with
+    or without a grid cap (then each workgroup loops over several facets with
+    the next facet's record loaded ahead).  All shapes give bitwise the same
+    solution."""
+    _need_gpu()
+    from paper_2207_08481_amd import Problem
+    from paper_2207_08481_amd.mcs import F32, F64
+    mesh = W.unit_square_mesh(n) if d == 2 else W.unit_cube_mesh(n)
+    sol = W.Manufactured2D() if d == 2 else W.CurlModes3D(seed=2)
+    f = torch.as_tensor(sol.f(W.lattice_points(mesh, k + 1)), device="cuda:0")
+    nu = torch.as_tensor(W.lognormal_nu(mesh.n_elements, seed=4), device="cuda:0")
+    print(f"[case] colour phase shapes d={d} n={n} k={k} precision={precision}", flush=True)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, k, precision=precision, autotune=0).bind("cuda:0")
+    pb.condense(nu)
+    dt = F64 if precision == 0 else F32
+    xs = []
+    for fpb, cap in ((1, 0), (2, 0), (1, 16), (2, 16)):
+        pb.set_launch_config(fpb, cap, dt)
+        assert pb.launch_config(dt)["facets_per_block"] == fpb
+        x, si = pb.solve(f)
+        assert si["status"] == 0
+        xs.append(x.clone())
+    for x in xs[1:]:
+        assert torch.equal(x, xs[0])
+
+
 @pytest.mark.parametrize("d,n,k", [(2, 2, 2), (3, 1, 3), (3, 2, 2)])
 def test_point_values_match_oracle(d, n, k):
     """mcs_eval: u_h and p_h of a coefficient vector at barycentric points
