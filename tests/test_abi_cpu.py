@@ -240,3 +240,19 @@ def test_outlet_errors():
     with pytest.raises(MCSError) as ex:
         Batch([(mesh.vertices, mesh.elements, mesh.lattice)], [2], face_bcs=[[0, 1, 0, 0]])
     assert ex.value.status == -10
+
+
+def test_launch_config_setter_validates():
+    """mcs_set_launch_config takes 1 or 2 facet blocks per workgroup and a
+    grid cap >= 0 for FP64 or FP32 work precision; anything else is refused
+    with MCS_ERR_ARG and leaves the shape unchanged (host only)."""
+    from paper_2207_08481_amd.mcs import F32, F64, MCSError, Problem
+    mesh = W.unit_cube_mesh(1)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 3)
+    pb.set_launch_config(2, 64, F32)
+    assert pb.launch_config(F32) == {"facets_per_block": 2, "grid_cap": 64, "us_per_launch": 0.0}
+    for fpb, cap, dt in ((3, 0, F64), (0, 0, F64), (1, -1, F64), (1, 0, 7)):
+        with pytest.raises(MCSError) as ex:
+            pb.set_launch_config(fpb, cap, dt)
+        assert "ERR_ARG" in str(ex.value)
+    assert pb.launch_config(F32)["facets_per_block"] == 2
