@@ -22,8 +22,10 @@
  * all of its device state lives in the caller's workspace (mcs_bind).
  *
  * Mesh: dim in {2, 3}; vertices[n_vertices * dim] (double, row-major);
- * elements[n_elements * (dim+1)] (int32, any vertex order).  All of the
- * boundary is Dirichlet (homogeneous).  The auxiliary multigrid needs the
+ * elements[n_elements * (dim+1)] (int32, any vertex order).  Each face of
+ * the box the lattice fills is Dirichlet or an outlet (mcs_mesh.face_bc); by
+ * default the whole boundary is Dirichlet with u = 0 (mcs_set_dirichlet sets
+ * other data).  The auxiliary multigrid needs the
  * vertices to form a structured lattice: lattice[a] = vertices per axis,
  * vertex (i, j[, l]) has index i + lattice[0] * (j + lattice[1] * l), and
  * every element lies inside one lattice cell.
@@ -213,7 +215,9 @@ int mcs_precond_apply(mcs_problem* pb, int op, int dt, const void* r, void* z);
 
 /* Solves K x = b(f) with preconditioned MINRES from x = 0 (precision 0), or
  * FP32 inner MINRES with FP64 iterative refinement on the true residual
- * (precision 1), then subtracts the mean of p.  f_lattice: device force
+ * (precision 1).  Without an outlet face it then subtracts the mean of p (p
+ * is fixed up to a constant); with one, p is unique and is returned as
+ * computed.  f_lattice: device force
  * values; x: device double[n_dof] (output).  info may be NULL.  [sync]
  * Errors: MCS_ERR_NOT_CONVERGED, MCS_ERR_BREAKDOWN, MCS_ERR_NONFINITE. */
 int mcs_solve(mcs_problem* pb, const double* f_lattice, double* x, mcs_solve_info* info);
@@ -296,11 +300,21 @@ int mcs_timer_read(mcs_problem* pb, int32_t kernel, double* total_ms, int64_t* l
 int mcs_get_launch_config(const mcs_problem* pb, int dt, int32_t* facets_per_block, int64_t* grid_cap, double* us);
 
 /* Sets that launch shape for work precision dt: facets_per_block 1 or 2, grid
- * cap >= 0 (0: one workgroup per facet block).  It holds until the next
- * mcs_condense with autotune on, which tunes again.  Every shape gives bitwise
- * the same results; the setter lets a caller fix the shape (or compare them).
- * Other values: MCS_ERR_ARG. */
+ * cap >= 0 (0: one workgroup per facet block).  A shape set here stays: the
+ * autotuner (mcs_options.autotune) only tunes the precision slots the caller
+ * has not set.  Every shape gives bitwise the same results; the setter lets a
+ * caller fix the shape (or compare them).  Other values, and MCS_F64 on a
+ * precision 1 problem (it has no FP64 smoother): MCS_ERR_ARG. */
 int mcs_set_launch_config(mcs_problem* pb, int dt, int32_t facets_per_block, int64_t grid_cap);
+
+/* Changes the stopping rules of later solves on a planned problem (the fields
+ * of mcs_options that do not change the layout): tol >= 0, max_it >= 1,
+ * 0 <= inner_tol < 1, max_outer >= 1.  With tol = 0 a solve runs max_it
+ * iterations (precision 0) or max_outer refinement steps of max_it inner
+ * iterations when inner_tol = 0 (precision 1), and returns its last iterate
+ * with MCS_ERR_NOT_CONVERGED: a fixed block of iterations, e.g. for timing.
+ * Other values: MCS_ERR_ARG. */
+int mcs_set_solve_options(mcs_problem* pb, double tol, int32_t max_it, double inner_tol, int32_t max_outer);
 
 void mcs_destroy(mcs_problem* pb);
 const char* mcs_status_string(int status);

@@ -156,8 +156,13 @@ struct Ctx {
   // final reduction of a dot product writes there directly, so that reading a
   // scalar needs no copy launch
   double* host_dev = nullptr;
+  // reduction partials (>= 1024 doubles) and the scalar slot of dot products
+  double* red;
+  double* scal;
   explicit Ctx(mcs_problem* p) : pb(p), st(p->stream), P(solve_params(p)), O(op_ptrs<R>(p)), L(mg_levels<R>(p)) {
     n = p->ndof;
+    red = p->p.red;
+    scal = p->p.scal;
     base = sizeof(R) == 8 ? reinterpret_cast<R*>(p->p.vec) - (int64_t)p->vbase64 * p->ndof
                           : reinterpret_cast<R*>(p->p.vec32);
     escr = reinterpret_cast<R*>(p->p.escr);
@@ -176,8 +181,11 @@ struct Ctx {
   // y = op x on full vectors; flags of k_elem_apply.
   void apply(const R* x, R* y, int flags) {
     if (flags & 8) launch_fill<R>(st, n, R(0), y);
-    // the timer takes the full operator apply of a single problem (no masks)
-    const bool timed = pb->timer_on && flags == (1 | 2 | 4) && !P.active && pb->t_tick[1]++ % pb->timer_period == 0;
+    // the timer takes the full operator apply of a single problem (no masks),
+    // in the precision of the MINRES iteration (precision 1: the FP32 applies,
+    // not the FP64 ones of the refinement residual)
+    const bool timed = pb->timer_on && flags == (1 | 2 | 4) && !P.active && (!pb->lean || sizeof(R) == 4) &&
+                       pb->t_tick[1]++ % pb->timer_period == 0;
     if (timed) {
       timer_start(pb, st, 1);
       pb->t_bytes[1] += pb->ne * kapply_bytes_per_elem(pb->sz, pb->d, sizeof(R));
@@ -341,10 +349,10 @@ struct Ctx {
 
   double dot(const R* a, const R* b, double* host) {
     if (host_dev) {
-      launch_dot<R>(st, n, a, b, pb->p.red, host_dev);
+      launch_dot<R>(st, n, a, b, red, host_dev);
     } else {
-      launch_dot<R>(st, n, a, b, pb->p.red, pb->p.scal);
-      hipMemcpyAsync(host, pb->p.scal, sizeof(double), hipMemcpyDeviceToHost, st);
+      launch_dot<R>(st, n, a, b, red, scal);
+      hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, st);
     }
     hipStreamSynchronize(st);
     timer_flush(pb);

@@ -98,11 +98,14 @@ int tune_smoother_precision(mcs_problem* pb, int slot) {
   return MCS_OK;
 }
 
+// Tunes each precision slot once per plan, except the slots whose shape the
+// caller fixed with mcs_set_launch_config.
 int tune_smoother(mcs_problem* pb) {
   int rc = MCS_OK;
-  if (!pb->lean) rc = tune_smoother_precision<double>(pb, 0);
+  if (!pb->lean && !pb->tune_fixed[0] && pb->tune_us[0] == 0.0) rc = tune_smoother_precision<double>(pb, 0);
   if (rc) return rc;
-  return tune_smoother_precision<float>(pb, 1);
+  if (!pb->tune_fixed[1] && pb->tune_us[1] == 0.0) rc = tune_smoother_precision<float>(pb, 1);
+  return rc;
 }
 
 int check_bound(mcs_problem* pb) {
@@ -538,7 +541,7 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   }
   rc = sync_status(pb, "condense");
   if (rc) return rc;
-  if (pb->opt.autotune && pb->tune_us[1] == 0.0) {   // once per plan; later condensations reuse it
+  if (pb->opt.autotune) {   // once per plan and slot; later condensations reuse the shapes
     rc = tune_smoother(pb);
     if (rc) return rc;
   }
@@ -733,38 +736,21 @@ int mcs_normalize_pressure(mcs_problem* pb, double* x) {
   return MCS_OK;
 }
 
-int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* info) {
-  int rc = check_bound(pb);
-  if (rc) return rc;
-  if (!pb->condensed) {
-    set_error("mcs_solve needs mcs_condense first");
-    return MCS_ERR_STATE;
-  }
-  if (!b || !x) {
-    set_error("null vector");
-    return MCS_ERR_ARG;
-  }
-  // pinned scalars of the host-side recurrences, released on every return path
-  struct Pinned {
-    double* p = nullptr;
-    ~Pinned() {
-      ApiLock lock(device_api_mutex());
-      if (p) hipHostFree(p);
-    }
-  } pin;
-  {
-    ApiLock lock(device_api_mutex());
-    HIPCHK(hipHostMalloc((void**)&pin.p, 64));
-  }
-  double* host = pin.p;
-  double* host_dev = nullptr;
-  HIPCHK(hipHostGetDevicePointer((void**)&host_dev, host, 0));
+// The iteration of mcs_solve_rhs.  Dot products reduce into `red` (>= 1024
+// partial sums) and leave their scalar in host memory: written directly
+// through host_dev (device alias of pinned memory) when it is given, else in
+// `scal` and copied into *host.  The pressure mean reduces into `red` too.
+static int solve_rhs_run(mcs_problem* pb, const double* b, double* x, mcs_solve_info* info, double* red,
+                         double* scal, double* host, double* host_dev) {
+  int rc = MCS_OK;
   hipStream_t st = pb->stream;
   const int64_t n = pb->ndof;
   mcs_solve_info inf{};
   auto t0 = std::chrono::steady_clock::now();
   Ctx<double> c64(pb);
   c64.host_dev = host_dev;
+  c64.red = red;
+  c64.scal = scal;
   if (pb->opt.precision == 0) {
     int its = 0;
     double rel = 0, b1 = 0;
@@ -775,6 +761,8 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
   } else {
     Ctx<float> c32(pb);
     c32.host_dev = host_dev;
+    c32.red = red;
+    c32.scal = scal;
     double* r64 = c64.v(VR64);
     float* r32 = c32.v(VB64);   // slot beyond the FP32 MINRES vectors
     float* d32 = c32.v(VX64);
@@ -837,7 +825,7 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
     inf.rel_residual = bn > 0 ? std::sqrt(rn / bn) : std::sqrt(rn);
   }
   SolveParams P = solve_params(pb);
-  if (!pb->has_outlet) launch_pressure_mean(st, P, pb->p.rpmom, pb->p.rpconst, x, pb->p.red);
+  if (!pb->has_outlet) launch_pressure_mean(st, P, pb->p.rpmom, pb->p.rpconst, x, red);
   hipError_t he = hipStreamSynchronize(st);
   if (he != hipSuccess) {
     set_error("HIP error '%s' in solve", hipGetErrorString(he));
@@ -848,6 +836,35 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
   if (rc) set_error("solve: %s after %d iterations (rel %.3e)", mcs_status_string(rc), inf.iterations,
                     inf.rel_precond_residual);
   return rc;
+}
+
+
+int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* info) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  if (!pb->condensed) {
+    set_error("mcs_solve needs mcs_condense first");
+    return MCS_ERR_STATE;
+  }
+  if (!b || !x) {
+    set_error("null vector");
+    return MCS_ERR_ARG;
+  }
+  // pinned scalars of the host-side recurrences, released on every return path
+  struct Pinned {
+    double* p = nullptr;
+    ~Pinned() {
+      ApiLock lock(device_api_mutex());
+      if (p) hipHostFree(p);
+    }
+  } pin;
+  {
+    ApiLock lock(device_api_mutex());
+    HIPCHK(hipHostMalloc((void**)&pin.p, 64));
+  }
+  double* host_dev = nullptr;
+  HIPCHK(hipHostGetDevicePointer((void**)&host_dev, pin.p, 0));
+  return solve_rhs_run(pb, b, x, info, pb->p.red, pb->p.scal, pin.p, host_dev);
 }
 
 int mcs_solve(mcs_problem* pb, const double* f_lattice, double* x, mcs_solve_info* info) {
@@ -1033,10 +1050,28 @@ int mcs_set_launch_config(mcs_problem* pb, int dt, int32_t facets_per_block, int
     set_error("launch config: bad argument");
     return MCS_ERR_ARG;
   }
+  if (dt == MCS_F64 && pb->lean) {
+    set_error("launch config: precision 1 has no FP64 smoother");
+    return MCS_ERR_ARG;
+  }
   const int slot = dt == MCS_F64 ? 0 : 1;
   pb->tune_fpw[slot] = facets_per_block;
   pb->tune_cap[slot] = grid_cap;
   pb->tune_us[slot] = 0.0;
+  pb->tune_fixed[slot] = true;
+  return MCS_OK;
+}
+
+int mcs_set_solve_options(mcs_problem* pb, double tol, int32_t max_it, double inner_tol, int32_t max_outer) {
+  if (!pb || !std::isfinite(tol) || tol < 0.0 || max_it < 1 || !std::isfinite(inner_tol) || inner_tol < 0.0 ||
+      inner_tol >= 1.0 || max_outer < 1) {
+    set_error("solve options: bad argument");
+    return MCS_ERR_ARG;
+  }
+  pb->opt.tol = tol;
+  pb->opt.max_it = max_it;
+  pb->opt.inner_tol = inner_tol;
+  pb->opt.max_outer = max_outer;
   return MCS_OK;
 }
 

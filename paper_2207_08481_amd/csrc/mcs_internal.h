@@ -221,6 +221,7 @@ struct mcs_problem {
   int tune_fpw[2] = {1, 1};
   int64_t tune_cap[2] = {0, 0};
   double tune_us[2] = {0.0, 0.0};
+  bool tune_fixed[2] = {false, false};   // set by the caller: autotuning leaves the slot alone
   // kernel timer: [0] smoother phase launches, [1] K apply launches
   bool timer_on = false;
   int timer_period = 1;               // time one call in timer_period

@@ -20,6 +20,7 @@ OK = 0
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_MESH", -3: "ERR_WORKSPACE", -4: "ERR_NOT_SPD",
           -5: "ERR_NOT_CONVERGED", -6: "ERR_BREAKDOWN", -7: "ERR_NONFINITE", -8: "ERR_STATE",
           -9: "ERR_HIP", -10: "ERR_UNSUPPORTED"}
+STATUS_NOT_CONVERGED = -5
 F64, F32 = 0, 1
 OP = {"K": 0, "A": 1, "ADELTA": 2, "B": 3, "BT": 4}
 PC = {"KHAT": 0, "AEXT": 1, "ADELTA_MULT": 2, "SMOOTH_FWD": 3, "SMOOTH_BWD": 4, "AUX": 5,
@@ -30,7 +31,7 @@ SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs
            "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
                  "mcs_get_array",
            "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config",
-           "mcs_set_launch_config", "mcs_destroy",
+           "mcs_set_launch_config", "mcs_set_solve_options", "mcs_destroy",
            "mcs_status_string", "mcs_last_error",
            "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
            "mcs_batch_solve", "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable",
@@ -132,6 +133,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_timer_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_get_launch_config.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_set_launch_config.argtypes = [vp, i32, i32, i64]
+    lib.mcs_set_solve_options.argtypes = [vp, C.c_double, i32, C.c_double, i32]
     lib.mcs_batch_launch_config.argtypes = [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
                                             C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_destroy.argtypes = [vp]
@@ -161,7 +163,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
                  "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
                  "mcs_get_array",
-                 "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_set_launch_config", "mcs_batch_plan",
+                 "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_set_launch_config", "mcs_set_solve_options", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
                  "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable", "mcs_batch_timer_read",
                  "mcs_server_create",
@@ -280,19 +282,25 @@ class Problem:
         _check(self._lib.mcs_precond_apply(self._h, PC[op], self._dt(r), r.data_ptr(), z.data_ptr()))
         return z
 
-    def solve(self, f_lattice):
+    def solve(self, f_lattice, allow_max_it=False):
+        """(x, info).  With allow_max_it, a solve that stops at max_it
+        (MCS_ERR_NOT_CONVERGED) returns its last iterate instead of raising."""
         import torch
         f = torch.as_tensor(f_lattice, dtype=torch.float64, device=self.device).contiguous()
         x = self.vector()
         si = SolveInfo()
         rc = self._lib.mcs_solve(self._h, f.data_ptr(), x.data_ptr(), C.byref(si))
-        _check(rc)
+        if not (allow_max_it and rc == STATUS_NOT_CONVERGED):
+            _check(rc)
         return x, si.as_dict()
 
-    def solve_rhs(self, b):
+    def solve_rhs(self, b, allow_max_it=False):
+        """(x, info) for right-hand side b; allow_max_it as for solve()."""
         x = self.vector()
         si = SolveInfo()
-        _check(self._lib.mcs_solve_rhs(self._h, b.data_ptr(), x.data_ptr(), C.byref(si)))
+        rc = self._lib.mcs_solve_rhs(self._h, b.data_ptr(), x.data_ptr(), C.byref(si))
+        if not (allow_max_it and rc == STATUS_NOT_CONVERGED):
+            _check(rc)
         return x, si.as_dict()
 
     def eval(self, x, ref_pts):
@@ -362,8 +370,18 @@ class Problem:
         return {"facets_per_block": f.value, "grid_cap": c.value, "us_per_launch": us.value}
 
     def set_launch_config(self, facets_per_block, grid_cap=0, dt=F64):
-        """Fixes the colour phase's launch shape (until the next autotuned condense)."""
+        """Fixes the colour phase's launch shape for precision slot dt; the
+        autotuner leaves a slot set here alone.  dt=F64 on a precision 1
+        problem (no FP64 smoother) raises."""
         _check(self._lib.mcs_set_launch_config(self._h, dt, facets_per_block, grid_cap))
+
+    def set_solve_options(self, tol, max_it, inner_tol=None, max_outer=None):
+        """Stopping rules of later solves (tol, max_it, inner_tol, max_outer)."""
+        o = self._opt
+        inner = o.inner_tol if inner_tol is None else inner_tol
+        outer = o.max_outer if max_outer is None else max_outer
+        _check(self._lib.mcs_set_solve_options(self._h, tol, max_it, inner, outer))
+        o.tol, o.max_it, o.inner_tol, o.max_outer = tol, max_it, inner, outer
 
     def timer_enable(self, on=True, period=1):
         """Kernel timer on (one call in `period` is timed) or off."""

@@ -256,3 +256,25 @@ def test_launch_config_setter_validates():
             pb.set_launch_config(fpb, cap, dt)
         assert "ERR_ARG" in str(ex.value)
     assert pb.launch_config(F32)["facets_per_block"] == 2
+    # a precision 1 problem has no FP64 smoother: its FP64 slot is refused
+    lean = Problem(mesh.vertices, mesh.elements, mesh.lattice, 3, precision=1)
+    with pytest.raises(MCSError) as ex:
+        lean.set_launch_config(1, 0, F64)
+    assert "ERR_ARG" in str(ex.value)
+    lean.set_launch_config(2, 0, F32)
+    assert lean.launch_config(F32)["facets_per_block"] == 2
+
+
+def test_solve_options_setter_validates():
+    """mcs_set_solve_options changes tol, max_it, inner_tol and max_outer of a
+    planned problem; out-of-range values are refused with MCS_ERR_ARG (host
+    only)."""
+    from paper_2207_08481_amd.mcs import MCSError, Problem
+    mesh = W.unit_cube_mesh(1)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, precision=1)
+    pb.set_solve_options(0.0, 100, 0.0, 1)
+    for args in ((-1.0, 10, 0.0, 1), (float("nan"), 10, 0.0, 1), (1e-8, 0, 0.0, 1), (1e-8, 10, 1.0, 1),
+                 (1e-8, 10, -0.5, 1), (1e-8, 10, 1e-5, 0)):
+        with pytest.raises(MCSError) as ex:
+            pb.set_solve_options(*args)
+        assert "ERR_ARG" in str(ex.value)

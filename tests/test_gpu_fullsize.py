@@ -148,3 +148,39 @@ def test_cube32_k4_sampled_elements_and_apply():
     _check_apply(pb, elems, nb, 1e-5, torch.float32)
     del pb
     torch.cuda.empty_cache()
+
+
+def test_cube32_k4_mixed_precision_solve_matches_fp64():
+    """The mixed-precision 32^3 k = 4 solve of the benchmark (FP32 inner
+    MINRES, FP64 refinement, the workload's tolerance) against the FP64 GPU
+    solve of the same problem at tol 1e-10 (the FP64 path is pinned to the
+    oracle on small meshes): velocity and mean-free pressure within 1e-8
+    relative L2, by a degree-7 quadrature through mcs_eval."""
+    _need_gpu()
+    from paper_2207_08481_amd import Problem
+    from tests.quadrature import simplex_rule
+    wl = W.workload("cube32_k4_lognormal")
+    mesh, k, nu, f = wl["mesh"], wl["k"], wl["nu"], wl["f_lattice"]
+    pts, w = simplex_rule(3, 5)
+    ft = torch.as_tensor(f, device="cuda:0")
+    nut = torch.as_tensor(nu, device="cuda:0")
+    fields = []
+    for precision, tol in ((1, wl["tol"]), (0, 1e-10)):
+        print(f"[case] 32^3 x 6 tets, k={k}, precision {precision}, tol {tol}", flush=True)
+        pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, k, precision=precision, tol=tol,
+                     max_it=5000, autotune=1).bind("cuda:0")
+        pb.condense(nut)
+        x, si = pb.solve(ft)
+        print(f"  status {si['status']} iterations {si['iterations']} outer {si['outer_steps']} "
+              f"t {si['t_solve_ms']:.0f} ms", flush=True)
+        assert si["status"] == 0, si
+        u, p = pb.eval(x, pts)
+        fields.append((u.cpu(), p.cpu()))
+        del pb, x, u, p
+        torch.cuda.empty_cache()
+    (um, pm), (ud, pd) = fields
+    w = torch.as_tensor(w)
+    eu = ((w[None, :, None] * (um - ud) ** 2).sum() / (w[None, :, None] * ud ** 2).sum()).sqrt().item()
+    ep = ((w[None, :] * (pm - pd) ** 2).sum() / (w[None, :] * pd ** 2).sum()).sqrt().item()
+    print(f"  mixed against FP64: u {eu:.2e} p {ep:.2e}", flush=True)
+    assert eu < 1e-8 and ep < 1e-8, (eu, ep)
