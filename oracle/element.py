@@ -234,7 +234,7 @@ def lattice_bernstein(d, m, lattice_sorted):
 
 
 def element_system(X, nu, k, f_lattice_sorted=None, lattice_sorted=None, m=None,
-                   keep_blocks=False, pinned=()):
+                   keep_blocks=False, pinned=(), sigma_rotation_seed=None):
     """All element quantities of the hybridised MCS method on one element.
 
     Returns a dict with
@@ -249,12 +249,22 @@ def element_system(X, nu, k, f_lattice_sorted=None, lattice_sorted=None, m=None,
     zero (tangential dofs on an outlet facet); their rows and columns of A are
     replaced by those of the identity, so that they decouple before the
     bubbles are condensed.
+
+    sigma_rotation_seed: when given, Sigma_h(T) is represented in another
+    orthonormal basis, Z Q with Q a seeded random orthogonal matrix.  sigma and
+    omega are condensed, so the element operators do not depend on the basis
+    (Sec. 4.2); only their rounding changes.  Tests use it to measure how far
+    two FP64 computations of the same discrete problem drift apart.
     """
     ed = X if isinstance(X, ElementData) else element_geometry(X, k)
     d, nv = ed.d, ed.d + 1
     dims = ed.dims
     vol = ed.vol
     Z, Dm = sigma_space(ed)
+    if sigma_rotation_seed is not None:
+        g = np.random.default_rng(sigma_rotation_seed).standard_normal((Z.shape[1], Z.shape[1]))
+        Q, _ = np.linalg.qr(g)
+        Z = Z @ Q
     Kn = skew_basis(d)
     Ik = multi_indices(nv, k)
     nDm = len(Dm)

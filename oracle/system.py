@@ -38,7 +38,8 @@ def _lattice_indices(d, m):
 
 
 class GlobalSystem:
-    def __init__(self, vertices, elements, nu, k, f_lattice=None, m=None, face_bc=None, g_lattice=None):
+    def __init__(self, vertices, elements, nu, k, f_lattice=None, m=None, face_bc=None, g_lattice=None,
+                 sigma_rotation_seed=None):
         self.topo = topo = Topology(vertices, elements, face_bc)
         d = self.d = topo.dim
         self.k = k
@@ -67,7 +68,8 @@ class GlobalSystem:
                 ls = lat[:, topo.perm[e]]
             pinned = [n_u + i * nh + j for i in range(d + 1) if topo.facet_outlet[topo.elem_facets[e, i]]
                       for j in range(nh)]
-            es = element_system(ed, self.nu[e], k, fl, ls, self.m, pinned=pinned)
+            es = element_system(ed, self.nu[e], k, fl, ls, self.m, pinned=pinned,
+                                sigma_rotation_seed=sigma_rotation_seed)
             self.elems.append(es)
             xd = np.zeros(n_u + (d + 1) * nh)
             if g_lattice is not None:
