@@ -14,6 +14,14 @@ for the double Schur complement A^d -- oracle (FP64, sequential).
 * Additive variant (Sec. 5.2, the additive auxiliary-space preconditioner of
   Theorem aux_pc_schur): A-hat^d_a^{-1} = D^{-1} + E^d C^{-1} E^d^T with D the
   facet block Jacobi preconditioner, one block D_F per free facet.
+* l1 variant (the l1 block smoothers of the numerics of Sec. 7, in the
+  multiplicative ASP of Sec. 5.2): the facet block Gauss-Seidel sweeps are
+  replaced by facet block l1-Jacobi sweeps x += M^{-1} (s - A^d x) with
+  M = blockdiag(M_F), M_F = D_F + diag(l_F), l_i = sum over the free facet
+  dofs j outside the block of i of |a_ij| sqrt(a_ii / a_jj): the l1 row sums
+  of the diagonally scaled S^{-1} A^d S^{-1} (S = diag(A^d)^{1/2}) taken back
+  to the unscaled dofs, so that M does not depend on the scaling of the basis
+  (normal and tangential facet dofs scale differently in h).  A^d <= M.
 * Full-system variant (Sec. 5.2, Theorem aux_pc with the Gauss-Seidel form of
   Corollary aux_pc_mult; the paper's Table ST_full_vs_cond compares it with the
   condensed one): A-hat is applied to the whole velocity block A without the
@@ -287,7 +295,7 @@ def assemble_p1(gs):
 
 class Preconditioner:
     def __init__(self, gs, lattice, smoothing_steps=2, coarse_max=512, variant="multiplicative"):
-        assert variant in ("multiplicative", "additive", "full")
+        assert variant in ("multiplicative", "additive", "full", "l1")
         self.gs = gs
         topo = gs.topo
         d = gs.d
@@ -319,6 +327,32 @@ class Preconditioner:
         self.Mp_inv = [np.linalg.inv(es["Mp"]) for es in gs.elems]
         if variant == "full":
             self._setup_full()
+        if variant == "l1":
+            self._setup_l1()
+
+    def _setup_l1(self):
+        """l1 facet block Jacobi blocks M_F = D_F + diag(l_F) and their
+        inverses.  For two free dofs i, j of different blocks the pair adds
+        |a_ij| [[s_i/s_j, -sgn], [-sgn, s_j/s_i]] (s = sqrt(diag A^d)), a
+        positive semidefinite 2 x 2 form, to M - A^d: hence A^d <= M."""
+        gs, topo = self.gs, self.gs.topo
+        Ad = self.Ad.tocsr()
+        sq = np.sqrt(np.maximum(Ad.diagonal(), 0.0))
+        blk = np.full(gs.n_dof, -1)
+        for g in range(topo.n_free_facets):
+            blk[gs.facet_dofs(g)] = g
+        lsum = np.zeros(gs.n_dof)
+        for i in range(gs.off_f, gs.off_p):
+            for jj in range(Ad.indptr[i], Ad.indptr[i + 1]):
+                j = Ad.indices[jj]
+                if blk[j] != blk[i]:
+                    lsum[i] += abs(Ad.data[jj]) * sq[i] / sq[j]
+        self.l1_diag = lsum
+        self.Minv = []
+        for g in range(topo.n_free_facets):
+            fd = gs.facet_dofs(g)
+            M = Ad[fd][:, fd].toarray() + np.diag(lsum[fd])
+            self.Minv.append(np.linalg.inv(M))
 
     def _setup_full(self):
         """Velocity block A, overlapping facet blocks and their inverses, the
@@ -425,8 +459,37 @@ class Preconditioner:
         """A-hat^d_a^{-1} s = D^{-1} s + E^d C^{-1} E^d^T s."""
         return self.block_jacobi(s) + self.aux_correction(s)
 
+    def l1_jacobi(self, r):
+        """M^{-1} r, facet block by facet block (the l1 variant's smoother)."""
+        gs = self.gs
+        z = np.zeros_like(r)
+        for g in range(gs.topo.n_free_facets):
+            fd = gs.facet_dofs(g)
+            z[fd] = self.Minv[g] @ r[fd]
+        return z
+
+    def l1_sweep(self, x, s):
+        """One l1-Jacobi sweep x + M^{-1} (s - A^d x)."""
+        return x + self.l1_jacobi(s - self.Ad @ x)
+
+    def Ad_l1_inv(self, s):
+        """A-hat^d^{-1} s of the l1 variant: x^0 = 0; s l1-Jacobi sweeps; the
+        coarse correction on the residual; s l1-Jacobi sweeps (the smoother is
+        its own adjoint, so the operator is symmetric)."""
+        x = np.zeros_like(s)
+        for _ in range(self.steps):
+            x = self.l1_sweep(x, s)
+        x = x + self.aux_correction(s - self.Ad @ x)
+        for _ in range(self.steps):
+            x = self.l1_sweep(x, s)
+        return x
+
     def Ad_inv(self, s):
-        return self.Ad_add_inv(s) if self.variant == "additive" else self.Ad_mult_inv(s)
+        if self.variant == "additive":
+            return self.Ad_add_inv(s)
+        if self.variant == "l1":
+            return self.Ad_l1_inv(s)
+        return self.Ad_mult_inv(s)
 
     def A_ext_inv(self, r):
         """A-hat_ext^{-1} r for a velocity vector r (pressure part ignored/zero):
