@@ -66,6 +66,12 @@ WORKLOADS = {
     "channel_k3": ("channel_k3", 0, "plane channel 4 x 1 x 1 (40 x 10 x 10 cells x 6 tets = 24,000), k=3, nu=1e-3, "
                                     "parabolic profile as Dirichlet data on the inlet and z = 0, 1, no-slip plates, "
                                     "outlet Gamma_NT at x = 4, FP64, tol 1e-10", 1e-10),
+    "cube16_k3_l1": ("cube16_k3", 0, "unit cube 16^3 x 6 tets (24,576), k=3, nu=1, curl of 8 random sin^2 modes, "
+                                     "FP64, tol 1e-10; multiplicative auxiliary-space preconditioner with facet block "
+                                     "l1-Jacobi sweeps (no colour phases)", 1e-10),
+    "cube32_k4_mixed_l1": ("cube32_k4_lognormal", 1, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 "
+                           "contrast), random smooth f, FP32 inner MINRES + FP64 refinement, tol 1e-8; facet block "
+                           "l1-Jacobi sweeps", 1e-8),
     "cube16_k3_full": ("cube16_k3", 0, "unit cube 16^3 x 6 tets (24,576), k=3, nu=1, curl of 8 random sin^2 modes, "
                                        "FP64, tol 1e-10; full-system auxiliary-space preconditioner (overlapping "
                                        "facet blocks on A, no bubble factorisation in the preconditioner)", 1e-10),
@@ -470,7 +476,8 @@ def run_single(args, name, steps, warmup, block):
     mesh = wl["mesh"]
     k = wl["k"]
     dev = "cuda:0"
-    smoother = 1 if name.endswith("_additive") else 2 if name.endswith("_full") else 0
+    smoother = (1 if name.endswith("_additive") else 2 if name.endswith("_full") else
+                3 if name.endswith("_l1") else 0)
     pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, k, precision=precision,
                  tol=tol, max_it=5000, autotune=1, smoother=smoother, face_bc=wl.get("face_bc")).bind(dev)
     if wl.get("g_lattice") is not None:
@@ -584,7 +591,7 @@ def run_single(args, name, steps, warmup, block):
                                       "on A)"), "model_packed": None}
         secondary = roof("kapply", kapply_name)
     else:
-        # no Gauss-Seidel phases: the operator apply is the largest kernel
+        # no Gauss-Seidel phases (additive, l1): the operator apply is timed
         roof_main = roof("kapply", kapply_name)
     cfg = {"workload": desc, "n_dof": ndof, "tets": mesh.n_elements, "order": k,
            "iterations_per_step": its / steps, "t_sol_ms_per_step": t_sol / steps,

@@ -18,7 +18,7 @@ namespace mcs {
 int64_t offset_of(const mcs_problem* pb, const char* name);
 
 // work-vector slots
-enum { VX = 0, VR1, VR2, VY, VV, VW1, VW2, VKV, PA1, PG, PS, PT, PT1, PTMP, PB1, VB64, VR64, VX64, VT64, NVEC };
+enum { VX = 0, VR1, VR2, VY, VV, VW1, VW2, VKV, PA1, PG, PS, PT, PT1, PTMP, PB1, VB64, VR64, VX64, VT64, PZ, NVEC };
 
 template <typename T>
 T* ws_ptr(mcs_problem* pb, const char* name) {
@@ -206,12 +206,18 @@ struct Ctx {
     launch_mg_restrict<R>(st, d, L[l], L[l + 1]);
     vcycle(l + 1);
     launch_mg_prolong<R>(st, d, L[l], L[l + 1]);
+    // post-smoothing x += D^{-1} (b - A x): the residual first (mode 1 reads x,
+    // writes r), then the pointwise update (mode 2), so that no launch reads
+    // the x it writes
+    launch_mg_point<R>(st, d, L[l], 1);
     launch_mg_point<R>(st, d, L[l], 2);
   }
 
   // `smoothing_steps` block Gauss-Seidel sweeps on A^d (colours ascending or
-  // descending); y holds the element products A^d_T x_T and is kept current.
-  void sweeps(R* x, const R* s, R* y, bool forward) {
+  // descending); y holds the element products A^d_T x_T and is kept current,
+  // except by the very last colour phase when y_dead (the caller does not use
+  // y afterwards): that phase only updates x (launch_smooth_last).
+  void sweeps(R* x, const R* s, R* y, bool forward, bool y_dead = false) {
     SolveParams Pt = P;
     // the timer samples one call in timer_period (all launches of that call)
     const bool timed = pb->timer_on && pb->t_tick[0]++ % pb->timer_period == 0;
@@ -221,6 +227,10 @@ struct Ctx {
     for (int it = 0; it < pb->opt.smoothing_steps; ++it)
       for (int cc = 0; cc < pb->ncol; ++cc) {
         int c = forward ? cc : pb->ncol - 1 - cc;
+        if (y_dead && it == pb->opt.smoothing_steps - 1 && cc == pb->ncol - 1) {
+          launch_smooth_last<R>(st, P, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y);
+          continue;
+        }
         if (timed) {
           timer_start(pb, st, 0);
           launch_smooth_phase<R>(st, Pt, O, pb->colour_off[c], pb->colour_off[c + 1], x, s, y, fpw, cap);
@@ -245,6 +255,10 @@ struct Ctx {
   // Gauss-Seidel sweeps around the coarse correction) or additive
   // (D^{-1} s + E^d C^{-1} E^d^T s with the facet block Jacobi D).
   void ad_inv(const R* s, R* x) {
+    if (pb->opt.smoother == 3) {
+      ad_l1_inv(s, x);
+      return;
+    }
     if (pb->opt.smoother == 1) {
       launch_fill<R>(st, n, R(0), x);
       launch_block_jacobi<R>(st, P, O, s, x);
@@ -262,7 +276,38 @@ struct Ctx {
     launch_facet_sum<R>(st, P, escr, s, R(-1), tmp);
     aux(tmp, x, 1);
     launch_ycorr<R>(st, P, O.W, pb->p.elem_verts, pb->p.vfree_of_lat, (const R*)L[0].x, escr);
-    sweeps(x, s, escr, false);
+    sweeps(x, s, escr, false, true);   // the products are not needed after the last phase
+  }
+
+  // x = A-hat^d^{-1} s of the l1 variant (smoother 3): facet block l1-Jacobi
+  // sweeps x += M^{-1} (s - A^d x) (the facet blocks hold M_F^{-1}) around
+  // the coarse correction; the element scratch keeps the products A^d_T x_T
+  // (recomputed after a sweep, updated through W_T after the coarse
+  // correction).  The first sweep from x = 0 is x = M^{-1} s.
+  void ad_l1_inv(const R* s, R* x) {
+    R *tmp = v(PTMP), *z = v(PZ);
+    const int64_t of = pb->off_f, nf = (int64_t)pb->nff * pb->sz.nfb;
+    const int steps = pb->opt.smoothing_steps;
+    auto products = [&]() { launch_elem_apply<R>(st, P, O, x, tmp, escr, 1 | 8); };
+    auto sweep = [&]() {
+      launch_facet_sum<R>(st, P, escr, s, R(-1), tmp);
+      launch_block_jacobi<R>(st, P, O, tmp, z);
+      launch_axpby<R>(st, nf, 1.0, z + of, 1.0, x + of);
+    };
+    launch_fill<R>(st, n, R(0), x);
+    launch_block_jacobi<R>(st, P, O, s, x);
+    for (int it = 1; it < steps; ++it) {
+      products();
+      sweep();
+    }
+    products();
+    launch_facet_sum<R>(st, P, escr, s, R(-1), tmp);
+    aux(tmp, x, 1);
+    launch_ycorr<R>(st, P, O.W, pb->p.elem_verts, pb->p.vfree_of_lat, (const R*)L[0].x, escr);
+    for (int it = 0; it < steps; ++it) {
+      if (it > 0) products();
+      sweep();
+    }
   }
 
   FullDev full_dev() const {

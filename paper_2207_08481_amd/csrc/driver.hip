@@ -476,6 +476,16 @@ int mcs_condense(mcs_problem* pb, const double* nu) {
   F.EF = p.EF;
   F.EF32 = p.EF32;
   F.status = status;
+  F.elem_ff = p.elem_ff;
+  if (pb->opt.smoother == 3 && pb->nff > 0) {
+    // the facet blocks become M_F = D_F + diag(l_F) (l1-Jacobi); the FP64
+    // refinement slots are free during the condensation
+    Ctx<double> c(pb);
+    double* diag = c.v(VR64) + pb->off_f;
+    double* l1 = c.v(VT64) + pb->off_f;
+    launch_l1_terms(st, F, diag, l1);
+    F.l1diag = l1;
+  }
   if (pb->nff > 0) launch_facet_setup(st, F);
   launch_wsetup(st, F, p.elem_ff, pb->ne, p.W, p.W32);
   if (pb->opt.smoother == 2) {

@@ -71,6 +71,12 @@ struct FacetSetupParams {
   double* EF;
   float* EF32;
   int* status;
+  // smoother 3: the l1 terms added to the diagonal of each facet block before
+  // it is inverted ([free facet][n_fb], or nullptr), and the assembled
+  // diagonal of A^d they are computed from
+  const double* l1diag;
+  double* addiag;
+  const int32_t* elem_ff;
 };
 
 // One lattice block of a multigrid level (see MGBlock).

@@ -562,6 +562,53 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
 //   tangential rows: coefficient of lambda_v in degree k-1 times the
 //                    coordinates of P_t e_c in the tangent basis t_b.
 // --------------------------------------------------------------------------
+// l1 terms of the facet block l1-Jacobi smoother (smoother 3): for facet dof
+// i = (g, q), l_i = sum over the free dofs j of the other facets of its
+// neighbours of |a_ij| sqrt(a_ii / a_jj), a the assembled A^d (two facets
+// share at most one element, so a_ij is that element's entry).  Pass 0 forms
+// the assembled diagonal, pass 1 the sums.
+__device__ inline double ad_entry(const FacetSetupParams& P, size_t i) {
+  return P.Ad ? P.Ad[i] : (double)P.Adh[i] + (double)P.Adl[i];
+}
+__global__ void k_l1_terms(FacetSetupParams P, int pass, double* __restrict__ out) {
+  const Sizes s = P.s;
+  const int nfb = s.nfb, nd = s.nd, nv = s.d + 1;
+  const int64_t n = P.nff * nfb;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = idx / nfb;
+    const int q = (int)(idx % nfb);
+    double t = 0.0;
+    for (int side = 0; side < 2; ++side) {
+      const int64_t e = P.facet_el[2 * g + side];
+      if (e < 0) continue;
+      const int sl = P.facet_slot[2 * g + side];
+      const size_t row = (size_t)e * nd * nd + (size_t)(sl * nfb + q) * nd;
+      if (pass == 0) {
+        t += ad_entry(P, row + sl * nfb + q);
+        continue;
+      }
+      const double si = sqrt(P.addiag[idx]);
+      for (int h = 0; h < nv; ++h) {
+        if (h == sl) continue;
+        const int G = P.elem_ff[e * nv + h];
+        if (G < 0) continue;
+        for (int qq = 0; qq < nfb; ++qq)
+          t += fabs(ad_entry(P, row + h * nfb + qq)) * si / sqrt(P.addiag[(int64_t)G * nfb + qq]);
+      }
+    }
+    out[idx] = t;
+  }
+}
+
+void launch_l1_terms(hipStream_t st, const FacetSetupParams& P, double* diag, double* l1) {
+  const int64_t n = P.nff * P.s.nfb;
+  const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1 << 20))), b(256);
+  FacetSetupParams Q = P;
+  hipLaunchKernelGGL(k_l1_terms, g, b, 0, st, Q, 0, diag);
+  Q.addiag = diag;
+  hipLaunchKernelGGL(k_l1_terms, g, b, 0, st, Q, 1, l1);
+}
+
 __global__ void __launch_bounds__(256) k_facet_setup(FacetSetupParams P) {
   const Sizes s = P.s;
   const int d = s.d, nv = d + 1, nfb = s.nfb, nd = s.nd;
@@ -581,7 +628,7 @@ __global__ void __launch_bounds__(256) k_facet_setup(FacetSetupParams P) {
         const size_t ai = (size_t)e * nd * nd + (size_t)(sl * nfb + i) * nd + sl * nfb + j;
         t += P.Ad ? P.Ad[ai] : (double)P.Adh[ai] + (double)P.Adl[ai];
       }
-      S[i * FLD + j] = t;
+      S[i * FLD + j] = t + (i == j && P.l1diag ? P.l1diag[g * nfb + i] : 0.0);
     }
     __syncthreads();
     bool ok = block_cholesky(S, nfb, FLD);

@@ -537,6 +537,46 @@ __global__ void __launch_bounds__(256) k_smooth_y2(SolveParams P, OpPtrs<R> O, i
   }
 }
 
+// The last colour phase of a Gauss-Seidel application whose element products
+// are not used afterwards: x_F += D_F^{-1} (s_F - y_T1,F - y_T2,F) for the
+// facets of the colour, without reading the facets' rows of A^d or updating y.
+// One thread per row of a facet block; the block's residual and the packed
+// D_F^{-1} are summed in the order of the colour phase kernels, so x is
+// bitwise the x they give.
+template <typename R, int NFB, bool OUT>
+__global__ void __launch_bounds__(256) k_smooth_last(SolveParams P, OpPtrs<R> O, int32_t c0, int32_t c1,
+                                                     R* __restrict__ x, const R* __restrict__ srhs,
+                                                     const R* __restrict__ y) {
+  constexpr int NP = NFB * (NFB + 1) / 2;
+  const int nd = P.s.nd;
+  const int64_t n = (int64_t)(c1 - c0) * NFB;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ci = c0 + idx / NFB;
+    const int i = (int)(idx % NFB);
+    const int4 dsc = *reinterpret_cast<const int4*>(P.colour_desc + 4 * ci);
+    const int64_t g = dsc.x, e1 = dsc.y;
+    const int s1 = dsc.w & 0xFF;
+    const bool has2 = !OUT || dsc.z >= 0;
+    const int64_t e2 = has2 ? (int64_t)dsc.z : e1;
+    const int s2 = has2 ? (dsc.w >> 8) & 0xFF : s1;
+    if (P.active && facet_off(P, g)) continue;
+    const R* Di = O.DinvP + (size_t)g * NP;
+    const int64_t f0 = P.off_f + g * NFB;
+    const int rb = i * NFB - i * (i - 1) / 2 - i;
+    R acc = R(0);
+#pragma unroll
+    for (int j = 0; j < NFB; ++j) {
+      const R sv = srhs[f0 + j];
+      const R y1 = y[e1 * nd + s1 * NFB + j];
+      const R y2 = y[e2 * nd + s2 * NFB + j];
+      const R r = has2 ? sv - y1 - y2 : sv - y1;
+      const int pk = j < i ? j * NFB - j * (j - 1) / 2 - j + i : rb + j;
+      acc += Di[pk] * r;
+    }
+    x[f0 + i] = x[f0 + i] + acc;
+  }
+}
+
 // z_F = D_F^{-1} r_F for every free facet block: the facet block Jacobi of the
 // additive variant (Theorem aux_pc_schur); one thread per row of a block.
 template <typename R>
@@ -707,8 +747,9 @@ __device__ inline void mg_coords(int64_t v, const int* n, int c[3]) {
 
 // Multigrid kernels run over the lattice blocks of a level, one block per
 // blockIdx.y; vertex indices are block-local plus the block's offset.
-// mode 0: x = Dinv b;  mode 1: r = b - A x;  mode 2: x += Dinv (b - A x), on
-// the continuing blocks.  One 32-lane group per vertex, one stencil tap per lane.
+// mode 0: x = Dinv b;  mode 1: r = b - A x;  mode 2: x += Dinv r (pointwise,
+// r from a mode 1 launch: a Jacobi step never reads the x it writes), on the
+// continuing blocks.  One 32-lane group per vertex, one stencil tap per lane.
 template <typename R, int D>
 __global__ void __launch_bounds__(256) k_mg_point(MGLevelDev L, int mode) {
   constexpr int d = D, st = D == 3 ? 27 : 9, dd = D * D;
@@ -731,7 +772,7 @@ __global__ void __launch_bounds__(256) k_mg_point(MGLevelDev L, int mode) {
     if (lane == 0 && inner) {
 #pragma unroll
       for (int k = 0; k < 3; ++k)
-        if (k < d) bv[k] = b[v * d + k];
+        if (k < d) bv[k] = mode == 2 ? r[v * d + k] : b[v * d + k];
       if (mode != 1) {
 #pragma unroll
         for (int k = 0; k < 9; ++k)
@@ -744,7 +785,7 @@ __global__ void __launch_bounds__(256) k_mg_point(MGLevelDev L, int mode) {
       }
     }
     R part[3] = {R(0), R(0), R(0)};
-    if (inner && mode != 0 && lane < st) {
+    if (inner && mode == 1 && lane < st) {
       const int o = lane;
       int w[3] = {c[0] + o % 3 - 1, c[1] + (o / 3) % 3 - 1, d == 3 ? c[2] + o / 9 - 1 : 0};
       if (lat_free(w, B.n, d, B.ffm)) {
@@ -1404,6 +1445,31 @@ void launch_smooth_phase(hipStream_t st, const SolveParams& P, const OpPtrs<R>& 
     default: break;
   }
 }
+template <typename R, int NFB>
+static void smooth_last_launch(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
+                               const R* s, const R* y) {
+  const dim3 g(grid_for((int64_t)(c1 - c0) * NFB)), b(256);
+  if (P.has_outlet)
+    hipLaunchKernelGGL((k_smooth_last<R, NFB, true>), g, b, 0, st, P, O, c0, c1, x, s, y);
+  else
+    hipLaunchKernelGGL((k_smooth_last<R, NFB, false>), g, b, 0, st, P, O, c0, c1, x, s, y);
+}
+template <typename R>
+void launch_smooth_last(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
+                        const R* s, const R* y) {
+  if (c1 <= c0) return;
+  switch (P.s.nfb) {
+    case 5: smooth_last_launch<R, 5>(st, P, O, c0, c1, x, s, y); break;
+    case 7: smooth_last_launch<R, 7>(st, P, O, c0, c1, x, s, y); break;
+    case 9: smooth_last_launch<R, 9>(st, P, O, c0, c1, x, s, y); break;
+    case 11: smooth_last_launch<R, 11>(st, P, O, c0, c1, x, s, y); break;
+    case 12: smooth_last_launch<R, 12>(st, P, O, c0, c1, x, s, y); break;
+    case 22: smooth_last_launch<R, 22>(st, P, O, c0, c1, x, s, y); break;
+    case 35: smooth_last_launch<R, 35>(st, P, O, c0, c1, x, s, y); break;
+    case 51: smooth_last_launch<R, 51>(st, P, O, c0, c1, x, s, y); break;
+    default: break;
+  }
+}
 template <typename R>
 void launch_block_jacobi(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* z) {
   hipLaunchKernelGGL(k_block_jacobi<R>, dim3(grid_for(P.nff * P.s.nfb)), dim3(256), 0, st, P, O, r, z);
@@ -1525,6 +1591,8 @@ void launch_scale_convert(hipStream_t st, int64_t n, double a, const A* x, B* y,
   template void launch_smooth_phase<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, int32_t, int32_t, R*, \
                                        const R*, R*, int, int64_t);                                            \
   template void launch_block_jacobi<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, R*);      \
+  template void launch_smooth_last<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, int32_t, int32_t, R*,   \
+                                      const R*, const R*);                                                      \
   template void launch_ycorr<R>(hipStream_t, const SolveParams&, const R*, const int32_t*, const int32_t*,       \
                                 const R*, R*);                                                                  \
   template void launch_edt<R>(hipStream_t, const SolveParams&, const OpPtrs<R>&, const R*, R*, int64_t,         \

@@ -16,6 +16,14 @@ template <typename R>
 void launch_smooth_phase(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
                          const R* s, R* y, int facets_per_block = 1, int64_t grid_cap = 0);
 int smooth_team_threads(int nd);
+// Assembled diagonal of A^d on the facet dofs (diag) and the l1 terms of the
+// facet block l1-Jacobi smoother (l1), both [free facet][n_fb] doubles.
+void launch_l1_terms(hipStream_t st, const FacetSetupParams& P, double* diag, double* l1);
+// The last colour phase when the element products are not needed afterwards
+// (x only; bitwise the x of launch_smooth_phase).
+template <typename R>
+void launch_smooth_last(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, int32_t c0, int32_t c1, R* x,
+                        const R* s, const R* y);
 template <typename R>
 void launch_block_jacobi(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* z);
 template <typename R>

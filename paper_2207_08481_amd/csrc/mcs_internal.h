@@ -137,6 +137,7 @@ struct DevPtrs {
   double* DinvP;            // D_F^{-1} upper triangles, row-major packed (colour phases)
   float* DinvP32;
   float *Adl, *Hl, *Aool;   // low parts of the split storage (lean layout)
+
   double* adtmp;            // per-slot FP64 A^d buffer of the condensation (lean layout)
   // multigrid coarsest
   double* Cinv;           // [nc][nc]

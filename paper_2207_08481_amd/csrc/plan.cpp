@@ -153,9 +153,9 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
     set_error("precision must be 0 or 1");
     return MCS_ERR_ARG;
   }
-  if (pb->opt.smoother < 0 || pb->opt.smoother > 2) {
-    set_error("smoother must be 0 (multiplicative, block Gauss-Seidel), 1 (additive, facet block Jacobi) or 2 "
-              "(full system, overlapping block Gauss-Seidel)");
+  if (pb->opt.smoother < 0 || pb->opt.smoother > 3) {
+    set_error("smoother must be 0 (multiplicative, block Gauss-Seidel), 1 (additive, facet block Jacobi), 2 "
+              "(full system, overlapping block Gauss-Seidel) or 3 (multiplicative, facet block l1-Jacobi)");
     return MCS_ERR_ARG;
   }
   pb->sz = make_sizes(d, k);

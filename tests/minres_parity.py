@@ -77,3 +77,36 @@ def check_equal_iterations(gs, x_gpu, x_oracle, n_it, twin):
           f"oracle twin (rotated Sigma basis, permuted numbering): u {du:.2e} p {dp:.2e}", flush=True)
     assert eu < max(1e-12, 10 * du) and ep < max(1e-12, 10 * dp), out
     return out
+
+
+def twin_iterations(gs, twin, tol, seeds=(0, 1)):
+    """MINRES iteration counts of the oracle's twin at tol, one per random dof
+    numbering."""
+    from oracle.minres import minres
+    K, pc_apply, b = twin()
+    out = []
+    for seed in seeds:
+        perm = np.random.default_rng(seed).permutation(gs.n_dof)
+        Kp = K[perm][:, perm].tocsr()
+
+        def Mp(r, perm=perm):
+            z = np.zeros(gs.n_dof)
+            z[perm] = r
+            return pc_apply(z)[perm]
+
+        _, info = minres(lambda v: Kp @ v, Mp, b[perm], tol=tol, max_it=5000)
+        out.append(info["iterations"])
+    return out
+
+
+def check_iterations(gs, its_gpu, its_oracle, twin, tol=1e-10):
+    """Iterations within +-1 of the oracle's, or, where they are not, within
+    +-1 of the range the oracle's twins (rotated Sigma basis, permuted
+    numberings) span: slowly converging runs move by a few iterations under
+    FP64 rounding alone."""
+    if abs(its_gpu - its_oracle) <= 1:
+        return
+    tw = twin_iterations(gs, twin, tol)
+    lo, hi = min([its_oracle] + tw), max([its_oracle] + tw)
+    print(f"[parity] iterations gpu {its_gpu} oracle {its_oracle}; oracle twins {tw}", flush=True)
+    assert lo - 1 <= its_gpu <= hi + 1, (its_gpu, its_oracle, tw)

@@ -115,11 +115,12 @@ def test_error_codes():
     with pytest.raises(MCSError) as ex:
         Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, precision=3)
     assert ex.value.status == -1
-    # smoother options: 0..2; the full-system variant needs precision 0 and
+    # smoother options: 0..3; the full-system variant needs precision 0 and
     # blocks of at most 64 dofs (3D: k <= 3)
     with pytest.raises(MCSError) as ex:
-        Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, smoother=3)
+        Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, smoother=4)
     assert ex.value.status == -1
+    Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, smoother=3, precision=1).close()
     with pytest.raises(MCSError) as ex:
         Problem(mesh.vertices, mesh.elements, mesh.lattice, 2, precision=1, smoother=2)
     assert ex.value.status == -10

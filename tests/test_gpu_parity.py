@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.minres_parity import check_equal_iterations, oracle_twin
+from tests.minres_parity import check_equal_iterations, check_iterations, oracle_twin
 
 pytestmark = pytest.mark.gpu
 
@@ -497,6 +497,76 @@ def test_additive_variant_parity(d, n, k, cm):
     assert sin["iterations"] == ito
     check_equal_iterations(gs, xn.cpu().numpy(), xo, ito,
                            oracle_twin(m, c["nu"], k, c["f"], coarse_max=cm, variant="additive"))
+
+
+@pytest.mark.parametrize("d,n,k,cm", [(2, 4, 2, 20), (3, 2, 2, 512), (3, 2, 3, 512), (3, 4, 2, 20)])
+def test_l1_variant_parity(d, n, k, cm):
+    """smoother = 3 (multiplicative auxiliary-space preconditioner with facet
+    block l1-Jacobi sweeps) against the oracle's l1 variant: A-hat^d^{-1},
+    A-hat_ext^{-1}, K-hat^{-1} (FP64 and FP32), and a solve: MINRES iterations
+    within +-1 (or of the range of the oracle's twins: this preconditioner
+    converges slowly, and the oracle itself moves by up to 3 iterations under
+    another rounding) and, at the oracle's iteration count, the
+    equal-iteration bar."""
+    _need_gpu()
+    from paper_2207_08481_amd import Problem
+    from oracle.precond import Preconditioner
+    from oracle.minres import minres
+    c = setup_case(d, n, k, coarse_max=cm)
+    gs, m = c["gs"], c["mesh"]
+    print(f"[case] l1 variant d={d} n={n} k={k} cm={cm}", flush=True)
+    pc = Preconditioner(gs, m.lattice, coarse_max=cm, variant="l1")
+    pb = Problem(m.vertices, m.elements, m.lattice, k, coarse_max=cm, smoother=3, tol=1e-10,
+                 max_it=3000).bind("cuda:0")
+    pb.condense(torch.as_tensor(c["nu"], device="cuda:0"))
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal(gs.n_dof)
+    rt = torch.as_tensor(r, device="cuda:0")
+    fd = slice(gs.off_f, gs.off_p)
+    rr = r.copy()
+    rr[:gs.off_f] = 0
+    rr[gs.off_p:] = 0
+    z = pb.precond_apply("ADELTA_MULT", rt).cpu().numpy()
+    assert _rel(z[fd], pc.Ad_l1_inv(rr)[fd]) < 1e-11
+    ru = r.copy()
+    ru[gs.off_p:] = 0
+    z = pb.precond_apply("AEXT", rt).cpu().numpy()
+    assert _rel(z[:gs.off_p], pc.A_ext_inv(ru)[:gs.off_p]) < 1e-11
+    ref = pc.apply(r.copy())
+    z = pb.precond_apply("KHAT", rt).cpu().numpy()
+    assert _rel(z, ref) < 1e-11
+    z32 = pb.precond_apply("KHAT", rt.float()).double().cpu().numpy()
+    assert _rel(z32, ref) < 1e-4
+    K = c["K"]
+    xo, info = minres(lambda v: K @ v, pc.apply, gs.assemble_rhs(), tol=1e-10, max_it=3000)
+    xo = gs.normalize_pressure(xo)
+    f = torch.as_tensor(c["f"], device="cuda:0")
+    x, si = pb.solve(f)
+    assert si["status"] == 0
+    its, ito = si["iterations"], info["iterations"]
+    print(f"[case] l1 iterations gpu {its} oracle {ito}", flush=True)
+    twin = oracle_twin(m, c["nu"], k, c["f"], coarse_max=cm, variant="l1")
+    check_iterations(gs, its, ito, twin)
+    pb.set_solve_options(0.0, ito)
+    xn, sin = pb.solve(f, allow_max_it=True)
+    assert sin["iterations"] == ito
+    check_equal_iterations(gs, xn.cpu().numpy(), xo, ito, twin)
+
+
+def test_l1_variant_mixed_precision():
+    """smoother = 3 with FP32 inner MINRES and FP64 refinement reaches 1e-8
+    relative L2 against the oracle's direct solve."""
+    _need_gpu()
+    from paper_2207_08481_amd import Problem
+    c = setup_case(3, 2, 3)
+    gs, m = c["gs"], c["mesh"]
+    pb = Problem(m.vertices, m.elements, m.lattice, 3, precision=1, smoother=3, tol=1e-10,
+                 max_it=3000).bind("cuda:0")
+    pb.condense(torch.as_tensor(c["nu"], device="cuda:0"))
+    x, si = pb.solve(torch.as_tensor(c["f"], device="cuda:0"))
+    assert si["status"] == 0, si
+    eu, ep = _l2_rel(gs, x.cpu().numpy(), gs.direct_solve())
+    assert eu < 1e-8 and ep < 1e-8, (eu, ep, si)
 
 
 def test_kernel_timer_counts():
