@@ -570,10 +570,11 @@ def test_l1_variant_mixed_precision():
 
 
 def test_kernel_timer_counts():
-    """The measurement hook: smoother phase launches come in whole sweeps
-    (smoothing_steps x n_colours per A-hat^d_m application, four applications
-    per K-hat^{-1}), one operator apply per MINRES iteration (and one for the
-    final true residual), and the bytes of
+    """The measurement hook: smoother phase launches come in whole
+    applications of A-hat^d_m (2 smoothing_steps n_colours colour phases, of
+    which the last one, which does not update the element products, is not
+    timed; two applications per K-hat^{-1}), one operator apply per MINRES
+    iteration (and one for the final true residual), and the bytes of
     the operator apply are launches x elements x the per-element count
     (n_d^2 + n_b n_d + n_b^2 + 2 (n_d + n_b + n_p)) words + 4 (d+1) + 8."""
     c = setup_case(3, 2, 3)
@@ -584,8 +585,8 @@ def test_kernel_timer_counts():
     ka = pb.timer_read("kapply")
     pb.timer_enable(False)
     assert si["status"] == 0
-    per_pc = 4 * 2 * info.n_colours
-    assert sm[1] > 0 and sm[1] % per_pc == 0 and sm[0] > 0
+    per_pc = 2 * (2 * 2 * info.n_colours - 1)
+    assert sm[1] > 0 and sm[1] % per_pc == 0 and sm[1] // per_pc == si["iterations"] + 1 and sm[0] > 0
     # one apply per iteration and one for the true residual b - K x at the end
     assert ka[1] == si["iterations"] + 1 and ka[0] > 0
     nb, nfb, npr = info.n_bub, info.n_fb, info.n_p
