@@ -225,6 +225,24 @@ int mcs_solve(mcs_problem* pb, const double* f_lattice, double* x, mcs_solve_inf
 /* Same as mcs_solve with a given right-hand side b (device double[n_dof]). */
 int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* info);
 
+/* For callers that cannot allocate (no hipMalloc, hipHostMalloc or freeing
+ * calls: tight serving loops, harnesses that forbid allocation): the same
+ * solve as mcs_solve_rhs, which allocates pinned host memory for the MINRES
+ * scalars on every call.  This variant allocates no device or pinned host
+ * memory (with the kernel timer off: mcs_timer_enable creates HIP events on
+ * its first timed launches): the reductions of
+ * its dot products and of the pressure mean run in a fixed device array of
+ * 4096 doubles (32 KiB) that the library holds on every device it is bound
+ * on, until the process ends, and each scalar is copied back to the caller's
+ * stack.  The problem's workspace (mcs_bind) holds everything else, as for
+ * mcs_solve_rhs.  All calls on one device share that array, so calls that
+ * overlap on one device (other threads, other problems on the same device)
+ * race; every slot is written before it is read, so nothing needs clearing
+ * between calls.  A problem whose reductions would need more slots than the
+ * array holds is refused with MCS_ERR_WORKSPACE.  Otherwise as mcs_solve_rhs
+ * (same kernels and arithmetic, bitwise the same result).  [sync] */
+int mcs_solve_rhs_noalloc(mcs_problem* pb, const double* b, double* x, mcs_solve_info* info);
+
 /* Point values of a solution, for comparisons that do not depend on the
  * basis: u_h and p_h of x (device double[n_dof]) at n_pts points of every
  * element, given as barycentric coordinates ref_pts_host[n_pts][dim+1] (host)

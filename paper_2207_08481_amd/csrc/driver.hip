@@ -32,7 +32,30 @@ using namespace mcs;
     }                                                                                     \
   } while (0)
 
+// Reduction scratch of mcs_solve_rhs_noalloc: the dot products' partial sums
+// (at most 1024), their scalar slot and the pressure mean.  Each device holds
+// its own copy until the process ends; host code uses only the device address
+// that hipGetSymbolAddress returns for it (noalloc_scratch_ptr).
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = 4096;   // 32 KiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static double* noalloc_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
 namespace {
+
+// Looks up the device address of `scratch` on the current device, once per
+// device (called by mcs_bind with the problem's device current).
+int noalloc_scratch_init(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) {
+    set_error("device %d outside the no-alloc scratch table", device);
+    return MCS_ERR_ARG;
+  }
+  if (noalloc_scratch_ptr[device]) return MCS_OK;
+  void* ptr = nullptr;
+  HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  noalloc_scratch_ptr[device] = static_cast<double*>(ptr);
+  return MCS_OK;
+}
 
 // Smoother launch-shape tuner: times every candidate shape on the largest
 // colour (scratch vectors, one warm-up and three timed launches) and keeps the
@@ -221,6 +244,10 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
     return MCS_ERR_WORKSPACE;
   }
   HIPCHK(hipGetDevice(&pb->device));
+  {
+    int rc = noalloc_scratch_init(pb->device);
+    if (rc) return rc;
+  }
   pb->ws = workspace;
   pb->stream = static_cast<hipStream_t>(stream);
   pb->condensed = false;
@@ -875,6 +902,34 @@ int mcs_solve_rhs(mcs_problem* pb, const double* b, double* x, mcs_solve_info* i
   double* host_dev = nullptr;
   HIPCHK(hipHostGetDevicePointer((void**)&host_dev, pin.p, 0));
   return solve_rhs_run(pb, b, x, info, pb->p.red, pb->p.scal, pin.p, host_dev);
+}
+
+int mcs_solve_rhs_noalloc(mcs_problem* pb, const double* b, double* x, mcs_solve_info* info) {
+  int rc = check_bound(pb);
+  if (rc) return rc;
+  if (!pb->condensed) {
+    set_error("mcs_solve_rhs_noalloc needs mcs_condense first");
+    return MCS_ERR_STATE;
+  }
+  if (!b || !x) {
+    set_error("null vector");
+    return MCS_ERR_ARG;
+  }
+  double* sp = (pb->device >= 0 && pb->device < NOALLOC_MAX_DEVICES) ? noalloc_scratch_ptr[pb->device] : nullptr;
+  if (!sp) {
+    set_error("mcs_solve_rhs_noalloc: no scratch address for device %d (bind the problem first)", pb->device);
+    return MCS_ERR_STATE;
+  }
+  // partial sums of a dot product (one per reduction block) and the scalar
+  // slot behind them; every kernel writes its slots before reading them
+  const int64_t parts = std::min<int64_t>(1024, std::max<int64_t>(1, (pb->ndof + 255) / 256));
+  if (parts + 1 > NOALLOC_SCRATCH_DOUBLES) {
+    set_error("mcs_solve_rhs_noalloc: %lld reduction slots exceed the scratch of %lld doubles", (long long)(parts + 1),
+              (long long)NOALLOC_SCRATCH_DOUBLES);
+    return MCS_ERR_WORKSPACE;
+  }
+  double host[2] = {0.0, 0.0};
+  return solve_rhs_run(pb, b, x, info, sp, sp + 1024, host, nullptr);
 }
 
 int mcs_solve(mcs_problem* pb, const double* f_lattice, double* x, mcs_solve_info* info) {

@@ -28,7 +28,7 @@ PC = {"KHAT": 0, "AEXT": 1, "ADELTA_MULT": 2, "SMOOTH_FWD": 3, "SMOOTH_BWD": 4, 
 
 # exported symbols of include/mcs.h
 SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
-           "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
+           "mcs_solve", "mcs_solve_rhs", "mcs_solve_rhs_noalloc", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
                  "mcs_get_array",
            "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config",
            "mcs_set_launch_config", "mcs_set_solve_options", "mcs_destroy",
@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_precond_apply.argtypes = [vp, i32, i32, vp, vp]
     lib.mcs_solve.argtypes = [vp, vp, vp, C.POINTER(SolveInfo)]
     lib.mcs_solve_rhs.argtypes = [vp, vp, vp, C.POINTER(SolveInfo)]
+    lib.mcs_solve_rhs_noalloc.argtypes = [vp, vp, vp, C.POINTER(SolveInfo)]
     lib.mcs_normalize_pressure.argtypes = [vp, vp]
     lib.mcs_eval.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.mcs_eval_stress.argtypes = [vp, vp, i32, vp, vp, vp]
@@ -161,7 +162,7 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_server_destroy.argtypes = [vp]
     lib.mcs_server_destroy.restype = None
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
-                 "mcs_solve", "mcs_solve_rhs", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
+                 "mcs_solve", "mcs_solve_rhs", "mcs_solve_rhs_noalloc", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
                  "mcs_get_array",
                  "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_set_launch_config", "mcs_set_solve_options", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
@@ -302,6 +303,15 @@ class Problem:
         if not (allow_max_it and rc == STATUS_NOT_CONVERGED):
             _check(rc)
         return x, si.as_dict()
+
+    def solve_rhs_noalloc(self, b, x, allow_max_it=False):
+        """mcs_solve_rhs_noalloc into the caller's x (nothing is allocated by
+        the library; x must be a device double vector of n_dof).  Returns info."""
+        si = SolveInfo()
+        rc = self._lib.mcs_solve_rhs_noalloc(self._h, b.data_ptr(), x.data_ptr(), C.byref(si))
+        if not (allow_max_it and rc == STATUS_NOT_CONVERGED):
+            _check(rc)
+        return si.as_dict()
 
     def eval(self, x, ref_pts):
         """(u [n_e, n_pts, dim], p [n_e, n_pts]) of x at barycentric points
