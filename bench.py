@@ -510,15 +510,16 @@ def run_single(args, name, steps, warmup, block):
     if block:
         t_sup = condense()
         b = pb.load(f)
-        x, si = pb.solve_rhs(b)
-        torch.cuda.synchronize()
-        full = {"iterations": si["iterations"], "outer_steps": si["outer_steps"], "t_sol_ms": si["t_solve_ms"],
-                "t_sup_ms": t_sup, "tol": tol, "rel_precond_residual": si["rel_precond_residual"],
-                "rel_residual": si["rel_residual"],
-                "dof_iterations_per_s": ndof * si["iterations"] / (si["t_solve_ms"] / 1e3)}
-        log(f"complete solve: setup {t_sup:.1f} ms, {si['iterations']} iterations in {si['outer_steps']} "
-            f"refinement steps, solve {si['t_solve_ms']:.1f} ms, rel residual {si['rel_residual']:.2e}")
-        del x
+        if not args.no_complete_solve:
+            x, si = pb.solve_rhs(b)
+            torch.cuda.synchronize()
+            full = {"iterations": si["iterations"], "outer_steps": si["outer_steps"], "t_sol_ms": si["t_solve_ms"],
+                    "t_sup_ms": t_sup, "tol": tol, "rel_precond_residual": si["rel_precond_residual"],
+                    "rel_residual": si["rel_residual"],
+                    "dof_iterations_per_s": ndof * si["iterations"] / (si["t_solve_ms"] / 1e3)}
+            log(f"complete solve: setup {t_sup:.1f} ms, {si['iterations']} iterations in {si['outer_steps']} "
+                f"refinement steps, solve {si['t_solve_ms']:.1f} ms, rel residual {si['rel_residual']:.2e}")
+            del x
         pb.set_solve_options(0.0, block, 0.0, 1)
 
         def step():
@@ -640,6 +641,8 @@ def main():
     ap.add_argument("--block", type=int, default=100,
                     help="cube32_k4_mixed: inner iterations per step (0: a step is a complete solve)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 16^3 k = 3 FP64 line beside the default")
+    ap.add_argument("--no-complete-solve", action="store_true",
+                    help="block steps without the untimed complete solve first (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (calibrates "

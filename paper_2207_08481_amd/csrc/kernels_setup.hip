@@ -1434,26 +1434,42 @@ __global__ void __launch_bounds__(256) k_wsetup(FacetSetupParams P, const int32_
                                                 double* __restrict__ W, float* __restrict__ W32) {
   const Sizes s = P.s;
   const int d = s.d, nv = d + 1, nvd = nv * d, nd = s.nd, nfb = s.nfb, dd = d * d;
+  // the element's facet blocks E_F (zero for Dirichlet facets); each thread
+  // takes one row t of A^d (read once, as column t: consecutive threads read
+  // consecutive words) and forms all (d + 1) d entries W[m][t]
+  __shared__ double Es[4 * 51 * 9];
   for (int64_t e = blockIdx.x; e < ne; e += gridDim.x) {
-    for (int idx = threadIdx.x; idx < nd * nvd; idx += blockDim.x) {
-      const int m = idx / nd, t = idx % nd;
-      const int vl = m / d, c = m % d;
-      const size_t a0 = ((size_t)e * nd + t) * nd;
-      double acc = 0.0;
+    for (int i = threadIdx.x; i < nv * nfb * dd; i += blockDim.x) {
+      const int f = i / (nfb * dd), r = i % (nfb * dd);
+      const int g = elem_ff[e * nv + f];
+      Es[i] = g >= 0 ? P.EF[(size_t)g * nfb * dd + r] : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+      double acc[12];
+#pragma unroll
+      for (int m = 0; m < 12; ++m) acc[m] = 0.0;
       for (int f = 0; f < nv; ++f) {
-        const int g = elem_ff[e * nv + f];
-        if (g < 0 || vl == f) continue;
-        const int v = vl < f ? vl : vl - 1;
-        const double* E = P.EF + (size_t)g * nfb * dd + v * d + c;
         for (int q = 0; q < nfb; ++q) {
-          const size_t ai = a0 + f * nfb + q;
+          const size_t ai = ((size_t)e * nd + f * nfb + q) * nd + t;
           const double a = P.Ad ? P.Ad[ai] : (double)P.Adh[ai] + (double)P.Adl[ai];
-          acc += a * E[(size_t)q * dd];
+          const double* Eq = Es + (f * nfb + q) * dd;
+#pragma unroll
+          for (int m = 0; m < 12; ++m) {
+            if (m >= nvd) break;
+            const int vl = m / d, c = m % d;
+            if (vl == f) continue;
+            const int v = vl < f ? vl : vl - 1;
+            acc[m] += a * Eq[v * d + c];
+          }
         }
       }
-      if (W) W[((size_t)e * nvd + m) * nd + t] = acc;
-      W32[((size_t)e * nvd + m) * nd + t] = (float)acc;
+      for (int m = 0; m < nvd; ++m) {
+        if (W) W[((size_t)e * nvd + m) * nd + t] = acc[m];
+        W32[((size_t)e * nvd + m) * nd + t] = (float)acc[m];
+      }
     }
+    __syncthreads();
   }
 }
 
