@@ -58,7 +58,8 @@ __device__ inline R group_sum(R v) {
 // contiguous columns); epi(i, sum) runs on the group's first lane.  The row
 // loop is uniform over the participating waves (t0, nthr multiples of 64).
 template <int L, typename MA, typename R, typename F>
-__device__ inline void rows_times(MA M, size_t m0, int nrow, int ncol, const R* v, int t0, int nthr, F epi) {
+__device__ inline void rows_times(MA M, size_t m0, int nrow, int ncol, const R* v, int t0, int nthr, F epi,
+                                  R* keep = nullptr, int ldk = 0) {
   const int t = threadIdx.x - t0;
   const int g = t / L, l = t % L, ng = nthr / L;
   for (int i0 = 0; i0 < nrow; i0 += ng) {
@@ -66,7 +67,16 @@ __device__ inline void rows_times(MA M, size_t m0, int nrow, int ncol, const R* 
     R acc = R(0);
     if (i < nrow) {
       const size_t mi = m0 + (size_t)i * ncol;
-      for (int j = l; j < ncol; j += L) acc += M(mi + j) * v[j];
+      if (keep) {
+        // the matrix entries are also kept in LDS (row stride ldk) for a later product
+        for (int j = l; j < ncol; j += L) {
+          const R m = M(mi + j);
+          keep[i * ldk + j] = m;
+          acc += m * v[j];
+        }
+      } else {
+        for (int j = l; j < ncol; j += L) acc += M(mi + j) * v[j];
+      }
     }
     acc = group_sum<L>(acc);
     if (l == 0 && i < nrow) epi(i, acc);
@@ -99,8 +109,12 @@ __device__ inline void build_rowmap(const Sizes& s, int* rmap) {
 // B_T[q][row] = -s |det J| Bp^[q][iu(row)] (s = 1 bubble, 1/det J facet row).
 template <typename R, typename MA, int FL, int CP>
 __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH, MA MAoo, const R* __restrict__ x,
-                                                    R* __restrict__ y, R* __restrict__ escr, int flags) {
+                                                    R* __restrict__ y, R* __restrict__ escr, int flags, int ldh) {
   if constexpr (FL >= 0) flags = FL;   // specialised instantiations fold the flag tests
+  // ldh > 0 (instantiations with CP > 1): H is read once; the rows read for
+  // z_o = x_o + H x_d are kept in LDS (row stride ldh) for H^T w_o
+  extern __shared__ __align__(16) unsigned char ea_lds[];
+  R* sH = (CP > 1 && ldh > 0) ? reinterpret_cast<R*>(ea_lds) : nullptr;
   const Sizes s = P.s;
   const int nb = s.nb, nd = s.nd, np = s.np, nu = s.nu;
   __shared__ R xd[MAXND], xo[MAXNB], zo[MAXNB], wo[MAXNB];
@@ -154,9 +168,9 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
     } else if (doH && overlap && tid >= tA) {
       // one wave left for H (n_d > 128): 4-lane groups, 16 rows at a time
       if (256 - tA >= 128)
-        rows_times<16>(MH, h0, nb, nd, xd, tA, 256 - tA, [&](int i, R v) { zo[i] = xo[i] + v; });
+        rows_times<16>(MH, h0, nb, nd, xd, tA, 256 - tA, [&](int i, R v) { zo[i] = xo[i] + v; }, sH, ldh);
       else
-        rows_times<4>(MH, h0, nb, nd, xd, tA, 256 - tA, [&](int i, R v) { zo[i] = xo[i] + v; });
+        rows_times<4>(MH, h0, nb, nd, xd, tA, 256 - tA, [&](int i, R v) { zo[i] = xo[i] + v; }, sH, ldh);
     }
     if (doBu) {
       for (int row = tid; row < nb + nd; row += blockDim.x) {
@@ -166,7 +180,7 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
     }
     if (doH && !overlap) {
       __syncthreads();
-      rows_times<16>(MH, h0, nb, nd, xd, 0, 256, [&](int i, R v) { zo[i] = xo[i] + v; });
+      rows_times<16>(MH, h0, nb, nd, xd, 0, 256, [&](int i, R v) { zo[i] = xo[i] + v; }, sH, ldh);
     }
     __syncthreads();
     if (doH) {
@@ -176,8 +190,13 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
     if (tid < nd) {
       if constexpr (CP > 1) acc = doA ? adx[tid] : R(0);
       if (doH) {
+        if (sH) {
 #pragma unroll 4
-        for (int i = 0; i < nb; ++i) acc += MH(h0 + tid + (size_t)i * nd) * wo[i];
+          for (int i = 0; i < nb; ++i) acc += sH[i * ldh + tid] * wo[i];
+        } else {
+#pragma unroll 4
+          for (int i = 0; i < nb; ++i) acc += MH(h0 + tid + (size_t)i * nd) * wo[i];
+        }
       }
       if (doBT) {
         const int iu = rmap[nb + tid];
@@ -1337,24 +1356,29 @@ static void elem_apply_launch(hipStream_t st, const SolveParams& P, MA Ad, MA H,
   // even n_d takes two rows of A^d per thread
   const dim3 g(elem_grid(P.ne)), b(256);
   if constexpr (std::is_same<MA, MatP<R>>::value) {
+    // H read once through LDS when its rows fit 64 KiB (k <= 4)
+    const int ldh = P.s.nd | 1;
+    const size_t hb = (size_t)P.s.nb * ldh * sizeof(R);
+    const int hl = hb <= 65536 ? ldh : 0;
+    const size_t lds = hl ? hb : 0;
     // FP32 with n_d divisible by 4: four rows per thread (16-byte loads)
     if constexpr (sizeof(R) == 4) {
       if (flags == (1 | 2 | 4) && P.s.nd % 4 == 0) {
-        hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 4>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags);
+        hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 4>), g, b, lds, st, P, Ad, H, Aoo, x, y, escr, flags, hl);
         return;
       }
     }
     if (flags == (1 | 2 | 4) && P.s.nd % 2 == 0) {
-      hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 2>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags);
+      hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 2>), g, b, lds, st, P, Ad, H, Aoo, x, y, escr, flags, hl);
       return;
     }
   }
   if (flags == (1 | 2 | 4))
-    hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags);
+    hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags, 0);
   else if (flags == (2 | 16))
-    hipLaunchKernelGGL((k_elem_apply<R, MA, 18, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags);
+    hipLaunchKernelGGL((k_elem_apply<R, MA, 18, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags, 0);
   else
-    hipLaunchKernelGGL((k_elem_apply<R, MA, -1, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags);
+    hipLaunchKernelGGL((k_elem_apply<R, MA, -1, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags, 0);
 }
 template <typename R>
 void launch_elem_apply(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* x, R* y, R* escr, int flags) {
@@ -1374,6 +1398,8 @@ template <typename R>
 void launch_ext_pre(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* to, R* escr) {
   if (P.s.nb <= 24 && P.s.nd + P.s.nb <= 256)
     hipLaunchKernelGGL((k_ext_pre<R, 24>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, r, to, escr);
+  else if (P.s.nb <= 32 && P.s.nd + P.s.nb <= 256)
+    hipLaunchKernelGGL((k_ext_pre<R, 32>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, r, to, escr);
   else
     hipLaunchKernelGGL((k_ext_pre<R, 0>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, r, to, escr);
 }
@@ -1381,6 +1407,8 @@ template <typename R>
 void launch_ext_post(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* t, const R* to, R* y) {
   if (P.s.nb <= 32 && P.s.nd <= 96)
     hipLaunchKernelGGL((k_ext_post<R, 12, 1>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
+  else if (P.s.nb <= 32 && P.s.nd <= 144)
+    hipLaunchKernelGGL((k_ext_post<R, 18, 1>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
   else if (P.s.nb <= 64 && P.s.nd <= 144)
     hipLaunchKernelGGL((k_ext_post<R, 18, 2>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
   else
