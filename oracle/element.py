@@ -18,7 +18,11 @@ by global index, barycentric coordinates lambda_0..lambda_d:
   continuous (Sec. 3: BDM is H(div)-conforming).
 * hat V_h on facet F: lambda_F^gamma t_b, |gamma| = k-1 over the facet
   vertices, t_b = x_{f_b} - x_{f_0} (b = 1..d-1), index (b-1)*n_gamma + gamma.
-* W_h(T) = P^{k-1}(T, K), Q_h(T) = P^{k-1}(T) (basis lambda^gamma),
+* W_h(T) = P^{k-1}(T, K) for k >= 2; for k = 1 (3D, Sec. 6) the lowest-order
+  Raviart-Thomas space P^0(T, R^3) + x P^0(T), normal-continuous, entering
+  through kappa(omega), with one flux dof per facet and a stabilising
+  (div omega, div eta) term (weight nu |T|^(2/3));
+  Q_h(T) = P^{k-1}(T) (basis lambda^gamma),
   Sigma_h(T) = {tau in P^k(T, D): tau_nt in P^{k-1}(F) for all F in dT},
   built here as the null space of the top-degree nt-trace moments in
   P^k(T, D) (eq. fes_Sigma).
@@ -84,7 +88,12 @@ def facet_normal_geo(P):
 
 
 def expected_dims(d, k):
-    """Dimensions of the local spaces (closed forms)."""
+    """Dimensions of the local spaces (closed forms).  For k = 1 (3D only,
+    Sec. 6) W_h(T) is the lowest-order Raviart-Thomas space (one normal flux
+    per facet, n_w = 1), coupled across facets, so its dofs join the facet
+    blocks; for k >= 2 it is P^{k-1}(T, K) and n_w = 0."""
+    if k == 1 and d != 3:
+        raise ValueError("the lowest order k = 1 is the three-dimensional method of Sec. 6")
     nk = math.comb(k + d, d)
     nkm1 = math.comb(k - 1 + d, d)
     nF = math.comb(k + d - 1, d - 1)
@@ -93,10 +102,36 @@ def expected_dims(d, k):
     n_bub = n_u - (d + 1) * nF
     n_hat = (d - 1) * nFm1
     n_sig = (d * d - 1) * nk - (d + 1) * (d - 1) * (nF - nFm1)
-    n_om = (d * (d - 1) // 2) * nkm1
-    return dict(n_u=n_u, n_bub=n_bub, n_F=nF, n_hat=n_hat, n_fb=nF + n_hat,
+    n_w = 1 if k == 1 else 0
+    n_om = d + 1 if k == 1 else (d * (d - 1) // 2) * nkm1
+    return dict(n_u=n_u, n_bub=n_bub, n_F=nF, n_hat=n_hat, n_w=n_w, n_fb=nF + n_hat + n_w,
                 n_sig=n_sig, n_om=n_om, n_p=nkm1,
-                n_A=n_u + (d + 1) * n_hat, n_d=(d + 1) * (nF + n_hat))
+                n_A=n_u + (d + 1) * (n_hat + n_w), n_d=(d + 1) * (nF + n_hat + n_w))
+
+
+def kappa(w):
+    """The skew matrix kappa(w) of a vector w in R^3 with kappa(curl u) equal
+    to the skew part (grad u - grad u^T) / 2 of grad u (Sec. 6 replaces omega
+    by kappa(omega) in the bilinear forms)."""
+    return 0.5 * np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+
+
+def rt0_basis(ed):
+    """Lowest-order Raviart-Thomas basis of W_h(T) for k = 1 (Sec. 6):
+    psi_i = s_i (x - x_i) / (d |T|), one function per local facet i, with flux
+    1 through F_i w.r.t. the global facet normal n_F (s_i = n_out,i . n_F = +-1)
+    and zero normal component on the other facets.  Returns the coefficients
+    over I_1 (lambda_0 .. lambda_d; x - x_i = sum_j lambda_j (x_j - x_i)),
+    shape (d+1, d+1, d), and div psi_i = s_i / |T|."""
+    d = ed.d
+    nv = d + 1
+    C = np.zeros((nv, nv, d))
+    s = np.zeros(nv)
+    for i in range(nv):
+        s[i] = np.sign(ed.normals_out[i] @ ed.normals_geo[i])
+        for j in range(nv):
+            C[i, j] = s[i] * (ed.X[j] - ed.X[i]) / (d * ed.vol)
+    return C, s / ed.vol
 
 
 @dataclass
@@ -311,12 +346,6 @@ def element_system(X, nu, k, f_lattice_sorted=None, lattice_sorted=None, m=None,
             Bhs[i * n_hat + j] = val.reshape(nfull)
     # restrict to Sigma_h(T)
     Mss = Z.T @ Mfull @ Z
-    Bws = Bws_full @ Z
-    Bsig = np.vstack([Bus @ Z, Bhs @ Z])                 # (n_A, n_sig)
-    n_sig, n_om = Z.shape[1], Bws.shape[0]
-    assert n_om == dims["n_om"]
-    M = np.block([[-Mss, Bws.T], [Bws, np.zeros((n_om, n_om))]])
-    Bfull = np.hstack([Bsig, np.zeros((Bsig.shape[0], n_om))])
 
     # div of velocity basis, A^div, pressure coupling, pressure mass
     divphi = np.einsum("sab,ibs->ia", Dk, Phi)            # (n_u, |I_{k-1}|)
@@ -327,7 +356,35 @@ def element_system(X, nu, k, f_lattice_sorted=None, lattice_sorted=None, m=None,
     n_A = dims["n_A"]
     Adiv_ext = np.zeros((n_A, n_A))
     Adiv_ext[:n_u, :n_u] = Adiv
-    A = Adiv_ext - Bfull @ np.linalg.solve(M, Bfull.T)
+    if k >= 2:
+        Bws = Bws_full @ Z
+        Bsig = np.vstack([Bus @ Z, Bhs @ Z])                 # (n_A, n_sig)
+        n_sig, n_om = Z.shape[1], Bws.shape[0]
+        assert n_om == dims["n_om"]
+        M = np.block([[-Mss, Bws.T], [Bws, np.zeros((n_om, n_om))]])
+        Bfull = np.hstack([Bsig, np.zeros((Bsig.shape[0], n_om))])
+        A = Adiv_ext - Bfull @ np.linalg.solve(M, Bfull.T)
+    else:
+        # k = 1 (Sec. 6): omega in the Raviart-Thomas space, kappa(omega) in
+        # place of omega, so only sigma is condensed; omega's facet fluxes
+        # stay in the system beside (u, uhat), with the stabilisation
+        # nu h_T^2 (div omega, div eta)_T with h_T = |T|^(1/3): a weight
+        # that keeps the term bounded by the lowest-order norm of Sec. 6
+        # (||div omega||_T <~ h_T^-1 ||omega||_T), so that the facet block
+        # smoother and E of the preconditioner stay robust in h.  With the
+        # sigma rows
+        # -M_ss sigma + B^T (u, uhat, omega) = 0 the condensed block is
+        # A^div + B M_ss^{-1} B^T + stabilisation.
+        Crt, divrt = rt0_basis(ed)
+        Bw_full = np.zeros((nv, nfull))
+        for i in range(nv):
+            Kc = np.array([kappa(Crt[i, j]) for j in range(nv)])          # (|I_1|, d, d)
+            DKc = np.einsum("mrs,brs->mb", Dm, Kc)                         # (m, beta)
+            Bw_full[i] = vol * np.einsum("ab,mb->am", G_kk, DKc).reshape(nfull)
+        Bws = Bw_full @ Z
+        Bsig = np.vstack([Bus @ Z, Bhs @ Z, Bws])            # (n_A, n_sig)
+        Adiv_ext[n_A - nv:, n_A - nv:] = nu * vol ** (2.0 / 3.0) * vol * np.outer(divrt, divrt)
+        A = Adiv_ext + Bsig @ np.linalg.solve(Mss, Bsig.T)
     A = 0.5 * (A + A.T)
     for p in pinned:
         A[p, :] = 0.0
@@ -341,18 +398,20 @@ def element_system(X, nu, k, f_lattice_sorted=None, lattice_sorted=None, m=None,
         G_mk = product_moments(nv, m, k)
         F = vol * np.einsum("ar,ab,ibr->i", fc, G_mk, Phi)
 
-    # reorder: [bubbles | per facet (normal fns, tangential fns)]
+    # reorder: [bubbles | per facet (normal fns, tangential fns[, omega flux])]
     nb, nF = dims["n_bub"], dims["n_F"]
     perm = list(range(nb))
     for i in range(nv):
         perm += list(range(nb + i * nF, nb + (i + 1) * nF))
         perm += list(range(n_u + i * n_hat, n_u + (i + 1) * n_hat))
+        if dims["n_w"]:
+            perm.append(n_u + nv * n_hat + i)
     perm = np.asarray(perm)
     Ar = A[np.ix_(perm, perm)]
     Aoo = Ar[:nb, :nb]
     Aod = Ar[:nb, nb:]
     Add = Ar[nb:, nb:]
-    H = np.linalg.solve(Aoo, Aod)
+    H = np.linalg.solve(Aoo, Aod) if nb else np.zeros((0, Add.shape[0]))
     Ad = Add - Aod.T @ H
     Ad = 0.5 * (Ad + Ad.T)
     out = dict(ed=ed, A=A, B=B, Adiv=Adiv, Mp=Mp, F=F, perm=perm,
@@ -373,6 +432,8 @@ def recover_stress(ed, nu, k, u_local):
     ([Phi | Vhat]).  Returns coefficient arrays over lambda^alpha (sorted
     vertices): S (|I_k|, d, d) for sigma_h and W (|I_{k-1}|, d, d) for
     omega_h."""
+    if k == 1:
+        raise NotImplementedError("stress recovery is built for k >= 2")
     es = element_system(ed, nu, k, keep_blocks=True)
     Z, Mss, Bws, Bsig, Dm, Kn = es["Z"], es["Mss"], es["Bws"], es["Bsig"], es["Dm"], es["Kn"]
     n_sig, n_om = Z.shape[1], Bws.shape[0]

@@ -32,7 +32,8 @@ for the double Schur complement A^d -- oracle (FP64, sequential).
   of one element differ), the coarse correction E C^{-1} E^T with the full
   embedding (bubble rows included), s sweeps in reverse colour order.
 * E^d: rows of the embedding E u = (u, u_t) of continuous P1 (eq. defE) for the
-  facet dofs (eq. defED).
+  facet dofs (eq. defED).  For k = 1 (Sec. 6) E u = (u, Pi^0 u_t, curl u): the
+  facet mean of the tangential trace and the flux of curl u through the facet.
 * C: one symmetric V(1,1) multigrid cycle for A-bar, the P1 form
   a(u, v) = nu int eps(u) : eps(v) (eq. defAhat, read with nu, not nu^{-1}),
   on the vertex lattice: coarse points every second index per axis plus the
@@ -184,6 +185,18 @@ def p1_in_element_basis(es, v_local, c):
     cu, *_ = np.linalg.lstsq(M, target.ravel(), rcond=None)
     assert np.allclose(M @ cu, target.ravel(), atol=1e-10 * max(1.0, np.abs(target).max()))
     ch = []
+    if k == 1:
+        # Sec. 6: the tangential trace of a P1 field is not in hat V_h (P^0):
+        # E takes its facet mean Pi^0 (the L2 projection onto constants)
+        for i in range(nv):
+            n = ed.normals_out[i]
+            Pt = np.eye(d) - np.outer(n, n)
+            mean = (0.0 if v_local == i else 1.0 / d) * np.eye(d)[c]
+            V = ed.Vhat[i][:, 0, :]                 # (n_hat, d): the tangents t_b
+            chi, *_ = np.linalg.lstsq(V.T, Pt @ mean, rcond=None)
+            assert np.allclose(V.T @ chi, Pt @ mean, atol=1e-12)
+            ch.append(chi)
+        return cu, ch
     tgt_t = elevate_to(lin, nv, 1, k - 1)       # (|I_{k-1}|, d)
     Ikm1 = multi_indices(nv, k - 1)
     for i in range(nv):
@@ -233,6 +246,13 @@ def embedding(gs, full=False):
                         continue                # pi_0: no tangential rows on outlets
                     for q in range(nh):
                         rows.append(base + nF + q); cols.append(col); vals.append(ch[i][q])
+                    if gs.dims["n_w"]:
+                        # k = 1 (Sec. 6): the omega component curl(u-bar); its
+                        # flux through F w.r.t. n_F, |F| (grad lambda_v x e_c) . n_F
+                        ed = es["ed"]
+                        cv = np.cross(ed.grad_lambda[vl], np.eye(d)[c])
+                        rows.append(base + nF + nh); cols.append(col)
+                        vals.append(ed.areas[i] * cv @ ed.normals_geo[i])
         for i in range(d + 1):
             g = topo.free_facet_of[topo.elem_facets[e, i]]
             if g >= 0:

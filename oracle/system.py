@@ -59,6 +59,8 @@ class GlobalSystem:
         self.elems = []
         self.xD = []
         n_u, nh = dims["n_u"], dims["n_hat"]
+        if k == 1 and topo.has_outlet:
+            raise NotImplementedError("k = 1 is built for Dirichlet boundaries only")
         for e in range(n_e):
             X = topo.element_coords(e)
             ed = element_geometry(X, k)
@@ -71,7 +73,7 @@ class GlobalSystem:
             es = element_system(ed, self.nu[e], k, fl, ls, self.m, pinned=pinned,
                                 sigma_rotation_seed=sigma_rotation_seed)
             self.elems.append(es)
-            xd = np.zeros(n_u + (d + 1) * nh)
+            xd = np.zeros(dims["n_A"])
             if g_lattice is not None:
                 for i in range(d + 1):
                     if topo.facet_dirichlet[topo.elem_facets[e, i]]:
@@ -106,6 +108,15 @@ class GlobalSystem:
         Mf = np.einsum("jgr,gh,lhr->jl", V, Gk1, V)
         rf = np.einsum("ar,ag,jgr->j", gc, Gmk1, V)
         xd[n_u + i * self.nh: n_u + (i + 1) * self.nh] = np.linalg.solve(Mf, rf)
+        if self.dims["n_w"]:
+            # k = 1: the flux of curl g through F w.r.t. n_F (the value of
+            # omega = curl u on the boundary, Sec. 6)
+            from .poly import gradient_matrices
+            D = gradient_matrices(nv, m, ed.grad_lambda)               # (d, |I_{m-1}|, |I_m|)
+            G = np.einsum("sab,br->ars", D, gc)                        # d g_r / d x_s
+            curl = np.stack([G[:, 2, 1] - G[:, 1, 2], G[:, 0, 2] - G[:, 2, 0], G[:, 1, 0] - G[:, 0, 1]], axis=1)
+            mom = facet_product_moments(nv, m - 1, 0, i)[:, 0] * area
+            xd[n_u + nv * self.nh + i] = mom @ (curl @ ed.normals_geo[i])
 
     # ------------------------------------------------------------------ maps
     def local_dofs(self, e):
