@@ -8,7 +8,12 @@
  * (arXiv 2207.08481).  Problem statement: Sec. 1, eq. (stokes):
  *     -div(nu eps(u)) + grad p = f,  div u = 0  in Omega,   u = 0 on dOmega,
  * discretised by eq. (discrmixedstressstokesweak) with the spaces of Sec. 3
- * (order k >= 2), sigma and omega statically condensed (Sec. 4.2), and solved
+ * (order k >= 2), sigma and omega statically condensed (Sec. 4.2), or, for
+ * k = 1 in 3D, by the lowest-order method of Sec. 6 (omega in the
+ * lowest-order Raviart-Thomas space entering through kappa(omega), one flux
+ * dof per facet beside the velocity dofs, only sigma condensed, the
+ * stabilisation nu |T|^(2/3) (div omega, div eta)_T, E u = (u, Pi^0 u_t,
+ * curl u); homogeneous Dirichlet boundaries only), and solved
  * by MINRES preconditioned with the block factorisation eq. (mhatinvfactor)
  * whose velocity block is the multiplicative auxiliary-space preconditioner
  * of the double Schur complement (Sec. 6.1, Theorem aux_pc_schur, Corollary
@@ -35,13 +40,15 @@
  *   velocity bubbles (zero normal trace), per element n_bub functions
  *       lambda^alpha (x_a - x_s0), |alpha| = k, s0 = min supp(alpha),
  *       a in supp(alpha) \ {s0}   (alpha lexicographically descending);
- *   per free facet one block of n_fb = n_F + n_hat dofs:
+ *   per free facet one block of n_fb = n_F + n_hat (+ 1 for k = 1) dofs:
  *       n_F normal dofs: BDM facet functions lambda^beta (x_j0 - x_i) * c with
  *       normal trace lambda^beta / |F| w.r.t. the facet normal n_F (the
  *       normal of the sorted facet vertex tuple), beta over the facet
  *       vertices, |beta| = k;
  *       n_hat tangential dofs: lambda_F^gamma (x_{f_b} - x_{f_0}),
  *       b = 1..dim-1 (outer), |gamma| = k-1 (inner);
+ *       k = 1 only: the flux of omega through F w.r.t. n_F (basis
+ *       s (x - x_i) / (3 |T|) on an element, s = +-1 its orientation);
  *   pressure, per element n_p functions lambda^gamma, |gamma| = k-1.
  *   Global vector: [u_bubble: element-major][facet blocks: free facets in
  *   canonical order (sorted by their sorted vertex tuple)][p: element-major].
@@ -125,7 +132,7 @@ typedef struct {
 } mcs_mesh;
 
 typedef struct {
-  int32_t order;            /* k >= 2 */
+  int32_t order;            /* k in 2..5; k = 1: dim 3, all-Dirichlet, single problems (Sec. 6) */
   int32_t precision;        /* 0: FP64 MINRES; 1: FP32 inner MINRES + FP64 refinement */
   int32_t smoothing_steps;  /* block-GS sweeps before / after the coarse correction (2) */
   int32_t max_it;           /* MINRES iteration limit (per inner solve) */
@@ -170,8 +177,11 @@ typedef struct mcs_problem mcs_problem;
 
 /* Host only.  Copies the mesh, builds topology, dof numbering, facet colouring
  * and the multigrid plan; fills *info (sizes, workspace bytes).  Reference:
- * Sec. 3 (mesh, facets, spaces).  Errors: MCS_ERR_ARG, MCS_ERR_MESH,
- * MCS_ERR_UNSUPPORTED. */
+ * Sec. 3 (mesh, facets, spaces); k = 1: Sec. 6 (facet blocks of n_F + n_hat
+ * + 1 = 6 dofs: normal moments, tangential means, the flux of omega; no
+ * bubbles).  Errors: MCS_ERR_ARG (k = 1 in 2D among others), MCS_ERR_MESH,
+ * MCS_ERR_UNSUPPORTED (k > 5; k = 1 with outlet faces or the full-system
+ * variant). */
 int mcs_plan(const mcs_mesh* mesh, const mcs_options* options, mcs_problem** out,
              mcs_info* info);
 
@@ -203,7 +213,8 @@ int mcs_load(mcs_problem* pb, const double* f_lattice, double* b);
  * the lift x_D plus the free dofs that mcs_solve returns (mcs_load subtracts
  * K x_D; mcs_eval and mcs_eval_stress include x_D).  g_lattice_host = NULL
  * returns to homogeneous data.  Needs a bound problem.  [sync]  Errors:
- * MCS_ERR_ARG for non-finite data. */
+ * MCS_ERR_ARG for non-finite data; MCS_ERR_UNSUPPORTED for k = 1 (built for
+ * homogeneous data). */
 int mcs_set_dirichlet(mcs_problem* pb, const double* g_lattice_host);
 
 /* y = op x (see mcs_op); x, y: device vectors of length n_dof in dtype dt
@@ -261,8 +272,8 @@ int mcs_eval(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_
  * sigma_vals and omega_vals (device) [n_elements][n_pts][dim][dim], row-major
  * matrices.  For conforming velocity data sigma_h = -nu dev eps(u_h) and
  * omega_h = kappa(curl u_h) (Lemma SPD).  Needs mcs_condense first
- * (MCS_ERR_STATE); n_pts as for mcs_eval (MCS_ERR_ARG).  Uses the
- * condensation scratch.  [sync] */
+ * (MCS_ERR_STATE); n_pts as for mcs_eval (MCS_ERR_ARG); k = 1 is refused
+ * (MCS_ERR_UNSUPPORTED).  Uses the condensation scratch.  [sync] */
 int mcs_eval_stress(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_pts_host,
                     double* sigma_vals, double* omega_vals);
 
@@ -361,8 +372,9 @@ typedef struct {
   size_t workspace_bytes;   /* bytes the caller must provide to mcs_batch_bind */
 } mcs_batch_info;
 
-/* Host only.  Plans n >= 1 members: meshes[i] with order orders[i]; the other
- * options (precision, tolerances, smoothing, limits) are shared.  Errors as
+/* Host only.  Plans n >= 1 members: meshes[i] with order orders[i] (2..5:
+ * k = 1 is for single problems, MCS_ERR_UNSUPPORTED); the other options
+ * (precision, tolerances, smoothing, limits) are shared.  Errors as
  * mcs_plan, naming the member. */
 int mcs_batch_plan(const mcs_mesh* meshes, const int32_t* orders, int32_t n, const mcs_options* options,
                    mcs_batch** out, mcs_batch_info* info);

@@ -372,10 +372,14 @@ struct Ctx {
       return;
     }
     R *S = v(PS), *T = v(PT), *T1 = v(PT1);
-    launch_ext_pre<R>(st, P, O, r, T1, escr);
-    launch_facet_sum<R>(st, P, escr, r, R(-1), S);
-    ad_inv(S, T);
-    launch_ext_post<R>(st, P, O, T, T1, y);
+    if (pb->sz.nb == 0) {
+      ad_inv(r, T);   // no velocity bubbles (k = 1): A-hat_ext = A-hat^d
+    } else {
+      launch_ext_pre<R>(st, P, O, r, T1, escr);
+      launch_facet_sum<R>(st, P, escr, r, R(-1), S);
+      ad_inv(S, T);
+      launch_ext_post<R>(st, P, O, T, T1, y);
+    }
     launch_axpby<R>(st, pb->nff * pb->sz.nfb, 1.0, T + pb->off_f, 0.0, y + pb->off_f);
     launch_fill<R>(st, pb->ndof - pb->off_p, R(0), y + pb->off_p);
   }

@@ -272,6 +272,7 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   p.rBf = ws_ptr<double>(pb, "rBf");
   p.rU = ws_ptr<double>(pb, "rU");
   p.rL = ws_ptr<double>(pb, "rL");
+  p.rLam = ws_ptr<double>(pb, "rLam");
   p.rD = ws_ptr<double>(pb, "rD");
   p.rBp = ws_ptr<double>(pb, "rBp");
   p.rMp = ws_ptr<double>(pb, "rMp");
@@ -371,6 +372,7 @@ int mcs_bind(mcs_problem* pb, void* workspace, size_t bytes, void* stream) {
   HIPCHK(up(p.rBf, r.Bf.data(), r.Bf.size() * 8));
   HIPCHK(up(p.rU, r.U.data(), r.U.size() * 8));
   HIPCHK(up(p.rL, r.L.data(), r.L.size() * 8));
+  HIPCHK(up(p.rLam, r.Lam.data(), r.Lam.size() * 8));
   HIPCHK(up(p.rD, r.D.data(), r.D.size() * 8));
   HIPCHK(up(p.rBp, r.Bp.data(), r.Bp.size() * 8));
   HIPCHK(up(p.rMp, r.Mp.data(), r.Mp.size() * 8));
@@ -440,6 +442,7 @@ static CondParams cond_params(mcs_problem* pb, int* status) {
   C.rBf = p.rBf;
   C.rU = p.rU;
   C.rL = p.rL;
+  C.rLam = p.rLam;
   C.rD = p.rD;
   for (int f = 0; f < 4; ++f) C.facet_measure[f] = pb->ref.facet_measure[f];
   C.scratch = p.cscratch;
@@ -627,6 +630,10 @@ int mcs_set_dirichlet(mcs_problem* pb, const double* g_lattice_host) {
   if (!g_lattice_host) {
     pb->has_dirichlet = false;
     return MCS_OK;
+  }
+  if (pb->sz.nw) {
+    set_error("mcs_set_dirichlet: k = 1 is built for homogeneous Dirichlet data");
+    return MCS_ERR_UNSUPPORTED;
   }
   std::vector<double> xd;
   try {
@@ -1071,6 +1078,10 @@ int mcs_eval_stress(mcs_problem* pb, const double* x, int32_t n_pts, const doubl
   if (!pb->condensed) {
     set_error("mcs_eval_stress: call mcs_condense first");
     return MCS_ERR_STATE;
+  }
+  if (pb->sz.nw) {
+    set_error("mcs_eval_stress: the stress recovery is built for k >= 2");
+    return MCS_ERR_UNSUPPORTED;
   }
   const int nv = pb->d + 1;
   if (!x || !ref_pts_host || !sigma_vals || !omega_vals || n_pts <= 0 || (int64_t)n_pts * nv > pb->nred) {

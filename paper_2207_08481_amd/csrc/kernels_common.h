@@ -21,6 +21,7 @@ struct CondParams {
   const double* coords;
   const double* nu;
   const double *rV, *rBf, *rU, *rL, *rD;
+  const double* rLam;   // [ns][nv] int_T^ psi_a lambda_j (k = 1: the omega rows of G)
   double facet_measure[4];
   double* scratch;
   double* detJ;

@@ -295,17 +295,30 @@ __device__ __forceinline__ void stress_tables(const CondParams& P, int64_t e, El
 
 // Column c of the reduced stress space -> (trace-free basis index m, scalar
 // index a): every psi_a for the symmetric D_m, only the top-degree psi_a for
-// the skew D_m.
+// the skew D_m (a >= sklo = n_{k-1}); for k = 1 omega is not condensed and
+// the skew D_m keep every psi_a (sklo = 0).
 __device__ __forceinline__ void sig_col(const Sizes& s, int c, int& m, int& a) {
-  const int ntop = s.ns - s.nsm1;
+  const int ntop = s.ns - s.sklo;
   if (c < s.nsym * s.ns) {
     m = c / s.ns;
     a = c % s.ns;
   } else {
     const int cc = c - s.nsym * s.ns;
     m = s.nsym + cc / ntop;
-    a = s.nsm1 + cc % ntop;
+    a = s.sklo + cc % ntop;
   }
+}
+
+// k = 1 (Sec. 6): omega in the lowest-order Raviart-Thomas space, one flux
+// dof per facet f w.r.t. the facet's global normal (sorted vertices:
+// (x_b - x_a) x (x_c - x_a)): psi_f = s_f (x - x_f) / (d |T|), s_f = +-1 its
+// orientation against the outward normal, div psi_f = s_f / |T|.
+__device__ __forceinline__ double rt_sign(const ElemGeo& g, int f) {
+  const double* t0 = g.t[f][0];
+  const double* t1 = g.t[f][1];
+  const double c0 = t0[1] * t1[2] - t0[2] * t1[1], c1 = t0[2] * t1[0] - t0[0] * t1[2],
+               c2 = t0[0] * t1[1] - t0[1] * t1[0];
+  return c0 * g.n[f][0] + c1 * g.n[f][1] + c2 * g.n[f][2] > 0.0 ? 1.0 : -1.0;
 }
 
 // G[i, (m, a)] = b(psi_a D_m, phi_i) for the local velocity row i (order:
@@ -322,6 +335,25 @@ __device__ __forceinline__ double g_entry(const CondParams& P, const ElemGeo& g,
     f = (i - s.nb) / s.nfb;
     q = (i - s.nb) % s.nfb;
     if (q < s.nF) { iu = s.nb + f * s.nF + q; sc = idet; }
+  }
+  if (q >= s.nF + s.nh) {
+    // omega row (k = 1): int_T psi_a D_m : kappa(psi_f), kappa(w) the skew
+    // matrix with kappa(curl u) = skew(grad u), i.e. (1/2) [w]_x.  With
+    // x - x_f = sum_j lambda_j (x_j - x_f) and |T| = |det J| |T^|:
+    //   s_f / (d |T^|) sum_j (D_m : kappa(x_j - x_f)) int_T^ psi_a lambda_j
+    double D[3][3];
+    dm_basis(d, m, D);
+    double t = 0.0;
+    for (int j = 0; j < nv; ++j) {
+      if (j == f) continue;
+      double w[3];
+      for (int r = 0; r < 3; ++r) w[r] = g.X[j][r] - g.X[f][r];
+      // D : (1/2)[w]_x, [w]_x = [[0,-w2,w1],[w2,0,-w0],[-w1,w0,0]]
+      const double dk = 0.5 * (-D[0][1] * w[2] + D[0][2] * w[1] + D[1][0] * w[2] - D[1][2] * w[0] -
+                               D[2][0] * w[1] + D[2][1] * w[0]);
+      t += dk * P.rLam[(size_t)a * nv + j];
+    }
+    return rt_sign(g, f) * t * 2.0;   // (d - 1)! = 2: k = 1 is three-dimensional
   }
   if (iu >= 0) {
     double t = 0.0;
@@ -441,6 +473,15 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
             if (c < s.nb) ic = c;
             else { int f = (c - s.nb) / s.nfb, t = (c - s.nb) % s.nfb; if (t < s.nF) { ic = s.nb + f * s.nF + t; sc2 = idet; } }
             if (ir >= 0 && ic >= 0) v += (nuT / d) * sr * sc2 * adet * P.rD[(size_t)ir * s.nu + ic];
+            if (s.nw) {
+              // k = 1: nu |T|^(2/3) (div omega, div eta)_T on the omega rows,
+              // div psi_f = s_f / |T|
+              const int tr = (r - s.nb) % s.nfb, tc = (c - s.nb) % s.nfb;
+              if (r >= s.nb && c >= s.nb && tr == s.nF + s.nh && tc == s.nF + s.nh) {
+                const double c23 = cbrt(g.vol);
+                v += nuT * c23 * c23 * rt_sign(g, (r - s.nb) / s.nfb) * rt_sign(g, (c - s.nb) / s.nfb) / g.vol;
+              }
+            }
             A[(size_t)r * s.nA + c] = v;
             A[(size_t)c * s.nA + r] = v;
           }
@@ -698,6 +739,11 @@ __global__ void __launch_bounds__(256) k_facet_setup(FacetSetupParams P) {
       double val;
       if (q < s.nF) {
         val = geo[3] * geo[c] * P.rcn[q * d + v];
+      } else if (q >= s.nF + s.nh) {
+        // k = 1: the flux of curl(lambda_v e_c) through F w.r.t. n_F, by
+        // Stokes the circulation of lambda_v e_c along dF (X_0 -> X_1 -> X_2,
+        // positive about n_F): (1/2) e_c . (X_{v+1} - X_{v-1})
+        val = 0.5 * (X[(v + 1) % 3][c] - X[(v + 2) % 3][c]);
       } else if (P.facet_out && P.facet_out[g]) {
         val = 0.0;   // pi_0 (Lemma outflow): the outlet's tangential dofs stay zero
       } else {

@@ -1463,6 +1463,7 @@ void launch_smooth_phase(hipStream_t st, const SolveParams& P, const OpPtrs<R>& 
   if (cap <= 0) cap = 1 << 20;
   switch (P.s.nfb) {
     case 5: smooth_launch<R, 5>(st, P, O, c0, c1, x, s, y, fpw, cap, T1); break;
+    case 6: smooth_launch<R, 6>(st, P, O, c0, c1, x, s, y, fpw, cap, T1); break;
     case 7: smooth_launch<R, 7>(st, P, O, c0, c1, x, s, y, fpw, cap, T1); break;
     case 9: smooth_launch<R, 9>(st, P, O, c0, c1, x, s, y, fpw, cap, T1); break;
     case 11: smooth_launch<R, 11>(st, P, O, c0, c1, x, s, y, fpw, cap, T1); break;
@@ -1488,6 +1489,7 @@ void launch_smooth_last(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O
   if (c1 <= c0) return;
   switch (P.s.nfb) {
     case 5: smooth_last_launch<R, 5>(st, P, O, c0, c1, x, s, y); break;
+    case 6: smooth_last_launch<R, 6>(st, P, O, c0, c1, x, s, y); break;
     case 7: smooth_last_launch<R, 7>(st, P, O, c0, c1, x, s, y); break;
     case 9: smooth_last_launch<R, 9>(st, P, O, c0, c1, x, s, y); break;
     case 11: smooth_last_launch<R, 11>(st, P, O, c0, c1, x, s, y); break;

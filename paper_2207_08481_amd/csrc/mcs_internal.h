@@ -30,8 +30,11 @@ struct Sizes {
   int ns, nsm1;       // dim P^k(T), dim P^{k-1}(T)
   int nFk, nFkm1;     // dim P^k(F), dim P^{k-1}(F)
   int nu, nb, nF, nh, nfb, nd, nA, np;  // BDM, bubbles, facet normal, facet tangential, block, A^d, A, pressure
+  int nw;             // omega flux dofs per facet: 1 for k = 1 (W_h in H(div), Sec. 6), else 0
   int nsym, nskew;    // orthonormal trace-free basis: symmetric / skew parts
-  int nsig;           // reduced sigma columns: nsym * ns + nskew * (ns - nsm1)
+  int sklo;           // first psi_a of the skew stress columns: nsm1 (omega in P^{k-1}(T, K)
+                      // condensed), 0 for k = 1 (omega global)
+  int nsig;           // reduced sigma columns: nsym * ns + nskew * (ns - sklo)
   int nlam;           // nt-degree constraints: (d+1)(d-1)(nFk - nFkm1)
   int nlat;           // lattice points of degree m
 };
@@ -62,6 +65,8 @@ struct RefTables {
   std::vector<int32_t> latmap; // [(d+1)!][nlat]   caller lattice index -> sorted lattice index
   std::vector<double> cn;    // [nFk][d]            lambda_v (facet vertex v) in degree-k facet Bernstein
   std::vector<double> ct;    // [nFkm1][d]          lambda_v in degree k-1 facet Bernstein
+                             //                     (k = 1: its facet mean 1/d, the projection Pi^0)
+  std::vector<double> Lam;   // [ns][nv]            int_T^ psi_a lambda_j
   std::vector<double> pconst;// [np]                coefficients of p = 1
   std::vector<double> pmom;  // [np]                int_T^ lambda^gamma / |T^|
   std::vector<double> phi;   // [nu][nv + 3]        BDM function i: alpha (nv), reference vector w (3)
@@ -126,7 +131,7 @@ struct DevPtrs {
   int32_t* vfree_of_lat;  // [nvert] lattice vertex -> free P1 vertex or -1
   int32_t* free_to_lat;   // [nfv] free P1 vertex -> lattice vertex
   // reference tables
-  double *rV, *rBf, *rU, *rL, *rD, *rBp, *rMp, *rMpinv, *rRf, *rcn, *rct, *rpconst, *rpmom, *rphi, *rpidx, *rpsi, *rpsib;
+  double *rV, *rBf, *rU, *rL, *rD, *rLam, *rBp, *rMp, *rMpinv, *rRf, *rcn, *rct, *rpconst, *rpmom, *rphi, *rpidx, *rpsi, *rpsib;
   int32_t* rlatmap;
   // element operators
   double *nu, *detJ;

@@ -119,9 +119,13 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
     return MCS_ERR_ARG;
   }
   const int k = opt->order;
-  if (k < 2 || k > 5) {
-    set_error("order k must be in 2..5 (got %d)", k);
-    return k < 2 ? MCS_ERR_ARG : MCS_ERR_UNSUPPORTED;
+  if (k < 1 || k > 5) {
+    set_error("order k must be in 1..5 (got %d)", k);
+    return k < 1 ? MCS_ERR_ARG : MCS_ERR_UNSUPPORTED;
+  }
+  if (k == 1 && d != 3) {
+    set_error("the lowest order k = 1 is the three-dimensional method (H(div) omega, Sec. 6)");
+    return MCS_ERR_ARG;
   }
   if (mesh->n_vertices <= d || mesh->n_elements <= 0 || !mesh->vertices_host || !mesh->elements_host) {
     set_error("empty mesh");
@@ -139,6 +143,10 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
       return MCS_ERR_ARG;
     }
     if (mesh->face_bc[a] == 1) ffm |= 1 << a;
+  }
+  if (k == 1 && ffm) {
+    set_error("k = 1 is built for Dirichlet boundaries only (no outlet faces)");
+    return MCS_ERR_UNSUPPORTED;
   }
   pb->pffm.assign(1, ffm);
   pb->d = d;
@@ -159,6 +167,10 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
     return MCS_ERR_ARG;
   }
   pb->sz = make_sizes(d, k);
+  if (k == 1 && pb->opt.smoother == 2) {
+    set_error("k = 1 has no velocity bubbles: the full-system variant is the condensed one (smoother 0)");
+    return MCS_ERR_UNSUPPORTED;
+  }
   if (pb->opt.smoother == 2) {
     const int nbk = pb->sz.nfb + 2 * pb->sz.nb;
     if (pb->opt.precision != 0 || nbk > 64) {
@@ -628,6 +640,7 @@ int layout_workspace(mcs_problem* pb) {
   L.add("rBf", Dd(r.Bf.size()));
   L.add("rU", Dd(r.U.size()));
   L.add("rL", Dd(r.L.size()));
+  L.add("rLam", Dd(r.Lam.size()));
   L.add("rD", Dd(r.D.size()));
   L.add("rBp", Dd(r.Bp.size()));
   L.add("rMp", Dd(r.Mp.size()));

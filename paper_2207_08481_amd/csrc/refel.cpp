@@ -342,13 +342,15 @@ Sizes make_sizes(int d, int k) {
   s.nF = s.nFk;
   s.nb = s.nu - (d + 1) * s.nF;
   s.nh = (d - 1) * s.nFkm1;
-  s.nfb = s.nF + s.nh;
+  s.nw = k == 1 ? 1 : 0;
+  s.nfb = s.nF + s.nh + s.nw;
   s.nd = (d + 1) * s.nfb;
-  s.nA = s.nu + (d + 1) * s.nh;
+  s.nA = s.nu + (d + 1) * (s.nh + s.nw);
   s.np = s.nsm1;
   s.nsym = d * (d + 1) / 2 - 1;
   s.nskew = d * (d - 1) / 2;
-  s.nsig = s.nsym * s.ns + s.nskew * (s.ns - s.nsm1);
+  s.sklo = k == 1 ? 0 : s.nsm1;
+  s.nsig = s.nsym * s.ns + s.nskew * (s.ns - s.sklo);
   s.nlam = (d + 1) * (d - 1) * (s.nFk - s.nFkm1);
   s.nlat = (int)binom(s.m + d, d);
   return s;
@@ -469,6 +471,7 @@ RefTables build_ref_tables(int d, int k) {
   T.Bp.assign((size_t)s.np * s.nu, 0.0);
   T.Mp.assign((size_t)s.np * s.np, 0.0);
   T.Rf.assign((size_t)nlat * s.nu * d, 0.0);
+  T.Lam.assign((size_t)s.ns * nv, 0.0);
   {
     Rule R = simplex_rule(d, k + 3);
     std::vector<double> val(s.nu * d), grad(s.nu * d * d), dv(s.nu), ps(s.ns), pp(s.np),
@@ -496,6 +499,8 @@ RefTables build_ref_tables(int d, int k) {
       }
       for (int g = 0; g < s.np; ++g)
         for (int h = 0; h < s.np; ++h) T.Mp[g * s.np + h] += w * pp[g] * pp[h];
+      for (int a = 0; a < s.ns; ++a)
+        for (int j = 0; j < nv; ++j) T.Lam[(size_t)a * nv + j] += w * ps[a] * lam[j];
     }
   }
   T.Mpinv = dense_inverse(T.Mp, s.np);
@@ -565,13 +570,19 @@ RefTables build_ref_tables(int d, int k) {
         T.cn[b * d + v] = fact(k - 1) / den;
       }
     T.ct.assign((size_t)s.nFkm1 * d, 0.0);
-    for (int g = 0; g < s.nFkm1; ++g)
-      for (int v = 0; v < d; ++v) {
-        if (IFg[g][v] < 1) continue;
-        double den = 1.0;
-        for (int j = 0; j < d; ++j) den *= fact(IFg[g][j] - (j == v ? 1 : 0));
-        T.ct[g * d + v] = fact(k - 2) / den;
-      }
+    if (k == 1) {
+      // the tangential trace of a P1 field is not in hat V_h = P^0: E takes
+      // its facet mean (Sec. 6), 1/d of each facet vertex's value
+      for (int v = 0; v < d; ++v) T.ct[v] = 1.0 / d;
+    } else {
+      for (int g = 0; g < s.nFkm1; ++g)
+        for (int v = 0; v < d; ++v) {
+          if (IFg[g][v] < 1) continue;
+          double den = 1.0;
+          for (int j = 0; j < d; ++j) den *= fact(IFg[g][j] - (j == v ? 1 : 0));
+          T.ct[g * d + v] = fact(k - 2) / den;
+        }
+    }
   }
   // basis descriptions for point evaluation
   T.phi.assign((size_t)s.nu * (nv + 3), 0.0);

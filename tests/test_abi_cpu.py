@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 
 @needs_lib
-@pytest.mark.parametrize("d,n,k", [(2, 4, 2), (2, 3, 4), (3, 2, 2), (3, 3, 3), (3, 2, 5)])
+@pytest.mark.parametrize("d,n,k", [(2, 4, 2), (2, 3, 4), (3, 2, 2), (3, 3, 3), (3, 2, 5), (3, 3, 1)])
 def test_plan_sizes_and_topology(d, n, k):
     from paper_2207_08481_amd import Problem
     from oracle.topology import Topology
@@ -89,7 +89,7 @@ def test_error_codes():
     from paper_2207_08481_amd.mcs import Problem, MCSError
     mesh = W.unit_cube_mesh(2)
     with pytest.raises(MCSError) as ex:
-        Problem(mesh.vertices, mesh.elements, mesh.lattice, 1)
+        Problem(mesh.vertices, mesh.elements, mesh.lattice, 0)
     assert ex.value.status == -1
     with pytest.raises(MCSError) as ex:
         Problem(mesh.vertices, mesh.elements, mesh.lattice, 6)
@@ -279,3 +279,24 @@ def test_solve_options_setter_validates():
         with pytest.raises(MCSError) as ex:
             pb.set_solve_options(*args)
         assert "ERR_ARG" in str(ex.value)
+
+
+@needs_lib
+def test_lowest_order_plan_and_refusals():
+    """k = 1 (Sec. 6) plans in 3D with facet blocks of six dofs and no
+    bubbles; it is refused in 2D (ERR_ARG), with outlet faces, with the
+    full-system variant and in batches (ERR_UNSUPPORTED)."""
+    from paper_2207_08481_amd import Batch, Problem
+    from paper_2207_08481_amd.mcs import MCSError
+    m3 = W.unit_cube_mesh(2)
+    i = Problem(m3.vertices, m3.elements, m3.lattice, 1).info
+    assert (i.n_fb, i.n_bub, i.n_F, i.n_hat, i.n_p) == (6, 0, 3, 2, 1)
+    m2 = W.unit_square_mesh(3)
+    with pytest.raises(MCSError, match="ERR_ARG"):
+        Problem(m2.vertices, m2.elements, m2.lattice, 1)
+    with pytest.raises(MCSError, match="ERR_UNSUPPORTED"):
+        Problem(m3.vertices, m3.elements, m3.lattice, 1, face_bc=[0, 1, 0, 0, 0, 0])
+    with pytest.raises(MCSError, match="ERR_UNSUPPORTED"):
+        Problem(m3.vertices, m3.elements, m3.lattice, 1, smoother=2)
+    with pytest.raises(MCSError, match="member 1"):
+        Batch([(m3.vertices, m3.elements, m3.lattice)] * 2, [2, 1])
