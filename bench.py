@@ -60,6 +60,8 @@ WORKLOADS = {
     "cube32_k4_fp64": ("cube32_k4_lognormal", 0, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 "
                        "contrast), random smooth f, FP64, tol 1e-10", 1e-10),
     "square8_k2": ("square8_k2", 0, "unit square 8x8 x 2 triangles, k=2, nu=1, FP64, tol 1e-10", 1e-10),
+    "cube64_k1": ("cube64_k1", 0, "unit cube 64^3 x 6 tets (1,572,864), lowest order k=1 (H(div) omega, Sec. 6), "
+                               "nu=1, curl of 8 random sin^2 modes, FP64, tol 1e-10", 1e-10),
     "cube16_k3_additive": ("cube16_k3", 0, "unit cube 16^3 x 6 tets (24,576), k=3, nu=1, curl of 8 random sin^2 "
                                            "modes, FP64, tol 1e-10; additive auxiliary-space preconditioner with the "
                                            "facet block-Jacobi smoother", 1e-10),
@@ -571,8 +573,14 @@ def run_single(args, name, steps, warmup, block):
     # steps); complete-solve steps: the solve phase without the condensation
     value = ndof * its / (wall if block else t_sol / 1e3)
 
+    info = pb.info
+    # the two-column colour phase serves the 3D blocks of 12, 22 and (FP32) 35
+    # dofs; other blocks (k = 1: 6 dofs) take the one-column kernel
+    two_col = pb.dim == 3 and (info.n_fb in (12, 22) or (info.n_fb == 35 and precision == 1))
+    smooth_kernel = "k_smooth_y2" if two_col else "k_smooth_y"
+
     def roof(kern, kname):
-        kfull = {"smooth": "k_smooth_y2", "kapply": "k_elem_apply"}[kern]
+        kfull = {"smooth": smooth_kernel, "kapply": "k_elem_apply"}[kern]
         if kern == "smooth" and smoother == 2:
             kfull = "k_full_smooth"
         return roofline(pb, timed, kern, kname, t_sol, period, copy_gbs, read_gbs,
@@ -582,10 +590,11 @@ def run_single(args, name, steps, warmup, block):
     kapply_name = f"k_elem_apply, {wname} (operator apply K x)"
     secondary = None
     if smoother == 0:
-        # the block Gauss-Seidel colour phase dominates the multiplicative solve;
-        # every bench mesh is 3D with k <= 4: the two-column colour phase
+        # the block Gauss-Seidel colour phase dominates the multiplicative solve
         roof_main = roof("smooth", f"k_smooth_y2, {wname} (one colour of one block Gauss-Seidel sweep, two "
-                                   "columns of the row block per thread)")
+                                   "columns of the row block per thread)" if two_col else
+                         f"k_smooth_y, {wname} (one colour of one block Gauss-Seidel sweep, one row of A^d per "
+                         "thread)")
         secondary = roof("kapply", kapply_name)
     elif smoother == 2:
         roof_main = {**roof("smooth", "k_full_smooth (one colour of one overlapping block Gauss-Seidel sweep "

@@ -370,6 +370,14 @@ def workload(name: str, **kw):
         nu = np.ones(mesh.n_elements)
         f = sol.f(lattice_points(mesh, k + 1))
         return dict(mesh=mesh, nu=nu, k=k, f_lattice=f, solution=sol, tol=1e-10)
+    if name == "cube64_k1":
+        # the lowest-order method (k = 1, Sec. 6) on 64^3 x 6 tets
+        n = kw.get("n", 64)
+        mesh = unit_cube_mesh(n)
+        sol = CurlModes3D(seed=2, nu=1.0)
+        nu = np.ones(mesh.n_elements)
+        f = sol.f(lattice_points(mesh, 2))
+        return dict(mesh=mesh, nu=nu, k=1, f_lattice=f, solution=sol, tol=1e-10)
     if name == "channel_k3":
         # plane channel flow in a 4 x 1 x 1 box (40 x 10 x 10 cells, 24,000
         # tets), nu = 1e-3 as in the paper's channel runs: the profile as
