@@ -178,6 +178,19 @@ struct Ctx {
     for (auto& l : L) l.active = active;
   }
 
+  // Element parts of the operator (escr, pressure rows of y) and of the
+  // pressure block; the lowest order (no bubbles, one pressure dof) takes the
+  // one-wave-per-element kernels.
+  bool wave_elements() const { return pb->sz.nb == 0 && pb->sz.np == 1; }
+  void elem_apply(const R* x, R* y, int flags) {
+    if (wave_elements()) launch_elem_apply_wave<R>(st, P, O, x, y, escr, flags);
+    else launch_elem_apply<R>(st, P, O, x, y, escr, flags);
+  }
+  void elem_press(const R* a, const R* r, R* y, int with_B) {
+    if (wave_elements()) launch_elem_press_wave<R>(st, P, a, r, y, with_B);
+    else launch_elem_press<R>(st, P, a, r, y, with_B);
+  }
+
   // y = op x on full vectors; flags of k_elem_apply.
   void apply(const R* x, R* y, int flags) {
     if (flags & 8) launch_fill<R>(st, n, R(0), y);
@@ -190,7 +203,7 @@ struct Ctx {
       timer_start(pb, st, 1);
       pb->t_bytes[1] += pb->ne * kapply_bytes_per_elem(pb->sz, pb->d, sizeof(R));
     }
-    launch_elem_apply<R>(st, P, O, x, y, escr, flags);
+    elem_apply(x, y, flags);
     if (timed) timer_stop(pb, st);
     launch_facet_sum<R>(st, P, escr, nullptr, R(1), y);
   }
@@ -288,7 +301,7 @@ struct Ctx {
     R *tmp = v(PTMP), *z = v(PZ);
     const int64_t of = pb->off_f, nf = (int64_t)pb->nff * pb->sz.nfb;
     const int steps = pb->opt.smoothing_steps;
-    auto products = [&]() { launch_elem_apply<R>(st, P, O, x, tmp, escr, 1 | 8); };
+    auto products = [&]() { elem_apply(x, tmp, 1 | 8); };
     auto sweep = [&]() {
       launch_facet_sum<R>(st, P, escr, s, R(-1), tmp);
       launch_block_jacobi<R>(st, P, O, tmp, z);
@@ -388,8 +401,8 @@ struct Ctx {
   void khat(const R* r, R* z) {
     R *A1 = v(PA1), *G = v(PG), *B1 = v(PB1);
     ext_inv(r, A1);
-    launch_elem_press<R>(st, P, A1, r, z, 1);
-    launch_elem_apply<R>(st, P, O, z, G, escr, 2 | 16);
+    elem_press(A1, r, z, 1);
+    elem_apply(z, G, 2 | 16);
     launch_facet_sum<R>(st, P, escr, nullptr, R(1), G);
     ext_inv(G, B1);
     launch_axpby<R>(st, pb->off_p, 1.0, A1, 0.0, z);

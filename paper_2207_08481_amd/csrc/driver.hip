@@ -713,7 +713,7 @@ int precond_op(mcs_problem* pb, int op, const void* rv, void* zv) {
     }
     case MCS_PC_MP_INV:
       launch_fill<R>(c.st, c.n, R(0), z);
-      launch_elem_press<R>(c.st, c.P, r, r, z, 0);
+      c.elem_press(r, r, z, 0);
       break;
     default:
       set_error("unknown preconditioner operator %d", op);

@@ -1398,8 +1398,6 @@ template <typename R>
 void launch_ext_pre(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* r, R* to, R* escr) {
   if (P.s.nb <= 24 && P.s.nd + P.s.nb <= 256)
     hipLaunchKernelGGL((k_ext_pre<R, 24>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, r, to, escr);
-  else if (P.s.nb <= 32 && P.s.nd + P.s.nb <= 256)
-    hipLaunchKernelGGL((k_ext_pre<R, 32>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, r, to, escr);
   else
     hipLaunchKernelGGL((k_ext_pre<R, 0>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, r, to, escr);
 }
@@ -1407,8 +1405,6 @@ template <typename R>
 void launch_ext_post(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* t, const R* to, R* y) {
   if (P.s.nb <= 32 && P.s.nd <= 96)
     hipLaunchKernelGGL((k_ext_post<R, 12, 1>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
-  else if (P.s.nb <= 32 && P.s.nd <= 144)
-    hipLaunchKernelGGL((k_ext_post<R, 18, 1>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
   else if (P.s.nb <= 64 && P.s.nd <= 144)
     hipLaunchKernelGGL((k_ext_post<R, 18, 2>), dim3(elem_grid(P.ne)), dim3(256), 0, st, P, O, t, to, y);
   else

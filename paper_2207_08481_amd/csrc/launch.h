@@ -45,6 +45,12 @@ template <typename R>
 void launch_mg_coarse(hipStream_t st, const double* Cinv, const int32_t* cmap, int d, const MGLevelDev& L);
 template <typename R>
 void launch_elem_press(hipStream_t st, const SolveParams& P, const R* a, const R* r, R* y, int with_B);
+// the same two operations for k = 1 (no bubbles, n_p = 1): one wave per element
+template <typename R>
+void launch_elem_apply_wave(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* x, R* y, R* escr,
+                            int flags);
+template <typename R>
+void launch_elem_press_wave(hipStream_t st, const SolveParams& P, const R* a, const R* r, R* y, int with_B);
 template <typename R>
 void launch_axpby(hipStream_t st, int64_t n, double a, const R* x, double b, R* y);
 template <typename R>
