@@ -606,7 +606,8 @@ def run_single(args, name, steps, warmup, block):
     cfg = {"workload": desc, "n_dof": ndof, "tets": mesh.n_elements, "order": k,
            "iterations_per_step": its / steps, "t_sol_ms_per_step": t_sol / steps,
            "rel_precond_residual": infos[-1]["rel_precond_residual"],
-           "smoother_launch": pb.launch_config(0 if precision == 0 else 1)}
+           "smoother_launch": pb.launch_config(0 if precision == 0 else 1),
+           "apply_launch": pb.apply_config(0 if precision == 0 else 1)}
     if block:
         cfg["step"] = (f"one refinement step: {block} inner FP32 MINRES iterations from the FP64 residual of b, "
                        "then the FP64 update, residual b - K x and its norm")

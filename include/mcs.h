@@ -336,6 +336,22 @@ int mcs_get_launch_config(const mcs_problem* pb, int dt, int32_t* facets_per_blo
  * precision 1 problem (it has no FP64 smoother): MCS_ERR_ARG. */
 int mcs_set_launch_config(mcs_problem* pb, int dt, int32_t facets_per_block, int64_t grid_cap);
 
+/* Rows of A^d per thread in the operator apply K x for work precision dt
+ * (MCS_F64 / MCS_F32): 1, 2 or 4 (FP32), 0 = the largest that n_d allows (the
+ * default); us = the tuner's time per K x (0 if not tuned).  The autotuner
+ * (mcs_options.autotune) times the valid choices at the first mcs_condense,
+ * except for k = 1 (one wave per element) and the split FP64 storage of
+ * precision 1 (one row per thread).  The tuner tries the choices whose
+ * products H x_d use the lane width of the default, which give bitwise the
+ * same results; a choice set by hand may change that width (3D k >= 4 in
+ * FP64) and with it the rounding of those sums. */
+int mcs_get_apply_config(const mcs_problem* pb, int dt, int32_t* rows_per_thread, double* us);
+
+/* Sets that choice (0, 1, 2, or 4 for MCS_F32; a choice the sizes do not
+ * allow falls back to the next smaller one) and keeps the autotuner off that
+ * slot.  Other values: MCS_ERR_ARG. */
+int mcs_set_apply_config(mcs_problem* pb, int dt, int32_t rows_per_thread);
+
 /* Changes the stopping rules of later solves on a planned problem (the fields
  * of mcs_options that do not change the layout): tol >= 0, max_it >= 1,
  * 0 <= inner_tol < 1, max_outer >= 1.  With tol = 0 a solve runs max_it

@@ -167,6 +167,7 @@ struct Ctx {
                           : reinterpret_cast<R*>(p->p.vec32);
     escr = reinterpret_cast<R*>(p->p.escr);
     fscr = reinterpret_cast<R*>(p->p.fscr);
+    P.apply_rpt = p->tune_rpt[sizeof(R) == 8 ? 0 : 1];
   }
   R* v(int i) { return base + (int64_t)i * n; }
 

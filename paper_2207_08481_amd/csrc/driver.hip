@@ -121,13 +121,72 @@ int tune_smoother_precision(mcs_problem* pb, int slot) {
   return MCS_OK;
 }
 
+// Operator apply tuner: times K x (the apply of the iteration) with the
+// numbers of A^d rows per thread (4 only in FP32; plain storage only: the
+// split FP64 storage takes one row per thread) whose H products use the lane
+// width of the default choice, so that every candidate gives bitwise the same
+// results, and keeps the fastest.
+template <typename R>
+int tune_apply_precision(mcs_problem* pb, int slot) {
+  const int nd = pb->sz.nd;
+  const int cp0 = (sizeof(R) == 4 && nd % 4 == 0) ? 4 : nd % 2 == 0 ? 2 : 1;   // the default
+  std::vector<int> cand;
+  for (int cp : {1, 2, 4})
+    if (cp <= cp0 && nd % cp == 0 && apply_h_lanes(nd, cp) == apply_h_lanes(nd, cp0)) cand.push_back(cp);
+  if (cand.size() < 2) return MCS_OK;   // nothing to choose
+  if (pb->sz.nb == 0 && pb->sz.np == 1) return MCS_OK;   // k = 1: one wave per element, no rows to choose
+  if (sizeof(R) == 8 && pb->lean) return MCS_OK;         // split storage: one row per thread
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      ApiLock lock(device_api_mutex());
+      for (auto x : e)
+        if (x) hipEventDestroy(x);
+    }
+  } ev;
+  {
+    ApiLock lock(device_api_mutex());
+    HIPCHK(hipEventCreate(&ev.e[0]));
+    HIPCHK(hipEventCreate(&ev.e[1]));
+  }
+  double best = 1e300;
+  int best_rpt = 0;
+  for (int rpt : cand) {
+    pb->tune_rpt[slot] = rpt;
+    Ctx<R> c(pb);
+    R* x = c.v(PT);
+    R* y = c.v(PS);
+    launch_fill<R>(c.st, c.n, R(1), x);
+    c.apply(x, y, 1 | 2 | 4);
+    HIPCHK(hipEventRecord(ev.e[0], c.st));
+    for (int r = 0; r < 3; ++r) c.apply(x, y, 1 | 2 | 4);
+    HIPCHK(hipEventRecord(ev.e[1], c.st));
+    HIPCHK(hipEventSynchronize(ev.e[1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+    const double us = ms * 1e3 / 3.0;
+    if (us < best) {
+      best = us;
+      best_rpt = rpt;
+    }
+  }
+  pb->tune_rpt[slot] = best_rpt;
+  pb->tune_rpt_us[slot] = best;
+  return MCS_OK;
+}
+
 // Tunes each precision slot once per plan, except the slots whose shape the
-// caller fixed with mcs_set_launch_config.
+// caller fixed with mcs_set_launch_config / mcs_set_apply_config.
 int tune_smoother(mcs_problem* pb) {
   int rc = MCS_OK;
   if (!pb->lean && !pb->tune_fixed[0] && pb->tune_us[0] == 0.0) rc = tune_smoother_precision<double>(pb, 0);
   if (rc) return rc;
   if (!pb->tune_fixed[1] && pb->tune_us[1] == 0.0) rc = tune_smoother_precision<float>(pb, 1);
+  if (rc) return rc;
+  if (!pb->tune_rpt_fixed[0] && pb->tune_rpt_us[0] == 0.0) rc = tune_apply_precision<double>(pb, 0);
+  if (rc) return rc;
+  if (pb->opt.precision == 1 && !pb->tune_rpt_fixed[1] && pb->tune_rpt_us[1] == 0.0)
+    rc = tune_apply_precision<float>(pb, 1);
   return rc;
 }
 
@@ -1135,6 +1194,31 @@ int mcs_set_launch_config(mcs_problem* pb, int dt, int32_t facets_per_block, int
   pb->tune_cap[slot] = grid_cap;
   pb->tune_us[slot] = 0.0;
   pb->tune_fixed[slot] = true;
+  return MCS_OK;
+}
+
+int mcs_get_apply_config(const mcs_problem* pb, int dt, int32_t* rows_per_thread, double* us) {
+  if (!pb || (dt != MCS_F64 && dt != MCS_F32)) {
+    set_error("apply config: bad argument");
+    return MCS_ERR_ARG;
+  }
+  const int slot = dt == MCS_F64 ? 0 : 1;
+  if (rows_per_thread) *rows_per_thread = pb->tune_rpt[slot];
+  if (us) *us = pb->tune_rpt_us[slot];
+  return MCS_OK;
+}
+
+int mcs_set_apply_config(mcs_problem* pb, int dt, int32_t rows_per_thread) {
+  if (!pb || (dt != MCS_F64 && dt != MCS_F32) ||
+      !(rows_per_thread == 0 || rows_per_thread == 1 || rows_per_thread == 2 ||
+        (rows_per_thread == 4 && dt == MCS_F32))) {
+    set_error("apply config: dt must be MCS_F64 or MCS_F32 and rows_per_thread 0, 1, 2 (or 4 in FP32)");
+    return MCS_ERR_ARG;
+  }
+  const int slot = dt == MCS_F64 ? 0 : 1;
+  pb->tune_rpt[slot] = rows_per_thread;
+  pb->tune_rpt_us[slot] = 0.0;
+  pb->tune_rpt_fixed[slot] = true;
   return MCS_OK;
 }
 

@@ -182,6 +182,9 @@ struct SolveParams {
   // Dirichlet dofs per element ([ne][nd]): when set, gathers of facet values
   // take them for the element's Dirichlet facets (lifting and point values)
   const double* xD;
+  // rows of A^d per thread in the operator apply (1, 2 or 4; 0: the largest
+  // that n_d and the word size allow); every choice gives bitwise the same sums
+  int apply_rpt;
 };
 
 __device__ inline bool elem_off(const SolveParams& P, int64_t e) {

@@ -1361,14 +1361,15 @@ static void elem_apply_launch(hipStream_t st, const SolveParams& P, MA Ad, MA H,
     const size_t hb = (size_t)P.s.nb * ldh * sizeof(R);
     const int hl = hb <= 65536 ? ldh : 0;
     const size_t lds = hl ? hb : 0;
+    const int rpt = P.apply_rpt;   // 0: the largest the sizes allow
     // FP32 with n_d divisible by 4: four rows per thread (16-byte loads)
     if constexpr (sizeof(R) == 4) {
-      if (flags == (1 | 2 | 4) && P.s.nd % 4 == 0) {
+      if (flags == (1 | 2 | 4) && P.s.nd % 4 == 0 && (rpt == 0 || rpt == 4)) {
         hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 4>), g, b, lds, st, P, Ad, H, Aoo, x, y, escr, flags, hl);
         return;
       }
     }
-    if (flags == (1 | 2 | 4) && P.s.nd % 2 == 0) {
+    if (flags == (1 | 2 | 4) && P.s.nd % 2 == 0 && rpt != 1) {
       hipLaunchKernelGGL((k_elem_apply<R, MA, 7, 2>), g, b, lds, st, P, Ad, H, Aoo, x, y, escr, flags, hl);
       return;
     }
@@ -1379,6 +1380,15 @@ static void elem_apply_launch(hipStream_t st, const SolveParams& P, MA Ad, MA H,
     hipLaunchKernelGGL((k_elem_apply<R, MA, 18, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags, 0);
   else
     hipLaunchKernelGGL((k_elem_apply<R, MA, -1, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags, 0);
+}
+// Lanes per row of H in z_o = x_o + H x_d of k_elem_apply with cp rows of
+// A^d per thread (the split of the 256 threads above): rows are summed in
+// lane-strided order, so choices of cp with the same width give bitwise the
+// same results, and choices with different widths differ in rounding only.
+int apply_h_lanes(int nd, int cp) {
+  const int tA = ((nd / cp + 63) >> 6) << 6;
+  if (tA >= 256) return 16;
+  return 256 - tA >= 128 ? 16 : 4;
 }
 template <typename R>
 void launch_elem_apply(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* x, R* y, R* escr, int flags) {

@@ -228,6 +228,11 @@ struct mcs_problem {
   int64_t tune_cap[2] = {0, 0};
   double tune_us[2] = {0.0, 0.0};
   bool tune_fixed[2] = {false, false};   // set by the caller: autotuning leaves the slot alone
+  // rows of A^d per thread of the operator apply per work precision (0: the
+  // default choice), its tuned time per launch, and the caller's pin
+  int tune_rpt[2] = {0, 0};
+  double tune_rpt_us[2] = {0.0, 0.0};
+  bool tune_rpt_fixed[2] = {false, false};
   // kernel timer: [0] smoother phase launches, [1] K apply launches
   bool timer_on = false;
   int timer_period = 1;               // time one call in timer_period

@@ -31,7 +31,8 @@ SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs
            "mcs_solve", "mcs_solve_rhs", "mcs_solve_rhs_noalloc", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
                  "mcs_get_array",
            "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config",
-           "mcs_set_launch_config", "mcs_set_solve_options", "mcs_destroy",
+           "mcs_set_launch_config", "mcs_get_apply_config", "mcs_set_apply_config", "mcs_set_solve_options",
+           "mcs_destroy",
            "mcs_status_string", "mcs_last_error",
            "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
            "mcs_batch_solve", "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable",
@@ -134,6 +135,8 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_timer_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_get_launch_config.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.mcs_set_launch_config.argtypes = [vp, i32, i32, i64]
+    lib.mcs_get_apply_config.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(C.c_double)]
+    lib.mcs_set_apply_config.argtypes = [vp, i32, i32]
     lib.mcs_set_solve_options.argtypes = [vp, C.c_double, i32, C.c_double, i32]
     lib.mcs_batch_launch_config.argtypes = [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
                                             C.POINTER(i64), C.POINTER(C.c_double)]
@@ -164,7 +167,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs_precond_apply",
                  "mcs_solve", "mcs_solve_rhs", "mcs_solve_rhs_noalloc", "mcs_normalize_pressure", "mcs_eval", "mcs_eval_stress", "mcs_set_dirichlet",
                  "mcs_get_array",
-                 "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_set_launch_config", "mcs_set_solve_options", "mcs_batch_plan",
+                 "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_set_launch_config", "mcs_get_apply_config", "mcs_set_apply_config", "mcs_set_solve_options", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
                  "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable", "mcs_batch_timer_read",
                  "mcs_server_create",
@@ -384,6 +387,18 @@ class Problem:
         autotuner leaves a slot set here alone.  dt=F64 on a precision 1
         problem (no FP64 smoother) raises."""
         _check(self._lib.mcs_set_launch_config(self._h, dt, facets_per_block, grid_cap))
+
+    def apply_config(self, dt=F64):
+        """Rows of A^d per thread of the operator apply for precision slot dt
+        (0: the default choice) and the tuner's time per K x in us."""
+        r, us = C.c_int32(), C.c_double()
+        _check(self._lib.mcs_get_apply_config(self._h, dt, C.byref(r), C.byref(us)))
+        return {"rows_per_thread": r.value, "us_per_apply": us.value}
+
+    def set_apply_config(self, rows_per_thread, dt=F64):
+        """Fixes the apply's rows of A^d per thread (0, 1, 2, or 4 in FP32);
+        the autotuner leaves a slot set here alone."""
+        _check(self._lib.mcs_set_apply_config(self._h, dt, rows_per_thread))
 
     def set_solve_options(self, tol, max_it, inner_tol=None, max_outer=None):
         """Stopping rules of later solves (tol, max_it, inner_tol, max_outer)."""

@@ -266,6 +266,25 @@ def test_launch_config_setter_validates():
     assert lean.launch_config(F32)["facets_per_block"] == 2
 
 
+@needs_lib
+def test_apply_config_setter_validates():
+    """mcs_set_apply_config takes 0 (the default), 1 or 2 rows of A^d per
+    thread, and 4 in FP32; anything else is refused with MCS_ERR_ARG and
+    leaves the choice unchanged (host only)."""
+    from paper_2207_08481_amd.mcs import F32, F64, MCSError, Problem
+    mesh = W.unit_cube_mesh(1)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 3)
+    assert pb.apply_config(F64) == {"rows_per_thread": 0, "us_per_apply": 0.0}
+    pb.set_apply_config(4, F32)
+    pb.set_apply_config(1, F64)
+    assert pb.apply_config(F32)["rows_per_thread"] == 4 and pb.apply_config(F64)["rows_per_thread"] == 1
+    for rpt, dt in ((4, F64), (3, F32), (-1, F64), (8, F32), (1, 7)):
+        with pytest.raises(MCSError) as ex:
+            pb.set_apply_config(rpt, dt)
+        assert "ERR_ARG" in str(ex.value)
+    assert pb.apply_config(F32)["rows_per_thread"] == 4 and pb.apply_config(F64)["rows_per_thread"] == 1
+
+
 def test_solve_options_setter_validates():
     """mcs_set_solve_options changes tol, max_it, inner_tol and max_outer of a
     planned problem; out-of-range values are refused with MCS_ERR_ARG (host

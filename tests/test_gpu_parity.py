@@ -378,9 +378,9 @@ def test_solve_high_order_mixed_precision(d, n, k):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_autotuned_launch_shapes_give_identical_results(precision):
-    """The tuner only picks the smoother's launch shape (facet blocks per
-    workgroup, grid cap); the solution is bitwise the same as with the default
-    shape."""
+    """The tuner picks the smoother's launch shape (facet blocks per
+    workgroup, grid cap) and the apply's rows of A^d per thread; the solution
+    is bitwise the same as with the default choices."""
     _need_gpu()
     from paper_2207_08481_amd import Problem
     c = setup_case(3, 2, 2)
@@ -393,10 +393,36 @@ def test_autotuned_launch_shapes_give_identical_results(precision):
         assert cfg["facets_per_block"] in (1, 2)
         if tune:
             assert cfg["us_per_launch"] > 0
+            ac = pb.apply_config(1 if precision else 0)
+            assert ac["rows_per_thread"] in (1, 2, 4) and ac["us_per_apply"] > 0
         x, si = pb.solve(torch.as_tensor(c["f"], device="cuda:0"))
         assert si["status"] == 0
         xs.append(x)
     assert torch.equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("d,n,k", [(3, 2, 3), (3, 1, 4), (2, 3, 5)])
+def test_apply_rows_per_thread_agree(d, n, k):
+    """K x with 1, 2 and (FP32) 4 rows of A^d per thread agrees to rounding
+    (the lane width of the H products may change with the choice: 3D k = 4),
+    and bitwise where the width is the default's (2D k = 5, 3D k = 3 and the
+    FP32 choices 2 and 4 at 3D k = 4): the choices the tuner tries."""
+    from paper_2207_08481_amd.mcs import F32, F64
+    c = setup_case(d, n, k)
+    pb = c["pb"]
+    x = torch.as_tensor(np.random.default_rng(3).standard_normal(pb.n_dof), device="cuda:0")
+    same = {(3, 3): {F64: (0, 1, 2), F32: (0, 1, 2, 4)}, (3, 4): {F64: (0, 2), F32: (0, 2, 4)},
+            (2, 5): {F64: (0, 1), F32: (0, 1)}}[(d, k)]
+    for dt, xt, choices, tol in ((F64, x, (0, 1, 2), 1e-13), (F32, x.float(), (0, 1, 2, 4), 1e-6)):
+        ys = {}
+        for rpt in choices:
+            pb.set_apply_config(rpt, dt)
+            ys[rpt] = pb.apply("K", xt).double()
+        for rpt in choices:
+            assert (torch.linalg.norm(ys[rpt] - ys[0]) <= tol * torch.linalg.norm(ys[0])).item(), (dt, rpt)
+        for rpt in same[dt]:
+            assert torch.equal(ys[rpt], ys[0]), (dt, rpt)
+        pb.set_apply_config(0, dt)
 
 
 @pytest.mark.parametrize("d,n,k,precision", [(3, 3, 3, 0), (3, 3, 2, 0), (3, 3, 3, 1), (2, 6, 3, 0)])
