@@ -405,7 +405,7 @@ def run_serve(args, precision, desc):
                    "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
                    "queue_ms_p50": float(np.percentile(qms, 50)), "mean_batch_size": float(bsz.mean()),
                    "dof_iterations_per_s": float((ndof * its).sum() / wall), "converged": ok,
-                   "arena_gb": args.serve_arena_gb, "arena_peak_gb": st["arena_peak"] / 1e9,
+                   "arena_gib": args.serve_arena_gb, "arena_peak_gib": st["arena_peak"] / (1 << 30),
                    "max_inflight": args.serve_inflight, "batches": st["batches"]},
         "roofline": None,
     }
@@ -574,9 +574,11 @@ def run_single(args, name, steps, warmup, block):
     value = ndof * its / (wall if block else t_sol / 1e3)
 
     info = pb.info
-    # the two-column colour phase serves the 3D blocks of 12, 22 and (FP32) 35
-    # dofs; other blocks (k = 1: 6 dofs) take the one-column kernel
-    two_col = pb.dim == 3 and (info.n_fb in (12, 22) or (info.n_fb == 35 and precision == 1))
+    # the two-column colour phase serves the 3D blocks of 6, 12, 22 and (FP32)
+    # 35 dofs with one facet per workgroup; two facets per workgroup and the
+    # other blocks take the one-column kernel
+    two_col = (pb.dim == 3 and (info.n_fb in (6, 12, 22) or (info.n_fb == 35 and precision == 1))
+               and pb.launch_config(0 if precision == 0 else 1)["facets_per_block"] == 1)
     smooth_kernel = "k_smooth_y2" if two_col else "k_smooth_y"
 
     def roof(kern, kname):
@@ -659,7 +661,7 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters against a plain copy of known size)")
     ap.add_argument("--serve-requests", type=int, default=32, help="serve: open-loop requests")
     ap.add_argument("--serve-closed", type=int, default=12, help="serve: closed-loop requests")
-    ap.add_argument("--serve-arena-gb", type=float, default=200.0, help="serve: HBM budget (GB)")
+    ap.add_argument("--serve-arena-gb", type=float, default=200.0, help="serve: HBM budget (GiB)")
     ap.add_argument("--serve-inflight", type=int, default=3, help="serve: concurrent micro-batches")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -1440,7 +1440,7 @@ static void smooth_launch(hipStream_t st, const SolveParams& P, const OpPtrs<R>&
       return;
     }
   }
-  if constexpr (NFB == 12 || NFB == 22 || (NFB == 35 && sizeof(R) == 4)) {
+  if constexpr (NFB == 6 || NFB == 12 || NFB == 22 || (NFB == 35 && sizeof(R) == 4)) {
     // 3D: two columns per thread
     if (P.s.nd == 4 * NFB && P.s.d == 3) {
       const unsigned b2 = (unsigned)std::min<int64_t>(c1 - c0, cap);

@@ -425,7 +425,8 @@ def test_apply_rows_per_thread_agree(d, n, k):
         pb.set_apply_config(0, dt)
 
 
-@pytest.mark.parametrize("d,n,k,precision", [(3, 3, 3, 0), (3, 3, 2, 0), (3, 3, 3, 1), (2, 6, 3, 0)])
+@pytest.mark.parametrize("d,n,k,precision", [(3, 3, 3, 0), (3, 3, 2, 0), (3, 3, 3, 1), (2, 6, 3, 0), (3, 3, 1, 0),
+                                             (3, 3, 1, 1)])
 def test_colour_phase_kernels_agree_bitwise(d, n, k, precision):
     """The colour phase runs as the two-column kernel (one facet per
     workgroup, 3D) or the one-column kernel (two facets per workgroup), with
