@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcs.so")
-SOURCES = ["refel.cpp", "plan.cpp", "kernels_setup.hip", "kernels_solve.hip", "kernels_lowest.hip",
+SOURCES = ["refel.cpp", "plan.cpp", "kernels_setup.hip", "kernels_solve.hip", "kernels_wave.hip",
            "kernels_batch.hip", "driver.hip",
            "batch.hip", "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
