@@ -45,33 +45,73 @@ constexpr int EPB = 4;   // elements (waves) per workgroup
 // 2 = + B^T p, 4 = p <- B u, 8 = A^d only, 16 = zero pressure rows when B u
 // is not requested.  Facet rows go to escr[e][n_d] (summed per facet by
 // k_facet_sum), the pressure row to y.  B_T[q][row] = -|det J| / det J
-// Bp^[q][iu(row)] for the facet functions.
+// Bp^[q][iu(row)] for the facet functions.  Four elements per wave, 16 lanes
+// each; a lane owns two adjacent rows (n_d <= 32, even) and loads both of
+// their entries of a column of A^d at once (A^d symmetric: column = row).
 template <typename R, typename MA>
 __global__ void __launch_bounds__(256) k_elem_apply_wave(SolveParams P, MA MAd, const R* __restrict__ x,
                                                          R* __restrict__ y, R* __restrict__ escr, int flags) {
+  typedef R r2v __attribute__((ext_vector_type(2)));
+  constexpr int LPE = 16;                               // lanes per element
   const Sizes s = P.s;
-  const int nd = s.nd, nu = s.nu;
-  const int lane = threadIdx.x & 63;
+  const int nd = s.nd;
+  const int lane = threadIdx.x & 63, sub = lane & (LPE - 1), es = lane / LPE;
+  const int gbase = lane - sub;                         // first lane of the element's group
   const bool doA = flags & 1, doBT = flags & 2, doBu = flags & 4;
-  const int iu = lane < nd ? facet_row_bdm(s, lane) : -1;
-  const int lr = lane < nd ? lane : nd - 1;   // lanes past n_d read a valid row, store nothing
-  const double bp = iu >= 0 ? P.rBp[iu] : 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * EPB + (threadIdx.x >> 6); e < P.ne; e += (int64_t)gridDim.x * EPB) {
-    if (elem_off(P, e)) continue;
-    const R xd = (doA || doBu) ? gather_lane(P, x, e, lane) : R(0);
-    const double sf = P.detJ[e] > 0 ? -1.0 : 1.0;
-    R acc = R(0);
-    if (doA) {
-      const size_t a0 = (size_t)e * nd * nd + lr;   // A^d symmetric: column lr = row lr
-#pragma unroll 8
-      for (int j = 0; j < nd; ++j) acc += MAd(a0 + (size_t)j * nd) * __shfl(xd, j, 64);
+  const int r0 = 2 * sub;                               // the lane's rows r0, r0 + 1
+  const bool act = r0 < nd;
+  const int rc = act ? r0 : nd - 2;                     // inactive lanes read valid rows
+  const int iu0 = act ? facet_row_bdm(s, r0) : -1, iu1 = act ? facet_row_bdm(s, r0 + 1) : -1;
+  const double bp0 = iu0 >= 0 ? P.rBp[iu0] : 0.0, bp1 = iu1 >= 0 ? P.rBp[iu1] : 0.0;
+  const int64_t per = (int64_t)(blockDim.x / 64) * 4;   // elements per workgroup
+  for (int64_t e0 = (int64_t)blockIdx.x * per + (threadIdx.x >> 6) * 4; e0 < P.ne; e0 += (int64_t)gridDim.x * per) {
+    // every lane takes part in the shuffles; slots past the end or switched
+    // off read a valid element and store nothing
+    const int64_t eslot = e0 + es;
+    const bool live = eslot < P.ne && !elem_off(P, eslot);
+    const int64_t e = eslot < P.ne ? eslot : P.ne - 1;
+    R xd0 = R(0), xd1 = R(0);
+    if ((doA || doBu) && act) {
+      xd0 = gather_lane(P, x, e, r0);
+      xd1 = gather_lane(P, x, e, r0 + 1);
     }
-    if (doBT && iu >= 0) acc += (R)(sf * (bp * (double)x[P.off_p + e]));
-    if (lane < nd) escr[e * nd + lane] = acc;
+    const double sf = P.detJ[e] > 0 ? -1.0 : 1.0;
+    R acc0 = R(0), acc1 = R(0);
+    if (doA) {
+      const size_t a0 = (size_t)e * nd * nd + rc;
+#pragma unroll 8
+      for (int j = 0; j < nd; ++j) {
+        const R xj = (j & 1) ? __shfl(xd1, gbase + (j >> 1), 64) : __shfl(xd0, gbase + (j >> 1), 64);
+        R m0, m1;
+        if constexpr (std::is_same<MA, MatP<R>>::value) {
+          const r2v m = *reinterpret_cast<const r2v*>(MAd.p + a0 + (size_t)j * nd);
+          m0 = m.x;
+          m1 = m.y;
+        } else {
+          m0 = MAd(a0 + (size_t)j * nd);
+          m1 = MAd(a0 + (size_t)j * nd + 1);
+        }
+        acc0 += m0 * xj;
+        acc1 += m1 * xj;
+      }
+    }
+    if (doBT) {
+      const double pe = (double)x[P.off_p + e];
+      if (iu0 >= 0) acc0 += (R)(sf * (bp0 * pe));
+      if (iu1 >= 0) acc1 += (R)(sf * (bp1 * pe));
+    }
+    if (live && act) {
+      r2v o;
+      o.x = acc0;
+      o.y = acc1;
+      *reinterpret_cast<r2v*>(escr + e * nd + r0) = o;
+    }
     if (doBu) {
-      const double a = lane_sum(iu >= 0 ? bp * (sf * (double)xd) : 0.0);
-      if (lane == 0) y[P.off_p + e] = (R)a;
-    } else if (!(flags & 8) && (flags & 16) && lane == 0) {
+      double a = (iu0 >= 0 ? bp0 * (sf * (double)xd0) : 0.0) + (iu1 >= 0 ? bp1 * (sf * (double)xd1) : 0.0);
+#pragma unroll
+      for (int off = LPE / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+      if (live && sub == 0) y[P.off_p + e] = (R)a;
+    } else if (!(flags & 8) && (flags & 16) && live && sub == 0) {
       y[P.off_p + e] = R(0);
     }
   }
@@ -107,7 +147,13 @@ static unsigned wave_grid(int64_t ne) {
 template <typename R>
 void launch_elem_apply_wave(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* x, R* y, R* escr,
                             int flags) {
-  const dim3 g(wave_grid(P.ne)), b(64 * EPB);
+  if (P.s.nd > 32 || P.s.nd % 2) {   // the kernel's lane layout: two rows per lane, 16 lanes
+    launch_elem_apply<R>(st, P, O, x, y, escr, flags);
+    return;
+  }
+  // four elements per wave
+  const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((P.ne + 4 * EPB - 1) / (4 * EPB), 1 << 20))),
+      b(64 * EPB);
   if constexpr (sizeof(R) == 8) {
     if (!O.Ad) {   // split storage: FP64 entries as FP32 hi + lo
       hipLaunchKernelGGL((k_elem_apply_wave<R, MatHL>), g, b, 0, st, P, MatHL{O.hAd, O.lAd}, x, y, escr, flags);
