@@ -13,7 +13,7 @@
  * lowest-order Raviart-Thomas space entering through kappa(omega), one flux
  * dof per facet beside the velocity dofs, only sigma condensed, the
  * stabilisation nu |T|^(2/3) (div omega, div eta)_T, E u = (u, Pi^0 u_t,
- * curl u); homogeneous Dirichlet boundaries only), and solved
+ * curl u); Dirichlet boundaries only), and solved
  * by MINRES preconditioned with the block factorisation eq. (mhatinvfactor)
  * whose velocity block is the multiplicative auxiliary-space preconditioner
  * of the double Schur complement (Sec. 6.1, Theorem aux_pc_schur, Corollary
@@ -132,7 +132,7 @@ typedef struct {
 } mcs_mesh;
 
 typedef struct {
-  int32_t order;            /* k in 2..5; k = 1: dim 3, all-Dirichlet, single problems (Sec. 6) */
+  int32_t order;            /* k in 2..5; k = 1: dim 3, Dirichlet faces only, single problems (Sec. 6) */
   int32_t precision;        /* 0: FP64 MINRES; 1: FP32 inner MINRES + FP64 refinement */
   int32_t smoothing_steps;  /* block-GS sweeps before / after the coarse correction (2) */
   int32_t max_it;           /* MINRES iteration limit (per inner solve) */
@@ -212,9 +212,9 @@ int mcs_load(mcs_problem* pb, const double* f_lattice, double* b);
  * (mu^beta / |F|, |beta| = k) and of g_t onto V-hat(F); the solution is then
  * the lift x_D plus the free dofs that mcs_solve returns (mcs_load subtracts
  * K x_D; mcs_eval and mcs_eval_stress include x_D).  g_lattice_host = NULL
- * returns to homogeneous data.  Needs a bound problem.  [sync]  Errors:
- * MCS_ERR_ARG for non-finite data; MCS_ERR_UNSUPPORTED for k = 1 (built for
- * homogeneous data). */
+ * returns to homogeneous data.  For k = 1 the flux of curl g through each
+ * Dirichlet facet is omega's dof there (Sec. 6).  Needs a bound problem.
+ * [sync]  Errors: MCS_ERR_ARG for non-finite data. */
 int mcs_set_dirichlet(mcs_problem* pb, const double* g_lattice_host);
 
 /* y = op x (see mcs_op); x, y: device vectors of length n_dof in dtype dt

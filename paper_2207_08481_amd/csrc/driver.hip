@@ -690,10 +690,6 @@ int mcs_set_dirichlet(mcs_problem* pb, const double* g_lattice_host) {
     pb->has_dirichlet = false;
     return MCS_OK;
   }
-  if (pb->sz.nw) {
-    set_error("mcs_set_dirichlet: k = 1 is built for homogeneous Dirichlet data");
-    return MCS_ERR_UNSUPPORTED;
-  }
   std::vector<double> xd;
   try {
     dirichlet_lift(pb, g_lattice_host, xd);

@@ -656,8 +656,9 @@ RefTables build_ref_tables(int d, int k) {
 // order of the element ([n_e][n_d]): the normal dofs c with
 // sum_beta c_beta mu^beta / |F| the L2 projection of g.n_F onto P^k(F), and
 // the tangential dofs the L2 projection of g_t onto V-hat(F) (basis
-// mu^gamma t_b, t_b = x_{f_b} - x_{f_0}).  g is interpolated on the facet
-// from the lattice points that lie on it.
+// mu^gamma t_b, t_b = x_{f_b} - x_{f_0}); for k = 1 also the flux of curl g
+// through the facet (omega's dof).  g is interpolated on the facet from the
+// lattice points that lie on it.
 void dirichlet_lift(const mcs_problem* pb, const double* g_lattice, std::vector<double>& xD) {
   const Sizes& s = pb->sz;
   const int d = pb->d, nv = d + 1, k = s.k, m = s.m;
@@ -766,6 +767,24 @@ void dirichlet_lift(const mcs_problem* pb, const double* g_lattice, std::vector<
             }
         solve_dense(M, nt, rhs);
         for (int q = 0; q < nt; ++q) out[s.nF + q] = rhs[q];
+      }
+      // k = 1 (Sec. 6): omega's dof, the flux of curl g through F w.r.t.
+      // n_F, by Stokes the circulation of g's interpolant along dF
+      // (X_0 -> X_1 -> X_2, positive about n_F); on the edge from a to b a
+      // facet monomial mu^beta with no weight on the third vertex integrates
+      // to beta_a! beta_b! / (beta_a + beta_b + 1)! times (X_b - X_a)
+      if (s.nw) {
+        double circ = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          const int b = (a + 1) % 3, o = (a + 2) % 3;
+          for (int j = 0; j < nm; ++j) {
+            if (Fm[j][o] != 0) continue;
+            double gt = 0.0;
+            for (int r = 0; r < d; ++r) gt += coef[(size_t)j * d + r] * (X[b][r] - X[a][r]);
+            circ += fact(Fm[j][a]) * fact(Fm[j][b]) / fact(Fm[j][a] + Fm[j][b] + 1) * gt;
+          }
+        }
+        out[s.nF + s.nh] = circ;
       }
     }
   }

@@ -13,6 +13,7 @@ levels)."""
 import numpy as np
 import pytest
 
+import workloads as W
 from tests.minres_parity import check_equal_iterations, check_iterations, oracle_twin
 from tests.test_gpu_parity import _l2_rel, _rel, setup_case
 
@@ -181,15 +182,47 @@ def test_lowest_order_variants(smoother, variant):
 
 
 def test_lowest_order_refusals_on_device():
-    """The stress recovery and inhomogeneous Dirichlet data are built for
-    k >= 2: refused with ERR_UNSUPPORTED, the problem stays usable."""
+    """The stress recovery is built for k >= 2: refused with ERR_UNSUPPORTED,
+    the problem stays usable."""
     from paper_2207_08481_amd.mcs import MCSError
     c = setup_case(3, 1, 1)
     pb = c["pb"]
     x = torch.zeros(pb.n_dof, dtype=torch.float64, device="cuda:0")
     with pytest.raises(MCSError, match="ERR_UNSUPPORTED"):
         pb.eval_stress(x, np.array([[0.25, 0.25, 0.25, 0.25]]))
-    with pytest.raises(MCSError, match="ERR_UNSUPPORTED"):
-        pb.set_dirichlet(np.zeros_like(c["f"]))
     y = pb.apply("K", torch.ones(pb.n_dof, dtype=torch.float64, device="cuda:0")).cpu().numpy()
     assert _rel(y, c["K"] @ np.ones(pb.n_dof)) < 1e-12
+
+
+def test_lowest_order_linear_flow_with_dirichlet_data():
+    """Inhomogeneous Dirichlet data at k = 1: on a Dirichlet facet the lift
+    holds the normal moments and tangential means of g and the flux of curl g
+    (omega's dof).  A linear divergence-free flow with its boundary values and
+    f = grad p for a linear p (the oracle's patch test) is reproduced at
+    points of every element, the pressure as its element means, and the load
+    vector with the lift equals the oracle's."""
+    from oracle.system import GlobalSystem
+    from paper_2207_08481_amd import Problem
+    Gm = np.array([[1.0, -1.0, 2.0], [3.0, 1.0, -1.0], [1.0, -2.0, -2.0]])
+    c0 = np.array([0.3, -0.2, 0.5])
+    gp = np.array([0.5, -1.0, 2.0])
+    mesh = W.unit_cube_mesh(2)
+    pts = W.lattice_points(mesh, 2)
+    f = np.broadcast_to(gp, pts.shape).copy()
+    g = pts @ Gm.T + c0
+    gs = GlobalSystem(mesh.vertices, mesh.elements, 0.8, 1, f, g_lattice=g)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 1, tol=1e-12, max_it=3000).bind("cuda:0")
+    pb.condense(torch.full((mesh.n_elements,), 0.8, dtype=torch.float64, device="cuda:0"))
+    pb.set_dirichlet(g)
+    ft = torch.as_tensor(f, device="cuda:0")
+    assert _rel(pb.load(ft).cpu().numpy(), gs.assemble_rhs()) < 1e-12
+    x, si = pb.solve(ft)
+    assert si["status"] == 0, si
+    lam = np.random.default_rng(4).dirichlet(np.ones(4), size=5)
+    u, p = pb.eval(x, lam)
+    X = np.einsum("pj,ejr->epr", lam, mesh.vertices[mesh.elements])
+    assert np.abs(u.cpu().numpy() - (X @ Gm.T + c0)).max() < 1e-8
+    pm = mesh.vertices[mesh.elements].mean(axis=1) @ gp       # element means of p (equal volumes)
+    ph = p.cpu().numpy()
+    assert np.abs(ph - ph[:, :1]).max() < 1e-10               # P^0 pressure
+    assert np.abs((ph[:, 0] - ph[:, 0].mean()) - (pm - pm.mean())).max() < 1e-8
