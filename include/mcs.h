@@ -132,7 +132,7 @@ typedef struct {
 } mcs_mesh;
 
 typedef struct {
-  int32_t order;            /* k in 2..5; k = 1: dim 3, Dirichlet faces only, single problems (Sec. 6) */
+  int32_t order;            /* k in 2..5; k = 1: dim 3, Dirichlet faces only (Sec. 6) */
   int32_t precision;        /* 0: FP64 MINRES; 1: FP32 inner MINRES + FP64 refinement */
   int32_t smoothing_steps;  /* block-GS sweeps before / after the coarse correction (2) */
   int32_t max_it;           /* MINRES iteration limit (per inner solve) */
@@ -388,9 +388,8 @@ typedef struct {
   size_t workspace_bytes;   /* bytes the caller must provide to mcs_batch_bind */
 } mcs_batch_info;
 
-/* Host only.  Plans n >= 1 members: meshes[i] with order orders[i] (2..5:
- * k = 1 is for single problems, MCS_ERR_UNSUPPORTED); the other options
- * (precision, tolerances, smoothing, limits) are shared.  Errors as
+/* Host only.  Plans n >= 1 members: meshes[i] with order orders[i]; the other
+ * options (precision, tolerances, smoothing, limits) are shared.  Errors as
  * mcs_plan, naming the member. */
 int mcs_batch_plan(const mcs_mesh* meshes, const int32_t* orders, int32_t n, const mcs_options* options,
                    mcs_batch** out, mcs_batch_info* info);

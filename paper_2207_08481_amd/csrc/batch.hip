@@ -297,11 +297,6 @@ int mcs_batch_plan(const mcs_mesh* meshes, const int32_t* orders, int32_t n, con
     set_error("batch plan: the full-system variant (smoother 2) is for single problems");
     return MCS_ERR_UNSUPPORTED;
   }
-  for (int i = 0; i < n; ++i)
-    if (orders[i] == 1) {
-      set_error("batch plan: member %d has k = 1; the lowest order is built for single problems", i);
-      return MCS_ERR_UNSUPPORTED;
-    }
   *out = nullptr;
   std::unique_ptr<mcs_batch> B(new (std::nothrow) mcs_batch());
   if (!B) {

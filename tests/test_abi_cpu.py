@@ -303,8 +303,9 @@ def test_solve_options_setter_validates():
 @needs_lib
 def test_lowest_order_plan_and_refusals():
     """k = 1 (Sec. 6) plans in 3D with facet blocks of six dofs and no
-    bubbles; it is refused in 2D (ERR_ARG), with outlet faces, with the
-    full-system variant and in batches (ERR_UNSUPPORTED)."""
+    bubbles, also as a batch member (a group of its own); it is refused in 2D
+    (ERR_ARG), with outlet faces and with the full-system variant
+    (ERR_UNSUPPORTED)."""
     from paper_2207_08481_amd import Batch, Problem
     from paper_2207_08481_amd.mcs import MCSError
     m3 = W.unit_cube_mesh(2)
@@ -317,5 +318,5 @@ def test_lowest_order_plan_and_refusals():
         Problem(m3.vertices, m3.elements, m3.lattice, 1, face_bc=[0, 1, 0, 0, 0, 0])
     with pytest.raises(MCSError, match="ERR_UNSUPPORTED"):
         Problem(m3.vertices, m3.elements, m3.lattice, 1, smoother=2)
-    with pytest.raises(MCSError, match="member 1"):
-        Batch([(m3.vertices, m3.elements, m3.lattice)] * 2, [2, 1])
+    b = Batch([(m3.vertices, m3.elements, m3.lattice)] * 2, [2, 1])
+    assert b.info.n_groups == 2

@@ -169,3 +169,56 @@ def test_batch_matches_single_problem_solve():
     x1, si = pb.solve(torch.as_tensor(c["f"], device="cuda:0"))
     assert abs(si["iterations"] - infos[0]["iterations"]) <= 1
     assert (xs[0] - x1).norm().item() <= 1e-9 * x1.norm().item()
+
+
+# k = 1 members (Sec. 6: their own group, no bubbles, facet blocks of 6)
+# beside a k = 2 member: (dim, n, k, nu, force seed)
+K1_MEMBERS = [(3, 2, 1, 1.0, 21), (3, 3, 1, 0.6, 22), (3, 2, 2, 1.3, 23)]
+
+
+def test_batch_lowest_order_members():
+    """k = 1 members in a batch: FP64 iterations within +-1 of the oracle's
+    MINRES (or of its twins' range), every member within 1e-8 of its direct
+    solve in FP64 and with FP32 inner iterations, and a k = 1 member bitwise
+    the same alone as in the batch."""
+    _need_gpu()
+    from oracle.minres import minres
+    from oracle.precond import Preconditioner
+    from oracle.system import GlobalSystem
+    from paper_2207_08481_amd import Batch
+    from tests.minres_parity import check_iterations, oracle_twin
+    cs = []
+    for d, n, k, nu, seed in K1_MEMBERS:
+        mesh = W.unit_cube_mesh(n)
+        nu_e = np.full(mesh.n_elements, nu)
+        f = W.RandomForce(d, seed=seed).f(W.lattice_points(mesh, k + 1))
+        cs.append(dict(mesh=mesh, nu=nu_e, f=f, k=k, gs=GlobalSystem(mesh.vertices, mesh.elements, nu_e, k, f)))
+    print("[batch] k = 1 members", K1_MEMBERS, flush=True)
+    fs = [torch.as_tensor(c["f"], device="cuda:0") for c in cs]
+    res = {}
+    for precision in (0, 1):
+        b = Batch([(c["mesh"].vertices, c["mesh"].elements, c["mesh"].lattice) for c in cs], [c["k"] for c in cs],
+                  precision=precision, tol=1e-10, max_it=3000).bind("cuda:0")
+        assert b.info.n_groups == 2
+        b.condense([torch.as_tensor(c["nu"], device="cuda:0") for c in cs])
+        res[precision] = b.solve(fs)
+    xs, infos = res[0]
+    for x, c, inf in zip(xs, cs, infos):
+        assert inf["status"] == 0, inf
+        gs = c["gs"]
+        K = gs.assemble_K()
+        pc = Preconditioner(gs, c["mesh"].lattice)
+        _, oinfo = minres(lambda v: K @ v, pc.apply, gs.assemble_rhs(), tol=1e-10, max_it=3000)
+        print(f"  k={c['k']}: iterations batch {inf['iterations']} oracle {oinfo['iterations']}", flush=True)
+        check_iterations(gs, inf["iterations"], oinfo["iterations"], oracle_twin(c["mesh"], c["nu"], c["k"], c["f"]))
+    for precision in (0, 1):
+        xs_p, infos_p = res[precision]
+        for x, c, inf in zip(xs_p, cs, infos_p):
+            assert inf["status"] == 0, inf
+            eu, ep = _l2_rel(c["gs"], x.cpu().numpy(), c["gs"].direct_solve())
+            assert eu < 1e-8 and ep < 1e-8, (precision, c["k"], eu, ep)
+    solo = Batch([(cs[1]["mesh"].vertices, cs[1]["mesh"].elements, cs[1]["mesh"].lattice)], [1], precision=0,
+                 tol=1e-10, max_it=3000).bind("cuda:0")
+    solo.condense([torch.as_tensor(cs[1]["nu"], device="cuda:0")])
+    xs1, _ = solo.solve([fs[1]])
+    assert torch.equal(xs1[0], res[0][0][1])
