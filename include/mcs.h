@@ -272,8 +272,9 @@ int mcs_eval(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_
  * sigma_vals and omega_vals (device) [n_elements][n_pts][dim][dim], row-major
  * matrices.  For conforming velocity data sigma_h = -nu dev eps(u_h) and
  * omega_h = kappa(curl u_h) (Lemma SPD).  Needs mcs_condense first
- * (MCS_ERR_STATE); n_pts as for mcs_eval (MCS_ERR_ARG); k = 1 is refused
- * (MCS_ERR_UNSUPPORTED).  Uses the condensation scratch.  [sync] */
+ * (MCS_ERR_STATE); n_pts as for mcs_eval (MCS_ERR_ARG).  For k = 1 omega_h is
+ * the Raviart-Thomas field of the facet fluxes in x and omega_vals holds
+ * kappa(omega_h).  Uses the condensation scratch.  [sync] */
 int mcs_eval_stress(mcs_problem* pb, const double* x, int32_t n_pts, const double* ref_pts_host,
                     double* sigma_vals, double* omega_vals);
 

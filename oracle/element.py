@@ -431,9 +431,22 @@ def recover_stress(ed, nu, k, u_local):
     u_local: velocity coefficients in the local order of the matrix 'A'
     ([Phi | Vhat]).  Returns coefficient arrays over lambda^alpha (sorted
     vertices): S (|I_k|, d, d) for sigma_h and W (|I_{k-1}|, d, d) for
-    omega_h."""
+    omega_h (k = 1: W (|I_1|, d, d), the skew field kappa(omega_h))."""
     if k == 1:
-        raise NotImplementedError("stress recovery is built for k >= 2")
+        # Sec. 6: only sigma is local; -M_ss sigma + B^T (u, uhat, omega) = 0,
+        # and omega is the Raviart-Thomas field of its facet fluxes (returned
+        # as kappa(omega), degree 1)
+        es = element_system(ed, nu, k, keep_blocks=True)
+        Z, Mss, Bsig, Dm = es["Z"], es["Mss"], es["Bsig"], es["Dm"]
+        ul = np.asarray(u_local, dtype=np.float64)
+        sig = np.linalg.solve(Mss, Bsig.T @ ul)
+        cs = (Z @ sig).reshape(ed.d + 1, len(Dm))
+        S = np.einsum("am,mrs->ars", cs, Dm)
+        Crt, _ = rt0_basis(ed)
+        n_u, n_hat = ed.dims["n_u"], ed.dims["n_hat"]
+        wdof = ul[n_u + (ed.d + 1) * n_hat:]
+        W = np.array([kappa(wdof @ Crt[:, j]) for j in range(ed.d + 1)])
+        return S, W
     es = element_system(ed, nu, k, keep_blocks=True)
     Z, Mss, Bws, Bsig, Dm, Kn = es["Z"], es["Mss"], es["Bws"], es["Bsig"], es["Dm"], es["Kn"]
     n_sig, n_om = Z.shape[1], Bws.shape[0]

@@ -270,4 +270,4 @@ class GlobalSystem:
         from .poly import evaluate
         es = self.elems[e]
         S, W = recover_stress(es["ed"], self.nu[e], self.k, self.local_velocity(x, e))
-        return evaluate(S, self.d + 1, self.k, lam), evaluate(W, self.d + 1, self.k - 1, lam)
+        return evaluate(S, self.d + 1, self.k, lam), evaluate(W, self.d + 1, max(self.k - 1, 1), lam)

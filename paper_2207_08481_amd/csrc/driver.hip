@@ -1134,10 +1134,6 @@ int mcs_eval_stress(mcs_problem* pb, const double* x, int32_t n_pts, const doubl
     set_error("mcs_eval_stress: call mcs_condense first");
     return MCS_ERR_STATE;
   }
-  if (pb->sz.nw) {
-    set_error("mcs_eval_stress: the stress recovery is built for k >= 2");
-    return MCS_ERR_UNSUPPORTED;
-  }
   const int nv = pb->d + 1;
   if (!x || !ref_pts_host || !sigma_vals || !omega_vals || n_pts <= 0 || (int64_t)n_pts * nv > pb->nred) {
     set_error("mcs_eval_stress: null pointer or n_pts outside 1..%lld", (long long)(pb->nred / nv));

@@ -1182,7 +1182,9 @@ __global__ void __launch_bounds__(256) k_stress(StressParams S) {
   const CondParams& P = S.C;
   const Sizes s = P.s;
   const int d = s.d, nv = d + 1, tid = threadIdx.x;
-  const int nW = s.nskew * s.nsm1;
+  // omega's coefficients (k >= 2: the skew P^{k-1} multiplier, recovered
+  // from the local problem; k = 1: omega is global, its facet fluxes are in x)
+  const int nW = s.nw ? 0 : s.nskew * s.nsm1;
   __shared__ ElemGeo g;
   __shared__ double sEm[8][3][3];
   __shared__ double sW[4][8][3];
@@ -1263,15 +1265,15 @@ __global__ void __launch_bounds__(256) k_stress(StressParams S) {
         psi[a] = v;
       }
       double sg[3][3] = {}, om[3][3] = {};
-      const int ntop = s.ns - s.nsm1;
+      const int ntop = s.ns - s.sklo;
       for (int m = 0; m < s.nsym + s.nskew; ++m) {
         double cs = 0.0, cw = 0.0;
         if (m < s.nsym) {
           for (int a = 0; a < s.ns; ++a) cs += gs[m * s.ns + a] * psi[a];
         } else {
           const int mk = m - s.nsym;
-          for (int a = 0; a < ntop; ++a) cs += gs[s.nsym * s.ns + mk * ntop + a] * psi[s.nsm1 + a];
-          for (int a = 0; a < s.nsm1; ++a) cw += wc[mk * s.nsm1 + a] * psi[a];
+          for (int a = 0; a < ntop; ++a) cs += gs[s.nsym * s.ns + mk * ntop + a] * psi[s.sklo + a];
+          for (int a = 0; a < nW / s.nskew; ++a) cw += wc[mk * s.nsm1 + a] * psi[a];
         }
         double D[3][3];
         dm_basis(d, m, D);
@@ -1280,6 +1282,22 @@ __global__ void __launch_bounds__(256) k_stress(StressParams S) {
             sg[r][c] += cs * D[r][c];
             om[r][c] += cw * D[r][c];
           }
+      }
+      if (s.nw) {
+        // k = 1: omega_h = sum_f flux_f s_f (x - x_f) / (d |T|) with
+        // x - x_f = sum_j lambda_j (x_j - x_f); the output is kappa(omega_h)
+        double w[3] = {0.0, 0.0, 0.0};
+        for (int f = 0; f < nv; ++f) {
+          const double cf = ul[s.nb + f * s.nfb + s.nF + s.nh] * rt_sign(g, f) / (d * g.vol);
+          for (int j = 0; j < nv; ++j)
+            for (int r = 0; r < 3; ++r) w[r] += cf * lam[j] * (g.X[j][r] - g.X[f][r]);
+        }
+        om[0][1] = -0.5 * w[2];
+        om[0][2] = 0.5 * w[1];
+        om[1][0] = 0.5 * w[2];
+        om[1][2] = -0.5 * w[0];
+        om[2][0] = -0.5 * w[1];
+        om[2][1] = 0.5 * w[0];
       }
       const size_t o = ((size_t)e * S.npts + q) * d * d;
       for (int r = 0; r < d; ++r)

@@ -631,7 +631,7 @@ def test_kernel_timer_counts():
 
 
 @pytest.mark.parametrize("d,n,k,nu_kind", [(2, 4, 2, "one"), (2, 2, 5, "lognormal"), (3, 2, 2, "lognormal"),
-                                           (3, 1, 4, "one"), (3, 1, 5, "lognormal")])
+                                           (3, 1, 4, "one"), (3, 1, 5, "lognormal"), (3, 2, 1, "lognormal")])
 def test_stress_recovery_matches_oracle(d, n, k, nu_kind):
     """mcs_eval_stress: sigma_h and omega_h recovered element by element from
     an arbitrary coefficient vector (local problems eq. projection) equal the

@@ -247,3 +247,45 @@ def test_velocity_converges_in_h():
     r1 = math.log(errs[0] / errs[1]) / math.log(1.5)
     r2 = math.log(errs[1] / errs[2]) / math.log(4 / 3)
     assert errs[2] < errs[1] < errs[0] and r1 > 0.9 and r2 > 1.2, (errs, r1, r2)
+
+
+def test_stress_of_a_linear_flow():
+    """Recovery at k = 1: for a linear velocity with its facet means as uhat
+    and omega = curl u (conforming data), sigma_h = -nu dev eps(u) and
+    kappa(omega_h) = kappa(curl u), the skew part of grad u."""
+    from oracle.element import recover_stress
+    from oracle.poly import evaluate
+    X, ed = _element()
+    rng = np.random.default_rng(8)
+    G = rng.standard_normal((3, 3))
+    curl = np.array([G[2, 1] - G[1, 2], G[0, 2] - G[2, 0], G[1, 0] - G[0, 1]])
+    ul = _linear_field_dofs(X, ed, G, rng.standard_normal(3), curl)
+    nu = 0.6
+    S, W = recover_stress(ed, nu, 1, ul)
+    lam = rng.dirichlet(np.ones(4), size=5)
+    eps = 0.5 * (G + G.T)
+    dev = eps - np.trace(eps) / 3 * np.eye(3)
+    assert np.abs(evaluate(S, 4, 1, lam) - (-nu * dev)).max() <= 1e-10 * np.abs(G).max()
+    assert np.abs(evaluate(W, 4, 1, lam) - 0.5 * (G - G.T)).max() <= 1e-10 * np.abs(G).max()
+
+
+def test_stress_energy_identity():
+    """For arbitrary element coefficients (u, uhat, omega): the condensed
+    energy is nu^-1 ||sigma_h||^2 + nu/3 ||div u||^2 plus the stabilisation
+    nu |T|^(2/3) ||div omega||^2."""
+    from oracle.element import recover_stress, rt0_basis
+    from oracle.poly import product_moments
+    X, ed = _element()
+    nu = 0.7
+    es = element_system(ed, nu, 1)
+    rng = np.random.default_rng(5)
+    ul = rng.standard_normal(es["A"].shape[0])
+    S, _ = recover_stress(ed, nu, 1, ul)
+    Gm = product_moments(4, 1, 1) * ed.vol
+    ss = np.einsum("ars,ab,brs->", S, Gm, S)
+    cu = ul[: es["Adiv"].shape[0]]
+    _, divrt = rt0_basis(ed)
+    w = ul[-4:]
+    stab = nu * ed.vol ** (2.0 / 3.0) * ed.vol * (divrt @ w) ** 2
+    lhs = ul @ es["A"] @ ul
+    assert abs(lhs - (ss / nu + cu @ es["Adiv"] @ cu + stab)) <= 1e-11 * abs(lhs)
