@@ -132,7 +132,7 @@ typedef struct {
 } mcs_mesh;
 
 typedef struct {
-  int32_t order;            /* k in 2..5; k = 1: dim 3, Dirichlet faces only (Sec. 6) */
+  int32_t order;            /* k in 2..5; k = 1: dim 3 only (Sec. 6) */
   int32_t precision;        /* 0: FP64 MINRES; 1: FP32 inner MINRES + FP64 refinement */
   int32_t smoothing_steps;  /* block-GS sweeps before / after the coarse correction (2) */
   int32_t max_it;           /* MINRES iteration limit (per inner solve) */
@@ -179,9 +179,10 @@ typedef struct mcs_problem mcs_problem;
  * and the multigrid plan; fills *info (sizes, workspace bytes).  Reference:
  * Sec. 3 (mesh, facets, spaces); k = 1: Sec. 6 (facet blocks of n_F + n_hat
  * + 1 = 6 dofs: normal moments, tangential means, the flux of omega; no
- * bubbles).  Errors: MCS_ERR_ARG (k = 1 in 2D among others), MCS_ERR_MESH,
- * MCS_ERR_UNSUPPORTED (k > 5; k = 1 with outlet faces or the full-system
- * variant). */
+ * bubbles; on an outlet facet the tangential dofs are fixed to zero and the
+ * omega flux stays an unknown).  Errors: MCS_ERR_ARG (k = 1 in 2D among
+ * others), MCS_ERR_MESH, MCS_ERR_UNSUPPORTED (k > 5; k = 1 with the
+ * full-system variant). */
 int mcs_plan(const mcs_mesh* mesh, const mcs_options* options, mcs_problem** out,
              mcs_info* info);
 

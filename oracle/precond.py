@@ -242,10 +242,9 @@ def embedding(gs, full=False):
                     base = gs.off_f + g * gs.nfb
                     for q in range(nF):
                         rows.append(base + q); cols.append(col); vals.append(cu[nb + i * nF + q])
-                    if topo.free_outlet[g]:
-                        continue                # pi_0: no tangential rows on outlets
-                    for q in range(nh):
-                        rows.append(base + nF + q); cols.append(col); vals.append(ch[i][q])
+                    if not topo.free_outlet[g]:  # pi_0: no tangential rows on outlets
+                        for q in range(nh):
+                            rows.append(base + nF + q); cols.append(col); vals.append(ch[i][q])
                     if gs.dims["n_w"]:
                         # k = 1 (Sec. 6): the omega component curl(u-bar); its
                         # flux through F w.r.t. n_F, |F| (grad lambda_v x e_c) . n_F

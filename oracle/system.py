@@ -59,8 +59,6 @@ class GlobalSystem:
         self.elems = []
         self.xD = []
         n_u, nh = dims["n_u"], dims["n_hat"]
-        if k == 1 and topo.has_outlet:
-            raise NotImplementedError("k = 1 is built for Dirichlet boundaries only")
         for e in range(n_e):
             X = topo.element_coords(e)
             ed = element_geometry(X, k)

@@ -489,14 +489,15 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
       }
     __syncthreads();
     // tangential dofs of an outlet facet are fixed to zero: identity rows and
-    // columns, so that they decouple before the bubbles are condensed
+    // columns, so that they decouple before the bubbles are condensed (k = 1:
+    // the omega flux stays free there, W_h vanishes on Gamma_D only, Sec. 6)
     if (P.facet_out) {
       const int nv = d + 1;
       auto pinned = [&](int r) {
         if (r < s.nb) return false;
         const int f = (r - s.nb) / s.nfb, q = (r - s.nb) % s.nfb;
         const int gf = P.elem_ff[e * nv + f];
-        return q >= s.nF && gf >= 0 && P.facet_out[gf] != 0;
+        return q >= s.nF && q < s.nF + s.nh && gf >= 0 && P.facet_out[gf] != 0;
       };
       for (int idx = tid; idx < s.nA * s.nA; idx += blockDim.x) {
         const int r = idx / s.nA, c = idx % s.nA;

@@ -144,10 +144,6 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
     }
     if (mesh->face_bc[a] == 1) ffm |= 1 << a;
   }
-  if (k == 1 && ffm) {
-    set_error("k = 1 is built for Dirichlet boundaries only (no outlet faces)");
-    return MCS_ERR_UNSUPPORTED;
-  }
   pb->pffm.assign(1, ffm);
   pb->d = d;
   pb->opt = *opt;

@@ -33,7 +33,8 @@ def l2_rel(gs, x, y):
     return np.sqrt(du / nu_), np.sqrt(dp / np_)
 
 
-def oracle_twin(mesh, nu, k, f, coarse_max=512, variant="multiplicative", smoothing_steps=2, seed=1):
+def oracle_twin(mesh, nu, k, f, coarse_max=512, variant="multiplicative", smoothing_steps=2, seed=1,
+                face_bc=None, g_lattice=None):
     """A callable building the twin: (K, K-hat^{-1}, b) of the oracle's
     system with Sigma_h(T) in a rotated basis (build(rotation) takes another
     rotation seed)."""
@@ -41,7 +42,8 @@ def oracle_twin(mesh, nu, k, f, coarse_max=512, variant="multiplicative", smooth
         from oracle.precond import Preconditioner
         from oracle.system import GlobalSystem
         rs = seed if rotation is None else rotation
-        gs = GlobalSystem(mesh.vertices, mesh.elements, nu, k, f, sigma_rotation_seed=rs)
+        gs = GlobalSystem(mesh.vertices, mesh.elements, nu, k, f, face_bc=face_bc, g_lattice=g_lattice,
+                          sigma_rotation_seed=rs)
         pc = Preconditioner(gs, mesh.lattice, smoothing_steps=smoothing_steps, coarse_max=coarse_max,
                             variant=variant)
         return gs.assemble_K(), pc.apply, gs.assemble_rhs()

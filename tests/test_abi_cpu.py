@@ -303,9 +303,9 @@ def test_solve_options_setter_validates():
 @needs_lib
 def test_lowest_order_plan_and_refusals():
     """k = 1 (Sec. 6) plans in 3D with facet blocks of six dofs and no
-    bubbles, also as a batch member (a group of its own); it is refused in 2D
-    (ERR_ARG), with outlet faces and with the full-system variant
-    (ERR_UNSUPPORTED)."""
+    bubbles, also as a batch member (a group of its own) and with an outlet
+    face (one more free facet layer, as for k >= 2); it is refused in 2D
+    (ERR_ARG) and with the full-system variant (ERR_UNSUPPORTED)."""
     from paper_2207_08481_amd import Batch, Problem
     from paper_2207_08481_amd.mcs import MCSError
     m3 = W.unit_cube_mesh(2)
@@ -314,8 +314,8 @@ def test_lowest_order_plan_and_refusals():
     m2 = W.unit_square_mesh(3)
     with pytest.raises(MCSError, match="ERR_ARG"):
         Problem(m2.vertices, m2.elements, m2.lattice, 1)
-    with pytest.raises(MCSError, match="ERR_UNSUPPORTED"):
-        Problem(m3.vertices, m3.elements, m3.lattice, 1, face_bc=[0, 1, 0, 0, 0, 0])
+    io = Problem(m3.vertices, m3.elements, m3.lattice, 1, face_bc=[0, 1, 0, 0, 0, 0]).info
+    assert io.n_fb == 6 and io.n_free_facets == i.n_free_facets + 2 * 2 * 2
     with pytest.raises(MCSError, match="ERR_UNSUPPORTED"):
         Problem(m3.vertices, m3.elements, m3.lattice, 1, smoother=2)
     b = Batch([(m3.vertices, m3.elements, m3.lattice)] * 2, [2, 1])

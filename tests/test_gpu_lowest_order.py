@@ -213,3 +213,66 @@ def test_lowest_order_linear_flow_with_dirichlet_data():
     ph = p.cpu().numpy()
     assert np.abs(ph - ph[:, :1]).max() < 1e-10               # P^0 pressure
     assert np.abs((ph[:, 0] - ph[:, 0].mean()) - (pm - pm.mean())).max() < 1e-8
+
+
+@pytest.mark.parametrize("forced", [False, True])
+def test_lowest_order_with_outlet(forced):
+    """k = 1 with an outlet at x = L (eq. stokes_NT): the outlet's tangential
+    dofs are identity rows, its normal dofs and omega flux are unknowns.
+    forced = False: the oracle's outlet patch test (a linear flow with
+    Dirichlet data on the other faces, p = 0), whose load, operators and
+    K-hat^{-1} equal the oracle's and whose solution is the flow itself.
+    forced = True: homogeneous data and a smooth load; FP64 MINRES iterations
+    against the oracle's (or its twins'), then the equal-iteration bar."""
+    from oracle.minres import minres
+    from oracle.precond import Preconditioner
+    from oracle.system import GlobalSystem
+    from paper_2207_08481_amd import Problem
+    from tests.test_oracle_lowest_order import _outlet_flow
+    mesh, gs, u, fbc = _outlet_flow()
+    nu = 0.9
+    pts = W.lattice_points(mesh, 2)
+    g = u(pts)
+    f = np.zeros(pts.shape)
+    if forced:
+        f = W.CurlModes3D(seed=5, nu=nu).f(pts)
+        g = None
+        gs = GlobalSystem(mesh.vertices, mesh.elements, nu, 1, f, face_bc=fbc)
+    print(f"[k1 outlet] forced={forced} n_e={mesh.n_elements}", flush=True)
+    pc = Preconditioner(gs, mesh.lattice)
+    K = gs.assemble_K()
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 1, face_bc=fbc, tol=1e-10,
+                 max_it=3000).bind("cuda:0")
+    pb.condense(torch.full((mesh.n_elements,), nu, dtype=torch.float64, device="cuda:0"))
+    if g is not None:
+        pb.set_dirichlet(g)
+    ft = torch.as_tensor(f, device="cuda:0")
+    x = np.random.default_rng(3).standard_normal(gs.n_dof)
+    xt = torch.as_tensor(x, device="cuda:0")
+    assert _rel(pb.apply("K", xt).cpu().numpy(), K @ x) < 1e-12
+    yAd = pb.apply("ADELTA", xt).cpu().numpy()
+    assert _rel(yAd[gs.off_f:gs.off_p], (pc.Ad @ x)[gs.off_f:gs.off_p]) < 1e-12
+    assert _rel(pb.load(ft).cpu().numpy(), gs.assemble_rhs()) < 1e-12
+    assert _rel(pb.precond_apply("KHAT", xt).cpu().numpy(), pc.apply(x.copy())) < 1e-11
+    xs, si = pb.solve(ft)
+    assert si["status"] == 0, si
+    xn = xs.cpu().numpy()
+    assert _rel(xn, gs.direct_solve()) < 1e-8
+    if not forced:
+        lam = np.random.default_rng(4).dirichlet(np.ones(4), size=5)
+        uh, ph = pb.eval(xs, lam)
+        X = np.einsum("pj,ejr->epr", lam, mesh.vertices[mesh.elements])
+        assert np.abs(uh.cpu().numpy() - u(X)).max() < 1e-8
+        assert np.abs(ph.cpu().numpy()).max() < 1e-8
+        return
+    xo, info = minres(lambda v: K @ v, pc.apply, gs.assemble_rhs(), tol=1e-10, max_it=3000)
+    ito = info["iterations"]
+    twin = oracle_twin(mesh, nu, 1, f, face_bc=fbc)
+    print(f"  iterations gpu {si['iterations']} oracle {ito}", flush=True)
+    check_iterations(gs, si["iterations"], ito, twin)
+    neq = (2 * ito) // 3
+    xe, _ = minres(lambda v: K @ v, pc.apply, gs.assemble_rhs(), tol=0.0, max_it=neq)
+    pb.set_solve_options(0.0, neq)
+    xq, sq = pb.solve(ft, allow_max_it=True)
+    assert sq["iterations"] == neq
+    check_equal_iterations(gs, xq.cpu().numpy(), xe, neq, twin)

@@ -289,3 +289,82 @@ def test_stress_energy_identity():
     stab = nu * ed.vol ** (2.0 / 3.0) * ed.vol * (divrt @ w) ** 2
     lhs = ul @ es["A"] @ ul
     assert abs(lhs - (ss / nu + cu @ es["Adiv"] @ cu + stab)) <= 1e-11 * abs(lhs)
+
+
+def _outlet_flow(cells=(3, 2, 2), L=1.5, nu=0.9):
+    """u = (c0 + c1 y + c2 z, a (x - L), b (x - L)), p = 0, f = 0: divergence
+    free, u_t = 0 on x = L and eps(u)_nn = du_x/dx = 0 there, so the outlet
+    condition of eq. stokes_NT holds with p = 0; Dirichlet data on the other
+    five faces."""
+    c0, c1, c2, a, b = 0.4, -0.7, 1.1, 0.6, -0.3
+
+    def u(X):
+        X = np.asarray(X, dtype=np.float64)
+        return np.stack([c0 + c1 * X[..., 1] + c2 * X[..., 2], a * (X[..., 0] - L), b * (X[..., 0] - L)], axis=-1)
+
+    mesh = W.box_mesh(cells, (L, 1.0, 1.0))
+    pts = W.lattice_points(mesh, 2)
+    fbc = [0, 1, 0, 0, 0, 0]
+    gs = GlobalSystem(mesh.vertices, mesh.elements, nu, 1, np.zeros(pts.shape), face_bc=fbc, g_lattice=u(pts))
+    return mesh, gs, u, fbc
+
+
+def test_linear_flow_with_outlet_reproduced():
+    """Patch test with an outlet (eq. stokes_NT): the outlet's tangential dofs
+    are fixed to zero, its normal dofs and the omega flux are free (W_h
+    vanishes on Gamma_D only, Sec. 6).  The linear flow and p = 0 are
+    reproduced exactly; the omega flux through the outlet is that of curl u
+    (zero: curl u = (0, c2 - b, a - c1) is tangential to x = L)."""
+    mesh, gs, u, _ = _outlet_flow()
+    assert gs.topo.has_outlet and gs.topo.facet_outlet.sum() == 2 * 2 * 2
+    x = gs.direct_solve()
+    lam = np.random.default_rng(4).dirichlet(np.ones(4), size=6)
+    for e in range(gs.n_e):
+        Xe = gs.topo.element_coords(e)
+        ue, pe = gs.eval_element(x, e, lam)
+        assert np.abs(ue - u(lam @ Xe)).max() < 1e-11
+        assert np.abs(pe).max() < 1e-11
+    for g in np.nonzero(gs.topo.free_outlet)[0]:
+        dofs = gs.facet_dofs(g)
+        assert np.all(x[dofs[gs.nF:gs.nF + gs.nh]] == 0)
+        assert abs(x[dofs[gs.nF + gs.nh]]) < 1e-11
+
+
+def test_outlet_omega_flux_is_free():
+    """The omega flux of an outlet facet is an unknown of the system: its row
+    of K couples to other dofs, while the tangential rows of the outlet are
+    identity rows.  (An exact flow with u_t = 0 on x = L has curl u . n = 0
+    there, so the patch test alone cannot tell a free flux from a fixed one.)"""
+    mesh, gs, _, _ = _outlet_flow(cells=(2, 2, 2), L=1.0)
+    K = gs.assemble_K().tocsr()
+    for g in np.nonzero(gs.topo.free_outlet)[0]:
+        dofs = gs.facet_dofs(g)
+        w = dofs[gs.nF + gs.nh]
+        row = K[w].toarray().ravel()
+        row[w] = 0.0
+        assert np.abs(row).max() > 0
+        for q in dofs[gs.nF:gs.nF + gs.nh]:
+            r = K[q].toarray().ravel()
+            assert r[q] == 1.0 and np.count_nonzero(r) == 1
+
+
+def test_outlet_preconditioned_minres_matches_direct():
+    """Lemma outflow for the lowest order: with the tangential penalty in
+    A-bar and pi_0 in E (the curl row kept on outlets), E^T A E is bounded by
+    A-bar, and the preconditioned MINRES reaches the direct solution."""
+    mesh, gs, _, _ = _outlet_flow(cells=(2, 2, 2), L=1.0, nu=1.0)
+    sol = W.CurlModes3D(seed=5, nu=1.0)
+    f = sol.f(W.lattice_points(mesh, 2))
+    gs = GlobalSystem(mesh.vertices, mesh.elements, 1.0, 1, f, face_bc=[0, 1, 0, 0, 0, 0])
+    pc = Preconditioner(gs, mesh.lattice)
+    idx = np.arange(gs.off_f, gs.off_p)
+    Ad = pc.Ad.toarray()[np.ix_(idx, idx)]
+    E = pc.E.toarray()[idx]
+    lam = np.linalg.eigvals(np.linalg.solve(pc.Abar.toarray(), E.T @ Ad @ E)).real
+    assert lam.max() <= 1.02
+    K = gs.assemble_K()
+    b = gs.assemble_rhs()
+    x, info = minres(lambda v: K @ v, pc.apply, b, tol=1e-10, max_it=1000)
+    xd = gs.direct_solve(b)
+    assert info["converged"]
+    assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
