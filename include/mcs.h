@@ -13,7 +13,7 @@
  * lowest-order Raviart-Thomas space entering through kappa(omega), one flux
  * dof per facet beside the velocity dofs, only sigma condensed, the
  * stabilisation nu |T|^(2/3) (div omega, div eta)_T, E u = (u, Pi^0 u_t,
- * curl u); Dirichlet boundaries only), and solved
+ * curl u)), and solved
  * by MINRES preconditioned with the block factorisation eq. (mhatinvfactor)
  * whose velocity block is the multiplicative auxiliary-space preconditioner
  * of the double Schur complement (Sec. 6.1, Theorem aux_pc_schur, Corollary
