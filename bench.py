@@ -60,7 +60,7 @@ WORKLOADS = {
     "cube32_k4_fp64": ("cube32_k4_lognormal", 0, "unit cube 32^3 x 6 tets (196,608), k=4, lognormal nu (1e3 "
                        "contrast), random smooth f, FP64, tol 1e-10", 1e-10),
     "square8_k2": ("square8_k2", 0, "unit square 8x8 x 2 triangles, k=2, nu=1, FP64, tol 1e-10", 1e-10),
-    "cube64_k1": ("cube64_k1", 0, "unit cube 64^3 x 6 tets (1,572,864), lowest order k=1 (H(div) omega, Sec. 6), "
+    "cube64_k1": ("cube64_k1", 0, "unit cube 64^3 x 6 tets (1,572,864), lowest order k=1 (H(div) omega, Sec. 7), "
                                "nu=1, curl of 8 random sin^2 modes, FP64, tol 1e-10", 1e-10),
     "cube16_k3_additive": ("cube16_k3", 0, "unit cube 16^3 x 6 tets (24,576), k=3, nu=1, curl of 8 random sin^2 "
                                            "modes, FP64, tol 1e-10; additive auxiliary-space preconditioner with the "

@@ -9,7 +9,7 @@
  *     -div(nu eps(u)) + grad p = f,  div u = 0  in Omega,   u = 0 on dOmega,
  * discretised by eq. (discrmixedstressstokesweak) with the spaces of Sec. 3
  * (order k >= 2), sigma and omega statically condensed (Sec. 4.2), or, for
- * k = 1 in 3D, by the lowest-order method of Sec. 6 (omega in the
+ * k = 1 in 3D, by the lowest-order method of Sec. 7 (omega in the
  * lowest-order Raviart-Thomas space entering through kappa(omega), one flux
  * dof per facet beside the velocity dofs, only sigma condensed, the
  * stabilisation nu |T|^(2/3) (div omega, div eta)_T, E u = (u, Pi^0 u_t,
@@ -132,7 +132,7 @@ typedef struct {
 } mcs_mesh;
 
 typedef struct {
-  int32_t order;            /* k in 2..5; k = 1: dim 3 only (Sec. 6) */
+  int32_t order;            /* k in 2..5; k = 1: dim 3 only (Sec. 7) */
   int32_t precision;        /* 0: FP64 MINRES; 1: FP32 inner MINRES + FP64 refinement */
   int32_t smoothing_steps;  /* block-GS sweeps before / after the coarse correction (2) */
   int32_t max_it;           /* MINRES iteration limit (per inner solve) */
@@ -177,7 +177,7 @@ typedef struct mcs_problem mcs_problem;
 
 /* Host only.  Copies the mesh, builds topology, dof numbering, facet colouring
  * and the multigrid plan; fills *info (sizes, workspace bytes).  Reference:
- * Sec. 3 (mesh, facets, spaces); k = 1: Sec. 6 (facet blocks of n_F + n_hat
+ * Sec. 3 (mesh, facets, spaces); k = 1: Sec. 7 (facet blocks of n_F + n_hat
  * + 1 = 6 dofs: normal moments, tangential means, the flux of omega; no
  * bubbles; on an outlet facet the tangential dofs are fixed to zero and the
  * omega flux stays an unknown).  Errors: MCS_ERR_ARG (k = 1 in 2D among
@@ -214,7 +214,7 @@ int mcs_load(mcs_problem* pb, const double* f_lattice, double* b);
  * the lift x_D plus the free dofs that mcs_solve returns (mcs_load subtracts
  * K x_D; mcs_eval and mcs_eval_stress include x_D).  g_lattice_host = NULL
  * returns to homogeneous data.  For k = 1 the flux of curl g through each
- * Dirichlet facet is omega's dof there (Sec. 6).  Needs a bound problem.
+ * Dirichlet facet is omega's dof there (Sec. 7).  Needs a bound problem.
  * [sync]  Errors: MCS_ERR_ARG for non-finite data. */
 int mcs_set_dirichlet(mcs_problem* pb, const double* g_lattice_host);
 

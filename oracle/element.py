@@ -18,7 +18,7 @@ by global index, barycentric coordinates lambda_0..lambda_d:
   continuous (Sec. 3: BDM is H(div)-conforming).
 * hat V_h on facet F: lambda_F^gamma t_b, |gamma| = k-1 over the facet
   vertices, t_b = x_{f_b} - x_{f_0} (b = 1..d-1), index (b-1)*n_gamma + gamma.
-* W_h(T) = P^{k-1}(T, K) for k >= 2; for k = 1 (3D, Sec. 6) the lowest-order
+* W_h(T) = P^{k-1}(T, K) for k >= 2; for k = 1 (3D, Sec. 7) the lowest-order
   Raviart-Thomas space P^0(T, R^3) + x P^0(T), normal-continuous, entering
   through kappa(omega), with one flux dof per facet and a stabilising
   (div omega, div eta) term (weight nu |T|^(2/3));
@@ -89,11 +89,11 @@ def facet_normal_geo(P):
 
 def expected_dims(d, k):
     """Dimensions of the local spaces (closed forms).  For k = 1 (3D only,
-    Sec. 6) W_h(T) is the lowest-order Raviart-Thomas space (one normal flux
+    Sec. 7) W_h(T) is the lowest-order Raviart-Thomas space (one normal flux
     per facet, n_w = 1), coupled across facets, so its dofs join the facet
     blocks; for k >= 2 it is P^{k-1}(T, K) and n_w = 0."""
     if k == 1 and d != 3:
-        raise ValueError("the lowest order k = 1 is the three-dimensional method of Sec. 6")
+        raise ValueError("the lowest order k = 1 is the three-dimensional method of Sec. 7")
     nk = math.comb(k + d, d)
     nkm1 = math.comb(k - 1 + d, d)
     nF = math.comb(k + d - 1, d - 1)
@@ -111,13 +111,13 @@ def expected_dims(d, k):
 
 def kappa(w):
     """The skew matrix kappa(w) of a vector w in R^3 with kappa(curl u) equal
-    to the skew part (grad u - grad u^T) / 2 of grad u (Sec. 6 replaces omega
+    to the skew part (grad u - grad u^T) / 2 of grad u (Sec. 7 replaces omega
     by kappa(omega) in the bilinear forms)."""
     return 0.5 * np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
 
 
 def rt0_basis(ed):
-    """Lowest-order Raviart-Thomas basis of W_h(T) for k = 1 (Sec. 6):
+    """Lowest-order Raviart-Thomas basis of W_h(T) for k = 1 (Sec. 7):
     psi_i = s_i (x - x_i) / (d |T|), one function per local facet i, with flux
     1 through F_i w.r.t. the global facet normal n_F (s_i = n_out,i . n_F = +-1)
     and zero normal component on the other facets.  Returns the coefficients
@@ -365,11 +365,11 @@ def element_system(X, nu, k, f_lattice_sorted=None, lattice_sorted=None, m=None,
         Bfull = np.hstack([Bsig, np.zeros((Bsig.shape[0], n_om))])
         A = Adiv_ext - Bfull @ np.linalg.solve(M, Bfull.T)
     else:
-        # k = 1 (Sec. 6): omega in the Raviart-Thomas space, kappa(omega) in
+        # k = 1 (Sec. 7): omega in the Raviart-Thomas space, kappa(omega) in
         # place of omega, so only sigma is condensed; omega's facet fluxes
         # stay in the system beside (u, uhat), with the stabilisation
         # nu h_T^2 (div omega, div eta)_T with h_T = |T|^(1/3): a weight
-        # that keeps the term bounded by the lowest-order norm of Sec. 6
+        # that keeps the term bounded by the lowest-order norm of Sec. 7
         # (||div omega||_T <~ h_T^-1 ||omega||_T), so that the facet block
         # smoother and E of the preconditioner stay robust in h.  With the
         # sigma rows
@@ -433,7 +433,7 @@ def recover_stress(ed, nu, k, u_local):
     vertices): S (|I_k|, d, d) for sigma_h and W (|I_{k-1}|, d, d) for
     omega_h (k = 1: W (|I_1|, d, d), the skew field kappa(omega_h))."""
     if k == 1:
-        # Sec. 6: only sigma is local; -M_ss sigma + B^T (u, uhat, omega) = 0,
+        # Sec. 7: only sigma is local; -M_ss sigma + B^T (u, uhat, omega) = 0,
         # and omega is the Raviart-Thomas field of its facet fluxes (returned
         # as kappa(omega), degree 1)
         es = element_system(ed, nu, k, keep_blocks=True)

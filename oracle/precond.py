@@ -14,7 +14,7 @@ for the double Schur complement A^d -- oracle (FP64, sequential).
 * Additive variant (Sec. 5.2, the additive auxiliary-space preconditioner of
   Theorem aux_pc_schur): A-hat^d_a^{-1} = D^{-1} + E^d C^{-1} E^d^T with D the
   facet block Jacobi preconditioner, one block D_F per free facet.
-* l1 variant (the l1 block smoothers of the numerics of Sec. 7, in the
+* l1 variant (the l1 block smoothers of the numerics of Sec. 8, in the
   multiplicative ASP of Sec. 5.2): the facet block Gauss-Seidel sweeps are
   replaced by facet block l1-Jacobi sweeps x += M^{-1} (s - A^d x) with
   M = blockdiag(M_F), M_F = D_F + diag(l_F), l_i = sum over the free facet
@@ -32,7 +32,7 @@ for the double Schur complement A^d -- oracle (FP64, sequential).
   of one element differ), the coarse correction E C^{-1} E^T with the full
   embedding (bubble rows included), s sweeps in reverse colour order.
 * E^d: rows of the embedding E u = (u, u_t) of continuous P1 (eq. defE) for the
-  facet dofs (eq. defED).  For k = 1 (Sec. 6) E u = (u, Pi^0 u_t, curl u): the
+  facet dofs (eq. defED).  For k = 1 (Sec. 7) E u = (u, Pi^0 u_t, curl u): the
   facet mean of the tangential trace and the flux of curl u through the facet.
 * C: one symmetric V(1,1) multigrid cycle for A-bar, the P1 form
   a(u, v) = nu int eps(u) : eps(v) (eq. defAhat, read with nu, not nu^{-1}),
@@ -186,7 +186,7 @@ def p1_in_element_basis(es, v_local, c):
     assert np.allclose(M @ cu, target.ravel(), atol=1e-10 * max(1.0, np.abs(target).max()))
     ch = []
     if k == 1:
-        # Sec. 6: the tangential trace of a P1 field is not in hat V_h (P^0):
+        # Sec. 7: the tangential trace of a P1 field is not in hat V_h (P^0):
         # E takes its facet mean Pi^0 (the L2 projection onto constants)
         for i in range(nv):
             n = ed.normals_out[i]
@@ -246,7 +246,7 @@ def embedding(gs, full=False):
                         for q in range(nh):
                             rows.append(base + nF + q); cols.append(col); vals.append(ch[i][q])
                     if gs.dims["n_w"]:
-                        # k = 1 (Sec. 6): the omega component curl(u-bar); its
+                        # k = 1 (Sec. 7): the omega component curl(u-bar); its
                         # flux through F w.r.t. n_F, |F| (grad lambda_v x e_c) . n_F
                         ed = es["ed"]
                         cv = np.cross(ed.grad_lambda[vl], np.eye(d)[c])

@@ -108,7 +108,7 @@ class GlobalSystem:
         xd[n_u + i * self.nh: n_u + (i + 1) * self.nh] = np.linalg.solve(Mf, rf)
         if self.dims["n_w"]:
             # k = 1: the flux of curl g through F w.r.t. n_F (the value of
-            # omega = curl u on the boundary, Sec. 6)
+            # omega = curl u on the boundary, Sec. 7)
             from .poly import gradient_matrices
             D = gradient_matrices(nv, m, ed.grad_lambda)               # (d, |I_{m-1}|, |I_m|)
             G = np.einsum("sab,br->ars", D, gc)                        # d g_r / d x_s

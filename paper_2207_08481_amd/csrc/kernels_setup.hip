@@ -309,7 +309,7 @@ __device__ __forceinline__ void sig_col(const Sizes& s, int c, int& m, int& a) {
   }
 }
 
-// k = 1 (Sec. 6): omega in the lowest-order Raviart-Thomas space, one flux
+// k = 1 (Sec. 7): omega in the lowest-order Raviart-Thomas space, one flux
 // dof per facet f w.r.t. the facet's global normal (sorted vertices:
 // (x_b - x_a) x (x_c - x_a)): psi_f = s_f (x - x_f) / (d |T|), s_f = +-1 its
 // orientation against the outward normal, div psi_f = s_f / |T|.
@@ -490,7 +490,7 @@ __global__ void __launch_bounds__(256) k_condense(CondParams P) {
     __syncthreads();
     // tangential dofs of an outlet facet are fixed to zero: identity rows and
     // columns, so that they decouple before the bubbles are condensed (k = 1:
-    // the omega flux stays free there, W_h vanishes on Gamma_D only, Sec. 6)
+    // the omega flux stays free there, W_h vanishes on Gamma_D only, Sec. 7)
     if (P.facet_out) {
       const int nv = d + 1;
       auto pinned = [&](int r) {

@@ -1,4 +1,4 @@
-// Element kernels of the lowest-order method (k = 1, Sec. 6): no velocity
+// Element kernels of the lowest-order method (k = 1, Sec. 7): no velocity
 // bubbles, facet blocks of 6 dofs (n_d = 24) and one pressure dof per
 // element.  The general element kernels give a whole workgroup to an element
 // and synchronise it between phases; with 24 rows that leaves most lanes idle

@@ -30,7 +30,7 @@ struct Sizes {
   int ns, nsm1;       // dim P^k(T), dim P^{k-1}(T)
   int nFk, nFkm1;     // dim P^k(F), dim P^{k-1}(F)
   int nu, nb, nF, nh, nfb, nd, nA, np;  // BDM, bubbles, facet normal, facet tangential, block, A^d, A, pressure
-  int nw;             // omega flux dofs per facet: 1 for k = 1 (W_h in H(div), Sec. 6), else 0
+  int nw;             // omega flux dofs per facet: 1 for k = 1 (W_h in H(div), Sec. 7), else 0
   int nsym, nskew;    // orthonormal trace-free basis: symmetric / skew parts
   int sklo;           // first psi_a of the skew stress columns: nsm1 (omega in P^{k-1}(T, K)
                       // condensed), 0 for k = 1 (omega global)

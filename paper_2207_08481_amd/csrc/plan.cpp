@@ -124,7 +124,7 @@ int plan_problem(const mcs_mesh* mesh, const mcs_options* opt, mcs_problem* pb) 
     return k < 1 ? MCS_ERR_ARG : MCS_ERR_UNSUPPORTED;
   }
   if (k == 1 && d != 3) {
-    set_error("the lowest order k = 1 is the three-dimensional method (H(div) omega, Sec. 6)");
+    set_error("the lowest order k = 1 is the three-dimensional method (H(div) omega, Sec. 7)");
     return MCS_ERR_ARG;
   }
   if (mesh->n_vertices <= d || mesh->n_elements <= 0 || !mesh->vertices_host || !mesh->elements_host) {

@@ -572,7 +572,7 @@ RefTables build_ref_tables(int d, int k) {
     T.ct.assign((size_t)s.nFkm1 * d, 0.0);
     if (k == 1) {
       // the tangential trace of a P1 field is not in hat V_h = P^0: E takes
-      // its facet mean (Sec. 6), 1/d of each facet vertex's value
+      // its facet mean (Sec. 7), 1/d of each facet vertex's value
       for (int v = 0; v < d; ++v) T.ct[v] = 1.0 / d;
     } else {
       for (int g = 0; g < s.nFkm1; ++g)
@@ -768,7 +768,7 @@ void dirichlet_lift(const mcs_problem* pb, const double* g_lattice, std::vector<
         solve_dense(M, nt, rhs);
         for (int q = 0; q < nt; ++q) out[s.nF + q] = rhs[q];
       }
-      // k = 1 (Sec. 6): omega's dof, the flux of curl g through F w.r.t.
+      // k = 1 (Sec. 7): omega's dof, the flux of curl g through F w.r.t.
       // n_F, by Stokes the circulation of g's interpolant along dF
       // (X_0 -> X_1 -> X_2, positive about n_F); on the edge from a to b a
       // facet monomial mu^beta with no weight on the third vertex integrates

@@ -302,7 +302,7 @@ def test_solve_options_setter_validates():
 
 @needs_lib
 def test_lowest_order_plan_and_refusals():
-    """k = 1 (Sec. 6) plans in 3D with facet blocks of six dofs and no
+    """k = 1 (Sec. 7) plans in 3D with facet blocks of six dofs and no
     bubbles, also as a batch member (a group of its own) and with an outlet
     face (one more free facet layer, as for k >= 2); it is refused in 2D
     (ERR_ARG) and with the full-system variant (ERR_UNSUPPORTED)."""

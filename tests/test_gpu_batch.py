@@ -171,7 +171,7 @@ def test_batch_matches_single_problem_solve():
     assert (xs[0] - x1).norm().item() <= 1e-9 * x1.norm().item()
 
 
-# k = 1 members (Sec. 6: their own group, no bubbles, facet blocks of 6)
+# k = 1 members (Sec. 7: their own group, no bubbles, facet blocks of 6)
 # beside a k = 2 member: (dim, n, k, nu, force seed)
 K1_MEMBERS = [(3, 2, 1, 1.0, 21), (3, 3, 1, 0.6, 22), (3, 2, 2, 1.3, 23)]
 

@@ -1,4 +1,4 @@
-"""GPU parity of the lowest-order method, k = 1 in 3D (Sec. 6): the HIP path
+"""GPU parity of the lowest-order method, k = 1 in 3D (Sec. 7): the HIP path
 through the C ABI against the FP64 oracle (tests/test_oracle_lowest_order.py
 pins the oracle).
 

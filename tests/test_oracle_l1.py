@@ -1,6 +1,6 @@
 """Pins of the oracle's l1 variant: the multiplicative auxiliary-space
 preconditioner of Sec. 5.2 with facet block l1-Jacobi sweeps (the l1 block
-smoothers of the numerics of Sec. 7) in place of the block Gauss-Seidel
+smoothers of the numerics of Sec. 8) in place of the block Gauss-Seidel
 sweeps.  M = blockdiag(D_F + diag(l_F)) with the l1 row sums of the diagonally
 scaled A^d taken back to the unscaled dofs."""
 import numpy as np

@@ -1,11 +1,11 @@
-"""Pins of the oracle's lowest-order method, k = 1 in 3D (Sec. 6): W_h the
+"""Pins of the oracle's lowest-order method, k = 1 in 3D (Sec. 7): W_h the
 lowest-order Raviart-Thomas space (one flux per facet, coupled across facets),
 kappa(omega) in place of omega, the stabilisation nu h_T^2 (div omega,
 div eta)_T with h_T = |T|^(1/3), only sigma condensed, facet blocks of
 3 + 2 + 1 dofs, and E u = (u, Pi^0 u_t, curl u).
 
 The pins are the facts that fix the method independently of how the oracle
-writes it: the dimension count of Sec. 6, the rigid motions (the reason for
+writes it: the dimension count of Sec. 7, the rigid motions (the reason for
 the extra dof: a rotation must cost no energy), a linear Stokes flow
 reproduced exactly (patch test, with the pressure projected onto P^0), the
 energy identity of E (Corollary embed), divergence-free velocities, the
@@ -37,7 +37,7 @@ def problem(n, nu=1.0):
 
 
 def test_dofs_per_facet():
-    """Sec. 6: with k = 1 a facet has three coupling dofs in V_h (BDM^1), two
+    """Sec. 7: with k = 1 a facet has three coupling dofs in V_h (BDM^1), two
     in hat V_h, and the flux of omega in W_h makes six; there are no velocity
     bubbles, Sigma_h(T) has 16 dimensions and the pressure is P^0.  The
     two-dimensional method is not defined there."""
@@ -79,7 +79,7 @@ def _linear_field_dofs(X, ed, G, c, omega):
 def test_rigid_motions_cost_no_energy():
     """The six rigid motions u = a + b x x (curl u = 2b) with omega = curl u
     lie in the kernel of the element's condensed operator: this is what the
-    sixth facet dof is for (Sec. 6).  With omega = -curl u, or for a pure
+    sixth facet dof is for (Sec. 7).  With omega = -curl u, or for a pure
     strain, the energy is not zero."""
     X, ed = _element()
     A = element_system(ed, 1.3, 1)["A"]
@@ -229,7 +229,7 @@ def test_preconditioned_minres_matches_direct():
 
 def test_velocity_converges_in_h():
     """Manufactured flow, n = 2, 3, 4 (parity unpinned by the paper: it gives
-    no rates for Sec. 6; a lower bound on the observed order is asserted,
+    no rates for Sec. 7; a lower bound on the observed order is asserted,
     measured errors 0.95, 0.61, 0.40, orders 1.1 and 1.5)."""
     errs = []
     for n in (2, 3, 4):
@@ -312,7 +312,7 @@ def _outlet_flow(cells=(3, 2, 2), L=1.5, nu=0.9):
 def test_linear_flow_with_outlet_reproduced():
     """Patch test with an outlet (eq. stokes_NT): the outlet's tangential dofs
     are fixed to zero, its normal dofs and the omega flux are free (W_h
-    vanishes on Gamma_D only, Sec. 6).  The linear flow and p = 0 are
+    vanishes on Gamma_D only, Sec. 7).  The linear flow and p = 0 are
     reproduced exactly; the omega flux through the outlet is that of curl u
     (zero: curl u = (0, c2 - b, a - c1) is tangential to x = L)."""
     mesh, gs, u, _ = _outlet_flow()

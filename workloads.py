@@ -371,7 +371,7 @@ def workload(name: str, **kw):
         f = sol.f(lattice_points(mesh, k + 1))
         return dict(mesh=mesh, nu=nu, k=k, f_lattice=f, solution=sol, tol=1e-10)
     if name == "cube64_k1":
-        # the lowest-order method (k = 1, Sec. 6) on 64^3 x 6 tets
+        # the lowest-order method (k = 1, Sec. 7) on 64^3 x 6 tets
         n = kw.get("n", 64)
         mesh = unit_cube_mesh(n)
         sol = CurlModes3D(seed=2, nu=1.0)
