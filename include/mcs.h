@@ -9,7 +9,7 @@
  *     -div(nu eps(u)) + grad p = f,  div u = 0  in Omega,   u = 0 on dOmega,
  * discretised by eq. (discrmixedstressstokesweak) with the spaces of Sec. 3
  * (order k >= 2), sigma and omega statically condensed (Sec. 4.2), or, for
- * k = 1 in 3D, by the lowest-order method of Sec. 7 (omega in the
+ * k = 1 in 3D, by the method of Sec. 7, the lowest order case (omega in the
  * lowest-order Raviart-Thomas space entering through kappa(omega), one flux
  * dof per facet beside the velocity dofs, only sigma condensed, the
  * stabilisation nu |T|^(2/3) (div omega, div eta)_T, E u = (u, Pi^0 u_t,

@@ -18,9 +18,10 @@ by global index, barycentric coordinates lambda_0..lambda_d:
   continuous (Sec. 3: BDM is H(div)-conforming).
 * hat V_h on facet F: lambda_F^gamma t_b, |gamma| = k-1 over the facet
   vertices, t_b = x_{f_b} - x_{f_0} (b = 1..d-1), index (b-1)*n_gamma + gamma.
-* W_h(T) = P^{k-1}(T, K) for k >= 2; for k = 1 (3D, Sec. 7) the lowest-order
-  Raviart-Thomas space P^0(T, R^3) + x P^0(T), normal-continuous, entering
-  through kappa(omega), with one flux dof per facet and a stabilising
+* W_h(T) = P^{k-1}(T, K) for k >= 2; for k = 1 (3D, Sec. 7 "The lowest order
+  case") the lowest-order Raviart-Thomas space P^0(T, R^3) + x P^0(T),
+  normal-continuous, entering through kappa(omega), with one flux dof per
+  facet and a stabilising
   (div omega, div eta) term (weight nu |T|^(2/3));
   Q_h(T) = P^{k-1}(T) (basis lambda^gamma),
   Sigma_h(T) = {tau in P^k(T, D): tau_nt in P^{k-1}(F) for all F in dT},

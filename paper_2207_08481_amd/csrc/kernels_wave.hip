@@ -1,6 +1,6 @@
-// Element kernels of the lowest-order method (k = 1, Sec. 7): no velocity
-// bubbles, facet blocks of 6 dofs (n_d = 24) and one pressure dof per
-// element.  The general element kernels give a whole workgroup to an element
+// Element kernels of the lowest-order method (k = 1, Sec. 7 "The lowest order
+// case"): no velocity bubbles, facet blocks of 6 dofs (n_d = 24) and one
+// pressure dof per element.  The general element kernels give a whole workgroup to an element
 // and synchronise it between phases; with 24 rows that leaves most lanes idle
 // and the barriers on the critical path.  Here one wave owns one element
 // (four per workgroup) and its lanes own the element's rows: no workgroup

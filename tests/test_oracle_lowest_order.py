@@ -1,8 +1,8 @@
-"""Pins of the oracle's lowest-order method, k = 1 in 3D (Sec. 7): W_h the
-lowest-order Raviart-Thomas space (one flux per facet, coupled across facets),
-kappa(omega) in place of omega, the stabilisation nu h_T^2 (div omega,
-div eta)_T with h_T = |T|^(1/3), only sigma condensed, facet blocks of
-3 + 2 + 1 dofs, and E u = (u, Pi^0 u_t, curl u).
+"""Pins of the oracle's lowest-order method, k = 1 in 3D (Sec. 7, the lowest
+order case): W_h the lowest-order Raviart-Thomas space (one flux per facet,
+coupled across facets), kappa(omega) in place of omega, the stabilisation
+nu h_T^2 (div omega, div eta)_T with h_T = |T|^(1/3), only sigma condensed,
+facet blocks of 3 + 2 + 1 dofs, and E u = (u, Pi^0 u_t, curl u).
 
 The pins are the facts that fix the method independently of how the oracle
 writes it: the dimension count of Sec. 7, the rigid motions (the reason for
