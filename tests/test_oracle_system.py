@@ -147,6 +147,27 @@ def test_convergence_rates_2d(k):
     assert rp[-1] >= k - 0.6, (errs, rp)
 
 
+def test_convergence_rates_3d():
+    """3D manufactured flow (a sum of curl modes, p linear), k = 2 on n = 2,
+    3, 4 (parity unpinned by the paper, which prints no rates; measured
+    velocity orders 2.06, 2.25 and pressure orders 1.82, 2.38, still rising
+    towards the asymptotic ones, so the 2D bounds are asserted on the last
+    pair), and the error falls from k = 2 to k = 3 at n = 2 (0.69 -> 0.37)."""
+    errs = []
+    for n in (2, 3, 4):
+        mesh, gs, sol = problem(3, n, 2)
+        errs.append(_l2_errors(gs, gs.normalize_pressure(gs.direct_solve()), sol))
+    errs = np.asarray(errs)
+    h = 1.0 / np.array([2.0, 3.0, 4.0])
+    ru = np.log(errs[:-1, 0] / errs[1:, 0]) / np.log(h[:-1] / h[1:])
+    rp = np.log(errs[:-1, 1] / errs[1:, 1]) / np.log(h[:-1] / h[1:])
+    assert ru[-1] >= 2 - 0.2 and ru[-1] > ru[0], (errs, ru)
+    assert rp[-1] >= 2 - 0.6, (errs, rp)
+    mesh, gs3, sol = problem(3, 2, 3)
+    e3 = _l2_errors(gs3, gs3.normalize_pressure(gs3.direct_solve()), sol)[0]
+    assert e3 < 0.7 * errs[0, 0], (e3, errs[0, 0])
+
+
 def test_convergence_in_k_2d():
     """Error decreases monotonically in k for smooth data (n = 4)."""
     e = [_l2_errors(problem(2, 4, k)[1], problem(2, 4, k)[1].normalize_pressure(
