@@ -418,6 +418,26 @@ int mcs_batch_condense(mcs_batch* b, const double* const* nu_host);
  * failing member's status (each member's own status is in infos).  [sync] */
 int mcs_batch_solve(mcs_batch* b, const double* const* f_host, double* const* x_host, mcs_solve_info* infos);
 
+/* Asynchronous form of mcs_batch_solve: waits for the work queued so far on
+ * the bind stream (the inputs must be ready then), starts the solve on a
+ * library thread and returns.  f_host and x_host as for mcs_batch_solve; the
+ * pointer arrays are copied, the device memory they name must stay valid and
+ * untouched until mcs_batch_wait returns.  While a solve is in flight and
+ * until mcs_batch_wait has collected it, every other call on the batch but
+ * mcs_batch_poll and mcs_batch_destroy (which waits for the solve) returns
+ * MCS_ERR_STATE.  Errors: MCS_ERR_STATE (not bound or condensed, or a solve
+ * in flight), MCS_ERR_ARG.  [async] */
+int mcs_batch_solve_async(mcs_batch* b, const double* const* f_host, double* const* x_host);
+
+/* *done = 1 once the solve started by mcs_batch_solve_async has finished, 0
+ * while it runs.  MCS_ERR_STATE if none was started.  Host only, no wait. */
+int mcs_batch_poll(const mcs_batch* b, int32_t* done);
+
+/* Waits for the solve started by mcs_batch_solve_async and returns its status
+ * as mcs_batch_solve would (its error text in mcs_last_error); infos: host
+ * array of n entries or NULL.  MCS_ERR_STATE if none was started.  [sync] */
+int mcs_batch_wait(mcs_batch* b, mcs_solve_info* infos);
+
 /* Execution mode of mcs_batch_solve: use_graph = 1 (default) replays each run
  * of `chunk` MINRES iterations of all groups as one captured HIP graph;
  * use_graph = 0 launches the same kernels one by one.  chunk is a positive

@@ -8,11 +8,14 @@
 // every kernel, and the iterations of all groups (one HIP stream each) are
 // captured once as a graph and replayed.  Precision 1 refines every member in
 // FP64 on its own true residual, as mcs_solve does for one problem.
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <new>
+#include <string>
+#include <thread>
 #include <utility>
 
 #include "ctx.h"
@@ -120,6 +123,15 @@ struct mcs_batch {
   int use_graph = 1, chunk = 6;
   bool timer = false;               // smoother timing: launches one by one
   hipGraphExec_t gexec[2] = {nullptr, nullptr};   // inner iteration chunk, FP64 / FP32
+  // mcs_batch_solve_async: 0 no solve started, 1 running, 2 finished and not
+  // yet collected by mcs_batch_wait
+  std::atomic<int> async_state{0};
+  std::thread async_thread;
+  std::vector<const double*> async_f;
+  std::vector<double*> async_x;
+  std::vector<mcs_solve_info> async_inf;
+  int async_rc = 0;
+  std::string async_err;
   ~mcs_batch() {
     for (auto& g : gexec)
       if (g) hipGraphExecDestroy(g);
@@ -135,6 +147,16 @@ struct mcs_batch {
 };
 
 namespace {
+
+// Calls other than poll, wait and destroy are refused while an asynchronous
+// solve has not been collected.
+bool async_busy(const mcs_batch* B) {
+  if (B && B->async_state.load(std::memory_order_acquire) != 0) {
+    set_error("an asynchronous solve of this batch is in flight (mcs_batch_wait collects it)");
+    return true;
+  }
+  return false;
+}
 
 // main stream -> every group stream
 int fork(mcs_batch* B) {
@@ -423,6 +445,7 @@ int mcs_batch_member_info(const mcs_batch* B, int32_t i, mcs_info* info) {
 }
 
 int mcs_batch_set_mode(mcs_batch* B, int use_graph, int chunk) {
+  if (async_busy(B)) return MCS_ERR_STATE;
   if (!B || chunk <= 0 || chunk % 6 != 0) {
     set_error("batch mode: chunk must be a positive multiple of 6");
     return MCS_ERR_ARG;
@@ -440,6 +463,7 @@ int mcs_batch_set_mode(mcs_batch* B, int use_graph, int chunk) {
 }
 
 int mcs_batch_bind(mcs_batch* B, void* workspace, size_t bytes, void* stream) {
+  if (async_busy(B)) return MCS_ERR_STATE;
   ApiLock lock(device_api_mutex());
   if (!B) {
     set_error("null batch");
@@ -497,6 +521,7 @@ int mcs_batch_bind(mcs_batch* B, void* workspace, size_t bytes, void* stream) {
 }
 
 int mcs_batch_condense(mcs_batch* B, const double* const* nu) {
+  if (async_busy(B)) return MCS_ERR_STATE;
   if (!B || !B->ws) {
     set_error("batch is not bound");
     return B ? MCS_ERR_STATE : MCS_ERR_ARG;
@@ -526,7 +551,12 @@ int mcs_batch_condense(mcs_batch* B, const double* const* nu) {
   return MCS_OK;
 }
 
-int mcs_batch_solve(mcs_batch* B, const double* const* f, double* const* xo, mcs_solve_info* infos) {
+}  // extern "C"
+
+namespace {
+
+// The body of mcs_batch_solve (also run on the thread of mcs_batch_solve_async).
+int batch_solve(mcs_batch* B, const double* const* f, double* const* xo, mcs_solve_info* infos) {
   if (!B || !B->ws || !B->condensed) {
     set_error("batch solve needs bind and condense first");
     return B ? MCS_ERR_STATE : MCS_ERR_ARG;
@@ -795,6 +825,85 @@ int mcs_batch_solve(mcs_batch* B, const double* const* f, double* const* xo, mcs
   return rc;
 }
 
+}  // namespace
+
+extern "C" {
+
+int mcs_batch_solve(mcs_batch* B, const double* const* f, double* const* xo, mcs_solve_info* infos) {
+  if (async_busy(B)) return MCS_ERR_STATE;
+  return batch_solve(B, f, xo, infos);
+}
+
+int mcs_batch_solve_async(mcs_batch* B, const double* const* f, double* const* xo) {
+  if (async_busy(B)) return MCS_ERR_STATE;
+  if (!B || !B->ws || !B->condensed) {
+    set_error("batch solve needs bind and condense first");
+    return B ? MCS_ERR_STATE : MCS_ERR_ARG;
+  }
+  if (!f || !xo) {
+    set_error("null force or solution array");
+    return MCS_ERR_ARG;
+  }
+  for (int i = 0; i < B->n; ++i)
+    if (!f[i] || !xo[i]) {
+      set_error("member %d: null force or solution pointer", i);
+      return MCS_ERR_ARG;
+    }
+  // the inputs are read once the bind stream's work so far has finished
+  if (B->user) HIPCHK(hipStreamSynchronize(B->user));
+  B->async_f.assign(f, f + B->n);
+  B->async_x.assign(xo, xo + B->n);
+  B->async_inf.assign(B->n, mcs_solve_info{});
+  B->async_rc = MCS_OK;
+  B->async_err.clear();
+  B->async_state.store(1, std::memory_order_release);
+  try {
+    B->async_thread = std::thread([B] {
+      hipSetDevice(B->device);
+      const int rc = batch_solve(B, B->async_f.data(), B->async_x.data(), B->async_inf.data());
+      B->async_rc = rc;
+      if (rc) B->async_err = mcs_last_error();
+      B->async_state.store(2, std::memory_order_release);
+    });
+  } catch (...) {
+    B->async_state.store(0, std::memory_order_release);
+    set_error("could not start the solve thread");
+    return MCS_ERR_STATE;
+  }
+  return MCS_OK;
+}
+
+int mcs_batch_poll(const mcs_batch* B, int32_t* done) {
+  if (!B || !done) {
+    set_error("batch poll: null argument");
+    return MCS_ERR_ARG;
+  }
+  const int st = B->async_state.load(std::memory_order_acquire);
+  if (st == 0) {
+    set_error("batch poll: no asynchronous solve was started");
+    return MCS_ERR_STATE;
+  }
+  *done = st == 2 ? 1 : 0;
+  return MCS_OK;
+}
+
+int mcs_batch_wait(mcs_batch* B, mcs_solve_info* infos) {
+  if (!B) {
+    set_error("batch wait: null batch");
+    return MCS_ERR_ARG;
+  }
+  if (B->async_state.load(std::memory_order_acquire) == 0) {
+    set_error("batch wait: no asynchronous solve was started");
+    return MCS_ERR_STATE;
+  }
+  if (B->async_thread.joinable()) B->async_thread.join();
+  if (infos) std::copy(B->async_inf.begin(), B->async_inf.end(), infos);
+  const int rc = B->async_rc;
+  if (rc) set_error("%s", B->async_err.c_str());
+  B->async_state.store(0, std::memory_order_release);
+  return rc;
+}
+
 int mcs_batch_launch_config(const mcs_batch* B, int32_t g, int dt, int32_t* dim, int32_t* order,
                             int32_t* facets_per_block, int64_t* grid_cap, double* us) {
   if (!B || g < 0 || g >= (int32_t)B->groups.size()) {
@@ -808,6 +917,7 @@ int mcs_batch_launch_config(const mcs_batch* B, int32_t g, int dt, int32_t* dim,
 }
 
 int mcs_batch_timer_enable(mcs_batch* B, int enable) {
+  if (async_busy(B)) return MCS_ERR_STATE;
   if (!B || !B->ws) {
     set_error("batch is not bound");
     return B ? MCS_ERR_STATE : MCS_ERR_ARG;
@@ -821,6 +931,7 @@ int mcs_batch_timer_enable(mcs_batch* B, int enable) {
 }
 
 int mcs_batch_timer_read(mcs_batch* B, double* total_ms, int64_t* launches, double* bytes) {
+  if (async_busy(B)) return MCS_ERR_STATE;
   if (!B || !B->ws) {
     set_error("batch is not bound");
     return B ? MCS_ERR_STATE : MCS_ERR_ARG;
@@ -843,6 +954,9 @@ int mcs_batch_timer_read(mcs_batch* B, double* total_ms, int64_t* launches, doub
 }
 
 void mcs_batch_destroy(mcs_batch* B) {
+  // an asynchronous solve still running is waited for (outside the API lock,
+  // which the solve thread takes)
+  if (B && B->async_thread.joinable()) B->async_thread.join();
   ApiLock lock(device_api_mutex());
   delete B;
 }

@@ -35,7 +35,8 @@ SYMBOLS = ["mcs_plan", "mcs_bind", "mcs_condense", "mcs_load", "mcs_apply", "mcs
            "mcs_destroy",
            "mcs_status_string", "mcs_last_error",
            "mcs_batch_plan", "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense",
-           "mcs_batch_solve", "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable",
+           "mcs_batch_solve", "mcs_batch_solve_async", "mcs_batch_poll", "mcs_batch_wait",
+           "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable",
            "mcs_batch_timer_read",
            "mcs_batch_destroy", "mcs_server_create", "mcs_server_submit", "mcs_server_poll",
            "mcs_server_wait", "mcs_server_stats", "mcs_server_destroy"]
@@ -152,6 +153,9 @@ def load_library(path: str = LIB_PATH):
     lib.mcs_batch_bind.argtypes = [vp, vp, C.c_size_t, vp]
     lib.mcs_batch_condense.argtypes = [vp, vp]
     lib.mcs_batch_solve.argtypes = [vp, vp, vp, vp]
+    lib.mcs_batch_solve_async.argtypes = [vp, vp, vp]
+    lib.mcs_batch_poll.argtypes = [vp, C.POINTER(i32)]
+    lib.mcs_batch_wait.argtypes = [vp, vp]
     lib.mcs_batch_set_mode.argtypes = [vp, i32, i32]
     lib.mcs_batch_timer_enable.argtypes = [vp, i32]
     lib.mcs_batch_timer_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
@@ -169,7 +173,7 @@ def load_library(path: str = LIB_PATH):
                  "mcs_get_array",
                  "mcs_get_topology", "mcs_get_full_colouring", "mcs_timer_enable", "mcs_timer_read", "mcs_get_launch_config", "mcs_set_launch_config", "mcs_get_apply_config", "mcs_set_apply_config", "mcs_set_solve_options", "mcs_batch_plan",
                  "mcs_batch_member_info", "mcs_batch_bind", "mcs_batch_condense", "mcs_batch_solve",
-                 "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable", "mcs_batch_timer_read",
+                 "mcs_batch_solve_async", "mcs_batch_poll", "mcs_batch_wait", "mcs_batch_set_mode", "mcs_batch_launch_config", "mcs_batch_timer_enable", "mcs_batch_timer_read",
                  "mcs_server_create",
                  "mcs_server_submit", "mcs_server_poll", "mcs_server_wait", "mcs_server_stats"):
         getattr(lib, name).restype = i32
@@ -534,6 +538,31 @@ class Batch:
         xs = [torch.zeros(m.n_dof, dtype=torch.float64, device=self.device) for m in self.members]
         infos = (SolveInfo * self.n)()
         rc = self._lib.mcs_batch_solve(self._h, _ptr_array(fs), _ptr_array(xs), infos)
+        out = [infos[i].as_dict() for i in range(self.n)]
+        if rc != OK and rc != -5:
+            _check(rc)
+        return xs, out
+
+    def solve_async(self, forces):
+        """Starts the solve on a library thread (mcs_batch_solve_async) and
+        returns at once; poll() tells whether it finished, wait() returns what
+        solve() would."""
+        import torch
+        fs = [torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous() for f in forces]
+        xs = [torch.zeros(m.n_dof, dtype=torch.float64, device=self.device) for m in self.members]
+        _check(self._lib.mcs_batch_solve_async(self._h, _ptr_array(fs), _ptr_array(xs)))
+        self._async = (fs, xs)   # the device memory stays alive until wait()
+
+    def poll(self):
+        d = C.c_int32()
+        _check(self._lib.mcs_batch_poll(self._h, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self):
+        infos = (SolveInfo * self.n)()
+        rc = self._lib.mcs_batch_wait(self._h, infos)
+        fs, xs = getattr(self, "_async", (None, None))
+        self._async = None
         out = [infos[i].as_dict() for i in range(self.n)]
         if rc != OK and rc != -5:
             _check(rc)

@@ -320,3 +320,24 @@ def test_lowest_order_plan_and_refusals():
         Problem(m3.vertices, m3.elements, m3.lattice, 1, smoother=2)
     b = Batch([(m3.vertices, m3.elements, m3.lattice)] * 2, [2, 1])
     assert b.info.n_groups == 2
+
+
+@needs_lib
+def test_batch_async_calls_need_a_started_solve():
+    """mcs_batch_solve_async refuses a batch that is not bound and condensed,
+    and mcs_batch_poll / mcs_batch_wait refuse when no asynchronous solve was
+    started (MCS_ERR_STATE, host only)."""
+    import ctypes as C
+    from paper_2207_08481_amd import Batch
+    from paper_2207_08481_amd.mcs import STATUS
+    m3 = W.unit_cube_mesh(1)
+    b = Batch([(m3.vertices, m3.elements, m3.lattice)] * 2, [2, 2])
+    lib = b._lib
+    state = [k for k, v in STATUS.items() if v == "ERR_STATE"][0]
+    ptrs = (C.c_void_p * 2)(1, 1)
+    assert lib.mcs_batch_solve_async(b._h, ptrs, ptrs) == state
+    d = C.c_int32(7)
+    assert lib.mcs_batch_poll(b._h, C.byref(d)) == state and d.value == 7
+    assert lib.mcs_batch_wait(b._h, None) == state
+    assert "no asynchronous solve" in lib.mcs_last_error().decode()
+    b.close()

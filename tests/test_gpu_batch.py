@@ -140,6 +140,37 @@ def test_batch_graph_equals_eager(precision):
         _ = torch.ones(1000, device="cuda:0").sum().item()   # eager work between replays
 
 
+def test_batch_solve_async_equals_solve():
+    """mcs_batch_solve_async runs the solve on a library thread; polled, then
+    collected by mcs_batch_wait, it gives bitwise the solution and iteration
+    counts of mcs_batch_solve, twice in a row.  Until wait collects it, the
+    other batch calls return MCS_ERR_STATE."""
+    import time
+    from paper_2207_08481_amd.mcs import MCSError
+    b, cs = make_batch(range(len(MEMBERS)), precision=1, tol=1e-9)
+    fs = [torch.as_tensor(c["f"], device="cuda:0") for c in cs]
+    xs, infos = b.solve(fs)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        b.solve_async(fs)
+        with pytest.raises(MCSError, match="ERR_STATE"):
+            b.solve(fs)
+        with pytest.raises(MCSError, match="ERR_STATE"):
+            b.solve_async(fs)
+        t0 = time.time()
+        while not b.poll():
+            assert time.time() - t0 < 120, "asynchronous batch solve did not finish"
+            time.sleep(0.01)
+        xa, ia = b.wait()
+        torch.cuda.synchronize()
+        for a, g, i0, i1 in zip(xs, xa, infos, ia):
+            assert i0["iterations"] == i1["iterations"] and i1["status"] == 0
+            assert torch.equal(a, g), rep
+    with pytest.raises(MCSError, match="ERR_STATE"):
+        b.poll()
+    b.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_member_result_independent_of_batch(precision):
     """A member's solution and iteration count are bitwise the same alone, in
