@@ -68,6 +68,10 @@ WORKLOADS = {
     "channel_k3": ("channel_k3", 0, "plane channel 4 x 1 x 1 (40 x 10 x 10 cells x 6 tets = 24,000), k=3, nu=1e-3, "
                                     "parabolic profile as Dirichlet data on the inlet and z = 0, 1, no-slip plates, "
                                     "outlet Gamma_NT at x = 4, FP64, tol 1e-10", 1e-10),
+    "channel_k1": ("channel_k1", 0, "plane channel 4 x 1 x 1 (160 x 40 x 40 cells x 6 tets = 1,536,000), lowest order "
+                                    "k=1 (H(div) omega, Sec. 7), nu=1e-3, parabolic profile as Dirichlet data on the "
+                                    "inlet and z = 0, 1, no-slip plates, outlet Gamma_NT at x = 4, FP64, tol 1e-10",
+                   1e-10),
     "cube16_k3_l1": ("cube16_k3", 0, "unit cube 16^3 x 6 tets (24,576), k=3, nu=1, curl of 8 random sin^2 modes, "
                                      "FP64, tol 1e-10; multiplicative auxiliary-space preconditioner with facet block "
                                      "l1-Jacobi sweeps (no colour phases)", 1e-10),
