@@ -276,3 +276,31 @@ def test_lowest_order_with_outlet(forced):
     xq, sq = pb.solve(ft, allow_max_it=True)
     assert sq["iterations"] == neq
     check_equal_iterations(gs, xq.cpu().numpy(), xe, neq, twin)
+
+
+@pytest.mark.parametrize("smoother,variant,precision", [(1, "additive", 0), (3, "l1", 0), (0, "multiplicative", 1)])
+def test_lowest_order_outlet_variants(smoother, variant, precision):
+    """k = 1 with an outlet under the additive and the l1 variants (K-hat^{-1}
+    against the oracle's variant to 1e-11, the FP64 solve to 1e-8 of the
+    direct solve) and in mixed precision (1e-8 of the direct solve)."""
+    from oracle.precond import Preconditioner
+    from oracle.system import GlobalSystem
+    from paper_2207_08481_amd import Problem
+    from tests.test_oracle_lowest_order import _outlet_flow
+    mesh, _, _, fbc = _outlet_flow()
+    nu = 0.9
+    f = W.CurlModes3D(seed=5, nu=nu).f(W.lattice_points(mesh, 2))
+    gs = GlobalSystem(mesh.vertices, mesh.elements, nu, 1, f, face_bc=fbc)
+    print(f"[k1 outlet variant] {variant} precision={precision}", flush=True)
+    pb = Problem(mesh.vertices, mesh.elements, mesh.lattice, 1, face_bc=fbc, smoother=smoother, precision=precision,
+                 tol=1e-10, max_it=3000).bind("cuda:0")
+    pb.condense(torch.full((mesh.n_elements,), nu, dtype=torch.float64, device="cuda:0"))
+    if precision == 0:
+        pc = Preconditioner(gs, mesh.lattice, variant=variant)
+        x = np.random.default_rng(6).standard_normal(gs.n_dof)
+        z = pb.precond_apply("KHAT", torch.as_tensor(x, device="cuda:0")).cpu().numpy()
+        assert _rel(z, pc.apply(x.copy())) < 1e-11
+    xs, si = pb.solve(torch.as_tensor(f, device="cuda:0"))
+    assert si["status"] == 0, si
+    eu, ep = _l2_rel(gs, xs.cpu().numpy(), gs.direct_solve())
+    assert eu < 1e-8 and ep < 1e-8, (eu, ep, si)
