@@ -184,3 +184,46 @@ def test_cube32_k4_mixed_precision_solve_matches_fp64():
     ep = ((w[None, :] * (pm - pd) ** 2).sum() / (w[None, :] * pd ** 2).sum()).sqrt().item()
     print(f"  mixed against FP64: u {eu:.2e} p {ep:.2e}", flush=True)
     assert eu < 1e-8 and ep < 1e-8, (eu, ep)
+
+
+def test_batch256_mixed_sampled_members():
+    """The 256-member batch of the benchmark (4^3..16^3 cubes x 6 tets drawn
+    log-uniform, k uniform in {2, 3, 4}, lognormal nu per member, random
+    forces; FP32 inner MINRES with per-member FP64 refinement to tol 1e-8), run
+    as the benchmark runs it (one batch, graph replays, tuned launch shapes):
+    every member converges; two sampled k = 2 members (4^3 cubes) are within
+    1e-8 relative L2 of the oracle's direct solve (velocity and pressure); a
+    sampled k = 3 and k = 4 member give bitwise the same solution and iteration
+    count when solved as a batch of their own."""
+    _need_gpu()
+    from oracle.system import GlobalSystem
+    from paper_2207_08481_amd import Batch
+    from tests.test_gpu_batch import _l2_rel
+    specs = W.batch_members(256, seed=5)
+    members = [W.batch_member(sp) for sp in specs]
+    dev = "cuda:0"
+
+    def run(idx):
+        b = Batch([(members[i]["mesh"].vertices, members[i]["mesh"].elements, members[i]["mesh"].lattice)
+                   for i in idx], [members[i]["k"] for i in idx], precision=1, tol=1e-8, max_it=5000).bind(dev)
+        b.condense([torch.as_tensor(members[i]["nu"], device=dev) for i in idx])
+        xs, infos = b.solve([torch.as_tensor(members[i]["f_lattice"], device=dev) for i in idx])
+        xs = [x.cpu() for x in xs]
+        b.close()
+        return xs, infos
+
+    print("[batch256] solving the whole batch", flush=True)
+    xs, infos = run(range(256))
+    assert all(inf["status"] == 0 for inf in infos), [i for i, inf in enumerate(infos) if inf["status"]]
+    k2 = [i for i, sp in enumerate(specs) if sp["n"] == 4 and sp["k"] == 2][:2]
+    for i in k2:
+        m = members[i]
+        gs = GlobalSystem(m["mesh"].vertices, m["mesh"].elements, m["nu"], m["k"], m["f_lattice"])
+        eu, ep = _l2_rel(gs, xs[i].numpy(), gs.direct_solve())
+        print(f"  member {i} (n=4, k=2): u {eu:.2e} p {ep:.2e}", flush=True)
+        assert eu < 1e-8 and ep < 1e-8, (i, eu, ep)
+    for k in (3, 4):
+        i = next(j for j, sp in enumerate(specs) if sp["k"] == k)
+        xa, ia = run([i])
+        assert ia[0]["iterations"] == infos[i]["iterations"], (i, ia[0], infos[i])
+        assert torch.equal(xa[0], xs[i]), i
