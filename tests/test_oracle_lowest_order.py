@@ -228,9 +228,10 @@ def test_preconditioned_minres_matches_direct():
 
 
 def test_velocity_converges_in_h():
-    """Manufactured flow, n = 2, 3, 4 (parity unpinned by the paper: it gives
-    no rates for Sec. 7; a lower bound on the observed order is asserted,
-    measured errors 0.95, 0.61, 0.40, orders 1.1 and 1.5)."""
+    """Manufactured flow, n = 2, 3, 4: the error falls at an order near the
+    lowest-order method's first order in h (the paper prints no rates for
+    Sec. 7, so a lower bound on the observed order is asserted; measured
+    errors 0.95, 0.61, 0.40, orders 1.1 and 1.5)."""
     errs = []
     for n in (2, 3, 4):
         mesh, gs, sol = problem(n)

@@ -133,8 +133,9 @@ def _l2_errors(gs, x, sol):
 
 @pytest.mark.parametrize("k", [2, 3])
 def test_convergence_rates_2d(k):
-    """Manufactured-solution convergence in h (parity unpinned by the paper:
-    expected orders from the MCS literature; conservative bounds asserted)."""
+    """Manufactured-solution convergence in h: the orders of the method for
+    smooth data (the paper prints no rates; conservative lower bounds below
+    the expected orders are asserted)."""
     errs = []
     for n in (2, 4, 8):
         mesh, gs, sol = problem(2, n, k)
@@ -149,7 +150,7 @@ def test_convergence_rates_2d(k):
 
 def test_convergence_rates_3d():
     """3D manufactured flow (a sum of curl modes, p linear), k = 2 on n = 2,
-    3, 4 (parity unpinned by the paper, which prints no rates; measured
+    3, 4 (the paper prints no rates; measured
     velocity orders 2.06, 2.25 and pressure orders 1.82, 2.38, still rising
     towards the asymptotic ones, so the 2D bounds are asserted on the last
     pair), and the error falls from k = 2 to k = 3 at n = 2 (0.69 -> 0.37)."""
