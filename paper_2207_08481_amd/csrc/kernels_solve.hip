@@ -57,9 +57,12 @@ __device__ inline R group_sum(R v) {
 // [t0, t0 + nthr) form groups of L lanes, one group per row (lanes over the
 // contiguous columns); epi(i, sum) runs on the group's first lane.  The row
 // loop is uniform over the participating waves (t0, nthr multiples of 64).
+// A lane's entries are loaded U at a time, all in flight together, then
+// summed in column order (so the sums do not depend on U).
 template <int L, typename MA, typename R, typename F>
 __device__ inline void rows_times(MA M, size_t m0, int nrow, int ncol, const R* v, int t0, int nthr, F epi,
                                   R* keep = nullptr, int ldk = 0) {
+  constexpr int U = 8;
   const int t = threadIdx.x - t0;
   const int g = t / L, l = t % L, ng = nthr / L;
   for (int i0 = 0; i0 < nrow; i0 += ng) {
@@ -67,20 +70,43 @@ __device__ inline void rows_times(MA M, size_t m0, int nrow, int ncol, const R* 
     R acc = R(0);
     if (i < nrow) {
       const size_t mi = m0 + (size_t)i * ncol;
-      if (keep) {
-        // the matrix entries are also kept in LDS (row stride ldk) for a later product
-        for (int j = l; j < ncol; j += L) {
-          const R m = M(mi + j);
-          keep[i * ldk + j] = m;
-          acc += m * v[j];
+      for (int jb = l; jb < ncol; jb += U * L) {
+        R m[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int j = jb + u * L;
+          m[u] = j < ncol ? M(mi + j) : R(0);
         }
-      } else {
-        for (int j = l; j < ncol; j += L) acc += M(mi + j) * v[j];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int j = jb + u * L;
+          if (j < ncol) {
+            // the matrix entries are also kept in LDS (row stride ldk) for a later product
+            if (keep) keep[i * ldk + j] = m[u];
+            acc += m[u] * v[j];
+          }
+        }
       }
     }
     acc = group_sum<L>(acc);
     if (l == 0 && i < nrow) epi(i, acc);
   }
+}
+
+// sum_q Bp^[q][iu] x_p[q] over q < n_p, in order of q; the table entries are
+// loaded 8 at a time, all in flight together.
+template <typename R>
+__device__ inline double bp_column(const double* __restrict__ T, int nu, int iu, const R* xp, int np) {
+  double b = 0.0;
+  for (int q0 = 0; q0 < np; q0 += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = q0 + u < np ? T[(size_t)(q0 + u) * nu + iu] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q0 + u < np) b += t[u] * (double)xp[q0 + u];
+  }
+  return b;
 }
 
 // Per-workgroup table of the velocity rows of an element (reordered local
@@ -201,8 +227,7 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
       if (doBT) {
         const int iu = rmap[nb + tid];
         if (iu >= 0) {
-          double b = 0.0;
-          for (int q = 0; q < np; ++q) b += P.rBp[(size_t)q * nu + iu] * (double)xp[q];
+          const double b = bp_column(P.rBp, nu, iu, xp, np);
           acc += (R)(sf * b);
         }
       }
@@ -211,8 +236,7 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
     if (!onlyAd && tid < nb) {
       R a = doH ? wo[tid] : R(0);
       if (doBT) {
-        double b = 0.0;
-        for (int q = 0; q < np; ++q) b += P.rBp[(size_t)q * nu + tid] * (double)xp[q];
+        const double b = bp_column(P.rBp, nu, tid, xp, np);
         a += (R)(sb * b);
       }
       y[e * nb + tid] = a;
