@@ -169,16 +169,25 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
     if constexpr (CP > 1) {
       if (tid < nd / CP) {
         if (doA) {
+          // batches of U columns: a batch's loads are issued together, then
+          // summed in order (columns past n_d load the last one and add it
+          // times 0; the sums run over j in order, as for one row per thread)
           typedef R rcv __attribute__((ext_vector_type(CP)));
+          constexpr int U = 12;
           const R* a0 = MAd.p + (size_t)e * nd * nd + CP * tid;
           R ac[CP];
 #pragma unroll
           for (int c = 0; c < CP; ++c) ac[c] = R(0);
-#pragma unroll 8
-          for (int j = 0; j < nd; ++j) {
-            const rcv v = *reinterpret_cast<const rcv*>(a0 + (size_t)j * nd);
+          for (int jb = 0; jb < nd; jb += U) {
+            rcv b[U];
 #pragma unroll
-            for (int c = 0; c < CP; ++c) ac[c] += v[c] * xd[j];
+            for (int u = 0; u < U; ++u) b[u] = *reinterpret_cast<const rcv*>(a0 + (size_t)min(jb + u, nd - 1) * nd);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const R xj = xd[min(jb + u, nd - 1)] * R(jb + u < nd ? 1 : 0);
+#pragma unroll
+              for (int c = 0; c < CP; ++c) ac[c] += b[u][c] * xj;
+            }
           }
 #pragma unroll
           for (int c = 0; c < CP; ++c) adx[CP * tid + c] = ac[c];
