@@ -57,39 +57,48 @@ __device__ inline R group_sum(R v) {
 // [t0, t0 + nthr) form groups of L lanes, one group per row (lanes over the
 // contiguous columns); epi(i, sum) runs on the group's first lane.  The row
 // loop is uniform over the participating waves (t0, nthr multiples of 64).
-// A lane's entries are loaded U at a time, all in flight together, then
-// summed in column order (so the sums do not depend on U).
+// A group takes two rows per pass; a lane's entries of both are loaded U at
+// a time, all in flight together, then each row is summed in column order
+// (so the sums depend neither on U nor on the pairing of rows).
 template <int L, typename MA, typename R, typename F>
 __device__ inline void rows_times(MA M, size_t m0, int nrow, int ncol, const R* v, int t0, int nthr, F epi,
                                   R* keep = nullptr, int ldk = 0) {
-  constexpr int U = 8;
+  constexpr int U = sizeof(R) == 8 ? 4 : 8;   // 16 words of two rows in flight per lane
   const int t = threadIdx.x - t0;
   const int g = t / L, l = t % L, ng = nthr / L;
-  for (int i0 = 0; i0 < nrow; i0 += ng) {
-    const int i = i0 + g;
-    R acc = R(0);
-    if (i < nrow) {
-      const size_t mi = m0 + (size_t)i * ncol;
-      for (int jb = l; jb < ncol; jb += U * L) {
-        R m[U];
+  for (int i0 = 0; i0 < nrow; i0 += 2 * ng) {
+    const int ia = i0 + g, ib = i0 + ng + g;
+    const bool va = ia < nrow, vb = ib < nrow;
+    const size_t ma0 = m0 + (size_t)(va ? ia : 0) * ncol, mb0 = m0 + (size_t)(vb ? ib : 0) * ncol;
+    R acca = R(0), accb = R(0);
+    for (int jb = l; jb < ncol; jb += U * L) {
+      R ma[U], mb[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int j = jb + u * L;
-          m[u] = j < ncol ? M(mi + j) : R(0);
-        }
+      for (int u = 0; u < U; ++u) {
+        const int j = jb + u * L;
+        ma[u] = va && j < ncol ? M(ma0 + j) : R(0);
+        mb[u] = vb && j < ncol ? M(mb0 + j) : R(0);
+      }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int j = jb + u * L;
-          if (j < ncol) {
-            // the matrix entries are also kept in LDS (row stride ldk) for a later product
-            if (keep) keep[i * ldk + j] = m[u];
-            acc += m[u] * v[j];
+      for (int u = 0; u < U; ++u) {
+        const int j = jb + u * L;
+        if (j < ncol) {
+          // the matrix entries are also kept in LDS (row stride ldk) for a later product
+          if (va) {
+            if (keep) keep[ia * ldk + j] = ma[u];
+            acca += ma[u] * v[j];
+          }
+          if (vb) {
+            if (keep) keep[ib * ldk + j] = mb[u];
+            accb += mb[u] * v[j];
           }
         }
       }
     }
-    acc = group_sum<L>(acc);
-    if (l == 0 && i < nrow) epi(i, acc);
+    acca = group_sum<L>(acca);
+    accb = group_sum<L>(accb);
+    if (l == 0 && va) epi(ia, acca);
+    if (l == 0 && vb) epi(ib, accb);
   }
 }
 
@@ -251,11 +260,31 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
       y[e * nb + tid] = a;
     }
     if (doBu) {
-      for (int q = wave; q < np; q += 4) {
-        double a = 0.0;
-        for (int iu = lane; iu < nu; iu += 64) a += P.rBp[(size_t)q * nu + iu] * us[iu];
-        a = wave_sum(a);
-        if (lane == 0) y[P.off_p + e * np + q] = (R)a;
+      // the wave's rows q = wave + 4 r: the table entries of QB rows (three
+      // per lane and row: n_u <= 192) are loaded together, then each row is
+      // summed over iu in order
+      constexpr int QB = 2;
+      for (int q0 = wave; q0 < np; q0 += 4 * QB) {
+        double t[QB][3];
+#pragma unroll
+        for (int r = 0; r < QB; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const int q = q0 + 4 * r, iu = lane + 64 * c;
+            t[r][c] = q < np && iu < nu ? P.rBp[(size_t)q * nu + iu] : 0.0;
+          }
+#pragma unroll
+        for (int r = 0; r < QB; ++r) {
+          const int q = q0 + 4 * r;   // uniform over the wave
+          if (q < np) {
+            double a = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              if (lane + 64 * c < nu) a += t[r][c] * us[lane + 64 * c];
+            a = wave_sum(a);
+            if (lane == 0) y[P.off_p + e * np + q] = (R)a;
+          }
+        }
       }
     } else if (!onlyAd && tid < np && (flags & 16)) {
       y[P.off_p + e * np + tid] = R(0);
