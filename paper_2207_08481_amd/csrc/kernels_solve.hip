@@ -102,20 +102,56 @@ __device__ inline void rows_times(MA M, size_t m0, int nrow, int ncol, const R* 
   }
 }
 
-// sum_q Bp^[q][iu] x_p[q] over q < n_p, in order of q; the table entries are
-// loaded 8 at a time, all in flight together.
-template <typename R>
-__device__ inline double bp_column(const double* __restrict__ T, int nu, int iu, const R* xp, int np) {
+// sum_q T[q st] v[q] over q < n, in order of q; the table entries are loaded
+// 8 at a time, all in flight together.
+template <typename V>
+__device__ inline double dot_strided8(const double* __restrict__ T, size_t st, const V* v, int n) {
   double b = 0.0;
-  for (int q0 = 0; q0 < np; q0 += 8) {
+  for (int q0 = 0; q0 < n; q0 += 8) {
     double t[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = q0 + u < np ? T[(size_t)(q0 + u) * nu + iu] : 0.0;
+    for (int u = 0; u < 8; ++u) t[u] = q0 + u < n ? T[(size_t)(q0 + u) * st] : 0.0;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (q0 + u < np) b += t[u] * (double)xp[q0 + u];
+      if (q0 + u < n) b += t[u] * (double)v[q0 + u];
   }
   return b;
+}
+// sum_q Bp^[q][iu] x_p[q] over q < n_p
+template <typename R>
+__device__ inline double bp_column(const double* __restrict__ T, int nu, int iu, const R* xp, int np) {
+  return dot_strided8(T + iu, (size_t)nu, xp, np);
+}
+// The rows q = wave + 4 r (r >= 0, q < n_p) of sum_iu Bp^[q][iu] us[iu] for
+// the calling wave, in order of iu for each row; the table entries of two
+// rows (three per lane and row: n_u <= 192) are loaded together.  out(q, sum)
+// runs on lane 0.
+template <typename F>
+__device__ inline void bu_rows(const double* __restrict__ T, int nu, int np, const double* us, int wave, int lane,
+                               F out) {
+  constexpr int QB = 2;
+  for (int q0 = wave; q0 < np; q0 += 4 * QB) {
+    double t[QB][3];
+#pragma unroll
+    for (int r = 0; r < QB; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int q = q0 + 4 * r, iu = lane + 64 * c;
+        t[r][c] = q < np && iu < nu ? T[(size_t)q * nu + iu] : 0.0;
+      }
+#pragma unroll
+    for (int r = 0; r < QB; ++r) {
+      const int q = q0 + 4 * r;   // uniform over the wave
+      if (q < np) {
+        double a = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          if (lane + 64 * c < nu) a += t[r][c] * us[lane + 64 * c];
+        a = wave_sum(a);
+        if (lane == 0) out(q, a);
+      }
+    }
+  }
 }
 
 // Per-workgroup table of the velocity rows of an element (reordered local
@@ -260,32 +296,7 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
       y[e * nb + tid] = a;
     }
     if (doBu) {
-      // the wave's rows q = wave + 4 r: the table entries of QB rows (three
-      // per lane and row: n_u <= 192) are loaded together, then each row is
-      // summed over iu in order
-      constexpr int QB = 2;
-      for (int q0 = wave; q0 < np; q0 += 4 * QB) {
-        double t[QB][3];
-#pragma unroll
-        for (int r = 0; r < QB; ++r)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const int q = q0 + 4 * r, iu = lane + 64 * c;
-            t[r][c] = q < np && iu < nu ? P.rBp[(size_t)q * nu + iu] : 0.0;
-          }
-#pragma unroll
-        for (int r = 0; r < QB; ++r) {
-          const int q = q0 + 4 * r;   // uniform over the wave
-          if (q < np) {
-            double a = 0.0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-              if (lane + 64 * c < nu) a += t[r][c] * us[lane + 64 * c];
-            a = wave_sum(a);
-            if (lane == 0) y[P.off_p + e * np + q] = (R)a;
-          }
-        }
-      }
+      bu_rows(P.rBp, nu, np, us, wave, lane, [&](int q, double a) { y[P.off_p + e * np + q] = (R)a; });
     } else if (!onlyAd && tid < np && (flags & 16)) {
       y[P.off_p + e * np + tid] = R(0);
     }
@@ -353,21 +364,23 @@ __global__ void __launch_bounds__(256) k_ext_pre(SolveParams P, OpPtrs<R> O, con
     } else {
       if (tid < nb) ro[tid] = r[e * nb + tid];
       __syncthreads();
-      if (hcol) {
-        const R* H = O.H + (size_t)e * nb * nd + tid;
+      // column tid of H_T and row tid - ob of Aoo^{-1} (a thread may own
+      // both when n_d + n_o > 256): 16 entries loaded at a time (in flight
+      // together), then summed in order
+      auto colsum = [&](const R* m, size_t st) {
         R acc = R(0);
-#pragma unroll 8
-        for (int i = 0; i < nb; ++i) acc += H[(size_t)i * nd] * ro[i];
-        escr[e * nd + tid] = acc;
-      }
-      if (arow) {
-        const int i = tid - ob;
-        const R* Ai = O.Aooinv + (size_t)e * nb * nb + i;
-        R acc = R(0);
-#pragma unroll 8
-        for (int j = 0; j < nb; ++j) acc += Ai[(size_t)j * nb] * ro[j];
-        to[e * nb + i] = acc;
-      }
+        for (int q0 = 0; q0 < nb; q0 += 16) {
+          R a[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) a[u] = m[(size_t)min(q0 + u, nb - 1) * st];
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            if (q0 + u < nb) acc += a[u] * ro[q0 + u];
+        }
+        return acc;
+      };
+      if (hcol) escr[e * nd + tid] = colsum(O.H + (size_t)e * nb * nd + tid, (size_t)nd);
+      if (arow) to[e * nb + tid - ob] = colsum(O.Aooinv + (size_t)e * nb * nb + (tid - ob), (size_t)nb);
     }
     __syncthreads();
   }
@@ -1041,19 +1054,15 @@ __global__ void __launch_bounds__(256) k_elem_press(SolveParams P, const R* __re
       }
     }
     __syncthreads();
-    for (int q = wave; q < np; q += 4) {
-      double acc = 0.0;
-      if (with_B) {
-        for (int iu = lane; iu < nu; iu += 64) acc += P.rBp[(size_t)q * nu + iu] * us[iu];
-        acc = wave_sum(acc);
-      }
-      if (lane == 0) bp[q] = rp[q] - acc;
+    if (with_B) {
+      bu_rows(P.rBp, nu, np, us, wave, lane, [&](int q, double a) { bp[q] = rp[q] - a; });
+    } else {
+      for (int q = tid; q < np; q += blockDim.x) bp[q] = rp[q];
     }
     __syncthreads();
     if (tid < np) {
       double sc = nue / fabs(det);
-      double acc = 0.0;
-      for (int j = 0; j < np; ++j) acc += P.rMpinv[tid * np + j] * bp[j];
+      const double acc = dot_strided8(P.rMpinv + (size_t)tid * np, 1, bp, np);
       y[P.off_p + e * np + tid] = (R)(sc * acc);
     }
     __syncthreads();
