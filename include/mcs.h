@@ -344,9 +344,11 @@ int mcs_set_launch_config(mcs_problem* pb, int dt, int32_t facets_per_block, int
  * (mcs_options.autotune) times the valid choices at the first mcs_condense,
  * except for k = 1 (one wave per element) and the split FP64 storage of
  * precision 1 (one row per thread).  The tuner tries the choices whose
- * products H x_d use the lane width of the default, which give bitwise the
- * same results; a choice set by hand may change that width (3D k >= 4 in
- * FP64) and with it the rounding of those sums. */
+ * products H x_d use the lane width of the default and whose A^d sums run in
+ * the same order (four rows per thread, FP32, split the columns of A^d over
+ * two waves), which give bitwise the same results (a single such choice is
+ * timed for the record); a choice set by hand may change the rounding of
+ * those sums. */
 int mcs_get_apply_config(const mcs_problem* pb, int dt, int32_t* rows_per_thread, double* us);
 
 /* Sets that choice (0, 1, 2, or 4 for MCS_F32; a choice the sizes do not

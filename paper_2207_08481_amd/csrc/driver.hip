@@ -132,8 +132,10 @@ int tune_apply_precision(mcs_problem* pb, int slot) {
   const int cp0 = (sizeof(R) == 4 && nd % 4 == 0) ? 4 : nd % 2 == 0 ? 2 : 1;   // the default
   std::vector<int> cand;
   for (int cp : {1, 2, 4})
-    if (cp <= cp0 && nd % cp == 0 && apply_h_lanes(nd, cp) == apply_h_lanes(nd, cp0)) cand.push_back(cp);
-  if (cand.size() < 2) return MCS_OK;   // nothing to choose
+    if (cp <= cp0 && nd % cp == 0 && apply_h_lanes(nd, cp) == apply_h_lanes(nd, cp0) &&
+        apply_col_split(nd, cp) == apply_col_split(nd, cp0))
+      cand.push_back(cp);
+  if (cand.empty()) return MCS_OK;   // (a single choice is still timed, for the record)
   if (pb->sz.nb == 0 && pb->sz.np == 1) return MCS_OK;   // k = 1: one wave per element, no rows to choose
   if (sizeof(R) == 8 && pb->lean) return MCS_OK;         // split storage: one row per thread
   struct Events {

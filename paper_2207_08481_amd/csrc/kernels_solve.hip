@@ -177,6 +177,9 @@ __device__ inline void build_rowmap(const Sizes& s, int* rmap) {
 // remaining waves form z_o = x_o + H x_d (16-lane groups per row of H);
 // phase 2: w_o = A_oo z_o; phase 3: H^T w_o (one column per thread) and the
 // pressure coupling.  Every row is summed in the same order for CP = 1 and 2.
+// CP = 4 (FP32; n_d / 4 <= 64 rows of quads) splits the columns of A^d over
+// two waves (j < ceil(n_d / 2) and the rest), their sums added in phase 3:
+// two shorter load chains in place of one.
 // B_T[q][row] = -s |det J| Bp^[q][iu(row)] (s = 1 bubble, 1/det J facet row).
 template <typename R, typename MA, int FL, int CP>
 __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH, MA MAoo, const R* __restrict__ x,
@@ -192,12 +195,15 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
   __shared__ R xp[MAXNP];
   __shared__ int rmap[MAXNB + MAXND];
   __shared__ double us[MAXNB + MAXND];   // Piola-scaled velocity for B u, by BDM index
-  __shared__ R adx[CP > 1 ? MAXND : 1];   // A^d x_d (CP > 1)
+  constexpr int KS = CP == 4 ? 2 : 1;     // column slices of the A^d product
+  __shared__ R adx[CP > 1 ? KS * MAXND : 1];   // A^d x_d (CP > 1), per slice
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool doA = flags & 1, doBT = flags & 2, doBu = flags & 4, onlyAd = flags & 8;
   const bool doH = doA && !onlyAd;
   build_rowmap(s, rmap);
-  const int tA = ((nd / CP + 63) >> 6) << 6;     // threads of the A^d product
+  const int nq = nd / CP;
+  constexpr bool split = KS == 2;   // n_d <= MAXND = 256: n_q <= 64 rows of quads
+  const int tA = split ? 128 : ((nq + 63) >> 6) << 6;     // threads of the A^d product
   const bool overlap = tA < 256;
   for (int64_t e = blockIdx.x; e < P.ne; e += gridDim.x) {
     if (elem_off(P, e)) continue;
@@ -212,12 +218,36 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
     const size_t h0 = (size_t)e * nb * nd;
     R acc = R(0);
     if constexpr (CP > 1) {
-      if (tid < nd / CP) {
+      // batches of U columns: a batch's loads are issued together, then
+      // summed in order (columns past the range load its last one and add it
+      // times 0; the sums run over j in order)
+      typedef R rcv __attribute__((ext_vector_type(CP)));
+      if constexpr (split) {
+        // wave sl takes the columns [jlo, jhi) of the rows [CP qq, CP qq + CP)
+        constexpr int U = 8;   // registers: still 4 waves per SIMD
+        const int sl = tid >> 6, qq = tid & 63;
+        const int half = (nd + 1) / 2, jlo = sl * half, jhi = min(nd, jlo + half);
+        if (tid < tA && qq < nq && doA) {
+          const R* a0 = MAd.p + (size_t)e * nd * nd + CP * qq;
+          R ac[CP];
+#pragma unroll
+          for (int c = 0; c < CP; ++c) ac[c] = R(0);
+          for (int jb = jlo; jb < jhi; jb += U) {
+            rcv b[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) b[u] = *reinterpret_cast<const rcv*>(a0 + (size_t)min(jb + u, jhi - 1) * nd);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const R xj = xd[min(jb + u, jhi - 1)] * R(jb + u < jhi ? 1 : 0);
+#pragma unroll
+              for (int c = 0; c < CP; ++c) ac[c] += b[u][c] * xj;
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < CP; ++c) adx[sl * MAXND + CP * qq + c] = ac[c];
+        }
+      } else if (tid < nd / CP) {
         if (doA) {
-          // batches of U columns: a batch's loads are issued together, then
-          // summed in order (columns past n_d load the last one and add it
-          // times 0; the sums run over j in order, as for one row per thread)
-          typedef R rcv __attribute__((ext_vector_type(CP)));
           constexpr int U = 12;
           const R* a0 = MAd.p + (size_t)e * nd * nd + CP * tid;
           R ac[CP];
@@ -268,7 +298,7 @@ __global__ void __launch_bounds__(256) k_elem_apply(SolveParams P, MA MAd, MA MH
       __syncthreads();
     }
     if (tid < nd) {
-      if constexpr (CP > 1) acc = doA ? adx[tid] : R(0);
+      if constexpr (CP > 1) acc = doA ? (split ? adx[tid] + adx[MAXND + tid] : adx[tid]) : R(0);
       if (doH) {
         if (sH) {
 #pragma unroll 4
@@ -1452,12 +1482,15 @@ static void elem_apply_launch(hipStream_t st, const SolveParams& P, MA Ad, MA H,
   else
     hipLaunchKernelGGL((k_elem_apply<R, MA, -1, 1>), g, b, 0, st, P, Ad, H, Aoo, x, y, escr, flags, 0);
 }
+// Whether the A^d product of k_elem_apply with cp rows per thread splits the
+// columns over two waves (its sums then differ in rounding from the unsplit ones).
+bool apply_col_split(int nd, int cp) { return cp == 4 && nd > 0; }
 // Lanes per row of H in z_o = x_o + H x_d of k_elem_apply with cp rows of
 // A^d per thread (the split of the 256 threads above): rows are summed in
 // lane-strided order, so choices of cp with the same width give bitwise the
 // same results, and choices with different widths differ in rounding only.
 int apply_h_lanes(int nd, int cp) {
-  const int tA = ((nd / cp + 63) >> 6) << 6;
+  const int tA = apply_col_split(nd, cp) ? 128 : ((nd / cp + 63) >> 6) << 6;
   if (tA >= 256) return 16;
   return 256 - tA >= 128 ? 16 : 4;
 }

@@ -7,6 +7,7 @@ namespace mcs {
 template <typename R>
 void launch_elem_apply(hipStream_t st, const SolveParams& P, const OpPtrs<R>& O, const R* x, R* y, R* escr, int flags);
 int apply_h_lanes(int nd, int rows_per_thread);
+bool apply_col_split(int nd, int rows_per_thread);
 template <typename R>
 void launch_facet_sum(hipStream_t st, const SolveParams& P, const R* escr, const R* base, R sign, R* y);
 template <typename R>

@@ -405,17 +405,17 @@ def test_autotuned_launch_shapes_give_identical_results(precision):
 def test_apply_rows_per_thread_agree(d, n, k):
     """K x with 1, 2 and (FP32) 4 rows of A^d per thread agrees to rounding
     (FP64: 1e-12 of the oracle's K x; FP32: 1e-6 of one row per thread), and
-    bitwise where the lane width of the H products is the default's (2D k = 5,
-    3D k = 3 and the FP32 choices 2 and 4 at 3D k = 4): the choices the tuner
-    tries."""
+    bitwise where the lane width of the H products and the order of the A^d
+    sums are the default's (four rows per thread split the columns over two
+    waves): the choices the tuner tries."""
     from paper_2207_08481_amd.mcs import F32, F64
     c = setup_case(d, n, k)
     pb = c["pb"]
     xn = np.random.default_rng(3).standard_normal(pb.n_dof)
     x = torch.as_tensor(xn, device="cuda:0")
     ref = torch.as_tensor(c["K"] @ xn, device="cuda:0")
-    groups = {(3, 3): {F64: [(0, 1, 2)], F32: [(0, 1, 2, 4)]},
-              (3, 4): {F64: [(0, 2)], F32: [(0, 2, 4)]},
+    groups = {(3, 3): {F64: [(0, 1, 2)], F32: [(0, 4), (1, 2)]},
+              (3, 4): {F64: [(0, 2)], F32: [(0, 4)]},
               (2, 5): {F64: [(0, 1)], F32: [(0, 1)]}}[(d, k)]
     for dt, xt, choices, tol in ((F64, x, (0, 1, 2), 1e-12), (F32, x.float(), (0, 1, 2, 4), 1e-6)):
         ys = {}
