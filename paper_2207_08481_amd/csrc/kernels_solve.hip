@@ -735,16 +735,28 @@ __global__ void k_elem_ycorr(SolveParams P, const R* __restrict__ W, const int32
     const R* We = W + (size_t)e * nvd * nd + t;
     R acc = R(0);
     if constexpr (D > 0) {
-      // the (d+1) d entries of the row first, then the vertex ids
+      // the (d+1) d entries of the row, the vertex ids, their free flags and
+      // values: each group of loads issued together (three round trips in
+      // place of one chain per vertex), then summed in order
       R wv[(D + 1) * D];
 #pragma unroll
       for (int i = 0; i < (D + 1) * D; ++i) wv[i] = We[(size_t)i * nd];
+      int64_t vv[D + 1];
+#pragma unroll
+      for (int vl = 0; vl < D + 1; ++vl) vv[vl] = elem_verts[e * (D + 1) + vl];
+      bool fr[D + 1];
+#pragma unroll
+      for (int vl = 0; vl < D + 1; ++vl) fr[vl] = vfree_of_lat[vv[vl]] >= 0;
+      R xv[(D + 1) * D];
+#pragma unroll
+      for (int vl = 0; vl < D + 1; ++vl)
+#pragma unroll
+        for (int c = 0; c < D; ++c) xv[vl * D + c] = fr[vl] ? x0[vv[vl] * D + c] : R(0);
 #pragma unroll
       for (int vl = 0; vl < D + 1; ++vl) {
-        const int64_t v = elem_verts[e * (D + 1) + vl];
-        if (vfree_of_lat[v] < 0) continue;
+        if (!fr[vl]) continue;
 #pragma unroll
-        for (int c = 0; c < D; ++c) acc += wv[vl * D + c] * x0[v * D + c];
+        for (int c = 0; c < D; ++c) acc += wv[vl * D + c] * xv[vl * D + c];
       }
     } else {
       for (int vl = 0; vl < nv; ++vl) {
